@@ -1,0 +1,189 @@
+/*
+ * mlb: multicomponent Enskog lattice-Boltzmann step on MI355X (gfx950).
+ *
+ * C ABI of the GPU library libmlb.so.  Plain pointers and sizes only.
+ *
+ * The method (Marini Bettolo Marconi & Melchionna, "Multicomponent diffusion
+ * in nanosystems"): M species of hard spheres with diameters sigma_aa,
+ * unit masses, uniform temperature T and optional attractive tails evolve
+ * by the kinetic equation of Sec. 2, eq. (evolution): relaxation at rate
+ * omega towards the orthogonalised local equilibrium psi_perp of
+ * eqs. (psia)-(prefactor), plus the molecular-field term
+ * Phi_a . (v - u) psi_a / kT, where Phi_a is the self-consistent field of
+ * Sec. 3, eq. (splitforce):
+ *   - hard-core mean field, a shell integral of g_ab n_b at radius sigma_ab,
+ *     eq. (potmeanforce);
+ *   - RPA attractive field, a convolution of n_b with grad U_ab, below
+ *     eq. (potmeanforce);
+ *   - drag and viscous forces, eqs. (gammaab), (tensorgamma), (viscousforce),
+ *     evaluated as one pair form with a Crank-Nicolson treatment of the
+ *     velocity dependence (one local Jacobi predictor sweep);
+ *   - an external body force F^a (eq. evolution).
+ * Space and velocity are discretised on a D3Q19 lattice (spacing and time
+ * step 1, kT = 1/3, m = 1).
+ *
+ * Conventions for every entry point:
+ *   - Device pointers are HIP device addresses; "host" pointers are CPU
+ *     memory.  Field arrays are species-major, x fastest:
+ *       scalar field  [M][nz][ny][nx]
+ *       vector field  [M][3][nz][ny][nx]
+ *       populations   [M][19][nz][ny][nx]   (velocity order below)
+ *     in the mixture's precision (float for 32, double for 64) unless a
+ *     function says float64.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *     asynchronous on that stream unless documented as synchronising.
+ *   - The caller owns every buffer, including the workspace; the library
+ *     allocates no device memory.  Workspace contents belong to the library
+ *     between mlb_init_mixture and mlb_destroy.
+ *   - Status codes, never exceptions; mlb_last_error() gives a message for
+ *     the last failing call of the calling thread.
+ *   - Calls on one handle must not overlap on different streams.
+ *
+ * D3Q19 velocity order: rest; +x, -x, +y, -y, +z, -z; then
+ * (1,1,0), (-1,-1,0), (1,-1,0), (-1,1,0), (1,0,1), (-1,0,-1), (1,0,-1),
+ * (-1,0,1), (0,1,1), (0,-1,-1), (0,1,-1), (0,-1,1).
+ */
+#ifndef MLB_H
+#define MLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MLB_MAX_SPECIES 4
+#define MLB_Q 19
+
+typedef enum {
+    MLB_OK = 0,
+    MLB_EINVAL = -1,       /* invalid argument or parameter set                   */
+    MLB_ENOMEM = -2,       /* workspace smaller than mlb_workspace_bytes()         */
+    MLB_EHIP = -3,         /* a HIP runtime call failed                            */
+    MLB_ENONFINITE = -5,   /* a conserved sum is not finite                        */
+    MLB_ESTATE = -6,       /* call not valid in the handle's current state        */
+    MLB_EUNSUPPORTED = -7  /* option not available for this precision or geometry */
+} mlb_status;
+
+enum { MLB_SCHEME_CN_J1 = 0, MLB_SCHEME_FE = 1 };
+enum { MLB_TAIL_AUTO = 0, MLB_TAIL_DIRECT = 1, MLB_TAIL_SPECTRAL = 2 };
+enum { MLB_PART_MF = 1u, MLB_PART_TAIL = 2u, MLB_PART_DISS = 4u, MLB_PART_EXT = 8u,
+       MLB_PART_ALL = 15u };
+
+/* Problem statement (Sec. 2 and Sec. 3).  Lattice units. */
+typedef struct {
+    int32_t nx, ny, nz;            /* lattice size; x and z periodic                  */
+    int32_t nspecies;              /* M, 1..4                                         */
+    int32_t precision;             /* 32 (float) or 64 (double)                       */
+    int32_t scheme;                /* MLB_SCHEME_CN_J1 (default) or MLB_SCHEME_FE     */
+    int32_t tail_mode;             /* MLB_TAIL_*: AUTO = spectral in 32, direct in 64 */
+    int32_t walls_y;               /* 0: y periodic; 1: solid layers y=0 and y=ny-1   */
+    double tau;                    /* relaxation time, omega = 1/tau (one for all)    */
+    double kT;                     /* must be 1/3 (= c_s^2 with unit masses)          */
+    double mass[MLB_MAX_SPECIES];  /* must all be 1                                   */
+    double sigma[MLB_MAX_SPECIES]; /* hard-core diameters sigma_aa; sigma_ab = mean   */
+    double eps[MLB_MAX_SPECIES * MLB_MAX_SPECIES]; /* U_ab = -eps_ab (sigma_ab/r)^6 for
+                                      sigma_ab < r <= rc_factor sigma_ab; 0 = off; row
+                                      stride MLB_MAX_SPECIES, must be symmetric        */
+    double rc_factor;              /* tail cutoff in units of sigma_ab                */
+    double ext_force[MLB_MAX_SPECIES * 3]; /* uniform body force F^a per species      */
+    double wall_ux[2];             /* x velocity of the wall at y=0 and at y=ny-1     */
+} mlb_params;
+
+typedef struct mlb_mixture_s *mlb_mixture;
+
+/* Bytes of device workspace a mixture with these parameters needs (256-byte
+ * aligned pointer required).  Returns 0 if the parameters are invalid (the
+ * reason is in mlb_last_error()).  Conditions: 1 <= M <= 4, masses 1,
+ * kT = 1/3, sigma > 0, every stencil offset smaller than the box edge in
+ * each periodic direction. */
+size_t mlb_workspace_bytes(const mlb_params *p);
+
+/* Create a mixture: builds the stencil tables on the host, lays out the
+ * workspace and sets the populations to psi_perp(n0, n0 u0, u) (eq.
+ * prefactor with u the barycentric velocity), i.e. the local equilibrium of
+ * the given fields.  n0 [M][N], u0 [M][3][N]: DEVICE float64 arrays
+ * (species densities and velocities); values on solid layers are ignored.
+ * Synchronises `stream`.  On success *out receives a handle that must be
+ * released with mlb_destroy. */
+mlb_status mlb_init_mixture(const mlb_params *p, void *workspace, size_t workspace_bytes,
+                            const double *n0, const double *u0, void *stream, mlb_mixture *out);
+
+/* Advance the populations by nsteps >= 0 time steps of the kinetic equation
+ * (Sec. 2, eq. evolution, with the field of Sec. 3). */
+mlb_status mlb_step(mlb_mixture h, int32_t nsteps, void *stream);
+
+/* Species densities n_a [M][N] and momentum densities n_a u_a [M][3][N]
+ * (eq. colonna) of the current populations, into caller device buffers. */
+mlb_status mlb_moments(mlb_mixture h, void *n_out, void *j_out, void *stream);
+
+/* Force density n_a Phi_a [M][3][N] acting in the next step (eq. splitforce,
+ * times n_a), restricted to the parts in `parts` (MLB_PART_* mask):
+ * MF = hard-core mean field, TAIL = attractive field, EXT = n_a F^a,
+ * DISS = drag + viscous force as applied by the time integrator. */
+mlb_status mlb_forces(mlb_mixture h, void *nphi_out, uint32_t parts, void *stream);
+
+/* Every intermediate field of one step evaluated on the current
+ * populations (for per-kernel checks); NULL skips an output.
+ * n [M][N], j [M][3][N], u [3][N] barycentric velocity, g [P][N] contact
+ * values for the pairs (0,0),(0,1)..(0,M-1),(1,1).. (P = M(M+1)/2),
+ * vhat [M][3][N] predicted velocities, H [M][3][N] predictor-time force,
+ * nphi [M][3][N] total force density. */
+mlb_status mlb_fields(mlb_mixture h, void *n, void *j, void *u, void *g, void *vhat, void *H,
+                      void *nphi, void *stream);
+
+/* Copy the populations [M][19][N] out of / into the mixture (device). */
+mlb_status mlb_get_populations(mlb_mixture h, void *f_out, void *stream);
+mlb_status mlb_set_populations(mlb_mixture h, const void *f_in, void *stream);
+
+/* Global FP64 sums of the current state, accumulated on the GPU in float64:
+ * mass[a] = sum_r n_a, mom[3a+d] = sum_r j_a,d (the conserved quantities of
+ * eqs. continuity and momentcomponent).  HOST outputs; synchronises the
+ * stream.  Returns MLB_ENONFINITE if any sum is not finite. */
+mlb_status mlb_conserved(mlb_mixture h, double *mass, double *mom, void *stream);
+
+/* Composition-mode projection (Sec. 5.1): appends one float64 sample
+ * (t, |sum_r (n_a - n_b) exp(-i 2 pi x / nx)|) for species pair (a, b) to the
+ * handle's on-device time series (capacity mlb_series_capacity()). */
+mlb_status mlb_record_mode(mlb_mixture h, int32_t a, int32_t b, void *stream);
+/* Second-moment record for a tracer band (Sec. 5.2): appends (t, Var_x) of
+ * the y,z-summed density of species a along x, in float64. */
+mlb_status mlb_record_spread(mlb_mixture h, int32_t a, void *stream);
+int32_t mlb_series_capacity(void);
+/* Clear the time series (length 0). */
+mlb_status mlb_series_reset(mlb_mixture h, void *stream);
+/* Least-squares fit over the recorded samples with t >= t_min, in float64 on
+ * the GPU.  kind 0 (mode): D = -slope(ln A, t) / (2 pi / nx)^2, the decay
+ * 1/tau = D q^2 of Sec. 5.1.  kind 1 (spread): D = slope(Var, t) / 2.
+ * HOST output; synchronises the stream. */
+mlb_status mlb_fit_series(mlb_mixture h, int32_t kind, double t_min, double *D_out, void *stream);
+/* Copy the recorded series to HOST memory: t[count], v[count]; returns the
+ * count through *count.  Synchronises. */
+mlb_status mlb_get_series(mlb_mixture h, double *t, double *v, int32_t capacity, int32_t *count,
+                          void *stream);
+
+/* Per-pass GPU timing.  While profiling is on, mlb_step records a HIP event
+ * pair around every kernel pass on the step's stream.  mlb_profile_end
+ * synchronises that stream and returns, per pass k < MLB_NPASS, the summed
+ * milliseconds ms[k] and the number of launches launches[k] (HOST arrays),
+ * then turns profiling off.  Pass order: moments, contact values, spectral
+ * tail, first gather, second gather + collision + streaming. */
+#define MLB_NPASS 5
+mlb_status mlb_profile_begin(mlb_mixture h);
+mlb_status mlb_profile_end(mlb_mixture h, double *ms, int32_t *launches, void *stream);
+const char *mlb_pass_name(int32_t k);
+
+/* Number of steps taken since init. */
+int64_t mlb_step_count(mlb_mixture h);
+
+/* Release the handle (host memory only; the caller frees the workspace). */
+mlb_status mlb_destroy(mlb_mixture h);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char *mlb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLB_H */

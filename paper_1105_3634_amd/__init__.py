@@ -1,0 +1,200 @@
+"""mlb: MI355X-native multicomponent Enskog lattice-Boltzmann step.
+
+Python face of libmlb.so (see include/mlb.h).  PyTorch supplies device
+memory and streams; all arithmetic of the step runs in the library's HIP
+kernels.  Importing this package does not need a GPU; creating a mixture
+does, and fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+from ._lib import (MlbError, PART_ALL, PART_DISS, PART_EXT, PART_MF, PART_TAIL, Q, SCHEME_CN_J1, SCHEME_FE,
+                   TAIL_AUTO, TAIL_DIRECT, TAIL_SPECTRAL)
+
+__all__ = ["GpuMixture", "make_params", "workspace_bytes", "MlbError", "PART_ALL", "PART_MF", "PART_TAIL",
+           "PART_DISS", "PART_EXT", "TAIL_AUTO", "TAIL_DIRECT", "TAIL_SPECTRAL", "SCHEME_CN_J1", "SCHEME_FE"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def make_params(mix, precision: int = 32, tail_mode: int = TAIL_AUTO) -> _lib.Params:
+    """Fill the C parameter block from a mixture description (any object with
+    nx, ny, nz, sigma, tau, kT, rc_factor, walls_y, wall_ux, scheme and the
+    eps_matrix() / fext_matrix() accessors)."""
+    p = _lib.Params()
+    p.nx, p.ny, p.nz = int(mix.nx), int(mix.ny), int(mix.nz)
+    M = len(mix.sigma)
+    p.nspecies = M
+    p.precision = int(precision)
+    p.scheme = int(getattr(mix, "scheme", SCHEME_CN_J1))
+    p.tail_mode = int(tail_mode)
+    p.walls_y = 1 if getattr(mix, "walls_y", False) else 0
+    p.tau = float(mix.tau)
+    p.kT = float(mix.kT)
+    eps = np.asarray(mix.eps_matrix(), dtype=np.float64).reshape(M, M)
+    fx = np.asarray(mix.fext_matrix(), dtype=np.float64).reshape(M, 3)
+    for a in range(M):
+        p.mass[a] = 1.0
+        p.sigma[a] = float(mix.sigma[a])
+        for b in range(M):
+            p.eps[a * _lib.MAX_SPECIES + b] = float(eps[a, b])
+        for d in range(3):
+            p.ext_force[3 * a + d] = float(fx[a, d])
+    p.rc_factor = float(getattr(mix, "rc_factor", 2.5))
+    wu = getattr(mix, "wall_ux", (0.0, 0.0))
+    p.wall_ux[0], p.wall_ux[1] = float(wu[0]), float(wu[1])
+    return p
+
+
+def workspace_bytes(params: _lib.Params) -> int:
+    lib = _lib.load()
+    n = lib.mlb_workspace_bytes(C.byref(params))
+    if n == 0:
+        raise MlbError(-1, "mlb_workspace_bytes", lib.mlb_last_error().decode())
+    return int(n)
+
+
+def _stream_handle(stream) -> C.c_void_p:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(int(s.cuda_stream))
+
+
+class GpuMixture:
+    """One mixture on the GPU.  Fields come back as torch tensors on the device."""
+
+    def __init__(self, mix, n0: np.ndarray, u0: np.ndarray, precision: int = 32, tail_mode: int = TAIL_AUTO,
+                 device: str = "cuda:0", stream=None):
+        torch = _torch()
+        self.lib = _lib.load()
+        self.mix = mix
+        self.params = make_params(mix, precision, tail_mode)
+        self.M = len(mix.sigma)
+        self.P = self.M * (self.M + 1) // 2
+        self.shape = (int(mix.nz), int(mix.ny), int(mix.nx))
+        self.N = int(np.prod(self.shape))
+        self.device = torch.device(device)
+        self.dtype = torch.float64 if precision == 64 else torch.float32
+        self.stream = stream
+        nbytes = workspace_bytes(self.params)
+        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self._ws_raw = raw
+        self.ws = raw[off:off + nbytes]
+        n0_d = torch.as_tensor(np.ascontiguousarray(n0, dtype=np.float64)).to(self.device)
+        u0_d = torch.as_tensor(np.ascontiguousarray(u0, dtype=np.float64)).to(self.device)
+        assert n0_d.numel() == self.M * self.N and u0_d.numel() == 3 * self.M * self.N
+        h = C.c_void_p()
+        st = self.lib.mlb_init_mixture(C.byref(self.params), C.c_void_p(self.ws.data_ptr()), nbytes,
+                                       C.c_void_p(n0_d.data_ptr()), C.c_void_p(u0_d.data_ptr()),
+                                       _stream_handle(stream), C.byref(h))
+        _lib.check(st, "mlb_init_mixture")
+        self.h = h
+
+    def close(self) -> None:
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.mlb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --------------------------------------------------------------- driving
+    def step(self, nsteps: int = 1) -> None:
+        _lib.check(self.lib.mlb_step(self.h, int(nsteps), _stream_handle(self.stream)), "mlb_step")
+
+    @property
+    def steps(self) -> int:
+        return int(self.lib.mlb_step_count(self.h))
+
+    def _empty(self, *shape):
+        return _torch().empty(shape, dtype=self.dtype, device=self.device)
+
+    def moments(self):
+        n = self._empty(self.M, *self.shape)
+        j = self._empty(self.M, 3, *self.shape)
+        _lib.check(self.lib.mlb_moments(self.h, C.c_void_p(n.data_ptr()), C.c_void_p(j.data_ptr()),
+                                        _stream_handle(self.stream)), "mlb_moments")
+        return n, j
+
+    def forces(self, parts: int = PART_ALL):
+        out = self._empty(self.M, 3, *self.shape)
+        _lib.check(self.lib.mlb_forces(self.h, C.c_void_p(out.data_ptr()), int(parts), _stream_handle(self.stream)),
+                   "mlb_forces")
+        return out
+
+    def fields(self) -> Dict[str, "object"]:
+        M, sh = self.M, self.shape
+        out = {"n": self._empty(M, *sh), "j": self._empty(M, 3, *sh), "u": self._empty(3, *sh),
+               "g": self._empty(self.P, *sh), "vhat": self._empty(M, 3, *sh), "H": self._empty(M, 3, *sh),
+               "N": self._empty(M, 3, *sh)}
+        ptrs = [C.c_void_p(out[k].data_ptr()) for k in ("n", "j", "u", "g", "vhat", "H", "N")]
+        _lib.check(self.lib.mlb_fields(self.h, *ptrs, _stream_handle(self.stream)), "mlb_fields")
+        return out
+
+    def populations(self):
+        f = self._empty(self.M, Q, *self.shape)
+        _lib.check(self.lib.mlb_get_populations(self.h, C.c_void_p(f.data_ptr()), _stream_handle(self.stream)),
+                   "mlb_get_populations")
+        return f
+
+    def set_populations(self, f) -> None:
+        f = f.to(device=self.device, dtype=self.dtype).contiguous()
+        assert f.numel() == self.M * Q * self.N
+        _lib.check(self.lib.mlb_set_populations(self.h, C.c_void_p(f.data_ptr()), _stream_handle(self.stream)),
+                   "mlb_set_populations")
+        self._keep = f
+
+    # ---------------------------------------------------------------- timing
+    def profile_begin(self) -> None:
+        _lib.check(self.lib.mlb_profile_begin(self.h), "mlb_profile_begin")
+
+    def profile_end(self) -> Dict[str, tuple]:
+        """{pass name: (summed ms, launches)} for the passes run since profile_begin."""
+        ms = (C.c_double * _lib.NPASS)()
+        cnt = (C.c_int32 * _lib.NPASS)()
+        _lib.check(self.lib.mlb_profile_end(self.h, ms, cnt, _stream_handle(self.stream)), "mlb_profile_end")
+        return {self.lib.mlb_pass_name(k).decode(): (ms[k], cnt[k]) for k in range(_lib.NPASS)}
+
+    # ------------------------------------------------------- float64 reductions
+    def conserved(self):
+        mass = (C.c_double * self.M)()
+        mom = (C.c_double * (3 * self.M))()
+        _lib.check(self.lib.mlb_conserved(self.h, mass, mom, _stream_handle(self.stream)), "mlb_conserved")
+        return np.array(mass[:]), np.array(mom[:]).reshape(self.M, 3)
+
+    def record_mode(self, a: int = 0, b: int = 1) -> None:
+        _lib.check(self.lib.mlb_record_mode(self.h, a, b, _stream_handle(self.stream)), "mlb_record_mode")
+
+    def record_spread(self, a: int) -> None:
+        _lib.check(self.lib.mlb_record_spread(self.h, a, _stream_handle(self.stream)), "mlb_record_spread")
+
+    def reset_series(self) -> None:
+        _lib.check(self.lib.mlb_series_reset(self.h, _stream_handle(self.stream)), "mlb_series_reset")
+
+    def fit(self, kind: int = 0, t_min: float = 0.0) -> float:
+        out = C.c_double()
+        _lib.check(self.lib.mlb_fit_series(self.h, kind, float(t_min), C.byref(out), _stream_handle(self.stream)),
+                   "mlb_fit_series")
+        return float(out.value)
+
+    def series(self):
+        cap = int(self.lib.mlb_series_capacity())
+        t = (C.c_double * cap)()
+        v = (C.c_double * cap)()
+        cnt = C.c_int32()
+        _lib.check(self.lib.mlb_get_series(self.h, t, v, cap, C.byref(cnt), _stream_handle(self.stream)),
+                   "mlb_get_series")
+        n = cnt.value
+        return np.array(t[:n]), np.array(v[:n])

@@ -1,0 +1,102 @@
+"""ctypes binding of libmlb.so (argument marshalling only).
+
+Every step of the path runs in the library's HIP kernels; this module only
+converts Python values and torch tensors (device memory, streams) into the
+plain pointers of include/mlb.h.  It raises if the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmlb.so")
+
+MAX_SPECIES = 4
+Q = 19
+NPASS = 5
+
+MLB_OK = 0
+STATUS = {0: "MLB_OK", -1: "MLB_EINVAL", -2: "MLB_ENOMEM", -3: "MLB_EHIP", -5: "MLB_ENONFINITE",
+          -6: "MLB_ESTATE", -7: "MLB_EUNSUPPORTED"}
+
+SCHEME_CN_J1, SCHEME_FE = 0, 1
+TAIL_AUTO, TAIL_DIRECT, TAIL_SPECTRAL = 0, 1, 2
+PART_MF, PART_TAIL, PART_DISS, PART_EXT, PART_ALL = 1, 2, 4, 8, 15
+
+
+class MlbError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("nspecies", C.c_int32), ("precision", C.c_int32), ("scheme", C.c_int32),
+        ("tail_mode", C.c_int32), ("walls_y", C.c_int32),
+        ("tau", C.c_double), ("kT", C.c_double),
+        ("mass", C.c_double * MAX_SPECIES),
+        ("sigma", C.c_double * MAX_SPECIES),
+        ("eps", C.c_double * (MAX_SPECIES * MAX_SPECIES)),
+        ("rc_factor", C.c_double),
+        ("ext_force", C.c_double * (MAX_SPECIES * 3)),
+        ("wall_ux", C.c_double * 2),
+    ]
+
+
+# (name, restype, argtypes)
+_SIGS = [
+    ("mlb_workspace_bytes", C.c_size_t, [C.POINTER(Params)]),
+    ("mlb_init_mixture", C.c_int, [C.POINTER(Params), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("mlb_step", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    ("mlb_moments", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("mlb_forces", C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p]),
+    ("mlb_fields", C.c_int, [C.c_void_p] + [C.c_void_p] * 7 + [C.c_void_p]),
+    ("mlb_get_populations", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("mlb_set_populations", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("mlb_conserved", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]),
+    ("mlb_record_mode", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
+    ("mlb_record_spread", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    ("mlb_series_capacity", C.c_int32, []),
+    ("mlb_series_reset", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("mlb_fit_series", C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_double), C.c_void_p]),
+    ("mlb_get_series", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32,
+                                 C.POINTER(C.c_int32), C.c_void_p]),
+    ("mlb_step_count", C.c_int64, [C.c_void_p]),
+    ("mlb_profile_begin", C.c_int, [C.c_void_p]),
+    ("mlb_profile_end", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_void_p]),
+    ("mlb_pass_name", C.c_char_p, [C.c_int32]),
+    ("mlb_destroy", C.c_int, [C.c_void_p]),
+    ("mlb_last_error", C.c_char_p, []),
+]
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libmlb.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(or python paper_1105_3634_amd/build.py); there is no fallback path")
+    lib = C.CDLL(LIB_PATH)
+    for name, res, args in _SIGS:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return [s[0] for s in _SIGS]
+
+
+def check(status: int, where: str) -> None:
+    if status != MLB_OK:
+        raise MlbError(status, where, load().mlb_last_error().decode())

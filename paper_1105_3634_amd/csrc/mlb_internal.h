@@ -1,0 +1,110 @@
+// Internal declarations of the mlb GPU library: the per-system descriptor the
+// kernels read, the stencil tables built on the host, and the launch entry
+// points of each pass.  Not part of the public ABI (include/mlb.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace mlb {
+
+constexpr int kMaxS = 4;
+constexpr int kQ = 19;
+constexpr int kBlock = 256;          // threads per block of the per-site passes
+
+// Stencil offsets travel packed: three signed bytes (ex, ey, ez).
+__host__ __device__ inline int32_t pack_offset(int ex, int ey, int ez)
+{
+    return (ex & 0xff) | ((ey & 0xff) << 8) | ((ez & 0xff) << 16);
+}
+__host__ __device__ inline void unpack_offset(int32_t p, int &ex, int &ey, int &ez)
+{
+    ex = (int)(int8_t)(p & 0xff);
+    ey = (int)(int8_t)((p >> 8) & 0xff);
+    ez = (int)(int8_t)((p >> 16) & 0xff);
+}
+
+// One lattice system as the kernels see it.  Lives in device memory; every
+// block belongs to one system, so all loads from it are wave-uniform.
+template <typename T>
+struct SysDesc {
+    int nx, ny, nz, M, P, walls;
+    long long N;
+    int block_start;                 // first block of this system in a per-site launch
+    int nblocks;                     // blocks of this system (ceil(N / kBlock))
+    T *f[2];                         // population double buffer [M][19][N]
+    T *n, *j, *u, *g, *vh, *H, *Nf;  // fields (see mlb.h for layouts)
+    T *tail;                         // attractive field sum_b K_ab * n_b [M][3][N] (spectral mode)
+    T *parts;                        // optional force-part accumulator [M][3][N] (forces query)
+    unsigned parts_mask;
+    int tail_direct;                 // 1: direct tail sum in the first gather
+    int scheme;
+    int omega_is_one;
+    // stencils: indices into the batch-wide tables
+    int sh_start[kMaxS][kMaxS], sh_cnt[kMaxS][kMaxS];
+    int tl_start[kMaxS][kMaxS], tl_cnt[kMaxS][kMaxS];
+    int bl_start[kMaxS], bl_cnt[kMaxS], bl_full[kMaxS];
+    // constants (computed in float64 on the host, rounded to T)
+    T cm[kMaxS][kMaxS];              // -kT sigma_ab^2 w_hat / 2
+    T cg[kMaxS][kMaxS];              // kappa_ab / 6
+    T ck[kMaxS][kMaxS];              // kappa_ab / 2
+    T dd[kMaxS][kMaxS];              // sigma_a sigma_b / (sigma_a + sigma_b)
+    T s2[kMaxS], s3[kMaxS];          // (pi/6) sigma^2, (pi/6) sigma^3
+    T fext[kMaxS][3];
+    T omega, om1;
+    T wall_ux[2];
+};
+
+// Batch-wide stencil tables (device).
+template <typename T>
+struct Tables {
+    const int32_t *sh_e;  const T *sh_u;     // shell half-lists: packed offset, unit vector [3]
+    const int32_t *tl_e;  const T *tl_w;     // tail half-lists: packed offset, vector weight [3]
+    const int32_t *bl_e;                     // ball half-lists: packed offset
+};
+
+// ---------------------------------------------------------------- host side
+struct HostStencil {
+    std::vector<int32_t> e;      // packed offsets
+    std::vector<double> v;       // 3 per entry: unit vector (shell) or weight (tail)
+    int full = 0;                // size of the symmetric set
+    int max_abs[3] = {0, 0, 0};  // largest |component| per axis
+};
+
+enum { kShell = 0, kBall = 1, kTail = 2 };
+HostStencil build_stencil(int kind, double s, double rc);
+
+struct PairConst {
+    double cm, cg, ck, dd;
+};
+PairConst pair_constants(double sa, double sb, double kT, int shell_full);
+
+// Launch entry points (one per precision), all on `st`.
+template <typename T>
+struct Launch {
+    static void moments(const SysDesc<T> *sys, const int *blk_sys, int nblk, int parity, hipStream_t st);
+    static void contact(const SysDesc<T> *sys, const int *blk_sys, int nblk, Tables<T> tb, hipStream_t st);
+    static void gather1(const SysDesc<T> *sys, const int *blk_sys, int nblk, int maxM, Tables<T> tb,
+                        hipStream_t st);
+    static void step2(const SysDesc<T> *sys, const int *blk_sys, int nblk, int maxM, Tables<T> tb,
+                      int parity, int write_force_only, hipStream_t st);
+    static void init_pop(const SysDesc<T> *sys, const int *blk_sys, int nblk, const double *n0,
+                         const double *u0, hipStream_t st);
+};
+
+// float64 reductions (reduce.hip)
+void launch_conserved(const void *n, const void *j, int prec, int M, long long N, double *partials,
+                      int nparts, double *out, hipStream_t st);
+void launch_mode(const void *n, int prec, int a, int b, int nx, long long N, double *partials,
+                 int nparts, double *series, int *count, int cap, double t, hipStream_t st);
+void launch_spread(const void *n, int prec, int a, int nx, long long N, double *partials, int nparts,
+                   double *series, int *count, int cap, double t, hipStream_t st);
+void launch_fit(const double *series, const int *count, int cap, int kind, double t_min, double k2,
+                double *out, hipStream_t st);
+void launch_zero_i32(int *p, int n, hipStream_t st);
+
+}  // namespace mlb

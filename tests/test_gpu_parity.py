@@ -1,0 +1,148 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Float64: bit-for-bit equality of every intermediate field and of the
+populations after many steps (both sides evaluate the same operations in
+the same order, without contraction).
+Float32: densities within 1e-5 of the oracle (relative to the field's max
+norm) after 100 steps; the float64 error of each case is printed.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("n", "j", "u", "g", "vhat", "H", "N")
+
+
+def _gpu(m, n0, u0, precision, **kw):
+    import paper_1105_3634_amd as mlb
+    return mlb.GpuMixture(m, n0, u0, precision=precision, **kw)
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _case(name):
+    if name == "step_binary":
+        return W.config_step_binary()
+    if name == "random_binary":
+        m = W.Mixture(8, 8, 8, sigma=(2.0, 3.0))
+        return (m,) + W.random_state(m, [0.012, 0.009], rel=0.4, u_amp=0.03, seed=11)
+    if name == "ternary_tail_ext":
+        eps = np.array([[0.1, 0.12, 0.08], [0.12, 0.15, 0.05], [0.08, 0.05, 0.2]])
+        fx = np.array([[1e-5, 0, 0], [0, -2e-5, 0], [0, 0, 3e-5]])
+        m = W.Mixture(12, 12, 12, sigma=(1.5, 2.0, 2.5), eps=eps, rc_factor=2.0, fext=fx)
+        return (m,) + W.random_state(m, [0.03, 0.015, 0.008], rel=0.4, u_amp=0.03, seed=12)
+    if name == "walls":
+        m = W.Mixture(10, 11, 9, sigma=(2.0, 3.0), walls_y=True, wall_ux=(-0.03, 0.04))
+        return (m,) + W.random_state(m, [0.012, 0.009], rel=0.4, u_amp=0.03, seed=13)
+    if name == "fe_tau":
+        m = W.Mixture(9, 10, 11, sigma=(2.0, 2.5), tau=0.8, scheme=W.SCHEME_FE)
+        return (m,) + W.random_state(m, [0.006, 0.004], rel=0.3, u_amp=0.02, seed=14)
+    if name == "bulk_small":
+        return W.config_bulk_diffusion(32, 24, 24, seed=5)
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["step_binary", "random_binary", "ternary_tail_ext", "walls", "fe_tau"])
+def test_fp64_fields_bit_exact(oracle_lib, name):
+    m, n0, u0 = _case(name)
+    print(f"[fp64 fields] case={name} shape={m.shape()} M={m.M}", flush=True)
+    o = oracle_lib.Oracle(m)
+    f = o.step(o.init(n0, u0), 3)
+    ref = o.fields(f)
+    g = _gpu(m, n0, u0, 64)
+    g.step(3)
+    d = g.fields()
+    for k in FIELDS:
+        got = _np(d[k])
+        assert np.array_equal(got, ref[k]), (k, np.abs(got - ref[k]).max())
+
+
+@pytest.mark.parametrize("name,steps", [("step_binary", 100), ("ternary_tail_ext", 20), ("walls", 40),
+                                        ("fe_tau", 30)])
+def test_fp64_populations_bit_exact(oracle_lib, name, steps):
+    m, n0, u0 = _case(name)
+    print(f"[fp64 steps] case={name} shape={m.shape()} steps={steps}", flush=True)
+    o = oracle_lib.Oracle(m)
+    fo = o.step(o.init(n0, u0), steps)
+    g = _gpu(m, n0, u0, 64)
+    g.step(steps)
+    fg = _np(g.populations())
+    assert np.array_equal(fg, fo), np.abs(fg - fo).max()
+
+
+def _rel_maxnorm(got, ref):
+    out = []
+    for a in range(ref.shape[0]):
+        out.append(np.abs(got[a] - ref[a]).max() / np.abs(ref[a]).max())
+    return max(out)
+
+
+@pytest.mark.parametrize("name,steps", [("step_binary", 100), ("bulk_small", 100), ("walls", 100)])
+def test_fp32_densities_within_1e5(oracle_lib, name, steps):
+    m, n0, u0 = _case(name)
+    print(f"[fp32 densities] case={name} shape={m.shape()} steps={steps}", flush=True)
+    o = oracle_lib.Oracle(m)
+    fo = o.step(o.init(n0, u0), steps)
+    no = o.fields(fo)["n"]
+    g32 = _gpu(m, n0, u0, 32)
+    g32.step(steps)
+    n32 = _np(g32.moments()[0])
+    g64 = _gpu(m, n0, u0, 64)
+    g64.step(steps)
+    n64 = _np(g64.moments()[0])
+    e32, e64 = _rel_maxnorm(n32, no), _rel_maxnorm(n64, no)
+    print(f"  fp32 rel err {e32:.3e}   fp64 rel err {e64:.3e}", flush=True)
+    assert e64 == 0.0
+    assert e32 < 1e-5
+
+
+def test_fp32_forces_parts(oracle_lib):
+    import paper_1105_3634_amd as mlb
+    m, n0, u0 = _case("ternary_tail_ext")
+    o = oracle_lib.Oracle(m)
+    f = o.init(n0, u0)
+    ref = o.fields(f)
+    for prec, tol in ((64, 0.0), (32, 2e-6)):
+        g = _gpu(m, n0, u0, prec)
+        for mask, parts in ((mlb.PART_MF, ["Nmf"]), (mlb.PART_TAIL, ["Ntail"]), (mlb.PART_EXT, ["Next"]),
+                            (mlb.PART_DISS, ["Dold", "Dnew"]), (mlb.PART_ALL, None)):
+            got = _np(g.forces(mask))
+            if parts is None:
+                want = ref["N"]
+            elif parts == ["Dold", "Dnew"]:
+                want = 0.5 * ref["Dold"] + 0.5 * ref["Dnew"]
+            else:
+                want = ref[parts[0]]
+            err = np.abs(got - want).max() / max(np.abs(want).max(), 1e-300)
+            assert err <= max(tol, 1e-15 if prec == 64 else tol), (prec, mask, err)
+
+
+def test_conserved_sums_fp64(oracle_lib):
+    """Float64 GPU sums of the conserved quantities.  In float64 mass and total
+    momentum hold to rounding; in float32 the collision and the pair forces
+    cancel only to float32 rounding, so the drift is bounded by
+    eps32 * total mass * steps."""
+    m, n0, u0 = _case("random_binary")
+    o = oracle_lib.Oracle(m)
+    d = o.fields(o.init(n0, u0))
+    steps = 50
+    for prec in (64, 32):
+        g = _gpu(m, n0, u0, prec)
+        mass0, mom0 = g.conserved()
+        g.step(steps)
+        mass1, mom1 = g.conserved()
+        drift = np.abs(mom1.sum(0) - mom0.sum(0)).max()
+        print(f"  precision {prec}: mass drift {np.abs(mass1 / mass0 - 1).max():.2e}, momentum drift {drift:.2e}")
+        if prec == 64:
+            np.testing.assert_allclose(mass0, d["n"].sum(axis=(1, 2, 3)), rtol=1e-14)
+            np.testing.assert_allclose(mass1, mass0, rtol=1e-13)
+            assert drift < 1e-15 * m.N
+        else:
+            np.testing.assert_allclose(mass0, d["n"].sum(axis=(1, 2, 3)), rtol=1e-6)
+            np.testing.assert_allclose(mass1, mass0, rtol=2e-6)
+            assert drift < 6e-8 * mass0.sum() * steps
