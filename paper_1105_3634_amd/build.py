@@ -28,6 +28,7 @@ UNITS = [
     ("step_f64.hip", ["-ffp-contract=off"]),
     ("step_f32.hip", ["-ffp-contract=fast"]),
     ("reduce.hip", ["-ffp-contract=off"]),
+    ("spectral.hip", ["-ffp-contract=fast"]),
     ("tables.cpp", ["-ffp-contract=off", "-x", "hip"]),
     ("api.cpp", ["-ffp-contract=off", "-x", "hip"]),
 ]

@@ -16,6 +16,7 @@
 
 #include "../../include/mlb.h"
 #include "mlb_internal.h"
+#include "spectral.h"
 
 namespace {
 
@@ -135,8 +136,17 @@ struct Layout {
     size_t sys, blk, sh_e, sh_u, tl_e, tl_w, bl_e;
     size_t f0, f1, n, j, u, g, vh, H, Nf;
     size_t red, red_out, series, series_cnt, fit_out;
+    // spectral tail (float32 only)
+    size_t wxf, wxi, wyf, wyi, wzf, wzi, S, s1, s2, tail;
     size_t total;
 };
+
+// Spectral mode: float32, a tail on some pair, y periodic.
+bool wants_spectral(const mlb_params *p, const HostTables &t)
+{
+    if (t.tl_e.empty() || p->walls_y || p->precision != 32) return false;
+    return p->tail_mode == MLB_TAIL_AUTO || p->tail_mode == MLB_TAIL_SPECTRAL;
+}
 
 Layout make_layout(const mlb_params *p, const HostTables &t, size_t tsize, size_t sys_size, int nblk)
 {
@@ -166,6 +176,20 @@ Layout make_layout(const mlb_params *p, const HostTables &t, size_t tsize, size_
     L.series = take(sizeof(double) * 2 * kSeriesCap);
     L.series_cnt = take(sizeof(int));
     L.fit_out = take(sizeof(double) * 4);
+    if (wants_spectral(p, t)) {
+        const size_t nkx = (size_t)p->nx / 2 + 1, Sp = nkx * p->ny * p->nz;
+        const size_t fields = std::max(3 * M, 3 * P);
+        L.wxf = take(sizeof(float) * p->nx * 2 * nkx);
+        L.wxi = take(sizeof(float) * 2 * nkx * p->nx);
+        L.wyf = take(sizeof(float) * 4 * p->ny * p->ny);
+        L.wyi = take(sizeof(float) * 4 * p->ny * p->ny);
+        L.wzf = take(sizeof(float) * 4 * p->nz * p->nz);
+        L.wzi = take(sizeof(float) * 4 * p->nz * p->nz);
+        L.S = take(sizeof(float) * 3 * P * Sp);
+        L.s1 = take(sizeof(float) * 2 * fields * Sp);
+        L.s2 = take(sizeof(float) * 2 * fields * Sp);
+        L.tail = take(sizeof(float) * 3 * M * N);
+    }
     L.total = off;
     return L;
 }
@@ -186,6 +210,8 @@ struct mlb_mixture_s {
     std::vector<unsigned char> sys_host;   // two descriptors: [0] stepping, [1] query
     size_t sys_size = 0;
     int tail_direct = 1;
+    bool spectral = false;
+    mlb::SpectralPlan plan;
     // per-pass event timing
     bool profiling = false;
     std::vector<hipEvent_t> events;          // pool, reused
@@ -232,7 +258,7 @@ void fill_desc(mlb_mixture_s *h, mlb::SysDesc<T> &S)
     S.vh = reinterpret_cast<T *>(ws + h->L.vh);
     S.H = reinterpret_cast<T *>(ws + h->L.H);
     S.Nf = reinterpret_cast<T *>(ws + h->L.Nf);
-    S.tail = nullptr;
+    S.tail = h->spectral ? reinterpret_cast<T *>(ws + h->L.tail) : nullptr;
     S.parts = nullptr;
     S.parts_mask = 0;
     S.tail_direct = h->tail_direct;
@@ -317,6 +343,13 @@ void pass(mlb_mixture_s *h, int id, hipStream_t st, F &&launch)
     h->marks.emplace_back(id, (int)k);
 }
 
+void run_tail(mlb_mixture_s *h, hipStream_t st)
+{
+    char *ws = h->ws;
+    h->plan.apply(reinterpret_cast<const float *>(ws + h->L.n), reinterpret_cast<float *>(ws + h->L.s1),
+                  reinterpret_cast<float *>(ws + h->L.s2), reinterpret_cast<float *>(ws + h->L.tail), st);
+}
+
 template <typename T>
 void run_step(mlb_mixture_s *h, hipStream_t st)
 {
@@ -326,6 +359,7 @@ void run_step(mlb_mixture_s *h, hipStream_t st)
     const int nblk = h->nblk, M = h->M, par = h->parity;
     pass(h, kPassMoments, st, [&] { mlb::Launch<T>::moments(sys, blk, nblk, par, st); });
     pass(h, kPassContact, st, [&] { mlb::Launch<T>::contact(sys, blk, nblk, tb, st); });
+    if (h->spectral) pass(h, kPassTail, st, [&] { run_tail(h, st); });
     pass(h, kPassGather1, st, [&] { mlb::Launch<T>::gather1(sys, blk, nblk, M, tb, st); });
     pass(h, kPassStep2, st, [&] { mlb::Launch<T>::step2(sys, blk, nblk, M, tb, par, 0, st); });
     h->parity ^= 1;
@@ -347,6 +381,7 @@ mlb_status run_query(mlb_mixture_s *h, T *parts, unsigned mask, hipStream_t st)
     const mlb::Tables<T> tb = h->tables<T>();
     mlb::Launch<T>::moments(sys, h->blk(), h->nblk, h->parity, st);
     mlb::Launch<T>::contact(sys, h->blk(), h->nblk, tb, st);
+    if (h->spectral) run_tail(h, st);
     mlb::Launch<T>::gather1(sys, h->blk(), h->nblk, h->M, tb, st);
     mlb::Launch<T>::step2(sys, h->blk(), h->nblk, h->M, tb, h->parity, 1, st);
     HIP_TRY(hipGetLastError());
@@ -355,6 +390,62 @@ mlb_status run_query(mlb_mixture_s *h, T *parts, unsigned mask, hipStream_t st)
 }
 
 size_t tsize_of(const mlb_params *p) { return p->precision == 64 ? sizeof(double) : sizeof(float); }
+
+// Upload the DFT matrices, place the tail kernels w_ab on the periodic grid
+// (the population buffer f1 serves as scratch; it is overwritten by the
+// first step) and transform them into the sine spectra S_ab.
+mlb_status setup_spectral(mlb_mixture_s *h, hipStream_t st)
+{
+    const mlb_params *p = &h->p;
+    mlb::SpectralPlan &pl = h->plan;
+    char *ws = h->ws;
+    pl.nx = p->nx; pl.ny = p->ny; pl.nz = p->nz; pl.nkx = p->nx / 2 + 1;
+    pl.M = h->M; pl.P = h->P;
+    pl.Sz = (long long)pl.ny * pl.nkx;
+    pl.Sp = pl.Sz * pl.nz;
+    pl.wxf = reinterpret_cast<const float *>(ws + h->L.wxf);
+    pl.wxi = reinterpret_cast<const float *>(ws + h->L.wxi);
+    pl.wyf = reinterpret_cast<const float *>(ws + h->L.wyf);
+    pl.wyi = reinterpret_cast<const float *>(ws + h->L.wyi);
+    pl.wzf = reinterpret_cast<const float *>(ws + h->L.wzf);
+    pl.wzi = reinterpret_cast<const float *>(ws + h->L.wzi);
+    pl.S = reinterpret_cast<float *>(ws + h->L.S);
+    std::vector<float> m[6] = {mlb::SpectralPlan::dft_x_forward(p->nx), mlb::SpectralPlan::dft_x_inverse(p->nx),
+                               mlb::SpectralPlan::dft_block(p->ny, false), mlb::SpectralPlan::dft_block(p->ny, true),
+                               mlb::SpectralPlan::dft_block(p->nz, false), mlb::SpectralPlan::dft_block(p->nz, true)};
+    const size_t offs[6] = {h->L.wxf, h->L.wxi, h->L.wyf, h->L.wyi, h->L.wzf, h->L.wzi};
+    for (int k = 0; k < 6; ++k)
+        HIP_TRY(hipMemcpyAsync(ws + offs[k], m[k].data(), sizeof(float) * m[k].size(), hipMemcpyHostToDevice, st));
+    // kernels on the grid: field (p, d) = sum over the full tail set of w_d(e) at e mod L
+    const long long N = h->N;
+    std::vector<float> placed((size_t)3 * h->P * N, 0.0f);
+    std::vector<double> acc((size_t)3 * N);
+    const HostTables &t = h->tabs;
+    for (int a = 0; a < h->M; ++a)
+        for (int b = a; b < h->M; ++b) {
+            const int pi = a * h->M - (a * (a - 1)) / 2 + (b - a);
+            std::fill(acc.begin(), acc.end(), 0.0);
+            for (int k = 0; k < t.tl_cnt[a][b]; ++k) {
+                int ex, ey, ez;
+                mlb::unpack_offset(t.tl_e[t.tl_start[a][b] + k], ex, ey, ez);
+                for (int sgn = -1; sgn <= 1; sgn += 2) {
+                    const int x = ((sgn * ex) % p->nx + p->nx) % p->nx;
+                    const int y = ((sgn * ey) % p->ny + p->ny) % p->ny;
+                    const int z = ((sgn * ez) % p->nz + p->nz) % p->nz;
+                    const long long site = ((long long)z * p->ny + y) * p->nx + x;
+                    for (int d = 0; d < 3; ++d) acc[(size_t)d * N + site] += sgn * t.tl_w[3 * (t.tl_start[a][b] + k) + d];
+                }
+            }
+            for (int d = 0; d < 3; ++d)
+                for (long long i = 0; i < N; ++i) placed[((size_t)pi * 3 + d) * N + i] = (float)acc[(size_t)d * N + i];
+        }
+    float *scratch = reinterpret_cast<float *>(ws + h->L.f1);
+    HIP_TRY(hipMemcpyAsync(scratch, placed.data(), sizeof(float) * placed.size(), hipMemcpyHostToDevice, st));
+    pl.build_spectrum(scratch, reinterpret_cast<float *>(ws + h->L.s1), reinterpret_cast<float *>(ws + h->L.s2), st);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));   // host staging vectors die here
+    return MLB_OK;
+}
 
 }  // namespace
 
@@ -395,9 +486,10 @@ mlb_status mlb_init_mixture(const mlb_params *p, void *workspace, size_t workspa
     if (workspace_bytes < h->L.total)
         return fail(MLB_ENOMEM, "workspace too small: need " + std::to_string(h->L.total) + " bytes");
     const bool any_tail = !h->tabs.tl_e.empty();
-    if (p->tail_mode == MLB_TAIL_SPECTRAL && any_tail)
-        return fail(MLB_EUNSUPPORTED, "spectral tail not available in this build");
-    h->tail_direct = 1;
+    if (p->tail_mode == MLB_TAIL_SPECTRAL && any_tail && (p->precision != 32 || p->walls_y))
+        return fail(MLB_EUNSUPPORTED, "the spectral tail needs float32 and a periodic box");
+    h->spectral = wants_spectral(p, h->tabs);
+    h->tail_direct = h->spectral ? 0 : 1;
     h->ws = static_cast<char *>(workspace);
     h->sys_host.assign(2 * h->sys_size, 0);
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -413,6 +505,7 @@ mlb_status mlb_init_mixture(const mlb_params *p, void *workspace, size_t workspa
         *h->host_desc<float>(1) = *h->host_desc<float>(0);
         if ((s = upload_tables<float>(h.get(), st)) != MLB_OK) return s;
         if ((s = upload_desc<float>(h.get(), 0, st)) != MLB_OK) return s;
+        if (h->spectral && (s = setup_spectral(h.get(), st)) != MLB_OK) return s;
         mlb::Launch<float>::init_pop(h->dev_desc<float>(0), h->blk(), h->nblk, n0, u0, st);
     }
     mlb::launch_zero_i32(reinterpret_cast<int *>(h->ws + h->L.series_cnt), 1, st);

@@ -146,3 +146,39 @@ def test_conserved_sums_fp64(oracle_lib):
             np.testing.assert_allclose(mass0, d["n"].sum(axis=(1, 2, 3)), rtol=1e-6)
             np.testing.assert_allclose(mass1, mass0, rtol=2e-6)
             assert drift < 6e-8 * mass0.sum() * steps
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 16), (24, 12, 14), (15, 13, 17), (40, 20, 24)])
+def test_fp32_spectral_tail_matches_direct_sum(oracle_lib, shape):
+    """The MFMA DFT path of the attractive field against the oracle's float64
+    direct sum (also checks the matrix-core lane layout: a wrong layout
+    scrambles the field)."""
+    import paper_1105_3634_amd as mlb
+    eps = np.array([[0.15, 0.1], [0.1, 0.05]])
+    m = W.Mixture(*shape, sigma=(1.5, 2.5), eps=eps, rc_factor=2.2)
+    n0, u0 = W.random_state(m, [0.02, 0.01], rel=0.5, u_amp=0.01, seed=21)
+    print(f"[spectral tail] shape={m.shape()}", flush=True)
+    o = oracle_lib.Oracle(m)
+    ref = o.fields(o.init(n0, u0))
+    for mode in (mlb.TAIL_SPECTRAL, mlb.TAIL_DIRECT):
+        g = _gpu(m, n0, u0, 32, tail_mode=mode)
+        got = _np(g.forces(mlb.PART_TAIL))
+        err = np.abs(got - ref["Ntail"]).max() / np.abs(ref["Ntail"]).max()
+        print(f"  mode {mode}: rel err {err:.2e}", flush=True)
+        assert err < 2e-6, (mode, err)
+        tot = _np(g.forces(mlb.PART_ALL))
+        err = np.abs(tot - ref["N"]).max() / np.abs(ref["N"]).max()
+        assert err < 1e-5, (mode, err)
+
+
+def test_fp32_spectral_bulk_diffusion_100_steps(oracle_lib):
+    import paper_1105_3634_amd as mlb
+    m, n0, u0 = _case("bulk_small")
+    o = oracle_lib.Oracle(m)
+    no = o.fields(o.step(o.init(n0, u0), 100))["n"]
+    for mode in (mlb.TAIL_SPECTRAL, mlb.TAIL_DIRECT):
+        g = _gpu(m, n0, u0, 32, tail_mode=mode)
+        g.step(100)
+        e = _rel_maxnorm(_np(g.moments()[0]), no)
+        print(f"  tail mode {mode}: fp32 density rel err {e:.3e}", flush=True)
+        assert e < 1e-5
