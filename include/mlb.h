@@ -174,6 +174,12 @@ mlb_status mlb_profile_begin(mlb_mixture h);
 mlb_status mlb_profile_end(mlb_mixture h, double *ms, int32_t *launches, void *stream);
 const char *mlb_pass_name(int32_t k);
 
+/* Step loop as a graph: when enabled (the default), mlb_step captures two
+ * consecutive steps once into a hipGraph (on a private capture stream) and
+ * replays it on `stream`; odd remainders and profiled runs launch eagerly.
+ * Results are identical either way. */
+mlb_status mlb_set_graph(mlb_mixture h, int32_t enable);
+
 /* Number of steps taken since init. */
 int64_t mlb_step_count(mlb_mixture h);
 
@@ -182,6 +188,50 @@ mlb_status mlb_destroy(mlb_mixture h);
 
 /* Message of the calling thread's last failure ("" if none). */
 const char *mlb_last_error(void);
+
+
+/* ------------------------------------------------------------------------
+ * Batched ensemble: many independent mixtures of uneven size, composition
+ * and packing advanced together.  Every pass of a step is one launch over
+ * the blocks of all systems (a block->system map in the workspace), and the
+ * step loop is replayed as one captured hipGraph.  All systems share the
+ * precision; attractive tails are summed directly (no spectral path) and
+ * float32 batches without tails use the LDS-tile gathers.
+ * ---------------------------------------------------------------------- */
+typedef struct mlb_batch_s *mlb_batch;
+enum { MLB_OPT_TUNE = 1u,       /* time every tile shape and block order at init, keep the fastest */
+       MLB_OPT_NO_GRAPH = 2u }; /* launch the passes eagerly instead of replaying a graph */
+
+/* Workspace bytes for `count` systems described by systems[0..count-1]; 0 if
+ * any is invalid. */
+size_t mlb_batch_workspace_bytes(const mlb_params *systems, int32_t count);
+/* Create the ensemble.  n0[k], u0[k]: DEVICE float64 fields of system k
+ * ([M_k][N_k], [M_k][3][N_k]); the arrays n0 and u0 themselves are HOST
+ * arrays of `count` pointers.  Synchronises `stream`.  With MLB_OPT_TUNE the
+ * autotuner runs full trial steps of every candidate and then restores the
+ * initial populations. */
+mlb_status mlb_init_batch(const mlb_params *systems, int32_t count, void *workspace, size_t workspace_bytes,
+                          const double *const *n0, const double *const *u0, uint32_t options, void *stream,
+                          mlb_batch *out);
+mlb_status mlb_batch_step(mlb_batch h, int32_t nsteps, void *stream);
+/* Per-system views: densities / momenta, populations of system k (device). */
+mlb_status mlb_batch_moments(mlb_batch h, int32_t system, void *n_out, void *j_out, void *stream);
+mlb_status mlb_batch_get_populations(mlb_batch h, int32_t system, void *f_out, void *stream);
+/* Append the (species 0 - species 1) mode amplitude of every system to its
+ * own float64 time series (systems with one species are skipped). */
+mlb_status mlb_batch_record_modes(mlb_batch h, void *stream);
+/* Mode-decay fit of every system (kind 0 of mlb_fit_series): D_out is a
+ * HOST array of `count` values.  Synchronises. */
+mlb_status mlb_batch_fit(mlb_batch h, double t_min, double *D_out, void *stream);
+/* The tile shape (0: 16x4x4, 1: 8x8x4, 2: 32x4x2) and block order (0:
+ * linear, 1: XCD-chunked) in use; trial_ms (HOST, 6 values, may be NULL)
+ * receives the measured milliseconds per step of each candidate
+ * (index 2 * shape + order; 0 when not measured). */
+mlb_status mlb_batch_tuning(mlb_batch h, int32_t *shape, int32_t *order, double *trial_ms);
+mlb_status mlb_batch_profile_begin(mlb_batch h);
+mlb_status mlb_batch_profile_end(mlb_batch h, double *ms, int32_t *launches, void *stream);
+int64_t mlb_batch_step_count(mlb_batch h);
+mlb_status mlb_batch_destroy(mlb_batch h);
 
 #ifdef __cplusplus
 }

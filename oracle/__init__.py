@@ -60,6 +60,8 @@ def _load():
     lib.or_stencil.restype = C.c_int
     lib.or_stencil.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), dp]
     lib.or_pair_constants.argtypes = [C.c_void_p, C.c_int, C.c_int, dp]
+    lib.or_moments.argtypes = [C.c_void_p, dp, dp]
+    lib.or_step_ext.argtypes = [C.c_void_p, dp, dp, dp]
     lib.or_threads.restype = C.c_int
     lib.or_set_threads.argtypes = [C.c_int]
     _lib = lib
@@ -130,6 +132,64 @@ class Oracle:
         out = np.empty_like(f)
         _lib.or_step(self._h, _ptr(f), _ptr(out), int(nsteps))
         return out
+
+    def densities(self, f: np.ndarray) -> np.ndarray:
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        n = np.empty((self.M,) + self.m.shape())
+        _lib.or_moments(self._h, _ptr(f), _ptr(n))
+        return n
+
+    # ---------------------------------------------------- FFT attractive field
+    def _tail_spectra(self):
+        """FFT of the attractive kernels w_ab placed on the periodic grid
+        (the convolution the direct sum evaluates; pinned to it by the tests)."""
+        if getattr(self, "_spec", None) is not None:
+            return self._spec
+        m = self.m
+        eps = m.eps_matrix()
+        spec = {}
+        for a in range(self.M):
+            for b in range(a, self.M):
+                if eps[a, b] == 0:
+                    continue
+                e, w = self.stencil("tail", a, b)
+                K = np.zeros((3,) + m.shape())
+                for sgn in (1, -1):
+                    idx = ((sgn * e[:, 2]) % m.nz, (sgn * e[:, 1]) % m.ny, (sgn * e[:, 0]) % m.nx)
+                    for d in range(3):
+                        np.add.at(K[d], idx, sgn * w[:, d])
+                # sum_e w(e) n(r + e) = ifft(conj(fft(w)) fft(n))
+                spec[(a, b)] = np.conj(np.fft.rfftn(K, axes=(1, 2, 3)))
+        self._spec = spec
+        return spec
+
+    def tail_field_fft(self, n: np.ndarray) -> np.ndarray:
+        """sum_b (K_ab * n_b) [M][3][N] by FFT, float64."""
+        spec = self._tail_spectra()
+        m = self.m
+        nh = np.fft.rfftn(n, axes=(1, 2, 3))
+        out = np.zeros((self.M, 3) + m.shape())
+        for a in range(self.M):
+            acc = None
+            for b in range(self.M):
+                key = (min(a, b), max(a, b))
+                if key not in spec:
+                    continue
+                term = spec[key] * nh[b][None]
+                acc = term if acc is None else acc + term
+            if acc is not None:
+                out[a] = np.fft.irfftn(acc, s=m.shape(), axes=(1, 2, 3))
+        return out
+
+    def step_fft(self, f: np.ndarray, nsteps: int = 1) -> np.ndarray:
+        """Steps with the attractive field by FFT instead of the ordered direct sum."""
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        for _ in range(int(nsteps)):
+            tail = np.ascontiguousarray(self.tail_field_fft(self.densities(f)))
+            out = np.empty_like(f)
+            _lib.or_step_ext(self._h, _ptr(f), _ptr(out), _ptr(tail))
+            f = out
+        return f
 
     def fields(self, f: np.ndarray) -> Dict[str, np.ndarray]:
         f = np.ascontiguousarray(f, dtype=np.float64)

@@ -185,6 +185,8 @@ typedef struct {
     double s2[OR_MAXS], s3[OR_MAXS]; /* (pi/6) sigma^2, (pi/6) sigma^3      */
     /* work fields */
     double *n, *j, *u, *g, *vh, *H, *N2, *Nmf, *Ntl, *Nex, *Dold, *Dnew, *Gam;
+    /* optional externally supplied attractive field sum_b (K_ab * n_b) [M][3][N] */
+    const double *tail_ext;
 } or_ctx;
 
 static int pair_index(int M, int a, int b)
@@ -466,7 +468,7 @@ static void gather_one(or_ctx *c)
                     dv[d] = dv[d] + c->ck[a][b] * sdv[d];
                 }
                 gam = gam + c->cg[a][b] * sg;
-                if (c->has_tail[a][b]) {
+                if (c->has_tail[a][b] && !c->tail_ext) {
                     const or_list *T = &c->tail[a][b];
                     double st[3] = {0.0, 0.0, 0.0};
                     for (int k = 0; k < T->n; ++k) {
@@ -481,6 +483,8 @@ static void gather_one(or_ctx *c)
                     tl[0] = tl[0] + st[0]; tl[1] = tl[1] + st[1]; tl[2] = tl[2] + st[2];
                 }
             }
+            if (c->tail_ext)
+                for (int d = 0; d < 3; ++d) tl[d] = c->tail_ext[o3 + (size_t)d * N + s];
             double hg = 0.5 * gam;
             for (int d = 0; d < 3; ++d) {
                 double Nmf = na * mf[d];
@@ -688,6 +692,27 @@ void or_step(or_ctx *c, const double *fin, double *fout, int nsteps)
     }
     if (nsteps <= 0) memcpy(fout, a, sizeof(double) * nf);
     free(a);
+}
+
+/* Species densities of f (S1 only), n [M][N]. */
+void or_moments(or_ctx *c, const double *f, double *n)
+{
+    moments(c, f);
+    memcpy(n, c->n, sizeof(double) * (size_t)c->M * (size_t)c->N);
+}
+
+/* One step with the attractive field supplied by the caller: tail[M][3][N]
+ * = sum_b sum_{e in T_ab} w_ab(e) n_b(r + e) for the densities of fin (the
+ * same convolution the direct sum evaluates, e.g. computed by FFT). */
+void or_step_ext(or_ctx *c, const double *fin, double *fout, const double *tail)
+{
+    c->tail_ext = tail;
+    moments(c, fin);
+    contact_values(c);
+    gather_one(c);
+    gather_two(c);
+    collide_stream(c, fin, fout);
+    c->tail_ext = NULL;
 }
 
 /* Evaluate S1-S4 on f and expose every intermediate field.  Any output

@@ -13,10 +13,10 @@ from typing import Dict, Optional, Sequence
 import numpy as np
 
 from . import _lib
-from ._lib import (MlbError, PART_ALL, PART_DISS, PART_EXT, PART_MF, PART_TAIL, Q, SCHEME_CN_J1, SCHEME_FE,
-                   TAIL_AUTO, TAIL_DIRECT, TAIL_SPECTRAL)
+from ._lib import (MlbError, OPT_NO_GRAPH, OPT_TUNE, PART_ALL, PART_DISS, PART_EXT, PART_MF, PART_TAIL, Q,
+                   SCHEME_CN_J1, SCHEME_FE, TAIL_AUTO, TAIL_DIRECT, TAIL_SPECTRAL)
 
-__all__ = ["GpuMixture", "make_params", "workspace_bytes", "MlbError", "PART_ALL", "PART_MF", "PART_TAIL",
+__all__ = ["GpuMixture", "GpuBatch", "OPT_TUNE", "OPT_NO_GRAPH", "make_params", "workspace_bytes", "MlbError", "PART_ALL", "PART_MF", "PART_TAIL",
            "PART_DISS", "PART_EXT", "TAIL_AUTO", "TAIL_DIRECT", "TAIL_SPECTRAL", "SCHEME_CN_J1", "SCHEME_FE"]
 
 
@@ -114,6 +114,9 @@ class GpuMixture:
     def step(self, nsteps: int = 1) -> None:
         _lib.check(self.lib.mlb_step(self.h, int(nsteps), _stream_handle(self.stream)), "mlb_step")
 
+    def set_graph(self, enable: bool) -> None:
+        _lib.check(self.lib.mlb_set_graph(self.h, 1 if enable else 0), "mlb_set_graph")
+
     @property
     def steps(self) -> int:
         return int(self.lib.mlb_step_count(self.h))
@@ -198,3 +201,99 @@ class GpuMixture:
                    "mlb_get_series")
         n = cnt.value
         return np.array(t[:n]), np.array(v[:n])
+
+
+class GpuBatch:
+    """An ensemble of independent mixtures advanced by shared launches."""
+
+    SHAPES = ("16x4x4", "8x8x4", "32x4x2")
+
+    def __init__(self, mixes: Sequence, n0s: Sequence[np.ndarray], u0s: Sequence[np.ndarray], precision: int = 32,
+                 options: int = 0, device: str = "cuda:0", stream=None):
+        torch = _torch()
+        self.lib = _lib.load()
+        self.count = len(mixes)
+        self.params = (_lib.Params * self.count)(*[make_params(m, precision, TAIL_DIRECT) for m in mixes])
+        self.mixes = list(mixes)
+        self.device = torch.device(device)
+        self.dtype = torch.float64 if precision == 64 else torch.float32
+        self.stream = stream
+        nbytes = self.lib.mlb_batch_workspace_bytes(self.params, self.count)
+        if nbytes == 0:
+            raise MlbError(-1, "mlb_batch_workspace_bytes", self.lib.mlb_last_error().decode())
+        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self._ws_raw = raw
+        self.ws = raw[off:off + nbytes]
+        self._n0 = [torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(self.device) for a in n0s]
+        self._u0 = [torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(self.device) for a in u0s]
+        n0p = (C.c_void_p * self.count)(*[t.data_ptr() for t in self._n0])
+        u0p = (C.c_void_p * self.count)(*[t.data_ptr() for t in self._u0])
+        h = C.c_void_p()
+        _lib.check(self.lib.mlb_init_batch(self.params, self.count, C.c_void_p(self.ws.data_ptr()), nbytes, n0p, u0p,
+                                           int(options), _stream_handle(stream), C.byref(h)), "mlb_init_batch")
+        self.h = h
+        self._n0 = self._u0 = None
+
+    def close(self) -> None:
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.mlb_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, nsteps: int = 1) -> None:
+        _lib.check(self.lib.mlb_batch_step(self.h, int(nsteps), _stream_handle(self.stream)), "mlb_batch_step")
+
+    @property
+    def steps(self) -> int:
+        return int(self.lib.mlb_batch_step_count(self.h))
+
+    def _shape(self, k):
+        m = self.mixes[k]
+        return len(m.sigma), (int(m.nz), int(m.ny), int(m.nx))
+
+    def moments(self, k: int):
+        torch = _torch()
+        M, sh = self._shape(k)
+        n = torch.empty((M,) + sh, dtype=self.dtype, device=self.device)
+        j = torch.empty((M, 3) + sh, dtype=self.dtype, device=self.device)
+        _lib.check(self.lib.mlb_batch_moments(self.h, k, C.c_void_p(n.data_ptr()), C.c_void_p(j.data_ptr()),
+                                              _stream_handle(self.stream)), "mlb_batch_moments")
+        return n, j
+
+    def populations(self, k: int):
+        torch = _torch()
+        M, sh = self._shape(k)
+        f = torch.empty((M, Q) + sh, dtype=self.dtype, device=self.device)
+        _lib.check(self.lib.mlb_batch_get_populations(self.h, k, C.c_void_p(f.data_ptr()), _stream_handle(self.stream)),
+                   "mlb_batch_get_populations")
+        return f
+
+    def record_modes(self) -> None:
+        _lib.check(self.lib.mlb_batch_record_modes(self.h, _stream_handle(self.stream)), "mlb_batch_record_modes")
+
+    def fit(self, t_min: float = 0.0) -> np.ndarray:
+        out = (C.c_double * self.count)()
+        _lib.check(self.lib.mlb_batch_fit(self.h, float(t_min), out, _stream_handle(self.stream)), "mlb_batch_fit")
+        return np.array(out[:])
+
+    def tuning(self):
+        shape, order = C.c_int32(), C.c_int32()
+        ms = (C.c_double * 6)()
+        _lib.check(self.lib.mlb_batch_tuning(self.h, C.byref(shape), C.byref(order), ms), "mlb_batch_tuning")
+        return {"shape": int(shape.value), "order": int(order.value), "trial_ms": list(ms[:])}
+
+    def profile_begin(self) -> None:
+        _lib.check(self.lib.mlb_batch_profile_begin(self.h), "mlb_batch_profile_begin")
+
+    def profile_end(self) -> Dict[str, tuple]:
+        ms = (C.c_double * _lib.NPASS)()
+        cnt = (C.c_int32 * _lib.NPASS)()
+        _lib.check(self.lib.mlb_batch_profile_end(self.h, ms, cnt, _stream_handle(self.stream)),
+                   "mlb_batch_profile_end")
+        return {self.lib.mlb_pass_name(k).decode(): (ms[k], cnt[k]) for k in range(_lib.NPASS)}

@@ -69,9 +69,24 @@ _SIGS = [
     ("mlb_profile_begin", C.c_int, [C.c_void_p]),
     ("mlb_profile_end", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_void_p]),
     ("mlb_pass_name", C.c_char_p, [C.c_int32]),
+    ("mlb_set_graph", C.c_int, [C.c_void_p, C.c_int32]),
     ("mlb_destroy", C.c_int, [C.c_void_p]),
     ("mlb_last_error", C.c_char_p, []),
+    ("mlb_batch_workspace_bytes", C.c_size_t, [C.POINTER(Params), C.c_int32]),
+    ("mlb_init_batch", C.c_int, [C.POINTER(Params), C.c_int32, C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p),
+                                 C.POINTER(C.c_void_p), C.c_uint32, C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("mlb_batch_step", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    ("mlb_batch_moments", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("mlb_batch_get_populations", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    ("mlb_batch_record_modes", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("mlb_batch_fit", C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_double), C.c_void_p]),
+    ("mlb_batch_tuning", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    ("mlb_batch_profile_begin", C.c_int, [C.c_void_p]),
+    ("mlb_batch_profile_end", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_void_p]),
+    ("mlb_batch_step_count", C.c_int64, [C.c_void_p]),
+    ("mlb_batch_destroy", C.c_int, [C.c_void_p]),
 ]
+OPT_TUNE, OPT_NO_GRAPH = 1, 2
 
 _lib = None
 

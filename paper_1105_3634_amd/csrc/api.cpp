@@ -1,17 +1,22 @@
 // C ABI of the mlb library (declared in include/mlb.h).
 //
-// A mixture is a batch of one system in the batched kernel layout: the
-// system descriptor, the block->system map, the stencil tables and all
-// fields live in the caller's workspace; this file validates parameters,
-// builds the tables on the host, lays out the workspace and sequences the
-// passes of each step on the caller's stream.
+// The core object is a batch of lattice systems.  A mixture is a batch of
+// one.  All device memory is the caller's workspace; this file validates
+// parameters, builds the stencil tables on the host, lays out the
+// workspace, builds the block->system maps, sequences the passes of a step
+// on the caller's stream (optionally replaying a captured hipGraph) and
+// runs the autotuner.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/mlb.h"
@@ -35,21 +40,29 @@ mlb_status fail(mlb_status st, const std::string &msg)
             return fail(MLB_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+#define TRY(expr)                    \
+    do {                             \
+        mlb_status s_ = (expr);      \
+        if (s_ != MLB_OK) return s_; \
+    } while (0)
+
 constexpr size_t kAlign = 256;
 constexpr int kSeriesCap = 8192;
 constexpr int kRedParts = 512;
+constexpr int kXcds = 8;   // MI355X: workgroups are dealt round-robin over 8 XCDs
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-// Host view of the tables of one system.
+// ----------------------------------------------------------- host tables
 struct HostTables {
     std::vector<int32_t> sh_e, tl_e, bl_e;
-    std::vector<double> sh_u, tl_w;
+    std::vector<double> sh_u, sh_ee, tl_w;
     int sh_start[mlb::kMaxS][mlb::kMaxS] = {}, sh_cnt[mlb::kMaxS][mlb::kMaxS] = {};
     int sh_full[mlb::kMaxS][mlb::kMaxS] = {};
     int tl_start[mlb::kMaxS][mlb::kMaxS] = {}, tl_cnt[mlb::kMaxS][mlb::kMaxS] = {};
     int bl_start[mlb::kMaxS] = {}, bl_cnt[mlb::kMaxS] = {}, bl_full[mlb::kMaxS] = {};
     int reach[3] = {0, 0, 0};
+    int shell_reach = 0;
 };
 
 bool validate(const mlb_params *p, std::string &why)
@@ -58,6 +71,7 @@ bool validate(const mlb_params *p, std::string &why)
     const int M = p->nspecies;
     if (M < 1 || M > MLB_MAX_SPECIES) { why = "nspecies must be 1..4"; return false; }
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) { why = "lattice sizes must be positive"; return false; }
+    if ((long long)p->nx * p->ny * p->nz > (1LL << 31) / 4) { why = "lattice too large"; return false; }
     if (p->precision != 32 && p->precision != 64) { why = "precision must be 32 or 64"; return false; }
     if (p->scheme != MLB_SCHEME_CN_J1 && p->scheme != MLB_SCHEME_FE) { why = "unknown scheme"; return false; }
     if (p->tail_mode < MLB_TAIL_AUTO || p->tail_mode > MLB_TAIL_SPECTRAL) { why = "unknown tail mode"; return false; }
@@ -100,6 +114,12 @@ bool build_tables(const mlb_params *p, HostTables &t, std::string &why)
             t.sh_full[a][b] = sh.full;
             t.sh_e.insert(t.sh_e.end(), sh.e.begin(), sh.e.end());
             t.sh_u.insert(t.sh_u.end(), sh.v.begin(), sh.v.end());
+            for (size_t k = 0; k < sh.e.size(); ++k) {
+                const double *u = &sh.v[3 * k];
+                const double ee[6] = {u[0] * u[0], u[0] * u[1], u[0] * u[2], u[1] * u[1], u[1] * u[2], u[2] * u[2]};
+                t.sh_ee.insert(t.sh_ee.end(), ee, ee + 6);
+            }
+            for (int d = 0; d < 3; ++d) t.shell_reach = std::max(t.shell_reach, sh.max_abs[d]);
             reach(sh);
             const double eps = p->eps[a * MLB_MAX_SPECIES + b];
             if (eps > 0.0) {
@@ -132,298 +152,373 @@ bool build_tables(const mlb_params *p, HostTables &t, std::string &why)
     return true;
 }
 
-struct Layout {
-    size_t sys, blk, sh_e, sh_u, tl_e, tl_w, bl_e;
-    size_t f0, f1, n, j, u, g, vh, H, Nf;
-    size_t red, red_out, series, series_cnt, fit_out;
-    // spectral tail (float32 only)
-    size_t wxf, wxi, wyf, wyi, wzf, wzi, S, s1, s2, tail;
-    size_t total;
-};
+bool has_tail(const HostTables &t) { return !t.tl_e.empty(); }
 
-// Spectral mode: float32, a tail on some pair, y periodic.
-bool wants_spectral(const mlb_params *p, const HostTables &t)
+// Spectral attractive field: float32, a tail on some pair, y periodic, single system.
+bool wants_spectral(const mlb_params *p, const HostTables &t, int count)
 {
-    if (t.tl_e.empty() || p->walls_y || p->precision != 32) return false;
+    if (!has_tail(t) || p->walls_y || p->precision != 32 || count != 1) return false;
     return p->tail_mode == MLB_TAIL_AUTO || p->tail_mode == MLB_TAIL_SPECTRAL;
 }
 
-Layout make_layout(const mlb_params *p, const HostTables &t, size_t tsize, size_t sys_size, int nblk)
-{
-    const size_t M = (size_t)p->nspecies, N = (size_t)p->nx * p->ny * p->nz;
-    const size_t P = M * (M + 1) / 2;
-    Layout L{};
-    size_t off = 0;
-    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + std::max<size_t>(bytes, 1)); return o; };
-    L.sys = take(2 * sys_size);
-    L.blk = take(sizeof(int) * (size_t)nblk);
-    L.sh_e = take(sizeof(int32_t) * t.sh_e.size());
-    L.sh_u = take(tsize * t.sh_u.size());
-    L.tl_e = take(sizeof(int32_t) * t.tl_e.size());
-    L.tl_w = take(tsize * t.tl_w.size());
-    L.bl_e = take(sizeof(int32_t) * t.bl_e.size());
-    L.f0 = take(tsize * M * mlb::kQ * N);
-    L.f1 = take(tsize * M * mlb::kQ * N);
-    L.n = take(tsize * M * N);
-    L.j = take(tsize * 3 * M * N);
-    L.u = take(tsize * 3 * N);
-    L.g = take(tsize * P * N);
-    L.vh = take(tsize * 3 * M * N);
-    L.H = take(tsize * 3 * M * N);
-    L.Nf = take(tsize * 3 * M * N);
-    L.red = take(sizeof(double) * kRedParts * 16);
-    L.red_out = take(sizeof(double) * 16);
-    L.series = take(sizeof(double) * 2 * kSeriesCap);
-    L.series_cnt = take(sizeof(int));
-    L.fit_out = take(sizeof(double) * 4);
-    if (wants_spectral(p, t)) {
-        const size_t nkx = (size_t)p->nx / 2 + 1, Sp = nkx * p->ny * p->nz;
-        const size_t fields = std::max(3 * M, 3 * P);
-        L.wxf = take(sizeof(float) * p->nx * 2 * nkx);
-        L.wxi = take(sizeof(float) * 2 * nkx * p->nx);
-        L.wyf = take(sizeof(float) * 4 * p->ny * p->ny);
-        L.wyi = take(sizeof(float) * 4 * p->ny * p->ny);
-        L.wzf = take(sizeof(float) * 4 * p->nz * p->nz);
-        L.wzi = take(sizeof(float) * 4 * p->nz * p->nz);
-        L.S = take(sizeof(float) * 3 * P * Sp);
-        L.s1 = take(sizeof(float) * 2 * fields * Sp);
-        L.s2 = take(sizeof(float) * 2 * fields * Sp);
-        L.tail = take(sizeof(float) * 3 * M * N);
-    }
-    L.total = off;
-    return L;
-}
-
-}  // namespace
-
-// --------------------------------------------------------------- the handle
-struct mlb_mixture_s {
-    mlb_params p;
+// ----------------------------------------------------------- per system
+struct SysHost {
+    mlb_params p{};
     int M = 0, P = 0;
     long long N = 0;
-    int nblk = 0;
-    char *ws = nullptr;
-    Layout L{};
     HostTables tabs;
-    int parity = 0;
-    int64_t steps = 0;
-    std::vector<unsigned char> sys_host;   // two descriptors: [0] stepping, [1] query
-    size_t sys_size = 0;
-    int tail_direct = 1;
+    int sh_base = 0, tl_base = 0, bl_base = 0;   // offsets into the batch tables
     bool spectral = false;
     mlb::SpectralPlan plan;
-    // per-pass event timing
-    bool profiling = false;
-    std::vector<hipEvent_t> events;          // pool, reused
-    std::vector<std::pair<int, int>> marks;  // (pass, index of the start event)
-    size_t next_event = 0;
-    ~mlb_mixture_s()
-    {
-        for (hipEvent_t e : events) (void)hipEventDestroy(e);
-    }
-
-    template <typename T> mlb::SysDesc<T> *host_desc(int k) { return reinterpret_cast<mlb::SysDesc<T> *>(sys_host.data() + k * sys_size); }
-    template <typename T> const mlb::SysDesc<T> *dev_desc(int k) const { return reinterpret_cast<const mlb::SysDesc<T> *>(ws + L.sys + k * sys_size); }
-    const int *blk() const { return reinterpret_cast<const int *>(ws + L.blk); }
-    template <typename T> mlb::Tables<T> tables() const
-    {
-        mlb::Tables<T> tb;
-        tb.sh_e = reinterpret_cast<const int32_t *>(ws + L.sh_e);
-        tb.sh_u = reinterpret_cast<const T *>(ws + L.sh_u);
-        tb.tl_e = reinterpret_cast<const int32_t *>(ws + L.tl_e);
-        tb.tl_w = reinterpret_cast<const T *>(ws + L.tl_w);
-        tb.bl_e = reinterpret_cast<const int32_t *>(ws + L.bl_e);
-        return tb;
-    }
+    int nblocks = 0;
+    size_t f0 = 0, f1 = 0, n = 0, j = 0, u = 0, g = 0, vh = 0, H = 0, Nf = 0, Tloc = 0;
+    size_t wxf = 0, wxi = 0, wyf = 0, wyi = 0, wzf = 0, wzi = 0, S = 0, s1 = 0, s2 = 0, tail = 0;
+    size_t series = 0, series_cnt = 0;
 };
 
-namespace {
+struct Tuning {
+    int shape = 0, order = 1;
+    double trial_ms[2 * mlb::kTileVariants] = {0, 0, 0, 0, 0, 0};
+};
 
-template <typename T>
-void fill_desc(mlb_mixture_s *h, mlb::SysDesc<T> &S)
-{
-    const mlb_params *p = &h->p;
-    std::memset(&S, 0, sizeof(S));
-    S.nx = p->nx; S.ny = p->ny; S.nz = p->nz; S.M = h->M; S.P = h->P; S.walls = p->walls_y ? 1 : 0;
-    S.N = h->N;
-    S.block_start = 0;
-    S.nblocks = h->nblk;
-    char *ws = h->ws;
-    S.f[0] = reinterpret_cast<T *>(ws + h->L.f0);
-    S.f[1] = reinterpret_cast<T *>(ws + h->L.f1);
-    S.n = reinterpret_cast<T *>(ws + h->L.n);
-    S.j = reinterpret_cast<T *>(ws + h->L.j);
-    S.u = reinterpret_cast<T *>(ws + h->L.u);
-    S.g = reinterpret_cast<T *>(ws + h->L.g);
-    S.vh = reinterpret_cast<T *>(ws + h->L.vh);
-    S.H = reinterpret_cast<T *>(ws + h->L.H);
-    S.Nf = reinterpret_cast<T *>(ws + h->L.Nf);
-    S.tail = h->spectral ? reinterpret_cast<T *>(ws + h->L.tail) : nullptr;
-    S.parts = nullptr;
-    S.parts_mask = 0;
-    S.tail_direct = h->tail_direct;
-    S.scheme = p->scheme;
-    S.omega_is_one = (1.0 / p->tau == 1.0) ? 1 : 0;
-    const HostTables &t = h->tabs;
-    for (int a = 0; a < h->M; ++a) {
-        S.bl_start[a] = t.bl_start[a]; S.bl_cnt[a] = t.bl_cnt[a]; S.bl_full[a] = t.bl_full[a];
-        const double sg = p->sigma[a];
-        S.s2[a] = (T)((M_PI / 6.0) * (sg * sg));
-        S.s3[a] = (T)((M_PI / 6.0) * ((sg * sg) * sg));
-        for (int d = 0; d < 3; ++d) S.fext[a][d] = (T)p->ext_force[a * 3 + d];
-        for (int b = 0; b < h->M; ++b) {
-            S.sh_start[a][b] = t.sh_start[a][b]; S.sh_cnt[a][b] = t.sh_cnt[a][b];
-            S.tl_start[a][b] = t.tl_start[a][b]; S.tl_cnt[a][b] = t.tl_cnt[a][b];
-            const mlb::PairConst c = mlb::pair_constants(p->sigma[a], p->sigma[b], p->kT, t.sh_full[a][b]);
-            S.cm[a][b] = (T)c.cm; S.cg[a][b] = (T)c.cg; S.ck[a][b] = (T)c.ck; S.dd[a][b] = (T)c.dd;
-        }
-    }
-    const double omega = 1.0 / p->tau;
-    S.omega = (T)omega;
-    S.om1 = (T)(1.0 - omega);
-    S.wall_ux[0] = (T)p->wall_ux[0];
-    S.wall_ux[1] = (T)p->wall_ux[1];
-}
-
-template <typename T>
-mlb_status upload_tables(mlb_mixture_s *h, hipStream_t st)
-{
-    const HostTables &t = h->tabs;
-    std::vector<T> su(t.sh_u.begin(), t.sh_u.end()), tw(t.tl_w.begin(), t.tl_w.end());
-    char *ws = h->ws;
-    if (!t.sh_e.empty()) HIP_TRY(hipMemcpyAsync(ws + h->L.sh_e, t.sh_e.data(), 4 * t.sh_e.size(), hipMemcpyHostToDevice, st));
-    if (!su.empty()) HIP_TRY(hipMemcpyAsync(ws + h->L.sh_u, su.data(), sizeof(T) * su.size(), hipMemcpyHostToDevice, st));
-    if (!t.tl_e.empty()) HIP_TRY(hipMemcpyAsync(ws + h->L.tl_e, t.tl_e.data(), 4 * t.tl_e.size(), hipMemcpyHostToDevice, st));
-    if (!tw.empty()) HIP_TRY(hipMemcpyAsync(ws + h->L.tl_w, tw.data(), sizeof(T) * tw.size(), hipMemcpyHostToDevice, st));
-    if (!t.bl_e.empty()) HIP_TRY(hipMemcpyAsync(ws + h->L.bl_e, t.bl_e.data(), 4 * t.bl_e.size(), hipMemcpyHostToDevice, st));
-    std::vector<int> blk((size_t)h->nblk, 0);
-    HIP_TRY(hipMemcpyAsync(ws + h->L.blk, blk.data(), sizeof(int) * blk.size(), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipStreamSynchronize(st));   // host staging vectors die here
-    return MLB_OK;
-}
-
-template <typename T>
-mlb_status upload_desc(mlb_mixture_s *h, int k, hipStream_t st)
-{
-    HIP_TRY(hipMemcpyAsync(h->ws + h->L.sys + k * h->sys_size, h->sys_host.data() + k * h->sys_size, h->sys_size,
-                           hipMemcpyHostToDevice, st));
-    return MLB_OK;
-}
+// Autotuner results keyed by a signature of the batch (process-wide).
+std::mutex g_tune_mu;
+std::map<std::string, Tuning> g_tune_cache;
 
 enum { kPassMoments = 0, kPassContact = 1, kPassTail = 2, kPassGather1 = 3, kPassStep2 = 4 };
 const char *kPassNames[MLB_NPASS] = {"moments", "contact", "tail", "gather1", "step2"};
 
-hipEvent_t take_event(mlb_mixture_s *h)
-{
-    if (h->next_event == h->events.size()) {
-        hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        h->events.push_back(e);
-    }
-    return h->events[h->next_event++];
-}
+}  // namespace
 
-// Run one pass; when profiling, bracket it with an event pair on `st`.
-template <typename F>
-void pass(mlb_mixture_s *h, int id, hipStream_t st, F &&launch)
-{
-    if (!h->profiling) {
-        launch();
-        return;
-    }
-    const size_t k = h->next_event;
-    hipEvent_t a = take_event(h), b = take_event(h);
-    if (!a || !b) {
-        launch();
-        return;
-    }
-    (void)hipEventRecord(a, st);
-    launch();
-    (void)hipEventRecord(b, st);
-    h->marks.emplace_back(id, (int)k);
-}
+// ---------------------------------------------------------------- the core
+struct mlb_batch_s {
+    int count = 0, prec = 32, maxM = 1, reach_max = 0;
+    bool tiled = false;
+    std::vector<SysHost> sys;
+    char *ws = nullptr;
+    size_t total = 0;
+    // shared regions
+    size_t desc = 0, map_site = 0, map_tile = 0, map_ident = 0;
+    size_t t_sh_e = 0, t_sh_u = 0, t_sh_ee = 0, t_tl_e = 0, t_tl_w = 0, t_bl_e = 0;
+    size_t red = 0, red_out = 0, fit_out = 0;
+    size_t desc_size = 0;
+    int nblk_site = 0, nblk_tile = 0, ident_len = 0;
+    int map_tile_cap = 0;
+    Tuning tune;
+    std::vector<unsigned char> desc_host;   // count stepping descriptors + 1 query descriptor
+    int parity = 0;
+    int64_t steps = 0;
+    // per-pass timing
+    bool profiling = false;
+    std::vector<hipEvent_t> events;
+    std::vector<std::pair<int, int>> marks;
+    size_t next_event = 0;
+    // graph of two steps (starting at parity 0)
+    bool use_graph = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph = nullptr;
 
-void run_tail(mlb_mixture_s *h, hipStream_t st)
+    virtual ~mlb_batch_s()
+    {
+        if (graph) (void)hipGraphExecDestroy(graph);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    }
+    template <typename T> mlb::SysDesc<T> *hdesc(int k) { return reinterpret_cast<mlb::SysDesc<T> *>(desc_host.data() + k * desc_size); }
+    template <typename T> const mlb::SysDesc<T> *ddesc(int k) const { return reinterpret_cast<const mlb::SysDesc<T> *>(ws + desc + k * desc_size); }
+    const int2 *map_of(size_t off) const { return reinterpret_cast<const int2 *>(ws + off); }
+    template <typename T> mlb::Tables<T> tables() const
+    {
+        mlb::Tables<T> tb;
+        tb.sh_e = reinterpret_cast<const int32_t *>(ws + t_sh_e);
+        tb.sh_u = reinterpret_cast<const T *>(ws + t_sh_u);
+        tb.sh_ee = reinterpret_cast<const T *>(ws + t_sh_ee);
+        tb.tl_e = reinterpret_cast<const int32_t *>(ws + t_tl_e);
+        tb.tl_w = reinterpret_cast<const T *>(ws + t_tl_w);
+        tb.bl_e = reinterpret_cast<const int32_t *>(ws + t_bl_e);
+        return tb;
+    }
+};
+
+struct mlb_mixture_s : mlb_batch_s {};
+
+namespace {
+
+using Batch = mlb_batch_s;
+
+size_t tsize_of(int prec) { return prec == 64 ? sizeof(double) : sizeof(float); }
+
+// ---------------------------------------------------------------- layout
+// Prepare every SysHost (tables, flags) and lay out the workspace.
+bool plan_batch(Batch &B, const mlb_params *params, int count, std::string &why)
 {
-    char *ws = h->ws;
-    h->plan.apply(reinterpret_cast<const float *>(ws + h->L.n), reinterpret_cast<float *>(ws + h->L.s1),
-                  reinterpret_cast<float *>(ws + h->L.s2), reinterpret_cast<float *>(ws + h->L.tail), st);
+    if (count < 1) { why = "count must be >= 1"; return false; }
+    B.count = count;
+    B.prec = params[0].precision;
+    B.sys.resize(count);
+    B.maxM = 1;
+    B.reach_max = 0;
+    bool any_direct_tail = false;
+    for (int k = 0; k < count; ++k) {
+        if (!validate(&params[k], why)) { why = "system " + std::to_string(k) + ": " + why; return false; }
+        if (params[k].precision != B.prec) { why = "all systems must share the precision"; return false; }
+        SysHost &S = B.sys[k];
+        S.p = params[k];
+        if (!build_tables(&S.p, S.tabs, why)) { why = "system " + std::to_string(k) + ": " + why; return false; }
+        S.M = S.p.nspecies;
+        S.P = S.M * (S.M + 1) / 2;
+        S.N = (long long)S.p.nx * S.p.ny * S.p.nz;
+        S.nblocks = (int)((S.N + mlb::kBlock - 1) / mlb::kBlock);
+        if (S.p.tail_mode == MLB_TAIL_SPECTRAL && has_tail(S.tabs) && (B.prec != 32 || S.p.walls_y || count != 1)) {
+            why = "the spectral tail needs float32, a periodic box and a single system";
+            return false;
+        }
+        S.spectral = wants_spectral(&S.p, S.tabs, count);
+        any_direct_tail = any_direct_tail || (has_tail(S.tabs) && !S.spectral);
+        B.maxM = std::max(B.maxM, S.M);
+        B.reach_max = std::max(B.reach_max, S.tabs.shell_reach);
+    }
+    bool fits = true;
+    for (int v = 0; v < mlb::kTileVariants; ++v) fits = fits && mlb::tile_lds_bytes_of(v, B.reach_max) <= 160 * 1024;
+    B.tiled = B.prec == 32 && !any_direct_tail && fits;
+    const size_t ts = tsize_of(B.prec);
+    B.desc_size = align_up(B.prec == 64 ? sizeof(mlb::SysDesc<double>) : sizeof(mlb::SysDesc<float>));
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + std::max<size_t>(bytes, 1)); return o; };
+    B.desc = take((size_t)(count + 1) * B.desc_size);
+    // maps
+    B.nblk_site = 0;
+    int max_tiles_any = 0, ident = 0, tiles_total_max = 0;
+    for (auto &S : B.sys) {
+        B.nblk_site += S.nblocks;
+        ident = std::max(ident, S.nblocks);
+    }
+    for (int v = 0; v < mlb::kTileVariants; ++v) {
+        int tot = 0;
+        for (auto &S : B.sys) {
+            const int nt = mlb::tile_count(v, S.p.nx, S.p.ny, S.p.nz);
+            tot += nt;
+            max_tiles_any = std::max(max_tiles_any, nt);
+        }
+        tiles_total_max = std::max(tiles_total_max, tot);
+    }
+    B.ident_len = std::max(ident, max_tiles_any);
+    B.map_tile_cap = (tiles_total_max + kXcds - 1) / kXcds * kXcds;
+    B.map_site = take(sizeof(int2) * (size_t)B.nblk_site);
+    B.map_tile = take(sizeof(int2) * (size_t)B.map_tile_cap);
+    B.map_ident = take(sizeof(int2) * (size_t)B.ident_len);
+    // tables (concatenated)
+    size_t nsh = 0, ntl = 0, nbl = 0;
+    for (auto &S : B.sys) {
+        S.sh_base = (int)nsh; S.tl_base = (int)ntl; S.bl_base = (int)nbl;
+        nsh += S.tabs.sh_e.size(); ntl += S.tabs.tl_e.size(); nbl += S.tabs.bl_e.size();
+    }
+    B.t_sh_e = take(4 * nsh);
+    B.t_sh_u = take(ts * 3 * nsh);
+    B.t_sh_ee = take(ts * 6 * nsh);
+    B.t_tl_e = take(4 * ntl);
+    B.t_tl_w = take(ts * 3 * ntl);
+    B.t_bl_e = take(4 * nbl);
+    B.red = take(sizeof(double) * kRedParts * 16);
+    B.red_out = take(sizeof(double) * 16);
+    B.fit_out = take(sizeof(double) * 4 * (size_t)count);
+    for (auto &S : B.sys) {
+        const size_t M = (size_t)S.M, N = (size_t)S.N, P = (size_t)S.P;
+        S.f0 = take(ts * M * mlb::kQ * N);
+        S.f1 = take(ts * M * mlb::kQ * N);
+        S.n = take(ts * M * N);
+        S.j = take(ts * 3 * M * N);
+        S.u = take(ts * 3 * N);
+        S.g = take(ts * P * N);
+        S.vh = take(ts * 3 * M * N);
+        S.H = take(ts * 3 * M * N);
+        S.Nf = take(ts * 3 * M * N);
+        S.Tloc = B.tiled ? take(ts * 6 * M * N) : 0;
+        if (S.spectral) {
+            const size_t nkx = (size_t)S.p.nx / 2 + 1, Sp = nkx * S.p.ny * S.p.nz;
+            const size_t fields = std::max(3 * M, 3 * P);
+            S.wxf = take(sizeof(float) * S.p.nx * 2 * nkx);
+            S.wxi = take(sizeof(float) * 2 * nkx * S.p.nx);
+            S.wyf = take(sizeof(float) * 4 * S.p.ny * S.p.ny);
+            S.wyi = take(sizeof(float) * 4 * S.p.ny * S.p.ny);
+            S.wzf = take(sizeof(float) * 4 * S.p.nz * S.p.nz);
+            S.wzi = take(sizeof(float) * 4 * S.p.nz * S.p.nz);
+            S.S = take(sizeof(float) * 3 * P * Sp);
+            S.s1 = take(sizeof(float) * 2 * fields * Sp);
+            S.s2 = take(sizeof(float) * 2 * fields * Sp);
+            S.tail = take(sizeof(float) * 3 * M * N);
+        }
+        S.series = take(sizeof(double) * 2 * kSeriesCap);
+        S.series_cnt = take(sizeof(int));
+    }
+    B.total = off;
+    return true;
 }
 
 template <typename T>
-void run_step(mlb_mixture_s *h, hipStream_t st)
+void fill_desc(Batch &B, int k, mlb::SysDesc<T> &D)
 {
-    const mlb::SysDesc<T> *sys = h->dev_desc<T>(0);
-    const mlb::Tables<T> tb = h->tables<T>();
-    const int *blk = h->blk();
-    const int nblk = h->nblk, M = h->M, par = h->parity;
-    pass(h, kPassMoments, st, [&] { mlb::Launch<T>::moments(sys, blk, nblk, par, st); });
-    pass(h, kPassContact, st, [&] { mlb::Launch<T>::contact(sys, blk, nblk, tb, st); });
-    if (h->spectral) pass(h, kPassTail, st, [&] { run_tail(h, st); });
-    pass(h, kPassGather1, st, [&] { mlb::Launch<T>::gather1(sys, blk, nblk, M, tb, st); });
-    pass(h, kPassStep2, st, [&] { mlb::Launch<T>::step2(sys, blk, nblk, M, tb, par, 0, st); });
-    h->parity ^= 1;
-    h->steps += 1;
+    SysHost &S = B.sys[k];
+    const mlb_params *p = &S.p;
+    std::memset(&D, 0, sizeof(D));
+    D.nx = p->nx; D.ny = p->ny; D.nz = p->nz; D.M = S.M; D.P = S.P; D.walls = p->walls_y ? 1 : 0;
+    D.N = S.N;
+    D.nblocks = S.nblocks;
+    D.reach = S.tabs.shell_reach;
+    char *ws = B.ws;
+    D.f[0] = reinterpret_cast<T *>(ws + S.f0);
+    D.f[1] = reinterpret_cast<T *>(ws + S.f1);
+    D.n = reinterpret_cast<T *>(ws + S.n);
+    D.j = reinterpret_cast<T *>(ws + S.j);
+    D.u = reinterpret_cast<T *>(ws + S.u);
+    D.g = reinterpret_cast<T *>(ws + S.g);
+    D.vh = reinterpret_cast<T *>(ws + S.vh);
+    D.H = reinterpret_cast<T *>(ws + S.H);
+    D.Nf = reinterpret_cast<T *>(ws + S.Nf);
+    D.Tloc = B.tiled ? reinterpret_cast<T *>(ws + S.Tloc) : nullptr;
+    D.tail = S.spectral ? reinterpret_cast<T *>(ws + S.tail) : nullptr;
+    D.parts = nullptr;
+    D.parts_mask = 0;
+    D.tail_direct = S.spectral ? 0 : 1;
+    D.scheme = p->scheme;
+    D.omega_is_one = (1.0 / p->tau == 1.0) ? 1 : 0;
+    const HostTables &t = S.tabs;
+    for (int a = 0; a < S.M; ++a) {
+        D.bl_start[a] = S.bl_base + t.bl_start[a]; D.bl_cnt[a] = t.bl_cnt[a]; D.bl_full[a] = t.bl_full[a];
+        const double sg = p->sigma[a];
+        D.s2[a] = (T)((M_PI / 6.0) * (sg * sg));
+        D.s3[a] = (T)((M_PI / 6.0) * ((sg * sg) * sg));
+        for (int d = 0; d < 3; ++d) D.fext[a][d] = (T)p->ext_force[a * 3 + d];
+        for (int b = 0; b < S.M; ++b) {
+            D.sh_start[a][b] = S.sh_base + t.sh_start[a][b]; D.sh_cnt[a][b] = t.sh_cnt[a][b];
+            D.tl_start[a][b] = S.tl_base + t.tl_start[a][b]; D.tl_cnt[a][b] = t.tl_cnt[a][b];
+            const mlb::PairConst c = mlb::pair_constants(p->sigma[a], p->sigma[b], p->kT, t.sh_full[a][b]);
+            D.cm[a][b] = (T)c.cm; D.cg[a][b] = (T)c.cg; D.ck[a][b] = (T)c.ck; D.dd[a][b] = (T)c.dd;
+        }
+    }
+    const double omega = 1.0 / p->tau;
+    D.omega = (T)omega;
+    D.om1 = (T)(1.0 - omega);
+    D.wall_ux[0] = (T)p->wall_ux[0];
+    D.wall_ux[1] = (T)p->wall_ux[1];
 }
 
-// Evaluate the passes up to the force on the current populations with the
-// query descriptor (parts accumulator optionally set).
-template <typename T>
-mlb_status run_query(mlb_mixture_s *h, T *parts, unsigned mask, hipStream_t st)
+// Tile map for tile shape v: logical tiles (system-major, z-slab order)
+// dealt to physical blocks.  order 1 gives XCD x the contiguous chunk
+// [x C, (x+1) C) of logical tiles (block b runs on XCD b mod 8), so tiles
+// that share halos share an L2; padding blocks idle.
+std::vector<int2> tile_map(const Batch &B, int v, int order, int &nblk)
 {
-    mlb::SysDesc<T> *q = h->host_desc<T>(1);
-    *q = *h->host_desc<T>(0);
-    q->parts = parts;
-    q->parts_mask = mask;
-    mlb_status s = upload_desc<T>(h, 1, st);
-    if (s != MLB_OK) return s;
-    const mlb::SysDesc<T> *sys = h->dev_desc<T>(1);
-    const mlb::Tables<T> tb = h->tables<T>();
-    mlb::Launch<T>::moments(sys, h->blk(), h->nblk, h->parity, st);
-    mlb::Launch<T>::contact(sys, h->blk(), h->nblk, tb, st);
-    if (h->spectral) run_tail(h, st);
-    mlb::Launch<T>::gather1(sys, h->blk(), h->nblk, h->M, tb, st);
-    mlb::Launch<T>::step2(sys, h->blk(), h->nblk, h->M, tb, h->parity, 1, st);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<int2> logical;
+    for (int k = 0; k < B.count; ++k) {
+        const SysHost &S = B.sys[k];
+        const int nt = mlb::tile_count(v, S.p.nx, S.p.ny, S.p.nz);
+        for (int i = 0; i < nt; ++i) logical.push_back(make_int2(k, i));
+    }
+    const int T = (int)logical.size();
+    if (order == 0) {
+        nblk = T;
+        return logical;
+    }
+    const int chunk = (T + kXcds - 1) / kXcds;
+    nblk = chunk * kXcds;
+    std::vector<int2> phys((size_t)nblk, make_int2(-1, 0));
+    for (int b = 0; b < nblk; ++b) {
+        const int L = (b % kXcds) * chunk + b / kXcds;
+        if (L < T) phys[(size_t)b] = logical[(size_t)L];
+    }
+    return phys;
+}
+
+template <typename T>
+mlb_status upload_static(Batch &B, hipStream_t st)
+{
+    // concatenated tables
+    std::vector<int32_t> sh_e, tl_e, bl_e;
+    std::vector<T> sh_u, sh_ee, tl_w;
+    for (auto &S : B.sys) {
+        sh_e.insert(sh_e.end(), S.tabs.sh_e.begin(), S.tabs.sh_e.end());
+        tl_e.insert(tl_e.end(), S.tabs.tl_e.begin(), S.tabs.tl_e.end());
+        bl_e.insert(bl_e.end(), S.tabs.bl_e.begin(), S.tabs.bl_e.end());
+        for (double v : S.tabs.sh_u) sh_u.push_back((T)v);
+        for (double v : S.tabs.sh_ee) sh_ee.push_back((T)v);
+        for (double v : S.tabs.tl_w) tl_w.push_back((T)v);
+    }
+    char *ws = B.ws;
+    auto up = [&](size_t off, const void *src, size_t bytes) -> mlb_status {
+        if (bytes) HIP_TRY(hipMemcpyAsync(ws + off, src, bytes, hipMemcpyHostToDevice, st));
+        return MLB_OK;
+    };
+    TRY(up(B.t_sh_e, sh_e.data(), 4 * sh_e.size()));
+    TRY(up(B.t_sh_u, sh_u.data(), sizeof(T) * sh_u.size()));
+    TRY(up(B.t_sh_ee, sh_ee.data(), sizeof(T) * sh_ee.size()));
+    TRY(up(B.t_tl_e, tl_e.data(), 4 * tl_e.size()));
+    TRY(up(B.t_tl_w, tl_w.data(), sizeof(T) * tl_w.size()));
+    TRY(up(B.t_bl_e, bl_e.data(), 4 * bl_e.size()));
+    // per-site block map and the identity map used by single-system launches
+    std::vector<int2> site, ident((size_t)B.ident_len);
+    for (int k = 0; k < B.count; ++k)
+        for (int i = 0; i < B.sys[k].nblocks; ++i) site.push_back(make_int2(k, i));
+    for (int i = 0; i < B.ident_len; ++i) ident[(size_t)i] = make_int2(0, i);
+    TRY(up(B.map_site, site.data(), sizeof(int2) * site.size()));
+    TRY(up(B.map_ident, ident.data(), sizeof(int2) * ident.size()));
+    // descriptors
+    B.desc_host.assign((size_t)(B.count + 1) * B.desc_size, 0);
+    for (int k = 0; k < B.count; ++k) fill_desc<T>(B, k, *B.hdesc<T>(k));
+    TRY(up(B.desc, B.desc_host.data(), (size_t)B.count * B.desc_size));
+    HIP_TRY(hipStreamSynchronize(st));   // host staging vectors die here
     return MLB_OK;
 }
 
-size_t tsize_of(const mlb_params *p) { return p->precision == 64 ? sizeof(double) : sizeof(float); }
-
-// Upload the DFT matrices, place the tail kernels w_ab on the periodic grid
-// (the population buffer f1 serves as scratch; it is overwritten by the
-// first step) and transform them into the sine spectra S_ab.
-mlb_status setup_spectral(mlb_mixture_s *h, hipStream_t st)
+mlb_status set_tiling(Batch &B, int shape, int order, hipStream_t st)
 {
-    const mlb_params *p = &h->p;
-    mlb::SpectralPlan &pl = h->plan;
-    char *ws = h->ws;
+    int nblk = 0;
+    std::vector<int2> m = tile_map(B, shape, order, nblk);
+    if (nblk > B.map_tile_cap) return fail(MLB_EINVAL, "tile map overflow");
+    HIP_TRY(hipMemcpyAsync(B.ws + B.map_tile, m.data(), sizeof(int2) * m.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    B.nblk_tile = nblk;
+    B.tune.shape = shape;
+    B.tune.order = order;
+    if (B.graph) {
+        (void)hipGraphExecDestroy(B.graph);
+        B.graph = nullptr;
+    }
+    return MLB_OK;
+}
+
+// Upload the DFT matrices, place the tail kernels on the periodic grid
+// (population buffer f1 is scratch; the first step overwrites it) and
+// transform them into the sine spectra.
+mlb_status setup_spectral(Batch &B, SysHost &S, hipStream_t st)
+{
+    const mlb_params *p = &S.p;
+    mlb::SpectralPlan &pl = S.plan;
+    char *ws = B.ws;
     pl.nx = p->nx; pl.ny = p->ny; pl.nz = p->nz; pl.nkx = p->nx / 2 + 1;
-    pl.M = h->M; pl.P = h->P;
+    pl.M = S.M; pl.P = S.P;
     pl.Sz = (long long)pl.ny * pl.nkx;
     pl.Sp = pl.Sz * pl.nz;
-    pl.wxf = reinterpret_cast<const float *>(ws + h->L.wxf);
-    pl.wxi = reinterpret_cast<const float *>(ws + h->L.wxi);
-    pl.wyf = reinterpret_cast<const float *>(ws + h->L.wyf);
-    pl.wyi = reinterpret_cast<const float *>(ws + h->L.wyi);
-    pl.wzf = reinterpret_cast<const float *>(ws + h->L.wzf);
-    pl.wzi = reinterpret_cast<const float *>(ws + h->L.wzi);
-    pl.S = reinterpret_cast<float *>(ws + h->L.S);
+    pl.wxf = reinterpret_cast<const float *>(ws + S.wxf);
+    pl.wxi = reinterpret_cast<const float *>(ws + S.wxi);
+    pl.wyf = reinterpret_cast<const float *>(ws + S.wyf);
+    pl.wyi = reinterpret_cast<const float *>(ws + S.wyi);
+    pl.wzf = reinterpret_cast<const float *>(ws + S.wzf);
+    pl.wzi = reinterpret_cast<const float *>(ws + S.wzi);
+    pl.S = reinterpret_cast<float *>(ws + S.S);
     std::vector<float> m[6] = {mlb::SpectralPlan::dft_x_forward(p->nx), mlb::SpectralPlan::dft_x_inverse(p->nx),
                                mlb::SpectralPlan::dft_block(p->ny, false), mlb::SpectralPlan::dft_block(p->ny, true),
                                mlb::SpectralPlan::dft_block(p->nz, false), mlb::SpectralPlan::dft_block(p->nz, true)};
-    const size_t offs[6] = {h->L.wxf, h->L.wxi, h->L.wyf, h->L.wyi, h->L.wzf, h->L.wzi};
+    const size_t offs[6] = {S.wxf, S.wxi, S.wyf, S.wyi, S.wzf, S.wzi};
     for (int k = 0; k < 6; ++k)
         HIP_TRY(hipMemcpyAsync(ws + offs[k], m[k].data(), sizeof(float) * m[k].size(), hipMemcpyHostToDevice, st));
-    // kernels on the grid: field (p, d) = sum over the full tail set of w_d(e) at e mod L
-    const long long N = h->N;
-    std::vector<float> placed((size_t)3 * h->P * N, 0.0f);
+    const long long N = S.N;
+    std::vector<float> placed((size_t)3 * S.P * N, 0.0f);
     std::vector<double> acc((size_t)3 * N);
-    const HostTables &t = h->tabs;
-    for (int a = 0; a < h->M; ++a)
-        for (int b = a; b < h->M; ++b) {
-            const int pi = a * h->M - (a * (a - 1)) / 2 + (b - a);
+    const HostTables &t = S.tabs;
+    for (int a = 0; a < S.M; ++a)
+        for (int b = a; b < S.M; ++b) {
+            const int pi = a * S.M - (a * (a - 1)) / 2 + (b - a);
             std::fill(acc.begin(), acc.end(), 0.0);
             for (int k = 0; k < t.tl_cnt[a][b]; ++k) {
                 int ex, ey, ez;
@@ -439,11 +534,327 @@ mlb_status setup_spectral(mlb_mixture_s *h, hipStream_t st)
             for (int d = 0; d < 3; ++d)
                 for (long long i = 0; i < N; ++i) placed[((size_t)pi * 3 + d) * N + i] = (float)acc[(size_t)d * N + i];
         }
-    float *scratch = reinterpret_cast<float *>(ws + h->L.f1);
+    float *scratch = reinterpret_cast<float *>(ws + S.f1);
     HIP_TRY(hipMemcpyAsync(scratch, placed.data(), sizeof(float) * placed.size(), hipMemcpyHostToDevice, st));
-    pl.build_spectrum(scratch, reinterpret_cast<float *>(ws + h->L.s1), reinterpret_cast<float *>(ws + h->L.s2), st);
+    pl.build_spectrum(scratch, reinterpret_cast<float *>(ws + S.s1), reinterpret_cast<float *>(ws + S.s2), st);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipStreamSynchronize(st));   // host staging vectors die here
+    HIP_TRY(hipStreamSynchronize(st));
+    return MLB_OK;
+}
+
+// ------------------------------------------------------------------ passes
+hipEvent_t take_event(Batch &B)
+{
+    if (B.next_event == B.events.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        B.events.push_back(e);
+    }
+    return B.events[B.next_event++];
+}
+
+template <typename F>
+void pass(Batch &B, int id, hipStream_t st, F &&launch)
+{
+    if (!B.profiling) {
+        launch();
+        return;
+    }
+    const size_t k = B.next_event;
+    hipEvent_t a = take_event(B), b = take_event(B);
+    if (!a || !b) {
+        launch();
+        return;
+    }
+    (void)hipEventRecord(a, st);
+    launch();
+    (void)hipEventRecord(b, st);
+    B.marks.emplace_back(id, (int)k);
+}
+
+void run_tail(Batch &B, SysHost &S, hipStream_t st)
+{
+    char *ws = B.ws;
+    S.plan.apply(reinterpret_cast<const float *>(ws + S.n), reinterpret_cast<float *>(ws + S.s1),
+                 reinterpret_cast<float *>(ws + S.s2), reinterpret_cast<float *>(ws + S.tail), st);
+}
+
+// One step over all systems (query == false) or the force evaluation of
+// system `qk` through the query descriptor (query == true).
+template <typename T>
+void run_passes(Batch &B, hipStream_t st, bool query, int qk, int force_only)
+{
+    const mlb::SysDesc<T> *sys = query ? B.ddesc<T>(B.count) : B.ddesc<T>(0);
+    const mlb::Tables<T> tb = B.tables<T>();
+    const int par = B.parity;
+    const int2 *smap = query ? B.map_of(B.map_ident) : B.map_of(B.map_site);
+    const int nsite = query ? B.sys[qk].nblocks : B.nblk_site;
+    const int M = query ? B.sys[qk].M : B.maxM;
+    pass(B, kPassMoments, st, [&] { mlb::Launch<T>::moments(sys, smap, nsite, par, st); });
+    pass(B, kPassContact, st, [&] { mlb::Launch<T>::contact(sys, smap, nsite, tb, st); });
+    for (int k = 0; k < B.count; ++k)
+        if ((!query || k == qk) && B.sys[k].spectral) pass(B, kPassTail, st, [&] { run_tail(B, B.sys[k], st); });
+    if constexpr (std::is_same<T, float>::value) {
+        if (B.tiled) {
+            const int shape = B.tune.shape;
+            const int2 *tmap = query ? B.map_of(B.map_ident) : B.map_of(B.map_tile);
+            const int ntl = query ? mlb::tile_count(shape, B.sys[qk].p.nx, B.sys[qk].p.ny, B.sys[qk].p.nz)
+                                  : B.nblk_tile;
+            pass(B, kPassGather1, st,
+                 [&] { mlb::launch_gather1_tile(shape, sys, tmap, ntl, M, tb, B.reach_max, st); });
+            pass(B, kPassStep2, st,
+                 [&] { mlb::launch_step2_tile(shape, sys, tmap, ntl, M, tb, B.reach_max, par, force_only, st); });
+            return;
+        }
+    }
+    pass(B, kPassGather1, st, [&] { mlb::Launch<T>::gather1(sys, smap, nsite, M, tb, st); });
+    pass(B, kPassStep2, st, [&] { mlb::Launch<T>::step2(sys, smap, nsite, M, tb, par, force_only, st); });
+}
+
+void step_once(Batch &B, hipStream_t st)
+{
+    if (B.prec == 64) run_passes<double>(B, st, false, 0, 0);
+    else run_passes<float>(B, st, false, 0, 0);
+    B.parity ^= 1;
+    B.steps += 1;
+}
+
+mlb_status build_graph(Batch &B)
+{
+    if (!B.cap_stream) HIP_TRY(hipStreamCreateWithFlags(&B.cap_stream, hipStreamNonBlocking));
+    const int par0 = B.parity;
+    const int64_t steps0 = B.steps;
+    B.parity = 0;
+    HIP_TRY(hipStreamBeginCapture(B.cap_stream, hipStreamCaptureModeRelaxed));
+    step_once(B, B.cap_stream);
+    step_once(B, B.cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(B.cap_stream, &g);
+    B.parity = par0;
+    B.steps = steps0;
+    if (e != hipSuccess) return fail(MLB_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&B.graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        B.graph = nullptr;
+        return fail(MLB_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    return MLB_OK;
+}
+
+mlb_status do_steps(Batch &B, int nsteps, hipStream_t st)
+{
+    if (nsteps < 0) return fail(MLB_EINVAL, "nsteps must be >= 0");
+    int left = nsteps;
+    if (B.use_graph && !B.profiling && left >= 2) {
+        if (B.parity == 1) {
+            step_once(B, st);
+            --left;
+        }
+        if (left >= 2) {
+            if (!B.graph) TRY(build_graph(B));
+            while (left >= 2) {
+                HIP_TRY(hipGraphLaunch(B.graph, st));
+                B.steps += 2;
+                left -= 2;
+            }
+        }
+    }
+    while (left-- > 0) step_once(B, st);
+    HIP_TRY(hipGetLastError());
+    return MLB_OK;
+}
+
+template <typename T>
+mlb_status run_query(Batch &B, int k, T *parts, unsigned mask, hipStream_t st)
+{
+    mlb::SysDesc<T> *q = B.hdesc<T>(B.count);
+    *q = *B.hdesc<T>(k);
+    q->parts = parts;
+    q->parts_mask = mask;
+    HIP_TRY(hipMemcpyAsync(B.ws + B.desc + (size_t)B.count * B.desc_size, q, B.desc_size, hipMemcpyHostToDevice, st));
+    run_passes<T>(B, st, true, k, 1);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    return MLB_OK;
+}
+
+template <typename T>
+mlb_status init_populations(Batch &B, const double *const *n0, const double *const *u0, hipStream_t st)
+{
+    for (int k = 0; k < B.count; ++k) {
+        // query descriptor slot + identity map: one system per launch
+        mlb::SysDesc<T> *q = B.hdesc<T>(B.count);
+        *q = *B.hdesc<T>(k);
+        HIP_TRY(hipMemcpyAsync(B.ws + B.desc + (size_t)B.count * B.desc_size, q, B.desc_size, hipMemcpyHostToDevice,
+                               st));
+        mlb::Launch<T>::init_pop(B.ddesc<T>(B.count), B.map_of(B.map_ident), B.sys[k].nblocks, n0[k], u0[k], st);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    B.parity = 0;
+    B.steps = 0;
+    return MLB_OK;
+}
+
+std::string tune_key(const Batch &B)
+{
+    std::string k = std::to_string(B.prec) + ":" + std::to_string(B.count);
+    for (const auto &S : B.sys) {
+        k += "|" + std::to_string(S.p.nx) + "x" + std::to_string(S.p.ny) + "x" + std::to_string(S.p.nz) + ":" +
+             std::to_string(S.M) + ":" + std::to_string(S.tabs.shell_reach) + ":" + std::to_string(S.tabs.sh_e.size());
+    }
+    return k;
+}
+
+// Time every tile shape and block order over full steps; keep the fastest.
+template <typename T>
+mlb_status autotune(Batch &B, const double *const *n0, const double *const *u0, hipStream_t st)
+{
+    const std::string key = tune_key(B);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            const Tuning cached = it->second;
+            TRY(set_tiling(B, cached.shape, cached.order, st));
+            B.tune = cached;
+            return MLB_OK;
+        }
+    }
+    Tuning best;
+    double best_ms = 1e300;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int warm = 2, reps = 6;
+    mlb_status status = MLB_OK;
+    for (int v = 0; v < mlb::kTileVariants && status == MLB_OK; ++v)
+        for (int order = 0; order < 2 && status == MLB_OK; ++order) {
+            status = set_tiling(B, v, order, st);
+            if (status != MLB_OK) break;
+            for (int i = 0; i < warm; ++i) step_once(B, st);
+            float ms = 0.f;
+            if (hipEventRecord(e0, st) != hipSuccess) { status = fail(MLB_EHIP, "event record"); break; }
+            for (int i = 0; i < reps; ++i) step_once(B, st);
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                status = fail(MLB_EHIP, "event timing");
+                break;
+            }
+            const double per = ms / reps;
+            best.trial_ms[2 * v + order] = per;
+            if (per < best_ms) {
+                best_ms = per;
+                best.shape = v;
+                best.order = order;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (status != MLB_OK) return status;
+    TRY(set_tiling(B, best.shape, best.order, st));
+    B.tune = best;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = best;
+    }
+    return init_populations<T>(B, n0, u0, st);   // the trial steps changed the state
+}
+
+template <typename T>
+mlb_status create(Batch &B, const mlb_params *params, int count, void *workspace, size_t bytes,
+                  const double *const *n0, const double *const *u0, uint32_t options, hipStream_t st)
+{
+    std::string why;
+    if (!plan_batch(B, params, count, why)) return fail(MLB_EINVAL, why);
+    if (!workspace || ((uintptr_t)workspace % kAlign) != 0)
+        return fail(MLB_EINVAL, "workspace must be a 256-byte aligned device pointer");
+    if (bytes < B.total) return fail(MLB_ENOMEM, "workspace too small: need " + std::to_string(B.total) + " bytes");
+    if (!n0 || !u0) return fail(MLB_EINVAL, "n0 and u0 are required");
+    for (int k = 0; k < count; ++k)
+        if (!n0[k] || !u0[k]) return fail(MLB_EINVAL, "n0 and u0 are required for every system");
+    B.ws = static_cast<char *>(workspace);
+    B.use_graph = (options & MLB_OPT_NO_GRAPH) == 0;
+    if (B.tiled && !mlb::tile_prepare(B.reach_max)) B.tiled = false;
+    TRY(upload_static<T>(B, st));
+    if (B.tiled) TRY(set_tiling(B, 0, 1, st));
+    for (auto &S : B.sys)
+        if (S.spectral) TRY(setup_spectral(B, S, st));
+    TRY(init_populations<T>(B, n0, u0, st));
+    for (auto &S : B.sys) mlb::launch_zero_i32(reinterpret_cast<int *>(B.ws + S.series_cnt), 1, st);
+    HIP_TRY(hipStreamSynchronize(st));
+    if (B.tiled && (options & MLB_OPT_TUNE)) TRY(autotune<T>(B, n0, u0, st));
+    HIP_TRY(hipGetLastError());
+    return MLB_OK;
+}
+
+size_t workspace_for(const mlb_params *params, int count)
+{
+    Batch B;
+    std::string why;
+    if (!plan_batch(B, params, count, why)) {
+        g_err = why;
+        return 0;
+    }
+    return B.total;
+}
+
+hipStream_t S_(void *stream) { return static_cast<hipStream_t>(stream); }
+
+// ---------------------------------------------------- per-system helpers
+mlb_status moments_of(Batch &B, int k, void *n_out, void *j_out, hipStream_t st)
+{
+    if (k < 0 || k >= B.count) return fail(MLB_EINVAL, "bad system index");
+    SysHost &S = B.sys[k];
+    // moments of every system in one launch (cheap), then copy system k
+    if (B.prec == 64) mlb::Launch<double>::moments(B.ddesc<double>(0), B.map_of(B.map_site), B.nblk_site, B.parity, st);
+    else mlb::Launch<float>::moments(B.ddesc<float>(0), B.map_of(B.map_site), B.nblk_site, B.parity, st);
+    const size_t ts = tsize_of(B.prec);
+    if (n_out) HIP_TRY(hipMemcpyAsync(n_out, B.ws + S.n, ts * S.M * S.N, hipMemcpyDeviceToDevice, st));
+    if (j_out) HIP_TRY(hipMemcpyAsync(j_out, B.ws + S.j, ts * 3 * S.M * S.N, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipGetLastError());
+    return MLB_OK;
+}
+
+mlb_status populations_of(Batch &B, int k, void *f_out, hipStream_t st)
+{
+    if (k < 0 || k >= B.count) return fail(MLB_EINVAL, "bad system index");
+    SysHost &S = B.sys[k];
+    HIP_TRY(hipMemcpyAsync(f_out, B.ws + (B.parity ? S.f1 : S.f0), tsize_of(B.prec) * S.M * mlb::kQ * S.N,
+                           hipMemcpyDeviceToDevice, st));
+    return MLB_OK;
+}
+
+mlb_status record_mode_of(Batch &B, int k, int a, int b, hipStream_t st)
+{
+    SysHost &S = B.sys[k];
+    mlb::launch_mode(B.ws + S.n, B.prec, a, b, S.p.nx, S.N, reinterpret_cast<double *>(B.ws + B.red), kRedParts,
+                     reinterpret_cast<double *>(B.ws + S.series), reinterpret_cast<int *>(B.ws + S.series_cnt),
+                     kSeriesCap, (double)B.steps, st);
+    HIP_TRY(hipGetLastError());
+    return MLB_OK;
+}
+
+mlb_status profile_end(Batch &B, double *ms, int32_t *launches, hipStream_t st)
+{
+    if (!B.profiling) return fail(MLB_ESTATE, "profiling was not started");
+    HIP_TRY(hipStreamSynchronize(st));
+    double acc[MLB_NPASS] = {0, 0, 0, 0, 0};
+    int cnt[MLB_NPASS] = {0, 0, 0, 0, 0};
+    for (auto &m : B.marks) {
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, B.events[m.second], B.events[m.second + 1]));
+        acc[m.first] += t;
+        cnt[m.first] += 1;
+    }
+    for (int k = 0; k < MLB_NPASS; ++k) {
+        if (ms) ms[k] = acc[k];
+        if (launches) launches[k] = cnt[k];
+    }
+    B.profiling = false;
+    B.marks.clear();
+    B.next_event = 0;
     return MLB_OK;
 }
 
@@ -452,65 +863,20 @@ mlb_status setup_spectral(mlb_mixture_s *h, hipStream_t st)
 // ===================================================================== ABI
 extern "C" {
 
-size_t mlb_workspace_bytes(const mlb_params *p)
-{
-    std::string why;
-    if (!validate(p, why)) { g_err = why; return 0; }
-    HostTables t;
-    if (!build_tables(p, t, why)) { g_err = why; return 0; }
-    const long long N = (long long)p->nx * p->ny * p->nz;
-    const int nblk = (int)((N + mlb::kBlock - 1) / mlb::kBlock);
-    const size_t sys_size = p->precision == 64 ? sizeof(mlb::SysDesc<double>) : sizeof(mlb::SysDesc<float>);
-    return make_layout(p, t, tsize_of(p), align_up(sys_size), nblk).total;
-}
+size_t mlb_workspace_bytes(const mlb_params *p) { return workspace_for(p, 1); }
 
 mlb_status mlb_init_mixture(const mlb_params *p, void *workspace, size_t workspace_bytes, const double *n0,
                             const double *u0, void *stream, mlb_mixture *out)
 {
     if (!out) return fail(MLB_EINVAL, "out is NULL");
     *out = nullptr;
-    std::string why;
-    if (!validate(p, why)) return fail(MLB_EINVAL, why);
-    if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return fail(MLB_EINVAL, "workspace must be a 256-byte aligned device pointer");
-    if (!n0 || !u0) return fail(MLB_EINVAL, "n0 and u0 are required");
+    if (!p) return fail(MLB_EINVAL, "params is NULL");
     std::unique_ptr<mlb_mixture_s> h(new mlb_mixture_s());
-    h->p = *p;
-    if (!build_tables(p, h->tabs, why)) return fail(MLB_EINVAL, why);
-    h->M = p->nspecies;
-    h->P = h->M * (h->M + 1) / 2;
-    h->N = (long long)p->nx * p->ny * p->nz;
-    h->nblk = (int)((h->N + mlb::kBlock - 1) / mlb::kBlock);
-    const bool f64 = p->precision == 64;
-    h->sys_size = align_up(f64 ? sizeof(mlb::SysDesc<double>) : sizeof(mlb::SysDesc<float>));
-    h->L = make_layout(p, h->tabs, tsize_of(p), h->sys_size, h->nblk);
-    if (workspace_bytes < h->L.total)
-        return fail(MLB_ENOMEM, "workspace too small: need " + std::to_string(h->L.total) + " bytes");
-    const bool any_tail = !h->tabs.tl_e.empty();
-    if (p->tail_mode == MLB_TAIL_SPECTRAL && any_tail && (p->precision != 32 || p->walls_y))
-        return fail(MLB_EUNSUPPORTED, "the spectral tail needs float32 and a periodic box");
-    h->spectral = wants_spectral(p, h->tabs);
-    h->tail_direct = h->spectral ? 0 : 1;
-    h->ws = static_cast<char *>(workspace);
-    h->sys_host.assign(2 * h->sys_size, 0);
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    mlb_status s;
-    if (f64) {
-        fill_desc<double>(h.get(), *h->host_desc<double>(0));
-        *h->host_desc<double>(1) = *h->host_desc<double>(0);
-        if ((s = upload_tables<double>(h.get(), st)) != MLB_OK) return s;
-        if ((s = upload_desc<double>(h.get(), 0, st)) != MLB_OK) return s;
-        mlb::Launch<double>::init_pop(h->dev_desc<double>(0), h->blk(), h->nblk, n0, u0, st);
-    } else {
-        fill_desc<float>(h.get(), *h->host_desc<float>(0));
-        *h->host_desc<float>(1) = *h->host_desc<float>(0);
-        if ((s = upload_tables<float>(h.get(), st)) != MLB_OK) return s;
-        if ((s = upload_desc<float>(h.get(), 0, st)) != MLB_OK) return s;
-        if (h->spectral && (s = setup_spectral(h.get(), st)) != MLB_OK) return s;
-        mlb::Launch<float>::init_pop(h->dev_desc<float>(0), h->blk(), h->nblk, n0, u0, st);
-    }
-    mlb::launch_zero_i32(reinterpret_cast<int *>(h->ws + h->L.series_cnt), 1, st);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipStreamSynchronize(st));
+    const double *n0v[1] = {n0}, *u0v[1] = {u0};
+    mlb_status s = p->precision == 64
+                       ? create<double>(*h, p, 1, workspace, workspace_bytes, n0v, u0v, 0, S_(stream))
+                       : create<float>(*h, p, 1, workspace, workspace_bytes, n0v, u0v, 0, S_(stream));
+    if (s != MLB_OK) return s;
     *out = h.release();
     return MLB_OK;
 }
@@ -518,49 +884,40 @@ mlb_status mlb_init_mixture(const mlb_params *p, void *workspace, size_t workspa
 mlb_status mlb_step(mlb_mixture h, int32_t nsteps, void *stream)
 {
     if (!h) return fail(MLB_EINVAL, "handle is NULL");
-    if (nsteps < 0) return fail(MLB_EINVAL, "nsteps must be >= 0");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    for (int t = 0; t < nsteps; ++t) {
-        if (h->p.precision == 64) run_step<double>(h, st);
-        else run_step<float>(h, st);
-    }
-    HIP_TRY(hipGetLastError());
+    return do_steps(*h, nsteps, S_(stream));
+}
+
+mlb_status mlb_set_graph(mlb_mixture h, int32_t enable)
+{
+    if (!h) return fail(MLB_EINVAL, "handle is NULL");
+    h->use_graph = enable != 0;
     return MLB_OK;
 }
 
 mlb_status mlb_moments(mlb_mixture h, void *n_out, void *j_out, void *stream)
 {
     if (!h) return fail(MLB_EINVAL, "handle is NULL");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const size_t ts = tsize_of(&h->p);
-    if (h->p.precision == 64) mlb::Launch<double>::moments(h->dev_desc<double>(0), h->blk(), h->nblk, h->parity, st);
-    else mlb::Launch<float>::moments(h->dev_desc<float>(0), h->blk(), h->nblk, h->parity, st);
-    if (n_out) HIP_TRY(hipMemcpyAsync(n_out, h->ws + h->L.n, ts * h->M * h->N, hipMemcpyDeviceToDevice, st));
-    if (j_out) HIP_TRY(hipMemcpyAsync(j_out, h->ws + h->L.j, ts * 3 * h->M * h->N, hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipGetLastError());
-    return MLB_OK;
+    return moments_of(*h, 0, n_out, j_out, S_(stream));
 }
 
 mlb_status mlb_forces(mlb_mixture h, void *nphi_out, uint32_t parts, void *stream)
 {
     if (!h || !nphi_out) return fail(MLB_EINVAL, "handle and output are required");
     if (parts == 0 || parts > MLB_PART_ALL) return fail(MLB_EINVAL, "parts mask must be a non-empty subset of MLB_PART_ALL");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    if (h->p.precision == 64) return run_query<double>(h, static_cast<double *>(nphi_out), parts, st);
-    return run_query<float>(h, static_cast<float *>(nphi_out), parts, st);
+    if (h->prec == 64) return run_query<double>(*h, 0, static_cast<double *>(nphi_out), parts, S_(stream));
+    return run_query<float>(*h, 0, static_cast<float *>(nphi_out), parts, S_(stream));
 }
 
 mlb_status mlb_fields(mlb_mixture h, void *n, void *j, void *u, void *g, void *vhat, void *H, void *nphi, void *stream)
 {
     if (!h) return fail(MLB_EINVAL, "handle is NULL");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    mlb_status s = h->p.precision == 64 ? run_query<double>(h, nullptr, 0, st) : run_query<float>(h, nullptr, 0, st);
-    if (s != MLB_OK) return s;
-    const size_t ts = tsize_of(&h->p), M = h->M, N = (size_t)h->N;
+    hipStream_t st = S_(stream);
+    TRY(h->prec == 64 ? run_query<double>(*h, 0, nullptr, 0, st) : run_query<float>(*h, 0, nullptr, 0, st));
+    const SysHost &S = h->sys[0];
+    const size_t ts = tsize_of(h->prec), M = S.M, N = (size_t)S.N;
     struct { void *dst; size_t off, bytes; } cp[] = {
-        {n, h->L.n, ts * M * N}, {j, h->L.j, ts * 3 * M * N}, {u, h->L.u, ts * 3 * N},
-        {g, h->L.g, ts * (size_t)h->P * N}, {vhat, h->L.vh, ts * 3 * M * N}, {H, h->L.H, ts * 3 * M * N},
-        {nphi, h->L.Nf, ts * 3 * M * N}};
+        {n, S.n, ts * M * N}, {j, S.j, ts * 3 * M * N}, {u, S.u, ts * 3 * N}, {g, S.g, ts * (size_t)S.P * N},
+        {vhat, S.vh, ts * 3 * M * N}, {H, S.H, ts * 3 * M * N}, {nphi, S.Nf, ts * 3 * M * N}};
     for (auto &c : cp)
         if (c.dst) HIP_TRY(hipMemcpyAsync(c.dst, h->ws + c.off, c.bytes, hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -570,37 +927,34 @@ mlb_status mlb_fields(mlb_mixture h, void *n, void *j, void *u, void *g, void *v
 mlb_status mlb_get_populations(mlb_mixture h, void *f_out, void *stream)
 {
     if (!h || !f_out) return fail(MLB_EINVAL, "handle and output are required");
-    const size_t bytes = tsize_of(&h->p) * h->M * mlb::kQ * h->N;
-    HIP_TRY(hipMemcpyAsync(f_out, h->ws + (h->parity ? h->L.f1 : h->L.f0), bytes, hipMemcpyDeviceToDevice,
-                           static_cast<hipStream_t>(stream)));
-    return MLB_OK;
+    return populations_of(*h, 0, f_out, S_(stream));
 }
 
 mlb_status mlb_set_populations(mlb_mixture h, const void *f_in, void *stream)
 {
     if (!h || !f_in) return fail(MLB_EINVAL, "handle and input are required");
-    const size_t bytes = tsize_of(&h->p) * h->M * mlb::kQ * h->N;
-    HIP_TRY(hipMemcpyAsync(h->ws + (h->parity ? h->L.f1 : h->L.f0), f_in, bytes, hipMemcpyDeviceToDevice,
-                           static_cast<hipStream_t>(stream)));
+    const SysHost &S = h->sys[0];
+    HIP_TRY(hipMemcpyAsync(h->ws + (h->parity ? S.f1 : S.f0), f_in, tsize_of(h->prec) * S.M * mlb::kQ * S.N,
+                           hipMemcpyDeviceToDevice, S_(stream)));
     return MLB_OK;
 }
 
 mlb_status mlb_conserved(mlb_mixture h, double *mass, double *mom, void *stream)
 {
     if (!h) return fail(MLB_EINVAL, "handle is NULL");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    mlb_status s = mlb_moments(h, nullptr, nullptr, stream);
-    if (s != MLB_OK) return s;
-    double *out = reinterpret_cast<double *>(h->ws + h->L.red_out);
-    mlb::launch_conserved(h->ws + h->L.n, h->ws + h->L.j, h->p.precision, h->M, h->N,
-                          reinterpret_cast<double *>(h->ws + h->L.red), kRedParts, out, st);
+    hipStream_t st = S_(stream);
+    TRY(moments_of(*h, 0, nullptr, nullptr, st));
+    const SysHost &S = h->sys[0];
+    double *out = reinterpret_cast<double *>(h->ws + h->red_out);
+    mlb::launch_conserved(h->ws + S.n, h->ws + S.j, h->prec, S.M, S.N, reinterpret_cast<double *>(h->ws + h->red),
+                          kRedParts, out, st);
     double host[16];
-    HIP_TRY(hipMemcpyAsync(host, out, sizeof(double) * 4 * h->M, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(host, out, sizeof(double) * 4 * S.M, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     bool finite = true;
-    for (int k = 0; k < 4 * h->M; ++k) finite = finite && std::isfinite(host[k]);
-    if (mass) for (int a = 0; a < h->M; ++a) mass[a] = host[a];
-    if (mom) for (int k = 0; k < 3 * h->M; ++k) mom[k] = host[h->M + k];
+    for (int k = 0; k < 4 * S.M; ++k) finite = finite && std::isfinite(host[k]);
+    if (mass) for (int a = 0; a < S.M; ++a) mass[a] = host[a];
+    if (mom) for (int k = 0; k < 3 * S.M; ++k) mom[k] = host[S.M + k];
     if (!finite) return fail(MLB_ENONFINITE, "a conserved sum is not finite");
     return MLB_OK;
 }
@@ -608,27 +962,22 @@ mlb_status mlb_conserved(mlb_mixture h, double *mass, double *mom, void *stream)
 mlb_status mlb_record_mode(mlb_mixture h, int32_t a, int32_t b, void *stream)
 {
     if (!h) return fail(MLB_EINVAL, "handle is NULL");
-    if (a < 0 || b < 0 || a >= h->M || b >= h->M || a == b) return fail(MLB_EINVAL, "bad species pair");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    mlb_status s = mlb_moments(h, nullptr, nullptr, stream);
-    if (s != MLB_OK) return s;
-    mlb::launch_mode(h->ws + h->L.n, h->p.precision, a, b, h->p.nx, h->N, reinterpret_cast<double *>(h->ws + h->L.red),
-                     kRedParts, reinterpret_cast<double *>(h->ws + h->L.series),
-                     reinterpret_cast<int *>(h->ws + h->L.series_cnt), kSeriesCap, (double)h->steps, st);
-    HIP_TRY(hipGetLastError());
-    return MLB_OK;
+    const SysHost &S = h->sys[0];
+    if (a < 0 || b < 0 || a >= S.M || b >= S.M || a == b) return fail(MLB_EINVAL, "bad species pair");
+    TRY(moments_of(*h, 0, nullptr, nullptr, S_(stream)));
+    return record_mode_of(*h, 0, a, b, S_(stream));
 }
 
 mlb_status mlb_record_spread(mlb_mixture h, int32_t a, void *stream)
 {
     if (!h) return fail(MLB_EINVAL, "handle is NULL");
-    if (a < 0 || a >= h->M) return fail(MLB_EINVAL, "bad species");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    mlb_status s = mlb_moments(h, nullptr, nullptr, stream);
-    if (s != MLB_OK) return s;
-    mlb::launch_spread(h->ws + h->L.n, h->p.precision, a, h->p.nx, h->N, reinterpret_cast<double *>(h->ws + h->L.red),
-                       kRedParts, reinterpret_cast<double *>(h->ws + h->L.series),
-                       reinterpret_cast<int *>(h->ws + h->L.series_cnt), kSeriesCap, (double)h->steps, st);
+    const SysHost &S = h->sys[0];
+    if (a < 0 || a >= S.M) return fail(MLB_EINVAL, "bad species");
+    hipStream_t st = S_(stream);
+    TRY(moments_of(*h, 0, nullptr, nullptr, st));
+    mlb::launch_spread(h->ws + S.n, h->prec, a, S.p.nx, S.N, reinterpret_cast<double *>(h->ws + h->red), kRedParts,
+                       reinterpret_cast<double *>(h->ws + S.series), reinterpret_cast<int *>(h->ws + S.series_cnt),
+                       kSeriesCap, (double)h->steps, st);
     HIP_TRY(hipGetLastError());
     return MLB_OK;
 }
@@ -638,7 +987,7 @@ int32_t mlb_series_capacity(void) { return kSeriesCap; }
 mlb_status mlb_series_reset(mlb_mixture h, void *stream)
 {
     if (!h) return fail(MLB_EINVAL, "handle is NULL");
-    mlb::launch_zero_i32(reinterpret_cast<int *>(h->ws + h->L.series_cnt), 1, static_cast<hipStream_t>(stream));
+    mlb::launch_zero_i32(reinterpret_cast<int *>(h->ws + h->sys[0].series_cnt), 1, S_(stream));
     HIP_TRY(hipGetLastError());
     return MLB_OK;
 }
@@ -647,11 +996,12 @@ mlb_status mlb_fit_series(mlb_mixture h, int32_t kind, double t_min, double *D_o
 {
     if (!h || !D_out) return fail(MLB_EINVAL, "handle and output are required");
     if (kind != 0 && kind != 1) return fail(MLB_EINVAL, "kind must be 0 (mode) or 1 (spread)");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const double k = 2.0 * M_PI / (double)h->p.nx;
-    double *out = reinterpret_cast<double *>(h->ws + h->L.fit_out);
-    mlb::launch_fit(reinterpret_cast<const double *>(h->ws + h->L.series),
-                    reinterpret_cast<const int *>(h->ws + h->L.series_cnt), kSeriesCap, kind, t_min, k * k, out, st);
+    hipStream_t st = S_(stream);
+    const SysHost &S = h->sys[0];
+    const double k = 2.0 * M_PI / (double)S.p.nx;
+    double *out = reinterpret_cast<double *>(h->ws + h->fit_out);
+    mlb::launch_fit(reinterpret_cast<const double *>(h->ws + S.series),
+                    reinterpret_cast<const int *>(h->ws + S.series_cnt), kSeriesCap, kind, t_min, k * k, out, st);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(D_out, out, sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -661,16 +1011,17 @@ mlb_status mlb_fit_series(mlb_mixture h, int32_t kind, double t_min, double *D_o
 mlb_status mlb_get_series(mlb_mixture h, double *t, double *v, int32_t capacity, int32_t *count, void *stream)
 {
     if (!h || !count) return fail(MLB_EINVAL, "handle and count are required");
-    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipStream_t st = S_(stream);
+    const SysHost &S = h->sys[0];
     int c = 0;
-    HIP_TRY(hipMemcpyAsync(&c, h->ws + h->L.series_cnt, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&c, h->ws + S.series_cnt, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     c = std::min(c, kSeriesCap);
     *count = c;
     const int n = std::min(c, capacity);
     if (n > 0 && (t || v)) {
         std::vector<double> buf(2 * (size_t)n);
-        HIP_TRY(hipMemcpyAsync(buf.data(), h->ws + h->L.series, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(buf.data(), h->ws + S.series, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         for (int i = 0; i < n; ++i) {
             if (t) t[i] = buf[2 * i];
@@ -694,24 +1045,7 @@ mlb_status mlb_profile_begin(mlb_mixture h)
 mlb_status mlb_profile_end(mlb_mixture h, double *ms, int32_t *launches, void *stream)
 {
     if (!h) return fail(MLB_EINVAL, "handle is NULL");
-    if (!h->profiling) return fail(MLB_ESTATE, "profiling was not started");
-    HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
-    double acc[MLB_NPASS] = {0, 0, 0, 0, 0};
-    int cnt[MLB_NPASS] = {0, 0, 0, 0, 0};
-    for (auto &m : h->marks) {
-        float t = 0.f;
-        HIP_TRY(hipEventElapsedTime(&t, h->events[m.second], h->events[m.second + 1]));
-        acc[m.first] += t;
-        cnt[m.first] += 1;
-    }
-    for (int k = 0; k < MLB_NPASS; ++k) {
-        if (ms) ms[k] = acc[k];
-        if (launches) launches[k] = cnt[k];
-    }
-    h->profiling = false;
-    h->marks.clear();
-    h->next_event = 0;
-    return MLB_OK;
+    return profile_end(*h, ms, launches, S_(stream));
 }
 
 const char *mlb_pass_name(int32_t k) { return (k >= 0 && k < MLB_NPASS) ? kPassNames[k] : ""; }
@@ -723,5 +1057,112 @@ mlb_status mlb_destroy(mlb_mixture h)
 }
 
 const char *mlb_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------ batch
+size_t mlb_batch_workspace_bytes(const mlb_params *systems, int32_t count)
+{
+    if (!systems || count < 1) {
+        g_err = "systems and count >= 1 are required";
+        return 0;
+    }
+    return workspace_for(systems, count);
+}
+
+mlb_status mlb_init_batch(const mlb_params *systems, int32_t count, void *workspace, size_t workspace_bytes,
+                          const double *const *n0, const double *const *u0, uint32_t options, void *stream,
+                          mlb_batch *out)
+{
+    if (!out) return fail(MLB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!systems || count < 1) return fail(MLB_EINVAL, "systems and count >= 1 are required");
+    std::unique_ptr<mlb_batch_s> h(new mlb_batch_s());
+    mlb_status s = systems[0].precision == 64
+                       ? create<double>(*h, systems, count, workspace, workspace_bytes, n0, u0, options, S_(stream))
+                       : create<float>(*h, systems, count, workspace, workspace_bytes, n0, u0, options, S_(stream));
+    if (s != MLB_OK) return s;
+    *out = h.release();
+    return MLB_OK;
+}
+
+mlb_status mlb_batch_step(mlb_batch h, int32_t nsteps, void *stream)
+{
+    if (!h) return fail(MLB_EINVAL, "handle is NULL");
+    return do_steps(*h, nsteps, S_(stream));
+}
+
+mlb_status mlb_batch_moments(mlb_batch h, int32_t system, void *n_out, void *j_out, void *stream)
+{
+    if (!h) return fail(MLB_EINVAL, "handle is NULL");
+    return moments_of(*h, system, n_out, j_out, S_(stream));
+}
+
+mlb_status mlb_batch_get_populations(mlb_batch h, int32_t system, void *f_out, void *stream)
+{
+    if (!h || !f_out) return fail(MLB_EINVAL, "handle and output are required");
+    return populations_of(*h, system, f_out, S_(stream));
+}
+
+mlb_status mlb_batch_record_modes(mlb_batch h, void *stream)
+{
+    if (!h) return fail(MLB_EINVAL, "handle is NULL");
+    hipStream_t st = S_(stream);
+    TRY(moments_of(*h, 0, nullptr, nullptr, st));
+    for (int k = 0; k < h->count; ++k)
+        if (h->sys[k].M >= 2) TRY(record_mode_of(*h, k, 0, 1, st));
+    return MLB_OK;
+}
+
+mlb_status mlb_batch_fit(mlb_batch h, double t_min, double *D_out, void *stream)
+{
+    if (!h || !D_out) return fail(MLB_EINVAL, "handle and output are required");
+    hipStream_t st = S_(stream);
+    double *out = reinterpret_cast<double *>(h->ws + h->fit_out);
+    for (int k = 0; k < h->count; ++k) {
+        const SysHost &S = h->sys[k];
+        const double kk = 2.0 * M_PI / (double)S.p.nx;
+        mlb::launch_fit(reinterpret_cast<const double *>(h->ws + S.series),
+                        reinterpret_cast<const int *>(h->ws + S.series_cnt), kSeriesCap, 0, t_min, kk * kk,
+                        out + 4 * k, st);
+    }
+    HIP_TRY(hipGetLastError());
+    std::vector<double> host(4 * (size_t)h->count);
+    HIP_TRY(hipMemcpyAsync(host.data(), out, sizeof(double) * host.size(), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int k = 0; k < h->count; ++k) D_out[k] = host[4 * (size_t)k];
+    return MLB_OK;
+}
+
+mlb_status mlb_batch_tuning(mlb_batch h, int32_t *shape, int32_t *order, double *trial_ms)
+{
+    if (!h) return fail(MLB_EINVAL, "handle is NULL");
+    if (shape) *shape = h->tiled ? h->tune.shape : -1;
+    if (order) *order = h->tiled ? h->tune.order : -1;
+    if (trial_ms)
+        for (int i = 0; i < 2 * mlb::kTileVariants; ++i) trial_ms[i] = h->tune.trial_ms[i];
+    return MLB_OK;
+}
+
+mlb_status mlb_batch_profile_begin(mlb_batch h)
+{
+    if (!h) return fail(MLB_EINVAL, "handle is NULL");
+    h->profiling = true;
+    h->marks.clear();
+    h->next_event = 0;
+    return MLB_OK;
+}
+
+mlb_status mlb_batch_profile_end(mlb_batch h, double *ms, int32_t *launches, void *stream)
+{
+    if (!h) return fail(MLB_EINVAL, "handle is NULL");
+    return profile_end(*h, ms, launches, S_(stream));
+}
+
+int64_t mlb_batch_step_count(mlb_batch h) { return h ? h->steps : -1; }
+
+mlb_status mlb_batch_destroy(mlb_batch h)
+{
+    delete h;
+    return MLB_OK;
+}
 
 }  // extern "C"

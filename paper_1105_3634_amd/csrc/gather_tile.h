@@ -1,0 +1,316 @@
+// Float32 gathers on LDS-staged halo tiles.
+//
+// Same fields as the ordered per-site kernels of step_kernels.h (which the
+// float64 build uses), with the arithmetic regrouped for throughput:
+//
+// For species a at r and partner b, over the half-shell pairs (+e, -e),
+//   G+- = g_ab(r) + g_ab(r+-e),   t+- = G+- n_b(r+-e)
+//   mean field   Smf_b = sum e_hat (t+ - t-)                       eq. (potmeanforce)
+//   tensor       Ts_b  = sum (t+ + t-) e_hat e_hat^T              eqs. (tensorgamma)
+//   current      Sv_b  = sum e_hat e_hat.(G+ j_b(r+e) + G- j_b(r-e))
+// and, with cm, ck, cg the pair constants,
+//   Nmf   = n_a sum_b cm Smf_b
+//   T_a   = sum_b ck Ts_b,   Gam_a = sum_b cg trace(Ts_b)
+//   D_a[u_old] = n_a sum_b ck Sv_b - T_a j_a        (pair form of eqs. gammaab +
+//                                                    viscousforce, Newton-3 antisymmetric)
+// The second gather needs only
+//   D_a[V] = n_a ( sum_b ck sum e_hat e_hat.(t+ V_b(r+e) + t- V_b(r-e)) - T_a V_a )
+// because T_a (stored by the first gather) already holds the local part.
+//
+// Tile: TX x TY x TZ = 256 sites (a template parameter; the autotuner picks
+// among the built shapes), one thread per site; per partner species the
+// block stages n_b, the three components of j_b (or V_b) and g_ab for the
+// tile plus a halo of R cells (R = largest stencil component of the
+// system) into LDS; periodic wrap and walls are resolved while filling, so
+// the inner loop is address arithmetic on a uniform offset and LDS loads.
+#pragma once
+
+#include "step_kernels.h"
+
+namespace mlb {
+
+constexpr int kTileFields = 5;   // n, v0, v1, v2, g
+
+struct TileGeo {
+    int x0, y0, z0;       // tile origin
+    int R, HX, HY, HZ;    // halo width and staged extents
+    int FS;               // floats per staged field
+};
+
+template <int TX, int TY, int TZ>
+__device__ inline TileGeo tile_geo(const SysDesc<float> &S, int local)
+{
+    TileGeo t;
+    const int tx = (S.nx + TX - 1) / TX, ty = (S.ny + TY - 1) / TY;
+    const int bx = local % tx, by = (local / tx) % ty, bz = local / (tx * ty);
+    t.x0 = bx * TX; t.y0 = by * TY; t.z0 = bz * TZ;
+    t.R = S.reach;
+    t.HX = TX + 2 * t.R; t.HY = TY + 2 * t.R; t.HZ = TZ + 2 * t.R;
+    t.FS = t.HX * t.HY * t.HZ;
+    return t;
+}
+
+__device__ inline int wrapi(int v, int n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// Stage (n_b, vec_b) as float4 and g as float into LDS for the halo tile:
+// lds4[FS] then ldsg[FS].
+__device__ inline void stage(const SysDesc<float> &S, const TileGeo &t, float4 *lds4, float *ldsg,
+                             const float *__restrict__ nb, const float *__restrict__ vb, const float *__restrict__ gp)
+{
+    const long long N = S.N;
+    for (int i = threadIdx.x; i < t.FS; i += kBlock) {
+        const int hx = i % t.HX, hy = (i / t.HX) % t.HY, hz = i / (t.HX * t.HY);
+        const int gx = wrapi(t.x0 - t.R + hx, S.nx), gz = wrapi(t.z0 - t.R + hz, S.nz);
+        int gy = t.y0 - t.R + hy;
+        bool in = true;
+        if (S.walls) in = gy >= 0 && gy < S.ny;
+        else gy = wrapi(gy, S.ny);
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        float g = 0.f;
+        if (in) {
+            const long long s = ((long long)gz * S.ny + gy) * S.nx + gx;
+            v = make_float4(nb[s], vb[s], vb[N + s], vb[2 * N + s]);
+            g = gp[s];
+        }
+        lds4[i] = v;
+        ldsg[i] = g;
+    }
+}
+
+struct TileSite {
+    int tx, ty, tz, x, y, z;
+    bool active;
+    long long s;
+    int c;   // LDS offset of the site
+};
+
+template <int TX, int TY, int TZ>
+__device__ inline TileSite tile_site(const SysDesc<float> &S, const TileGeo &t)
+{
+    TileSite q;
+    q.tx = threadIdx.x % TX;
+    q.ty = (threadIdx.x / TX) % TY;
+    q.tz = threadIdx.x / (TX * TY);
+    q.x = t.x0 + q.tx; q.y = t.y0 + q.ty; q.z = t.z0 + q.tz;
+    q.active = q.x < S.nx && q.y < S.ny && q.z < S.nz;
+    q.s = ((long long)q.z * S.ny + q.y) * S.nx + q.x;
+    q.c = (q.tx + t.R) + (q.ty + t.R) * t.HX + (q.tz + t.R) * t.HX * t.HY;
+    return q;
+}
+
+// ------------------------------------------------------------ first gather
+template <int TX, int TY, int TZ>
+__global__ void __launch_bounds__(kBlock) k_gather1_tile(const SysDesc<float> *__restrict__ sys,
+                                                         const int2 *__restrict__ bmap, Tables<float> tb)
+{
+    extern __shared__ float4 lds[];
+    static_assert(TX * TY * TZ == kBlock, "one thread per tile site");
+    const int2 bm = bmap[blockIdx.x];
+    if (bm.x < 0) return;
+    const SysDesc<float> &S = sys[bm.x];
+    const int a = blockIdx.y;
+    if (a >= S.M) return;
+    const TileGeo t = tile_geo<TX, TY, TZ>(S, bm.y);
+    const TileSite q = tile_site<TX, TY, TZ>(S, t);
+    const long long N = S.N;
+    const long long o3 = (long long)a * 3 * N;
+    float4 *L4 = lds;
+    float *Lg = reinterpret_cast<float *>(lds + t.FS);
+    const bool solid = q.active && S.walls && (q.y == 0 || q.y == S.ny - 1);
+    const long long sc = q.active ? q.s : 0;
+    const float na = S.n[(long long)a * N + sc];
+    const float ja0 = S.j[o3 + sc], ja1 = S.j[o3 + N + sc], ja2 = S.j[o3 + 2 * N + sc];
+    float mf0 = 0.f, mf1 = 0.f, mf2 = 0.f, dj0 = 0.f, dj1 = 0.f, dj2 = 0.f, gam = 0.f;
+    float T00 = 0.f, T01 = 0.f, T02 = 0.f, T11 = 0.f, T12 = 0.f, T22 = 0.f;
+    const int HXY = t.HX * t.HY;
+    for (int b = 0; b < S.M; ++b) {
+        const float *__restrict__ gpair = S.g + (long long)pidx(S.M, a, b) * N;
+        __syncthreads();
+        stage(S, t, L4, Lg, S.n + (long long)b * N, S.j + (long long)b * 3 * N, gpair);
+        __syncthreads();
+        const float g0 = Lg[q.c];
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f, v0 = 0.f, v1 = 0.f, v2 = 0.f;
+        float t00 = 0.f, t01 = 0.f, t02 = 0.f, t11 = 0.f, t12 = 0.f, t22 = 0.f;
+        const int k0 = S.sh_start[a][b], kn = S.sh_cnt[a][b];
+#pragma unroll 4
+        for (int k = 0; k < kn; ++k) {
+            int ex, ey, ez;
+            unpack_offset(tb.sh_e[k0 + k], ex, ey, ez);
+            const int off = ex + ey * t.HX + ez * HXY;
+            const float *u = tb.sh_u + 3 * (k0 + k);
+            const float *ee = tb.sh_ee + 6 * (k0 + k);
+            const float e0 = u[0], e1 = u[1], e2 = u[2];
+            const int p = q.c + off, m = q.c - off;
+            const float4 Ap = L4[p], Am = L4[m];
+            const float Gp = g0 + Lg[p], Gm = g0 + Lg[m];
+            const float tp = Gp * Ap.x, tm = Gm * Am.x;
+            const float dt = tp - tm, st = tp + tm;
+            s0 += e0 * dt; s1 += e1 * dt; s2 += e2 * dt;
+            t00 += st * ee[0]; t01 += st * ee[1]; t02 += st * ee[2];
+            t11 += st * ee[3]; t12 += st * ee[4]; t22 += st * ee[5];
+            const float w0 = Gp * Ap.y + Gm * Am.y;
+            const float w1 = Gp * Ap.z + Gm * Am.z;
+            const float w2 = Gp * Ap.w + Gm * Am.w;
+            const float pr = e0 * w0 + e1 * w1 + e2 * w2;
+            v0 += e0 * pr; v1 += e1 * pr; v2 += e2 * pr;
+        }
+        const float cm = S.cm[a][b], ck = S.ck[a][b];
+        mf0 += cm * s0; mf1 += cm * s1; mf2 += cm * s2;
+        dj0 += ck * v0; dj1 += ck * v1; dj2 += ck * v2;
+        T00 += ck * t00; T01 += ck * t01; T02 += ck * t02;
+        T11 += ck * t11; T12 += ck * t12; T22 += ck * t22;
+        gam += S.cg[a][b] * (t00 + t11 + t22);
+    }
+    if (!q.active) return;
+    const long long s = q.s;
+    float *__restrict__ Tout = S.Tloc + (long long)a * 6 * N;
+    if (solid) {
+        for (int d = 0; d < 3; ++d) {
+            S.vh[o3 + d * N + s] = 0.f;
+            S.H[o3 + d * N + s] = 0.f;
+            if (S.parts) S.parts[o3 + d * N + s] = 0.f;
+        }
+        for (int d = 0; d < 6; ++d) Tout[d * N + s] = 0.f;
+        return;
+    }
+    float tl0 = 0.f, tl1 = 0.f, tl2 = 0.f;
+    if (S.tail) {
+        tl0 = S.tail[o3 + s]; tl1 = S.tail[o3 + N + s]; tl2 = S.tail[o3 + 2 * N + s];
+    }
+    const float mfv[3] = {mf0, mf1, mf2}, tlv[3] = {tl0, tl1, tl2}, jav[3] = {ja0, ja1, ja2};
+    const float djv[3] = {dj0, dj1, dj2};
+    const float Tj[3] = {T00 * ja0 + T01 * ja1 + T02 * ja2, T01 * ja0 + T11 * ja1 + T12 * ja2,
+                         T02 * ja0 + T12 * ja1 + T22 * ja2};
+    const float hg = 0.5f * gam;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const float Nmf = na * mfv[d], Ntl = na * tlv[d], Nex = na * S.fext[a][d];
+        const float Nc = Nmf + Ntl + Nex;
+        const float Dd = na * djv[d] - Tj[d];
+        if (S.scheme == 1) {
+            S.H[o3 + d * N + s] = Nc + Dd;
+            S.vh[o3 + d * N + s] = 0.f;
+        } else {
+            S.H[o3 + d * N + s] = Nc + 0.5f * Dd;
+            S.vh[o3 + d * N + s] = (na != 0.f) ? (jav[d] + Nc + Dd + hg * jav[d]) / (na * (1.f + hg)) : 0.f;
+        }
+        if (S.parts) {
+            float acc = 0.f;
+            if (S.parts_mask & 1u) acc += Nmf;
+            if (S.parts_mask & 2u) acc += Ntl;
+            if (S.parts_mask & 8u) acc += Nex;
+            if (S.parts_mask & 4u) acc += (S.scheme == 1 ? Dd : 0.5f * Dd);
+            S.parts[o3 + d * N + s] = acc;
+        }
+    }
+    Tout[0 * N + s] = T00; Tout[1 * N + s] = T01; Tout[2 * N + s] = T02;
+    Tout[3 * N + s] = T11; Tout[4 * N + s] = T12; Tout[5 * N + s] = T22;
+}
+
+// ------------------------------- second gather + collision + push streaming
+template <int TX, int TY, int TZ>
+__global__ void __launch_bounds__(kBlock) k_step2_tile(const SysDesc<float> *__restrict__ sys,
+                                                       const int2 *__restrict__ bmap, Tables<float> tb, int parity,
+                                                       int write_force_only)
+{
+    extern __shared__ float4 lds[];
+    static_assert(TX * TY * TZ == kBlock, "one thread per tile site");
+    const int2 bm = bmap[blockIdx.x];
+    if (bm.x < 0) return;
+    const SysDesc<float> &S = sys[bm.x];
+    const int a = blockIdx.y;
+    if (a >= S.M) return;
+    const TileGeo t = tile_geo<TX, TY, TZ>(S, bm.y);
+    const TileSite q = tile_site<TX, TY, TZ>(S, t);
+    const long long N = S.N;
+    const long long o3 = (long long)a * 3 * N;
+    float4 *L4 = lds;
+    float *Lg = reinterpret_cast<float *>(lds + t.FS);
+    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
+    const int HXY = t.HX * t.HY;
+    if (S.scheme != 1) {
+        for (int b = 0; b < S.M; ++b) {
+            const float *__restrict__ gpair = S.g + (long long)pidx(S.M, a, b) * N;
+            __syncthreads();
+            stage(S, t, L4, Lg, S.n + (long long)b * N, S.vh + (long long)b * 3 * N, gpair);
+            __syncthreads();
+            const float g0 = Lg[q.c];
+            float v0 = 0.f, v1 = 0.f, v2 = 0.f;
+            const int k0 = S.sh_start[a][b], kn = S.sh_cnt[a][b];
+#pragma unroll 4
+            for (int k = 0; k < kn; ++k) {
+                int ex, ey, ez;
+                unpack_offset(tb.sh_e[k0 + k], ex, ey, ez);
+                const int off = ex + ey * t.HX + ez * HXY;
+                const float *u = tb.sh_u + 3 * (k0 + k);
+                const float e0 = u[0], e1 = u[1], e2 = u[2];
+                const int p = q.c + off, m = q.c - off;
+                const float4 Ap = L4[p], Am = L4[m];
+                const float tp = (g0 + Lg[p]) * Ap.x, tm = (g0 + Lg[m]) * Am.x;
+                const float w0 = tp * Ap.y + tm * Am.y;
+                const float w1 = tp * Ap.z + tm * Am.z;
+                const float w2 = tp * Ap.w + tm * Am.w;
+                const float pr = e0 * w0 + e1 * w1 + e2 * w2;
+                v0 += e0 * pr; v1 += e1 * pr; v2 += e2 * pr;
+            }
+            const float ck = S.ck[a][b];
+            acc0 += ck * v0; acc1 += ck * v1; acc2 += ck * v2;
+        }
+    }
+    if (!q.active) return;
+    const long long s = q.s;
+    if (S.walls && (q.y == 0 || q.y == S.ny - 1)) {
+        if (write_force_only)
+            for (int d = 0; d < 3; ++d) S.Nf[o3 + d * N + s] = 0.f;
+        return;
+    }
+    const float na = S.n[(long long)a * N + s];
+    float Na[3] = {S.H[o3 + s], S.H[o3 + N + s], S.H[o3 + 2 * N + s]};
+    if (S.scheme != 1) {
+        const float *__restrict__ Tl = S.Tloc + (long long)a * 6 * N;
+        const float T00 = Tl[s], T01 = Tl[N + s], T02 = Tl[2 * N + s], T11 = Tl[3 * N + s], T12 = Tl[4 * N + s],
+                    T22 = Tl[5 * N + s];
+        const float va0 = S.vh[o3 + s], va1 = S.vh[o3 + N + s], va2 = S.vh[o3 + 2 * N + s];
+        const float Dn[3] = {na * (acc0 - (T00 * va0 + T01 * va1 + T02 * va2)),
+                             na * (acc1 - (T01 * va0 + T11 * va1 + T12 * va2)),
+                             na * (acc2 - (T02 * va0 + T12 * va1 + T22 * va2))};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            Na[d] += 0.5f * Dn[d];
+            if (S.parts && (S.parts_mask & 4u)) S.parts[o3 + d * N + s] += 0.5f * Dn[d];
+        }
+    }
+    if (write_force_only) {
+        for (int d = 0; d < 3; ++d) S.Nf[o3 + d * N + s] = Na[d];
+        return;
+    }
+    const float ja[3] = {S.j[o3 + s], S.j[o3 + N + s], S.j[o3 + 2 * N + s]};
+    const float u[3] = {S.u[s], S.u[N + s], S.u[2 * N + s]};
+    const float *__restrict__ fin = S.f[parity] + (long long)a * kQ * N;
+    float *__restrict__ fout = S.f[parity ^ 1] + (long long)a * kQ * N;
+    const bool w1 = S.omega_is_one != 0;
+    const Site r{q.x, q.y, q.z};
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const float fi = w1 ? 0.f : fin[(long long)i * N + s];
+        const float fs = post_collision<float>(i, fi, w1, S.omega, S.om1, na, ja, u, Na);
+        const int yy = q.y + kC[i][1];
+        if (S.walls && (yy == 0 || yy == S.ny - 1)) {
+            const float uw = (yy == 0) ? S.wall_ux[0] : S.wall_ux[1];
+            fout[(long long)opposite(i) * N + s] = fs - ((6.f * lattice_weight<float>(i)) * na) * ((float)kC[i][0] * uw);
+        } else {
+            fout[(long long)i * N + nbr(S, r, kC[i][0], kC[i][1], kC[i][2])] = fs;
+        }
+    }
+}
+
+inline size_t tile_lds_bytes(int TX, int TY, int TZ, int R)
+{
+    return sizeof(float) * kTileFields * (size_t)(TX + 2 * R) * (TY + 2 * R) * (TZ + 2 * R);  // float4 + float
+}
+
+}  // namespace mlb

@@ -34,12 +34,13 @@ template <typename T>
 struct SysDesc {
     int nx, ny, nz, M, P, walls;
     long long N;
-    int block_start;                 // first block of this system in a per-site launch
-    int nblocks;                     // blocks of this system (ceil(N / kBlock))
+    int nblocks;                     // per-site blocks of this system (ceil(N / kBlock))
+    int reach;                       // largest |component| of any shell offset
     T *f[2];                         // population double buffer [M][19][N]
     T *n, *j, *u, *g, *vh, *H, *Nf;  // fields (see mlb.h for layouts)
     T *tail;                         // attractive field sum_b K_ab * n_b [M][3][N] (spectral mode)
     T *parts;                        // optional force-part accumulator [M][3][N] (forces query)
+    T *Tloc;                         // local friction tensor sum_b ck Ts_b [M][6][N] (tiled path)
     unsigned parts_mask;
     int tail_direct;                 // 1: direct tail sum in the first gather
     int scheme;
@@ -63,6 +64,7 @@ struct SysDesc {
 template <typename T>
 struct Tables {
     const int32_t *sh_e;  const T *sh_u;     // shell half-lists: packed offset, unit vector [3]
+    const T *sh_ee;                          // e e^T per shell entry [6]: xx, xy, xz, yy, yz, zz
     const int32_t *tl_e;  const T *tl_w;     // tail half-lists: packed offset, vector weight [3]
     const int32_t *bl_e;                     // ball half-lists: packed offset
 };
@@ -83,18 +85,33 @@ struct PairConst {
 };
 PairConst pair_constants(double sa, double sb, double kT, int shell_full);
 
-// Launch entry points (one per precision), all on `st`.
+// A launch covers the blocks of many systems: block b works on system
+// map[b].x (a negative value idles the block), local block map[b].y.
+// Launch entry points (one per precision), all on `st`; `maxM` is the
+// largest species count (grid y of the per-species passes).
 template <typename T>
 struct Launch {
-    static void moments(const SysDesc<T> *sys, const int *blk_sys, int nblk, int parity, hipStream_t st);
-    static void contact(const SysDesc<T> *sys, const int *blk_sys, int nblk, Tables<T> tb, hipStream_t st);
-    static void gather1(const SysDesc<T> *sys, const int *blk_sys, int nblk, int maxM, Tables<T> tb,
+    static void moments(const SysDesc<T> *sys, const int2 *map, int nblk, int parity, hipStream_t st);
+    static void contact(const SysDesc<T> *sys, const int2 *map, int nblk, Tables<T> tb, hipStream_t st);
+    static void gather1(const SysDesc<T> *sys, const int2 *map, int nblk, int maxM, Tables<T> tb,
                         hipStream_t st);
-    static void step2(const SysDesc<T> *sys, const int *blk_sys, int nblk, int maxM, Tables<T> tb,
+    static void step2(const SysDesc<T> *sys, const int2 *map, int nblk, int maxM, Tables<T> tb,
                       int parity, int write_force_only, hipStream_t st);
-    static void init_pop(const SysDesc<T> *sys, const int *blk_sys, int nblk, const double *n0,
+    static void init_pop(const SysDesc<T> *sys, const int2 *map, int nblk, const double *n0,
                          const double *u0, hipStream_t st);
 };
+
+// Float32 tiled gathers (gather_tile.h, built in step_f32.hip); tile shape
+// variant v: 0 = 16x4x4, 1 = 8x8x4, 2 = 32x4x2 sites.
+constexpr int kTileVariants = 3;
+void tile_dims(int v, int &tx, int &ty, int &tz);
+void launch_gather1_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM, Tables<float> tb,
+                         int reach_max, hipStream_t st);
+void launch_step2_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM, Tables<float> tb,
+                       int reach_max, int parity, int write_force_only, hipStream_t st);
+int tile_count(int v, int nx, int ny, int nz);
+bool tile_prepare(int reach_max);   // raise the dynamic-LDS limit once; false if it cannot fit
+size_t tile_lds_bytes_of(int v, int reach);
 
 // float64 reductions (reduce.hip)
 void launch_conserved(const void *n, const void *j, int prec, int M, long long N, double *partials,

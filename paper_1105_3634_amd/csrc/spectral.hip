@@ -30,18 +30,29 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int kTM = 64, kTN = 64, kTK = 16;
 constexpr int kGemmThreads = 256;
 
-__device__ inline long long addr(const MatAddr &m, int t, int r, int c)
+__device__ inline long long part_t(const MatAddr &m, int t)
 {
-    const int th = t / m.t_div, tl = t - th * m.t_div;
-    const int rh = r / m.r_div, rl = r - rh * m.r_div;
-    const int ch = c / m.c_div, cl = c - ch * m.c_div;
-    return (long long)th * m.s_thi + (long long)tl * m.s_tlo + (long long)rh * m.s_rhi + (long long)rl * m.s_rlo +
-           (long long)ch * m.s_chi + (long long)cl * m.s_clo;
+    const int h = t / m.t_div;
+    return (long long)h * m.s_thi + (long long)(t - h * m.t_div) * m.s_tlo;
+}
+__device__ inline long long part_r(const MatAddr &m, int r)
+{
+    const int h = r / m.r_div;
+    return (long long)h * m.s_rhi + (long long)(r - h * m.r_div) * m.s_rlo;
+}
+__device__ inline long long part_c(const MatAddr &m, int c)
+{
+    const int h = c / m.c_div;
+    return (long long)h * m.s_chi + (long long)(c - h * m.c_div) * m.s_clo;
 }
 
 // C(t) [M x N] = A(t) [M x K] * B(t) [K x N], all float32, general strided
-// addressing.  Workgroup: 4 waves, 64x64 output tile, each wave a 32x32
-// quadrant made of 2x2 MFMA 16x16 blocks; K staged through LDS 16 at a time.
+// addressing (separable: batch part + row part + column part).  Workgroup:
+// 4 waves, 64x64 output tile, each wave a 32x32 quadrant made of 2x2 MFMA
+// 16x16 blocks; K staged through LDS 16 at a time, the next K slice held in
+// registers while the current one is consumed.  Each thread loads a fixed
+// tile column of A (4 rows) and a fixed tile column of B (4 K-rows), so
+// row/column address parts are computed once per workgroup.
 // Lane layout of v_mfma_f32_16x16x4f32: A[i][k] from lane i + 16k,
 // B[k][j] from lane j + 16k, D[4q + v][j] in lane j + 16q, element v.
 __global__ void __launch_bounds__(kGemmThreads) k_gemm_f32(GemmDesc g)
@@ -52,25 +63,40 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm_f32(GemmDesc g)
     const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const float *__restrict__ A = g.A.base + part_t(g.A, t);
+    const float *__restrict__ B = g.B.base + part_t(g.B, t);
+    // A loads: rows ar + 16 i, K column ak
+    const int ar = tid / kTK, ak = tid % kTK;
+    long long arow[4];
+    bool arok[4];
+    for (int i = 0; i < 4; ++i) {
+        const int r = m0 + ar + 16 * i;
+        arok[i] = r < g.M;
+        arow[i] = arok[i] ? part_r(g.A, r) : 0;
+    }
+    // B loads: K rows bk + 4 i, column bc
+    const int bk = tid / kTN, bc = tid % kTN;
+    const bool bcok = n0 + bc < g.N;
+    const long long bcol = bcok ? part_c(g.B, n0 + bc) : 0;
+    float ra[4], rb[4];
+    auto load = [&](int k0) {
+        const int ka = k0 + ak;
+        const long long acol = ka < g.K ? part_c(g.A, ka) : 0;
+        for (int i = 0; i < 4; ++i) ra[i] = (arok[i] && ka < g.K) ? A[arow[i] + acol] : 0.f;
+        for (int i = 0; i < 4; ++i) {
+            const int kb = k0 + bk + 4 * i;
+            rb[i] = (bcok && kb < g.K) ? B[part_r(g.B, kb) + bcol] : 0.f;
+        }
+    };
     v4f acc[2][2];
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-    const float *__restrict__ A = g.A.base;
-    const float *__restrict__ B = g.B.base;
+    load(0);
     for (int k0 = 0; k0 < g.K; k0 += kTK) {
-        // A tile: 64 x 16, thread -> (row = e / 16, k = e % 16)
-        for (int e = tid; e < kTM * kTK; e += kGemmThreads) {
-            const int r = e / kTK, k = e % kTK;
-            const int gr = m0 + r, gk = k0 + k;
-            As[r][k] = (gr < g.M && gk < g.K) ? A[addr(g.A, t, gr, gk)] : 0.f;
-        }
-        // B tile: 16 x 64, thread -> (k = e / 64, col = e % 64)
-        for (int e = tid; e < kTK * kTN; e += kGemmThreads) {
-            const int k = e / kTN, c = e % kTN;
-            const int gk = k0 + k, gc = n0 + c;
-            Bs[k][c] = (gk < g.K && gc < g.N) ? B[addr(g.B, t, gk, gc)] : 0.f;
-        }
+        for (int i = 0; i < 4; ++i) As[ar + 16 * i][ak] = ra[i];
+        for (int i = 0; i < 4; ++i) Bs[bk + 4 * i][bc] = rb[i];
         __syncthreads();
+        if (k0 + kTK < g.K) load(k0 + kTK);
 #pragma unroll
         for (int kk = 0; kk < kTK; kk += 4) {
             const int ka = kk + (lane >> 4), li = lane & 15;
@@ -83,15 +109,18 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm_f32(GemmDesc g)
         }
         __syncthreads();
     }
-    float *__restrict__ C = g.C.base;
+    float *__restrict__ C = g.C.base + part_t(g.C, t);
     const int j = lane & 15, q = lane >> 4;
-    for (int bi = 0; bi < 2; ++bi)
-        for (int bj = 0; bj < 2; ++bj)
+    for (int bj = 0; bj < 2; ++bj) {
+        const int c = n0 + wn + 16 * bj + j;
+        if (c >= g.N) continue;
+        const long long cc = part_c(g.C, c);
+        for (int bi = 0; bi < 2; ++bi)
             for (int v = 0; v < 4; ++v) {
                 const int r = m0 + wm + 16 * bi + 4 * q + v;
-                const int c = n0 + wn + 16 * bj + j;
-                if (r < g.M && c < g.N) C[addr(g.C, t, r, c)] = acc[bi][bj][v];
+                if (r < g.M) C[part_r(g.C, r) + cc] = acc[bi][bj][v];
             }
+    }
 }
 
 void launch_gemm(const GemmDesc &g, hipStream_t st)

@@ -1,6 +1,69 @@
-// Float32 instantiation of the per-site passes (contraction allowed).
-#include "step_kernels.h"
+// Float32 instantiation of the per-site passes (contraction allowed) and
+// the tiled float32 gathers in three tile shapes.
+#include "gather_tile.h"
 
 namespace mlb {
 template struct Launch<float>;
+
+void tile_dims(int v, int &tx, int &ty, int &tz)
+{
+    static const int D[kTileVariants][3] = {{16, 4, 4}, {8, 8, 4}, {32, 4, 2}};
+    tx = D[v][0]; ty = D[v][1]; tz = D[v][2];
 }
+
+int tile_count(int v, int nx, int ny, int nz)
+{
+    int tx, ty, tz;
+    tile_dims(v, tx, ty, tz);
+    return ((nx + tx - 1) / tx) * ((ny + ty - 1) / ty) * ((nz + tz - 1) / tz);
+}
+
+size_t tile_lds_bytes_of(int v, int reach)
+{
+    int tx, ty, tz;
+    tile_dims(v, tx, ty, tz);
+    return tile_lds_bytes(tx, ty, tz, reach);
+}
+
+namespace {
+template <int TX, int TY, int TZ>
+bool prepare_one(int reach)
+{
+    const size_t bytes = tile_lds_bytes(TX, TY, TZ, reach);
+    if (bytes > 160 * 1024) return false;
+    if (hipFuncSetAttribute((const void *)k_gather1_tile<TX, TY, TZ>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)bytes) != hipSuccess)
+        return false;
+    return hipFuncSetAttribute((const void *)k_step2_tile<TX, TY, TZ>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes) == hipSuccess;
+}
+}  // namespace
+
+bool tile_prepare(int reach_max)
+{
+    return prepare_one<16, 4, 4>(reach_max) && prepare_one<8, 8, 4>(reach_max) && prepare_one<32, 4, 2>(reach_max);
+}
+
+void launch_gather1_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM, Tables<float> tb,
+                         int reach_max, hipStream_t st)
+{
+    const size_t lds = tile_lds_bytes_of(v, reach_max);
+    const dim3 grid(nblk, maxM);
+    if (v == 0) hipLaunchKernelGGL((k_gather1_tile<16, 4, 4>), grid, dim3(kBlock), lds, st, sys, map, tb);
+    else if (v == 1) hipLaunchKernelGGL((k_gather1_tile<8, 8, 4>), grid, dim3(kBlock), lds, st, sys, map, tb);
+    else hipLaunchKernelGGL((k_gather1_tile<32, 4, 2>), grid, dim3(kBlock), lds, st, sys, map, tb);
+}
+
+void launch_step2_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM, Tables<float> tb,
+                       int reach_max, int parity, int write_force_only, hipStream_t st)
+{
+    const size_t lds = tile_lds_bytes_of(v, reach_max);
+    const dim3 grid(nblk, maxM);
+    if (v == 0)
+        hipLaunchKernelGGL((k_step2_tile<16, 4, 4>), grid, dim3(kBlock), lds, st, sys, map, tb, parity, write_force_only);
+    else if (v == 1)
+        hipLaunchKernelGGL((k_step2_tile<8, 8, 4>), grid, dim3(kBlock), lds, st, sys, map, tb, parity, write_force_only);
+    else
+        hipLaunchKernelGGL((k_step2_tile<32, 4, 2>), grid, dim3(kBlock), lds, st, sys, map, tb, parity, write_force_only);
+}
+}  // namespace mlb

@@ -92,10 +92,12 @@ __device__ inline int pidx(int M, int a, int b)
 // ------------------------------------------------------------------ moments
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_moments(const SysDesc<T> *__restrict__ sys,
-                                                    const int *__restrict__ blk_sys, int parity)
+                                                    const int2 *__restrict__ bmap, int parity)
 {
-    const SysDesc<T> &S = sys[blk_sys[blockIdx.x]];
-    const long long s = (long long)(blockIdx.x - S.block_start) * kBlock + threadIdx.x;
+    const int2 bm = bmap[blockIdx.x];
+    if (bm.x < 0) return;
+    const SysDesc<T> &S = sys[bm.x];
+    const long long s = (long long)bm.y * kBlock + threadIdx.x;
     if (s >= S.N) return;
     const long long N = S.N;
     const T *__restrict__ f = S.f[parity];
@@ -138,10 +140,12 @@ __global__ void __launch_bounds__(kBlock) k_moments(const SysDesc<T> *__restrict
 //   q = 1/(1-xi3), z = d xi2 q, xi_k = (pi/6) sum_c sigma_c^k nbar_c.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_contact(const SysDesc<T> *__restrict__ sys,
-                                                    const int *__restrict__ blk_sys, Tables<T> tb)
+                                                    const int2 *__restrict__ bmap, Tables<T> tb)
 {
-    const SysDesc<T> &S = sys[blk_sys[blockIdx.x]];
-    const long long s = (long long)(blockIdx.x - S.block_start) * kBlock + threadIdx.x;
+    const int2 bm = bmap[blockIdx.x];
+    if (bm.x < 0) return;
+    const SysDesc<T> &S = sys[bm.x];
+    const long long s = (long long)bm.y * kBlock + threadIdx.x;
     if (s >= S.N) return;
     const long long N = S.N;
     const Site r = site_of(S, s);
@@ -185,12 +189,14 @@ __global__ void __launch_bounds__(kBlock) k_contact(const SysDesc<T> *__restrict
 // w(e) (n_b(r+e) - n_b(r-e)) over its half-list.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_gather1(const SysDesc<T> *__restrict__ sys,
-                                                    const int *__restrict__ blk_sys, Tables<T> tb)
+                                                    const int2 *__restrict__ bmap, Tables<T> tb)
 {
-    const SysDesc<T> &S = sys[blk_sys[blockIdx.x]];
+    const int2 bm = bmap[blockIdx.x];
+    if (bm.x < 0) return;
+    const SysDesc<T> &S = sys[bm.x];
     const int a = blockIdx.y;
     if (a >= S.M) return;
-    const long long s = (long long)(blockIdx.x - S.block_start) * kBlock + threadIdx.x;
+    const long long s = (long long)bm.y * kBlock + threadIdx.x;
     if (s >= S.N) return;
     const long long N = S.N;
     const Site r = site_of(S, s);
@@ -321,13 +327,15 @@ __device__ inline T post_collision(int i, T fi, bool omega_one, T omega, T om1, 
 // write_force_only the force is stored and no population is touched.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_step2(const SysDesc<T> *__restrict__ sys,
-                                                  const int *__restrict__ blk_sys, Tables<T> tb,
+                                                  const int2 *__restrict__ bmap, Tables<T> tb,
                                                   int parity, int write_force_only)
 {
-    const SysDesc<T> &S = sys[blk_sys[blockIdx.x]];
+    const int2 bm = bmap[blockIdx.x];
+    if (bm.x < 0) return;
+    const SysDesc<T> &S = sys[bm.x];
     const int a = blockIdx.y;
     if (a >= S.M) return;
-    const long long s = (long long)(blockIdx.x - S.block_start) * kBlock + threadIdx.x;
+    const long long s = (long long)bm.y * kBlock + threadIdx.x;
     if (s >= S.N) return;
     const long long N = S.N;
     const Site r = site_of(S, s);
@@ -406,12 +414,14 @@ __global__ void __launch_bounds__(kBlock) k_step2(const SysDesc<T> *__restrict__
 // f = psi_perp(n0, n0 u0, u) at fluid sites (float64 inputs), zero on walls.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_init_pop(const SysDesc<T> *__restrict__ sys,
-                                                     const int *__restrict__ blk_sys,
+                                                     const int2 *__restrict__ bmap,
                                                      const double *__restrict__ n0,
                                                      const double *__restrict__ u0)
 {
-    const SysDesc<T> &S = sys[blk_sys[blockIdx.x]];
-    const long long s = (long long)(blockIdx.x - S.block_start) * kBlock + threadIdx.x;
+    const int2 bm = bmap[blockIdx.x];
+    if (bm.x < 0) return;
+    const SysDesc<T> &S = sys[bm.x];
+    const long long s = (long long)bm.y * kBlock + threadIdx.x;
     if (s >= S.N) return;
     const long long N = S.N;
     const Site r = site_of(S, s);
@@ -450,33 +460,33 @@ __global__ void __launch_bounds__(kBlock) k_init_pop(const SysDesc<T> *__restric
 
 // ----------------------------------------------------------------- launches
 template <typename T>
-void Launch<T>::moments(const SysDesc<T> *sys, const int *blk_sys, int nblk, int parity, hipStream_t st)
+void Launch<T>::moments(const SysDesc<T> *sys, const int2 *map, int nblk, int parity, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_moments<T>, dim3(nblk), dim3(kBlock), 0, st, sys, blk_sys, parity);
+    hipLaunchKernelGGL(k_moments<T>, dim3(nblk), dim3(kBlock), 0, st, sys, map, parity);
 }
 template <typename T>
-void Launch<T>::contact(const SysDesc<T> *sys, const int *blk_sys, int nblk, Tables<T> tb, hipStream_t st)
+void Launch<T>::contact(const SysDesc<T> *sys, const int2 *map, int nblk, Tables<T> tb, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_contact<T>, dim3(nblk), dim3(kBlock), 0, st, sys, blk_sys, tb);
+    hipLaunchKernelGGL(k_contact<T>, dim3(nblk), dim3(kBlock), 0, st, sys, map, tb);
 }
 template <typename T>
-void Launch<T>::gather1(const SysDesc<T> *sys, const int *blk_sys, int nblk, int maxM, Tables<T> tb,
+void Launch<T>::gather1(const SysDesc<T> *sys, const int2 *map, int nblk, int maxM, Tables<T> tb,
                         hipStream_t st)
 {
-    hipLaunchKernelGGL(k_gather1<T>, dim3(nblk, maxM), dim3(kBlock), 0, st, sys, blk_sys, tb);
+    hipLaunchKernelGGL(k_gather1<T>, dim3(nblk, maxM), dim3(kBlock), 0, st, sys, map, tb);
 }
 template <typename T>
-void Launch<T>::step2(const SysDesc<T> *sys, const int *blk_sys, int nblk, int maxM, Tables<T> tb,
+void Launch<T>::step2(const SysDesc<T> *sys, const int2 *map, int nblk, int maxM, Tables<T> tb,
                       int parity, int write_force_only, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_step2<T>, dim3(nblk, maxM), dim3(kBlock), 0, st, sys, blk_sys, tb, parity,
+    hipLaunchKernelGGL(k_step2<T>, dim3(nblk, maxM), dim3(kBlock), 0, st, sys, map, tb, parity,
                        write_force_only);
 }
 template <typename T>
-void Launch<T>::init_pop(const SysDesc<T> *sys, const int *blk_sys, int nblk, const double *n0,
+void Launch<T>::init_pop(const SysDesc<T> *sys, const int2 *map, int nblk, const double *n0,
                          const double *u0, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_init_pop<T>, dim3(nblk), dim3(kBlock), 0, st, sys, blk_sys, n0, u0);
+    hipLaunchKernelGGL(k_init_pop<T>, dim3(nblk), dim3(kBlock), 0, st, sys, map, n0, u0);
 }
 
 }  // namespace mlb

@@ -1,0 +1,122 @@
+"""GPU tests of the batched ensemble runtime and of graph replay.
+
+- A batch of uneven systems advances exactly like the same systems run one
+  by one (the per-site arithmetic does not depend on which block or launch
+  computes it): bit-for-bit in float64 and in float32.
+- Graph replay equals eager launches, checked after every replay with eager
+  work and synchronisation in between.
+- The autotuner restores the initial state after its trial steps.
+- Float32 batch members stay within 1e-5 of the oracle.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _systems():
+    out = []
+    specs = [((16, 12, 12), 2.0, 0.25, 0.3), ((24, 16, 12), 3.4, 0.15, 0.7), ((12, 12, 20), 2.6, 0.3, 0.5),
+             ((20, 20, 16), 4.0, 0.12, 0.2)]
+    for (nx, ny, nz), s2, xi, x1 in specs:
+        m = W.Mixture(nx, ny, nz, sigma=(2.0, s2))
+        n = W.number_density(xi, (x1, 1 - x1), m.sigma)
+        n0, u0 = W.mode_state(m, n, x1, 0.05, noise=0.02, seed=nx * 7 + ny)
+        out.append((m, n0, u0))
+    return out
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_batch_equals_individual_mixtures(precision):
+    import paper_1105_3634_amd as mlb
+    sy = _systems()
+    print(f"[batch vs single] precision={precision} systems={[s[0].shape() for s in sy]}", flush=True)
+    b = mlb.GpuBatch([s[0] for s in sy], [s[1] for s in sy], [s[2] for s in sy], precision=precision)
+    b.step(7)
+    for k, (m, n0, u0) in enumerate(sy):
+        g = mlb.GpuMixture(m, n0, u0, precision=precision)
+        g.step(7)
+        assert np.array_equal(_np(b.populations(k)), _np(g.populations())), k
+
+
+def test_graph_replay_equals_eager():
+    import torch
+    import paper_1105_3634_amd as mlb
+    m, n0, u0 = W.config_step_binary(32, 12, 12)
+    for prec in (64, 32):
+        ge = mlb.GpuMixture(m, n0, u0, precision=prec)
+        ge.set_graph(False)
+        gg = mlb.GpuMixture(m, n0, u0, precision=prec)
+        gg.set_graph(True)
+        for rep in range(4):
+            ge.step(6)
+            gg.step(6)
+            torch.cuda.synchronize()
+            ne, _ = ge.moments()        # eager work between replays
+            ng, _ = gg.moments()
+            assert np.array_equal(_np(ge.populations()), _np(gg.populations())), (prec, rep)
+            assert np.array_equal(_np(ne), _np(ng))
+        # odd counts: an eager step then graph replays
+        ge.step(5)
+        gg.step(5)
+        assert np.array_equal(_np(ge.populations()), _np(gg.populations()))
+
+
+def test_autotuner_restores_initial_state():
+    import paper_1105_3634_amd as mlb
+    sy = _systems()
+    mixes, n0s, u0s = [s[0] for s in sy], [s[1] for s in sy], [s[2] for s in sy]
+    bt = mlb.GpuBatch(mixes, n0s, u0s, precision=32, options=mlb.OPT_TUNE)
+    tune = bt.tuning()
+    print(f"  tuning: {tune}", flush=True)
+    assert tune["shape"] in (0, 1, 2) and tune["order"] in (0, 1)
+    assert all(v > 0 for v in tune["trial_ms"])
+    assert bt.steps == 0
+    b0 = mlb.GpuBatch(mixes, n0s, u0s, precision=32)
+    bt.step(4)
+    b0.step(4)
+    for k in range(len(sy)):
+        assert np.array_equal(_np(bt.populations(k)), _np(b0.populations(k)))
+
+
+def test_batch_fp32_against_oracle(oracle_lib):
+    import paper_1105_3634_amd as mlb
+    sy = _systems()[:2]
+    b = mlb.GpuBatch([s[0] for s in sy], [s[1] for s in sy], [s[2] for s in sy], precision=32)
+    b.step(60)
+    for k, (m, n0, u0) in enumerate(sy):
+        o = oracle_lib.Oracle(m)
+        no = o.densities(o.step(o.init(n0, u0), 60))
+        n32 = _np(b.moments(k)[0])
+        err = max(np.abs(n32[a] - no[a]).max() / np.abs(no[a]).max() for a in range(m.M))
+        print(f"  system {k}: fp32 density rel err {err:.2e}", flush=True)
+        assert err < 1e-5
+
+
+def test_batch_mode_fit_matches_single_system_fit():
+    import paper_1105_3634_amd as mlb
+    sy = _systems()
+    b = mlb.GpuBatch([s[0] for s in sy], [s[1] for s in sy], [s[2] for s in sy], precision=32)
+    singles = [mlb.GpuMixture(m, n0, u0, precision=32) for m, n0, u0 in sy]
+    for t in range(21):
+        b.record_modes()
+        for g in singles:
+            g.record_mode(0, 1)
+        b.step(5)
+        for g in singles:
+            g.step(5)
+    Db = b.fit(t_min=20)
+    for k, g in enumerate(singles):
+        Ds = g.fit(0, t_min=20)
+        assert Db[k] == Ds, (k, Db[k], Ds)
+        t, v = g.series()
+        sel = t >= 20
+        slope = np.polyfit(t[sel], np.log(v[sel]), 1)[0]
+        kk = 2 * np.pi / sy[k][0].nx
+        np.testing.assert_allclose(Ds, -slope / kk ** 2, rtol=1e-9)

@@ -82,7 +82,8 @@ def _rel_maxnorm(got, ref):
     return max(out)
 
 
-@pytest.mark.parametrize("name,steps", [("step_binary", 100), ("bulk_small", 100), ("walls", 100)])
+@pytest.mark.parametrize("name,steps", [("step_binary", 100), ("bulk_small", 100), ("walls", 100),
+                                        ("fe_tau", 60), ("ternary_tail_ext", 50)])
 def test_fp32_densities_within_1e5(oracle_lib, name, steps):
     m, n0, u0 = _case(name)
     print(f"[fp32 densities] case={name} shape={m.shape()} steps={steps}", flush=True)

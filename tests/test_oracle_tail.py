@@ -68,3 +68,15 @@ def test_tail_plane_wave_is_odd_and_in_quadrature(oracle_lib):
     expect = n0[0] * (-1e-4 * np.sin(k * x) * lat)[None, None, :]
     np.testing.assert_allclose(d["Ntail"][0, 0], expect, rtol=0, atol=1e-13 * np.abs(expect).max())
     assert np.abs(d["Ntail"][0, 1:]).max() < 1e-20
+
+
+def test_fft_stepping_matches_direct_stepping(oracle_lib):
+    """The long-run oracle mode (attractive field by FFT) tracks the ordered
+    direct sum to float64 rounding over several steps."""
+    m = W.Mixture(16, 14, 12, sigma=(1.5, 2.5), eps=np.array([[0.15, 0.1], [0.1, 0.05]]), rc_factor=2.2)
+    n0, u0 = W.random_state(m, [0.02, 0.01], rel=0.5, u_amp=0.01, seed=31)
+    o = oracle_lib.Oracle(m)
+    f0 = o.init(n0, u0)
+    fd = o.step(f0, 5)
+    ff = o.step_fft(f0, 5)
+    assert np.abs(fd - ff).max() / np.abs(fd).max() < 1e-12
