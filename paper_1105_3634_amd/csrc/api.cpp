@@ -282,7 +282,8 @@ bool plan_batch(Batch &B, const mlb_params *params, int count, std::string &why)
     for (int v = 0; v < mlb::kTileVariants; ++v) fits = fits && mlb::tile_lds_bytes_of(v, B.reach_max) <= 160 * 1024;
     B.tiled = B.prec == 32 && !any_direct_tail && fits;
     const size_t ts = tsize_of(B.prec);
-    B.desc_size = align_up(B.prec == 64 ? sizeof(mlb::SysDesc<double>) : sizeof(mlb::SysDesc<float>));
+    // kernels index the descriptor array with the struct's own stride
+    B.desc_size = B.prec == 64 ? sizeof(mlb::SysDesc<double>) : sizeof(mlb::SysDesc<float>);
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + std::max<size_t>(bytes, 1)); return o; };
     B.desc = take((size_t)(count + 1) * B.desc_size);
