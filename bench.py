@@ -81,6 +81,23 @@ def algorithmic_work(mix, tail_direct: bool):
     return flops, bytes_, S, T
 
 
+def d12_check(mlb, mix, n0, u0):
+    """D_12 of the same workload over 2000 steps (mode decay, Sec. 5.1)
+    against the stored float64 oracle value."""
+    golden = os.path.join(ROOT, "tests", "golden", "bulk_diffusion_128x32x32_2000.json")
+    if not os.path.exists(golden) or (mix.nx, mix.ny, mix.nz) != (128, 32, 32):
+        return None
+    with open(golden) as fh:
+        ref = json.load(fh)
+    g = mlb.GpuMixture(mix, n0, u0, precision=32, device="cuda:0")
+    for t in range(0, 2001, 10):
+        g.record_mode(0, 1)
+        if t < 2000:
+            g.step(10)
+    D = g.fit(0, t_min=ref["fit_t_min"])
+    return {"d12": D, "d12_oracle_fp64": ref["D12"], "rel_err": D / ref["D12"] - 1, "steps": 2000}
+
+
 def cpu_baseline(mix, n0, u0, target_s=12.0):
     import oracle
     o = oracle.Oracle(mix)
@@ -104,6 +121,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tail", choices=["auto", "direct", "spectral"], default="auto")
+    ap.add_argument("--no-d12", action="store_true", help="skip the 2000-step D_12 accuracy check")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB elementwise copy (counter calibration for profiles)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of this "
@@ -116,9 +136,18 @@ def main():
     import paper_1105_3634_amd as mlb
     import workloads as W
 
+    if args.calibrate_copy:
+        x = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4}))
+        return
+
     mix, n0, u0 = W.config_bulk_diffusion()
     tail_mode = {"auto": mlb.TAIL_AUTO, "direct": mlb.TAIL_DIRECT, "spectral": mlb.TAIL_SPECTRAL}[args.tail]
-    g = mlb.GpuMixture(mix, n0, u0, precision=32, tail_mode=tail_mode, device="cuda:0")
+    g = mlb.GpuMixture(mix, n0, u0, precision=32, tail_mode=tail_mode, device="cuda:0", options=mlb.OPT_TUNE)
     g.step(args.warmup)
     torch.cuda.synchronize()
     g.profile_begin()
@@ -161,7 +190,11 @@ def main():
                      "flop_per_launch": flops[dom], "avg_launch_ms": avg_ms[dom]},
         "hbm_gbs_algorithmic": total_bytes / elapsed / 1e9,
         "passes_ms_per_step": {k: v[0] / args.steps for k, v in passes.items()},
+        "tuning": g.tuning(),
     }
+    acc = None if args.no_d12 else d12_check(mlb, mix, n0, u0)
+    if acc is not None:
+        line["d12"] = acc
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(mix, n0, u0)
     print(json.dumps(line), flush=True)

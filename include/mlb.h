@@ -68,6 +68,8 @@ typedef enum {
 
 enum { MLB_SCHEME_CN_J1 = 0, MLB_SCHEME_FE = 1 };
 enum { MLB_TAIL_AUTO = 0, MLB_TAIL_DIRECT = 1, MLB_TAIL_SPECTRAL = 2 };
+enum { MLB_OPT_TUNE = 1u,       /* time every tile shape and block order at init, keep the fastest */
+       MLB_OPT_NO_GRAPH = 2u }; /* launch the passes eagerly instead of replaying a graph */
 enum { MLB_PART_MF = 1u, MLB_PART_TAIL = 2u, MLB_PART_DISS = 4u, MLB_PART_EXT = 8u,
        MLB_PART_ALL = 15u };
 
@@ -109,6 +111,17 @@ size_t mlb_workspace_bytes(const mlb_params *p);
  * released with mlb_destroy. */
 mlb_status mlb_init_mixture(const mlb_params *p, void *workspace, size_t workspace_bytes,
                             const double *n0, const double *u0, void *stream, mlb_mixture *out);
+
+/* As mlb_init_mixture, with options (MLB_OPT_TUNE, MLB_OPT_NO_GRAPH; see the
+ * batched ensemble below).  With MLB_OPT_TUNE the float32 tile shape and
+ * block order are chosen by timing full steps of every candidate, after
+ * which the populations are reset to the initial state. */
+mlb_status mlb_init_mixture_ex(const mlb_params *p, void *workspace, size_t workspace_bytes,
+                               const double *n0, const double *u0, uint32_t options, void *stream,
+                               mlb_mixture *out);
+
+/* Tile shape and block order in use (see mlb_batch_tuning). */
+mlb_status mlb_tuning(mlb_mixture h, int32_t *shape, int32_t *order, double *trial_ms);
 
 /* Advance the populations by nsteps >= 0 time steps of the kinetic equation
  * (Sec. 2, eq. evolution, with the field of Sec. 3). */
@@ -199,8 +212,6 @@ const char *mlb_last_error(void);
  * float32 batches without tails use the LDS-tile gathers.
  * ---------------------------------------------------------------------- */
 typedef struct mlb_batch_s *mlb_batch;
-enum { MLB_OPT_TUNE = 1u,       /* time every tile shape and block order at init, keep the fastest */
-       MLB_OPT_NO_GRAPH = 2u }; /* launch the passes eagerly instead of replaying a graph */
 
 /* Workspace bytes for `count` systems described by systems[0..count-1]; 0 if
  * any is invalid. */

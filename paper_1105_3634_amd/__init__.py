@@ -72,7 +72,7 @@ class GpuMixture:
     """One mixture on the GPU.  Fields come back as torch tensors on the device."""
 
     def __init__(self, mix, n0: np.ndarray, u0: np.ndarray, precision: int = 32, tail_mode: int = TAIL_AUTO,
-                 device: str = "cuda:0", stream=None):
+                 device: str = "cuda:0", stream=None, options: int = 0):
         torch = _torch()
         self.lib = _lib.load()
         self.mix = mix
@@ -93,10 +93,10 @@ class GpuMixture:
         u0_d = torch.as_tensor(np.ascontiguousarray(u0, dtype=np.float64)).to(self.device)
         assert n0_d.numel() == self.M * self.N and u0_d.numel() == 3 * self.M * self.N
         h = C.c_void_p()
-        st = self.lib.mlb_init_mixture(C.byref(self.params), C.c_void_p(self.ws.data_ptr()), nbytes,
-                                       C.c_void_p(n0_d.data_ptr()), C.c_void_p(u0_d.data_ptr()),
-                                       _stream_handle(stream), C.byref(h))
-        _lib.check(st, "mlb_init_mixture")
+        st = self.lib.mlb_init_mixture_ex(C.byref(self.params), C.c_void_p(self.ws.data_ptr()), nbytes,
+                                          C.c_void_p(n0_d.data_ptr()), C.c_void_p(u0_d.data_ptr()), int(options),
+                                          _stream_handle(stream), C.byref(h))
+        _lib.check(st, "mlb_init_mixture_ex")
         self.h = h
 
     def close(self) -> None:
@@ -113,6 +113,12 @@ class GpuMixture:
     # --------------------------------------------------------------- driving
     def step(self, nsteps: int = 1) -> None:
         _lib.check(self.lib.mlb_step(self.h, int(nsteps), _stream_handle(self.stream)), "mlb_step")
+
+    def tuning(self):
+        shape, order = C.c_int32(), C.c_int32()
+        ms = (C.c_double * 6)()
+        _lib.check(self.lib.mlb_tuning(self.h, C.byref(shape), C.byref(order), ms), "mlb_tuning")
+        return {"shape": int(shape.value), "order": int(order.value), "trial_ms": list(ms[:])}
 
     def set_graph(self, enable: bool) -> None:
         _lib.check(self.lib.mlb_set_graph(self.h, 1 if enable else 0), "mlb_set_graph")

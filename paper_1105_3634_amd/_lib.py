@@ -51,6 +51,9 @@ _SIGS = [
     ("mlb_workspace_bytes", C.c_size_t, [C.POINTER(Params)]),
     ("mlb_init_mixture", C.c_int, [C.POINTER(Params), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
                                    C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("mlb_init_mixture_ex", C.c_int, [C.POINTER(Params), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
+                                      C.c_uint32, C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("mlb_tuning", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     ("mlb_step", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     ("mlb_moments", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("mlb_forces", C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p]),

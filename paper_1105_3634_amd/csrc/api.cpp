@@ -158,6 +158,7 @@ bool has_tail(const HostTables &t) { return !t.tl_e.empty(); }
 bool wants_spectral(const mlb_params *p, const HostTables &t, int count)
 {
     if (!has_tail(t) || p->walls_y || p->precision != 32 || count != 1) return false;
+    if (!mlb::SpectralPlan::fused_fits(p->ny, p->nz, p->nspecies)) return false;
     return p->tail_mode == MLB_TAIL_AUTO || p->tail_mode == MLB_TAIL_SPECTRAL;
 }
 
@@ -192,7 +193,7 @@ const char *kPassNames[MLB_NPASS] = {"moments", "contact", "tail", "gather1", "s
 
 // ---------------------------------------------------------------- the core
 struct mlb_batch_s {
-    int count = 0, prec = 32, maxM = 1, reach_max = 0;
+    int count = 0, prec = 32, maxM = 1, reach_max = 0, sh_max = 1;
     bool tiled = false;
     std::vector<SysHost> sys;
     char *ws = nullptr;
@@ -269,17 +270,22 @@ bool plan_batch(Batch &B, const mlb_params *params, int count, std::string &why)
         S.P = S.M * (S.M + 1) / 2;
         S.N = (long long)S.p.nx * S.p.ny * S.p.nz;
         S.nblocks = (int)((S.N + mlb::kBlock - 1) / mlb::kBlock);
-        if (S.p.tail_mode == MLB_TAIL_SPECTRAL && has_tail(S.tabs) && (B.prec != 32 || S.p.walls_y || count != 1)) {
-            why = "the spectral tail needs float32, a periodic box and a single system";
+        if (S.p.tail_mode == MLB_TAIL_SPECTRAL && has_tail(S.tabs) &&
+            (B.prec != 32 || S.p.walls_y || count != 1 ||
+             !mlb::SpectralPlan::fused_fits(S.p.ny, S.p.nz, S.p.nspecies))) {
+            why = "the spectral tail needs float32, a periodic box, a single system and a (y, z) plane that fits LDS";
             return false;
         }
         S.spectral = wants_spectral(&S.p, S.tabs, count);
         any_direct_tail = any_direct_tail || (has_tail(S.tabs) && !S.spectral);
         B.maxM = std::max(B.maxM, S.M);
         B.reach_max = std::max(B.reach_max, S.tabs.shell_reach);
+        for (int a = 0; a < S.M; ++a)
+            for (int b = 0; b < S.M; ++b) B.sh_max = std::max(B.sh_max, S.tabs.sh_cnt[a][b]);
     }
     bool fits = true;
-    for (int v = 0; v < mlb::kTileVariants; ++v) fits = fits && mlb::tile_lds_bytes_of(v, B.reach_max) <= 160 * 1024;
+    for (int v = 0; v < mlb::kTileVariants; ++v)
+        fits = fits && mlb::tile_lds_bytes_of(v, B.reach_max, B.sh_max) <= 160 * 1024;
     B.tiled = B.prec == 32 && !any_direct_tail && fits;
     const size_t ts = tsize_of(B.prec);
     // kernels index the descriptor array with the struct's own stride
@@ -366,6 +372,7 @@ void fill_desc(Batch &B, int k, mlb::SysDesc<T> &D)
     D.N = S.N;
     D.nblocks = S.nblocks;
     D.reach = S.tabs.shell_reach;
+    D.sh_max = B.sh_max;
     char *ws = B.ws;
     D.f[0] = reinterpret_cast<T *>(ws + S.f0);
     D.f[1] = reinterpret_cast<T *>(ws + S.f1);
@@ -510,6 +517,7 @@ mlb_status setup_spectral(Batch &B, SysHost &S, hipStream_t st)
     std::vector<float> m[6] = {mlb::SpectralPlan::dft_x_forward(p->nx), mlb::SpectralPlan::dft_x_inverse(p->nx),
                                mlb::SpectralPlan::dft_block(p->ny, false), mlb::SpectralPlan::dft_block(p->ny, true),
                                mlb::SpectralPlan::dft_block(p->nz, false), mlb::SpectralPlan::dft_block(p->nz, true)};
+    if (!mlb::SpectralPlan::prepare(p->ny, p->nz, S.M)) return fail(MLB_EHIP, "cannot raise the LDS limit of the tail kernel");
     const size_t offs[6] = {S.wxf, S.wxi, S.wyf, S.wyi, S.wzf, S.wzi};
     for (int k = 0; k < 6; ++k)
         HIP_TRY(hipMemcpyAsync(ws + offs[k], m[k].data(), sizeof(float) * m[k].size(), hipMemcpyHostToDevice, st));
@@ -602,9 +610,9 @@ void run_passes(Batch &B, hipStream_t st, bool query, int qk, int force_only)
             const int ntl = query ? mlb::tile_count(shape, B.sys[qk].p.nx, B.sys[qk].p.ny, B.sys[qk].p.nz)
                                   : B.nblk_tile;
             pass(B, kPassGather1, st,
-                 [&] { mlb::launch_gather1_tile(shape, sys, tmap, ntl, M, tb, B.reach_max, st); });
+                 [&] { mlb::launch_gather1_tile(shape, sys, tmap, ntl, M, tb, B.reach_max, B.sh_max, st); });
             pass(B, kPassStep2, st,
-                 [&] { mlb::launch_step2_tile(shape, sys, tmap, ntl, M, tb, B.reach_max, par, force_only, st); });
+                 [&] { mlb::launch_step2_tile(shape, sys, tmap, ntl, M, tb, B.reach_max, B.sh_max, par, force_only, st); });
             return;
         }
     }
@@ -777,7 +785,7 @@ mlb_status create(Batch &B, const mlb_params *params, int count, void *workspace
         if (!n0[k] || !u0[k]) return fail(MLB_EINVAL, "n0 and u0 are required for every system");
     B.ws = static_cast<char *>(workspace);
     B.use_graph = (options & MLB_OPT_NO_GRAPH) == 0;
-    if (B.tiled && !mlb::tile_prepare(B.reach_max)) B.tiled = false;
+    if (B.tiled && !mlb::tile_prepare(B.reach_max, B.sh_max)) B.tiled = false;
     TRY(upload_static<T>(B, st));
     if (B.tiled) TRY(set_tiling(B, 0, 1, st));
     for (auto &S : B.sys)
@@ -866,8 +874,8 @@ extern "C" {
 
 size_t mlb_workspace_bytes(const mlb_params *p) { return workspace_for(p, 1); }
 
-mlb_status mlb_init_mixture(const mlb_params *p, void *workspace, size_t workspace_bytes, const double *n0,
-                            const double *u0, void *stream, mlb_mixture *out)
+mlb_status mlb_init_mixture_ex(const mlb_params *p, void *workspace, size_t workspace_bytes, const double *n0,
+                               const double *u0, uint32_t options, void *stream, mlb_mixture *out)
 {
     if (!out) return fail(MLB_EINVAL, "out is NULL");
     *out = nullptr;
@@ -875,11 +883,17 @@ mlb_status mlb_init_mixture(const mlb_params *p, void *workspace, size_t workspa
     std::unique_ptr<mlb_mixture_s> h(new mlb_mixture_s());
     const double *n0v[1] = {n0}, *u0v[1] = {u0};
     mlb_status s = p->precision == 64
-                       ? create<double>(*h, p, 1, workspace, workspace_bytes, n0v, u0v, 0, S_(stream))
-                       : create<float>(*h, p, 1, workspace, workspace_bytes, n0v, u0v, 0, S_(stream));
+                       ? create<double>(*h, p, 1, workspace, workspace_bytes, n0v, u0v, options, S_(stream))
+                       : create<float>(*h, p, 1, workspace, workspace_bytes, n0v, u0v, options, S_(stream));
     if (s != MLB_OK) return s;
     *out = h.release();
     return MLB_OK;
+}
+
+mlb_status mlb_init_mixture(const mlb_params *p, void *workspace, size_t workspace_bytes, const double *n0,
+                            const double *u0, void *stream, mlb_mixture *out)
+{
+    return mlb_init_mixture_ex(p, workspace, workspace_bytes, n0, u0, 0, stream, out);
 }
 
 mlb_status mlb_step(mlb_mixture h, int32_t nsteps, void *stream)
@@ -1131,6 +1145,11 @@ mlb_status mlb_batch_fit(mlb_batch h, double t_min, double *D_out, void *stream)
     HIP_TRY(hipStreamSynchronize(st));
     for (int k = 0; k < h->count; ++k) D_out[k] = host[4 * (size_t)k];
     return MLB_OK;
+}
+
+mlb_status mlb_tuning(mlb_mixture h, int32_t *shape, int32_t *order, double *trial_ms)
+{
+    return mlb_batch_tuning(h, shape, order, trial_ms);
 }
 
 mlb_status mlb_batch_tuning(mlb_batch h, int32_t *shape, int32_t *order, double *trial_ms)

@@ -50,25 +50,34 @@ __device__ inline TileGeo tile_geo(const SysDesc<float> &S, int local)
     return t;
 }
 
-__device__ inline int wrapi(int v, int n)
+// Stage (n_b, vec_b) as float4 and g as float into LDS for the halo tile:
+// lds4[FS] then ldsg[FS].  Thread t walks the flat halo index t, t + 256, ...
+// with its (hx, hy, hz) coordinates advanced incrementally (no divisions);
+// consecutive threads read consecutive x, so global loads coalesce.
+__device__ inline int wrap_small(int v, int n)
 {
-    v %= n;
-    return v < 0 ? v + n : v;
+    while (v < 0) v += n;
+    while (v >= n) v -= n;
+    return v;
 }
 
-// Stage (n_b, vec_b) as float4 and g as float into LDS for the halo tile:
-// lds4[FS] then ldsg[FS].
 __device__ inline void stage(const SysDesc<float> &S, const TileGeo &t, float4 *lds4, float *ldsg,
                              const float *__restrict__ nb, const float *__restrict__ vb, const float *__restrict__ gp)
 {
     const long long N = S.N;
-    for (int i = threadIdx.x; i < t.FS; i += kBlock) {
-        const int hx = i % t.HX, hy = (i / t.HX) % t.HY, hz = i / (t.HX * t.HY);
-        const int gx = wrapi(t.x0 - t.R + hx, S.nx), gz = wrapi(t.z0 - t.R + hz, S.nz);
+    // step of kBlock in (hx, hy, hz) digits
+    const int HXY = t.HX * t.HY;
+    const int sz = kBlock / HXY, rem = kBlock - sz * HXY;
+    const int sy = rem / t.HX, sx = rem - sy * t.HX;
+    int i = threadIdx.x;
+    int hz = i / HXY, r0 = i - hz * HXY;
+    int hy = r0 / t.HX, hx = r0 - hy * t.HX;
+    for (; i < t.FS; i += kBlock) {
+        const int gx = wrap_small(t.x0 - t.R + hx, S.nx), gz = wrap_small(t.z0 - t.R + hz, S.nz);
         int gy = t.y0 - t.R + hy;
         bool in = true;
         if (S.walls) in = gy >= 0 && gy < S.ny;
-        else gy = wrapi(gy, S.ny);
+        else gy = wrap_small(gy, S.ny);
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         float g = 0.f;
         if (in) {
@@ -78,6 +87,31 @@ __device__ inline void stage(const SysDesc<float> &S, const TileGeo &t, float4 *
         }
         lds4[i] = v;
         ldsg[i] = g;
+        hx += sx; hy += sy; hz += sz;
+        if (hx >= t.HX) { hx -= t.HX; ++hy; }
+        if (hy >= t.HY) { hy -= t.HY; ++hz; }
+    }
+}
+
+// Copy the (a,b) half-shell into LDS: TA[k] = (LDS offset of e, e_hat),
+// TB[k] = (ee_xx, ee_xy, ee_xz, ee_yy), TC[k] = (ee_yz, ee_zz).  Reads of it
+// are wave-uniform broadcasts that share the in-order LDS counter with the
+// field reads, so the pair loop can be software-pipelined.
+__device__ inline void stage_table(const Tables<float> &tb, int k0, int kn, const TileGeo &t, float4 *TA, float4 *TB,
+                                   float2 *TC, bool with_ee)
+{
+    const int HXY = t.HX * t.HY;
+    for (int k = threadIdx.x; k < kn; k += kBlock) {
+        int ex, ey, ez;
+        unpack_offset(tb.sh_e[k0 + k], ex, ey, ez);
+        const int off = ex + ey * t.HX + ez * HXY;
+        const float *u = tb.sh_u + 3 * (k0 + k);
+        TA[k] = make_float4(__int_as_float(off), u[0], u[1], u[2]);
+        if (with_ee) {
+            const float *ee = tb.sh_ee + 6 * (k0 + k);
+            TB[k] = make_float4(ee[0], ee[1], ee[2], ee[3]);
+            TC[k] = make_float2(ee[4], ee[5]);
+        }
     }
 }
 
@@ -120,6 +154,9 @@ __global__ void __launch_bounds__(kBlock) k_gather1_tile(const SysDesc<float> *_
     const long long o3 = (long long)a * 3 * N;
     float4 *L4 = lds;
     float *Lg = reinterpret_cast<float *>(lds + t.FS);
+    float4 *TA = lds + t.FS + (t.FS + 3) / 4;
+    float4 *TB = TA + S.sh_max;
+    float2 *TC = reinterpret_cast<float2 *>(TB + S.sh_max);
     const bool solid = q.active && S.walls && (q.y == 0 || q.y == S.ny - 1);
     const long long sc = q.active ? q.s : 0;
     const float na = S.n[(long long)a * N + sc];
@@ -129,29 +166,28 @@ __global__ void __launch_bounds__(kBlock) k_gather1_tile(const SysDesc<float> *_
     const int HXY = t.HX * t.HY;
     for (int b = 0; b < S.M; ++b) {
         const float *__restrict__ gpair = S.g + (long long)pidx(S.M, a, b) * N;
+        const int k0 = S.sh_start[a][b], kn = S.sh_cnt[a][b];
         __syncthreads();
         stage(S, t, L4, Lg, S.n + (long long)b * N, S.j + (long long)b * 3 * N, gpair);
+        stage_table(tb, k0, kn, t, TA, TB, TC, true);
         __syncthreads();
         const float g0 = Lg[q.c];
         float s0 = 0.f, s1 = 0.f, s2 = 0.f, v0 = 0.f, v1 = 0.f, v2 = 0.f;
         float t00 = 0.f, t01 = 0.f, t02 = 0.f, t11 = 0.f, t12 = 0.f, t22 = 0.f;
-        const int k0 = S.sh_start[a][b], kn = S.sh_cnt[a][b];
 #pragma unroll 4
         for (int k = 0; k < kn; ++k) {
-            int ex, ey, ez;
-            unpack_offset(tb.sh_e[k0 + k], ex, ey, ez);
-            const int off = ex + ey * t.HX + ez * HXY;
-            const float *u = tb.sh_u + 3 * (k0 + k);
-            const float *ee = tb.sh_ee + 6 * (k0 + k);
-            const float e0 = u[0], e1 = u[1], e2 = u[2];
+            const float4 ta = TA[k], tb4 = TB[k];
+            const float2 tc = TC[k];
+            const int off = __float_as_int(ta.x);
+            const float e0 = ta.y, e1 = ta.z, e2 = ta.w;
             const int p = q.c + off, m = q.c - off;
             const float4 Ap = L4[p], Am = L4[m];
             const float Gp = g0 + Lg[p], Gm = g0 + Lg[m];
             const float tp = Gp * Ap.x, tm = Gm * Am.x;
             const float dt = tp - tm, st = tp + tm;
             s0 += e0 * dt; s1 += e1 * dt; s2 += e2 * dt;
-            t00 += st * ee[0]; t01 += st * ee[1]; t02 += st * ee[2];
-            t11 += st * ee[3]; t12 += st * ee[4]; t22 += st * ee[5];
+            t00 += st * tb4.x; t01 += st * tb4.y; t02 += st * tb4.z;
+            t11 += st * tb4.w; t12 += st * tc.x; t22 += st * tc.y;
             const float w0 = Gp * Ap.y + Gm * Am.y;
             const float w1 = Gp * Ap.z + Gm * Am.z;
             const float w2 = Gp * Ap.w + Gm * Am.w;
@@ -230,24 +266,24 @@ __global__ void __launch_bounds__(kBlock) k_step2_tile(const SysDesc<float> *__r
     const long long o3 = (long long)a * 3 * N;
     float4 *L4 = lds;
     float *Lg = reinterpret_cast<float *>(lds + t.FS);
+    float4 *TA = lds + t.FS + (t.FS + 3) / 4;
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
     const int HXY = t.HX * t.HY;
     if (S.scheme != 1) {
         for (int b = 0; b < S.M; ++b) {
             const float *__restrict__ gpair = S.g + (long long)pidx(S.M, a, b) * N;
+            const int k0 = S.sh_start[a][b], kn = S.sh_cnt[a][b];
             __syncthreads();
             stage(S, t, L4, Lg, S.n + (long long)b * N, S.vh + (long long)b * 3 * N, gpair);
+            stage_table(tb, k0, kn, t, TA, nullptr, nullptr, false);
             __syncthreads();
             const float g0 = Lg[q.c];
             float v0 = 0.f, v1 = 0.f, v2 = 0.f;
-            const int k0 = S.sh_start[a][b], kn = S.sh_cnt[a][b];
 #pragma unroll 4
             for (int k = 0; k < kn; ++k) {
-                int ex, ey, ez;
-                unpack_offset(tb.sh_e[k0 + k], ex, ey, ez);
-                const int off = ex + ey * t.HX + ez * HXY;
-                const float *u = tb.sh_u + 3 * (k0 + k);
-                const float e0 = u[0], e1 = u[1], e2 = u[2];
+                const float4 ta = TA[k];
+                const int off = __float_as_int(ta.x);
+                const float e0 = ta.y, e1 = ta.z, e2 = ta.w;
                 const int p = q.c + off, m = q.c - off;
                 const float4 Ap = L4[p], Am = L4[m];
                 const float tp = (g0 + Lg[p]) * Ap.x, tm = (g0 + Lg[m]) * Am.x;
@@ -308,9 +344,11 @@ __global__ void __launch_bounds__(kBlock) k_step2_tile(const SysDesc<float> *__r
     }
 }
 
-inline size_t tile_lds_bytes(int TX, int TY, int TZ, int R)
+// float4 + float per staged site, then the shell table (40 bytes per entry)
+inline size_t tile_lds_bytes(int TX, int TY, int TZ, int R, int sh_max)
 {
-    return sizeof(float) * kTileFields * (size_t)(TX + 2 * R) * (TY + 2 * R) * (TZ + 2 * R);  // float4 + float
+    const size_t FS = (size_t)(TX + 2 * R) * (TY + 2 * R) * (TZ + 2 * R);
+    return 16 * FS + 16 * ((FS + 3) / 4) + 40 * (size_t)sh_max;
 }
 
 }  // namespace mlb

@@ -36,6 +36,7 @@ struct SysDesc {
     long long N;
     int nblocks;                     // per-site blocks of this system (ceil(N / kBlock))
     int reach;                       // largest |component| of any shell offset
+    int sh_max;                      // longest half-shell of the launch (LDS table slots)
     T *f[2];                         // population double buffer [M][19][N]
     T *n, *j, *u, *g, *vh, *H, *Nf;  // fields (see mlb.h for layouts)
     T *tail;                         // attractive field sum_b K_ab * n_b [M][3][N] (spectral mode)
@@ -106,12 +107,12 @@ struct Launch {
 constexpr int kTileVariants = 3;
 void tile_dims(int v, int &tx, int &ty, int &tz);
 void launch_gather1_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM, Tables<float> tb,
-                         int reach_max, hipStream_t st);
+                         int reach_max, int sh_max, hipStream_t st);
 void launch_step2_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM, Tables<float> tb,
-                       int reach_max, int parity, int write_force_only, hipStream_t st);
+                       int reach_max, int sh_max, int parity, int write_force_only, hipStream_t st);
 int tile_count(int v, int nx, int ny, int nz);
-bool tile_prepare(int reach_max);   // raise the dynamic-LDS limit once; false if it cannot fit
-size_t tile_lds_bytes_of(int v, int reach);
+bool tile_prepare(int reach_max, int sh_max);   // raise the dynamic-LDS limit; false if it cannot fit
+size_t tile_lds_bytes_of(int v, int reach, int sh_max);
 
 // float64 reductions (reduce.hip)
 void launch_conserved(const void *n, const void *j, int prec, int M, long long N, double *partials,

@@ -1,4 +1,6 @@
 // Spectral evaluation of the attractive field (see spectral.hip).
+// Applicable when a (y, z) plane of the box fits the LDS budget
+// (SpectralPlan::fused_fits); otherwise the field is summed directly.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,8 +40,13 @@ struct SpectralPlan {
     static std::vector<float> dft_x_inverse(int nx);
     static std::vector<float> dft_block(int L, bool inverse);
 
-    void forward_stages(const float *real_in, int nfields, float *s1, float *s2, hipStream_t st) const;
-    void inverse_stages(float *s1, float *s2, int nfields, float *real_out, hipStream_t st) const;
+    // x stage as batched GEMMs; spectra in [field][kx][re|im][z][y]
+    void x_forward(const float *real_in, int nfields, float *s1, hipStream_t st) const;
+    void x_inverse(const float *s2, int nfields, float *real_out, hipStream_t st) const;
+    // fused y/z stages, one workgroup per kx; mode 0 writes the sine spectra
+    void launch_yz(int mode, int nin, const float *in, float *out, hipStream_t st) const;
+    static bool fused_fits(int ny, int nz, int M);
+    static bool prepare(int ny, int nz, int M);
     // placed: [P][3][N] kernels w_ab on the periodic grid (sum over wrapped offsets)
     void build_spectrum(const float *placed, float *s1, float *s2, hipStream_t st) const;
     // tail [M][3][N] = sum_b K_ab * n_b for density fields n [M][N]

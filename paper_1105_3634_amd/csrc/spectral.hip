@@ -7,13 +7,14 @@
 // so each step runs: a real-to-complex DFT of the M density fields, the
 // spectral product, and a complex-to-real inverse DFT of the 3M output
 // components.  Every 1-D DFT along an axis is a dense contraction with the
-// DFT matrix, executed as a batched float32 GEMM on the matrix cores
-// (v_mfma_f32_16x16x4f32):
-//   x (innermost):  rows = lines, C = A W          (W: nx x 2nkx, or 2nkx x nx)
-//   y, z:           C = W B                         (W: 2L x 2L real block form
-//                                                    of the complex DFT matrix)
-// Complex data live as split real/imaginary planes:
-//   spec[field][plane][z][y][kx],  kx < nkx = nx/2 + 1.
+// DFT matrix on the matrix cores (v_mfma_f32_16x16x4f32):
+//   x (innermost):  batched GEMM over lines, C = A W  (W: nx x 2nkx, or 2nkx x nx)
+//   y and z:        one workgroup per kx plane holds the plane in LDS and
+//                   applies the 2L x 2L real block form of the complex DFT
+//                   matrix along y, then along z; the spectral product and
+//                   the inverse y/z transforms run in the same kernel.
+// Complex data live as split real/imaginary parts, kx-major:
+//   spec[field][kx][re|im][z][y],  kx < nkx = nx/2 + 1.
 // The spectrum S_ab is obtained once at init by the same forward stages
 // applied to the kernels w_ab placed on the grid, scaled by 1/N so the
 // inverse stages need no normalisation.
@@ -27,8 +28,7 @@ namespace mlb {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int kTM = 64, kTN = 64, kTK = 16;
-constexpr int kGemmThreads = 256;
+constexpr int kTK = 16;
 
 __device__ inline long long part_t(const MatAddr &m, int t)
 {
@@ -48,43 +48,46 @@ __device__ inline long long part_c(const MatAddr &m, int c)
 
 // C(t) [M x N] = A(t) [M x K] * B(t) [K x N], all float32, general strided
 // addressing (separable: batch part + row part + column part).  Workgroup:
-// 4 waves, 64x64 output tile, each wave a 32x32 quadrant made of 2x2 MFMA
-// 16x16 blocks; K staged through LDS 16 at a time, the next K slice held in
-// registers while the current one is consumed.  Each thread loads a fixed
-// tile column of A (4 rows) and a fixed tile column of B (4 K-rows), so
-// row/column address parts are computed once per workgroup.
+// W waves (W = 4: 64x64 output tile; W = 1: 32x32), each wave a 32x32
+// block made of 2x2 MFMA 16x16 blocks; K staged through LDS 16 at a time,
+// the next K slice held in registers while the current one is consumed.
+// Each thread loads a fixed tile column of A and of B, so row/column
+// address parts are computed once per workgroup.
 // Lane layout of v_mfma_f32_16x16x4f32: A[i][k] from lane i + 16k,
 // B[k][j] from lane j + 16k, D[4q + v][j] in lane j + 16q, element v.
-__global__ void __launch_bounds__(kGemmThreads) k_gemm_f32(GemmDesc g)
+template <int W>
+__global__ void __launch_bounds__(64 * W) k_gemm_f32(GemmDesc g)
 {
+    constexpr int kTM = W == 4 ? 64 : 32, kTN = kTM, NT = 64 * W;
+    constexpr int RA = kTM * kTK / NT, RB = kTK * kTN / NT;   // loads per thread
     __shared__ float As[kTM][kTK + 1];
     __shared__ float Bs[kTK][kTN + 1];
     const int t = blockIdx.z;
     const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int wm = W == 4 ? (wave >> 1) * 32 : 0, wn = W == 4 ? (wave & 1) * 32 : 0;
     const float *__restrict__ A = g.A.base + part_t(g.A, t);
     const float *__restrict__ B = g.B.base + part_t(g.B, t);
-    // A loads: rows ar + 16 i, K column ak
+    // A loads: rows ar + (NT / kTK) i, K column ak
     const int ar = tid / kTK, ak = tid % kTK;
-    long long arow[4];
-    bool arok[4];
-    for (int i = 0; i < 4; ++i) {
-        const int r = m0 + ar + 16 * i;
+    long long arow[RA];
+    bool arok[RA];
+    for (int i = 0; i < RA; ++i) {
+        const int r = m0 + ar + (NT / kTK) * i;
         arok[i] = r < g.M;
         arow[i] = arok[i] ? part_r(g.A, r) : 0;
     }
-    // B loads: K rows bk + 4 i, column bc
+    // B loads: K rows bk + (NT / kTN) i, column bc
     const int bk = tid / kTN, bc = tid % kTN;
     const bool bcok = n0 + bc < g.N;
     const long long bcol = bcok ? part_c(g.B, n0 + bc) : 0;
-    float ra[4], rb[4];
+    float ra[RA], rb[RB];
     auto load = [&](int k0) {
         const int ka = k0 + ak;
         const long long acol = ka < g.K ? part_c(g.A, ka) : 0;
-        for (int i = 0; i < 4; ++i) ra[i] = (arok[i] && ka < g.K) ? A[arow[i] + acol] : 0.f;
-        for (int i = 0; i < 4; ++i) {
-            const int kb = k0 + bk + 4 * i;
+        for (int i = 0; i < RA; ++i) ra[i] = (arok[i] && ka < g.K) ? A[arow[i] + acol] : 0.f;
+        for (int i = 0; i < RB; ++i) {
+            const int kb = k0 + bk + (NT / kTN) * i;
             rb[i] = (bcok && kb < g.K) ? B[part_r(g.B, kb) + bcol] : 0.f;
         }
     };
@@ -93,8 +96,8 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm_f32(GemmDesc g)
         for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
     load(0);
     for (int k0 = 0; k0 < g.K; k0 += kTK) {
-        for (int i = 0; i < 4; ++i) As[ar + 16 * i][ak] = ra[i];
-        for (int i = 0; i < 4; ++i) Bs[bk + 4 * i][bc] = rb[i];
+        for (int i = 0; i < RA; ++i) As[ar + (NT / kTK) * i][ak] = ra[i];
+        for (int i = 0; i < RB; ++i) Bs[bk + (NT / kTN) * i][bc] = rb[i];
         __syncthreads();
         if (k0 + kTK < g.K) load(k0 + kTK);
 #pragma unroll
@@ -123,41 +126,182 @@ __global__ void __launch_bounds__(kGemmThreads) k_gemm_f32(GemmDesc g)
     }
 }
 
+// 64x64 tiles when they give the chip enough workgroups, else 32x32.
 void launch_gemm(const GemmDesc &g, hipStream_t st)
 {
-    dim3 grid((g.N + kTN - 1) / kTN, (g.M + kTM - 1) / kTM, g.batch);
-    hipLaunchKernelGGL(k_gemm_f32, grid, dim3(kGemmThreads), 0, st, g);
-}
-
-// Spectral product: out(a,d) = i sum_b S_{p(a,b), d} n^_b.
-//   re_out = -sum_b S n^_b,im,  im_out = sum_b S n^_b,re
-__global__ void k_spec_mul(const float *__restrict__ in, const float *__restrict__ S, float *__restrict__ out,
-                           int M, long long Sp)
-{
-    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= Sp) return;
-    const int a = blockIdx.y / 3, d = blockIdx.y % 3;
-    float re = 0.f, im = 0.f;
-    for (int b = 0; b < M; ++b) {
-        const int lo = a < b ? a : b, hi = a < b ? b : a;
-        const int p = lo * M - (lo * (lo - 1)) / 2 + (hi - lo);
-        const float s = S[((long long)p * 3 + d) * Sp + k];
-        const float nr = in[(long long)b * 2 * Sp + k], ni = in[(long long)b * 2 * Sp + Sp + k];
-        re -= s * ni;
-        im += s * nr;
+    const long long big = (long long)((g.N + 63) / 64) * ((g.M + 63) / 64) * g.batch;
+    if (big >= 48) {
+        dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, g.batch);
+        hipLaunchKernelGGL(k_gemm_f32<4>, grid, dim3(256), 0, st, g);
+    } else {
+        dim3 grid((g.N + 31) / 32, (g.M + 31) / 32, g.batch);
+        hipLaunchKernelGGL(k_gemm_f32<1>, grid, dim3(64), 0, st, g);
     }
-    out[(long long)blockIdx.y * 2 * Sp + k] = re;
-    out[(long long)blockIdx.y * 2 * Sp + Sp + k] = im;
 }
 
-// S = -Im(F[w]) / Ntot from the forward spectrum of the placed kernels.
-__global__ void k_spec_extract(const float *__restrict__ spec, float *__restrict__ S, int nfields, long long Sp,
-                               float scale)
+// ------------------------------------------------- fused y/z stages (LDS)
+// Workgroup (kx, g): the kx plane of every input field and one output
+// component g.  Complex planes live in LDS as two real parts, x-rows padded
+// to odd strides against bank conflicts:
+//   X[p][z][y]  (row stride RY = ny + 1)      T[p][ky][z]  (row stride RZ = nz + 1)
+// Each 1-D transform is a dense contraction on the matrix cores
+// (v_mfma_f32_16x16x4f32, 16x16 output blocks dealt to the 4 waves):
+//   y stage:  T[(p',ky)][z]  = sum_{(p,y)} Wy[(p',ky)][(p,y)] X[p][z][y]
+//   z stage:  X[p'][kz][ky] = sum_{(p,z)} T[p][ky][z] Wz[(p',kz)][(p,z)]
+// with Wy, Wz the real 2L x 2L block form of the complex DFT matrix, staged
+// in LDS (row stride 2L + 1).  The K loop runs per real/imaginary block so
+// lane indices need no division.
+struct YZArgs {
+    int ny, nz, nkx, M, mode, nin;   // mode 0: forward only -> sine spectra; 1: full product
+    long long PS, Sp, FSTR;          // plane part size in global memory, per-field spectrum size, field stride
+    const float *in;
+    float *out;
+    const float *S;
+    float scale;
+    const float *wyf, *wyi, *wzf, *wzi;
+};
+
+struct YZLds {
+    int ny, nz, RY, RZ, PX, PT, ty, tz;   // PX, PT: padded part sizes of X and T planes
+};
+
+__device__ inline void yz_stage_y(const YZLds &g, const float *Wy, const float *X, float *T)
 {
-    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= Sp) return;
-    const int f = blockIdx.y;
-    S[(long long)f * Sp + k] = -spec[(long long)f * 2 * Sp + Sp + k] * scale;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, q = lane >> 4;
+    const int bm = (g.ty + 15) / 16, bn = (g.nz + 15) / 16;
+    for (int blk = wave; blk < bm * bn; blk += 4) {
+        const int i0 = (blk / bn) * 16, j0 = (blk % bn) * 16;
+        const int ia = i0 + li, jb = j0 + li;
+        v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int p = 0; p < 2; ++p)
+            for (int y0 = 0; y0 < g.ny; y0 += 4) {
+                const int yy = y0 + q;
+                const float a = (ia < g.ty && yy < g.ny) ? Wy[ia * (g.ty + 1) + p * g.ny + yy] : 0.f;
+                const float b = (jb < g.nz && yy < g.ny) ? X[p * g.PX + jb * g.RY + yy] : 0.f;
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+            }
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + 4 * q + v;
+            if (i < g.ty && jb < g.nz) {
+                const int pp = i >= g.ny ? 1 : 0;
+                T[pp * g.PT + (i - pp * g.ny) * g.RZ + jb] = acc[v];
+            }
+        }
+    }
+}
+
+__device__ inline void yz_stage_z(const YZLds &g, const float *Wz, const float *T, float *X)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, q = lane >> 4;
+    const int bm = (g.ny + 15) / 16, bn = (g.tz + 15) / 16;
+    for (int blk = wave; blk < bm * bn; blk += 4) {
+        const int i0 = (blk / bn) * 16, j0 = (blk % bn) * 16;
+        const int ia = i0 + li, jb = j0 + li;
+        v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int p = 0; p < 2; ++p)
+            for (int z0 = 0; z0 < g.nz; z0 += 4) {
+                const int zz = z0 + q;
+                const float a = (ia < g.ny && zz < g.nz) ? T[p * g.PT + ia * g.RZ + zz] : 0.f;
+                const float b = (jb < g.tz && zz < g.nz) ? Wz[jb * (g.tz + 1) + p * g.nz + zz] : 0.f;
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+            }
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + 4 * q + v;
+            if (i < g.ny && jb < g.tz) {
+                const int pp = jb >= g.nz ? 1 : 0;
+                X[pp * g.PX + (jb - pp * g.nz) * g.RY + i] = acc[v];
+            }
+        }
+    }
+}
+
+__device__ inline void stage_matrix(float *dst, const float *__restrict__ src, int L2)
+{
+    for (int i = threadIdx.x; i < L2 * L2; i += blockDim.x) {
+        const int r = i / L2, c = i - r * L2;
+        dst[r * (L2 + 1) + c] = src[i];
+    }
+}
+
+__global__ void __launch_bounds__(256) k_tail_yz(YZArgs a)
+{
+    extern __shared__ float L[];
+    YZLds g;
+    g.ny = a.ny; g.nz = a.nz; g.RY = a.ny + 1; g.RZ = a.nz + 1;
+    g.PX = a.nz * g.RY; g.PT = a.ny * g.RZ; g.ty = 2 * a.ny; g.tz = 2 * a.nz;
+    const int kx = blockIdx.x, gout = blockIdx.y;
+    const int PL = 2 * (g.PX > g.PT ? g.PX : g.PT);   // one padded complex plane
+    float *IN = L;                                     // nin planes
+    float *W0 = IN + a.nin * PL, *W1 = W0 + PL;        // work planes
+    float *Wy = W1 + PL;                               // ty x (ty + 1)
+    float *Wz = Wy + g.ty * (g.ty + 1);                // tz x (tz + 1)
+    stage_matrix(Wy, a.wyf, g.ty);
+    stage_matrix(Wz, a.wzf, g.tz);
+    const long long P2 = 2 * a.PS;
+    for (int f = 0; f < a.nin; ++f)
+        for (long long i = threadIdx.x; i < P2; i += blockDim.x) {
+            const int p = i >= a.PS ? 1 : 0;
+            const int r = (int)(i - p * a.PS), z = r / a.ny, y = r - z * a.ny;
+            IN[f * PL + p * g.PX + z * g.RY + y] = a.in[f * a.FSTR + kx * P2 + i];
+        }
+    __syncthreads();
+    for (int f = 0; f < a.nin; ++f) {
+        yz_stage_y(g, Wy, IN + f * PL, W0);
+        __syncthreads();
+        yz_stage_z(g, Wz, W0, IN + f * PL);
+        __syncthreads();
+    }
+    if (a.mode == 0) {
+        // sine spectra of the odd kernels: S = -Im F[w] / N, layout [f][kx][kz][ky]
+        for (int f = 0; f < a.nin; ++f)
+            for (long long i = threadIdx.x; i < a.PS; i += blockDim.x) {
+                const int z = (int)(i / a.ny), y = (int)(i - (long long)z * a.ny);
+                a.out[f * a.Sp + kx * a.PS + i] = -IN[f * PL + g.PX + z * g.RY + y] * a.scale;
+            }
+        return;
+    }
+    // inverse matrices replace the forward ones
+    __syncthreads();
+    stage_matrix(Wy, a.wyi, g.ty);
+    stage_matrix(Wz, a.wzi, g.tz);
+    const int M = a.M, aa = gout / 3, d = gout % 3;
+    for (long long i = threadIdx.x; i < a.PS; i += blockDim.x) {
+        const int z = (int)(i / a.ny), y = (int)(i - (long long)z * a.ny);
+        const int o = z * g.RY + y;
+        float re = 0.f, im = 0.f;
+        for (int b = 0; b < M; ++b) {
+            const int lo = aa < b ? aa : b, hi = aa < b ? b : aa;
+            const int p = lo * M - (lo * (lo - 1)) / 2 + (hi - lo);
+            const float sv = a.S[(long long)(p * 3 + d) * a.Sp + kx * a.PS + i];
+            re -= sv * IN[b * PL + g.PX + o];
+            im += sv * IN[b * PL + o];
+        }
+        W1[o] = re;
+        W1[g.PX + o] = im;
+    }
+    __syncthreads();
+    yz_stage_y(g, Wy, W1, W0);
+    __syncthreads();
+    yz_stage_z(g, Wz, W0, W1);
+    __syncthreads();
+    for (long long i = threadIdx.x; i < P2; i += blockDim.x) {
+        const int p = i >= a.PS ? 1 : 0;
+        const int r = (int)(i - p * a.PS), z = r / a.ny, y = r - z * a.ny;
+        a.out[gout * a.FSTR + kx * P2 + i] = W1[p * g.PX + z * g.RY + y];
+    }
+}
+
+// LDS bytes of the fused kernel for nin input planes.
+size_t yz_lds_bytes(int ny, int nz, int nin)
+{
+    const size_t PX = (size_t)nz * (ny + 1), PT = (size_t)ny * (nz + 1);
+    const size_t PL = 2 * (PX > PT ? PX : PT);
+    return sizeof(float) * (PL * (nin + 2) + (size_t)(2 * ny) * (2 * ny + 1) + (size_t)(2 * nz) * (2 * nz + 1));
+}
+
+bool SpectralPlan::fused_fits(int ny, int nz, int M)
+{
+    return yz_lds_bytes(ny, nz, M > 1 ? M : 1) <= 150 * 1024;
 }
 
 // ------------------------------------------------------------------ plan
@@ -174,70 +318,62 @@ MatAddr dense(const float *base, long long ld)
 
 }  // namespace
 
-void SpectralPlan::forward_stages(const float *real_in, int nfields, float *s1, float *s2, hipStream_t st) const
+void SpectralPlan::x_forward(const float *real_in, int nfields, float *s1, hipStream_t st) const
 {
-    // x: rows (z, y) of each field; output columns (plane, kx)
+    // rows (z, y) of each field; output columns (plane, kx) into [f][kx][p][z][y]
     GemmDesc gx{};
     gx.M = nz * ny; gx.N = 2 * nkx; gx.K = nx; gx.batch = nfields;
-    gx.A = dense(real_in, nx); gx.A.t_div = 1 << 30; gx.A.s_tlo = (long long)nx * ny * nz;
+    gx.A = dense(real_in, nx); gx.A.s_tlo = (long long)nx * ny * nz;
     gx.B = dense(wxf, 2 * nkx);
-    gx.C = dense(s1, nkx); gx.C.s_tlo = 2 * Sp; gx.C.c_div = nkx; gx.C.s_chi = Sp; gx.C.s_clo = 1;
+    gx.C = dense(s1, 1); gx.C.s_tlo = 2 * Sp; gx.C.c_div = nkx; gx.C.s_chi = (long long)ny * nz;
+    gx.C.s_clo = 2LL * ny * nz;
     launch_gemm(gx, st);
-    // y: per field, rows (plane, ky), K (plane, y), columns (z, kx)
-    GemmDesc gy{};
-    gy.M = 2 * ny; gy.N = nz * nkx; gy.K = 2 * ny; gy.batch = nfields;
-    gy.A = dense(wyf, 2 * ny);
-    gy.B = dense(s1, 0); gy.B.s_tlo = 2 * Sp; gy.B.r_div = ny; gy.B.s_rhi = Sp; gy.B.s_rlo = nkx;
-    gy.B.c_div = nkx; gy.B.s_chi = Sz; gy.B.s_clo = 1;
-    gy.C = gy.B; gy.C.base = s2;
-    launch_gemm(gy, st);
-    // z: per field, rows (plane, kz), K (plane, z), columns (y, kx) contiguous
-    GemmDesc gz{};
-    gz.M = 2 * nz; gz.N = ny * nkx; gz.K = 2 * nz; gz.batch = nfields;
-    gz.A = dense(wzf, 2 * nz);
-    gz.B = dense(s2, 0); gz.B.s_tlo = 2 * Sp; gz.B.r_div = nz; gz.B.s_rhi = Sp; gz.B.s_rlo = Sz; gz.B.s_clo = 1;
-    gz.C = gz.B; gz.C.base = s1;
-    launch_gemm(gz, st);
 }
 
-void SpectralPlan::inverse_stages(float *s1, float *s2, int nfields, float *real_out, hipStream_t st) const
+void SpectralPlan::x_inverse(const float *s2, int nfields, float *real_out, hipStream_t st) const
 {
-    GemmDesc gz{};
-    gz.M = 2 * nz; gz.N = ny * nkx; gz.K = 2 * nz; gz.batch = nfields;
-    gz.A = dense(wzi, 2 * nz);
-    gz.B = dense(s2, 0); gz.B.s_tlo = 2 * Sp; gz.B.r_div = nz; gz.B.s_rhi = Sp; gz.B.s_rlo = Sz; gz.B.s_clo = 1;
-    gz.C = gz.B; gz.C.base = s1;
-    launch_gemm(gz, st);
-    GemmDesc gy{};
-    gy.M = 2 * ny; gy.N = nz * nkx; gy.K = 2 * ny; gy.batch = nfields;
-    gy.A = dense(wyi, 2 * ny);
-    gy.B = dense(s1, 0); gy.B.s_tlo = 2 * Sp; gy.B.r_div = ny; gy.B.s_rhi = Sp; gy.B.s_rlo = nkx;
-    gy.B.c_div = nkx; gy.B.s_chi = Sz; gy.B.s_clo = 1;
-    gy.C = gy.B; gy.C.base = s2;
-    launch_gemm(gy, st);
-    // x: complex-to-real; K (plane, kx)
     GemmDesc gx{};
     gx.M = nz * ny; gx.N = nx; gx.K = 2 * nkx; gx.batch = nfields;
-    gx.A = dense(s2, nkx); gx.A.s_tlo = 2 * Sp; gx.A.c_div = nkx; gx.A.s_chi = Sp; gx.A.s_clo = 1;
+    gx.A = dense(s2, 1); gx.A.s_tlo = 2 * Sp; gx.A.c_div = nkx; gx.A.s_chi = (long long)ny * nz;
+    gx.A.s_clo = 2LL * ny * nz;
     gx.B = dense(wxi, nx);
     gx.C = dense(real_out, nx); gx.C.s_tlo = (long long)nx * ny * nz;
     launch_gemm(gx, st);
 }
 
+void SpectralPlan::launch_yz(int mode, int nin, const float *in, float *out, hipStream_t st) const
+{
+    YZArgs a;
+    a.ny = ny; a.nz = nz; a.nkx = nkx; a.M = M; a.mode = mode; a.nin = nin;
+    a.PS = (long long)ny * nz; a.Sp = Sp; a.FSTR = 2 * Sp;
+    a.in = in; a.out = out; a.S = S;
+    a.scale = 1.0f / (float)((double)nx * ny * nz);
+    a.wyf = wyf; a.wyi = wyi; a.wzf = wzf; a.wzi = wzi;
+    const size_t lds = yz_lds_bytes(ny, nz, nin);
+    hipLaunchKernelGGL(k_tail_yz, dim3(nkx, mode == 0 ? 1 : 3 * M), dim3(256), lds, st, a);
+}
+
+bool SpectralPlan::prepare(int ny, int nz, int M)
+{
+    const size_t bytes = yz_lds_bytes(ny, nz, M > 1 ? M : 1);
+    return hipFuncSetAttribute((const void *)k_tail_yz, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
+           hipSuccess;
+}
+
 void SpectralPlan::build_spectrum(const float *placed, float *s1, float *s2, hipStream_t st) const
 {
+    (void)s2;
     const int nf = 3 * P;
-    forward_stages(placed, nf, s1, s2, st);
-    const float scale = 1.0f / (float)((double)nx * ny * nz);
-    hipLaunchKernelGGL(k_spec_extract, dim3((unsigned)((Sp + 255) / 256), nf), dim3(256), 0, st, s1, S, nf, Sp,
-                       scale);
+    x_forward(placed, nf, s1, st);
+    // one kernel field at a time keeps the LDS footprint at 3 planes
+    for (int f = 0; f < nf; ++f) launch_yz(0, 1, s1 + 2 * Sp * f, S + Sp * f, st);
 }
 
 void SpectralPlan::apply(const float *n, float *s1, float *s2, float *tail, hipStream_t st) const
 {
-    forward_stages(n, M, s1, s2, st);
-    hipLaunchKernelGGL(k_spec_mul, dim3((unsigned)((Sp + 255) / 256), 3 * M), dim3(256), 0, st, s1, S, s2, M, Sp);
-    inverse_stages(s1, s2, 3 * M, tail, st);
+    x_forward(n, M, s1, st);
+    launch_yz(1, M, s1, s2, st);
+    x_inverse(s2, 3 * M, tail, st);
 }
 
 }  // namespace mlb

@@ -18,18 +18,18 @@ int tile_count(int v, int nx, int ny, int nz)
     return ((nx + tx - 1) / tx) * ((ny + ty - 1) / ty) * ((nz + tz - 1) / tz);
 }
 
-size_t tile_lds_bytes_of(int v, int reach)
+size_t tile_lds_bytes_of(int v, int reach, int sh_max)
 {
     int tx, ty, tz;
     tile_dims(v, tx, ty, tz);
-    return tile_lds_bytes(tx, ty, tz, reach);
+    return tile_lds_bytes(tx, ty, tz, reach, sh_max);
 }
 
 namespace {
 template <int TX, int TY, int TZ>
-bool prepare_one(int reach)
+bool prepare_one(int reach, int sh_max)
 {
-    const size_t bytes = tile_lds_bytes(TX, TY, TZ, reach);
+    const size_t bytes = tile_lds_bytes(TX, TY, TZ, reach, sh_max);
     if (bytes > 160 * 1024) return false;
     if (hipFuncSetAttribute((const void *)k_gather1_tile<TX, TY, TZ>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)bytes) != hipSuccess)
@@ -39,15 +39,16 @@ bool prepare_one(int reach)
 }
 }  // namespace
 
-bool tile_prepare(int reach_max)
+bool tile_prepare(int reach_max, int sh_max)
 {
-    return prepare_one<16, 4, 4>(reach_max) && prepare_one<8, 8, 4>(reach_max) && prepare_one<32, 4, 2>(reach_max);
+    return prepare_one<16, 4, 4>(reach_max, sh_max) && prepare_one<8, 8, 4>(reach_max, sh_max) &&
+           prepare_one<32, 4, 2>(reach_max, sh_max);
 }
 
 void launch_gather1_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM, Tables<float> tb,
-                         int reach_max, hipStream_t st)
+                         int reach_max, int sh_max, hipStream_t st)
 {
-    const size_t lds = tile_lds_bytes_of(v, reach_max);
+    const size_t lds = tile_lds_bytes_of(v, reach_max, sh_max);
     const dim3 grid(nblk, maxM);
     if (v == 0) hipLaunchKernelGGL((k_gather1_tile<16, 4, 4>), grid, dim3(kBlock), lds, st, sys, map, tb);
     else if (v == 1) hipLaunchKernelGGL((k_gather1_tile<8, 8, 4>), grid, dim3(kBlock), lds, st, sys, map, tb);
@@ -55,9 +56,9 @@ void launch_gather1_tile(int v, const SysDesc<float> *sys, const int2 *map, int 
 }
 
 void launch_step2_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM, Tables<float> tb,
-                       int reach_max, int parity, int write_force_only, hipStream_t st)
+                       int reach_max, int sh_max, int parity, int write_force_only, hipStream_t st)
 {
-    const size_t lds = tile_lds_bytes_of(v, reach_max);
+    const size_t lds = tile_lds_bytes_of(v, reach_max, sh_max);
     const dim3 grid(nblk, maxM);
     if (v == 0)
         hipLaunchKernelGGL((k_step2_tile<16, 4, 4>), grid, dim3(kBlock), lds, st, sys, map, tb, parity, write_force_only);
