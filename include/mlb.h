@@ -181,8 +181,10 @@ mlb_status mlb_get_series(mlb_mixture h, double *t, double *v, int32_t capacity,
  * synchronises that stream and returns, per pass k < MLB_NPASS, the summed
  * milliseconds ms[k] and the number of launches launches[k] (HOST arrays),
  * then turns profiling off.  Pass order: moments, contact values, spectral
- * tail, first gather, second gather + collision + streaming. */
-#define MLB_NPASS 5
+ * tail, first gather, second gather + collision + streaming, closure
+ * network (with a closure attached; its steps time their collision and
+ * streaming under pass 4). */
+#define MLB_NPASS 6
 mlb_status mlb_profile_begin(mlb_mixture h);
 mlb_status mlb_profile_end(mlb_mixture h, double *ms, int32_t *launches, void *stream);
 const char *mlb_pass_name(int32_t k);
@@ -243,6 +245,81 @@ mlb_status mlb_batch_profile_begin(mlb_batch h);
 mlb_status mlb_batch_profile_end(mlb_batch h, double *ms, int32_t *launches, void *stream);
 int64_t mlb_batch_step_count(mlb_batch h);
 mlb_status mlb_batch_destroy(mlb_batch h);
+
+
+/* ------------------------------------------------------------------------
+ * Learned force closure.  A 3D convolutional network stands in for the
+ * evaluation of the force densities N_a = n_a Phi_a of a binary mixture
+ * (the field of Sec. 3, eq. (splitforce), with its Crank-Nicolson friction
+ * as used by the collision of eq. (evolution)): from the local densities
+ * and momentum densities it predicts both species' force fields, and a
+ * step with a closure attached needs only the moments, the network and
+ * the collision with streaming.
+ *
+ * Network: four 3x3x3 convolutions on the periodic lattice, channels
+ * 8 -> 32 -> 32 -> 32 -> 6, SiLU s(z) = z / (1 + exp(-z)) after the first
+ * three.  Input channels (n_0 / n_ref - 1, n_1 / n_ref - 1, j_0 / j_ref,
+ * j_1 / j_ref) (j_a: x, y, z), output channels N_a,d / f_ref at index
+ * 3a + d.  Weights are bfloat16 with float32 accumulation on the matrix
+ * cores; Adam keeps float32 master weights.
+ *
+ * Parameters (mlb_net_param_count() floats) travel as HOST float32 arrays,
+ * layer by layer: W[co][ci][kz][ky][kx] (kz, ky, kx = offset + 1; the
+ * layer computes y[co](r) = b[co] + sum W[co][ci][d + 1] x[ci](r + d) with
+ * periodic wrap), then b[co].
+ *
+ * A network object is bound to one grid (nx, ny, nz); its workspace
+ * (device memory, owned by the caller) holds parameters, Adam moments and
+ * activation buffers, plus gradient buffers if `training` is 1.
+ * ---------------------------------------------------------------------- */
+typedef struct mlb_net_s *mlb_net;
+
+size_t mlb_net_param_count(void);
+/* Workspace bytes for a network on an nx x ny x nz grid; 0 if invalid. */
+size_t mlb_net_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t training);
+/* Create with all parameters zero (asynchronous on `stream`). */
+mlb_status mlb_net_create(int32_t nx, int32_t ny, int32_t nz, int32_t training, void *workspace,
+                          size_t workspace_bytes, void *stream, mlb_net *out);
+/* Load / read all parameters (HOST arrays, layout above).  Loading resets
+ * the Adam moments and step count.  Both synchronise `stream`. */
+mlb_status mlb_net_set_params(mlb_net net, const float *params, void *stream);
+mlb_status mlb_net_get_params(mlb_net net, float *params, void *stream);
+/* Input and output scales n_ref, j_ref, f_ref (all > 0; default 1). */
+mlb_status mlb_net_set_scales(mlb_net net, double n_ref, double j_ref, double f_ref);
+/* y [6][N] = network(x [8][N]); DEVICE float32, channel-first, x fastest. */
+mlb_status mlb_net_forward(mlb_net net, const float *x, float *y, void *stream);
+/* One training step on the mean squared error over all N x 6 outputs:
+ * forward, backward, and (update != 0) one Adam step with rate lr,
+ * b1 = 0.9, b2 = 0.999, eps = 1e-8.  x [8][N] and target [6][N] are DEVICE
+ * float32.  loss (HOST, may be NULL) receives the loss before the update;
+ * grads (HOST, may be NULL, mlb_net_param_count() floats, parameter
+ * layout) the gradients.  Asking for either synchronises.  Needs
+ * training buffers (MLB_ESTATE otherwise). */
+mlb_status mlb_net_train_step(mlb_net net, const float *x, const float *target, float lr, int32_t update,
+                              double *loss, float *grads, void *stream);
+/* Adam steps taken since the last mlb_net_set_params. */
+int32_t mlb_net_adam_steps(mlb_net net);
+mlb_status mlb_net_destroy(mlb_net net);
+
+/* Attach a closure network to a float32 binary periodic mixture (the net's
+ * grid must equal the mixture's; net = NULL detaches).  From then on every
+ * step takes its force from the network, except steps whose index (the
+ * mlb_step_count before the step) is a multiple of check_every: those
+ * evaluate the exact force, use it, and compare it with the network's,
+ * err = ||N_net - N_exact||_2 / ||N_exact||_2 over all sites, species and
+ * components (float64 sums; synchronises the stream).  If err > tol the
+ * closure switches off for good and the exact force is used from then on.
+ * The handle keeps the network; the caller keeps it alive while attached. */
+mlb_status mlb_set_closure(mlb_mixture h, mlb_net net, int32_t check_every, double tol);
+/* checks made, step index of the fallback (-1 if none), error of the last
+ * check (-1 before the first), whether the closure is still in use. */
+mlb_status mlb_closure_stats(mlb_mixture h, int64_t *checks, int64_t *fallback_step, double *last_err,
+                             int32_t *active);
+/* A training pair from the current state (populations are not changed):
+ * x_out [8][N] the network input with `net`'s scales and target_out [6][N]
+ * the exact force divided by f_ref; DEVICE float32.  Needs a float32
+ * binary mixture on `net`'s grid. */
+mlb_status mlb_closure_sample(mlb_mixture h, mlb_net net, float *x_out, float *target_out, void *stream);
 
 #ifdef __cplusplus
 }

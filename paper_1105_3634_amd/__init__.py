@@ -208,6 +208,28 @@ class GpuMixture:
         n = cnt.value
         return np.array(t[:n]), np.array(v[:n])
 
+    # ------------------------------------------------------- learned closure
+    def set_closure(self, net: Optional["GpuNet"], check_every: int = 50, tol: float = 1e-2) -> None:
+        _lib.check(self.lib.mlb_set_closure(self.h, net.h if net is not None else None, int(check_every), float(tol)),
+                   "mlb_set_closure")
+        self._net = net
+
+    def closure_stats(self) -> Dict[str, object]:
+        checks, fb, err, act = C.c_int64(), C.c_int64(), C.c_double(), C.c_int32()
+        _lib.check(self.lib.mlb_closure_stats(self.h, C.byref(checks), C.byref(fb), C.byref(err), C.byref(act)),
+                   "mlb_closure_stats")
+        return {"checks": int(checks.value), "fallback_step": int(fb.value), "last_err": float(err.value),
+                "active": bool(act.value)}
+
+    def closure_sample(self, net: "GpuNet"):
+        """(x [8][...], target [6][...]) float32 device tensors for the current state."""
+        torch = _torch()
+        x = torch.empty((8,) + self.shape, dtype=torch.float32, device=self.device)
+        t = torch.empty((6,) + self.shape, dtype=torch.float32, device=self.device)
+        _lib.check(self.lib.mlb_closure_sample(self.h, net.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
+                                               _stream_handle(self.stream)), "mlb_closure_sample")
+        return x, t
+
 
 class GpuBatch:
     """An ensemble of independent mixtures advanced by shared launches."""
@@ -303,3 +325,116 @@ class GpuBatch:
         _lib.check(self.lib.mlb_batch_profile_end(self.h, ms, cnt, _stream_handle(self.stream)),
                    "mlb_batch_profile_end")
         return {self.lib.mlb_pass_name(k).decode(): (ms[k], cnt[k]) for k in range(_lib.NPASS)}
+
+
+NET_CHANNELS = (8, 32, 32, 32, 6)
+
+
+def net_flatten(layers) -> np.ndarray:
+    """Parameters as a list of {"W": [Co][Ci][3][3][3], "b": [Co]} -> the flat
+    float32 layout of mlb_net_set_params."""
+    parts = []
+    for L in layers:
+        parts.append(np.asarray(L["W"], dtype=np.float32).reshape(-1))
+        parts.append(np.asarray(L["b"], dtype=np.float32).reshape(-1))
+    return np.ascontiguousarray(np.concatenate(parts))
+
+
+def net_unflatten(flat: np.ndarray, channels=NET_CHANNELS):
+    out, k = [], 0
+    for ci, co in zip(channels[:-1], channels[1:]):
+        nw = co * ci * 27
+        out.append({"W": flat[k:k + nw].reshape(co, ci, 3, 3, 3).copy(), "b": flat[k + nw:k + nw + co].copy()})
+        k += nw + co
+    return out
+
+
+class GpuNet:
+    """The force-closure network on one grid (nz, ny, nx)."""
+
+    def __init__(self, shape, training: bool = False, device: str = "cuda:0", stream=None):
+        torch = _torch()
+        self.lib = _lib.load()
+        self.shape = tuple(int(v) for v in shape)
+        nz, ny, nx = self.shape
+        self.N = nx * ny * nz
+        self.device = torch.device(device)
+        self.stream = stream
+        self.nparams = int(self.lib.mlb_net_param_count())
+        nbytes = int(self.lib.mlb_net_workspace_bytes(nx, ny, nz, 1 if training else 0))
+        if nbytes == 0:
+            raise MlbError(-1, "mlb_net_workspace_bytes", self.lib.mlb_last_error().decode())
+        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self._ws_raw = raw
+        self.ws = raw[off:off + nbytes]
+        h = C.c_void_p()
+        _lib.check(self.lib.mlb_net_create(nx, ny, nz, 1 if training else 0, C.c_void_p(self.ws.data_ptr()), nbytes,
+                                           _stream_handle(stream), C.byref(h)), "mlb_net_create")
+        self.h = h
+
+    def close(self) -> None:
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.mlb_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params) -> None:
+        flat = params if isinstance(params, np.ndarray) else net_flatten(params)
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        assert flat.size == self.nparams
+        _lib.check(self.lib.mlb_net_set_params(self.h, flat.ctypes.data_as(C.POINTER(C.c_float)),
+                                               _stream_handle(self.stream)), "mlb_net_set_params")
+
+    def get_params(self, flat: bool = False):
+        out = np.empty(self.nparams, dtype=np.float32)
+        _lib.check(self.lib.mlb_net_get_params(self.h, out.ctypes.data_as(C.POINTER(C.c_float)),
+                                               _stream_handle(self.stream)), "mlb_net_get_params")
+        return out if flat else net_unflatten(out)
+
+    def set_scales(self, n_ref: float, j_ref: float, f_ref: float) -> None:
+        _lib.check(self.lib.mlb_net_set_scales(self.h, float(n_ref), float(j_ref), float(f_ref)),
+                   "mlb_net_set_scales")
+        self.scales = (float(n_ref), float(j_ref), float(f_ref))
+
+    def _dev(self, x, channels):
+        torch = _torch()
+        x = torch.as_tensor(x).to(device=self.device, dtype=torch.float32).contiguous()
+        assert x.numel() == channels * self.N
+        return x
+
+    def forward(self, x):
+        """x [8][nz][ny][nx] -> y [6][nz][ny][nx] (float32 device tensors)."""
+        torch = _torch()
+        x = self._dev(x, 8)
+        y = torch.empty((6,) + self.shape, dtype=torch.float32, device=self.device)
+        _lib.check(self.lib.mlb_net_forward(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                            _stream_handle(self.stream)), "mlb_net_forward")
+        return y
+
+    def train_step(self, x, target, lr: float = 1e-3, update: bool = True, want_loss: bool = True,
+                   want_grads: bool = False):
+        """One Adam step on the MSE; returns (loss before the update or None, gradients or None)."""
+        x = self._dev(x, 8)
+        t = self._dev(target, 6)
+        loss = C.c_double()
+        grads = np.empty(self.nparams, dtype=np.float32) if want_grads else None
+        _lib.check(self.lib.mlb_net_train_step(
+            self.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()), float(lr), 1 if update else 0,
+            C.byref(loss) if want_loss else None,
+            grads.ctypes.data_as(C.POINTER(C.c_float)) if want_grads else None,
+            _stream_handle(self.stream)), "mlb_net_train_step")
+        self._keep = (x, t)
+        return (float(loss.value) if want_loss else None), (net_unflatten(grads) if want_grads else None)
+
+    @property
+    def adam_steps(self) -> int:
+        return int(self.lib.mlb_net_adam_steps(self.h))
+
+
+__all__ += ["GpuNet", "net_flatten", "net_unflatten", "NET_CHANNELS"]

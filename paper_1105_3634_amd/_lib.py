@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libmlb.so")
 
 MAX_SPECIES = 4
 Q = 19
-NPASS = 5
+NPASS = 6
 
 MLB_OK = 0
 STATUS = {0: "MLB_OK", -1: "MLB_EINVAL", -2: "MLB_ENOMEM", -3: "MLB_EHIP", -5: "MLB_ENONFINITE",
@@ -88,6 +88,22 @@ _SIGS = [
     ("mlb_batch_profile_end", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_void_p]),
     ("mlb_batch_step_count", C.c_int64, [C.c_void_p]),
     ("mlb_batch_destroy", C.c_int, [C.c_void_p]),
+    ("mlb_net_param_count", C.c_size_t, []),
+    ("mlb_net_workspace_bytes", C.c_size_t, [C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    ("mlb_net_create", C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
+                                 C.POINTER(C.c_void_p)]),
+    ("mlb_net_set_params", C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.c_void_p]),
+    ("mlb_net_get_params", C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.c_void_p]),
+    ("mlb_net_set_scales", C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double]),
+    ("mlb_net_forward", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("mlb_net_train_step", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_float, C.c_int32,
+                                     C.POINTER(C.c_double), C.POINTER(C.c_float), C.c_void_p]),
+    ("mlb_net_adam_steps", C.c_int32, [C.c_void_p]),
+    ("mlb_net_destroy", C.c_int, [C.c_void_p]),
+    ("mlb_set_closure", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_double]),
+    ("mlb_closure_stats", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    ("mlb_closure_sample", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
 ]
 OPT_TUNE, OPT_NO_GRAPH = 1, 2
 

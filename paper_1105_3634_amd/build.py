@@ -29,6 +29,8 @@ UNITS = [
     ("step_f32.hip", ["-ffp-contract=fast"]),
     ("reduce.hip", ["-ffp-contract=off"]),
     ("spectral.hip", ["-ffp-contract=fast"]),
+    ("cnn.hip", ["-ffp-contract=fast"]),
+    ("closure.cpp", ["-ffp-contract=off", "-x", "hip"]),
     ("tables.cpp", ["-ffp-contract=off", "-x", "hip"]),
     ("api.cpp", ["-ffp-contract=off", "-x", "hip"]),
 ]

@@ -20,7 +20,9 @@
 #include <vector>
 
 #include "../../include/mlb.h"
+#include "cnn.h"
 #include "mlb_internal.h"
+#include "net_internal.h"
 #include "spectral.h"
 
 namespace {
@@ -186,10 +188,14 @@ struct Tuning {
 std::mutex g_tune_mu;
 std::map<std::string, Tuning> g_tune_cache;
 
-enum { kPassMoments = 0, kPassContact = 1, kPassTail = 2, kPassGather1 = 3, kPassStep2 = 4 };
-const char *kPassNames[MLB_NPASS] = {"moments", "contact", "tail", "gather1", "step2"};
+enum { kPassMoments = 0, kPassContact = 1, kPassTail = 2, kPassGather1 = 3, kPassStep2 = 4, kPassClosure = 5 };
+const char *kPassNames[MLB_NPASS] = {"moments", "contact", "tail", "gather1", "step2", "closure"};
 
 }  // namespace
+
+namespace mlb {
+mlb_status set_error(mlb_status st, const std::string &msg) { return fail(st, msg); }
+}  // namespace mlb
 
 // ---------------------------------------------------------------- the core
 struct mlb_batch_s {
@@ -218,10 +224,19 @@ struct mlb_batch_s {
     bool use_graph = true;
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph = nullptr;
+    // learned closure (single float32 binary system)
+    mlb_net_s *net = nullptr;
+    bool closure_active = false;
+    int check_every = 50;
+    double closure_tol = 1e-2;
+    int64_t closure_checks = 0, fallback_step = -1;
+    double last_err = -1.0;
+    hipGraphExec_t graph_closure = nullptr;
 
     virtual ~mlb_batch_s()
     {
         if (graph) (void)hipGraphExecDestroy(graph);
+        if (graph_closure) (void)hipGraphExecDestroy(graph_closure);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
     }
@@ -628,25 +643,108 @@ void step_once(Batch &B, hipStream_t st)
     B.steps += 1;
 }
 
-mlb_status build_graph(Batch &B)
+// A step with the closure's force: moments, network, collision + streaming.
+// With `check` the exact force is evaluated as well and used instead, and
+// the squared-error partials of the network's force land in the net.
+void closure_step(Batch &B, hipStream_t st, bool check)
+{
+    using T = float;
+    const mlb::SysDesc<T> *sys = B.ddesc<T>(0);
+    const int2 *smap = B.map_of(B.map_site);
+    SysHost &S = B.sys[0];
+    const int par = B.parity;
+    T *n = reinterpret_cast<T *>(B.ws + S.n), *j = reinterpret_cast<T *>(B.ws + S.j);
+    T *Nf = reinterpret_cast<T *>(B.ws + S.Nf);
+    if (!check) {
+        pass(B, kPassMoments, st, [&] { mlb::Launch<T>::moments(sys, smap, B.nblk_site, par, st); });
+        pass(B, kPassClosure, st, [&] { mlb::net_infer_fields(B.net, n, j, Nf, st); });
+    } else {
+        run_passes<T>(B, st, false, 0, 1);   // exact force into Nf, populations untouched
+        T *Nc = mlb::net_check_buffer(B.net);
+        pass(B, kPassClosure, st, [&] { mlb::net_infer_fields(B.net, n, j, Nc, st); });
+        int nparts = 0;
+        double *part = mlb::net_err_buffer(B.net, &nparts);
+        mlb::cnn_err_partial(3 * S.M * S.N, Nc, Nf, part, nparts, st);
+    }
+    pass(B, kPassStep2, st, [&] { mlb::Launch<T>::collide(sys, smap, B.nblk_site, B.maxM, par, st); });
+    B.parity ^= 1;
+    B.steps += 1;
+}
+
+mlb_status capture_pair(Batch &B, hipGraphExec_t *out, void (*one)(Batch &, hipStream_t))
 {
     if (!B.cap_stream) HIP_TRY(hipStreamCreateWithFlags(&B.cap_stream, hipStreamNonBlocking));
     const int par0 = B.parity;
     const int64_t steps0 = B.steps;
     B.parity = 0;
     HIP_TRY(hipStreamBeginCapture(B.cap_stream, hipStreamCaptureModeRelaxed));
-    step_once(B, B.cap_stream);
-    step_once(B, B.cap_stream);
+    one(B, B.cap_stream);
+    one(B, B.cap_stream);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(B.cap_stream, &g);
     B.parity = par0;
     B.steps = steps0;
     if (e != hipSuccess) return fail(MLB_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&B.graph, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-        B.graph = nullptr;
+        *out = nullptr;
         return fail(MLB_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    return MLB_OK;
+}
+
+void plain_step(Batch &B, hipStream_t st) { step_once(B, st); }
+void net_step(Batch &B, hipStream_t st) { closure_step(B, st, false); }
+
+// `nsteps` steps of one kind: pairs replay the captured graph of that kind
+// (which starts at parity 0), the rest launch eagerly.
+mlb_status run_steps(Batch &B, int nsteps, hipStream_t st, bool with_net)
+{
+    hipGraphExec_t &graph = with_net ? B.graph_closure : B.graph;
+    void (*one)(Batch &, hipStream_t) = with_net ? net_step : plain_step;
+    int left = nsteps;
+    if (B.use_graph && !B.profiling && left >= 2) {
+        if (B.parity == 1) {
+            one(B, st);
+            --left;
+        }
+        if (left >= 2) {
+            if (!graph) TRY(capture_pair(B, &graph, one));
+            while (left >= 2) {
+                HIP_TRY(hipGraphLaunch(graph, st));
+                B.steps += 2;
+                left -= 2;
+            }
+        }
+    }
+    while (left-- > 0) one(B, st);
+    HIP_TRY(hipGetLastError());
+    return MLB_OK;
+}
+
+// exact-force check step; switches the closure off when the error is above tolerance
+mlb_status check_closure(Batch &B, hipStream_t st)
+{
+    const int64_t at_step = B.steps;
+    closure_step(B, st, true);
+    HIP_TRY(hipGetLastError());
+    int nparts = 0;
+    const double *part = mlb::net_err_buffer(B.net, &nparts);
+    std::vector<double> h(2 * (size_t)nparts);
+    HIP_TRY(hipMemcpyAsync(h.data(), part, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    double e = 0.0, w = 0.0;
+    for (int k = 0; k < nparts; ++k) {
+        e += h[2 * k];
+        w += h[2 * k + 1];
+    }
+    const double err = w > 0.0 ? std::sqrt(e / w) : (e > 0.0 ? INFINITY : 0.0);
+    B.last_err = err;
+    B.closure_checks += 1;
+    if (!(err <= B.closure_tol)) {
+        B.closure_active = false;
+        B.fallback_step = at_step;
     }
     return MLB_OK;
 }
@@ -655,23 +753,18 @@ mlb_status do_steps(Batch &B, int nsteps, hipStream_t st)
 {
     if (nsteps < 0) return fail(MLB_EINVAL, "nsteps must be >= 0");
     int left = nsteps;
-    if (B.use_graph && !B.profiling && left >= 2) {
-        if (B.parity == 1) {
-            step_once(B, st);
+    while (left > 0 && B.net && B.closure_active) {
+        const int64_t phase = B.steps % B.check_every;
+        if (phase == 0) {
+            TRY(check_closure(B, st));
             --left;
+            continue;
         }
-        if (left >= 2) {
-            if (!B.graph) TRY(build_graph(B));
-            while (left >= 2) {
-                HIP_TRY(hipGraphLaunch(B.graph, st));
-                B.steps += 2;
-                left -= 2;
-            }
-        }
+        const int run = (int)std::min<int64_t>(left, B.check_every - phase);
+        TRY(run_steps(B, run, st, true));
+        left -= run;
     }
-    while (left-- > 0) step_once(B, st);
-    HIP_TRY(hipGetLastError());
-    return MLB_OK;
+    return run_steps(B, left, st, false);
 }
 
 template <typename T>
@@ -849,8 +942,8 @@ mlb_status profile_end(Batch &B, double *ms, int32_t *launches, hipStream_t st)
 {
     if (!B.profiling) return fail(MLB_ESTATE, "profiling was not started");
     HIP_TRY(hipStreamSynchronize(st));
-    double acc[MLB_NPASS] = {0, 0, 0, 0, 0};
-    int cnt[MLB_NPASS] = {0, 0, 0, 0, 0};
+    double acc[MLB_NPASS] = {};
+    int cnt[MLB_NPASS] = {};
     for (auto &m : B.marks) {
         float t = 0.f;
         HIP_TRY(hipEventElapsedTime(&t, B.events[m.second], B.events[m.second + 1]));
@@ -1072,6 +1165,66 @@ mlb_status mlb_destroy(mlb_mixture h)
 }
 
 const char *mlb_last_error(void) { return g_err.c_str(); }
+
+mlb_status mlb_set_closure(mlb_mixture h, mlb_net net, int32_t check_every, double tol)
+{
+    if (!h) return fail(MLB_EINVAL, "null handle");
+    Batch &B = *h;
+    if (B.graph_closure) {
+        (void)hipGraphExecDestroy(B.graph_closure);
+        B.graph_closure = nullptr;
+    }
+    if (!net) {
+        B.net = nullptr;
+        B.closure_active = false;
+        return MLB_OK;
+    }
+    const SysHost &S = B.sys[0];
+    if (B.count != 1 || B.prec != 32 || S.M != 2 || S.p.walls_y)
+        return fail(MLB_EUNSUPPORTED, "the closure needs a float32 binary periodic mixture");
+    int nx = 0, ny = 0, nz = 0;
+    mlb::net_grid(net, &nx, &ny, &nz);
+    if (nx != S.p.nx || ny != S.p.ny || nz != S.p.nz) return fail(MLB_EINVAL, "network grid differs from the mixture's");
+    if (check_every < 1) return fail(MLB_EINVAL, "check_every must be >= 1");
+    if (!(tol >= 0.0)) return fail(MLB_EINVAL, "tol must be >= 0");
+    B.net = net;
+    B.check_every = check_every;
+    B.closure_tol = tol;
+    B.closure_active = true;
+    B.closure_checks = 0;
+    B.fallback_step = -1;
+    B.last_err = -1.0;
+    return MLB_OK;
+}
+
+mlb_status mlb_closure_stats(mlb_mixture h, int64_t *checks, int64_t *fallback_step, double *last_err,
+                             int32_t *active)
+{
+    if (!h) return fail(MLB_EINVAL, "null handle");
+    if (checks) *checks = h->closure_checks;
+    if (fallback_step) *fallback_step = h->fallback_step;
+    if (last_err) *last_err = h->last_err;
+    if (active) *active = (h->net && h->closure_active) ? 1 : 0;
+    return MLB_OK;
+}
+
+mlb_status mlb_closure_sample(mlb_mixture h, mlb_net net, float *x_out, float *target_out, void *stream)
+{
+    if (!h || !net) return fail(MLB_EINVAL, "null handle");
+    if (!x_out || !target_out) return fail(MLB_EINVAL, "x_out and target_out must be device pointers");
+    Batch &B = *h;
+    const SysHost &S = B.sys[0];
+    if (B.count != 1 || B.prec != 32 || S.M != 2) return fail(MLB_EUNSUPPORTED, "needs a float32 binary mixture");
+    int nx = 0, ny = 0, nz = 0;
+    mlb::net_grid(net, &nx, &ny, &nz);
+    if (nx != S.p.nx || ny != S.p.ny || nz != S.p.nz) return fail(MLB_EINVAL, "network grid differs from the mixture's");
+    hipStream_t st = S_(stream);
+    run_passes<float>(B, st, false, 0, 1);
+    mlb::net_sample(net, reinterpret_cast<const float *>(B.ws + S.n), reinterpret_cast<const float *>(B.ws + S.j),
+                    reinterpret_cast<const float *>(B.ws + S.Nf), x_out, target_out, st);
+    HIP_TRY(hipGetLastError());
+    return MLB_OK;
+}
 
 // ------------------------------------------------------------------ batch
 size_t mlb_batch_workspace_bytes(const mlb_params *systems, int32_t count)

@@ -98,6 +98,8 @@ struct Launch {
                         hipStream_t st);
     static void step2(const SysDesc<T> *sys, const int2 *map, int nblk, int maxM, Tables<T> tb,
                       int parity, int write_force_only, hipStream_t st);
+    // collision + streaming with the given force S.Nf
+    static void collide(const SysDesc<T> *sys, const int2 *map, int nblk, int maxM, int parity, hipStream_t st);
     static void init_pop(const SysDesc<T> *sys, const int2 *map, int nblk, const double *n0,
                          const double *u0, hipStream_t st);
 };

@@ -1,0 +1,286 @@
+"""GPU parity of the learned force closure.
+
+The network (BF16 weights and activations, float32 accumulation on the
+matrix cores) against its float64 oracle (oracle/cnn.py), and the closure
+step (moments -> network -> collision + streaming, with exact-force checks
+and fallback) against the lattice oracle.
+
+Tolerances follow from the arithmetic.  bfloat16 keeps 8 significant bits,
+so one rounding moves a value by at most u = 2^-9 (relative).  The forward
+pass rounds the input and the weights once and three hidden activations
+once each; summed over four layers, the relative L2 error of the output is
+bounded by about 4 sqrt(2) u = 1.1e-2 and is typically near 2 sqrt(3) u.
+With input and weights pre-rounded on the oracle side only the three
+activation roundings remain: 3 u = 5.9e-3.  The backward pass adds one
+rounding of the gradient per layer (four more), hence 2.5e-2 per gradient
+tensor.  Adam runs in float32 on float32 master weights: agreement to a few
+float32 ulps of the weight plus a few ulps of the step.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import cnn
+
+pytestmark = pytest.mark.gpu
+
+U_BF16 = 2.0 ** -9
+
+
+def bf16(a):
+    """Round float values to bfloat16 (nearest even), returned as float64."""
+    a32 = np.ascontiguousarray(a, dtype=np.float32)
+    u = a32.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return (u.astype(np.uint32)).view(np.float32).astype(np.float64)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def mlb():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1105_3634_amd as m
+    return m
+
+
+def random_layers(seed, scale_b=0.1):
+    rng = np.random.default_rng(seed + 100)
+    layers = cnn.init_params(seed=seed)
+    for L in layers:
+        L["b"] = rng.normal(scale=scale_b, size=L["b"].shape)
+    return layers
+
+
+@pytest.mark.parametrize("shape", [(9, 10, 12), (4, 4, 4), (3, 5, 17)])
+def test_forward_matches_oracle(mlb, shape):
+    print(f"forward parity shape={shape}", flush=True)
+    layers = random_layers(7)
+    rng = np.random.default_rng(3)
+    x = rng.normal(scale=0.7, size=(8,) + shape)
+    net = mlb.GpuNet(shape)
+    net.set_params(layers)
+    y = net.forward(x).cpu().numpy().astype(np.float64)
+    y_ref, _ = cnn.forward(layers, x)
+    assert rel_l2(y, y_ref) < 4 * np.sqrt(2) * U_BF16
+    # with the input and weights rounded as the device rounds them
+    rounded = [{"W": bf16(L["W"]), "b": np.float32(L["b"]).astype(np.float64)} for L in layers]
+    y_r, _ = cnn.forward(rounded, bf16(x))
+    assert rel_l2(y, y_r) < 3 * U_BF16
+    assert np.max(np.abs(y - y_r)) < 8 * U_BF16 * np.max(np.abs(y_r))
+
+
+def test_parameter_roundtrip_and_zero_network(mlb):
+    shape = (4, 5, 6)
+    net = mlb.GpuNet(shape)
+    layers = random_layers(11)
+    flat = mlb.net_flatten(layers)
+    net.set_params(flat)
+    back = net.get_params(flat=True)
+    np.testing.assert_array_equal(back, flat)
+    zero = np.zeros_like(flat)
+    net.set_params(zero)
+    y = net.forward(np.random.default_rng(0).normal(size=(8,) + shape)).cpu().numpy()
+    assert np.all(y == 0.0)
+
+
+def test_gradients_match_oracle(mlb):
+    shape = (8, 9, 10)      # 720 sites: three 256-site blocks, the last ragged
+    print("gradient parity", flush=True)
+    layers = random_layers(5)
+    rng = np.random.default_rng(9)
+    x = rng.normal(scale=0.7, size=(8,) + shape)
+    t = rng.normal(scale=0.5, size=(6,) + shape)
+    net = mlb.GpuNet(shape, training=True)
+    net.set_params(layers)
+    loss, grads = net.train_step(x, t, update=False, want_grads=True)
+    y_ref, caches = cnn.forward(layers, x)
+    loss_ref, gy = cnn.mse(y_ref, t)
+    g_ref, _ = cnn.backward(layers, caches, gy)
+    assert abs(loss / loss_ref - 1.0) < 4 * np.sqrt(2) * U_BF16
+    for l in range(4):
+        for key in ("W", "b"):
+            e = rel_l2(grads[l][key], g_ref[l][key])
+            assert e < 2.5e-2, (l, key, e)
+    assert net.adam_steps == 0
+    np.testing.assert_array_equal(net.get_params(flat=True), mlb.net_flatten(layers))
+
+
+def test_adam_two_steps_match_oracle(mlb):
+    shape = (6, 6, 7)
+    layers = random_layers(2)
+    rng = np.random.default_rng(4)
+    x = rng.normal(scale=0.7, size=(8,) + shape)
+    t = rng.normal(scale=0.5, size=(6,) + shape)
+    net = mlb.GpuNet(shape, training=True)
+    net.set_params(layers)
+    p = mlb.net_flatten(layers).astype(np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    lr = 2e-3
+    for step in (1, 2):
+        _, g = net.train_step(x, t, lr=lr, want_grads=True)
+        cnn.adam_step(p, mlb.net_flatten(g).astype(np.float64), m, v, step, lr=lr)
+        got = net.get_params(flat=True).astype(np.float64)
+        np.testing.assert_allclose(got, p, rtol=4e-7, atol=4e-7 * lr * step)
+        p = got.copy()      # continue from the device's float32 weights
+    assert net.adam_steps == 2
+
+
+def test_training_reduces_loss(mlb):
+    """A few hundred Adam steps fit a fixed smooth target (the network can
+    represent a linear 3x3x3 stencil exactly)."""
+    shape = (8, 8, 8)
+    rng = np.random.default_rng(1)
+    x = rng.normal(scale=0.5, size=(8,) + shape)
+    Wt = rng.normal(scale=0.1, size=(6, 8, 3, 3, 3))
+    t = cnn.conv3d(x, Wt, np.zeros(6))
+    net = mlb.GpuNet(shape, training=True)
+    net.set_params(cnn.init_params(seed=0))
+    l0, _ = net.train_step(x, t, lr=2e-3)
+    for _ in range(300):
+        net.train_step(x, t, lr=2e-3, want_loss=False)
+    l1, _ = net.train_step(x, t, lr=2e-3)
+    assert l1 < 0.05 * l0, (l0, l1)
+
+
+# ------------------------------------------------------------ closure step
+def closure_case(nx=24, ny=12, nz=12):
+    return W.config_closure_physics(nx, ny, nz)
+
+
+def scales(n0):
+    n_ref = float(np.mean(n0))
+    return n_ref, 1e-3 * n_ref, 1e-4
+
+
+def test_closure_sample_matches_oracle(mlb, oracle_lib):
+    import oracle
+    mix, n0, u0 = closure_case()
+    o = oracle.Oracle(mix)
+    f = o.step(o.init(n0, u0), 3)
+    g = mlb.GpuMixture(mix, n0, u0, precision=32)
+    g.step(3)
+    net = mlb.GpuNet(mix.shape())
+    n_ref, j_ref, f_ref = scales(n0)
+    net.set_scales(n_ref, j_ref, f_ref)
+    x, t = g.closure_sample(net)
+    x, t = x.cpu().numpy(), t.cpu().numpy()
+    d = o.fields(f)
+    x_ref = np.concatenate([d["n"] / n_ref - 1.0, d["j"][0] / j_ref, d["j"][1] / j_ref])
+    t_ref = d["N"].reshape(6, *mix.shape()) / f_ref
+    assert np.max(np.abs(x - x_ref)) < 1e-5 * max(1.0, np.max(np.abs(x_ref)))
+    assert np.max(np.abs(t - t_ref)) < 1e-4 * np.max(np.abs(t_ref))
+    # sampling does not advance or change the state
+    assert g.steps == 3
+    np.testing.assert_allclose(g.moments()[0].cpu().numpy(), d["n"], rtol=1e-5)
+
+
+def test_closure_checks_every_step_follow_the_exact_path(mlb, oracle_lib):
+    """check_every = 1: every step takes the exact force; the trajectory is
+    the plain one (float32 bar) and no fallback happens with tol = inf."""
+    import oracle
+    mix, n0, u0 = closure_case()
+    g = mlb.GpuMixture(mix, n0, u0, precision=32)
+    net = mlb.GpuNet(mix.shape())
+    net.set_params(random_layers(1))
+    net.set_scales(*scales(n0))
+    g.set_closure(net, check_every=1, tol=float("inf"))
+    g.step(20)
+    st = g.closure_stats()
+    assert st["checks"] == 20 and st["active"] and st["fallback_step"] == -1 and st["last_err"] > 0
+    o = oracle.Oracle(mix)
+    f = o.step(o.init(n0, u0), 20)
+    n_ref = o.densities(f)
+    n = g.moments()[0].cpu().numpy()
+    assert np.max(np.abs(n - n_ref) / np.abs(n_ref)) < 1e-5
+
+
+def test_closure_falls_back_when_error_is_large(mlb, oracle_lib):
+    import oracle
+    mix, n0, u0 = closure_case()
+    g = mlb.GpuMixture(mix, n0, u0, precision=32)
+    net = mlb.GpuNet(mix.shape())
+    net.set_params(random_layers(3))          # untrained: far from the exact force
+    net.set_scales(*scales(n0))
+    g.set_closure(net, check_every=4, tol=1e-2)
+    g.step(13)
+    st = g.closure_stats()
+    assert st["checks"] == 1 and st["fallback_step"] == 0 and not st["active"] and st["last_err"] > 1e-2
+    o = oracle.Oracle(mix)
+    f = o.step(o.init(n0, u0), 13)
+    n_ref = o.densities(f)
+    n = g.moments()[0].cpu().numpy()
+    assert np.max(np.abs(n - n_ref) / np.abs(n_ref)) < 1e-5
+
+
+C19 = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1],
+                [1, 1, 0], [-1, -1, 0], [1, -1, 0], [-1, 1, 0], [1, 0, 1], [-1, 0, -1], [1, 0, -1],
+                [-1, 0, 1], [0, 1, 1], [0, -1, -1], [0, 1, -1], [0, -1, 1]])
+
+
+def test_closure_step_is_collision_with_network_force(mlb, oracle_lib):
+    """A step between checks: populations after it equal the oracle's
+    collision (eq. evolution) with the network's force at every site,
+    followed by streaming, from the same pre-step populations."""
+    import oracle
+    mix, n0, u0 = closure_case(16, 10, 10)
+    g = mlb.GpuMixture(mix, n0, u0, precision=32)
+    net = mlb.GpuNet(mix.shape())
+    net.set_params(random_layers(8, scale_b=0.02))
+    n_ref, j_ref, f_ref = scales(n0)
+    net.set_scales(n_ref, j_ref, f_ref)
+    g.set_closure(net, check_every=1000, tol=float("inf"))
+    g.step(1)                                   # step 0 is a check step (exact force)
+    f1 = g.populations().cpu().numpy().astype(np.float64)
+    x, _ = g.closure_sample(net)
+    Nnet = net.forward(x).cpu().numpy().astype(np.float64) * f_ref
+    g.step(1)
+    f2 = g.populations().cpu().numpy().astype(np.float64)
+    st = g.closure_stats()
+    assert st["checks"] == 1 and st["active"]
+    o = oracle.Oracle(mix)
+    d = o.fields(f1)
+    nz, ny, nx = mix.shape()
+    M = mix.M
+    Nnet = Nnet.reshape(M, 3, nz, ny, nx)
+    post = np.empty_like(f1)
+    for a in range(M):
+        for z in range(nz):
+            for y in range(ny):
+                for xx in range(nx):
+                    post[a, :, z, y, xx] = o.collide_site(f1[a, :, z, y, xx], d["n"][a, z, y, xx],
+                                                          d["j"][a, :, z, y, xx], d["u"][:, z, y, xx],
+                                                          Nnet[a, :, z, y, xx])
+    exp = np.empty_like(post)
+    for i in range(19):
+        exp[:, i] = np.roll(post[:, i], shift=(C19[i, 2], C19[i, 1], C19[i, 0]), axis=(1, 2, 3))
+    assert np.max(np.abs(f2 - exp)) < 2e-6 * np.max(np.abs(exp))
+
+
+def test_closure_graph_replays_match_eager(mlb):
+    """Closure steps replayed from the captured graph give the same
+    populations as eager launches, across check steps, with eager work
+    (samples, moments) between the calls."""
+    mix, n0, u0 = closure_case(16, 10, 10)
+    runs = []
+    for graph in (False, True):
+        g = mlb.GpuMixture(mix, n0, u0, precision=32)
+        g.set_graph(graph)
+        net = mlb.GpuNet(mix.shape())
+        net.set_params(random_layers(8, scale_b=0.02))
+        net.set_scales(*scales(n0))
+        g.set_closure(net, check_every=5, tol=float("inf"))
+        snaps = []
+        for k in range(4):
+            g.step(3)
+            g.closure_sample(net)
+            snaps.append(g.populations().cpu().numpy())
+        runs.append((snaps, g.closure_stats()))
+    for a, b in zip(runs[0][0], runs[1][0]):
+        np.testing.assert_array_equal(a, b)
+    assert runs[0][1] == runs[1][1] and runs[0][1]["checks"] == 3
