@@ -20,12 +20,15 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "species-site updates/s: plain vs batched/CNN-closure at fixed D12 error; HBM GB/s"
 FP32_PEAK_TFLOPS = 157.3       # MI355X vector FP32 (256 CU x 128 lanes x 2 flop x 2.4 GHz)
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0     # MI355X dense bf16 matrix
 
 
 def shell_size(s):
@@ -98,6 +101,148 @@ def d12_check(mlb, mix, n0, u0):
     return {"d12": D, "d12_oracle_fp64": ref["D12"], "rel_err": D / ref["D12"] - 1, "steps": 2000}
 
 
+def closure_leg(mlb, W, steps=5000, train_box=(192, 12, 12)):
+    """Learned force closure on the 192x64x64 binary workload at the
+    step-binary physics: train the network on snapshots of the plain solver
+    (a 192x12x12 box, composition modes and a composition step), then run
+    the plain step, the closure with exact-force checks every 50 steps
+    (fallback above 1e-2 relative error), and the closure without fallback;
+    D_12 from the mode decay of each, and the throughput of plain and
+    closure steps."""
+    import torch
+
+    from paper_1105_3634_amd.closure_train import init_params, train_closure
+
+    nx, ny, nz = train_box
+    n_tot = W.number_density(0.2, (0.5, 0.5), (2.0, 3.0))
+
+    def state(amp, wl, noise, seed):
+        def make():
+            m = W.Mixture(nx, ny, nz, sigma=(2.0, 3.0), tau=1.0, name="closure_train")
+            n0, u0 = W.mode_state(m, n_tot, 0.5, amp, noise=noise, seed=seed, wavelength=wl)
+            return m, n0, u0
+        return make
+
+    def step_state():
+        m = W.Mixture(nx, ny, nz, sigma=(2.0, 3.0), tau=1.0, name="closure_train")
+        n0, u0 = W.step_state(m, n_tot)
+        return m, n0, u0
+
+    specs = [(0.05, 192, 0.0), (0.02, 96, 0.0), (0.1, 192, 0.0), (0.03, 64, 0.0), (0.07, 128, 0.0),
+             (0.04, 192, 0.0), (0.01, 192, 0.0), (0.05, 96, 0.005), (0.05, 192, 0.01)]
+    states = [state(a, wl, nz_, 300 + i) for i, (a, wl, nz_) in enumerate(specs)] + [step_state]
+    tnet = mlb.GpuNet((nz, ny, nx), training=True)
+    tnet.set_params(init_params(0))
+    rep = train_closure(tnet, states, per_state=200, sample_every=5, epochs=10, lr=2e-3)
+    params = tnet.get_params(flat=True)
+    del tnet
+
+    mix, n0, u0 = W.config_closure_physics()
+    net = mlb.GpuNet(mix.shape())
+    net.set_params(params)
+    net.set_scales(*rep.scales)
+
+    def run(closure, tol):
+        g = mlb.GpuMixture(mix, n0, u0, precision=32, device="cuda:0")
+        if closure:
+            g.set_closure(net, check_every=50, tol=tol)
+        errs = []
+        for t in range(0, steps + 1, 10):
+            g.record_mode(0, 1)
+            if t < steps:
+                g.step(10)
+            if closure and t % 50 == 0:
+                errs.append(g.closure_stats()["last_err"])
+        D = g.fit(0, t_min=200)
+        out = {"d12": D}
+        if closure:
+            st = g.closure_stats()
+            out.update({"checks": st["checks"], "fallback_step": st["fallback_step"], "active_at_end": st["active"],
+                        "first_check_err": errs[0] if errs else None, "last_check_err": st["last_err"]})
+        return out
+
+    def rate(closure, k=200):
+        g = mlb.GpuMixture(mix, n0, u0, precision=32, device="cuda:0")
+        if closure:
+            g.set_closure(net, check_every=1 << 30, tol=float("inf"))
+        g.step(2)                                  # the step-0 check, graph capture
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(k)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        g.profile_begin()
+        g.step(20)
+        passes = g.profile_end()
+        return mix.M * mix.N * k / dt, {p: v[0] / 20 for p, v in passes.items() if v[1]}
+
+    plain = run(False, 0.0)
+    checked = run(True, 1e-2)
+    forced = run(True, float("inf"))
+    r_plain, p_plain = rate(False)
+    r_net, p_net = rate(True)
+    macs = 27 * (8 * 32 + 32 * 32 + 32 * 32 + 32 * 6)
+    net_ms = p_net.get("closure", 0.0)
+    tflops = 2.0 * macs * mix.N / (net_ms * 1e-3) / 1e12 if net_ms else None
+    return {
+        "workload": f"closure_{mix.nx}x{mix.ny}x{mix.nz}", "steps": steps,
+        "train": {"box": list(train_box), "snapshots": rep.samples, "adam_steps": rep.steps,
+                  "collect_s": rep.collect_seconds, "train_s": rep.train_seconds},
+        "plain": plain, "closure_checked": checked, "closure_no_fallback": forced,
+        "d12_rel_diff_no_fallback": forced["d12"] / plain["d12"] - 1.0,
+        "ssu_per_s": {"plain": r_plain, "closure": r_net, "speedup": r_net / r_plain},
+        "passes_ms_per_step": {"plain": p_plain, "closure": p_net},
+        "network_roofline": {"bound": "mfma", "achieved": tflops, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": tflops / BF16_PEAK_TFLOPS if tflops else None,
+                             "flop_per_site": 2 * macs, "avg_pass_ms": net_ms},
+    }
+
+
+def ensemble_leg(mlb, W, steps=1000, timed=200):
+    """Batched ensemble: 64 independent periodic binary systems (edges from
+    {32, 48, 64, 96}, x1, packing and sigma_22 drawn from a seed) advanced
+    by shared launches with the autotuned tile shape and the graph-captured
+    step loop; mode-decay D_12 of every system over `steps` steps, and the
+    throughput of `timed` plain steps."""
+    import torch
+
+    members = W.config_ensemble()
+    mixes = [m.mixture for m in members]
+    b = mlb.GpuBatch(mixes, [m.n0 for m in members], [m.u0 for m in members], precision=32,
+                     options=mlb.OPT_TUNE, device="cuda:0")
+    ssu_step = sum(len(m.sigma) * m.N for m in mixes)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(0, steps + 1, 10):
+        b.record_modes()
+        if t < steps:
+            b.step(10)
+    torch.cuda.synchronize()
+    run_s = time.perf_counter() - t0
+    D = b.fit(t_min=200)
+    b.step(4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(timed)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    b.profile_begin()
+    b.step(10)
+    passes = b.profile_end()
+    tune = b.tuning()
+    return {
+        "workload": f"ensemble_{len(mixes)}_systems", "systems": len(mixes),
+        "sites_total": int(sum(m.N for m in mixes)), "species_sites_per_step": int(ssu_step),
+        "ssu_per_s": ssu_step * timed / dt, "ms_per_step": dt * 1e3 / timed,
+        "run_with_mode_records": {"steps": steps, "seconds": run_s},
+        "d12": {"min": float(np.min(D)), "median": float(np.median(D)), "max": float(np.max(D)),
+                "finite": bool(np.all(np.isfinite(D)))},
+        "tuning": {"shape": mlb.GpuBatch.SHAPES[tune["shape"]], "order": ["linear", "xcd-chunked"][tune["order"]],
+                   "trial_ms": tune["trial_ms"]},
+        "passes_ms_per_step": {k: v[0] / 10 for k, v in passes.items() if v[1]},
+    }
+
+
 def cpu_baseline(mix, n0, u0, target_s=12.0):
     import oracle
     o = oracle.Oracle(mix)
@@ -122,6 +267,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tail", choices=["auto", "direct", "spectral"], default="auto")
     ap.add_argument("--no-d12", action="store_true", help="skip the 2000-step D_12 accuracy check")
+    ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
+    ap.add_argument("--closure-steps", type=int, default=5000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB elementwise copy (counter calibration for profiles)")
     args = ap.parse_args()
@@ -130,7 +278,6 @@ def main():
               "path is a design note, not a measured configuration", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1105_3634_amd as mlb
@@ -195,6 +342,16 @@ def main():
     acc = None if args.no_d12 else d12_check(mlb, mix, n0, u0)
     if acc is not None:
         line["d12"] = acc
+    if not args.no_ensemble:
+        try:
+            line["ensemble"] = ensemble_leg(mlb, W)
+        except Exception as exc:      # reported in the line; the headline stands on its own
+            line["ensemble"] = {"error": f"{type(exc).__name__}: {exc}"}
+    if not args.no_closure:
+        try:
+            line["closure"] = closure_leg(mlb, W, steps=args.closure_steps)
+        except Exception as exc:      # reported in the line; the headline stands on its own
+            line["closure"] = {"error": f"{type(exc).__name__}: {exc}"}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(mix, n0, u0)
     print(json.dumps(line), flush=True)

@@ -260,8 +260,11 @@ mlb_status mlb_batch_destroy(mlb_batch h);
  * 8 -> 32 -> 32 -> 32 -> 6, SiLU s(z) = z / (1 + exp(-z)) after the first
  * three.  Input channels (n_0 / n_ref - 1, n_1 / n_ref - 1, j_0 / j_ref,
  * j_1 / j_ref) (j_a: x, y, z), output channels N_a,d / f_ref at index
- * 3a + d.  Weights are bfloat16 with float32 accumulation on the matrix
- * cores; Adam keeps float32 master weights.
+ * 3a + d.  Weights and activations are bfloat16 with float32 accumulation
+ * on the matrix cores; the first layer carries inputs and weights as
+ * bfloat16 hi/lo pairs (about 16 significant bits), because the force is a
+ * small spatial derivative of its inputs.  Adam keeps float32 master
+ * weights.
  *
  * Parameters (mlb_net_param_count() floats) travel as HOST float32 arrays,
  * layer by layer: W[co][ci][kz][ky][kx] (kz, ky, kx = offset + 1; the
@@ -288,15 +291,17 @@ mlb_status mlb_net_get_params(mlb_net net, float *params, void *stream);
 mlb_status mlb_net_set_scales(mlb_net net, double n_ref, double j_ref, double f_ref);
 /* y [6][N] = network(x [8][N]); DEVICE float32, channel-first, x fastest. */
 mlb_status mlb_net_forward(mlb_net net, const float *x, float *y, void *stream);
-/* One training step on the mean squared error over all N x 6 outputs:
- * forward, backward, and (update != 0) one Adam step with rate lr,
- * b1 = 0.9, b2 = 0.999, eps = 1e-8.  x [8][N] and target [6][N] are DEVICE
- * float32.  loss (HOST, may be NULL) receives the loss before the update;
- * grads (HOST, may be NULL, mlb_net_param_count() floats, parameter
- * layout) the gradients.  Asking for either synchronises.  Needs
- * training buffers (MLB_ESTATE otherwise). */
-mlb_status mlb_net_train_step(mlb_net net, const float *x, const float *target, float lr, int32_t update,
-                              double *loss, float *grads, void *stream);
+/* One training step on loss_weight times the mean squared error over all
+ * N x 6 outputs: forward, backward, and (update != 0) one Adam step with
+ * rate lr, b1 = 0.9, b2 = 0.999, eps = 1e-8.  x [8][N] and target [6][N]
+ * are DEVICE float32; loss_weight > 0 (e.g. the reciprocal mean square of
+ * the target, for a relative error).  loss (HOST, may be NULL) receives the
+ * weighted loss before the update; grads (HOST, may be NULL,
+ * mlb_net_param_count() floats, parameter layout) the gradients.  Asking
+ * for either synchronises.  Needs training buffers (MLB_ESTATE
+ * otherwise). */
+mlb_status mlb_net_train_step(mlb_net net, const float *x, const float *target, float lr, float loss_weight,
+                              int32_t update, double *loss, float *grads, void *stream);
 /* Adam steps taken since the last mlb_net_set_params. */
 int32_t mlb_net_adam_steps(mlb_net net);
 mlb_status mlb_net_destroy(mlb_net net);
@@ -307,8 +312,9 @@ mlb_status mlb_net_destroy(mlb_net net);
  * mlb_step_count before the step) is a multiple of check_every: those
  * evaluate the exact force, use it, and compare it with the network's,
  * err = ||N_net - N_exact||_2 / ||N_exact||_2 over all sites, species and
- * components (float64 sums; synchronises the stream).  If err > tol the
- * closure switches off for good and the exact force is used from then on.
+ * components (float64 sums; synchronises the stream).  If err > tol, or
+ * err is not finite (NaN in either force), the closure switches off for
+ * good and the exact force is used from then on.
  * The handle keeps the network; the caller keeps it alive while attached. */
 mlb_status mlb_set_closure(mlb_mixture h, mlb_net net, int32_t check_every, double tol);
 /* checks made, step index of the fallback (-1 if none), error of the last

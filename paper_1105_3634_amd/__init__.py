@@ -418,14 +418,15 @@ class GpuNet:
         return y
 
     def train_step(self, x, target, lr: float = 1e-3, update: bool = True, want_loss: bool = True,
-                   want_grads: bool = False):
-        """One Adam step on the MSE; returns (loss before the update or None, gradients or None)."""
+                   want_grads: bool = False, loss_weight: float = 1.0):
+        """One Adam step on loss_weight x MSE; returns (loss before the update or None, gradients or None)."""
         x = self._dev(x, 8)
         t = self._dev(target, 6)
         loss = C.c_double()
         grads = np.empty(self.nparams, dtype=np.float32) if want_grads else None
         _lib.check(self.lib.mlb_net_train_step(
-            self.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()), float(lr), 1 if update else 0,
+            self.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()), float(lr), float(loss_weight),
+            1 if update else 0,
             C.byref(loss) if want_loss else None,
             grads.ctypes.data_as(C.POINTER(C.c_float)) if want_grads else None,
             _stream_handle(self.stream)), "mlb_net_train_step")

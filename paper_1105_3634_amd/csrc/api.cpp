@@ -739,7 +739,9 @@ mlb_status check_closure(Batch &B, hipStream_t st)
         e += h[2 * k];
         w += h[2 * k + 1];
     }
-    const double err = w > 0.0 ? std::sqrt(e / w) : (e > 0.0 ? INFINITY : 0.0);
+    // a non-finite sum (diverged state or network output) counts as a failed check
+    double err = NAN;
+    if (std::isfinite(e) && std::isfinite(w)) err = w > 0.0 ? std::sqrt(e / w) : (e > 0.0 ? INFINITY : 0.0);
     B.last_err = err;
     B.closure_checks += 1;
     if (!(err <= B.closure_tol)) {

@@ -68,7 +68,7 @@ bool plan(mlb_net_s &n, int nx, int ny, int nz, int training)
         L.b = take(4 * (size_t)L.cop); L.mb = take(4 * (size_t)L.cop); L.vb = take(4 * (size_t)L.cop);
     }
     const size_t N = (size_t)n.N;
-    n.x = take(2 * 16 * N);
+    n.x = take(2 * 32 * N);
     for (int l = 0; l < 3; ++l) n.a[l] = take(2 * 32 * N);
     n.y = take(4 * 16 * N);
     n.nc = take(4 * 6 * N);
@@ -210,7 +210,7 @@ mlb_status mlb_net_set_params(mlb_net n, const float *params, void *stream)
         HIP_TRY(hipMemsetAsync(n->ws + L.v, 0, 4 * (size_t)L.nw, st));
         HIP_TRY(hipMemsetAsync(n->ws + L.mb, 0, 4 * (size_t)L.cop, st));
         HIP_TRY(hipMemsetAsync(n->ws + L.vb, 0, 4 * (size_t)L.cop, st));
-        mlb::cnn_cast(L.nw, L.cop, L.cip, at<float>(*n, L.w), at<unsigned short>(*n, L.wb),
+        mlb::cnn_cast(L.nw, L.cop, L.cip, L.cin, mlb::net_split(l) ? 1 : 0, at<float>(*n, L.w), at<unsigned short>(*n, L.wb),
                       at<unsigned short>(*n, L.wt), st);
     }
     n->adam_t = 0;
@@ -265,19 +265,21 @@ mlb_status mlb_net_forward(mlb_net n, const float *x, float *y, void *stream)
     return MLB_OK;
 }
 
-mlb_status mlb_net_train_step(mlb_net n, const float *x, const float *target, float lr, int32_t update,
+mlb_status mlb_net_train_step(mlb_net n, const float *x, const float *target, float lr, float loss_weight, int32_t update,
                               double *loss, float *grads, void *stream)
 {
     if (mlb_status s = check_net(n)) return s;
     if (!n->training) return mlb::set_error(MLB_ESTATE, "network was created without training buffers");
     if (!x || !target) return mlb::set_error(MLB_EINVAL, "x and target must be device pointers");
     if (update && !(lr >= 0.f && std::isfinite(lr))) return mlb::set_error(MLB_EINVAL, "lr must be >= 0");
+    if (!(loss_weight > 0.f && std::isfinite(loss_weight)))
+        return mlb::set_error(MLB_EINVAL, "loss_weight must be positive and finite");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const mlb::CnnShape sh = shape_of(*n);
     mlb::cnn_pack_x(sh, x, at<unsigned short>(*n, n->x), st);
     mlb::cnn_pack_target(sh, target, 1.f, at<float>(*n, n->tg), st);
     forward(*n, true, st);
-    mlb::cnn_mse(sh, at<float>(*n, n->y), at<float>(*n, n->tg), at<unsigned short>(*n, n->g3),
+    mlb::cnn_mse(sh, loss_weight, at<float>(*n, n->y), at<float>(*n, n->tg), at<unsigned short>(*n, n->g3),
                  at<float>(*n, n->loss), st);
     // backward: gradient w.r.t. the pre-activation of layer l in gz
     const unsigned short *gz = at<unsigned short>(*n, n->g3);
@@ -295,7 +297,7 @@ mlb_status mlb_net_train_step(mlb_net n, const float *x, const float *target, fl
         n->adam_t += 1;
         for (int l = 0; l < mlb::kNetLayers; ++l) {
             const auto &L = n->L[l];
-            mlb::cnn_adam(L.nw, L.cop, L.cip, L.cout, L.cin, at<float>(*n, L.w), at<float>(*n, L.gw),
+            mlb::cnn_adam(L.nw, L.cop, L.cip, L.cout, L.cin, mlb::net_split(l) ? 1 : 0, at<float>(*n, L.w), at<float>(*n, L.gw),
                           at<float>(*n, L.m), at<float>(*n, L.v), lr, 0.9, 0.999, 1e-8, n->adam_t,
                           at<unsigned short>(*n, L.wb), at<unsigned short>(*n, L.wt), at<float>(*n, L.b),
                           at<float>(*n, L.gb), at<float>(*n, L.mb), at<float>(*n, L.vb), st);
@@ -320,7 +322,11 @@ mlb_status mlb_net_train_step(mlb_net n, const float *x, const float *target, fl
             HIP_TRY(hipStreamSynchronize(st));
             for (int co = 0; co < L.cout; ++co)
                 for (int ci = 0; ci < L.cin; ++ci)
-                    for (int t = 0; t < 27; ++t) *p++ = w[((size_t)t * L.cop + co) * L.cip + ci];
+                    for (int t = 0; t < 27; ++t) {
+                        const size_t k = ((size_t)t * L.cop + co) * L.cip + ci;
+                        // split layer: the weight's gradient is that of its x_hi and x_lo slots
+                        *p++ = mlb::net_split(l) ? w[k] + w[k + L.cin] : w[k];
+                    }
             for (int co = 0; co < L.cout; ++co) *p++ = b[co];
         }
     }

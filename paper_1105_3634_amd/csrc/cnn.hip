@@ -9,6 +9,15 @@
 // Layout: activations channel-last [site][C] (C padded to a multiple of
 // 16), weights [tap][C_out][C_in] in bfloat16, accumulation in float32 on
 // the matrix cores (v_mfma_f32_16x16x16bf16_1k: 16 x 16 x 16 per wave).
+//
+// The first layer runs in split bfloat16: every input value x is carried as
+// hi = bf16(x) and lo = bf16(x - hi), every weight w as hi and lo the same
+// way, and the 32 packed input channels [x_hi | x_lo | x_hi | 0] meet the
+// weight row [w_hi | w_hi | w_lo | 0], so one contraction gives
+// w_hi x_hi + w_hi x_lo + w_lo x_hi, about 16 significant bits.  The
+// force is a spatial derivative of fields whose local values it barely
+// changes; with 8-bit inputs or first-layer weights the rounding of the
+// undifferentiated part would swamp it.
 // Lane layout (one block): A[i][4g .. 4g+3] in lane i + 16g, B[4g .. 4g+3][j]
 // in lane j + 16g, D[4g + v][j] in lane j + 16g, element v.
 //
@@ -230,15 +239,16 @@ __global__ void k_sum_rows(const float *__restrict__ part, int nrows, int len, f
 
 // ------------------------------------------------------------- loss
 // y [s][COP] (float32 pre-activation of the last layer), target [s][NOUT];
-// g = 2 (y - t) / (N NOUT) as bf16 [s][COP]; loss partials per block.
-__global__ void k_mse(long long N, int COP, int NOUT, const float *__restrict__ y, const float *__restrict__ tg,
-                      unsigned short *__restrict__ gout, float *__restrict__ loss_part)
+// loss = wgt * mean (y - t)^2; g = wgt 2 (y - t) / (N NOUT) as bf16 [s][COP];
+// loss partials per block.
+__global__ void k_mse(long long N, int COP, int NOUT, float wgt, const float *__restrict__ y,
+                      const float *__restrict__ tg, unsigned short *__restrict__ gout, float *__restrict__ loss_part)
 {
     __shared__ float red[256];
     const long long s = (long long)blockIdx.x * 256 + threadIdx.x;
     float l = 0.f;
     if (s < N) {
-        const float inv = 2.f / ((float)N * (float)NOUT);
+        const float inv = wgt * 2.f / ((float)N * (float)NOUT);
         for (int c = 0; c < COP; ++c) {
             float gv = 0.f;
             if (c < NOUT) {
@@ -255,35 +265,52 @@ __global__ void k_mse(long long N, int COP, int NOUT, const float *__restrict__ 
         if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) loss_part[blockIdx.x] = wgt * red[0];
 }
 
 // ------------------------------------------------------------- Adam
 // master [t][co][ci] float32 (padded layout), grads same layout; refreshes
 // the bf16 copies W [t][co][ci] and WT [t][ci][co].  Padded entries stay 0.
+// split (first layer, CIP = 4 cin): master entries ci < cin; the gradient of
+// w is that of its x_hi and x_lo slots, and the bf16 row gets w_hi, w_hi,
+// w_lo, 0 in slots ci, ci + cin, ci + 2 cin, ci + 3 cin.
 struct AdamConst {
     float lr, b1, b2, omb1, omb2, c1, c2, eps;   // omb = 1 - b, c = 1 - b^t (formed in float64)
 };
 
-__global__ void k_adam(int n, int COP, int CIP, int cout, int cin, float *__restrict__ w, const float *__restrict__ gw,
-                       float *__restrict__ m, float *__restrict__ v, AdamConst k, unsigned short *__restrict__ wb,
-                       unsigned short *__restrict__ wt)
+__device__ inline void store_split(unsigned short *wb, int i, int cin, float w)
+{
+    const unsigned short hi = f2bf(w);
+    wb[i] = hi;
+    wb[i + cin] = hi;
+    wb[i + 2 * cin] = f2bf(w - bf2f(hi));
+    wb[i + 3 * cin] = 0;
+}
+
+__global__ void k_adam(int n, int COP, int CIP, int cout, int cin, int split, float *__restrict__ w,
+                       const float *__restrict__ gw, float *__restrict__ m, float *__restrict__ v, AdamConst k,
+                       unsigned short *__restrict__ wb, unsigned short *__restrict__ wt)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int t = i / (COP * CIP), r = i - t * COP * CIP, co = r / CIP, ci = r - co * CIP;
+    if (split && ci >= cin) return;                // written by the owner of slot ci % cin
     if (co >= cout || ci >= cin) {
         wb[i] = 0;
         wt[((long long)t * CIP + ci) * COP + co] = 0;
         return;
     }
-    const float gi = gw[i];
+    const float gi = split ? gw[i] + gw[i + cin] : gw[i];
     const float mi = k.b1 * m[i] + k.omb1 * gi;
     const float vi = k.b2 * v[i] + k.omb2 * gi * gi;
     m[i] = mi;
     v[i] = vi;
     const float wi = w[i] - k.lr * (mi / k.c1) / (sqrtf(vi / k.c2) + k.eps);
     w[i] = wi;
+    if (split) {
+        store_split(wb, i, cin, wi);
+        return;
+    }
     wb[i] = f2bf(wi);
     wt[((long long)t * CIP + ci) * COP + co] = f2bf(wi);
 }
@@ -301,40 +328,57 @@ __global__ void k_adam_bias(int n, float *__restrict__ b, const float *__restric
 }
 
 // refresh bf16 copies from float32 masters (after loading weights)
-__global__ void k_cast_weights(int n, int COP, int CIP, const float *__restrict__ w, unsigned short *__restrict__ wb,
-                               unsigned short *__restrict__ wt)
+__global__ void k_cast_weights(int n, int COP, int CIP, int cin, int split, const float *__restrict__ w,
+                               unsigned short *__restrict__ wb, unsigned short *__restrict__ wt)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int t = i / (COP * CIP), r = i - t * COP * CIP, co = r / CIP, ci = r - co * CIP;
+    if (split) {
+        if (ci < cin) store_split(wb, i, cin, w[i]);
+        return;
+    }
     wb[i] = f2bf(w[i]);
     wt[((long long)t * CIP + ci) * COP + co] = f2bf(w[i]);
 }
 
 // ---------------------------------------------------------- packing
-// x[s][0..15]: (n_0, n_1) / n_ref - 1, (j_0, j_1) / j_ref, zero padding.
+// split first-layer input of one site: x[0..31] = [hi(v) | lo(v) | hi(v) | 0]
+__device__ inline void store_input(unsigned short *__restrict__ x, const float v[8])
+{
+    for (int c = 0; c < 8; ++c) {
+        const unsigned short hi = f2bf(v[c]);
+        x[c] = hi;
+        x[8 + c] = f2bf(v[c] - bf2f(hi));
+        x[16 + c] = hi;
+        x[24 + c] = 0;
+    }
+}
+
+// network input of site s: (n_0, n_1) / n_ref - 1, (j_0, j_1) / j_ref
 __global__ void k_pack_input(long long N, const float *__restrict__ n, const float *__restrict__ j, float n_ref,
                              float j_ref, unsigned short *__restrict__ x)
 {
     const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= N) return;
-    float v[16];
+    float v[8];
     v[0] = n[s] / n_ref - 1.f;
     v[1] = n[N + s] / n_ref - 1.f;
     for (int d = 0; d < 3; ++d) {
         v[2 + d] = j[d * N + s] / j_ref;
         v[5 + d] = j[(3 + d) * N + s] / j_ref;
     }
-    for (int c = 8; c < 16; ++c) v[c] = 0.f;
-    for (int c = 0; c < 16; ++c) x[s * 16 + c] = f2bf(v[c]);
+    store_input(x + s * 32, v);
 }
 
-// x[s][c] = xf[c][s] for c < 8, zero padding to 16
+// input from channel-first float32 xf [8][N]
 __global__ void k_pack_x(long long N, const float *__restrict__ xf, unsigned short *__restrict__ x)
 {
     const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= N) return;
-    for (int c = 0; c < 16; ++c) x[s * 16 + c] = c < 8 ? f2bf(xf[c * N + s]) : (unsigned short)0;
+    float v[8];
+    for (int c = 0; c < 8; ++c) v[c] = xf[c * N + s];
+    store_input(x + s * 32, v);
 }
 
 // channel-first float32 network input and target from lattice fields:
@@ -408,7 +452,6 @@ void cnn_conv_fwd(int layer, const CnnShape &sh, const unsigned short *in, const
     const Grid3 g{sh.nx, sh.ny, sh.nz};
     const unsigned nb = nblocks(sh.N);
     switch (layer) {
-    case 0: hipLaunchKernelGGL((k_conv_fwd<16, 32>), dim3(nb), dim3(256), 0, st, g, sh.N, in, W, b, z, a, act); break;
     case 3: hipLaunchKernelGGL((k_conv_fwd<32, 16>), dim3(nb), dim3(256), 0, st, g, sh.N, in, W, b, z, a, act); break;
     default: hipLaunchKernelGGL((k_conv_fwd<32, 32>), dim3(nb), dim3(256), 0, st, g, sh.N, in, W, b, z, a, act); break;
     }
@@ -430,7 +473,6 @@ void cnn_conv_wgrad(int layer, const CnnShape &sh, const unsigned short *gout, c
     const unsigned nb = nblocks(sh.N);
     int cip = 32, cop = 32;
     switch (layer) {
-    case 0: cip = 16; hipLaunchKernelGGL((k_conv_wgrad<16, 32>), dim3(nb), dim3(256), 0, st, g, sh.N, gout, ain, part); break;
     case 3: cop = 16; hipLaunchKernelGGL((k_conv_wgrad<32, 16>), dim3(nb), dim3(256), 0, st, g, sh.N, gout, ain, part); break;
     default: hipLaunchKernelGGL((k_conv_wgrad<32, 32>), dim3(nb), dim3(256), 0, st, g, sh.N, gout, ain, part); break;
     }
@@ -443,25 +485,27 @@ size_t cnn_wgrad_part_floats(int layer, long long N)
     return (size_t)nblocks(N) * (size_t)(27 * net_cop(layer) * net_cip(layer) + net_cop(layer));
 }
 
-void cnn_mse(const CnnShape &sh, const float *y, const float *tg, unsigned short *gout, float *loss_part,
+void cnn_mse(const CnnShape &sh, float wgt, const float *y, const float *tg, unsigned short *gout, float *loss_part,
              hipStream_t st)
 {
-    hipLaunchKernelGGL(k_mse, dim3(nblocks(sh.N)), dim3(256), 0, st, sh.N, 16, 6, y, tg, gout, loss_part);
+    hipLaunchKernelGGL(k_mse, dim3(nblocks(sh.N)), dim3(256), 0, st, sh.N, 16, 6, wgt, y, tg, gout, loss_part);
 }
 
-void cnn_adam(int n, int cop, int cip, int cout, int cin, float *w, const float *gw, float *m, float *v, float lr,
+void cnn_adam(int n, int cop, int cip, int cout, int cin, int split, float *w, const float *gw, float *m, float *v, float lr,
               double b1, double b2, double eps, int step, unsigned short *wb, unsigned short *wt, float *b,
               const float *gb, float *mb, float *vb, hipStream_t st)
 {
     const AdamConst k{lr, (float)b1, (float)b2, (float)(1.0 - b1), (float)(1.0 - b2),
                       (float)(1.0 - std::pow(b1, step)), (float)(1.0 - std::pow(b2, step)), (float)eps};
-    hipLaunchKernelGGL(k_adam, dim3(nblocks(n)), dim3(256), 0, st, n, cop, cip, cout, cin, w, gw, m, v, k, wb, wt);
+    hipLaunchKernelGGL(k_adam, dim3(nblocks(n)), dim3(256), 0, st, n, cop, cip, cout, cin, split, w, gw, m, v, k, wb,
+                       wt);
     hipLaunchKernelGGL(k_adam_bias, dim3(1), dim3(64), 0, st, cop, b, gb, mb, vb, k);
 }
 
-void cnn_cast(int n, int cop, int cip, const float *w, unsigned short *wb, unsigned short *wt, hipStream_t st)
+void cnn_cast(int n, int cop, int cip, int cin, int split, const float *w, unsigned short *wb, unsigned short *wt,
+              hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cast_weights, dim3(nblocks(n)), dim3(256), 0, st, n, cop, cip, w, wb, wt);
+    hipLaunchKernelGGL(k_cast_weights, dim3(nblocks(n)), dim3(256), 0, st, n, cop, cip, cin, split, w, wb, wt);
 }
 
 void cnn_pack_input(const CnnShape &sh, const float *n, const float *j, float n_ref, float j_ref, unsigned short *x,
