@@ -50,55 +50,80 @@ __device__ inline TileGeo tile_geo(const SysDesc<float> &S, int local)
     return t;
 }
 
-// Stage (n_b, vec_b) as float4 and g as float into LDS for the halo tile:
-// lds4[FS] then ldsg[FS].  Thread t walks the flat halo index t, t + 256, ...
-// with its (hx, hy, hz) coordinates advanced incrementally (no divisions);
-// consecutive threads read consecutive x, so global loads coalesce.
-__device__ inline int wrap_small(int v, int n)
+// Staging of the halo tile.  Rows (hy, hz) of the tile are numbered
+// row = hy + HY hz; RowOff[row] holds the global site offset of the row's
+// x = 0 site ((gz ny + gy) nx after periodic wrap), or -1 for a row outside
+// the walls.  Thread t owns the halo column hx = t % HX (its wrapped global
+// x computed once) and the rows t / HX, t / HX + 256 / HX, ...; consecutive
+// threads read consecutive x, so global loads coalesce, and the per-element
+// work is a table read, an add and the loads.
+__device__ inline int wrap_mod(int v, int n)
 {
-    while (v < 0) v += n;
-    while (v >= n) v -= n;
-    return v;
+    v %= n;
+    return v < 0 ? v + n : v;
 }
 
-__device__ inline void stage(const SysDesc<float> &S, const TileGeo &t, float4 *lds4, float *ldsg,
-                             const float *__restrict__ nb, const float *__restrict__ vb, const float *__restrict__ gp)
+struct StageLane {
+    int hx, row0, rstep;   // rstep = 0: the thread stages nothing
+    int gx;
+};
+
+__device__ inline StageLane stage_lane(const SysDesc<float> &S, const TileGeo &t)
 {
-    const long long N = S.N;
-    // step of kBlock in (hx, hy, hz) digits
-    const int HXY = t.HX * t.HY;
-    const int sz = kBlock / HXY, rem = kBlock - sz * HXY;
-    const int sy = rem / t.HX, sx = rem - sy * t.HX;
-    int i = threadIdx.x;
-    int hz = i / HXY, r0 = i - hz * HXY;
-    int hy = r0 / t.HX, hx = r0 - hy * t.HX;
-    for (; i < t.FS; i += kBlock) {
-        const int gx = wrap_small(t.x0 - t.R + hx, S.nx), gz = wrap_small(t.z0 - t.R + hz, S.nz);
+    StageLane l;
+    l.rstep = kBlock / t.HX;
+    l.hx = threadIdx.x % t.HX;
+    l.row0 = threadIdx.x / t.HX;
+    if (l.row0 >= l.rstep) l.rstep = 0;          // left-over threads of the last partial column set
+    l.gx = wrap_mod(t.x0 - t.R + l.hx, S.nx);
+    return l;
+}
+
+__device__ inline void fill_rows(const SysDesc<float> &S, const TileGeo &t, int *RowOff)
+{
+    const int rows = t.HY * t.HZ;
+    for (int r = threadIdx.x; r < rows; r += kBlock) {
+        const int hz = r / t.HY, hy = r - hz * t.HY;
         int gy = t.y0 - t.R + hy;
-        bool in = true;
-        if (S.walls) in = gy >= 0 && gy < S.ny;
-        else gy = wrap_small(gy, S.ny);
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        float g = 0.f;
-        if (in) {
-            const long long s = ((long long)gz * S.ny + gy) * S.nx + gx;
-            v = make_float4(nb[s], vb[s], vb[N + s], vb[2 * N + s]);
-            g = gp[s];
+        const int gz = wrap_mod(t.z0 - t.R + hz, S.nz);
+        if (S.walls) {
+            RowOff[r] = (gy >= 0 && gy < S.ny) ? (gz * S.ny + gy) * S.nx : -1;
+        } else {
+            gy = wrap_mod(gy, S.ny);
+            RowOff[r] = (gz * S.ny + gy) * S.nx;
         }
-        lds4[i] = v;
-        ldsg[i] = g;
-        hx += sx; hy += sy; hz += sz;
-        if (hx >= t.HX) { hx -= t.HX; ++hy; }
-        if (hy >= t.HY) { hy -= t.HY; ++hz; }
     }
 }
 
-// Copy the (a,b) half-shell into LDS: TA[k] = (LDS offset of e, e_hat),
-// TB[k] = (ee_xx, ee_xy, ee_xz, ee_yy), TC[k] = (ee_yz, ee_zz).  Reads of it
-// are wave-uniform broadcasts that share the in-order LDS counter with the
-// field reads, so the pair loop can be software-pipelined.
+__device__ inline void stage(const SysDesc<float> &S, const TileGeo &t, const StageLane &l, const int *RowOff,
+                             float4 *lds4, float *ldsg, const float *__restrict__ nb, const float *__restrict__ vb,
+                             const float *__restrict__ gp)
+{
+    const unsigned N = (unsigned)S.N;
+    const int rows = t.HY * t.HZ;
+    if (l.rstep == 0) return;
+    for (int row = l.row0; row < rows; row += l.rstep) {
+        const int ro = RowOff[row];
+        const int i = l.hx + row * t.HX;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        float g = 0.f;
+        if (ro >= 0) {
+            const unsigned so = (unsigned)(ro + l.gx);
+            v = make_float4(nb[so], vb[so], vb[N + so], vb[2 * N + so]);
+            g = gp[so];
+        }
+        lds4[i] = v;
+        ldsg[i] = g;
+    }
+}
+
+// Copy the (a,b) half-shell into LDS: TA[k] = (byte offset of e in the
+// float4 field array, e_hat), TB[k] = (ee_xx, ee_xy, ee_xz, ee_yy),
+// TC[k] = (ee_yz, ee_zz, byte offset of e in the float array, unused).
+// Reads of it are wave-uniform broadcasts that share the in-order LDS
+// counter with the field reads, so the pair loop can be software-pipelined.
 __device__ inline void stage_table(const Tables<float> &tb, int k0, int kn, const TileGeo &t, float4 *TA, float4 *TB,
-                                   float2 *TC, bool with_ee)
+                                   float4 *TC, bool with_ee)
 {
     const int HXY = t.HX * t.HY;
     for (int k = threadIdx.x; k < kn; k += kBlock) {
@@ -106,14 +131,18 @@ __device__ inline void stage_table(const Tables<float> &tb, int k0, int kn, cons
         unpack_offset(tb.sh_e[k0 + k], ex, ey, ez);
         const int off = ex + ey * t.HX + ez * HXY;
         const float *u = tb.sh_u + 3 * (k0 + k);
-        TA[k] = make_float4(__int_as_float(off), u[0], u[1], u[2]);
+        TA[k] = make_float4(__int_as_float(16 * off), u[0], u[1], u[2]);
         if (with_ee) {
             const float *ee = tb.sh_ee + 6 * (k0 + k);
             TB[k] = make_float4(ee[0], ee[1], ee[2], ee[3]);
-            TC[k] = make_float2(ee[4], ee[5]);
+            TC[k] = make_float4(ee[4], ee[5], __int_as_float(4 * off), 0.f);
         }
     }
 }
+
+// field reads at a byte offset from the site's own address
+__device__ inline float4 ld4(const char *base, int byte) { return *reinterpret_cast<const float4 *>(base + byte); }
+__device__ inline float ld1(const char *base, int byte) { return *reinterpret_cast<const float *>(base + byte); }
 
 struct TileSite {
     int tx, ty, tz, x, y, z;
@@ -156,19 +185,23 @@ __global__ void __launch_bounds__(kBlock) k_gather1_tile(const SysDesc<float> *_
     float *Lg = reinterpret_cast<float *>(lds + t.FS);
     float4 *TA = lds + t.FS + (t.FS + 3) / 4;
     float4 *TB = TA + S.sh_max;
-    float2 *TC = reinterpret_cast<float2 *>(TB + S.sh_max);
+    float4 *TC = TB + S.sh_max;
+    int *RowOff = reinterpret_cast<int *>(TC + S.sh_max);
+    const StageLane sl = stage_lane(S, t);
+    fill_rows(S, t, RowOff);
+    const char *c4 = reinterpret_cast<const char *>(L4 + q.c);
+    const char *cg = reinterpret_cast<const char *>(Lg + q.c);
     const bool solid = q.active && S.walls && (q.y == 0 || q.y == S.ny - 1);
     const long long sc = q.active ? q.s : 0;
     const float na = S.n[(long long)a * N + sc];
     const float ja0 = S.j[o3 + sc], ja1 = S.j[o3 + N + sc], ja2 = S.j[o3 + 2 * N + sc];
     float mf0 = 0.f, mf1 = 0.f, mf2 = 0.f, dj0 = 0.f, dj1 = 0.f, dj2 = 0.f, gam = 0.f;
     float T00 = 0.f, T01 = 0.f, T02 = 0.f, T11 = 0.f, T12 = 0.f, T22 = 0.f;
-    const int HXY = t.HX * t.HY;
     for (int b = 0; b < S.M; ++b) {
         const float *__restrict__ gpair = S.g + (long long)pidx(S.M, a, b) * N;
         const int k0 = S.sh_start[a][b], kn = S.sh_cnt[a][b];
         __syncthreads();
-        stage(S, t, L4, Lg, S.n + (long long)b * N, S.j + (long long)b * 3 * N, gpair);
+        stage(S, t, sl, RowOff, L4, Lg, S.n + (long long)b * N, S.j + (long long)b * 3 * N, gpair);
         stage_table(tb, k0, kn, t, TA, TB, TC, true);
         __syncthreads();
         const float g0 = Lg[q.c];
@@ -176,13 +209,11 @@ __global__ void __launch_bounds__(kBlock) k_gather1_tile(const SysDesc<float> *_
         float t00 = 0.f, t01 = 0.f, t02 = 0.f, t11 = 0.f, t12 = 0.f, t22 = 0.f;
 #pragma unroll 4
         for (int k = 0; k < kn; ++k) {
-            const float4 ta = TA[k], tb4 = TB[k];
-            const float2 tc = TC[k];
-            const int off = __float_as_int(ta.x);
+            const float4 ta = TA[k], tb4 = TB[k], tc = TC[k];
+            const int o4 = __float_as_int(ta.x), o1 = __float_as_int(tc.z);
             const float e0 = ta.y, e1 = ta.z, e2 = ta.w;
-            const int p = q.c + off, m = q.c - off;
-            const float4 Ap = L4[p], Am = L4[m];
-            const float Gp = g0 + Lg[p], Gm = g0 + Lg[m];
+            const float4 Ap = ld4(c4, o4), Am = ld4(c4, -o4);
+            const float Gp = g0 + ld1(cg, o1), Gm = g0 + ld1(cg, -o1);
             const float tp = Gp * Ap.x, tm = Gm * Am.x;
             const float dt = tp - tm, st = tp + tm;
             s0 += e0 * dt; s1 += e1 * dt; s2 += e2 * dt;
@@ -267,14 +298,18 @@ __global__ void __launch_bounds__(kBlock) k_step2_tile(const SysDesc<float> *__r
     float4 *L4 = lds;
     float *Lg = reinterpret_cast<float *>(lds + t.FS);
     float4 *TA = lds + t.FS + (t.FS + 3) / 4;
+    int *RowOff = reinterpret_cast<int *>(TA + 3 * S.sh_max);
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
-    const int HXY = t.HX * t.HY;
     if (S.scheme != 1) {
+        const StageLane sl = stage_lane(S, t);
+        fill_rows(S, t, RowOff);
+        const char *c4 = reinterpret_cast<const char *>(L4 + q.c);
+        const char *cg = reinterpret_cast<const char *>(Lg + q.c);
         for (int b = 0; b < S.M; ++b) {
             const float *__restrict__ gpair = S.g + (long long)pidx(S.M, a, b) * N;
             const int k0 = S.sh_start[a][b], kn = S.sh_cnt[a][b];
             __syncthreads();
-            stage(S, t, L4, Lg, S.n + (long long)b * N, S.vh + (long long)b * 3 * N, gpair);
+            stage(S, t, sl, RowOff, L4, Lg, S.n + (long long)b * N, S.vh + (long long)b * 3 * N, gpair);
             stage_table(tb, k0, kn, t, TA, nullptr, nullptr, false);
             __syncthreads();
             const float g0 = Lg[q.c];
@@ -282,11 +317,10 @@ __global__ void __launch_bounds__(kBlock) k_step2_tile(const SysDesc<float> *__r
 #pragma unroll 4
             for (int k = 0; k < kn; ++k) {
                 const float4 ta = TA[k];
-                const int off = __float_as_int(ta.x);
+                const int o4 = __float_as_int(ta.x), o1 = o4 >> 2;
                 const float e0 = ta.y, e1 = ta.z, e2 = ta.w;
-                const int p = q.c + off, m = q.c - off;
-                const float4 Ap = L4[p], Am = L4[m];
-                const float tp = (g0 + Lg[p]) * Ap.x, tm = (g0 + Lg[m]) * Am.x;
+                const float4 Ap = ld4(c4, o4), Am = ld4(c4, -o4);
+                const float tp = (g0 + ld1(cg, o1)) * Ap.x, tm = (g0 + ld1(cg, -o1)) * Am.x;
                 const float w0 = tp * Ap.y + tm * Am.y;
                 const float w1 = tp * Ap.z + tm * Am.z;
                 const float w2 = tp * Ap.w + tm * Am.w;
@@ -344,11 +378,13 @@ __global__ void __launch_bounds__(kBlock) k_step2_tile(const SysDesc<float> *__r
     }
 }
 
-// float4 + float per staged site, then the shell table (40 bytes per entry)
+// float4 + float per staged site, the shell table (48 bytes per entry),
+// then the row-offset table (one int per halo row)
 inline size_t tile_lds_bytes(int TX, int TY, int TZ, int R, int sh_max)
 {
     const size_t FS = (size_t)(TX + 2 * R) * (TY + 2 * R) * (TZ + 2 * R);
-    return 16 * FS + 16 * ((FS + 3) / 4) + 40 * (size_t)sh_max;
+    const size_t rows = (size_t)(TY + 2 * R) * (TZ + 2 * R);
+    return 16 * FS + 16 * ((FS + 3) / 4) + 48 * (size_t)sh_max + 4 * rows;
 }
 
 }  // namespace mlb

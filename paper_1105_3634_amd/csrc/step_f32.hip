@@ -1,5 +1,7 @@
 // Float32 instantiation of the per-site passes (contraction allowed) and
 // the tiled float32 gathers in three tile shapes.
+#include <cstdint>
+
 #include "gather_tile.h"
 
 namespace mlb {
@@ -22,6 +24,7 @@ size_t tile_lds_bytes_of(int v, int reach, int sh_max)
 {
     int tx, ty, tz;
     tile_dims(v, tx, ty, tz);
+    if (tx + 2 * reach > kBlock) return SIZE_MAX;   // not stageable: one halo column per thread
     return tile_lds_bytes(tx, ty, tz, reach, sh_max);
 }
 
@@ -31,6 +34,7 @@ bool prepare_one(int reach, int sh_max)
 {
     const size_t bytes = tile_lds_bytes(TX, TY, TZ, reach, sh_max);
     if (bytes > 160 * 1024) return false;
+    if (TX + 2 * reach > kBlock) return false;   // staging gives each thread one halo column
     if (hipFuncSetAttribute((const void *)k_gather1_tile<TX, TY, TZ>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)bytes) != hipSuccess)
         return false;
