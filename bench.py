@@ -75,13 +75,53 @@ def algorithmic_work(mix, tail_direct: bool):
         "gather1": N * sum(25 * sum(S[a]) + (3.5 * sum(T[a]) if tail_direct else 0) + 40 for a in range(M)),
         "step2": N * sum(14.5 * sum(S[a]) + 30 * 19 for a in range(M)),
     }
+    tail_words = 0 if tail_direct else 3 * M
     bytes_ = {
+        # f in; n, j, u out
         "moments": N * w * (19 * M + 4 * M + 3),
+        # n in; g out
         "contact": N * w * (M + P),
-        "gather1": N * w * (4 * M + P + 6 * M),
-        "step2": N * w * (4 * M + P + 3 + 3 * M + 3 * M + 19 * M),
+        # n, j, g (and the spectral tail) in; V-hat, H, friction tensor out
+        "gather1": N * w * (4 * M + P + tail_words + 12 * M),
+        # f, n, V-hat, g, H, friction tensor, j, u in; f out
+        "step2": N * w * (19 * M + M + 3 * M + P + 3 * M + 6 * M + 3 * M + 3 + 19 * M),
     }
     return flops, bytes_, S, T
+
+
+PROFILE = os.path.join(ROOT, "profiles", "step_kernels_bulk_diffusion_128x32x32.md")
+
+
+def counter_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by its reading on a plain
+    copy), or None when the summary is missing or the kernel's sources have
+    changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(PROFILE):
+        return None
+    rec, traffic = {}, {}
+    for line in open(PROFILE):
+        line = line.strip()
+        if line.startswith("traffic_kib "):
+            name, rest = line[len("traffic_kib "):].split(":", 1)
+            f = rest.split()
+            traffic[name.strip()] = (float(f[1]), float(f[3]))
+        elif ":" in line and line.split(":", 1)[0] in ("sources_sha256", "sources", "fetch_scale", "write_scale"):
+            k, v = line.split(":", 1)
+            rec[k] = v.strip()
+    if "sources" not in rec or kernel not in traffic:
+        return None
+    h = hashlib.sha256()
+    for f in rec["sources"].split():
+        path = os.path.join(ROOT, f)
+        if not os.path.exists(path):
+            return None
+        h.update(open(path, "rb").read())
+    if h.hexdigest() != rec.get("sources_sha256"):
+        return None
+    fk, wk = traffic[kernel]
+    return 1024.0 * (fk * float(rec["fetch_scale"]) + wk * float(rec["write_scale"]))
 
 
 def d12_check(mlb, mix, n0, u0):
@@ -315,6 +355,10 @@ def main():
     avg_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in passes.items()}
     dom = max((k for k in avg_ms if k in flops), key=lambda k: avg_ms[k])
     achieved = flops[dom] / (avg_ms[dom] * 1e-3) / 1e12
+    shapes = ("16,4,4", "8,8,4", "32,4,2")
+    tune = g.tuning()
+    kname = {"gather1": "k_gather1_tile", "step2": "k_step2_tile"}.get(dom)
+    traffic = counter_traffic(f"{kname}<{shapes[tune['shape']]}>") if kname else None
     total_bytes = sum(bytes_.values()) * args.steps
     line = {
         "metric": METRIC,
@@ -333,11 +377,12 @@ def main():
                    "sigma": list(mix.sigma), "packing": 0.3, "eps_over_kT": 0.5, "rc_over_sigma": mix.rc_factor,
                    "tail": "direct" if tail_direct else "spectral", "scheme": "CN-J1", "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                     "flop_per_launch": flops[dom], "avg_launch_ms": avg_ms[dom]},
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
+                     "traffic_algorithmic": bytes_[dom], "flop_per_launch": flops[dom],
+                     "avg_launch_ms": avg_ms[dom]},
         "hbm_gbs_algorithmic": total_bytes / elapsed / 1e9,
         "passes_ms_per_step": {k: v[0] / args.steps for k, v in passes.items()},
-        "tuning": g.tuning(),
+        "tuning": tune,
     }
     acc = None if args.no_d12 else d12_check(mlb, mix, n0, u0)
     if acc is not None:
