@@ -232,11 +232,17 @@ struct mlb_batch_s {
     int64_t closure_checks = 0, fallback_step = -1;
     double last_err = -1.0;
     hipGraphExec_t graph_closure = nullptr;
+    // second stream for the contact pass while the spectral field runs
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
     virtual ~mlb_batch_s()
     {
         if (graph) (void)hipGraphExecDestroy(graph);
         if (graph_closure) (void)hipGraphExecDestroy(graph_closure);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (side) (void)hipStreamDestroy(side);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
     }
@@ -615,9 +621,23 @@ void run_passes(Batch &B, hipStream_t st, bool query, int qk, int force_only)
     const int nsite = query ? B.sys[qk].nblocks : B.nblk_site;
     const int M = query ? B.sys[qk].M : B.maxM;
     pass(B, kPassMoments, st, [&] { mlb::Launch<T>::moments(sys, smap, nsite, par, st); });
-    pass(B, kPassContact, st, [&] { mlb::Launch<T>::contact(sys, smap, nsite, tb, st); });
-    for (int k = 0; k < B.count; ++k)
-        if ((!query || k == qk) && B.sys[k].spectral) pass(B, kPassTail, st, [&] { run_tail(B, B.sys[k], st); });
+    bool spectral = false;
+    for (int k = 0; k < B.count; ++k) spectral = spectral || ((!query || k == qk) && B.sys[k].spectral);
+    if (spectral && B.side) {
+        // contact values and the spectral field both need only the moments:
+        // contact runs on the side stream, joined before the first gather
+        (void)hipEventRecord(B.ev_fork, st);
+        (void)hipStreamWaitEvent(B.side, B.ev_fork, 0);
+        pass(B, kPassContact, B.side, [&] { mlb::Launch<T>::contact(sys, smap, nsite, tb, B.side); });
+        (void)hipEventRecord(B.ev_join, B.side);
+        for (int k = 0; k < B.count; ++k)
+            if ((!query || k == qk) && B.sys[k].spectral) pass(B, kPassTail, st, [&] { run_tail(B, B.sys[k], st); });
+        (void)hipStreamWaitEvent(st, B.ev_join, 0);
+    } else {
+        pass(B, kPassContact, st, [&] { mlb::Launch<T>::contact(sys, smap, nsite, tb, st); });
+        for (int k = 0; k < B.count; ++k)
+            if ((!query || k == qk) && B.sys[k].spectral) pass(B, kPassTail, st, [&] { run_tail(B, B.sys[k], st); });
+    }
     if constexpr (std::is_same<T, float>::value) {
         if (B.tiled) {
             const int shape = B.tune.shape;
@@ -885,6 +905,14 @@ mlb_status create(Batch &B, const mlb_params *params, int count, void *workspace
     if (B.tiled) TRY(set_tiling(B, 0, 1, st));
     for (auto &S : B.sys)
         if (S.spectral) TRY(setup_spectral(B, S, st));
+    bool any_spectral = false;
+    for (auto &S : B.sys) any_spectral = any_spectral || S.spectral;
+    if (any_spectral) {
+        // default priority, like every stream of the library
+        HIP_TRY(hipStreamCreateWithFlags(&B.side, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&B.ev_fork, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&B.ev_join, hipEventDisableTiming));
+    }
     TRY(init_populations<T>(B, n0, u0, st));
     for (auto &S : B.sys) mlb::launch_zero_i32(reinterpret_cast<int *>(B.ws + S.series_cnt), 1, st);
     HIP_TRY(hipStreamSynchronize(st));

@@ -1,5 +1,5 @@
 // Spectral evaluation of the attractive field (see spectral.hip).
-// Applicable when a (y, z) plane of the box fits the LDS budget
+// Applicable when two (y, z) planes of the box fit the LDS budget
 // (SpectralPlan::fused_fits); otherwise the field is summed directly.
 #pragma once
 
@@ -43,8 +43,9 @@ struct SpectralPlan {
     // x stage as batched GEMMs; spectra in [field][kx][re|im][z][y]
     void x_forward(const float *real_in, int nfields, float *s1, hipStream_t st) const;
     void x_inverse(const float *s2, int nfields, float *real_out, hipStream_t st) const;
-    // fused y/z stages, one workgroup per kx; mode 0 writes the sine spectra
-    void launch_yz(int mode, int nin, const float *in, float *out, hipStream_t st) const;
+    // y/z stages, one workgroup per kx plane and field: mode 0 forward -> sine
+    // spectra of the kernels, 1 forward -> spectra, 2 products + inverse (3M outputs)
+    void launch_yz(int mode, int nfields, const float *in, float *out, hipStream_t st) const;
     static bool fused_fits(int ny, int nz, int M);
     static bool prepare(int ny, int nz, int M);
     // placed: [P][3][N] kernels w_ab on the periodic grid (sum over wrapped offsets)

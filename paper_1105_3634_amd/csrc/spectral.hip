@@ -9,10 +9,11 @@
 // components.  Every 1-D DFT along an axis is a dense contraction with the
 // DFT matrix on the matrix cores (v_mfma_f32_16x16x4f32):
 //   x (innermost):  batched GEMM over lines, C = A W  (W: nx x 2nkx, or 2nkx x nx)
-//   y and z:        one workgroup per kx plane holds the plane in LDS and
-//                   applies the 2L x 2L real block form of the complex DFT
-//                   matrix along y, then along z; the spectral product and
-//                   the inverse y/z transforms run in the same kernel.
+//   y and z:        one workgroup per (kx plane, field) holds the plane in
+//                   LDS and applies the 2L x 2L real block form of the
+//                   complex DFT matrix along y, then along z; a second
+//                   kernel forms the spectral products and runs the
+//                   inverse y/z transforms, one workgroup per (kx, component).
 // Complex data live as split real/imaginary parts, kx-major:
 //   spec[field][kx][re|im][z][y],  kx < nkx = nx/2 + 1.
 // The spectrum S_ab is obtained once at init by the same forward stages
@@ -30,18 +31,25 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int kTK = 16;
 
+// A divisor of kPlain or more marks a plain stride (no split); the test is
+// uniform across the launch, so it costs a scalar branch, not a division.
+constexpr int kPlain = 1 << 30;
+
 __device__ inline long long part_t(const MatAddr &m, int t)
 {
+    if (m.t_div >= kPlain) return (long long)t * m.s_tlo;
     const int h = t / m.t_div;
     return (long long)h * m.s_thi + (long long)(t - h * m.t_div) * m.s_tlo;
 }
 __device__ inline long long part_r(const MatAddr &m, int r)
 {
+    if (m.r_div >= kPlain) return (long long)r * m.s_rlo;
     const int h = r / m.r_div;
     return (long long)h * m.s_rhi + (long long)(r - h * m.r_div) * m.s_rlo;
 }
 __device__ inline long long part_c(const MatAddr &m, int c)
 {
+    if (m.c_div >= kPlain) return (long long)c * m.s_clo;
     const int h = c / m.c_div;
     return (long long)h * m.s_chi + (long long)(c - h * m.c_div) * m.s_clo;
 }
@@ -139,33 +147,59 @@ void launch_gemm(const GemmDesc &g, hipStream_t st)
     }
 }
 
-// ------------------------------------------------- fused y/z stages (LDS)
-// Workgroup (kx, g): the kx plane of every input field and one output
-// component g.  Complex planes live in LDS as two real parts, x-rows padded
-// to odd strides against bank conflicts:
+// ------------------------------------------------------- y/z stages (LDS)
+// Two kernels per application of the field:
+//   forward:  workgroup (kx, f) transforms the kx plane of input field f
+//             along y, then z, and writes its spectrum;
+//   inverse:  workgroup (kx, g) forms output component g's spectral product
+//             from the M input spectra and transforms it back along z, then y.
+// A complex plane lives in LDS as two real parts, rows padded to odd
+// strides against bank conflicts:
 //   X[p][z][y]  (row stride RY = ny + 1)      T[p][ky][z]  (row stride RZ = nz + 1)
 // Each 1-D transform is a dense contraction on the matrix cores
 // (v_mfma_f32_16x16x4f32, 16x16 output blocks dealt to the 4 waves):
 //   y stage:  T[(p',ky)][z]  = sum_{(p,y)} Wy[(p',ky)][(p,y)] X[p][z][y]
 //   z stage:  X[p'][kz][ky] = sum_{(p,z)} T[p][ky][z] Wz[(p',kz)][(p,z)]
-// with Wy, Wz the real 2L x 2L block form of the complex DFT matrix, staged
-// in LDS (row stride 2L + 1).  The K loop runs per real/imaginary block so
-// lane indices need no division.
+// with Wy, Wz the real 2L x 2L block form of the complex DFT matrix, read
+// from global memory (a few KB, resident in every L2).  The K loop runs per
+// real/imaginary block so lane indices need no division; plane indices use
+// a multiply-shift division by ny prepared on the host.
+struct FastDiv {
+    unsigned m;
+    int l;   // q = (umulhi(n, m) + n) >> l, exact for n < 2^31
+};
+
+__device__ inline int fdiv(int n, FastDiv d)
+{
+    const unsigned un = (unsigned)n;
+    return (int)((__umulhi(un, d.m) + un) >> d.l);
+}
+
 struct YZArgs {
-    int ny, nz, nkx, M, mode, nin;   // mode 0: forward only -> sine spectra; 1: full product
-    long long PS, Sp, FSTR;          // plane part size in global memory, per-field spectrum size, field stride
+    int ny, nz, M, mode;          // mode 0: forward -> sine spectra of the kernels; 1: forward -> spectra
+    int PS;                       // ny * nz (one real part of a plane)
+    long long Sp, FSTR;           // per-field spectrum part size, field stride in the spectra buffers
+    FastDiv div_ny;
     const float *in;
     float *out;
     const float *S;
     float scale;
-    const float *wyf, *wyi, *wzf, *wzi;
+    const float *wy, *wz;         // forward or inverse DFT matrices (2L x 2L, row-major)
 };
 
 struct YZLds {
     int ny, nz, RY, RZ, PX, PT, ty, tz;   // PX, PT: padded part sizes of X and T planes
 };
 
-__device__ inline void yz_stage_y(const YZLds &g, const float *Wy, const float *X, float *T)
+__device__ inline YZLds yz_geometry(const YZArgs &a)
+{
+    YZLds g;
+    g.ny = a.ny; g.nz = a.nz; g.RY = a.ny + 1; g.RZ = a.nz + 1;
+    g.PX = a.nz * g.RY; g.PT = a.ny * g.RZ; g.ty = 2 * a.ny; g.tz = 2 * a.nz;
+    return g;
+}
+
+__device__ inline void yz_stage_y(const YZLds &g, const float *__restrict__ Wy, const float *X, float *T)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, q = lane >> 4;
     const int bm = (g.ty + 15) / 16, bn = (g.nz + 15) / 16;
@@ -176,7 +210,7 @@ __device__ inline void yz_stage_y(const YZLds &g, const float *Wy, const float *
         for (int p = 0; p < 2; ++p)
             for (int y0 = 0; y0 < g.ny; y0 += 4) {
                 const int yy = y0 + q;
-                const float a = (ia < g.ty && yy < g.ny) ? Wy[ia * (g.ty + 1) + p * g.ny + yy] : 0.f;
+                const float a = (ia < g.ty && yy < g.ny) ? Wy[ia * g.ty + p * g.ny + yy] : 0.f;
                 const float b = (jb < g.nz && yy < g.ny) ? X[p * g.PX + jb * g.RY + yy] : 0.f;
                 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
             }
@@ -190,7 +224,7 @@ __device__ inline void yz_stage_y(const YZLds &g, const float *Wy, const float *
     }
 }
 
-__device__ inline void yz_stage_z(const YZLds &g, const float *Wz, const float *T, float *X)
+__device__ inline void yz_stage_z(const YZLds &g, const float *__restrict__ Wz, const float *T, float *X)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, q = lane >> 4;
     const int bm = (g.ny + 15) / 16, bn = (g.tz + 15) / 16;
@@ -202,7 +236,7 @@ __device__ inline void yz_stage_z(const YZLds &g, const float *Wz, const float *
             for (int z0 = 0; z0 < g.nz; z0 += 4) {
                 const int zz = z0 + q;
                 const float a = (ia < g.ny && zz < g.nz) ? T[p * g.PT + ia * g.RZ + zz] : 0.f;
-                const float b = (jb < g.tz && zz < g.nz) ? Wz[jb * (g.tz + 1) + p * g.nz + zz] : 0.f;
+                const float b = (jb < g.tz && zz < g.nz) ? Wz[jb * g.tz + p * g.nz + zz] : 0.f;
                 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
             }
         for (int v = 0; v < 4; ++v) {
@@ -215,93 +249,94 @@ __device__ inline void yz_stage_z(const YZLds &g, const float *Wz, const float *
     }
 }
 
-__device__ inline void stage_matrix(float *dst, const float *__restrict__ src, int L2)
+// grid (nkx, nfields): spectrum of the kx plane of field f
+__global__ void __launch_bounds__(256) k_yz_forward(YZArgs a)
 {
-    for (int i = threadIdx.x; i < L2 * L2; i += blockDim.x) {
-        const int r = i / L2, c = i - r * L2;
-        dst[r * (L2 + 1) + c] = src[i];
+    extern __shared__ float L[];
+    const YZLds g = yz_geometry(a);
+    const int kx = blockIdx.x, f = blockIdx.y;
+    const int PL = 2 * (g.PX > g.PT ? g.PX : g.PT);
+    float *X = L, *T = L + PL;
+    const int P2 = 2 * a.PS;
+    const float *__restrict__ src = a.in + f * a.FSTR + (long long)kx * P2;
+    for (int i = threadIdx.x; i < P2; i += blockDim.x) {
+        const int p = i >= a.PS ? 1 : 0;
+        const int r = i - p * a.PS, z = fdiv(r, a.div_ny), y = r - z * a.ny;
+        X[p * g.PX + z * g.RY + y] = src[i];
+    }
+    __syncthreads();
+    yz_stage_y(g, a.wy, X, T);
+    __syncthreads();
+    yz_stage_z(g, a.wz, T, X);
+    __syncthreads();
+    if (a.mode == 0) {
+        // sine spectra of the odd kernels: S = -Im F[w] / N, layout [f][kx][kz][ky]
+        float *__restrict__ dst = a.out + f * a.Sp + (long long)kx * a.PS;
+        for (int i = threadIdx.x; i < a.PS; i += blockDim.x) {
+            const int z = fdiv(i, a.div_ny), y = i - z * a.ny;
+            dst[i] = -X[g.PX + z * g.RY + y] * a.scale;
+        }
+        return;
+    }
+    float *__restrict__ dst = a.out + f * a.FSTR + (long long)kx * P2;
+    for (int i = threadIdx.x; i < P2; i += blockDim.x) {
+        const int p = i >= a.PS ? 1 : 0;
+        const int r = i - p * a.PS, z = fdiv(r, a.div_ny), y = r - z * a.ny;
+        dst[i] = X[p * g.PX + z * g.RY + y];
     }
 }
 
-__global__ void __launch_bounds__(256) k_tail_yz(YZArgs a)
+// grid (nkx, 3M): output component (species aa, direction d) of the field:
+// C^ = i sum_b S_{aa b, d} n^_b, then the inverse y/z stages
+__global__ void __launch_bounds__(256) k_yz_inverse(YZArgs a)
 {
     extern __shared__ float L[];
-    YZLds g;
-    g.ny = a.ny; g.nz = a.nz; g.RY = a.ny + 1; g.RZ = a.nz + 1;
-    g.PX = a.nz * g.RY; g.PT = a.ny * g.RZ; g.ty = 2 * a.ny; g.tz = 2 * a.nz;
+    const YZLds g = yz_geometry(a);
     const int kx = blockIdx.x, gout = blockIdx.y;
-    const int PL = 2 * (g.PX > g.PT ? g.PX : g.PT);   // one padded complex plane
-    float *IN = L;                                     // nin planes
-    float *W0 = IN + a.nin * PL, *W1 = W0 + PL;        // work planes
-    float *Wy = W1 + PL;                               // ty x (ty + 1)
-    float *Wz = Wy + g.ty * (g.ty + 1);                // tz x (tz + 1)
-    stage_matrix(Wy, a.wyf, g.ty);
-    stage_matrix(Wz, a.wzf, g.tz);
-    const long long P2 = 2 * a.PS;
-    for (int f = 0; f < a.nin; ++f)
-        for (long long i = threadIdx.x; i < P2; i += blockDim.x) {
-            const int p = i >= a.PS ? 1 : 0;
-            const int r = (int)(i - p * a.PS), z = r / a.ny, y = r - z * a.ny;
-            IN[f * PL + p * g.PX + z * g.RY + y] = a.in[f * a.FSTR + kx * P2 + i];
-        }
-    __syncthreads();
-    for (int f = 0; f < a.nin; ++f) {
-        yz_stage_y(g, Wy, IN + f * PL, W0);
-        __syncthreads();
-        yz_stage_z(g, Wz, W0, IN + f * PL);
-        __syncthreads();
-    }
-    if (a.mode == 0) {
-        // sine spectra of the odd kernels: S = -Im F[w] / N, layout [f][kx][kz][ky]
-        for (int f = 0; f < a.nin; ++f)
-            for (long long i = threadIdx.x; i < a.PS; i += blockDim.x) {
-                const int z = (int)(i / a.ny), y = (int)(i - (long long)z * a.ny);
-                a.out[f * a.Sp + kx * a.PS + i] = -IN[f * PL + g.PX + z * g.RY + y] * a.scale;
-            }
-        return;
-    }
-    // inverse matrices replace the forward ones
-    __syncthreads();
-    stage_matrix(Wy, a.wyi, g.ty);
-    stage_matrix(Wz, a.wzi, g.tz);
+    const int PL = 2 * (g.PX > g.PT ? g.PX : g.PT);
+    float *X = L, *T = L + PL;
+    const int P2 = 2 * a.PS;
     const int M = a.M, aa = gout / 3, d = gout % 3;
-    for (long long i = threadIdx.x; i < a.PS; i += blockDim.x) {
-        const int z = (int)(i / a.ny), y = (int)(i - (long long)z * a.ny);
+    for (int i = threadIdx.x; i < a.PS; i += blockDim.x) {
+        const int z = fdiv(i, a.div_ny), y = i - z * a.ny;
         const int o = z * g.RY + y;
         float re = 0.f, im = 0.f;
         for (int b = 0; b < M; ++b) {
             const int lo = aa < b ? aa : b, hi = aa < b ? b : aa;
-            const int p = lo * M - (lo * (lo - 1)) / 2 + (hi - lo);
-            const float sv = a.S[(long long)(p * 3 + d) * a.Sp + kx * a.PS + i];
-            re -= sv * IN[b * PL + g.PX + o];
-            im += sv * IN[b * PL + o];
+            const int pr = lo * M - (lo * (lo - 1)) / 2 + (hi - lo);
+            const float sv = a.S[(long long)(pr * 3 + d) * a.Sp + (long long)kx * a.PS + i];
+            const float *__restrict__ F = a.in + b * a.FSTR + (long long)kx * P2;
+            re -= sv * F[a.PS + i];
+            im += sv * F[i];
         }
-        W1[o] = re;
-        W1[g.PX + o] = im;
+        X[o] = re;
+        X[g.PX + o] = im;
     }
     __syncthreads();
-    yz_stage_y(g, Wy, W1, W0);
+    yz_stage_y(g, a.wy, X, T);
     __syncthreads();
-    yz_stage_z(g, Wz, W0, W1);
+    yz_stage_z(g, a.wz, T, X);
     __syncthreads();
-    for (long long i = threadIdx.x; i < P2; i += blockDim.x) {
+    float *__restrict__ dst = a.out + gout * a.FSTR + (long long)kx * P2;
+    for (int i = threadIdx.x; i < P2; i += blockDim.x) {
         const int p = i >= a.PS ? 1 : 0;
-        const int r = (int)(i - p * a.PS), z = r / a.ny, y = r - z * a.ny;
-        a.out[gout * a.FSTR + kx * P2 + i] = W1[p * g.PX + z * g.RY + y];
+        const int r = i - p * a.PS, z = fdiv(r, a.div_ny), y = r - z * a.ny;
+        dst[i] = X[p * g.PX + z * g.RY + y];
     }
 }
 
-// LDS bytes of the fused kernel for nin input planes.
-size_t yz_lds_bytes(int ny, int nz, int nin)
+// LDS bytes of the y/z kernels: two padded complex planes.
+size_t yz_lds_bytes(int ny, int nz)
 {
     const size_t PX = (size_t)nz * (ny + 1), PT = (size_t)ny * (nz + 1);
     const size_t PL = 2 * (PX > PT ? PX : PT);
-    return sizeof(float) * (PL * (nin + 2) + (size_t)(2 * ny) * (2 * ny + 1) + (size_t)(2 * nz) * (2 * nz + 1));
+    return sizeof(float) * 2 * PL;
 }
 
 bool SpectralPlan::fused_fits(int ny, int nz, int M)
 {
-    return yz_lds_bytes(ny, nz, M > 1 ? M : 1) <= 150 * 1024;
+    (void)M;
+    return yz_lds_bytes(ny, nz) <= 150 * 1024 && (long long)ny * nz < (1LL << 30);
 }
 
 // ------------------------------------------------------------------ plan
@@ -311,7 +346,7 @@ MatAddr dense(const float *base, long long ld)
 {
     MatAddr m{};
     m.base = const_cast<float *>(base);
-    m.t_div = 1 << 30; m.r_div = 1 << 30; m.c_div = 1 << 30;
+    m.t_div = kPlain; m.r_div = kPlain; m.c_div = kPlain;
     m.s_rlo = ld; m.s_clo = 1;
     return m;
 }
@@ -341,23 +376,45 @@ void SpectralPlan::x_inverse(const float *s2, int nfields, float *real_out, hipS
     launch_gemm(gx, st);
 }
 
-void SpectralPlan::launch_yz(int mode, int nin, const float *in, float *out, hipStream_t st) const
+namespace {
+FastDiv make_fastdiv(int d)
 {
-    YZArgs a;
-    a.ny = ny; a.nz = nz; a.nkx = nkx; a.M = M; a.mode = mode; a.nin = nin;
-    a.PS = (long long)ny * nz; a.Sp = Sp; a.FSTR = 2 * Sp;
+    int l = 0;
+    while ((1LL << l) < d) ++l;
+    const unsigned long long two32 = 1ULL << 32;
+    FastDiv f;
+    f.l = l;
+    f.m = (unsigned)((two32 * ((1ULL << l) - (unsigned long long)d)) / (unsigned long long)d + 1);
+    return f;
+}
+}  // namespace
+
+void SpectralPlan::launch_yz(int mode, int nfields, const float *in, float *out, hipStream_t st) const
+{
+    YZArgs a{};
+    a.ny = ny; a.nz = nz; a.M = M; a.mode = mode;
+    a.PS = ny * nz; a.Sp = Sp; a.FSTR = 2 * Sp;
+    a.div_ny = make_fastdiv(ny);
     a.in = in; a.out = out; a.S = S;
     a.scale = 1.0f / (float)((double)nx * ny * nz);
-    a.wyf = wyf; a.wyi = wyi; a.wzf = wzf; a.wzi = wzi;
-    const size_t lds = yz_lds_bytes(ny, nz, nin);
-    hipLaunchKernelGGL(k_tail_yz, dim3(nkx, mode == 0 ? 1 : 3 * M), dim3(256), lds, st, a);
+    const size_t lds = yz_lds_bytes(ny, nz);
+    if (mode == 2) {
+        a.wy = wyi; a.wz = wzi;
+        hipLaunchKernelGGL(k_yz_inverse, dim3(nkx, 3 * M), dim3(256), lds, st, a);
+    } else {
+        a.wy = wyf; a.wz = wzf;
+        hipLaunchKernelGGL(k_yz_forward, dim3(nkx, nfields), dim3(256), lds, st, a);
+    }
 }
 
 bool SpectralPlan::prepare(int ny, int nz, int M)
 {
-    const size_t bytes = yz_lds_bytes(ny, nz, M > 1 ? M : 1);
-    return hipFuncSetAttribute((const void *)k_tail_yz, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
-           hipSuccess;
+    (void)M;
+    const size_t bytes = yz_lds_bytes(ny, nz);
+    return hipFuncSetAttribute((const void *)k_yz_forward, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
+               hipSuccess &&
+           hipFuncSetAttribute((const void *)k_yz_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
+               hipSuccess;
 }
 
 void SpectralPlan::build_spectrum(const float *placed, float *s1, float *s2, hipStream_t st) const
@@ -365,15 +422,15 @@ void SpectralPlan::build_spectrum(const float *placed, float *s1, float *s2, hip
     (void)s2;
     const int nf = 3 * P;
     x_forward(placed, nf, s1, st);
-    // one kernel field at a time keeps the LDS footprint at 3 planes
-    for (int f = 0; f < nf; ++f) launch_yz(0, 1, s1 + 2 * Sp * f, S + Sp * f, st);
+    launch_yz(0, nf, s1, S, st);
 }
 
 void SpectralPlan::apply(const float *n, float *s1, float *s2, float *tail, hipStream_t st) const
 {
     x_forward(n, M, s1, st);
-    launch_yz(1, M, s1, s2, st);
-    x_inverse(s2, 3 * M, tail, st);
+    launch_yz(1, M, s1, s2, st);        // spectra of the M densities
+    launch_yz(2, 3 * M, s2, s1, st);    // products and inverse y/z stages, 3M components
+    x_inverse(s1, 3 * M, tail, st);
 }
 
 }  // namespace mlb
