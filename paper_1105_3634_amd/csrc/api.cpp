@@ -174,7 +174,7 @@ struct SysHost {
     bool spectral = false;
     mlb::SpectralPlan plan;
     int nblocks = 0;
-    size_t f0 = 0, f1 = 0, n = 0, j = 0, u = 0, g = 0, vh = 0, H = 0, Nf = 0, Tloc = 0;
+    size_t f0 = 0, f1 = 0, n = 0, j = 0, u = 0, g = 0, vh = 0, H = 0, Nf = 0, Tloc = 0, gfac = 0;
     size_t wxf = 0, wxi = 0, wyf = 0, wyi = 0, wzf = 0, wzi = 0, S = 0, s1 = 0, s2 = 0, tail = 0;
     size_t series = 0, series_cnt = 0;
 };
@@ -375,6 +375,7 @@ bool plan_batch(Batch &B, const mlb_params *params, int count, std::string &why)
             S.s1 = take(sizeof(float) * 2 * fields * Sp);
             S.s2 = take(sizeof(float) * 2 * fields * Sp);
             S.tail = take(sizeof(float) * 3 * M * N);
+            S.gfac = take(sizeof(float) * M * N);
         }
         S.series = take(sizeof(double) * 2 * kSeriesCap);
         S.series_cnt = take(sizeof(int));
@@ -406,6 +407,9 @@ void fill_desc(Batch &B, int k, mlb::SysDesc<T> &D)
     D.Nf = reinterpret_cast<T *>(ws + S.Nf);
     D.Tloc = B.tiled ? reinterpret_cast<T *>(ws + S.Tloc) : nullptr;
     D.tail = S.spectral ? reinterpret_cast<T *>(ws + S.tail) : nullptr;
+    // tiled float32: the spectral field runs beside contact values and the first gather
+    D.tail_deferred = (S.spectral && B.tiled) ? 1 : 0;
+    D.gfac = D.tail_deferred ? reinterpret_cast<T *>(ws + S.gfac) : nullptr;
     D.parts = nullptr;
     D.parts_mask = 0;
     D.tail_direct = S.spectral ? 0 : 1;
@@ -623,6 +627,31 @@ void run_passes(Batch &B, hipStream_t st, bool query, int qk, int force_only)
     pass(B, kPassMoments, st, [&] { mlb::Launch<T>::moments(sys, smap, nsite, par, st); });
     bool spectral = false;
     for (int k = 0; k < B.count; ++k) spectral = spectral || ((!query || k == qk) && B.sys[k].spectral);
+    if constexpr (std::is_same<T, float>::value) {
+        if (spectral && B.side && B.tiled) {
+            // the spectral field needs only the densities and enters through
+            // H and V-hat: it runs on the side stream beside contact values and
+            // the first gather, and k_add_tail folds it in before the second
+            const int shape = B.tune.shape;
+            const int2 *tmap = query ? B.map_of(B.map_ident) : B.map_of(B.map_tile);
+            const int ntl = query ? mlb::tile_count(shape, B.sys[qk].p.nx, B.sys[qk].p.ny, B.sys[qk].p.nz)
+                                  : B.nblk_tile;
+            (void)hipEventRecord(B.ev_fork, st);
+            (void)hipStreamWaitEvent(B.side, B.ev_fork, 0);
+            for (int k = 0; k < B.count; ++k)
+                if ((!query || k == qk) && B.sys[k].spectral)
+                    pass(B, kPassTail, B.side, [&] { run_tail(B, B.sys[k], B.side); });
+            (void)hipEventRecord(B.ev_join, B.side);
+            pass(B, kPassContact, st, [&] { mlb::Launch<T>::contact(sys, smap, nsite, tb, st); });
+            pass(B, kPassGather1, st,
+                 [&] { mlb::launch_gather1_tile(shape, sys, tmap, ntl, M, tb, B.reach_max, B.sh_max, st); });
+            (void)hipStreamWaitEvent(st, B.ev_join, 0);
+            pass(B, kPassTail, st, [&] { mlb::Launch<T>::add_tail(sys, smap, nsite, M, st); });
+            pass(B, kPassStep2, st,
+                 [&] { mlb::launch_step2_tile(shape, sys, tmap, ntl, M, tb, B.reach_max, B.sh_max, par, force_only, st); });
+            return;
+        }
+    }
     if (spectral && B.side) {
         // contact values and the spectral field both need only the moments:
         // contact runs on the side stream, joined before the first gather

@@ -242,10 +242,11 @@ __global__ void __launch_bounds__(kBlock) k_gather1_tile(const SysDesc<float> *_
             if (S.parts) S.parts[o3 + d * N + s] = 0.f;
         }
         for (int d = 0; d < 6; ++d) Tout[d * N + s] = 0.f;
+        if (S.tail_deferred) S.gfac[(long long)a * N + s] = 0.f;
         return;
     }
     float tl0 = 0.f, tl1 = 0.f, tl2 = 0.f;
-    if (S.tail) {
+    if (S.tail && !S.tail_deferred) {
         tl0 = S.tail[o3 + s]; tl1 = S.tail[o3 + N + s]; tl2 = S.tail[o3 + 2 * N + s];
     }
     const float mfv[3] = {mf0, mf1, mf2}, tlv[3] = {tl0, tl1, tl2}, jav[3] = {ja0, ja1, ja2};
@@ -253,6 +254,7 @@ __global__ void __launch_bounds__(kBlock) k_gather1_tile(const SysDesc<float> *_
     const float Tj[3] = {T00 * ja0 + T01 * ja1 + T02 * ja2, T01 * ja0 + T11 * ja1 + T12 * ja2,
                          T02 * ja0 + T12 * ja1 + T22 * ja2};
     const float hg = 0.5f * gam;
+    if (S.tail_deferred) S.gfac[(long long)a * N + s] = (na != 0.f) ? 1.f / (1.f + hg) : 0.f;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const float Nmf = na * mfv[d], Ntl = na * tlv[d], Nex = na * S.fext[a][d];

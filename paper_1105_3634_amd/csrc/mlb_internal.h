@@ -42,8 +42,10 @@ struct SysDesc {
     T *tail;                         // attractive field sum_b K_ab * n_b [M][3][N] (spectral mode)
     T *parts;                        // optional force-part accumulator [M][3][N] (forces query)
     T *Tloc;                         // local friction tensor sum_b ck Ts_b [M][6][N] (tiled path)
+    T *gfac;                         // 1 / (1 + Gamma_a / 2) per species-site when the tail is deferred [M][N]
     unsigned parts_mask;
     int tail_direct;                 // 1: direct tail sum in the first gather
+    int tail_deferred;               // 1: the first gather leaves the spectral tail out; k_add_tail adds it
     int scheme;
     int omega_is_one;
     // stencils: indices into the batch-wide tables
@@ -100,6 +102,8 @@ struct Launch {
                       int parity, int write_force_only, hipStream_t st);
     // collision + streaming with the given force S.Nf
     static void collide(const SysDesc<T> *sys, const int2 *map, int nblk, int maxM, int parity, hipStream_t st);
+    // the deferred spectral tail: H += n_a C_a, V-hat += C_a / (1 + Gamma_a / 2)
+    static void add_tail(const SysDesc<T> *sys, const int2 *map, int nblk, int maxM, hipStream_t st);
     static void init_pop(const SysDesc<T> *sys, const int2 *map, int nblk, const double *n0,
                          const double *u0, hipStream_t st);
 };

@@ -449,6 +449,35 @@ __global__ void __launch_bounds__(kBlock) k_collide(const SysDesc<T> *__restrict
     }
 }
 
+// The attractive field computed beside the first gather (tiled float32
+// path): its contribution N_tail = n_a C_a enters the predictor-time force
+// H and, through N^c, the predictor V-hat = (... + N^c ...) / (n_a (1 + Gamma_a / 2)).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_add_tail(const SysDesc<T> *__restrict__ sys,
+                                                     const int2 *__restrict__ bmap)
+{
+    const int2 bm = bmap[blockIdx.x];
+    if (bm.x < 0) return;
+    const SysDesc<T> &S = sys[bm.x];
+    const int a = blockIdx.y;
+    if (a >= S.M || !S.tail_deferred) return;
+    const long long s = (long long)bm.y * kBlock + threadIdx.x;
+    if (s >= S.N) return;
+    const long long N = S.N;
+    const Site r = site_of(S, s);
+    if (is_solid(S, r.y)) return;
+    const long long o3 = (long long)a * 3 * N;
+    const T na = S.n[(long long)a * N + s], gf = S.gfac[(long long)a * N + s];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const T c = S.tail[o3 + d * N + s];
+        const T ntl = na * c;
+        S.H[o3 + d * N + s] += ntl;
+        if (S.scheme != 1) S.vh[o3 + d * N + s] += c * gf;
+        if (S.parts && (S.parts_mask & 2u)) S.parts[o3 + d * N + s] += ntl;
+    }
+}
+
 // ------------------------------------------------------- initial populations
 // f = psi_perp(n0, n0 u0, u) at fluid sites (float64 inputs), zero on walls.
 template <typename T>
@@ -525,6 +554,11 @@ template <typename T>
 void Launch<T>::collide(const SysDesc<T> *sys, const int2 *map, int nblk, int maxM, int parity, hipStream_t st)
 {
     hipLaunchKernelGGL(k_collide<T>, dim3(nblk, maxM), dim3(kBlock), 0, st, sys, map, parity);
+}
+template <typename T>
+void Launch<T>::add_tail(const SysDesc<T> *sys, const int2 *map, int nblk, int maxM, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_add_tail<T>, dim3(nblk, maxM), dim3(kBlock), 0, st, sys, map);
 }
 template <typename T>
 void Launch<T>::init_pop(const SysDesc<T> *sys, const int2 *map, int nblk, const double *n0,
