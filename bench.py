@@ -337,14 +337,22 @@ def main():
     g = mlb.GpuMixture(mix, n0, u0, precision=32, tail_mode=tail_mode, device="cuda:0", options=mlb.OPT_TUNE)
     g.step(args.warmup)
     torch.cuda.synchronize()
-    g.profile_begin()
-    torch.cuda.synchronize()
+    # timed region: the steps as mlb_step runs them (pairs replayed from the
+    # captured hipGraph), inputs resident in HBM
     t0 = time.perf_counter()
     g.step(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    passes = g.profile_end()
     elapsed = t1 - t0
+    # per-pass durations: the same number of steps again, launched eagerly
+    # with a HIP event pair around every pass on the stream it runs on
+    g.profile_begin()
+    torch.cuda.synchronize()
+    te0 = time.perf_counter()
+    g.step(args.steps)
+    torch.cuda.synchronize()
+    eager_ms = (time.perf_counter() - te0) * 1e3 / args.steps
+    passes = g.profile_end()
     mass, _ = g.conserved()
     if not np.all(np.isfinite(mass)):
         raise RuntimeError("non-finite state after the timed steps")
@@ -380,6 +388,10 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
                      "traffic_algorithmic": bytes_[dom], "flop_per_launch": flops[dom],
                      "avg_launch_ms": avg_ms[dom]},
+        "timing": "value and ms_per_step: the timed steps replayed from the captured hipGraph (the default "
+                  "mlb_step path); avg_launch_ms and passes_ms_per_step: HIP events around every pass over a "
+                  "second run of the same number of steps with eager launches (eager_ms_per_step)",
+        "eager_ms_per_step": eager_ms,
         "hbm_gbs_algorithmic": total_bytes / elapsed / 1e9,
         "passes_ms_per_step": {k: v[0] / args.steps for k, v in passes.items()},
         "tuning": tune,

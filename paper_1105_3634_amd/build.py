@@ -22,6 +22,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics", "-Wno-unused-command-line-argument",
           f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
+# extra compiler flags (e.g. -D tuning macros), space separated
+COMMON += os.environ.get("MLB_HIPFLAGS", "").split()
 
 # (source, extra flags)
 UNITS = [
