@@ -389,8 +389,10 @@ def main():
                      "traffic_algorithmic": bytes_[dom], "flop_per_launch": flops[dom],
                      "avg_launch_ms": avg_ms[dom]},
         "timing": "value and ms_per_step: the timed steps replayed from the captured hipGraph (the default "
-                  "mlb_step path); avg_launch_ms and passes_ms_per_step: HIP events around every pass over a "
-                  "second run of the same number of steps with eager launches (eager_ms_per_step)",
+                  "mlb_step path, spectral tail overlapping contact values and the first gather on a second "
+                  "stream); avg_launch_ms and passes_ms_per_step: HIP events around every pass over a second "
+                  "run of the same number of steps, launched eagerly with the passes serialised "
+                  "(eager_ms_per_step)",
         "eager_ms_per_step": eager_ms,
         "hbm_gbs_algorithmic": total_bytes / elapsed / 1e9,
         "passes_ms_per_step": {k: v[0] / args.steps for k, v in passes.items()},

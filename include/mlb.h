@@ -183,7 +183,10 @@ mlb_status mlb_get_series(mlb_mixture h, double *t, double *v, int32_t capacity,
  * then turns profiling off.  Pass order: moments, contact values, spectral
  * tail, first gather, second gather + collision + streaming, closure
  * network (with a closure attached; its steps time their collision and
- * streaming under pass 4). */
+ * streaming under pass 4).  While profiling, the passes run one after the
+ * other on `stream` (outside profiling the spectral tail overlaps the
+ * contact values and the first gather on a second stream), and steps
+ * launch eagerly. */
 #define MLB_NPASS 6
 mlb_status mlb_profile_begin(mlb_mixture h);
 mlb_status mlb_profile_end(mlb_mixture h, double *ms, int32_t *launches, void *stream);

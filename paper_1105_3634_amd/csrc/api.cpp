@@ -64,7 +64,7 @@ struct HostTables {
     int tl_start[mlb::kMaxS][mlb::kMaxS] = {}, tl_cnt[mlb::kMaxS][mlb::kMaxS] = {};
     int bl_start[mlb::kMaxS] = {}, bl_cnt[mlb::kMaxS] = {}, bl_full[mlb::kMaxS] = {};
     int reach[3] = {0, 0, 0};
-    int shell_reach = 0;
+    int shell_reach = 0, ball_reach = 0;
 };
 
 bool validate(const mlb_params *p, std::string &why)
@@ -104,6 +104,7 @@ bool build_tables(const mlb_params *p, HostTables &t, std::string &why)
         t.bl_cnt[c] = (int)b.e.size();
         t.bl_full[c] = b.full;
         t.bl_e.insert(t.bl_e.end(), b.e.begin(), b.e.end());
+        for (int d = 0; d < 3; ++d) t.ball_reach = std::max(t.ball_reach, b.max_abs[d]);
         reach(b);
     }
     for (int a = 0; a < M; ++a)
@@ -199,7 +200,7 @@ mlb_status set_error(mlb_status st, const std::string &msg) { return fail(st, ms
 
 // ---------------------------------------------------------------- the core
 struct mlb_batch_s {
-    int count = 0, prec = 32, maxM = 1, reach_max = 0, sh_max = 1;
+    int count = 0, prec = 32, maxM = 1, reach_max = 0, sh_max = 1, ball_reach_max = 0, ball_total_max = 1;
     bool tiled = false;
     std::vector<SysHost> sys;
     char *ws = nullptr;
@@ -301,12 +302,15 @@ bool plan_batch(Batch &B, const mlb_params *params, int count, std::string &why)
         any_direct_tail = any_direct_tail || (has_tail(S.tabs) && !S.spectral);
         B.maxM = std::max(B.maxM, S.M);
         B.reach_max = std::max(B.reach_max, S.tabs.shell_reach);
+        B.ball_reach_max = std::max(B.ball_reach_max, S.tabs.ball_reach);
+        B.ball_total_max = std::max(B.ball_total_max, (int)S.tabs.bl_e.size());
         for (int a = 0; a < S.M; ++a)
             for (int b = 0; b < S.M; ++b) B.sh_max = std::max(B.sh_max, S.tabs.sh_cnt[a][b]);
     }
     bool fits = true;
     for (int v = 0; v < mlb::kTileVariants; ++v)
-        fits = fits && mlb::tile_lds_bytes_of(v, B.reach_max, B.sh_max) <= 160 * 1024;
+        fits = fits && mlb::tile_lds_bytes_of(v, B.reach_max, B.sh_max) <= 160 * 1024 &&
+               mlb::contact_lds_bytes_of(v, B.ball_reach_max, B.ball_total_max, B.maxM) <= 160 * 1024;
     B.tiled = B.prec == 32 && !any_direct_tail && fits;
     const size_t ts = tsize_of(B.prec);
     // kernels index the descriptor array with the struct's own stride
@@ -394,6 +398,8 @@ void fill_desc(Batch &B, int k, mlb::SysDesc<T> &D)
     D.N = S.N;
     D.nblocks = S.nblocks;
     D.reach = S.tabs.shell_reach;
+    D.ball_reach = S.tabs.ball_reach;
+    D.ball_total = (int)S.tabs.bl_e.size();
     D.sh_max = B.sh_max;
     char *ws = B.ws;
     D.f[0] = reinterpret_cast<T *>(ws + S.f0);
@@ -624,64 +630,97 @@ void run_passes(Batch &B, hipStream_t st, bool query, int qk, int force_only)
     const int2 *smap = query ? B.map_of(B.map_ident) : B.map_of(B.map_site);
     const int nsite = query ? B.sys[qk].nblocks : B.nblk_site;
     const int M = query ? B.sys[qk].M : B.maxM;
+    // float32 LDS tiles: contact values and both gathers share the tile map
+    bool tiled = false;
+    int shape = 0, ntl = 0;
+    const int2 *tmap = nullptr;
+    if constexpr (std::is_same<T, float>::value) {
+        if (B.tiled) {
+            tiled = true;
+            shape = B.tune.shape;
+            tmap = query ? B.map_of(B.map_ident) : B.map_of(B.map_tile);
+            ntl = query ? mlb::tile_count(shape, B.sys[qk].p.nx, B.sys[qk].p.ny, B.sys[qk].p.nz) : B.nblk_tile;
+        }
+    }
+    auto contact = [&](hipStream_t s) {
+        if constexpr (std::is_same<T, float>::value) {
+            if (tiled) {
+                pass(B, kPassContact, s, [&] {
+                    mlb::launch_contact_tile(shape, sys, tmap, ntl, tb, B.ball_reach_max, B.ball_total_max, B.maxM, s);
+                });
+                return;
+            }
+        }
+        pass(B, kPassContact, s, [&] { mlb::Launch<T>::contact(sys, smap, nsite, tb, s); });
+    };
+    auto gathers = [&] {
+        if constexpr (std::is_same<T, float>::value) {
+            if (tiled) {
+                pass(B, kPassGather1, st,
+                     [&] { mlb::launch_gather1_tile(shape, sys, tmap, ntl, M, tb, B.reach_max, B.sh_max, st); });
+                return;
+            }
+        }
+        pass(B, kPassGather1, st, [&] { mlb::Launch<T>::gather1(sys, smap, nsite, M, tb, st); });
+    };
+    auto second = [&] {
+        if constexpr (std::is_same<T, float>::value) {
+            if (tiled) {
+                pass(B, kPassStep2, st, [&] {
+                    mlb::launch_step2_tile(shape, sys, tmap, ntl, M, tb, B.reach_max, B.sh_max, par, force_only, st);
+                });
+                return;
+            }
+        }
+        pass(B, kPassStep2, st, [&] { mlb::Launch<T>::step2(sys, smap, nsite, M, tb, par, force_only, st); });
+    };
+    auto tails = [&](hipStream_t s) {
+        for (int k = 0; k < B.count; ++k)
+            if ((!query || k == qk) && B.sys[k].spectral) pass(B, kPassTail, s, [&] { run_tail(B, B.sys[k], s); });
+    };
+
     pass(B, kPassMoments, st, [&] { mlb::Launch<T>::moments(sys, smap, nsite, par, st); });
     bool spectral = false;
     for (int k = 0; k < B.count; ++k) spectral = spectral || ((!query || k == qk) && B.sys[k].spectral);
-    if constexpr (std::is_same<T, float>::value) {
-        if (spectral && B.side && B.tiled) {
-            // the spectral field needs only the densities and enters through
-            // H and V-hat: it runs on the side stream beside contact values and
-            // the first gather, and k_add_tail folds it in before the second
-            const int shape = B.tune.shape;
-            const int2 *tmap = query ? B.map_of(B.map_ident) : B.map_of(B.map_tile);
-            const int ntl = query ? mlb::tile_count(shape, B.sys[qk].p.nx, B.sys[qk].p.ny, B.sys[qk].p.nz)
-                                  : B.nblk_tile;
-            (void)hipEventRecord(B.ev_fork, st);
-            (void)hipStreamWaitEvent(B.side, B.ev_fork, 0);
-            for (int k = 0; k < B.count; ++k)
-                if ((!query || k == qk) && B.sys[k].spectral)
-                    pass(B, kPassTail, B.side, [&] { run_tail(B, B.sys[k], B.side); });
-            (void)hipEventRecord(B.ev_join, B.side);
-            pass(B, kPassContact, st, [&] { mlb::Launch<T>::contact(sys, smap, nsite, tb, st); });
-            pass(B, kPassGather1, st,
-                 [&] { mlb::launch_gather1_tile(shape, sys, tmap, ntl, M, tb, B.reach_max, B.sh_max, st); });
-            (void)hipStreamWaitEvent(st, B.ev_join, 0);
-            pass(B, kPassTail, st, [&] { mlb::Launch<T>::add_tail(sys, smap, nsite, M, st); });
-            pass(B, kPassStep2, st,
-                 [&] { mlb::launch_step2_tile(shape, sys, tmap, ntl, M, tb, B.reach_max, B.sh_max, par, force_only, st); });
-            return;
-        }
+    // per-pass timing wants each pass alone on the GPU: no side stream then
+    const bool overlap = B.side && !B.profiling;
+    if (spectral && tiled && !overlap) {
+        tails(st);
+        contact(st);
+        gathers();
+        pass(B, kPassTail, st, [&] { mlb::Launch<T>::add_tail(sys, smap, nsite, M, st); });
+        second();
+        return;
     }
-    if (spectral && B.side) {
-        // contact values and the spectral field both need only the moments:
-        // contact runs on the side stream, joined before the first gather
+    if (spectral && tiled) {
+        // the spectral field needs only the densities and enters through H and
+        // V-hat: it runs on the side stream beside contact values and the first
+        // gather, and k_add_tail folds it in before the second gather
         (void)hipEventRecord(B.ev_fork, st);
         (void)hipStreamWaitEvent(B.side, B.ev_fork, 0);
-        pass(B, kPassContact, B.side, [&] { mlb::Launch<T>::contact(sys, smap, nsite, tb, B.side); });
+        tails(B.side);
         (void)hipEventRecord(B.ev_join, B.side);
-        for (int k = 0; k < B.count; ++k)
-            if ((!query || k == qk) && B.sys[k].spectral) pass(B, kPassTail, st, [&] { run_tail(B, B.sys[k], st); });
+        contact(st);
+        gathers();
+        (void)hipStreamWaitEvent(st, B.ev_join, 0);
+        pass(B, kPassTail, st, [&] { mlb::Launch<T>::add_tail(sys, smap, nsite, M, st); });
+        second();
+        return;
+    }
+    if (spectral && overlap) {
+        // contact values and the spectral field both need only the moments
+        (void)hipEventRecord(B.ev_fork, st);
+        (void)hipStreamWaitEvent(B.side, B.ev_fork, 0);
+        contact(B.side);
+        (void)hipEventRecord(B.ev_join, B.side);
+        tails(st);
         (void)hipStreamWaitEvent(st, B.ev_join, 0);
     } else {
-        pass(B, kPassContact, st, [&] { mlb::Launch<T>::contact(sys, smap, nsite, tb, st); });
-        for (int k = 0; k < B.count; ++k)
-            if ((!query || k == qk) && B.sys[k].spectral) pass(B, kPassTail, st, [&] { run_tail(B, B.sys[k], st); });
+        contact(st);
+        tails(st);
     }
-    if constexpr (std::is_same<T, float>::value) {
-        if (B.tiled) {
-            const int shape = B.tune.shape;
-            const int2 *tmap = query ? B.map_of(B.map_ident) : B.map_of(B.map_tile);
-            const int ntl = query ? mlb::tile_count(shape, B.sys[qk].p.nx, B.sys[qk].p.ny, B.sys[qk].p.nz)
-                                  : B.nblk_tile;
-            pass(B, kPassGather1, st,
-                 [&] { mlb::launch_gather1_tile(shape, sys, tmap, ntl, M, tb, B.reach_max, B.sh_max, st); });
-            pass(B, kPassStep2, st,
-                 [&] { mlb::launch_step2_tile(shape, sys, tmap, ntl, M, tb, B.reach_max, B.sh_max, par, force_only, st); });
-            return;
-        }
-    }
-    pass(B, kPassGather1, st, [&] { mlb::Launch<T>::gather1(sys, smap, nsite, M, tb, st); });
-    pass(B, kPassStep2, st, [&] { mlb::Launch<T>::step2(sys, smap, nsite, M, tb, par, force_only, st); });
+    gathers();
+    second();
 }
 
 void step_once(Batch &B, hipStream_t st)
@@ -929,7 +968,8 @@ mlb_status create(Batch &B, const mlb_params *params, int count, void *workspace
         if (!n0[k] || !u0[k]) return fail(MLB_EINVAL, "n0 and u0 are required for every system");
     B.ws = static_cast<char *>(workspace);
     B.use_graph = (options & MLB_OPT_NO_GRAPH) == 0;
-    if (B.tiled && !mlb::tile_prepare(B.reach_max, B.sh_max)) B.tiled = false;
+    if (B.tiled && !mlb::tile_prepare(B.reach_max, B.sh_max, B.ball_reach_max, B.ball_total_max, B.maxM))
+        B.tiled = false;
     TRY(upload_static<T>(B, st));
     if (B.tiled) TRY(set_tiling(B, 0, 1, st));
     for (auto &S : B.sys)

@@ -38,13 +38,13 @@ struct TileGeo {
 };
 
 template <int TX, int TY, int TZ>
-__device__ inline TileGeo tile_geo(const SysDesc<float> &S, int local)
+__device__ inline TileGeo tile_geo(const SysDesc<float> &S, int local, int R)
 {
     TileGeo t;
     const int tx = (S.nx + TX - 1) / TX, ty = (S.ny + TY - 1) / TY;
     const int bx = local % tx, by = (local / tx) % ty, bz = local / (tx * ty);
     t.x0 = bx * TX; t.y0 = by * TY; t.z0 = bz * TZ;
-    t.R = S.reach;
+    t.R = R;
     t.HX = TX + 2 * t.R; t.HY = TY + 2 * t.R; t.HZ = TZ + 2 * t.R;
     t.FS = t.HX * t.HY * t.HZ;
     return t;
@@ -117,6 +117,18 @@ __device__ inline void stage(const SysDesc<float> &S, const TileGeo &t, const St
     }
 }
 
+// One scalar field of the halo tile (zero outside the walls).
+__device__ inline void stage1(const TileGeo &t, const StageLane &l, const int *RowOff, float *dst,
+                              const float *__restrict__ src)
+{
+    const int rows = t.HY * t.HZ;
+    if (l.rstep == 0) return;
+    for (int row = l.row0; row < rows; row += l.rstep) {
+        const int ro = RowOff[row];
+        dst[l.hx + row * t.HX] = ro >= 0 ? src[(unsigned)(ro + l.gx)] : 0.f;
+    }
+}
+
 // Copy the (a,b) half-shell into LDS: TA[k] = (byte offset of e in the
 // float4 field array, e_hat), TB[k] = (ee_xx, ee_xy, ee_xz, ee_yy),
 // TC[k] = (ee_yz, ee_zz, byte offset of e in the float array, unused).
@@ -177,7 +189,7 @@ __global__ void __launch_bounds__(kBlock) k_gather1_tile(const SysDesc<float> *_
     const SysDesc<float> &S = sys[bm.x];
     const int a = blockIdx.y;
     if (a >= S.M) return;
-    const TileGeo t = tile_geo<TX, TY, TZ>(S, bm.y);
+    const TileGeo t = tile_geo<TX, TY, TZ>(S, bm.y, S.reach);
     const TileSite q = tile_site<TX, TY, TZ>(S, t);
     const long long N = S.N;
     const long long o3 = (long long)a * 3 * N;
@@ -293,7 +305,7 @@ __global__ void __launch_bounds__(kBlock) k_step2_tile(const SysDesc<float> *__r
     const SysDesc<float> &S = sys[bm.x];
     const int a = blockIdx.y;
     if (a >= S.M) return;
-    const TileGeo t = tile_geo<TX, TY, TZ>(S, bm.y);
+    const TileGeo t = tile_geo<TX, TY, TZ>(S, bm.y, S.reach);
     const TileSite q = tile_site<TX, TY, TZ>(S, t);
     const long long N = S.N;
     const long long o3 = (long long)a * 3 * N;
@@ -378,6 +390,75 @@ __global__ void __launch_bounds__(kBlock) k_step2_tile(const SysDesc<float> *__r
             fout[(long long)i * N + nbr(S, r, kC[i][0], kC[i][1], kC[i][2])] = fs;
         }
     }
+}
+
+// ---------------------------------------------------------- contact values
+// Same fields as k_contact (ball-smoothed densities -> BMCSL contact values,
+// ball sums in the same order: centre, then each (+e, -e) pair of the
+// half-list); the densities of every species are staged for the tile plus a
+// halo of the ball reach.  LDS: M float arrays, the ball half-lists of all
+// species (index offsets), the row-offset table.
+template <int TX, int TY, int TZ>
+__global__ void __launch_bounds__(kBlock) k_contact_tile(const SysDesc<float> *__restrict__ sys,
+                                                         const int2 *__restrict__ bmap, Tables<float> tb)
+{
+    extern __shared__ float4 lds[];
+    static_assert(TX * TY * TZ == kBlock, "one thread per tile site");
+    const int2 bm = bmap[blockIdx.x];
+    if (bm.x < 0) return;
+    const SysDesc<float> &S = sys[bm.x];
+    const TileGeo t = tile_geo<TX, TY, TZ>(S, bm.y, S.ball_reach);
+    const TileSite q = tile_site<TX, TY, TZ>(S, t);
+    const long long N = S.N;
+    float *Ln = reinterpret_cast<float *>(lds);
+    int *Off = reinterpret_cast<int *>(Ln + S.M * t.FS);
+    int *RowOff = Off + S.ball_total;
+    const StageLane sl = stage_lane(S, t);
+    fill_rows(S, t, RowOff);
+    const int kb = S.bl_start[0];
+    for (int k = threadIdx.x; k < S.ball_total; k += kBlock) {
+        int ex, ey, ez;
+        unpack_offset(tb.bl_e[kb + k], ex, ey, ez);
+        Off[k] = ex + ey * t.HX + ez * t.HX * t.HY;
+    }
+    __syncthreads();
+    for (int c = 0; c < S.M; ++c) stage1(t, sl, RowOff, Ln + c * t.FS, S.n + (long long)c * N);
+    __syncthreads();
+    if (!q.active) return;
+    const long long s = q.s;
+    if (S.walls && (q.y == 0 || q.y == S.ny - 1)) {
+        for (int p = 0; p < S.P; ++p) S.g[(long long)p * N + s] = 0.f;
+        return;
+    }
+    float nb[kMaxS];
+    for (int c = 0; c < S.M; ++c) {
+        const float *L = Ln + c * t.FS + q.c;
+        float acc = L[0];
+        const int k0 = S.bl_start[c] - kb, kn = S.bl_cnt[c];
+        for (int k = 0; k < kn; ++k) {
+            const int o = Off[k0 + k];
+            acc = acc + (L[o] + L[-o]);
+        }
+        nb[c] = acc / (float)S.bl_full[c];
+    }
+    float x2 = S.s2[0] * nb[0], x3 = S.s3[0] * nb[0];
+    for (int c = 1; c < S.M; ++c) {
+        x2 = x2 + S.s2[c] * nb[c];
+        x3 = x3 + S.s3[c] * nb[c];
+    }
+    const float qf = 1.f / (1.f - x3);
+    for (int a = 0; a < S.M; ++a)
+        for (int b = a; b < S.M; ++b) {
+            const float z = (S.dd[a][b] * x2) * qf;
+            S.g[(long long)pidx(S.M, a, b) * N + s] = qf * ((1.f + z) * (1.f + 2.f * z));
+        }
+}
+
+inline size_t contact_lds_bytes(int TX, int TY, int TZ, int R, int ball_total, int maxM)
+{
+    const size_t FS = (size_t)(TX + 2 * R) * (TY + 2 * R) * (TZ + 2 * R);
+    const size_t rows = (size_t)(TY + 2 * R) * (TZ + 2 * R);
+    return 4 * ((size_t)maxM * FS + (size_t)ball_total + rows);
 }
 
 // float4 + float per staged site, the shell table (48 bytes per entry),

@@ -36,6 +36,8 @@ struct SysDesc {
     long long N;
     int nblocks;                     // per-site blocks of this system (ceil(N / kBlock))
     int reach;                       // largest |component| of any shell offset
+    int ball_reach;                  // largest |component| of any smoothing-ball offset
+    int ball_total;                  // entries of this system's ball half-lists (all species)
     int sh_max;                      // longest half-shell of the launch (LDS table slots)
     T *f[2];                         // population double buffer [M][19][N]
     T *n, *j, *u, *g, *vh, *H, *Nf;  // fields (see mlb.h for layouts)
@@ -116,9 +118,14 @@ void launch_gather1_tile(int v, const SysDesc<float> *sys, const int2 *map, int 
                          int reach_max, int sh_max, hipStream_t st);
 void launch_step2_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM, Tables<float> tb,
                        int reach_max, int sh_max, int parity, int write_force_only, hipStream_t st);
+// contact values on the same tiles (halo = ball reach), one thread per site
+void launch_contact_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, Tables<float> tb,
+                         int ball_reach_max, int ball_total_max, int maxM, hipStream_t st);
 int tile_count(int v, int nx, int ny, int nz);
-bool tile_prepare(int reach_max, int sh_max);   // raise the dynamic-LDS limit; false if it cannot fit
+// raise the dynamic-LDS limits; false if a kernel cannot fit
+bool tile_prepare(int reach_max, int sh_max, int ball_reach_max, int ball_total_max, int maxM);
 size_t tile_lds_bytes_of(int v, int reach, int sh_max);
+size_t contact_lds_bytes_of(int v, int ball_reach, int ball_total, int maxM);
 
 // float64 reductions (reduce.hip)
 void launch_conserved(const void *n, const void *j, int prec, int M, long long N, double *partials,

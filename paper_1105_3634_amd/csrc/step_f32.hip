@@ -28,25 +28,48 @@ size_t tile_lds_bytes_of(int v, int reach, int sh_max)
     return tile_lds_bytes(tx, ty, tz, reach, sh_max);
 }
 
+size_t contact_lds_bytes_of(int v, int ball_reach, int ball_total, int maxM)
+{
+    int tx, ty, tz;
+    tile_dims(v, tx, ty, tz);
+    if (tx + 2 * ball_reach > kBlock) return SIZE_MAX;
+    return contact_lds_bytes(tx, ty, tz, ball_reach, ball_total, maxM);
+}
+
 namespace {
 template <int TX, int TY, int TZ>
-bool prepare_one(int reach, int sh_max)
+bool prepare_one(int reach, int sh_max, int ball_reach, int ball_total, int maxM)
 {
     const size_t bytes = tile_lds_bytes(TX, TY, TZ, reach, sh_max);
-    if (bytes > 160 * 1024) return false;
-    if (TX + 2 * reach > kBlock) return false;   // staging gives each thread one halo column
+    const size_t cbytes = contact_lds_bytes(TX, TY, TZ, ball_reach, ball_total, maxM);
+    if (bytes > 160 * 1024 || cbytes > 160 * 1024) return false;
+    // staging gives each thread one halo column
+    if (TX + 2 * reach > kBlock || TX + 2 * ball_reach > kBlock) return false;
     if (hipFuncSetAttribute((const void *)k_gather1_tile<TX, TY, TZ>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)bytes) != hipSuccess)
+        return false;
+    if (hipFuncSetAttribute((const void *)k_contact_tile<TX, TY, TZ>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)cbytes) != hipSuccess)
         return false;
     return hipFuncSetAttribute((const void *)k_step2_tile<TX, TY, TZ>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)bytes) == hipSuccess;
 }
 }  // namespace
 
-bool tile_prepare(int reach_max, int sh_max)
+bool tile_prepare(int reach_max, int sh_max, int ball_reach_max, int ball_total_max, int maxM)
 {
-    return prepare_one<16, 4, 4>(reach_max, sh_max) && prepare_one<8, 8, 4>(reach_max, sh_max) &&
-           prepare_one<32, 4, 2>(reach_max, sh_max);
+    return prepare_one<16, 4, 4>(reach_max, sh_max, ball_reach_max, ball_total_max, maxM) &&
+           prepare_one<8, 8, 4>(reach_max, sh_max, ball_reach_max, ball_total_max, maxM) &&
+           prepare_one<32, 4, 2>(reach_max, sh_max, ball_reach_max, ball_total_max, maxM);
+}
+
+void launch_contact_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, Tables<float> tb,
+                         int ball_reach_max, int ball_total_max, int maxM, hipStream_t st)
+{
+    const size_t lds = contact_lds_bytes_of(v, ball_reach_max, ball_total_max, maxM);
+    if (v == 0) hipLaunchKernelGGL((k_contact_tile<16, 4, 4>), dim3(nblk), dim3(kBlock), lds, st, sys, map, tb);
+    else if (v == 1) hipLaunchKernelGGL((k_contact_tile<8, 8, 4>), dim3(nblk), dim3(kBlock), lds, st, sys, map, tb);
+    else hipLaunchKernelGGL((k_contact_tile<32, 4, 2>), dim3(nblk), dim3(kBlock), lds, st, sys, map, tb);
 }
 
 void launch_gather1_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM, Tables<float> tb,
