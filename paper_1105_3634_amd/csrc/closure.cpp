@@ -174,6 +174,7 @@ mlb_status mlb_net_create(int32_t nx, int32_t ny, int32_t nz, int32_t training, 
     if (!workspace || workspace_bytes < tmp.total)
         return mlb::set_error(MLB_EINVAL, "network workspace missing or too small (need " +
                                               std::to_string(tmp.total) + " bytes)");
+    if (!mlb::cnn_prepare()) return mlb::set_error(MLB_EHIP, "cannot raise the LDS limit of the convolution kernels");
     auto *n = new mlb_net_s(tmp);
     n->ws = static_cast<char *>(workspace);
     hipStream_t st = static_cast<hipStream_t>(stream);

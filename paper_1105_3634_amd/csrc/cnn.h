@@ -23,6 +23,8 @@ inline int net_cop(int l) { return l == 3 ? 16 : 32; }
 inline int net_cin(int l) { return l == 0 ? kNetIn : kNetHidden; }
 inline int net_cout(int l) { return l == 3 ? kNetOut : kNetHidden; }
 
+// raise the dynamic-LDS limit of the convolution kernels (once per process)
+bool cnn_prepare();
 // z (float32, may be null) = conv(in) + b; a (bf16, may be null) = act ? silu(z) : z
 void cnn_conv_fwd(int layer, const CnnShape &sh, const unsigned short *in, const unsigned short *W, const float *b,
                   float *z, unsigned short *a, int act, hipStream_t st);

@@ -8,7 +8,10 @@
 //
 // Layout: activations channel-last [site][C] (C padded to a multiple of
 // 16), weights [tap][C_out][C_in] in bfloat16, accumulation in float32 on
-// the matrix cores (v_mfma_f32_16x16x16bf16_1k: 16 x 16 x 16 per wave).
+// the matrix cores.  Forward and data-gradient convolutions run on LDS
+// tiles with v_mfma_f32_16x16x32_bf16 (k_conv_tile); the weight gradient
+// contracts over sites with v_mfma_f32_16x16x16bf16_1k (k_conv_wgrad).
+// 16 x 16 output blocks: D[4g + v][j] in lane j + 16g, element v.
 //
 // The first layer runs in split bfloat16: every input value x is carried as
 // hi = bf16(x) and lo = bf16(x - hi), every weight w as hi and lo the same
@@ -18,8 +21,6 @@
 // force is a spatial derivative of fields whose local values it barely
 // changes; with 8-bit inputs or first-layer weights the rounding of the
 // undifferentiated part would swamp it.
-// Lane layout (one block): A[i][4g .. 4g+3] in lane i + 16g, B[4g .. 4g+3][j]
-// in lane j + 16g, D[4g + v][j] in lane j + 16g, element v.
 //
 // Kernels: convolution forward (bias, optional SiLU, stores the
 // pre-activation for the backward pass), data gradient (transposed
@@ -30,6 +31,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "cnn.h"
 
@@ -38,14 +40,8 @@ namespace mlb {
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-__device__ inline unsigned short f2bf(float f)
-{
-    // round to nearest even
-    unsigned int u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);   // inf / nan
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
-}
+// float -> bfloat16, round to nearest even (v_cvt_pk_bf16_f32)
+__device__ inline unsigned short f2bf(float f) { return __builtin_bit_cast(unsigned short, (__bf16)f); }
 __device__ inline float bf2f(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
 
 __device__ inline float sigm(float z) { return 1.f / (1.f + __expf(-z)); }
@@ -63,109 +59,230 @@ __device__ inline long long shift_site(const Grid3 &g, int x, int y, int z, int 
     return ((long long)zz * g.ny + yy) * g.nx + xx;
 }
 
-// ------------------------------------------------------------ forward
-// out[s][co] = b[co] + sum_t sum_ci W[t][co][ci] in[s + d_t][ci]
-// Block: 4 waves x 64 sites; each wave: COP/16 channel blocks x 4 site blocks.
-template <int CIP, int COP>
-__global__ void __launch_bounds__(256) k_conv_fwd(Grid3 g, long long N, const unsigned short *__restrict__ in,
-                                                 const unsigned short *__restrict__ W, const float *__restrict__ bias,
-                                                 float *__restrict__ zout, unsigned short *__restrict__ aout, int act)
+// --------------------------------------------- tiled convolution (LDS)
+// out[s][o] = sum_t sum_k W[t][o][k] in[s + SGN d_t][k]   (k < KIN, o < OUT)
+//   forward (SGN = +1, EPI 0): W = weights [t][co][ci]; z = acc + b -> zout
+//     (float32, optional), aout = act ? silu(z) : z (bf16, optional)
+//   data gradient (SGN = -1, EPI 1): W = transposed weights [t][ci][co];
+//     gin = acc * silu'(zin) (bf16)
+// Persistent blocks (one per CU) walk 16 x 8 x 4 tiles; within a tile wave w
+// owns the plane z0 + w as 8 rows of 16 consecutive x (one MFMA site block
+// per row) and all OUT channels (16 independent accumulators for OUT = 32).
+// The layer's weights are staged in LDS once per block; each tile with a
+// one-cell halo (18 x 10 x 6 sites) is loaded into registers while the
+// previous tile computes, then stored to LDS.  Both are chunk-major: [channel chunk][site] and
+// [channel chunk][weight row], a chunk being the CW = KIN / 2 bytes one lane
+// feeds to one MFMA, so the 16 lanes of a site block read 16 consecutive
+// chunks.
+// KIN = 32: v_mfma_f32_16x16x32_bf16, lane j + 16 g holds channels
+// 8g..8g+7 of both operands (any fixed lane -> channel assignment shared by
+// the two operands gives the same sum); KIN = 16: v_mfma_f32_16x16x16bf16_1k
+// with channels 4g..4g+3.
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int kCTX = 16, kCTY = 8, kCTZ = 4;
+constexpr int kCHX = kCTX + 2, kCHY = kCTY + 2, kCHZ = kCTZ + 2;
+constexpr int kCHS = kCHX * kCHY * kCHZ;
+constexpr int kCRows = kCHY * kCHZ;
+
+__host__ __device__ constexpr int conv_lds(int kin, int out)
 {
-    constexpr int CB = COP / 16, KB = CIP / 16;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, gq = lane >> 4;
-    const long long s0 = (long long)blockIdx.x * 256 + wave * 64;
-    int sx[4], sy[4], sz[4];
-    bool ok[4];
-    for (int sb = 0; sb < 4; ++sb) {
-        const long long s = s0 + sb * 16 + li;
-        ok[sb] = s < N;
-        const long long ss = ok[sb] ? s : 0;
-        sx[sb] = (int)(ss % g.nx);
-        sy[sb] = (int)((ss / g.nx) % g.ny);
-        sz[sb] = (int)(ss / ((long long)g.nx * g.ny));
-    }
-    v4f acc[CB][4];
-    for (int c = 0; c < CB; ++c)
-        for (int sb = 0; sb < 4; ++sb) acc[c][sb] = v4f{0.f, 0.f, 0.f, 0.f};
-    for (int t = 0; t < 27; ++t) {
-        const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-        long long nb[4];
-        for (int sb = 0; sb < 4; ++sb) nb[sb] = shift_site(g, sx[sb], sy[sb], sz[sb], dx, dy, dz);
-        for (int kb = 0; kb < KB; ++kb) {
-            v4s a[CB], b[4];
-            for (int c = 0; c < CB; ++c)
-                a[c] = *reinterpret_cast<const v4s *>(W + ((long long)t * COP + c * 16 + li) * CIP + kb * 16 + 4 * gq);
-            for (int sb = 0; sb < 4; ++sb)
-                b[sb] = *reinterpret_cast<const v4s *>(in + nb[sb] * CIP + kb * 16 + 4 * gq);
-            for (int c = 0; c < CB; ++c)
-                for (int sb = 0; sb < 4; ++sb)
-                    acc[c][sb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[c], b[sb], acc[c][sb], 0, 0, 0);
-        }
-    }
-    for (int c = 0; c < CB; ++c)
-        for (int sb = 0; sb < 4; ++sb) {
-            if (!ok[sb]) continue;
-            const long long s = s0 + sb * 16 + li;
-            for (int v = 0; v < 4; ++v) {
-                const int co = c * 16 + 4 * gq + v;
-                const float z = acc[c][sb][v] + bias[co];
-                if (zout) zout[s * COP + co] = z;
-                const float av = act ? z * sigm(z) : z;
-                if (aout) aout[s * COP + co] = f2bf(av);
-            }
-        }
+    return 4 * kCHS * (kin / 2) + 4 * 27 * out * (kin / 2) + 2 * 4 * kCRows;
 }
 
-// ------------------------------------------------------- data gradient
-// gin[s][ci] = (sum_t sum_co W[t][co][ci] gout[s - d_t][co]) * silu'(zin[s][ci])
-// WT = weights transposed to [t][ci][co].
-template <int CIP, int COP>
-__global__ void __launch_bounds__(256) k_conv_dgrad(Grid3 g, long long N, const unsigned short *__restrict__ gout,
-                                                   const unsigned short *__restrict__ WT,
-                                                   const float *__restrict__ zin, unsigned short *__restrict__ gin)
+__device__ inline int wrap_cell(int v, int n)
 {
-    constexpr int CB = CIP / 16, KB = COP / 16;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, gq = lane >> 4;
-    const long long s0 = (long long)blockIdx.x * 256 + wave * 64;
-    int sx[4], sy[4], sz[4];
-    bool ok[4];
-    for (int sb = 0; sb < 4; ++sb) {
-        const long long s = s0 + sb * 16 + li;
-        ok[sb] = s < N;
-        const long long ss = ok[sb] ? s : 0;
-        sx[sb] = (int)(ss % g.nx);
-        sy[sb] = (int)((ss / g.nx) % g.ny);
-        sz[sb] = (int)(ss / ((long long)g.nx * g.ny));
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// native vector types (arrays of them stay in registers)
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+typedef unsigned v2u __attribute__((ext_vector_type(2)));
+template <int CW>
+struct Chunk;
+template <>
+struct Chunk<16> {
+    typedef v4u T;
+};
+template <>
+struct Chunk<8> {
+    typedef v2u T;
+};
+
+// Chunks (chunk chk of halo column gx, rows row0 + k RSTEP, k = K0 .. K0 +
+// H - 1) of a tile whose halo rows start at the site offsets RowOff[].  The
+// prefetch buffer is kept as halves of H chunks: the compiler keeps arrays
+// of this size in registers.
+template <int KIN, int H, int K0, int RSTEP>
+__device__ __forceinline__ void conv_fetch(const int *RowOff, unsigned gx, int row0, int chk,
+                                           const unsigned short *__restrict__ in,
+                                           typename Chunk<KIN / 2>::T (&pre)[H])
+{
+    typedef typename Chunk<KIN / 2>::T CT;
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        const unsigned site = (unsigned)RowOff[row0 + (K0 + k) * RSTEP] + gx;
+        pre[k] = *reinterpret_cast<const CT *>(in + site * KIN + chk * (KIN / 4));   // KIN / 4 channels per chunk
     }
-    v4f acc[CB][4];
-    for (int c = 0; c < CB; ++c)
-        for (int sb = 0; sb < 4; ++sb) acc[c][sb] = v4f{0.f, 0.f, 0.f, 0.f};
-    for (int t = 0; t < 27; ++t) {
-        const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-        long long nb[4];
-        for (int sb = 0; sb < 4; ++sb) nb[sb] = shift_site(g, sx[sb], sy[sb], sz[sb], -dx, -dy, -dz);
-        for (int kb = 0; kb < KB; ++kb) {
-            v4s a[CB], b[4];
-            for (int c = 0; c < CB; ++c)
-                a[c] = *reinterpret_cast<const v4s *>(WT + ((long long)t * CIP + c * 16 + li) * COP + kb * 16 + 4 * gq);
-            for (int sb = 0; sb < 4; ++sb)
-                b[sb] = *reinterpret_cast<const v4s *>(gout + nb[sb] * COP + kb * 16 + 4 * gq);
-            for (int c = 0; c < CB; ++c)
-                for (int sb = 0; sb < 4; ++sb)
-                    acc[c][sb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[c], b[sb], acc[c][sb], 0, 0, 0);
-        }
+}
+
+// Site offsets (wrapped z and y, x = 0) of the halo rows of a tile.
+__device__ inline void conv_rows(const Grid3 &g, int ntx, int nty, int tile, int *RowOff)
+{
+    const int y0 = ((tile / ntx) % nty) * kCTY, z0 = (tile / (ntx * nty)) * kCTZ;
+    const int r = threadIdx.x;
+    if (r < kCRows) {
+        const int hy = r % kCHY, hz = r / kCHY;
+        RowOff[r] = (wrap_cell(z0 - 1 + hz, g.nz) * g.ny + wrap_cell(y0 - 1 + hy, g.ny)) * g.nx;
     }
-    for (int c = 0; c < CB; ++c)
-        for (int sb = 0; sb < 4; ++sb) {
-            if (!ok[sb]) continue;
-            const long long s = s0 + sb * 16 + li;
-            for (int v = 0; v < 4; ++v) {
-                const int ci = c * 16 + 4 * gq + v;
-                const float z = zin[s * CIP + ci];
-                const float sg = sigm(z);
-                gin[s * CIP + ci] = f2bf(acc[c][sb][v] * (sg * (1.f + z * (1.f - sg))));
+}
+
+template <int KIN, int OUT, int SGN, int EPI>
+__global__ void __launch_bounds__(256) k_conv_tile(Grid3 g, long long N, const unsigned short *__restrict__ in,
+                                                  const unsigned short *__restrict__ W,
+                                                  const float *__restrict__ bias, const float *__restrict__ zin,
+                                                  float *__restrict__ zout, unsigned short *__restrict__ aout, int act)
+{
+    extern __shared__ __align__(16) unsigned char Ls[];
+    constexpr int CW = KIN / 2, NCH = 4, CB = OUT / 16;       // chunk bytes; 4 chunks per site or weight row
+    constexpr int WROWS = 27 * OUT;
+    constexpr int RSTEP = 256 / (kCHX * NCH);                 // halo rows staged per pass
+    constexpr int MAXK = kCRows / RSTEP;                      // rows per staging thread
+    static_assert(RSTEP * MAXK == kCRows, "staging threads cover the halo rows evenly");
+    typedef typename Chunk<CW>::T CT;
+    constexpr int PI = kCHS * CW, PW = WROWS * CW;             // chunk-plane strides (bytes)
+    unsigned char *Lin = Ls;                                  // [NCH][kCHS][CW]
+    unsigned char *Lwt = Ls + NCH * PI;                       // [NCH][WROWS][CW]
+    int *RowOff = reinterpret_cast<int *>(Lwt + NCH * PW);    // [2][kCRows], by tile parity
+    const int tid = threadIdx.x;
+    const int ntx = (g.nx + kCTX - 1) / kCTX, nty = (g.ny + kCTY - 1) / kCTY, ntz = (g.nz + kCTZ - 1) / kCTZ;
+    const int ntiles = ntx * nty * ntz;
+    // weights once per block
+    {
+        constexpr int WCH = WROWS * NCH;
+#pragma unroll 4
+        for (int i = tid; i < WCH; i += 256)
+            *reinterpret_cast<CT *>(Lwt + (i % NCH) * PW + (i / NCH) * CW) =
+                *reinterpret_cast<const CT *>(W + (long long)i * (CW / 2));
+    }
+    // staging thread = (chunk, halo column), x fastest; rows row0 + k RSTEP
+    const int ch = tid / kCHX, hx = tid % kCHX;
+    const int row0 = ch / NCH, chk = ch % NCH;
+    const bool stager = row0 < RSTEP;
+    auto column = [&](int tile) { return (unsigned)wrap_cell((tile % ntx) * kCTX - 1 + hx, g.nx); };
+    // the next tile's chunks, loaded while the current tile computes
+    constexpr int H = MAXK / 2;
+    static_assert(2 * H == MAXK, "two prefetch halves");
+    CT preA[H], preB[H];
+    if ((int)blockIdx.x < ntiles) conv_rows(g, ntx, nty, blockIdx.x, RowOff);
+    __syncthreads();
+    if (stager && (int)blockIdx.x < ntiles) {
+        const unsigned gx = column(blockIdx.x);
+        conv_fetch<KIN, H, 0, RSTEP>(RowOff, gx, row0, chk, in, preA);
+        conv_fetch<KIN, H, H, RSTEP>(RowOff, gx, row0, chk, in, preB);
+    }
+
+    const int lane = tid & 63, wave = tid >> 6, li = lane & 15, gq = lane >> 4;
+    // halo index of the wave's site (x0 + li, y0 + sb, z0 + wave) is
+    // (li + 1) + (sb + 1) kCHX + (wave + 1) kCHX kCHY; Lb points at sb = 0
+    const unsigned char *Lb = Lin + gq * PI + ((li + 1) + kCHX + (wave + 1) * kCHX * kCHY) * CW;
+    // weight row co = c 16 + li of tap t is chunk row t OUT + co
+    const unsigned char *Wl = Lwt + gq * PW + li * CW;
+    typedef typename std::conditional<KIN == 32, v8bf, v4s>::type OP;
+
+    for (int tile = blockIdx.x, it = 0; tile < ntiles; tile += gridDim.x, ++it) {
+        __syncthreads();   // the previous tile's reads of Lin are done
+        const int next = tile + (int)gridDim.x;
+        int *RowNext = RowOff + ((it + 1) & 1) * kCRows;
+        if (next < ntiles) conv_rows(g, ntx, nty, next, RowNext);
+        if (stager) {
+#pragma unroll
+            for (int k = 0; k < H; ++k) {
+                *reinterpret_cast<CT *>(Lin + chk * PI + (hx + (row0 + k * RSTEP) * kCHX) * CW) = preA[k];
+                *reinterpret_cast<CT *>(Lin + chk * PI + (hx + (row0 + (H + k) * RSTEP) * kCHX) * CW) = preB[k];
             }
         }
+        __syncthreads();
+        if (stager && next < ntiles) {
+            const unsigned gx = column(next);
+            conv_fetch<KIN, H, 0, RSTEP>(RowNext, gx, row0, chk, in, preA);
+            conv_fetch<KIN, H, H, RSTEP>(RowNext, gx, row0, chk, in, preB);
+        }
+
+        v4f acc[CB][kCTY];
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+#pragma unroll
+            for (int sb = 0; sb < kCTY; ++sb) acc[c][sb] = v4f{0.f, 0.f, 0.f, 0.f};
+        OP a[CB], an[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) a[c] = *reinterpret_cast<const OP *>(Wl + c * 16 * CW);
+#pragma unroll
+        for (int t = 0; t < 27; ++t) {
+            const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+            const int off = SGN * (dx + dy * kCHX + dz * kCHX * kCHY);
+            if (t + 1 < 27)
+#pragma unroll
+                for (int c = 0; c < CB; ++c)
+                    an[c] = *reinterpret_cast<const OP *>(Wl + ((t + 1) * OUT + c * 16) * CW);
+            OP b[kCTY];
+#pragma unroll
+            for (int sb = 0; sb < kCTY; ++sb) b[sb] = *reinterpret_cast<const OP *>(Lb + (off + sb * kCHX) * CW);
+#pragma unroll
+            for (int sb = 0; sb < kCTY; ++sb)
+#pragma unroll
+                for (int c = 0; c < CB; ++c) {
+                    if constexpr (KIN == 32)
+                        acc[c][sb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[c], b[sb], acc[c][sb], 0, 0, 0);
+                    else
+                        acc[c][sb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[c], b[sb], acc[c][sb], 0, 0, 0);
+                }
+            if (t + 1 < 27)
+#pragma unroll
+                for (int c = 0; c < CB; ++c) a[c] = an[c];
+        }
+
+        const int x0 = (tile % ntx) * kCTX, y0 = ((tile / ntx) % nty) * kCTY, z0 = (tile / (ntx * nty)) * kCTZ;
+        const int x = x0 + li, z = z0 + wave;
+        if (x >= g.nx || z >= g.nz) continue;
+#pragma unroll
+        for (int sb = 0; sb < kCTY; ++sb) {
+            const int y = y0 + sb;
+            if (y >= g.ny) break;
+            const long long s = ((long long)z * g.ny + y) * g.nx + x;
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                const int o0 = c * 16 + 4 * gq;
+                if constexpr (EPI == 0) {
+                    float zv[4];
+                    unsigned short av[4];
+                    for (int v = 0; v < 4; ++v) {
+                        zv[v] = acc[c][sb][v] + bias[o0 + v];
+                        av[v] = f2bf(act ? zv[v] * sigm(zv[v]) : zv[v]);
+                    }
+                    if (zout)
+                        *reinterpret_cast<float4 *>(zout + s * OUT + o0) = make_float4(zv[0], zv[1], zv[2], zv[3]);
+                    if (aout) {
+                        const uint2 pk = make_uint2((unsigned)av[0] | ((unsigned)av[1] << 16),
+                                                    (unsigned)av[2] | ((unsigned)av[3] << 16));
+                        *reinterpret_cast<uint2 *>(aout + s * OUT + o0) = pk;
+                    }
+                } else {
+                    const float4 zz = *reinterpret_cast<const float4 *>(zin + s * OUT + o0);
+                    const float zi[4] = {zz.x, zz.y, zz.z, zz.w};
+                    unsigned short gv[4];
+                    for (int v = 0; v < 4; ++v) {
+                        const float sg = sigm(zi[v]);
+                        gv[v] = f2bf(acc[c][sb][v] * (sg * (1.f + zi[v] * (1.f - sg))));
+                    }
+                    const uint2 pk = make_uint2((unsigned)gv[0] | ((unsigned)gv[1] << 16),
+                                                (unsigned)gv[2] | ((unsigned)gv[3] << 16));
+                    *reinterpret_cast<uint2 *>(aout + s * OUT + o0) = pk;
+                }
+            }
+        }
+    }
 }
 
 // ----------------------------------------------------- weight gradient
@@ -446,24 +563,61 @@ namespace {
 inline unsigned nblocks(long long n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 }
 
+namespace {
+// persistent grid: one block per compute unit (the LDS footprint allows one)
+unsigned conv_tiles(const CnnShape &sh)
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+            cus = n;
+        else
+            cus = 256;
+    }
+    const long long tiles =
+        (long long)((sh.nx + kCTX - 1) / kCTX) * ((sh.ny + kCTY - 1) / kCTY) * ((sh.nz + kCTZ - 1) / kCTZ);
+    return (unsigned)(tiles < cus ? tiles : cus);
+}
+}  // namespace
+
+bool cnn_prepare()
+{
+    return hipFuncSetAttribute((const void *)k_conv_tile<32, 32, 1, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               conv_lds(32, 32)) == hipSuccess &&
+           hipFuncSetAttribute((const void *)k_conv_tile<32, 16, 1, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               conv_lds(32, 16)) == hipSuccess &&
+           hipFuncSetAttribute((const void *)k_conv_tile<32, 32, -1, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               conv_lds(32, 32)) == hipSuccess &&
+           hipFuncSetAttribute((const void *)k_conv_tile<16, 32, -1, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               conv_lds(16, 32)) == hipSuccess;
+}
+
 void cnn_conv_fwd(int layer, const CnnShape &sh, const unsigned short *in, const unsigned short *W, const float *b,
                   float *z, unsigned short *a, int act, hipStream_t st)
 {
     const Grid3 g{sh.nx, sh.ny, sh.nz};
-    const unsigned nb = nblocks(sh.N);
-    switch (layer) {
-    case 3: hipLaunchKernelGGL((k_conv_fwd<32, 16>), dim3(nb), dim3(256), 0, st, g, sh.N, in, W, b, z, a, act); break;
-    default: hipLaunchKernelGGL((k_conv_fwd<32, 32>), dim3(nb), dim3(256), 0, st, g, sh.N, in, W, b, z, a, act); break;
-    }
+    const unsigned nb = conv_tiles(sh);
+    if (net_cop(layer) == 16)
+        hipLaunchKernelGGL((k_conv_tile<32, 16, 1, 0>), dim3(nb), dim3(256), conv_lds(32, 16), st, g, sh.N, in, W, b,
+                           nullptr, z, a, act);
+    else
+        hipLaunchKernelGGL((k_conv_tile<32, 32, 1, 0>), dim3(nb), dim3(256), conv_lds(32, 32), st, g, sh.N, in, W, b,
+                           nullptr, z, a, act);
 }
 
 void cnn_conv_dgrad(int layer, const CnnShape &sh, const unsigned short *gout, const unsigned short *WT, const float *zin,
                     unsigned short *gin, hipStream_t st)
 {
     const Grid3 g{sh.nx, sh.ny, sh.nz};
-    const unsigned nb = nblocks(sh.N);
-    if (layer == 3) hipLaunchKernelGGL((k_conv_dgrad<32, 16>), dim3(nb), dim3(256), 0, st, g, sh.N, gout, WT, zin, gin);
-    else hipLaunchKernelGGL((k_conv_dgrad<32, 32>), dim3(nb), dim3(256), 0, st, g, sh.N, gout, WT, zin, gin);
+    const unsigned nb = conv_tiles(sh);
+    if (net_cop(layer) == 16)
+        hipLaunchKernelGGL((k_conv_tile<16, 32, -1, 1>), dim3(nb), dim3(256), conv_lds(16, 32), st, g, sh.N, gout, WT,
+                           nullptr, zin, nullptr, gin, 0);
+    else
+        hipLaunchKernelGGL((k_conv_tile<32, 32, -1, 1>), dim3(nb), dim3(256), conv_lds(32, 32), st, g, sh.N, gout, WT,
+                           nullptr, zin, nullptr, gin, 0);
 }
 
 void cnn_conv_wgrad(int layer, const CnnShape &sh, const unsigned short *gout, const unsigned short *ain, float *part,
