@@ -75,14 +75,14 @@ def algorithmic_work(mix, tail_direct: bool):
         "gather1": N * sum(25 * sum(S[a]) + (3.5 * sum(T[a]) if tail_direct else 0) + 40 for a in range(M)),
         "step2": N * sum(14.5 * sum(S[a]) + 30 * 19 for a in range(M)),
     }
-    tail_words = 0 if tail_direct else 3 * M
     bytes_ = {
         # f in; n, j, u out
         "moments": N * w * (19 * M + 4 * M + 3),
         # n in; g out
         "contact": N * w * (M + P),
-        # n, j, g (and the spectral tail) in; V-hat, H, friction tensor out
-        "gather1": N * w * (4 * M + P + tail_words + 12 * M),
+        # n, j, g in; V-hat, H, friction tensor out; with the spectral tail
+        # (folded in afterwards) also 1 / (1 + Gamma / 2) out
+        "gather1": N * w * (4 * M + P + 12 * M + (0 if tail_direct else M)),
         # f, n, V-hat, g, H, friction tensor, j, u in; f out
         "step2": N * w * (19 * M + M + 3 * M + P + 3 * M + 6 * M + 3 * M + 3 + 19 * M),
     }
