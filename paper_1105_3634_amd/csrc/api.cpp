@@ -58,7 +58,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // ----------------------------------------------------------- host tables
 struct HostTables {
     std::vector<int32_t> sh_e, tl_e, bl_e;
-    std::vector<double> sh_u, sh_ee, tl_w;
+    std::vector<double> sh_u, tl_w;
     int sh_start[mlb::kMaxS][mlb::kMaxS] = {}, sh_cnt[mlb::kMaxS][mlb::kMaxS] = {};
     int sh_full[mlb::kMaxS][mlb::kMaxS] = {};
     int tl_start[mlb::kMaxS][mlb::kMaxS] = {}, tl_cnt[mlb::kMaxS][mlb::kMaxS] = {};
@@ -117,11 +117,6 @@ bool build_tables(const mlb_params *p, HostTables &t, std::string &why)
             t.sh_full[a][b] = sh.full;
             t.sh_e.insert(t.sh_e.end(), sh.e.begin(), sh.e.end());
             t.sh_u.insert(t.sh_u.end(), sh.v.begin(), sh.v.end());
-            for (size_t k = 0; k < sh.e.size(); ++k) {
-                const double *u = &sh.v[3 * k];
-                const double ee[6] = {u[0] * u[0], u[0] * u[1], u[0] * u[2], u[1] * u[1], u[1] * u[2], u[2] * u[2]};
-                t.sh_ee.insert(t.sh_ee.end(), ee, ee + 6);
-            }
             for (int d = 0; d < 3; ++d) t.shell_reach = std::max(t.shell_reach, sh.max_abs[d]);
             reach(sh);
             const double eps = p->eps[a * MLB_MAX_SPECIES + b];
@@ -207,7 +202,7 @@ struct mlb_batch_s {
     size_t total = 0;
     // shared regions
     size_t desc = 0, map_site = 0, map_tile = 0, map_ident = 0;
-    size_t t_sh_e = 0, t_sh_u = 0, t_sh_ee = 0, t_tl_e = 0, t_tl_w = 0, t_bl_e = 0;
+    size_t t_sh_e = 0, t_sh_u = 0, t_tl_e = 0, t_tl_w = 0, t_bl_e = 0;
     size_t red = 0, red_out = 0, fit_out = 0;
     size_t desc_size = 0;
     int nblk_site = 0, nblk_tile = 0, ident_len = 0;
@@ -255,7 +250,6 @@ struct mlb_batch_s {
         mlb::Tables<T> tb;
         tb.sh_e = reinterpret_cast<const int32_t *>(ws + t_sh_e);
         tb.sh_u = reinterpret_cast<const T *>(ws + t_sh_u);
-        tb.sh_ee = reinterpret_cast<const T *>(ws + t_sh_ee);
         tb.tl_e = reinterpret_cast<const int32_t *>(ws + t_tl_e);
         tb.tl_w = reinterpret_cast<const T *>(ws + t_tl_w);
         tb.bl_e = reinterpret_cast<const int32_t *>(ws + t_bl_e);
@@ -347,7 +341,6 @@ bool plan_batch(Batch &B, const mlb_params *params, int count, std::string &why)
     }
     B.t_sh_e = take(4 * nsh);
     B.t_sh_u = take(ts * 3 * nsh);
-    B.t_sh_ee = take(ts * 6 * nsh);
     B.t_tl_e = take(4 * ntl);
     B.t_tl_w = take(ts * 3 * ntl);
     B.t_bl_e = take(4 * nbl);
@@ -474,13 +467,12 @@ mlb_status upload_static(Batch &B, hipStream_t st)
 {
     // concatenated tables
     std::vector<int32_t> sh_e, tl_e, bl_e;
-    std::vector<T> sh_u, sh_ee, tl_w;
+    std::vector<T> sh_u, tl_w;
     for (auto &S : B.sys) {
         sh_e.insert(sh_e.end(), S.tabs.sh_e.begin(), S.tabs.sh_e.end());
         tl_e.insert(tl_e.end(), S.tabs.tl_e.begin(), S.tabs.tl_e.end());
         bl_e.insert(bl_e.end(), S.tabs.bl_e.begin(), S.tabs.bl_e.end());
         for (double v : S.tabs.sh_u) sh_u.push_back((T)v);
-        for (double v : S.tabs.sh_ee) sh_ee.push_back((T)v);
         for (double v : S.tabs.tl_w) tl_w.push_back((T)v);
     }
     char *ws = B.ws;
@@ -490,7 +482,6 @@ mlb_status upload_static(Batch &B, hipStream_t st)
     };
     TRY(up(B.t_sh_e, sh_e.data(), 4 * sh_e.size()));
     TRY(up(B.t_sh_u, sh_u.data(), sizeof(T) * sh_u.size()));
-    TRY(up(B.t_sh_ee, sh_ee.data(), sizeof(T) * sh_ee.size()));
     TRY(up(B.t_tl_e, tl_e.data(), 4 * tl_e.size()));
     TRY(up(B.t_tl_w, tl_w.data(), sizeof(T) * tl_w.size()));
     TRY(up(B.t_bl_e, bl_e.data(), 4 * bl_e.size()));

@@ -130,12 +130,11 @@ __device__ inline void stage1(const TileGeo &t, const StageLane &l, const int *R
 }
 
 // Copy the (a,b) half-shell into LDS: TA[k] = (byte offset of e in the
-// float4 field array, e_hat), TB[k] = (ee_xx, ee_xy, ee_xz, ee_yy),
-// TC[k] = (ee_yz, ee_zz, byte offset of e in the float array, unused).
-// Reads of it are wave-uniform broadcasts that share the in-order LDS
-// counter with the field reads, so the pair loop can be software-pipelined.
-__device__ inline void stage_table(const Tables<float> &tb, int k0, int kn, const TileGeo &t, float4 *TA, float4 *TB,
-                                   float4 *TC, bool with_ee)
+// float4 field array, e_hat); the g array's offset is a quarter of it and
+// the tensor e_hat e_hat^T is formed in registers.  Reads of TA are
+// wave-uniform broadcasts; every LDS read costs bandwidth, so the table
+// holds no more than this.
+__device__ inline void stage_table(const Tables<float> &tb, int k0, int kn, const TileGeo &t, float4 *TA)
 {
     const int HXY = t.HX * t.HY;
     for (int k = threadIdx.x; k < kn; k += kBlock) {
@@ -144,11 +143,6 @@ __device__ inline void stage_table(const Tables<float> &tb, int k0, int kn, cons
         const int off = ex + ey * t.HX + ez * HXY;
         const float *u = tb.sh_u + 3 * (k0 + k);
         TA[k] = make_float4(__int_as_float(16 * off), u[0], u[1], u[2]);
-        if (with_ee) {
-            const float *ee = tb.sh_ee + 6 * (k0 + k);
-            TB[k] = make_float4(ee[0], ee[1], ee[2], ee[3]);
-            TC[k] = make_float4(ee[4], ee[5], __int_as_float(4 * off), 0.f);
-        }
     }
 }
 
@@ -196,9 +190,7 @@ __global__ void __launch_bounds__(kBlock) k_gather1_tile(const SysDesc<float> *_
     float4 *L4 = lds;
     float *Lg = reinterpret_cast<float *>(lds + t.FS);
     float4 *TA = lds + t.FS + (t.FS + 3) / 4;
-    float4 *TB = TA + S.sh_max;
-    float4 *TC = TB + S.sh_max;
-    int *RowOff = reinterpret_cast<int *>(TC + S.sh_max);
+    int *RowOff = reinterpret_cast<int *>(TA + S.sh_max);
     const StageLane sl = stage_lane(S, t);
     fill_rows(S, t, RowOff);
     const char *c4 = reinterpret_cast<const char *>(L4 + q.c);
@@ -214,23 +206,24 @@ __global__ void __launch_bounds__(kBlock) k_gather1_tile(const SysDesc<float> *_
         const int k0 = S.sh_start[a][b], kn = S.sh_cnt[a][b];
         __syncthreads();
         stage(S, t, sl, RowOff, L4, Lg, S.n + (long long)b * N, S.j + (long long)b * 3 * N, gpair);
-        stage_table(tb, k0, kn, t, TA, TB, TC, true);
+        stage_table(tb, k0, kn, t, TA);
         __syncthreads();
         const float g0 = Lg[q.c];
         float s0 = 0.f, s1 = 0.f, s2 = 0.f, v0 = 0.f, v1 = 0.f, v2 = 0.f;
         float t00 = 0.f, t01 = 0.f, t02 = 0.f, t11 = 0.f, t12 = 0.f, t22 = 0.f;
 #pragma unroll 4
         for (int k = 0; k < kn; ++k) {
-            const float4 ta = TA[k], tb4 = TB[k], tc = TC[k];
-            const int o4 = __float_as_int(ta.x), o1 = __float_as_int(tc.z);
+            const float4 ta = TA[k];
+            const int o4 = __float_as_int(ta.x), o1 = o4 >> 2;
             const float e0 = ta.y, e1 = ta.z, e2 = ta.w;
             const float4 Ap = ld4(c4, o4), Am = ld4(c4, -o4);
             const float Gp = g0 + ld1(cg, o1), Gm = g0 + ld1(cg, -o1);
             const float tp = Gp * Ap.x, tm = Gm * Am.x;
             const float dt = tp - tm, st = tp + tm;
             s0 += e0 * dt; s1 += e1 * dt; s2 += e2 * dt;
-            t00 += st * tb4.x; t01 += st * tb4.y; t02 += st * tb4.z;
-            t11 += st * tb4.w; t12 += st * tc.x; t22 += st * tc.y;
+            const float se0 = st * e0, se1 = st * e1, se2 = st * e2;
+            t00 += se0 * e0; t01 += se0 * e1; t02 += se0 * e2;
+            t11 += se1 * e1; t12 += se1 * e2; t22 += se2 * e2;
             const float w0 = Gp * Ap.y + Gm * Am.y;
             const float w1 = Gp * Ap.z + Gm * Am.z;
             const float w2 = Gp * Ap.w + Gm * Am.w;
@@ -312,7 +305,7 @@ __global__ void __launch_bounds__(kBlock) k_step2_tile(const SysDesc<float> *__r
     float4 *L4 = lds;
     float *Lg = reinterpret_cast<float *>(lds + t.FS);
     float4 *TA = lds + t.FS + (t.FS + 3) / 4;
-    int *RowOff = reinterpret_cast<int *>(TA + 3 * S.sh_max);
+    int *RowOff = reinterpret_cast<int *>(TA + S.sh_max);
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
     if (S.scheme != 1) {
         const StageLane sl = stage_lane(S, t);
@@ -324,7 +317,7 @@ __global__ void __launch_bounds__(kBlock) k_step2_tile(const SysDesc<float> *__r
             const int k0 = S.sh_start[a][b], kn = S.sh_cnt[a][b];
             __syncthreads();
             stage(S, t, sl, RowOff, L4, Lg, S.n + (long long)b * N, S.vh + (long long)b * 3 * N, gpair);
-            stage_table(tb, k0, kn, t, TA, nullptr, nullptr, false);
+            stage_table(tb, k0, kn, t, TA);
             __syncthreads();
             const float g0 = Lg[q.c];
             float v0 = 0.f, v1 = 0.f, v2 = 0.f;
@@ -461,13 +454,13 @@ inline size_t contact_lds_bytes(int TX, int TY, int TZ, int R, int ball_total, i
     return 4 * ((size_t)maxM * FS + (size_t)ball_total + rows);
 }
 
-// float4 + float per staged site, the shell table (48 bytes per entry),
+// float4 + float per staged site, the shell table (16 bytes per entry),
 // then the row-offset table (one int per halo row)
 inline size_t tile_lds_bytes(int TX, int TY, int TZ, int R, int sh_max)
 {
     const size_t FS = (size_t)(TX + 2 * R) * (TY + 2 * R) * (TZ + 2 * R);
     const size_t rows = (size_t)(TY + 2 * R) * (TZ + 2 * R);
-    return 16 * FS + 16 * ((FS + 3) / 4) + 48 * (size_t)sh_max + 4 * rows;
+    return 16 * FS + 16 * ((FS + 3) / 4) + 16 * (size_t)sh_max + 4 * rows;
 }
 
 }  // namespace mlb

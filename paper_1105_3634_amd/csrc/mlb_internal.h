@@ -69,7 +69,6 @@ struct SysDesc {
 template <typename T>
 struct Tables {
     const int32_t *sh_e;  const T *sh_u;     // shell half-lists: packed offset, unit vector [3]
-    const T *sh_ee;                          // e e^T per shell entry [6]: xx, xy, xz, yy, yz, zz
     const int32_t *tl_e;  const T *tl_w;     // tail half-lists: packed offset, vector weight [3]
     const int32_t *bl_e;                     // ball half-lists: packed offset
 };
