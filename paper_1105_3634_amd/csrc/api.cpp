@@ -195,14 +195,14 @@ mlb_status set_error(mlb_status st, const std::string &msg) { return fail(st, ms
 
 // ---------------------------------------------------------------- the core
 struct mlb_batch_s {
-    int count = 0, prec = 32, maxM = 1, reach_max = 0, sh_max = 1, ball_reach_max = 0, ball_total_max = 1;
+    int count = 0, prec = 32, maxM = 1, reach_max = 0, ball_reach_max = 0, ball_total_max = 1;
     bool tiled = false;
     std::vector<SysHost> sys;
     char *ws = nullptr;
     size_t total = 0;
     // shared regions
     size_t desc = 0, map_site = 0, map_tile = 0, map_ident = 0;
-    size_t t_sh_e = 0, t_sh_u = 0, t_tl_e = 0, t_tl_w = 0, t_bl_e = 0;
+    size_t t_sh_e = 0, t_sh_u = 0, t_tl_e = 0, t_tl_w = 0, t_bl_e = 0, t_sh_q = 0;
     size_t red = 0, red_out = 0, fit_out = 0;
     size_t desc_size = 0;
     int nblk_site = 0, nblk_tile = 0, ident_len = 0;
@@ -253,6 +253,7 @@ struct mlb_batch_s {
         tb.tl_e = reinterpret_cast<const int32_t *>(ws + t_tl_e);
         tb.tl_w = reinterpret_cast<const T *>(ws + t_tl_w);
         tb.bl_e = reinterpret_cast<const int32_t *>(ws + t_bl_e);
+        tb.sh_q = reinterpret_cast<const float4 *>(ws + t_sh_q);
         return tb;
     }
 };
@@ -298,12 +299,10 @@ bool plan_batch(Batch &B, const mlb_params *params, int count, std::string &why)
         B.reach_max = std::max(B.reach_max, S.tabs.shell_reach);
         B.ball_reach_max = std::max(B.ball_reach_max, S.tabs.ball_reach);
         B.ball_total_max = std::max(B.ball_total_max, (int)S.tabs.bl_e.size());
-        for (int a = 0; a < S.M; ++a)
-            for (int b = 0; b < S.M; ++b) B.sh_max = std::max(B.sh_max, S.tabs.sh_cnt[a][b]);
     }
     bool fits = true;
     for (int v = 0; v < mlb::kTileVariants; ++v)
-        fits = fits && mlb::tile_lds_bytes_of(v, B.reach_max, B.sh_max) <= 160 * 1024 &&
+        fits = fits && mlb::tile_lds_bytes_of(v, B.reach_max) <= 160 * 1024 &&
                mlb::contact_lds_bytes_of(v, B.ball_reach_max, B.ball_total_max, B.maxM) <= 160 * 1024;
     B.tiled = B.prec == 32 && !any_direct_tail && fits;
     const size_t ts = tsize_of(B.prec);
@@ -344,6 +343,7 @@ bool plan_batch(Batch &B, const mlb_params *params, int count, std::string &why)
     B.t_tl_e = take(4 * ntl);
     B.t_tl_w = take(ts * 3 * ntl);
     B.t_bl_e = take(4 * nbl);
+    B.t_sh_q = take(16 * (nsh + mlb::kShellPad));
     B.red = take(sizeof(double) * kRedParts * 16);
     B.red_out = take(sizeof(double) * 16);
     B.fit_out = take(sizeof(double) * 4 * (size_t)count);
@@ -393,7 +393,6 @@ void fill_desc(Batch &B, int k, mlb::SysDesc<T> &D)
     D.reach = S.tabs.shell_reach;
     D.ball_reach = S.tabs.ball_reach;
     D.ball_total = (int)S.tabs.bl_e.size();
-    D.sh_max = B.sh_max;
     char *ws = B.ws;
     D.f[0] = reinterpret_cast<T *>(ws + S.f0);
     D.f[1] = reinterpret_cast<T *>(ws + S.f1);
@@ -485,6 +484,13 @@ mlb_status upload_static(Batch &B, hipStream_t st)
     TRY(up(B.t_tl_e, tl_e.data(), 4 * tl_e.size()));
     TRY(up(B.t_tl_w, tl_w.data(), sizeof(T) * tl_w.size()));
     TRY(up(B.t_bl_e, bl_e.data(), 4 * bl_e.size()));
+    std::vector<float4> sh_q(sh_e.size() + mlb::kShellPad, make_float4(0.f, 0.f, 0.f, 0.f));
+    for (size_t k = 0; k < sh_e.size(); ++k) {
+        float bits;
+        std::memcpy(&bits, &sh_e[k], 4);
+        sh_q[k] = make_float4(bits, (float)sh_u[3 * k], (float)sh_u[3 * k + 1], (float)sh_u[3 * k + 2]);
+    }
+    TRY(up(B.t_sh_q, sh_q.data(), sizeof(float4) * sh_q.size()));
     // per-site block map and the identity map used by single-system launches
     std::vector<int2> site, ident((size_t)B.ident_len);
     for (int k = 0; k < B.count; ++k)
@@ -648,7 +654,7 @@ void run_passes(Batch &B, hipStream_t st, bool query, int qk, int force_only)
         if constexpr (std::is_same<T, float>::value) {
             if (tiled) {
                 pass(B, kPassGather1, st,
-                     [&] { mlb::launch_gather1_tile(shape, sys, tmap, ntl, M, tb, B.reach_max, B.sh_max, st); });
+                     [&] { mlb::launch_gather1_tile(shape, sys, tmap, ntl, M, tb, B.reach_max, st); });
                 return;
             }
         }
@@ -658,7 +664,7 @@ void run_passes(Batch &B, hipStream_t st, bool query, int qk, int force_only)
         if constexpr (std::is_same<T, float>::value) {
             if (tiled) {
                 pass(B, kPassStep2, st, [&] {
-                    mlb::launch_step2_tile(shape, sys, tmap, ntl, M, tb, B.reach_max, B.sh_max, par, force_only, st);
+                    mlb::launch_step2_tile(shape, sys, tmap, ntl, M, tb, B.reach_max, par, force_only, st);
                 });
                 return;
             }
@@ -959,7 +965,7 @@ mlb_status create(Batch &B, const mlb_params *params, int count, void *workspace
         if (!n0[k] || !u0[k]) return fail(MLB_EINVAL, "n0 and u0 are required for every system");
     B.ws = static_cast<char *>(workspace);
     B.use_graph = (options & MLB_OPT_NO_GRAPH) == 0;
-    if (B.tiled && !mlb::tile_prepare(B.reach_max, B.sh_max, B.ball_reach_max, B.ball_total_max, B.maxM))
+    if (B.tiled && !mlb::tile_prepare(B.reach_max, B.ball_reach_max, B.ball_total_max, B.maxM))
         B.tiled = false;
     TRY(upload_static<T>(B, st));
     if (B.tiled) TRY(set_tiling(B, 0, 1, st));

@@ -25,11 +25,77 @@
 // the inner loop is address arithmetic on a uniform offset and LDS loads.
 #pragma once
 
+#include <algorithm>
+
 #include "step_kernels.h"
 
 namespace mlb {
 
 constexpr int kTileFields = 5;   // n, v0, v1, v2, g
+
+// The gathers run several threads per tile site: thread group h (the waves
+// of threads h * 256 ... h * 256 + 255) takes the h-th part of every shell
+// list, and the parts are added in group order at the end.  More waves per
+// CU at the same LDS footprint hide the LDS and scalar-load latencies of the
+// inner loop.  Split factor, shell-loop unrolling and the register budget
+// (waves per SIMD) per kernel:
+#ifndef MLB_G1_SPLIT
+#define MLB_G1_SPLIT 2
+#endif
+#ifndef MLB_G1_UNROLL
+#define MLB_G1_UNROLL 4
+#endif
+#ifndef MLB_G1_WAVES
+#define MLB_G1_WAVES 4
+#endif
+#ifndef MLB_S2_SPLIT
+#define MLB_S2_SPLIT 2
+#endif
+#ifndef MLB_S2_UNROLL
+#define MLB_S2_UNROLL 4
+#endif
+#ifndef MLB_S2_WAVES
+#define MLB_S2_WAVES 4
+#endif
+constexpr int kSplitG1 = MLB_G1_SPLIT, kSplitS2 = MLB_S2_SPLIT;
+constexpr int kGather1Threads = kSplitG1 * kBlock, kStep2Threads = kSplitS2 * kBlock;
+
+// shell entries [kb, ke) of group h of SPLIT
+template <int SPLIT>
+__device__ inline void split_range(int kn, int h, int &kb, int &ke)
+{
+    const int part = (kn + SPLIT - 1) / SPLIT;
+    kb = min(kn, h * part);
+    ke = min(kn, kb + part);
+}
+
+// Adds the partial sums of groups 1.. onto group 0's, in group order; the
+// LDS staging area is reused (after a barrier), V floats per site.  Returns
+// false for the threads of groups 1.., which have nothing more to do.
+template <int SPLIT, int V>
+__device__ inline bool split_reduce(float4 *lds, float (&v)[V])
+{
+    if (SPLIT == 1) return true;
+    float *R = reinterpret_cast<float *>(lds);
+    const int i = threadIdx.x % kBlock, h = threadIdx.x / kBlock;
+    __syncthreads();
+    if (h > 0)
+#pragma unroll
+        for (int j = 0; j < V; ++j) R[((h - 1) * V + j) * kBlock + i] = v[j];
+    __syncthreads();
+    if (h > 0) return false;
+    for (int g = 0; g < SPLIT - 1; ++g)
+#pragma unroll
+        for (int j = 0; j < V; ++j) v[j] += R[(g * V + j) * kBlock + i];
+    return true;
+}
+
+// Field pointers cast to the global address space: loads and stores then
+// compile to global_* instructions, which count only against the vector
+// memory counter (flat ones also hold the LDS counter, so a wait on LDS
+// data would wait for outstanding field loads as well).
+typedef __attribute__((address_space(1))) float gfloat;
+__device__ inline gfloat *glb(float *p) { return (gfloat *)p; }
 
 struct TileGeo {
     int x0, y0, z0;       // tile origin
@@ -54,7 +120,8 @@ __device__ inline TileGeo tile_geo(const SysDesc<float> &S, int local, int R)
 // row = hy + HY hz; RowOff[row] holds the global site offset of the row's
 // x = 0 site ((gz ny + gy) nx after periodic wrap), or -1 for a row outside
 // the walls.  Thread t owns the halo column hx = t % HX (its wrapped global
-// x computed once) and the rows t / HX, t / HX + 256 / HX, ...; consecutive
+// x computed once) and the rows t / HX, t / HX + NT / HX, ... (NT threads per
+// block); consecutive
 // threads read consecutive x, so global loads coalesce, and the per-element
 // work is a table read, an add and the loads.
 __device__ inline int wrap_mod(int v, int n)
@@ -68,10 +135,11 @@ struct StageLane {
     int gx;
 };
 
+template <int NT = kBlock>
 __device__ inline StageLane stage_lane(const SysDesc<float> &S, const TileGeo &t)
 {
     StageLane l;
-    l.rstep = kBlock / t.HX;
+    l.rstep = NT / t.HX;
     l.hx = threadIdx.x % t.HX;
     l.row0 = threadIdx.x / t.HX;
     if (l.row0 >= l.rstep) l.rstep = 0;          // left-over threads of the last partial column set
@@ -79,10 +147,11 @@ __device__ inline StageLane stage_lane(const SysDesc<float> &S, const TileGeo &t
     return l;
 }
 
+template <int NT = kBlock>
 __device__ inline void fill_rows(const SysDesc<float> &S, const TileGeo &t, int *RowOff)
 {
     const int rows = t.HY * t.HZ;
-    for (int r = threadIdx.x; r < rows; r += kBlock) {
+    for (int r = threadIdx.x; r < rows; r += NT) {
         const int hz = r / t.HY, hy = r - hz * t.HY;
         int gy = t.y0 - t.R + hy;
         const int gz = wrap_mod(t.z0 - t.R + hz, S.nz);
@@ -96,8 +165,8 @@ __device__ inline void fill_rows(const SysDesc<float> &S, const TileGeo &t, int 
 }
 
 __device__ inline void stage(const SysDesc<float> &S, const TileGeo &t, const StageLane &l, const int *RowOff,
-                             float4 *lds4, float *ldsg, const float *__restrict__ nb, const float *__restrict__ vb,
-                             const float *__restrict__ gp)
+                             float4 *lds4, float *ldsg, const gfloat *__restrict__ nb, const gfloat *__restrict__ vb,
+                             const gfloat *__restrict__ gp)
 {
     const unsigned N = (unsigned)S.N;
     const int rows = t.HY * t.HZ;
@@ -119,7 +188,7 @@ __device__ inline void stage(const SysDesc<float> &S, const TileGeo &t, const St
 
 // One scalar field of the halo tile (zero outside the walls).
 __device__ inline void stage1(const TileGeo &t, const StageLane &l, const int *RowOff, float *dst,
-                              const float *__restrict__ src)
+                              const gfloat *__restrict__ src)
 {
     const int rows = t.HY * t.HZ;
     if (l.rstep == 0) return;
@@ -129,21 +198,25 @@ __device__ inline void stage1(const TileGeo &t, const StageLane &l, const int *R
     }
 }
 
-// Copy the (a,b) half-shell into LDS: TA[k] = (byte offset of e in the
-// float4 field array, e_hat); the g array's offset is a quarter of it and
-// the tensor e_hat e_hat^T is formed in registers.  Reads of TA are
-// wave-uniform broadcasts; every LDS read costs bandwidth, so the table
-// holds no more than this.
-__device__ inline void stage_table(const Tables<float> &tb, int k0, int kn, const TileGeo &t, float4 *TA)
+// The (a,b) half-shell is read straight from the float4 table sh_q
+// (packed offset bits, e_hat): the index is wave-uniform, so the entries
+// arrive through scalar loads into SGPRs and the offset arithmetic runs on
+// the scalar unit.  LDS bandwidth, the binding resource of the gathers,
+// then carries only the staged fields.  shell_off returns the byte offset of
+// e in the float4 field array; the g array's offset is a quarter of it.
+typedef float ShellEntry __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) ShellEntry *ConstF4;   // read-only for the kernel's lifetime
+
+__device__ inline ConstF4 shell_list(const Tables<float> &tb, int k0)
 {
-    const int HXY = t.HX * t.HY;
-    for (int k = threadIdx.x; k < kn; k += kBlock) {
-        int ex, ey, ez;
-        unpack_offset(tb.sh_e[k0 + k], ex, ey, ez);
-        const int off = ex + ey * t.HX + ez * HXY;
-        const float *u = tb.sh_u + 3 * (k0 + k);
-        TA[k] = make_float4(__int_as_float(16 * off), u[0], u[1], u[2]);
-    }
+    return (ConstF4)(tb.sh_q + k0);
+}
+
+__device__ inline int shell_off(float packed, int HX, int HXY)
+{
+    int ex, ey, ez;
+    unpack_offset(__float_as_int(packed), ex, ey, ez);
+    return 16 * (ex + ey * HX + ez * HXY);
 }
 
 // field reads at a byte offset from the site's own address
@@ -161,9 +234,10 @@ template <int TX, int TY, int TZ>
 __device__ inline TileSite tile_site(const SysDesc<float> &S, const TileGeo &t)
 {
     TileSite q;
-    q.tx = threadIdx.x % TX;
-    q.ty = (threadIdx.x / TX) % TY;
-    q.tz = threadIdx.x / (TX * TY);
+    const int i = threadIdx.x % (TX * TY * TZ);
+    q.tx = i % TX;
+    q.ty = (i / TX) % TY;
+    q.tz = i / (TX * TY);
     q.x = t.x0 + q.tx; q.y = t.y0 + q.ty; q.z = t.z0 + q.tz;
     q.active = q.x < S.nx && q.y < S.ny && q.z < S.nz;
     q.s = ((long long)q.z * S.ny + q.y) * S.nx + q.x;
@@ -173,11 +247,12 @@ __device__ inline TileSite tile_site(const SysDesc<float> &S, const TileGeo &t)
 
 // ------------------------------------------------------------ first gather
 template <int TX, int TY, int TZ>
-__global__ void __launch_bounds__(kBlock) k_gather1_tile(const SysDesc<float> *__restrict__ sys,
+__global__ void __launch_bounds__(kGather1Threads) __attribute__((amdgpu_waves_per_eu(MLB_G1_WAVES)))
+k_gather1_tile(const SysDesc<float> *__restrict__ sys,
                                                          const int2 *__restrict__ bmap, Tables<float> tb)
 {
     extern __shared__ float4 lds[];
-    static_assert(TX * TY * TZ == kBlock, "one thread per tile site");
+    static_assert(TX * TY * TZ == kBlock, "kSplitG1 threads per tile site");
     const int2 bm = bmap[blockIdx.x];
     if (bm.x < 0) return;
     const SysDesc<float> &S = sys[bm.x];
@@ -185,36 +260,38 @@ __global__ void __launch_bounds__(kBlock) k_gather1_tile(const SysDesc<float> *_
     if (a >= S.M) return;
     const TileGeo t = tile_geo<TX, TY, TZ>(S, bm.y, S.reach);
     const TileSite q = tile_site<TX, TY, TZ>(S, t);
+    const int h = __builtin_amdgcn_readfirstlane(threadIdx.x / kBlock);   // wave-uniform
     const long long N = S.N;
     const long long o3 = (long long)a * 3 * N;
     float4 *L4 = lds;
     float *Lg = reinterpret_cast<float *>(lds + t.FS);
-    float4 *TA = lds + t.FS + (t.FS + 3) / 4;
-    int *RowOff = reinterpret_cast<int *>(TA + S.sh_max);
-    const StageLane sl = stage_lane(S, t);
-    fill_rows(S, t, RowOff);
+    int *RowOff = reinterpret_cast<int *>(lds + t.FS + (t.FS + 3) / 4);
+    const int HXY = t.HX * t.HY;
+    const StageLane sl = stage_lane<kGather1Threads>(S, t);
+    fill_rows<kGather1Threads>(S, t, RowOff);
     const char *c4 = reinterpret_cast<const char *>(L4 + q.c);
     const char *cg = reinterpret_cast<const char *>(Lg + q.c);
     const bool solid = q.active && S.walls && (q.y == 0 || q.y == S.ny - 1);
-    const long long sc = q.active ? q.s : 0;
-    const float na = S.n[(long long)a * N + sc];
-    const float ja0 = S.j[o3 + sc], ja1 = S.j[o3 + N + sc], ja2 = S.j[o3 + 2 * N + sc];
+    const long long sc = q.active && h == 0 ? q.s : 0;
+    const float na = glb(S.n)[(long long)a * N + sc];
+    const float ja0 = glb(S.j)[o3 + sc], ja1 = glb(S.j)[o3 + N + sc], ja2 = glb(S.j)[o3 + 2 * N + sc];
     float mf0 = 0.f, mf1 = 0.f, mf2 = 0.f, dj0 = 0.f, dj1 = 0.f, dj2 = 0.f, gam = 0.f;
     float T00 = 0.f, T01 = 0.f, T02 = 0.f, T11 = 0.f, T12 = 0.f, T22 = 0.f;
     for (int b = 0; b < S.M; ++b) {
-        const float *__restrict__ gpair = S.g + (long long)pidx(S.M, a, b) * N;
-        const int k0 = S.sh_start[a][b], kn = S.sh_cnt[a][b];
+        const gfloat *__restrict__ gpair = glb(S.g) + (long long)pidx(S.M, a, b) * N;
+        int kb, ke;
+        split_range<kSplitG1>(S.sh_cnt[a][b], h, kb, ke);
         __syncthreads();
-        stage(S, t, sl, RowOff, L4, Lg, S.n + (long long)b * N, S.j + (long long)b * 3 * N, gpair);
-        stage_table(tb, k0, kn, t, TA);
+        stage(S, t, sl, RowOff, L4, Lg, glb(S.n) + (long long)b * N, glb(S.j) + (long long)b * 3 * N, gpair);
         __syncthreads();
+        const ConstF4 Q = shell_list(tb, S.sh_start[a][b]);
         const float g0 = Lg[q.c];
         float s0 = 0.f, s1 = 0.f, s2 = 0.f, v0 = 0.f, v1 = 0.f, v2 = 0.f;
         float t00 = 0.f, t01 = 0.f, t02 = 0.f, t11 = 0.f, t12 = 0.f, t22 = 0.f;
-#pragma unroll 4
-        for (int k = 0; k < kn; ++k) {
-            const float4 ta = TA[k];
-            const int o4 = __float_as_int(ta.x), o1 = o4 >> 2;
+#pragma unroll MLB_G1_UNROLL
+        for (int k = kb; k < ke; ++k) {
+            const ShellEntry ta = Q[k];
+            const int o4 = shell_off(ta.x, t.HX, HXY), o1 = o4 >> 2;
             const float e0 = ta.y, e1 = ta.z, e2 = ta.w;
             const float4 Ap = ld4(c4, o4), Am = ld4(c4, -o4);
             const float Gp = g0 + ld1(cg, o1), Gm = g0 + ld1(cg, -o1);
@@ -237,40 +314,44 @@ __global__ void __launch_bounds__(kBlock) k_gather1_tile(const SysDesc<float> *_
         T11 += ck * t11; T12 += ck * t12; T22 += ck * t22;
         gam += S.cg[a][b] * (t00 + t11 + t22);
     }
+    float part[13] = {mf0, mf1, mf2, dj0, dj1, dj2, gam, T00, T01, T02, T11, T12, T22};
+    if (!split_reduce<kSplitG1>(lds, part)) return;
+    mf0 = part[0]; mf1 = part[1]; mf2 = part[2]; dj0 = part[3]; dj1 = part[4]; dj2 = part[5]; gam = part[6];
+    T00 = part[7]; T01 = part[8]; T02 = part[9]; T11 = part[10]; T12 = part[11]; T22 = part[12];
     if (!q.active) return;
     const long long s = q.s;
-    float *__restrict__ Tout = S.Tloc + (long long)a * 6 * N;
+    gfloat *__restrict__ Tout = glb(S.Tloc) + (long long)a * 6 * N;
     if (solid) {
         for (int d = 0; d < 3; ++d) {
-            S.vh[o3 + d * N + s] = 0.f;
-            S.H[o3 + d * N + s] = 0.f;
-            if (S.parts) S.parts[o3 + d * N + s] = 0.f;
+            glb(S.vh)[o3 + d * N + s] = 0.f;
+            glb(S.H)[o3 + d * N + s] = 0.f;
+            if (S.parts) glb(S.parts)[o3 + d * N + s] = 0.f;
         }
         for (int d = 0; d < 6; ++d) Tout[d * N + s] = 0.f;
-        if (S.tail_deferred) S.gfac[(long long)a * N + s] = 0.f;
+        if (S.tail_deferred) glb(S.gfac)[(long long)a * N + s] = 0.f;
         return;
     }
     float tl0 = 0.f, tl1 = 0.f, tl2 = 0.f;
     if (S.tail && !S.tail_deferred) {
-        tl0 = S.tail[o3 + s]; tl1 = S.tail[o3 + N + s]; tl2 = S.tail[o3 + 2 * N + s];
+        tl0 = glb(S.tail)[o3 + s]; tl1 = glb(S.tail)[o3 + N + s]; tl2 = glb(S.tail)[o3 + 2 * N + s];
     }
     const float mfv[3] = {mf0, mf1, mf2}, tlv[3] = {tl0, tl1, tl2}, jav[3] = {ja0, ja1, ja2};
     const float djv[3] = {dj0, dj1, dj2};
     const float Tj[3] = {T00 * ja0 + T01 * ja1 + T02 * ja2, T01 * ja0 + T11 * ja1 + T12 * ja2,
                          T02 * ja0 + T12 * ja1 + T22 * ja2};
     const float hg = 0.5f * gam;
-    if (S.tail_deferred) S.gfac[(long long)a * N + s] = (na != 0.f) ? 1.f / (1.f + hg) : 0.f;
+    if (S.tail_deferred) glb(S.gfac)[(long long)a * N + s] = (na != 0.f) ? 1.f / (1.f + hg) : 0.f;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const float Nmf = na * mfv[d], Ntl = na * tlv[d], Nex = na * S.fext[a][d];
         const float Nc = Nmf + Ntl + Nex;
         const float Dd = na * djv[d] - Tj[d];
         if (S.scheme == 1) {
-            S.H[o3 + d * N + s] = Nc + Dd;
-            S.vh[o3 + d * N + s] = 0.f;
+            glb(S.H)[o3 + d * N + s] = Nc + Dd;
+            glb(S.vh)[o3 + d * N + s] = 0.f;
         } else {
-            S.H[o3 + d * N + s] = Nc + 0.5f * Dd;
-            S.vh[o3 + d * N + s] = (na != 0.f) ? (jav[d] + Nc + Dd + hg * jav[d]) / (na * (1.f + hg)) : 0.f;
+            glb(S.H)[o3 + d * N + s] = Nc + 0.5f * Dd;
+            glb(S.vh)[o3 + d * N + s] = (na != 0.f) ? (jav[d] + Nc + Dd + hg * jav[d]) / (na * (1.f + hg)) : 0.f;
         }
         if (S.parts) {
             float acc = 0.f;
@@ -278,7 +359,7 @@ __global__ void __launch_bounds__(kBlock) k_gather1_tile(const SysDesc<float> *_
             if (S.parts_mask & 2u) acc += Ntl;
             if (S.parts_mask & 8u) acc += Nex;
             if (S.parts_mask & 4u) acc += (S.scheme == 1 ? Dd : 0.5f * Dd);
-            S.parts[o3 + d * N + s] = acc;
+            glb(S.parts)[o3 + d * N + s] = acc;
         }
     }
     Tout[0 * N + s] = T00; Tout[1 * N + s] = T01; Tout[2 * N + s] = T02;
@@ -287,12 +368,13 @@ __global__ void __launch_bounds__(kBlock) k_gather1_tile(const SysDesc<float> *_
 
 // ------------------------------- second gather + collision + push streaming
 template <int TX, int TY, int TZ>
-__global__ void __launch_bounds__(kBlock) k_step2_tile(const SysDesc<float> *__restrict__ sys,
+__global__ void __launch_bounds__(kStep2Threads) __attribute__((amdgpu_waves_per_eu(MLB_S2_WAVES)))
+k_step2_tile(const SysDesc<float> *__restrict__ sys,
                                                        const int2 *__restrict__ bmap, Tables<float> tb, int parity,
                                                        int write_force_only)
 {
     extern __shared__ float4 lds[];
-    static_assert(TX * TY * TZ == kBlock, "one thread per tile site");
+    static_assert(TX * TY * TZ == kBlock, "kSplitS2 threads per tile site");
     const int2 bm = bmap[blockIdx.x];
     if (bm.x < 0) return;
     const SysDesc<float> &S = sys[bm.x];
@@ -304,27 +386,61 @@ __global__ void __launch_bounds__(kBlock) k_step2_tile(const SysDesc<float> *__r
     const long long o3 = (long long)a * 3 * N;
     float4 *L4 = lds;
     float *Lg = reinterpret_cast<float *>(lds + t.FS);
-    float4 *TA = lds + t.FS + (t.FS + 3) / 4;
-    int *RowOff = reinterpret_cast<int *>(TA + S.sh_max);
+    int *RowOff = reinterpret_cast<int *>(lds + t.FS + (t.FS + 3) / 4);
+    const int HXY = t.HX * t.HY;
+    const int h = __builtin_amdgcn_readfirstlane(threadIdx.x / kBlock);   // wave-uniform
+    // The collision's inputs are loaded before the gathers, so that their
+    // latency hides behind the shell loops; group 0 owns the collision.
+    const bool fluid = q.active && !(S.walls && (q.y == 0 || q.y == S.ny - 1));
+    const bool epi = h == 0 && fluid;
+    const bool need_f = epi && !write_force_only && S.omega_is_one == 0;
+    const long long s = q.s;
+    float na = 0.f, Na[3] = {0.f, 0.f, 0.f}, Tl[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, va[3] = {0.f, 0.f, 0.f};
+    float ja[3] = {0.f, 0.f, 0.f}, u[3] = {0.f, 0.f, 0.f}, fi[kQ];
+    if (epi) {
+        na = glb(S.n)[(long long)a * N + s];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) Na[d] = glb(S.H)[o3 + d * N + s];
+        if (S.scheme != 1) {
+            const gfloat *__restrict__ Tg = glb(S.Tloc) + (long long)a * 6 * N;
+#pragma unroll
+            for (int d = 0; d < 6; ++d) Tl[d] = Tg[d * N + s];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) va[d] = glb(S.vh)[o3 + d * N + s];
+        }
+        if (!write_force_only) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                ja[d] = glb(S.j)[o3 + d * N + s];
+                u[d] = glb(S.u)[d * N + s];
+            }
+        }
+    }
+    {
+        const gfloat *__restrict__ fin = glb(S.f[parity]) + (long long)a * kQ * N;
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) fi[i] = need_f ? fin[(long long)i * N + s] : 0.f;
+    }
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
     if (S.scheme != 1) {
-        const StageLane sl = stage_lane(S, t);
-        fill_rows(S, t, RowOff);
+        const StageLane sl = stage_lane<kStep2Threads>(S, t);
+        fill_rows<kStep2Threads>(S, t, RowOff);
         const char *c4 = reinterpret_cast<const char *>(L4 + q.c);
         const char *cg = reinterpret_cast<const char *>(Lg + q.c);
         for (int b = 0; b < S.M; ++b) {
-            const float *__restrict__ gpair = S.g + (long long)pidx(S.M, a, b) * N;
-            const int k0 = S.sh_start[a][b], kn = S.sh_cnt[a][b];
+            const gfloat *__restrict__ gpair = glb(S.g) + (long long)pidx(S.M, a, b) * N;
+            int kb, ke;
+            split_range<kSplitS2>(S.sh_cnt[a][b], h, kb, ke);
             __syncthreads();
-            stage(S, t, sl, RowOff, L4, Lg, S.n + (long long)b * N, S.vh + (long long)b * 3 * N, gpair);
-            stage_table(tb, k0, kn, t, TA);
+            stage(S, t, sl, RowOff, L4, Lg, glb(S.n) + (long long)b * N, glb(S.vh) + (long long)b * 3 * N, gpair);
             __syncthreads();
+            const ConstF4 Q = shell_list(tb, S.sh_start[a][b]);
             const float g0 = Lg[q.c];
             float v0 = 0.f, v1 = 0.f, v2 = 0.f;
-#pragma unroll 4
-            for (int k = 0; k < kn; ++k) {
-                const float4 ta = TA[k];
-                const int o4 = __float_as_int(ta.x), o1 = o4 >> 2;
+#pragma unroll MLB_S2_UNROLL
+            for (int k = kb; k < ke; ++k) {
+                const ShellEntry ta = Q[k];
+                const int o4 = shell_off(ta.x, t.HX, HXY), o1 = o4 >> 2;
                 const float e0 = ta.y, e1 = ta.z, e2 = ta.w;
                 const float4 Ap = ld4(c4, o4), Am = ld4(c4, -o4);
                 const float tp = (g0 + ld1(cg, o1)) * Ap.x, tm = (g0 + ld1(cg, -o1)) * Am.x;
@@ -337,44 +453,40 @@ __global__ void __launch_bounds__(kBlock) k_step2_tile(const SysDesc<float> *__r
             const float ck = S.ck[a][b];
             acc0 += ck * v0; acc1 += ck * v1; acc2 += ck * v2;
         }
-    }
-    if (!q.active) return;
-    const long long s = q.s;
-    if (S.walls && (q.y == 0 || q.y == S.ny - 1)) {
-        if (write_force_only)
-            for (int d = 0; d < 3; ++d) S.Nf[o3 + d * N + s] = 0.f;
+        float part[3] = {acc0, acc1, acc2};
+        if (!split_reduce<kSplitS2>(lds, part)) return;
+        acc0 = part[0]; acc1 = part[1]; acc2 = part[2];
+    } else if (h > 0) {
         return;
     }
-    const float na = S.n[(long long)a * N + s];
-    float Na[3] = {S.H[o3 + s], S.H[o3 + N + s], S.H[o3 + 2 * N + s]};
+    if (!q.active) return;
+    if (!fluid) {
+        if (write_force_only)
+            for (int d = 0; d < 3; ++d) glb(S.Nf)[o3 + d * N + s] = 0.f;
+        return;
+    }
     if (S.scheme != 1) {
-        const float *__restrict__ Tl = S.Tloc + (long long)a * 6 * N;
-        const float T00 = Tl[s], T01 = Tl[N + s], T02 = Tl[2 * N + s], T11 = Tl[3 * N + s], T12 = Tl[4 * N + s],
-                    T22 = Tl[5 * N + s];
-        const float va0 = S.vh[o3 + s], va1 = S.vh[o3 + N + s], va2 = S.vh[o3 + 2 * N + s];
+        const float T00 = Tl[0], T01 = Tl[1], T02 = Tl[2], T11 = Tl[3], T12 = Tl[4], T22 = Tl[5];
+        const float va0 = va[0], va1 = va[1], va2 = va[2];
         const float Dn[3] = {na * (acc0 - (T00 * va0 + T01 * va1 + T02 * va2)),
                              na * (acc1 - (T01 * va0 + T11 * va1 + T12 * va2)),
                              na * (acc2 - (T02 * va0 + T12 * va1 + T22 * va2))};
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             Na[d] += 0.5f * Dn[d];
-            if (S.parts && (S.parts_mask & 4u)) S.parts[o3 + d * N + s] += 0.5f * Dn[d];
+            if (S.parts && (S.parts_mask & 4u)) glb(S.parts)[o3 + d * N + s] += 0.5f * Dn[d];
         }
     }
     if (write_force_only) {
-        for (int d = 0; d < 3; ++d) S.Nf[o3 + d * N + s] = Na[d];
+        for (int d = 0; d < 3; ++d) glb(S.Nf)[o3 + d * N + s] = Na[d];
         return;
     }
-    const float ja[3] = {S.j[o3 + s], S.j[o3 + N + s], S.j[o3 + 2 * N + s]};
-    const float u[3] = {S.u[s], S.u[N + s], S.u[2 * N + s]};
-    const float *__restrict__ fin = S.f[parity] + (long long)a * kQ * N;
-    float *__restrict__ fout = S.f[parity ^ 1] + (long long)a * kQ * N;
+    gfloat *__restrict__ fout = glb(S.f[parity ^ 1]) + (long long)a * kQ * N;
     const bool w1 = S.omega_is_one != 0;
     const Site r{q.x, q.y, q.z};
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
-        const float fi = w1 ? 0.f : fin[(long long)i * N + s];
-        const float fs = post_collision<float>(i, fi, w1, S.omega, S.om1, na, ja, u, Na);
+        const float fs = post_collision<float>(i, fi[i], w1, S.omega, S.om1, na, ja, u, Na);
         const int yy = q.y + kC[i][1];
         if (S.walls && (yy == 0 || yy == S.ny - 1)) {
             const float uw = (yy == 0) ? S.wall_ux[0] : S.wall_ux[1];
@@ -415,12 +527,12 @@ __global__ void __launch_bounds__(kBlock) k_contact_tile(const SysDesc<float> *_
         Off[k] = ex + ey * t.HX + ez * t.HX * t.HY;
     }
     __syncthreads();
-    for (int c = 0; c < S.M; ++c) stage1(t, sl, RowOff, Ln + c * t.FS, S.n + (long long)c * N);
+    for (int c = 0; c < S.M; ++c) stage1(t, sl, RowOff, Ln + c * t.FS, glb(S.n) + (long long)c * N);
     __syncthreads();
     if (!q.active) return;
     const long long s = q.s;
     if (S.walls && (q.y == 0 || q.y == S.ny - 1)) {
-        for (int p = 0; p < S.P; ++p) S.g[(long long)p * N + s] = 0.f;
+        for (int p = 0; p < S.P; ++p) glb(S.g)[(long long)p * N + s] = 0.f;
         return;
     }
     float nb[kMaxS];
@@ -443,7 +555,7 @@ __global__ void __launch_bounds__(kBlock) k_contact_tile(const SysDesc<float> *_
     for (int a = 0; a < S.M; ++a)
         for (int b = a; b < S.M; ++b) {
             const float z = (S.dd[a][b] * x2) * qf;
-            S.g[(long long)pidx(S.M, a, b) * N + s] = qf * ((1.f + z) * (1.f + 2.f * z));
+            glb(S.g)[(long long)pidx(S.M, a, b) * N + s] = qf * ((1.f + z) * (1.f + 2.f * z));
         }
 }
 
@@ -454,13 +566,15 @@ inline size_t contact_lds_bytes(int TX, int TY, int TZ, int R, int ball_total, i
     return 4 * ((size_t)maxM * FS + (size_t)ball_total + rows);
 }
 
-// float4 + float per staged site, the shell table (16 bytes per entry),
-// then the row-offset table (one int per halo row)
-inline size_t tile_lds_bytes(int TX, int TY, int TZ, int R, int sh_max)
+// float4 + float per staged site, then the row-offset table (one int per
+// halo row); at least the partial sums of the split reductions (13 floats
+// per site and extra group in the first gather, 3 in the second)
+inline size_t tile_lds_bytes(int TX, int TY, int TZ, int R)
 {
     const size_t FS = (size_t)(TX + 2 * R) * (TY + 2 * R) * (TZ + 2 * R);
     const size_t rows = (size_t)(TY + 2 * R) * (TZ + 2 * R);
-    return 16 * FS + 16 * ((FS + 3) / 4) + 16 * (size_t)sh_max + 4 * rows;
+    const size_t reduce = std::max((size_t)(kSplitG1 - 1) * 13, (size_t)(kSplitS2 - 1) * 3) * kBlock * 4;
+    return std::max(16 * FS + 16 * ((FS + 3) / 4) + 4 * rows, reduce);
 }
 
 }  // namespace mlb

@@ -38,7 +38,6 @@ struct SysDesc {
     int reach;                       // largest |component| of any shell offset
     int ball_reach;                  // largest |component| of any smoothing-ball offset
     int ball_total;                  // entries of this system's ball half-lists (all species)
-    int sh_max;                      // longest half-shell of the launch (LDS table slots)
     T *f[2];                         // population double buffer [M][19][N]
     T *n, *j, *u, *g, *vh, *H, *Nf;  // fields (see mlb.h for layouts)
     T *tail;                         // attractive field sum_b K_ab * n_b [M][3][N] (spectral mode)
@@ -71,7 +70,11 @@ struct Tables {
     const int32_t *sh_e;  const T *sh_u;     // shell half-lists: packed offset, unit vector [3]
     const int32_t *tl_e;  const T *tl_w;     // tail half-lists: packed offset, vector weight [3]
     const int32_t *bl_e;                     // ball half-lists: packed offset
+    // float32 tiled gathers: the shell half-lists as float4 (packed offset
+    // bits, unit vector), followed by kShellPad zero entries
+    const float4 *sh_q;
 };
+constexpr int kShellPad = 8;
 
 // ---------------------------------------------------------------- host side
 struct HostStencil {
@@ -114,16 +117,16 @@ struct Launch {
 constexpr int kTileVariants = 3;
 void tile_dims(int v, int &tx, int &ty, int &tz);
 void launch_gather1_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM, Tables<float> tb,
-                         int reach_max, int sh_max, hipStream_t st);
+                         int reach_max, hipStream_t st);
 void launch_step2_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM, Tables<float> tb,
-                       int reach_max, int sh_max, int parity, int write_force_only, hipStream_t st);
+                       int reach_max, int parity, int write_force_only, hipStream_t st);
 // contact values on the same tiles (halo = ball reach), one thread per site
 void launch_contact_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, Tables<float> tb,
                          int ball_reach_max, int ball_total_max, int maxM, hipStream_t st);
 int tile_count(int v, int nx, int ny, int nz);
 // raise the dynamic-LDS limits; false if a kernel cannot fit
-bool tile_prepare(int reach_max, int sh_max, int ball_reach_max, int ball_total_max, int maxM);
-size_t tile_lds_bytes_of(int v, int reach, int sh_max);
+bool tile_prepare(int reach_max, int ball_reach_max, int ball_total_max, int maxM);
+size_t tile_lds_bytes_of(int v, int reach);
 size_t contact_lds_bytes_of(int v, int ball_reach, int ball_total, int maxM);
 
 // float64 reductions (reduce.hip)

@@ -20,12 +20,12 @@ int tile_count(int v, int nx, int ny, int nz)
     return ((nx + tx - 1) / tx) * ((ny + ty - 1) / ty) * ((nz + tz - 1) / tz);
 }
 
-size_t tile_lds_bytes_of(int v, int reach, int sh_max)
+size_t tile_lds_bytes_of(int v, int reach)
 {
     int tx, ty, tz;
     tile_dims(v, tx, ty, tz);
     if (tx + 2 * reach > kBlock) return SIZE_MAX;   // not stageable: one halo column per thread
-    return tile_lds_bytes(tx, ty, tz, reach, sh_max);
+    return tile_lds_bytes(tx, ty, tz, reach);
 }
 
 size_t contact_lds_bytes_of(int v, int ball_reach, int ball_total, int maxM)
@@ -38,9 +38,9 @@ size_t contact_lds_bytes_of(int v, int ball_reach, int ball_total, int maxM)
 
 namespace {
 template <int TX, int TY, int TZ>
-bool prepare_one(int reach, int sh_max, int ball_reach, int ball_total, int maxM)
+bool prepare_one(int reach, int ball_reach, int ball_total, int maxM)
 {
-    const size_t bytes = tile_lds_bytes(TX, TY, TZ, reach, sh_max);
+    const size_t bytes = tile_lds_bytes(TX, TY, TZ, reach);
     const size_t cbytes = contact_lds_bytes(TX, TY, TZ, ball_reach, ball_total, maxM);
     if (bytes > 160 * 1024 || cbytes > 160 * 1024) return false;
     // staging gives each thread one halo column
@@ -56,11 +56,11 @@ bool prepare_one(int reach, int sh_max, int ball_reach, int ball_total, int maxM
 }
 }  // namespace
 
-bool tile_prepare(int reach_max, int sh_max, int ball_reach_max, int ball_total_max, int maxM)
+bool tile_prepare(int reach_max, int ball_reach_max, int ball_total_max, int maxM)
 {
-    return prepare_one<16, 4, 4>(reach_max, sh_max, ball_reach_max, ball_total_max, maxM) &&
-           prepare_one<8, 8, 4>(reach_max, sh_max, ball_reach_max, ball_total_max, maxM) &&
-           prepare_one<32, 4, 2>(reach_max, sh_max, ball_reach_max, ball_total_max, maxM);
+    return prepare_one<16, 4, 4>(reach_max, ball_reach_max, ball_total_max, maxM) &&
+           prepare_one<8, 8, 4>(reach_max, ball_reach_max, ball_total_max, maxM) &&
+           prepare_one<32, 4, 2>(reach_max, ball_reach_max, ball_total_max, maxM);
 }
 
 void launch_contact_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, Tables<float> tb,
@@ -73,25 +73,25 @@ void launch_contact_tile(int v, const SysDesc<float> *sys, const int2 *map, int 
 }
 
 void launch_gather1_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM, Tables<float> tb,
-                         int reach_max, int sh_max, hipStream_t st)
+                         int reach_max, hipStream_t st)
 {
-    const size_t lds = tile_lds_bytes_of(v, reach_max, sh_max);
+    const size_t lds = tile_lds_bytes_of(v, reach_max);
     const dim3 grid(nblk, maxM);
-    if (v == 0) hipLaunchKernelGGL((k_gather1_tile<16, 4, 4>), grid, dim3(kBlock), lds, st, sys, map, tb);
-    else if (v == 1) hipLaunchKernelGGL((k_gather1_tile<8, 8, 4>), grid, dim3(kBlock), lds, st, sys, map, tb);
-    else hipLaunchKernelGGL((k_gather1_tile<32, 4, 2>), grid, dim3(kBlock), lds, st, sys, map, tb);
+    if (v == 0) hipLaunchKernelGGL((k_gather1_tile<16, 4, 4>), grid, dim3(kGather1Threads), lds, st, sys, map, tb);
+    else if (v == 1) hipLaunchKernelGGL((k_gather1_tile<8, 8, 4>), grid, dim3(kGather1Threads), lds, st, sys, map, tb);
+    else hipLaunchKernelGGL((k_gather1_tile<32, 4, 2>), grid, dim3(kGather1Threads), lds, st, sys, map, tb);
 }
 
 void launch_step2_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM, Tables<float> tb,
-                       int reach_max, int sh_max, int parity, int write_force_only, hipStream_t st)
+                       int reach_max, int parity, int write_force_only, hipStream_t st)
 {
-    const size_t lds = tile_lds_bytes_of(v, reach_max, sh_max);
+    const size_t lds = tile_lds_bytes_of(v, reach_max);
     const dim3 grid(nblk, maxM);
     if (v == 0)
-        hipLaunchKernelGGL((k_step2_tile<16, 4, 4>), grid, dim3(kBlock), lds, st, sys, map, tb, parity, write_force_only);
+        hipLaunchKernelGGL((k_step2_tile<16, 4, 4>), grid, dim3(kStep2Threads), lds, st, sys, map, tb, parity, write_force_only);
     else if (v == 1)
-        hipLaunchKernelGGL((k_step2_tile<8, 8, 4>), grid, dim3(kBlock), lds, st, sys, map, tb, parity, write_force_only);
+        hipLaunchKernelGGL((k_step2_tile<8, 8, 4>), grid, dim3(kStep2Threads), lds, st, sys, map, tb, parity, write_force_only);
     else
-        hipLaunchKernelGGL((k_step2_tile<32, 4, 2>), grid, dim3(kBlock), lds, st, sys, map, tb, parity, write_force_only);
+        hipLaunchKernelGGL((k_step2_tile<32, 4, 2>), grid, dim3(kStep2Threads), lds, st, sys, map, tb, parity, write_force_only);
 }
 }  // namespace mlb
