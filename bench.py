@@ -83,8 +83,8 @@ def algorithmic_work(mix, tail_direct: bool):
         # n, j, g in; V-hat, H, friction tensor out; with the spectral tail
         # (folded in afterwards) also 1 / (1 + Gamma / 2) out
         "gather1": N * w * (4 * M + P + 12 * M + (0 if tail_direct else M)),
-        # f, n, V-hat, g, H, friction tensor, j, u in; f out
-        "step2": N * w * (19 * M + M + 3 * M + P + 3 * M + 6 * M + 3 * M + 3 + 19 * M),
+        # f (not read at omega = 1), n, V-hat, g, H, friction tensor, j, u in; f out
+        "step2": N * w * ((0 if mix.tau == 1.0 else 19 * M) + M + 3 * M + P + 3 * M + 6 * M + 3 * M + 3 + 19 * M),
     }
     return flops, bytes_, S, T
 
@@ -306,6 +306,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tail", choices=["auto", "direct", "spectral"], default="auto")
+    ap.add_argument("--tiling", default=None, metavar="SHAPE,ORDER",
+                    help="fixed tile shape (0: 16x4x4, 1: 8x8x4, 2: 32x4x2) and block order (0 linear, "
+                         "1 XCD-chunked) instead of the start-up autotuning (reproducible profiles)")
     ap.add_argument("--no-d12", action="store_true", help="skip the 2000-step D_12 accuracy check")
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
@@ -334,7 +337,12 @@ def main():
 
     mix, n0, u0 = W.config_bulk_diffusion()
     tail_mode = {"auto": mlb.TAIL_AUTO, "direct": mlb.TAIL_DIRECT, "spectral": mlb.TAIL_SPECTRAL}[args.tail]
-    g = mlb.GpuMixture(mix, n0, u0, precision=32, tail_mode=tail_mode, device="cuda:0", options=mlb.OPT_TUNE)
+    if args.tiling:
+        shape, order = (int(v) for v in args.tiling.split(","))
+        opts = mlb.opt_tiling(shape, order)
+    else:
+        opts = mlb.OPT_TUNE
+    g = mlb.GpuMixture(mix, n0, u0, precision=32, tail_mode=tail_mode, device="cuda:0", options=opts)
     g.step(args.warmup)
     torch.cuda.synchronize()
     # timed region: the steps as mlb_step runs them (pairs replayed from the

@@ -70,6 +70,10 @@ enum { MLB_SCHEME_CN_J1 = 0, MLB_SCHEME_FE = 1 };
 enum { MLB_TAIL_AUTO = 0, MLB_TAIL_DIRECT = 1, MLB_TAIL_SPECTRAL = 2 };
 enum { MLB_OPT_TUNE = 1u,       /* time every tile shape and block order at init, keep the fastest */
        MLB_OPT_NO_GRAPH = 2u }; /* launch the passes eagerly instead of replaying a graph */
+/* Fixed float32 tiling instead of the default or tuned one (overrides
+ * MLB_OPT_TUNE): tile shape 0 = 16x4x4, 1 = 8x8x4, 2 = 32x4x2 sites; block
+ * order 0 = linear, 1 = XCD-chunked.  Reproducible profiles use it. */
+#define MLB_OPT_TILING(shape, order) ((((uint32_t)(shape) + 1u) & 15u) << 4 | ((uint32_t)(order) & 1u) << 8)
 enum { MLB_PART_MF = 1u, MLB_PART_TAIL = 2u, MLB_PART_DISS = 4u, MLB_PART_EXT = 8u,
        MLB_PART_ALL = 15u };
 

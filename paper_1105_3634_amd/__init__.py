@@ -13,10 +13,10 @@ from typing import Dict, Optional, Sequence
 import numpy as np
 
 from . import _lib
-from ._lib import (MlbError, OPT_NO_GRAPH, OPT_TUNE, PART_ALL, PART_DISS, PART_EXT, PART_MF, PART_TAIL, Q,
+from ._lib import (MlbError, OPT_NO_GRAPH, OPT_TUNE, opt_tiling, PART_ALL, PART_DISS, PART_EXT, PART_MF, PART_TAIL, Q,
                    SCHEME_CN_J1, SCHEME_FE, TAIL_AUTO, TAIL_DIRECT, TAIL_SPECTRAL)
 
-__all__ = ["GpuMixture", "GpuBatch", "OPT_TUNE", "OPT_NO_GRAPH", "make_params", "workspace_bytes", "MlbError", "PART_ALL", "PART_MF", "PART_TAIL",
+__all__ = ["GpuMixture", "GpuBatch", "OPT_TUNE", "OPT_NO_GRAPH", "opt_tiling", "make_params", "workspace_bytes", "MlbError", "PART_ALL", "PART_MF", "PART_TAIL",
            "PART_DISS", "PART_EXT", "TAIL_AUTO", "TAIL_DIRECT", "TAIL_SPECTRAL", "SCHEME_CN_J1", "SCHEME_FE"]
 
 

@@ -107,6 +107,11 @@ _SIGS = [
 ]
 OPT_TUNE, OPT_NO_GRAPH = 1, 2
 
+
+def opt_tiling(shape: int, order: int) -> int:
+    """Option bits of a fixed float32 tiling (see MLB_OPT_TILING in mlb.h)."""
+    return ((shape + 1) & 15) << 4 | (order & 1) << 8
+
 _lib = None
 
 

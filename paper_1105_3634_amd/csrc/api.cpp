@@ -982,7 +982,15 @@ mlb_status create(Batch &B, const mlb_params *params, int count, void *workspace
     TRY(init_populations<T>(B, n0, u0, st));
     for (auto &S : B.sys) mlb::launch_zero_i32(reinterpret_cast<int *>(B.ws + S.series_cnt), 1, st);
     HIP_TRY(hipStreamSynchronize(st));
-    if (B.tiled && (options & MLB_OPT_TUNE)) TRY(autotune<T>(B, n0, u0, st));
+    const int fixed_shape = (int)((options >> 4) & 15u) - 1, fixed_order = (int)((options >> 8) & 1u);
+    if (fixed_shape >= mlb::kTileVariants) return fail(MLB_EINVAL, "MLB_OPT_TILING: no such tile shape");
+    if (B.tiled && fixed_shape >= 0) {
+        TRY(set_tiling(B, fixed_shape, fixed_order, st));
+        B.tune.shape = fixed_shape;
+        B.tune.order = fixed_order;
+    } else if (B.tiled && (options & MLB_OPT_TUNE)) {
+        TRY(autotune<T>(B, n0, u0, st));
+    }
     HIP_TRY(hipGetLastError());
     return MLB_OK;
 }

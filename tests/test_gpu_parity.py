@@ -183,3 +183,26 @@ def test_fp32_spectral_bulk_diffusion_100_steps(oracle_lib):
         e = _rel_maxnorm(_np(g.moments()[0]), no)
         print(f"  tail mode {mode}: fp32 density rel err {e:.3e}", flush=True)
         assert e < 1e-5
+
+
+@pytest.mark.parametrize("name", ["walls", "bulk_small"])
+def test_fp32_tilings_agree_bit_for_bit(name):
+    """Every tile shape and block order (MLB_OPT_TILING) sums each site's
+    shell lists in the same order, so the float32 states agree bit for bit."""
+    import paper_1105_3634_amd as mlb
+    m, n0, u0 = _case(name)
+    ref = None
+    for shape in range(3):
+        for order in range(2):
+            print(f"[tilings] case={name} shape={shape} order={order}", flush=True)
+            g = _gpu(m, n0, u0, 32, options=mlb.opt_tiling(shape, order))
+            t = g.tuning()
+            assert (t["shape"], t["order"]) == (shape, order)
+            g.step(6)
+            n, j = g.moments()
+            got = (_np(n), _np(j))
+            del g
+            if ref is None:
+                ref = got
+                continue
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (shape, order)
