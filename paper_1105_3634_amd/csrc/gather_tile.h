@@ -69,25 +69,26 @@ __device__ inline void split_range(int kn, int h, int &kb, int &ke)
     ke = min(kn, kb + part);
 }
 
-// Adds the partial sums of groups 1.. onto group 0's, in group order; the
-// LDS staging area is reused (after a barrier), V floats per site.  Returns
-// false for the threads of groups 1.., which have nothing more to do.
+// Every group ends with the sum of all groups' partial sums, added in group
+// order (the same bits in every group); the LDS staging area is reused after
+// a barrier, V floats per site and group.  The groups then share the
+// epilogue's stores.
 template <int SPLIT, int V>
-__device__ inline bool split_reduce(float4 *lds, float (&v)[V])
+__device__ inline void split_allreduce(float4 *lds, float (&v)[V])
 {
-    if (SPLIT == 1) return true;
+    if (SPLIT == 1) return;
     float *R = reinterpret_cast<float *>(lds);
     const int i = threadIdx.x % kBlock, h = threadIdx.x / kBlock;
     __syncthreads();
-    if (h > 0)
 #pragma unroll
-        for (int j = 0; j < V; ++j) R[((h - 1) * V + j) * kBlock + i] = v[j];
+    for (int j = 0; j < V; ++j) R[(h * V + j) * kBlock + i] = v[j];
     __syncthreads();
-    if (h > 0) return false;
-    for (int g = 0; g < SPLIT - 1; ++g)
 #pragma unroll
-        for (int j = 0; j < V; ++j) v[j] += R[(g * V + j) * kBlock + i];
-    return true;
+    for (int j = 0; j < V; ++j) {
+        float acc = R[j * kBlock + i];
+        for (int g = 1; g < SPLIT; ++g) acc += R[(g * V + j) * kBlock + i];
+        v[j] = acc;
+    }
 }
 
 // Field pointers cast to the global address space: loads and stores then
@@ -272,7 +273,10 @@ k_gather1_tile(const SysDesc<float> *__restrict__ sys,
     const char *c4 = reinterpret_cast<const char *>(L4 + q.c);
     const char *cg = reinterpret_cast<const char *>(Lg + q.c);
     const bool solid = q.active && S.walls && (q.y == 0 || q.y == S.ny - 1);
-    const long long sc = q.active && h == 0 ? q.s : 0;
+    // group 0 stores H and V-hat, group 1 (or 0 when alone) the friction
+    // tensor and 1 / (1 + Gamma / 2)
+    const bool do_hv = h == 0, do_t = kSplitG1 == 1 || h == 1;
+    const long long sc = q.active && (do_hv || do_t) ? q.s : 0;
     const float na = glb(S.n)[(long long)a * N + sc];
     const float ja0 = glb(S.j)[o3 + sc], ja1 = glb(S.j)[o3 + N + sc], ja2 = glb(S.j)[o3 + 2 * N + sc];
     float mf0 = 0.f, mf1 = 0.f, mf2 = 0.f, dj0 = 0.f, dj1 = 0.f, dj2 = 0.f, gam = 0.f;
@@ -315,22 +319,32 @@ k_gather1_tile(const SysDesc<float> *__restrict__ sys,
         gam += S.cg[a][b] * (t00 + t11 + t22);
     }
     float part[13] = {mf0, mf1, mf2, dj0, dj1, dj2, gam, T00, T01, T02, T11, T12, T22};
-    if (!split_reduce<kSplitG1>(lds, part)) return;
+    split_allreduce<kSplitG1>(lds, part);
     mf0 = part[0]; mf1 = part[1]; mf2 = part[2]; dj0 = part[3]; dj1 = part[4]; dj2 = part[5]; gam = part[6];
     T00 = part[7]; T01 = part[8]; T02 = part[9]; T11 = part[10]; T12 = part[11]; T22 = part[12];
-    if (!q.active) return;
+    if (!q.active || !(do_hv || do_t)) return;
     const long long s = q.s;
     gfloat *__restrict__ Tout = glb(S.Tloc) + (long long)a * 6 * N;
     if (solid) {
-        for (int d = 0; d < 3; ++d) {
-            glb(S.vh)[o3 + d * N + s] = 0.f;
-            glb(S.H)[o3 + d * N + s] = 0.f;
-            if (S.parts) glb(S.parts)[o3 + d * N + s] = 0.f;
+        if (do_hv)
+            for (int d = 0; d < 3; ++d) {
+                glb(S.vh)[o3 + d * N + s] = 0.f;
+                glb(S.H)[o3 + d * N + s] = 0.f;
+                if (S.parts) glb(S.parts)[o3 + d * N + s] = 0.f;
+            }
+        if (do_t) {
+            for (int d = 0; d < 6; ++d) Tout[d * N + s] = 0.f;
+            if (S.tail_deferred) glb(S.gfac)[(long long)a * N + s] = 0.f;
         }
-        for (int d = 0; d < 6; ++d) Tout[d * N + s] = 0.f;
-        if (S.tail_deferred) glb(S.gfac)[(long long)a * N + s] = 0.f;
         return;
     }
+    const float hg = 0.5f * gam;
+    if (do_t) {
+        if (S.tail_deferred) glb(S.gfac)[(long long)a * N + s] = (na != 0.f) ? 1.f / (1.f + hg) : 0.f;
+        Tout[0 * N + s] = T00; Tout[1 * N + s] = T01; Tout[2 * N + s] = T02;
+        Tout[3 * N + s] = T11; Tout[4 * N + s] = T12; Tout[5 * N + s] = T22;
+    }
+    if (!do_hv) return;
     float tl0 = 0.f, tl1 = 0.f, tl2 = 0.f;
     if (S.tail && !S.tail_deferred) {
         tl0 = glb(S.tail)[o3 + s]; tl1 = glb(S.tail)[o3 + N + s]; tl2 = glb(S.tail)[o3 + 2 * N + s];
@@ -339,8 +353,6 @@ k_gather1_tile(const SysDesc<float> *__restrict__ sys,
     const float djv[3] = {dj0, dj1, dj2};
     const float Tj[3] = {T00 * ja0 + T01 * ja1 + T02 * ja2, T01 * ja0 + T11 * ja1 + T12 * ja2,
                          T02 * ja0 + T12 * ja1 + T22 * ja2};
-    const float hg = 0.5f * gam;
-    if (S.tail_deferred) glb(S.gfac)[(long long)a * N + s] = (na != 0.f) ? 1.f / (1.f + hg) : 0.f;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const float Nmf = na * mfv[d], Ntl = na * tlv[d], Nex = na * S.fext[a][d];
@@ -362,8 +374,6 @@ k_gather1_tile(const SysDesc<float> *__restrict__ sys,
             glb(S.parts)[o3 + d * N + s] = acc;
         }
     }
-    Tout[0 * N + s] = T00; Tout[1 * N + s] = T01; Tout[2 * N + s] = T02;
-    Tout[3 * N + s] = T11; Tout[4 * N + s] = T12; Tout[5 * N + s] = T22;
 }
 
 // ------------------------------- second gather + collision + push streaming
@@ -390,9 +400,12 @@ k_step2_tile(const SysDesc<float> *__restrict__ sys,
     const int HXY = t.HX * t.HY;
     const int h = __builtin_amdgcn_readfirstlane(threadIdx.x / kBlock);   // wave-uniform
     // The collision's inputs are loaded before the gathers, so that their
-    // latency hides behind the shell loops; group 0 owns the collision.
+    // latency hides behind the shell loops.  Every group forms the total
+    // force; group h collides and streams populations [ib, ie).
+    constexpr int kPer = (kQ + kSplitS2 - 1) / kSplitS2;
+    const int ib = min(kQ, h * kPer), ie = min(kQ, ib + kPer);
     const bool fluid = q.active && !(S.walls && (q.y == 0 || q.y == S.ny - 1));
-    const bool epi = h == 0 && fluid;
+    const bool epi = fluid && (ib < ie || (h == 0 && write_force_only));
     const bool need_f = epi && !write_force_only && S.omega_is_one == 0;
     const long long s = q.s;
     float na = 0.f, Na[3] = {0.f, 0.f, 0.f}, Tl[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, va[3] = {0.f, 0.f, 0.f};
@@ -419,7 +432,7 @@ k_step2_tile(const SysDesc<float> *__restrict__ sys,
     {
         const gfloat *__restrict__ fin = glb(S.f[parity]) + (long long)a * kQ * N;
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) fi[i] = need_f ? fin[(long long)i * N + s] : 0.f;
+        for (int i = 0; i < kQ; ++i) fi[i] = (need_f && i >= ib && i < ie) ? fin[(long long)i * N + s] : 0.f;
     }
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
     if (S.scheme != 1) {
@@ -454,17 +467,16 @@ k_step2_tile(const SysDesc<float> *__restrict__ sys,
             acc0 += ck * v0; acc1 += ck * v1; acc2 += ck * v2;
         }
         float part[3] = {acc0, acc1, acc2};
-        if (!split_reduce<kSplitS2>(lds, part)) return;
+        split_allreduce<kSplitS2>(lds, part);
         acc0 = part[0]; acc1 = part[1]; acc2 = part[2];
-    } else if (h > 0) {
-        return;
     }
     if (!q.active) return;
     if (!fluid) {
-        if (write_force_only)
+        if (write_force_only && h == 0)
             for (int d = 0; d < 3; ++d) glb(S.Nf)[o3 + d * N + s] = 0.f;
         return;
     }
+    if (!epi) return;
     if (S.scheme != 1) {
         const float T00 = Tl[0], T01 = Tl[1], T02 = Tl[2], T11 = Tl[3], T12 = Tl[4], T22 = Tl[5];
         const float va0 = va[0], va1 = va[1], va2 = va[2];
@@ -474,11 +486,12 @@ k_step2_tile(const SysDesc<float> *__restrict__ sys,
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             Na[d] += 0.5f * Dn[d];
-            if (S.parts && (S.parts_mask & 4u)) glb(S.parts)[o3 + d * N + s] += 0.5f * Dn[d];
+            if (h == 0 && S.parts && (S.parts_mask & 4u)) glb(S.parts)[o3 + d * N + s] += 0.5f * Dn[d];
         }
     }
     if (write_force_only) {
-        for (int d = 0; d < 3; ++d) glb(S.Nf)[o3 + d * N + s] = Na[d];
+        if (h == 0)
+            for (int d = 0; d < 3; ++d) glb(S.Nf)[o3 + d * N + s] = Na[d];
         return;
     }
     gfloat *__restrict__ fout = glb(S.f[parity ^ 1]) + (long long)a * kQ * N;
@@ -486,6 +499,7 @@ k_step2_tile(const SysDesc<float> *__restrict__ sys,
     const Site r{q.x, q.y, q.z};
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
+        if (i < ib || i >= ie) continue;
         const float fs = post_collision<float>(i, fi[i], w1, S.omega, S.om1, na, ja, u, Na);
         const int yy = q.y + kC[i][1];
         if (S.walls && (yy == 0 || yy == S.ny - 1)) {
@@ -568,12 +582,12 @@ inline size_t contact_lds_bytes(int TX, int TY, int TZ, int R, int ball_total, i
 
 // float4 + float per staged site, then the row-offset table (one int per
 // halo row); at least the partial sums of the split reductions (13 floats
-// per site and extra group in the first gather, 3 in the second)
+// per site and group in the first gather, 3 in the second)
 inline size_t tile_lds_bytes(int TX, int TY, int TZ, int R)
 {
     const size_t FS = (size_t)(TX + 2 * R) * (TY + 2 * R) * (TZ + 2 * R);
     const size_t rows = (size_t)(TY + 2 * R) * (TZ + 2 * R);
-    const size_t reduce = std::max((size_t)(kSplitG1 - 1) * 13, (size_t)(kSplitS2 - 1) * 3) * kBlock * 4;
+    const size_t reduce = std::max((size_t)kSplitG1 * 13, (size_t)kSplitS2 * 3) * kBlock * 4;
     return std::max(16 * FS + 16 * ((FS + 3) / 4) + 4 * rows, reduce);
 }
 
