@@ -468,13 +468,23 @@ __global__ void __launch_bounds__(kBlock) k_add_tail(const SysDesc<T> *__restric
     if (is_solid(S, r.y)) return;
     const long long o3 = (long long)a * 3 * N;
     const T na = S.n[(long long)a * N + s], gf = S.gfac[(long long)a * N + s];
+    // all loads first: the stores could alias them as far as the compiler
+    // knows, which would serialise the three components
+    const bool fe = S.scheme == 1, pt = S.parts && (S.parts_mask & 2u);
+    T c[3], h[3], v[3], pp[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const T c = S.tail[o3 + d * N + s];
-        const T ntl = na * c;
-        S.H[o3 + d * N + s] += ntl;
-        if (S.scheme != 1) S.vh[o3 + d * N + s] += c * gf;
-        if (S.parts && (S.parts_mask & 2u)) S.parts[o3 + d * N + s] += ntl;
+        c[d] = S.tail[o3 + d * N + s];
+        h[d] = S.H[o3 + d * N + s];
+        v[d] = fe ? T(0) : S.vh[o3 + d * N + s];
+        pp[d] = pt ? S.parts[o3 + d * N + s] : T(0);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const T ntl = na * c[d];
+        S.H[o3 + d * N + s] = h[d] + ntl;
+        if (!fe) S.vh[o3 + d * N + s] = v[d] + c[d] * gf;
+        if (pt) S.parts[o3 + d * N + s] = pp[d] + ntl;
     }
 }
 
