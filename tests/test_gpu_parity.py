@@ -44,6 +44,11 @@ def _case(name):
         return (m,) + W.random_state(m, [0.006, 0.004], rel=0.3, u_amp=0.02, seed=14)
     if name == "bulk_small":
         return W.config_bulk_diffusion(32, 24, 24, seed=5)
+    if name == "quaternary_wide":
+        # four species up to sigma = 5: shell reach 5, wrapped halos larger
+        # than the box in y and z, seven distinct shells
+        m = W.Mixture(14, 13, 12, sigma=(2.0, 3.0, 4.0, 5.0))
+        return (m,) + W.random_state(m, [0.01, 0.005, 0.002, 0.001], rel=0.3, u_amp=0.02, seed=15)
     raise KeyError(name)
 
 
@@ -83,7 +88,7 @@ def _rel_maxnorm(got, ref):
 
 
 @pytest.mark.parametrize("name,steps", [("step_binary", 100), ("bulk_small", 100), ("walls", 100),
-                                        ("fe_tau", 60), ("ternary_tail_ext", 50)])
+                                        ("fe_tau", 60), ("ternary_tail_ext", 50), ("quaternary_wide", 30)])
 def test_fp32_densities_within_1e5(oracle_lib, name, steps):
     m, n0, u0 = _case(name)
     print(f"[fp32 densities] case={name} shape={m.shape()} steps={steps}", flush=True)
