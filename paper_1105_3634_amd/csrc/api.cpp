@@ -65,6 +65,7 @@ struct HostTables {
     int bl_start[mlb::kMaxS] = {}, bl_cnt[mlb::kMaxS] = {}, bl_full[mlb::kMaxS] = {};
     int reach[3] = {0, 0, 0};
     int shell_reach = 0, ball_reach = 0;
+    int tail_reach_y = 0;   // largest |e_y| of any tail offset
 };
 
 bool validate(const mlb_params *p, std::string &why)
@@ -138,6 +139,7 @@ bool build_tables(const mlb_params *p, HostTables &t, std::string &why)
                     t.tl_w.push_back(coef * tl.v[3 * k + 2]);
                 }
                 t.tl_e.insert(t.tl_e.end(), tl.e.begin(), tl.e.end());
+                t.tail_reach_y = std::max(t.tail_reach_y, tl.max_abs[1]);
                 reach(tl);
             }
         }
@@ -152,11 +154,27 @@ bool build_tables(const mlb_params *p, HostTables &t, std::string &why)
 
 bool has_tail(const HostTables &t) { return !t.tl_e.empty(); }
 
-// Spectral attractive field: float32, a tail on some pair, y periodic, single system.
+// Transform length along y of the spectral field: ny for a periodic box;
+// with walls, y is zero-padded past the tail's reach (rounded up to a
+// multiple of 8), so the circular convolution on the padded line equals the
+// linear one, in which points beyond the walls contribute nothing.
+int spectral_ny(const mlb_params *p, const HostTables &t)
+{
+    if (!p->walls_y) return p->ny;
+    return (p->ny + t.tail_reach_y + 7) / 8 * 8;
+}
+
+// Spectral attractive field: float32, a tail on some pair, single system,
+// the (y, z) plane of the transform within the LDS budget.
+bool spectral_possible(const mlb_params *p, const HostTables &t, int count)
+{
+    if (!has_tail(t) || p->precision != 32 || count != 1) return false;
+    return mlb::SpectralPlan::fused_fits(spectral_ny(p, t), p->nz, p->nspecies);
+}
+
 bool wants_spectral(const mlb_params *p, const HostTables &t, int count)
 {
-    if (!has_tail(t) || p->walls_y || p->precision != 32 || count != 1) return false;
-    if (!mlb::SpectralPlan::fused_fits(p->ny, p->nz, p->nspecies)) return false;
+    if (!spectral_possible(p, t, count)) return false;
     return p->tail_mode == MLB_TAIL_AUTO || p->tail_mode == MLB_TAIL_SPECTRAL;
 }
 
@@ -287,10 +305,8 @@ bool plan_batch(Batch &B, const mlb_params *params, int count, std::string &why)
         S.P = S.M * (S.M + 1) / 2;
         S.N = (long long)S.p.nx * S.p.ny * S.p.nz;
         S.nblocks = (int)((S.N + mlb::kBlock - 1) / mlb::kBlock);
-        if (S.p.tail_mode == MLB_TAIL_SPECTRAL && has_tail(S.tabs) &&
-            (B.prec != 32 || S.p.walls_y || count != 1 ||
-             !mlb::SpectralPlan::fused_fits(S.p.ny, S.p.nz, S.p.nspecies))) {
-            why = "the spectral tail needs float32, a periodic box, a single system and a (y, z) plane that fits LDS";
+        if (S.p.tail_mode == MLB_TAIL_SPECTRAL && has_tail(S.tabs) && !spectral_possible(&S.p, S.tabs, count)) {
+            why = "the spectral tail needs float32, a single system and a (y, z) transform plane that fits LDS";
             return false;
         }
         S.spectral = wants_spectral(&S.p, S.tabs, count);
@@ -360,12 +376,13 @@ bool plan_batch(Batch &B, const mlb_params *params, int count, std::string &why)
         S.Nf = take(ts * 3 * M * N);
         S.Tloc = B.tiled ? take(ts * 6 * M * N) : 0;
         if (S.spectral) {
-            const size_t nkx = (size_t)S.p.nx / 2 + 1, Sp = nkx * S.p.ny * S.p.nz;
+            const size_t nyt = (size_t)spectral_ny(&S.p, S.tabs);
+            const size_t nkx = (size_t)S.p.nx / 2 + 1, Sp = nkx * nyt * S.p.nz;
             const size_t fields = std::max(3 * M, 3 * P);
             S.wxf = take(sizeof(float) * S.p.nx * 2 * nkx);
             S.wxi = take(sizeof(float) * 2 * nkx * S.p.nx);
-            S.wyf = take(sizeof(float) * 4 * S.p.ny * S.p.ny);
-            S.wyi = take(sizeof(float) * 4 * S.p.ny * S.p.ny);
+            S.wyf = take(sizeof(float) * 4 * nyt * nyt);
+            S.wyi = take(sizeof(float) * 4 * nyt * nyt);
             S.wzf = take(sizeof(float) * 4 * S.p.nz * S.p.nz);
             S.wzi = take(sizeof(float) * 4 * S.p.nz * S.p.nz);
             S.S = take(sizeof(float) * 3 * P * Sp);
@@ -531,7 +548,8 @@ mlb_status setup_spectral(Batch &B, SysHost &S, hipStream_t st)
     const mlb_params *p = &S.p;
     mlb::SpectralPlan &pl = S.plan;
     char *ws = B.ws;
-    pl.nx = p->nx; pl.ny = p->ny; pl.nz = p->nz; pl.nkx = p->nx / 2 + 1;
+    const int nyt = spectral_ny(p, S.tabs);
+    pl.nx = p->nx; pl.ny = nyt; pl.nyr = p->ny; pl.nz = p->nz; pl.nkx = p->nx / 2 + 1;
     pl.M = S.M; pl.P = S.P;
     pl.Sz = (long long)pl.ny * pl.nkx;
     pl.Sp = pl.Sz * pl.nz;
@@ -543,13 +561,17 @@ mlb_status setup_spectral(Batch &B, SysHost &S, hipStream_t st)
     pl.wzi = reinterpret_cast<const float *>(ws + S.wzi);
     pl.S = reinterpret_cast<float *>(ws + S.S);
     std::vector<float> m[6] = {mlb::SpectralPlan::dft_x_forward(p->nx), mlb::SpectralPlan::dft_x_inverse(p->nx),
-                               mlb::SpectralPlan::dft_block(p->ny, false), mlb::SpectralPlan::dft_block(p->ny, true),
+                               mlb::SpectralPlan::dft_block(nyt, false), mlb::SpectralPlan::dft_block(nyt, true),
                                mlb::SpectralPlan::dft_block(p->nz, false), mlb::SpectralPlan::dft_block(p->nz, true)};
-    if (!mlb::SpectralPlan::prepare(p->ny, p->nz, S.M)) return fail(MLB_EHIP, "cannot raise the LDS limit of the tail kernel");
+    if (!mlb::SpectralPlan::prepare(nyt, p->nz, S.M)) return fail(MLB_EHIP, "cannot raise the LDS limit of the tail kernel");
     const size_t offs[6] = {S.wxf, S.wxi, S.wyf, S.wyi, S.wzf, S.wzi};
     for (int k = 0; k < 6; ++k)
         HIP_TRY(hipMemcpyAsync(ws + offs[k], m[k].data(), sizeof(float) * m[k].size(), hipMemcpyHostToDevice, st));
-    const long long N = S.N;
+    // the kernels w_ab placed on the transform grid (nx x nyt x nz), offsets
+    // wrapped on it; the placed fields are staged in the second population
+    // buffer, not yet in use
+    const long long N = (long long)p->nx * nyt * p->nz;
+    if ((size_t)3 * S.P * N > (size_t)mlb::kQ * S.M * S.N) return fail(MLB_EINVAL, "padded tail transform too large");
     std::vector<float> placed((size_t)3 * S.P * N, 0.0f);
     std::vector<double> acc((size_t)3 * N);
     const HostTables &t = S.tabs;
@@ -562,9 +584,9 @@ mlb_status setup_spectral(Batch &B, SysHost &S, hipStream_t st)
                 mlb::unpack_offset(t.tl_e[t.tl_start[a][b] + k], ex, ey, ez);
                 for (int sgn = -1; sgn <= 1; sgn += 2) {
                     const int x = ((sgn * ex) % p->nx + p->nx) % p->nx;
-                    const int y = ((sgn * ey) % p->ny + p->ny) % p->ny;
+                    const int y = ((sgn * ey) % nyt + nyt) % nyt;
                     const int z = ((sgn * ez) % p->nz + p->nz) % p->nz;
-                    const long long site = ((long long)z * p->ny + y) * p->nx + x;
+                    const long long site = ((long long)z * nyt + y) * p->nx + x;
                     for (int d = 0; d < 3; ++d) acc[(size_t)d * N + site] += sgn * t.tl_w[3 * (t.tl_start[a][b] + k) + d];
                 }
             }

@@ -27,6 +27,7 @@ void launch_gemm(const GemmDesc &g, hipStream_t st);
 
 struct SpectralPlan {
     int nx = 0, ny = 0, nz = 0, nkx = 0, M = 0, P = 0;
+    int nyr = 0;                  // lattice ny; ny is the transform length (zero-padded past walls)
     long long Sz = 0, Sp = 0;     // ny * nkx,  nz * ny * nkx
     // device matrices (row-major)
     const float *wxf = nullptr;   // nx x 2nkx        [cos | -sin]
@@ -40,8 +41,10 @@ struct SpectralPlan {
     static std::vector<float> dft_x_inverse(int nx);
     static std::vector<float> dft_block(int L, bool inverse);
 
-    // x stage as batched GEMMs; spectra in [field][kx][re|im][z][y]
-    void x_forward(const float *real_in, int nfields, float *s1, hipStream_t st) const;
+    // x stage as batched GEMMs; spectra in [field][kx][re|im][z][y], y < ny;
+    // lattice fields fill y < nyr (the rest is zero-padding), the placed
+    // kernels (on_transform_grid) every y < ny
+    void x_forward(const float *real_in, int nfields, float *s1, hipStream_t st, bool on_transform_grid = false) const;
     void x_inverse(const float *s2, int nfields, float *real_out, hipStream_t st) const;
     // y/z stages, one workgroup per kx plane and field: mode 0 forward -> sine
     // spectra of the kernels, 1 forward -> spectra, 2 products + inverse (3M outputs)

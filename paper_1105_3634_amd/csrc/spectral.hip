@@ -177,6 +177,7 @@ __device__ inline int fdiv(int n, FastDiv d)
 
 struct YZArgs {
     int ny, nz, M, mode;          // mode 0: forward -> sine spectra of the kernels; 1: forward -> spectra
+    int ny_real;                  // lattice rows of a plane; rows ny_real.. are zero-padding (mode 1)
     int PS;                       // ny * nz (one real part of a plane)
     long long Sp, FSTR;           // per-field spectrum part size, field stride in the spectra buffers
     FastDiv div_ny;
@@ -262,7 +263,7 @@ __global__ void __launch_bounds__(256) k_yz_forward(YZArgs a)
     for (int i = threadIdx.x; i < P2; i += blockDim.x) {
         const int p = i >= a.PS ? 1 : 0;
         const int r = i - p * a.PS, z = fdiv(r, a.div_ny), y = r - z * a.ny;
-        X[p * g.PX + z * g.RY + y] = src[i];
+        X[p * g.PX + z * g.RY + y] = (a.mode == 0 || y < a.ny_real) ? src[i] : 0.f;
     }
     __syncthreads();
     yz_stage_y(g, a.wy, X, T);
@@ -353,26 +354,34 @@ MatAddr dense(const float *base, long long ld)
 
 }  // namespace
 
-void SpectralPlan::x_forward(const float *real_in, int nfields, float *s1, hipStream_t st) const
+void SpectralPlan::x_forward(const float *real_in, int nfields, float *s1, hipStream_t st, bool on_transform_grid) const
 {
     // rows (z, y) of each field; output columns (plane, kx) into [f][kx][p][z][y]
+    const int rows_y = on_transform_grid ? ny : nyr;
     GemmDesc gx{};
-    gx.M = nz * ny; gx.N = 2 * nkx; gx.K = nx; gx.batch = nfields;
-    gx.A = dense(real_in, nx); gx.A.s_tlo = (long long)nx * ny * nz;
+    gx.M = nz * rows_y; gx.N = 2 * nkx; gx.K = nx; gx.batch = nfields;
+    gx.A = dense(real_in, nx); gx.A.s_tlo = (long long)nx * rows_y * nz;
     gx.B = dense(wxf, 2 * nkx);
     gx.C = dense(s1, 1); gx.C.s_tlo = 2 * Sp; gx.C.c_div = nkx; gx.C.s_chi = (long long)ny * nz;
     gx.C.s_clo = 2LL * ny * nz;
+    if (rows_y != ny) {   // row (z, y) of the lattice -> z ny + y of the padded plane
+        gx.C.r_div = rows_y; gx.C.s_rhi = ny; gx.C.s_rlo = 1;
+    }
     launch_gemm(gx, st);
 }
 
 void SpectralPlan::x_inverse(const float *s2, int nfields, float *real_out, hipStream_t st) const
 {
+    // lattice rows only: row (z, y) reads z ny + y of the padded plane
     GemmDesc gx{};
-    gx.M = nz * ny; gx.N = nx; gx.K = 2 * nkx; gx.batch = nfields;
+    gx.M = nz * nyr; gx.N = nx; gx.K = 2 * nkx; gx.batch = nfields;
     gx.A = dense(s2, 1); gx.A.s_tlo = 2 * Sp; gx.A.c_div = nkx; gx.A.s_chi = (long long)ny * nz;
     gx.A.s_clo = 2LL * ny * nz;
+    if (nyr != ny) {
+        gx.A.r_div = nyr; gx.A.s_rhi = ny; gx.A.s_rlo = 1;
+    }
     gx.B = dense(wxi, nx);
-    gx.C = dense(real_out, nx); gx.C.s_tlo = (long long)nx * ny * nz;
+    gx.C = dense(real_out, nx); gx.C.s_tlo = (long long)nx * nyr * nz;
     launch_gemm(gx, st);
 }
 
@@ -393,6 +402,7 @@ void SpectralPlan::launch_yz(int mode, int nfields, const float *in, float *out,
 {
     YZArgs a{};
     a.ny = ny; a.nz = nz; a.M = M; a.mode = mode;
+    a.ny_real = nyr;
     a.PS = ny * nz; a.Sp = Sp; a.FSTR = 2 * Sp;
     a.div_ny = make_fastdiv(ny);
     a.in = in; a.out = out; a.S = S;
@@ -421,7 +431,7 @@ void SpectralPlan::build_spectrum(const float *placed, float *s1, float *s2, hip
 {
     (void)s2;
     const int nf = 3 * P;
-    x_forward(placed, nf, s1, st);
+    x_forward(placed, nf, s1, st, true);
     launch_yz(0, nf, s1, S, st);
 }
 

@@ -44,6 +44,9 @@ def _case(name):
         return (m,) + W.random_state(m, [0.006, 0.004], rel=0.3, u_amp=0.02, seed=14)
     if name == "bulk_small":
         return W.config_bulk_diffusion(32, 24, 24, seed=5)
+    if name == "couette_small":
+        # the Taylor/Couette physics (ternary, tail 0.3 kT, moving walls) on 48x20x12
+        return W.config_taylor_couette(48, 20, 12)
     if name == "quaternary_wide":
         # four species up to sigma = 5: shell reach 5, wrapped halos larger
         # than the box in y and z, seven distinct shells
@@ -154,16 +157,20 @@ def test_conserved_sums_fp64(oracle_lib):
             assert drift < 6e-8 * mass0.sum() * steps
 
 
-@pytest.mark.parametrize("shape", [(16, 16, 16), (24, 12, 14), (15, 13, 17), (40, 20, 24)])
-def test_fp32_spectral_tail_matches_direct_sum(oracle_lib, shape):
+@pytest.mark.parametrize("shape,walls", [((16, 16, 16), False), ((24, 12, 14), False), ((15, 13, 17), False),
+                                         ((40, 20, 24), False), ((24, 18, 14), True), ((16, 21, 12), True)])
+def test_fp32_spectral_tail_matches_direct_sum(oracle_lib, shape, walls):
     """The MFMA DFT path of the attractive field against the oracle's float64
     direct sum (also checks the matrix-core lane layout: a wrong layout
-    scrambles the field)."""
+    scrambles the field).  With walls the transform runs on y zero-padded past
+    the tail's reach, so points beyond the walls contribute nothing, as in
+    the direct sum."""
     import paper_1105_3634_amd as mlb
     eps = np.array([[0.15, 0.1], [0.1, 0.05]])
-    m = W.Mixture(*shape, sigma=(1.5, 2.5), eps=eps, rc_factor=2.2)
+    kw = dict(walls_y=True, wall_ux=(-0.02, 0.03)) if walls else {}
+    m = W.Mixture(*shape, sigma=(1.5, 2.5), eps=eps, rc_factor=2.2, **kw)
     n0, u0 = W.random_state(m, [0.02, 0.01], rel=0.5, u_amp=0.01, seed=21)
-    print(f"[spectral tail] shape={m.shape()}", flush=True)
+    print(f"[spectral tail] shape={m.shape()} walls={walls}", flush=True)
     o = oracle_lib.Oracle(m)
     ref = o.fields(o.init(n0, u0))
     for mode in (mlb.TAIL_SPECTRAL, mlb.TAIL_DIRECT):
@@ -177,9 +184,10 @@ def test_fp32_spectral_tail_matches_direct_sum(oracle_lib, shape):
         assert err < 1e-5, (mode, err)
 
 
-def test_fp32_spectral_bulk_diffusion_100_steps(oracle_lib):
+@pytest.mark.parametrize("name", ["bulk_small", "couette_small"])
+def test_fp32_spectral_100_steps(oracle_lib, name):
     import paper_1105_3634_amd as mlb
-    m, n0, u0 = _case("bulk_small")
+    m, n0, u0 = _case(name)
     o = oracle_lib.Oracle(m)
     no = o.fields(o.step(o.init(n0, u0), 100))["n"]
     for mode in (mlb.TAIL_SPECTRAL, mlb.TAIL_DIRECT):
