@@ -283,6 +283,50 @@ def ensemble_leg(mlb, W, steps=1000, timed=200):
     }
 
 
+def taylor_leg(mlb, W, steps=5000, timed=200, packing=0.2):
+    """Taylor dispersion: the ternary mixture in Couette flow between walls
+    moving at -+U (256x64x16, tail 0.3 kT, spectral tail zero-padded past the
+    walls), a Gaussian tracer band of species 3; the axial spread of the
+    tracer is recorded every 10 steps and D_eff is half the slope of its
+    variance; throughput of `timed` graph-replayed steps.  Packing 0.2: at
+    0.25 the fluid piles up against the zero-density wall layers (no wall
+    potential) and the state diverges within 500 steps, in float64 too."""
+    import torch
+
+    mix, n0, u0 = W.config_taylor_couette(packing=packing)
+    g = mlb.GpuMixture(mix, n0, u0, precision=32, device="cuda:0", options=mlb.OPT_TUNE)
+    ssu_step = mix.M * mix.N
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(0, steps + 1, 10):
+        g.record_spread(2)
+        if t < steps:
+            g.step(10)
+    torch.cuda.synchronize()
+    run_s = time.perf_counter() - t0
+    d_eff = g.fit(1, t_min=steps / 5)
+    mass, _ = g.conserved()
+    g.step(4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(timed)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    g.profile_begin()
+    g.step(10)
+    passes = g.profile_end()
+    tune = g.tuning()
+    return {
+        "workload": f"taylor_couette_{mix.nx}x{mix.ny}x{mix.nz}", "species": mix.M, "sites": mix.N,
+        "packing": packing,
+        "ssu_per_s": ssu_step * timed / dt, "ms_per_step": dt * 1e3 / timed,
+        "run_with_spread_records": {"steps": steps, "seconds": run_s},
+        "d_eff": d_eff, "mass_finite": bool(np.all(np.isfinite(mass))),
+        "tuning": {"shape": ["16x4x4", "8x8x4", "32x4x2"][tune["shape"]], "order": ["linear", "xcd-chunked"][tune["order"]]},
+        "passes_ms_per_step": {k: v[0] / 10 for k, v in passes.items() if v[1]},
+    }
+
+
 def cpu_baseline(mix, n0, u0, target_s=12.0):
     import oracle
     o = oracle.Oracle(mix)
@@ -312,6 +356,7 @@ def main():
     ap.add_argument("--no-d12", action="store_true", help="skip the 2000-step D_12 accuracy check")
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
+    ap.add_argument("--no-taylor", action="store_true", help="skip the Taylor-dispersion (walls) leg")
     ap.add_argument("--closure-steps", type=int, default=5000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB elementwise copy (counter calibration for profiles)")
@@ -414,6 +459,11 @@ def main():
             line["ensemble"] = ensemble_leg(mlb, W)
         except Exception as exc:      # reported in the line; the headline stands on its own
             line["ensemble"] = {"error": f"{type(exc).__name__}: {exc}"}
+    if not args.no_taylor:
+        try:
+            line["taylor"] = taylor_leg(mlb, W)
+        except Exception as exc:      # reported in the line; the headline stands on its own
+            line["taylor"] = {"error": f"{type(exc).__name__}: {exc}"}
     if not args.no_closure:
         try:
             line["closure"] = closure_leg(mlb, W, steps=args.closure_steps)

@@ -167,14 +167,14 @@ def config_bulk_diffusion(nx=128, ny=32, nz=32, seed=2024, noise=0.01) -> Tuple[
     return m, n0, u0
 
 
-def config_taylor_couette(nx=256, ny=64, nz=16, U=0.05) -> Tuple[Mixture, np.ndarray, np.ndarray]:
-    """Ternary, sigma = 2, 3, 4, packing 0.25, eps/kT = 0.3 (cutoff 2.5 sigma),
-    bounce-back walls at y = 0 and ny-1 moving at -U and +U, Gaussian tracer
-    band of species 3 (width 8) centred in x."""
+def config_taylor_couette(nx=256, ny=64, nz=16, U=0.05, packing=0.25) -> Tuple[Mixture, np.ndarray, np.ndarray]:
+    """Ternary, sigma = 2, 3, 4, packing 0.25 (or `packing`), eps/kT = 0.3
+    (cutoff 2.5 sigma), bounce-back walls at y = 0 and ny-1 moving at -U and
+    +U, Gaussian tracer band of species 3 (width 8) centred in x."""
     eps = np.full((3, 3), 0.3 * KT)
     m = Mixture(nx, ny, nz, sigma=(2.0, 3.0, 4.0), eps=eps, rc_factor=2.5, walls_y=True,
                 wall_ux=(-U, U), name=f"taylor_couette_{nx}x{ny}x{nz}")
-    n = number_density(0.25, (0.5, 0.5), m.sigma[:2])
+    n = number_density(packing, (0.5, 0.5), m.sigma[:2])
     n0, u0 = tracer_band_state(m, n)
     return m, n0, u0
 
