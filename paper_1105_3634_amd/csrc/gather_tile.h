@@ -187,15 +187,30 @@ __device__ inline void stage(const SysDesc<float> &S, const TileGeo &t, const St
     }
 }
 
-// One scalar field of the halo tile (zero outside the walls).
+// One scalar field of the halo tile (zero outside the walls).  The thread's
+// rows go in batches of 8 whose loads are all issued before the first store
+// to LDS (one wait for memory per batch); rows outside the walls read site 0
+// and store zero.
 __device__ inline void stage1(const TileGeo &t, const StageLane &l, const int *RowOff, float *dst,
                               const gfloat *__restrict__ src)
 {
     const int rows = t.HY * t.HZ;
     if (l.rstep == 0) return;
-    for (int row = l.row0; row < rows; row += l.rstep) {
-        const int ro = RowOff[row];
-        dst[l.hx + row * t.HX] = ro >= 0 ? src[(unsigned)(ro + l.gx)] : 0.f;
+    constexpr int B = 8;
+    for (int row0 = l.row0; row0 < rows; row0 += B * l.rstep) {
+        float v[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int row = row0 + k * l.rstep;
+            const int ro = row < rows ? RowOff[row] : -1;
+            const float x = src[ro >= 0 ? (unsigned)(ro + l.gx) : 0u];
+            v[k] = ro >= 0 ? x : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int row = row0 + k * l.rstep;
+            if (row < rows) dst[l.hx + row * t.HX] = v[k];
+        }
     }
 }
 
