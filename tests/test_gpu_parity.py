@@ -158,7 +158,8 @@ def test_conserved_sums_fp64(oracle_lib):
 
 
 @pytest.mark.parametrize("shape,walls", [((16, 16, 16), False), ((24, 12, 14), False), ((15, 13, 17), False),
-                                         ((40, 20, 24), False), ((24, 18, 14), True), ((16, 21, 12), True)])
+                                         ((40, 20, 24), False), ((20, 32, 32), False), ((24, 18, 14), True),
+                                         ((16, 21, 12), True)])
 def test_fp32_spectral_tail_matches_direct_sum(oracle_lib, shape, walls):
     """The MFMA DFT path of the attractive field against the oracle's float64
     direct sum (also checks the matrix-core lane layout: a wrong layout
