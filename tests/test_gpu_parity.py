@@ -71,7 +71,7 @@ def test_fp64_fields_bit_exact(oracle_lib, name):
 
 
 @pytest.mark.parametrize("name,steps", [("step_binary", 100), ("ternary_tail_ext", 20), ("walls", 40),
-                                        ("fe_tau", 30)])
+                                        ("fe_tau", 30), ("couette_small", 10)])
 def test_fp64_populations_bit_exact(oracle_lib, name, steps):
     m, n0, u0 = _case(name)
     print(f"[fp64 steps] case={name} shape={m.shape()} steps={steps}", flush=True)
