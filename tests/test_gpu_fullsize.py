@@ -1,9 +1,13 @@
-"""Full-size bulk-diffusion workload (128x32x32, float32, spectral tail, the
-launch configuration bench.py times) against the stored float64 oracle run
-(tests/golden/bulk_diffusion_128x32x32_2000.json, written by
-tests/golden/make_bulk_diffusion_golden.py from the oracle only):
-densities at 4096 sampled sites after 100 steps within 1e-5 of the field's
-max norm, and D_12 from the mode decay over 2000 steps within 2 %."""
+"""Full-size workloads against stored float64 oracle runs (written by the
+scripts in tests/golden/ from the oracle only):
+- bulk diffusion (128x32x32, float32, spectral tail, the launch
+  configuration bench.py times): densities at 4096 sampled sites after 100
+  steps within 1e-5 of the field's max norm, and D_12 from the mode decay
+  over 2000 steps within 2 %;
+- Taylor/Couette (256x64x16, walls): float64 bit-exact and float32 within
+  1e-5 after 5 steps;
+- the 64-system ensemble (14.75M sites): three systems within 1e-5 after 20
+  steps."""
 import json
 import math
 import os
@@ -56,3 +60,74 @@ def test_d12_from_mode_decay(golden):
           flush=True)
     assert abs(rel) < 0.02
     assert amp_err < 1e-4
+
+
+# ---------------------------------------------------------------------------
+# Taylor/Couette (256x64x16 ternary, moving walls, tail) and the 64-system
+# ensemble at full size against float64 oracle references written by
+# tests/golden/make_fullsize_goldens.py (oracle only).
+TAYLOR = os.path.join(os.path.dirname(__file__), "golden", "taylor_couette_256x64x16_5.json")
+ENSEMBLE = os.path.join(os.path.dirname(__file__), "golden", "ensemble_64_members_20.json")
+
+
+def _load(path):
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def test_taylor_couette_float64_bit_exact_5_steps():
+    """Float64 follows the oracle's operation order: the sampled densities
+    after 5 steps are equal bit for bit (walls, moving walls, direct tail)."""
+    import paper_1105_3634_amd as mlb
+    ref = _load(TAYLOR)
+    m, n0, u0 = W.config_taylor_couette()
+    print(f"[taylor fp64] shape={m.shape()} steps={ref['steps']}", flush=True)
+    g = mlb.GpuMixture(m, n0, u0, precision=64)
+    g.step(ref["steps"])
+    n = g.moments()[0].cpu().numpy()
+    sites = np.array(ref["sample_sites"])
+    for a in range(m.M):
+        got = n[a].ravel()[sites]
+        assert np.array_equal(got, np.array(ref["n_sample"][a])), (a, np.abs(got - ref["n_sample"][a]).max())
+        assert n[a].sum() == pytest.approx(ref["mass"][a], rel=1e-13)
+
+
+def test_taylor_couette_float32_5_steps():
+    """Float32 with the spectral field on the y-padded transform (tiled
+    gathers): sampled densities within 1e-5 of the field's max norm."""
+    import paper_1105_3634_amd as mlb
+    ref = _load(TAYLOR)
+    m, n0, u0 = W.config_taylor_couette()
+    print(f"[taylor fp32] shape={m.shape()} steps={ref['steps']}", flush=True)
+    g = mlb.GpuMixture(m, n0, u0, precision=32, options=mlb.OPT_TUNE)
+    g.step(ref["steps"])
+    n = g.moments()[0].cpu().numpy().astype(np.float64)
+    sites = np.array(ref["sample_sites"])
+    for a in range(m.M):
+        err = np.abs(n[a].ravel()[sites] - np.array(ref["n_sample"][a])).max() / ref["maxnorm"][a]
+        print(f"  species {a}: fp32 rel err {err:.2e}", flush=True)
+        assert err < 1e-5
+        np.testing.assert_allclose(n[a].sum(), ref["mass"][a], rtol=1e-5)
+
+
+def test_ensemble_fullsize_20_steps():
+    """All 64 systems (14.75M sites) in one batch with the autotuned tiling
+    and graph replay, as the bench runs them; the three smallest systems
+    against the oracle after 20 steps (1e-5 of the max norm)."""
+    import paper_1105_3634_amd as mlb
+    ref = _load(ENSEMBLE)
+    members = W.config_ensemble()
+    assert len(members) == ref["count"]
+    print(f"[ensemble] systems={len(members)} steps={ref['steps']}", flush=True)
+    b = mlb.GpuBatch([x.mixture for x in members], [x.n0 for x in members], [x.u0 for x in members],
+                     precision=32, options=mlb.OPT_TUNE, device="cuda:0")
+    b.step(ref["steps"])
+    for sysref in ref["systems"]:
+        k = sysref["index"]
+        n = b.moments(k)[0].cpu().numpy().astype(np.float64)
+        sites = np.array(sysref["sample_sites"])
+        for a in range(n.shape[0]):
+            err = np.abs(n[a].ravel()[sites] - np.array(sysref["n_sample"][a])).max() / sysref["maxnorm"][a]
+            print(f"  system {k} species {a}: fp32 rel err {err:.2e}", flush=True)
+            assert err < 1e-5
+            np.testing.assert_allclose(n[a].sum(), sysref["mass"][a], rtol=1e-5)

@@ -80,3 +80,28 @@ def test_fft_stepping_matches_direct_stepping(oracle_lib):
     fd = o.step(f0, 5)
     ff = o.step_fft(f0, 5)
     assert np.abs(fd - ff).max() / np.abs(fd).max() < 1e-12
+
+
+@pytest.mark.parametrize("shape", [(16, 14, 12), (20, 11, 12)])
+def test_walled_tail_matches_padded_fft(oracle_lib, shape):
+    """With walls in y, points beyond the walls contribute nothing (solid
+    layers and out-of-box points hold no density).  The same field is a
+    circular convolution on y zero-padded past the tail's reach: the
+    oracle's ordered direct sum (walls) against an FFT on the padded grid."""
+    eps = np.array([[0.15, 0.1], [0.1, 0.05]])
+    m = W.Mixture(*shape, sigma=(1.5, 2.5), eps=eps, rc_factor=2.2, walls_y=True, wall_ux=(0.0, 0.0))
+    n0, u0 = W.random_state(m, [0.02, 0.01], rel=0.5, u_amp=0.0, seed=23)
+    o = oracle_lib.Oracle(m)
+    d = o.fields(o.init(n0, u0))
+    n = d["n"]
+    assert np.all(n[:, :, 0, :] == 0) and np.all(n[:, :, -1, :] == 0)
+    reach = int(np.ceil(m.rc_factor * max(m.sigma)))
+    nyp = m.ny + reach
+    pm = W.Mixture(m.nx, nyp, m.nz, sigma=m.sigma, eps=eps, rc_factor=m.rc_factor)
+    npad = np.zeros((m.M,) + pm.shape())
+    npad[:, :, :m.ny, :] = n
+    ref = _tail_fft(pm, npad)[:, :, :, :m.ny, :]
+    fluid = slice(1, m.ny - 1)
+    got = d["Ntail"][:, :, :, fluid, :]
+    err = np.abs(got - ref[:, :, :, fluid, :]).max() / np.abs(ref).max()
+    assert err < 1e-12, err
