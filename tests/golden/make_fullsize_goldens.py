@@ -7,6 +7,9 @@ taylor_couette_256x64x16_5.json: the ternary mixture between moving walls
   advanced 5 steps by the ordered oracle step (direct attractive sum, walls
   as solid layers); species densities at 4096 seeded sites, the field max
   norms and the species masses.
+closure_physics_192x64x64_5.json: the learned-closure workload's plain
+  path (binary, sigma 2 and 3, packing 0.2, composition mode along x,
+  192x64x64), 5 oracle steps; densities at 4096 seeded sites.
 ensemble_64_members_20.json: the 64-system ensemble of the batched
   workload (seed 4242); the three smallest systems advanced 20 steps by the
   oracle; densities at 1024 seeded sites of each, max norms and masses.
@@ -47,6 +50,20 @@ def taylor(steps):
             "mass": [float(n[a].sum()) for a in range(m.M)]}
 
 
+def closure_physics(steps):
+    m, n0, u0 = W.config_closure_physics()
+    o = oracle.Oracle(m)
+    t0 = time.time()
+    f = o.step(o.init(n0, u0), steps)
+    n = o.densities(f)
+    rng = np.random.Generator(np.random.PCG64(93))
+    sites = np.sort(rng.choice(m.N, size=4096, replace=False))
+    print(f"closure physics: {steps} steps in {time.time() - t0:.0f}s", flush=True)
+    return {"workload": m.name, "shape": list(m.shape()), "steps": steps, "sample_sites": sites.tolist(),
+            "n_sample": sample(n, sites), "maxnorm": [float(np.abs(n[a]).max()) for a in range(m.M)],
+            "mass": [float(n[a].sum()) for a in range(m.M)]}
+
+
 def ensemble(steps, pick=3):
     members = W.config_ensemble()
     order = sorted(range(len(members)), key=lambda k: (members[k].mixture.N, k))[:pick]
@@ -72,8 +89,20 @@ def main():
     ap.add_argument("--threads", type=int, default=8)
     ap.add_argument("--taylor-steps", type=int, default=5)
     ap.add_argument("--ensemble-steps", type=int, default=20)
+    ap.add_argument("--only", default="taylor,closure,ensemble")
     args = ap.parse_args()
     oracle.set_threads(args.threads)
+    todo = args.only.split(",")
+    if "closure" in todo:
+        c = closure_physics(5)
+        with open(os.path.join(HERE, "closure_physics_192x64x64_5.json"), "w") as fh:
+            json.dump(c, fh)
+    if "taylor" not in todo:
+        if "ensemble" in todo:
+            e = ensemble(args.ensemble_steps)
+            with open(os.path.join(HERE, f"ensemble_64_members_{args.ensemble_steps}.json"), "w") as fh:
+                json.dump(e, fh)
+        return
     t = taylor(args.taylor_steps)
     with open(os.path.join(HERE, f"taylor_couette_256x64x16_{args.taylor_steps}.json"), "w") as fh:
         json.dump(t, fh)

@@ -7,7 +7,9 @@ scripts in tests/golden/ from the oracle only):
 - Taylor/Couette (256x64x16, walls): float64 bit-exact and float32 within
   1e-5 after 5 steps;
 - the 64-system ensemble (14.75M sites): three systems within 1e-5 after 20
-  steps."""
+  steps;
+- the learned-closure workload's exact-force path (192x64x64): float32
+  within 1e-5 after 5 steps."""
 import json
 import math
 import os
@@ -99,7 +101,7 @@ def test_taylor_couette_float32_5_steps():
     ref = _load(TAYLOR)
     m, n0, u0 = W.config_taylor_couette()
     print(f"[taylor fp32] shape={m.shape()} steps={ref['steps']}", flush=True)
-    g = mlb.GpuMixture(m, n0, u0, precision=32, options=mlb.OPT_TUNE)
+    g = mlb.GpuMixture(m, n0, u0, precision=32, device="cuda:0")
     g.step(ref["steps"])
     n = g.moments()[0].cpu().numpy().astype(np.float64)
     sites = np.array(ref["sample_sites"])
@@ -131,3 +133,25 @@ def test_ensemble_fullsize_20_steps():
             print(f"  system {k} species {a}: fp32 rel err {err:.2e}", flush=True)
             assert err < 1e-5
             np.testing.assert_allclose(n[a].sum(), sysref["mass"][a], rtol=1e-5)
+
+
+CLOSURE = os.path.join(os.path.dirname(__file__), "golden", "closure_physics_192x64x64_5.json")
+
+
+def test_closure_workload_plain_path_float32_5_steps():
+    """The learned-closure workload's exact-force path at full size (192x64x64,
+    sigma 2 and 3, packing 0.2), tiled float32 gathers as the closure leg
+    runs them: sampled densities within 1e-5 of the max norm after 5 steps."""
+    import paper_1105_3634_amd as mlb
+    ref = _load(CLOSURE)
+    m, n0, u0 = W.config_closure_physics()
+    print(f"[closure plain fp32] shape={m.shape()} steps={ref['steps']}", flush=True)
+    g = mlb.GpuMixture(m, n0, u0, precision=32, device="cuda:0")
+    g.step(ref["steps"])
+    n = g.moments()[0].cpu().numpy().astype(np.float64)
+    sites = np.array(ref["sample_sites"])
+    for a in range(m.M):
+        err = np.abs(n[a].ravel()[sites] - np.array(ref["n_sample"][a])).max() / ref["maxnorm"][a]
+        print(f"  species {a}: fp32 rel err {err:.2e}", flush=True)
+        assert err < 1e-5
+        np.testing.assert_allclose(n[a].sum(), ref["mass"][a], rtol=1e-5)
