@@ -57,6 +57,14 @@ constexpr int kTileFields = 5;   // n, v0, v1, v2, g
 #ifndef MLB_S2_WAVES
 #define MLB_S2_WAVES 4
 #endif
+// z-paired LDS layout (below) in the first / second gather where the tile
+// shape allows it
+#ifndef MLB_G1_ZPAIR
+#define MLB_G1_ZPAIR 0
+#endif
+#ifndef MLB_S2_ZPAIR
+#define MLB_S2_ZPAIR 1
+#endif
 constexpr int kSplitG1 = MLB_G1_SPLIT, kSplitS2 = MLB_S2_SPLIT;
 constexpr int kGather1Threads = kSplitG1 * kBlock, kStep2Threads = kSplitS2 * kBlock;
 
@@ -101,10 +109,26 @@ __device__ inline gfloat *glb(float *p) { return (gfloat *)p; }
 struct TileGeo {
     int x0, y0, z0;       // tile origin
     int R, HX, HY, HZ;    // halo width and staged extents
+    int PXY;              // z-plane pitch of the staged arrays (sites)
     int FS;               // floats per staged field
 };
 
-template <int TX, int TY, int TZ>
+// Bank layout of the gathers' staged tiles.  LDS has 64 banks of 4 bytes,
+// and one cycle of a 16-byte read serves 16 lanes.  With 8-wide tiles and
+// lanes laid out x, then y, those 16 lanes cover two x rows of the halo tile,
+// and at halo widths such as 16 the rows lie a multiple of 256 bytes apart:
+// the same banks, so every read of the shell loops takes two cycles.  Such
+// tiles ("z-paired") therefore pad the z planes of the staged arrays to a
+// pitch of 8 mod 16 sites and give lanes 8..15 of every 16 the next z plane
+// instead of the next y row; the two halves then lie 128 bytes apart modulo
+// 256, on disjoint banks, and the 4-byte g reads of a whole wave (4 y rows
+// x 2 planes x 8 x) fall on distinct banks as well.  Other shapes keep
+// unpadded planes and the plain lane order.
+__host__ __device__ constexpr bool zpair_shape(int TX, int TZ) { return TX == 8 && TZ % 2 == 0; }
+
+__host__ __device__ inline int zpair_pitch(int plane) { return plane + ((24 - plane % 16) % 16); }
+
+template <int TX, int TY, int TZ, bool ZP = false>
 __device__ inline TileGeo tile_geo(const SysDesc<float> &S, int local, int R)
 {
     TileGeo t;
@@ -113,7 +137,8 @@ __device__ inline TileGeo tile_geo(const SysDesc<float> &S, int local, int R)
     t.x0 = bx * TX; t.y0 = by * TY; t.z0 = bz * TZ;
     t.R = R;
     t.HX = TX + 2 * t.R; t.HY = TY + 2 * t.R; t.HZ = TZ + 2 * t.R;
-    t.FS = t.HX * t.HY * t.HZ;
+    t.PXY = ZP ? zpair_pitch(t.HX * t.HY) : t.HX * t.HY;
+    t.FS = t.PXY * t.HZ;
     return t;
 }
 
@@ -148,12 +173,14 @@ __device__ inline StageLane stage_lane(const SysDesc<float> &S, const TileGeo &t
     return l;
 }
 
+// RowL (may be null) receives the row's LDS base, hy HX + hz PXY.
 template <int NT = kBlock>
-__device__ inline void fill_rows(const SysDesc<float> &S, const TileGeo &t, int *RowOff)
+__device__ inline void fill_rows(const SysDesc<float> &S, const TileGeo &t, int *RowOff, int *RowL = nullptr)
 {
     const int rows = t.HY * t.HZ;
     for (int r = threadIdx.x; r < rows; r += NT) {
         const int hz = r / t.HY, hy = r - hz * t.HY;
+        if (RowL) RowL[r] = hy * t.HX + hz * t.PXY;
         int gy = t.y0 - t.R + hy;
         const int gz = wrap_mod(t.z0 - t.R + hz, S.nz);
         if (S.walls) {
@@ -165,16 +192,18 @@ __device__ inline void fill_rows(const SysDesc<float> &S, const TileGeo &t, int 
     }
 }
 
+// Z-paired tiles (ZP) take each row's LDS base from RowL, others use row HX.
+template <bool ZP>
 __device__ inline void stage(const SysDesc<float> &S, const TileGeo &t, const StageLane &l, const int *RowOff,
-                             float4 *lds4, float *ldsg, const gfloat *__restrict__ nb, const gfloat *__restrict__ vb,
-                             const gfloat *__restrict__ gp)
+                             const int *RowL, float4 *lds4, float *ldsg, const gfloat *__restrict__ nb,
+                             const gfloat *__restrict__ vb, const gfloat *__restrict__ gp)
 {
     const unsigned N = (unsigned)S.N;
     const int rows = t.HY * t.HZ;
     if (l.rstep == 0) return;
     for (int row = l.row0; row < rows; row += l.rstep) {
         const int ro = RowOff[row];
-        const int i = l.hx + row * t.HX;
+        const int i = l.hx + (ZP ? RowL[row] : row * t.HX);
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         float g = 0.f;
         if (ro >= 0) {
@@ -187,7 +216,8 @@ __device__ inline void stage(const SysDesc<float> &S, const TileGeo &t, const St
     }
 }
 
-// One scalar field of the halo tile (zero outside the walls).  The thread's
+// One scalar field of the halo tile (zero outside the walls; unpadded
+// planes).  The thread's
 // rows go in batches of 8 whose loads are all issued before the first store
 // to LDS (one wait for memory per batch); rows outside the walls read site 0
 // and store zero.
@@ -228,6 +258,7 @@ __device__ inline ConstF4 shell_list(const Tables<float> &tb, int k0)
     return (ConstF4)(tb.sh_q + k0);
 }
 
+
 __device__ inline int shell_off(float packed, int HX, int HXY)
 {
     int ex, ey, ez;
@@ -246,18 +277,26 @@ struct TileSite {
     int c;   // LDS offset of the site
 };
 
-template <int TX, int TY, int TZ>
+// Site of this thread: x fastest, then y, then z; z-paired tiles (ZP) take
+// x, then one bit of z, then y, then the rest of z.
+template <int TX, int TY, int TZ, bool ZP = false>
 __device__ inline TileSite tile_site(const SysDesc<float> &S, const TileGeo &t)
 {
     TileSite q;
     const int i = threadIdx.x % (TX * TY * TZ);
     q.tx = i % TX;
-    q.ty = (i / TX) % TY;
-    q.tz = i / (TX * TY);
+    if (ZP) {
+        const int j = i / (2 * TX);
+        q.ty = j % TY;
+        q.tz = 2 * (j / TY) + (i / TX) % 2;
+    } else {
+        q.ty = (i / TX) % TY;
+        q.tz = i / (TX * TY);
+    }
     q.x = t.x0 + q.tx; q.y = t.y0 + q.ty; q.z = t.z0 + q.tz;
     q.active = q.x < S.nx && q.y < S.ny && q.z < S.nz;
     q.s = ((long long)q.z * S.ny + q.y) * S.nx + q.x;
-    q.c = (q.tx + t.R) + (q.ty + t.R) * t.HX + (q.tz + t.R) * t.HX * t.HY;
+    q.c = (q.tx + t.R) + (q.ty + t.R) * t.HX + (q.tz + t.R) * t.PXY;
     return q;
 }
 
@@ -274,17 +313,19 @@ k_gather1_tile(const SysDesc<float> *__restrict__ sys,
     const SysDesc<float> &S = sys[bm.x];
     const int a = blockIdx.y;
     if (a >= S.M) return;
-    const TileGeo t = tile_geo<TX, TY, TZ>(S, bm.y, S.reach);
-    const TileSite q = tile_site<TX, TY, TZ>(S, t);
+    constexpr bool ZP = MLB_G1_ZPAIR && zpair_shape(TX, TZ);
+    const TileGeo t = tile_geo<TX, TY, TZ, ZP>(S, bm.y, S.reach);
+    const TileSite q = tile_site<TX, TY, TZ, ZP>(S, t);
     const int h = __builtin_amdgcn_readfirstlane(threadIdx.x / kBlock);   // wave-uniform
     const long long N = S.N;
     const long long o3 = (long long)a * 3 * N;
     float4 *L4 = lds;
     float *Lg = reinterpret_cast<float *>(lds + t.FS);
     int *RowOff = reinterpret_cast<int *>(lds + t.FS + (t.FS + 3) / 4);
-    const int HXY = t.HX * t.HY;
+    int *RowL = RowOff + t.HY * t.HZ;
+    const int HXY = t.PXY;
     const StageLane sl = stage_lane<kGather1Threads>(S, t);
-    fill_rows<kGather1Threads>(S, t, RowOff);
+    fill_rows<kGather1Threads>(S, t, RowOff, ZP ? RowL : nullptr);
     const char *c4 = reinterpret_cast<const char *>(L4 + q.c);
     const char *cg = reinterpret_cast<const char *>(Lg + q.c);
     const bool solid = q.active && S.walls && (q.y == 0 || q.y == S.ny - 1);
@@ -301,7 +342,7 @@ k_gather1_tile(const SysDesc<float> *__restrict__ sys,
         int kb, ke;
         split_range<kSplitG1>(S.sh_cnt[a][b], h, kb, ke);
         __syncthreads();
-        stage(S, t, sl, RowOff, L4, Lg, glb(S.n) + (long long)b * N, glb(S.j) + (long long)b * 3 * N, gpair);
+        stage<ZP>(S, t, sl, RowOff, RowL, L4, Lg, glb(S.n) + (long long)b * N, glb(S.j) + (long long)b * 3 * N, gpair);
         __syncthreads();
         const ConstF4 Q = shell_list(tb, S.sh_start[a][b]);
         const float g0 = Lg[q.c];
@@ -405,14 +446,16 @@ k_step2_tile(const SysDesc<float> *__restrict__ sys,
     const SysDesc<float> &S = sys[bm.x];
     const int a = blockIdx.y;
     if (a >= S.M) return;
-    const TileGeo t = tile_geo<TX, TY, TZ>(S, bm.y, S.reach);
-    const TileSite q = tile_site<TX, TY, TZ>(S, t);
+    constexpr bool ZP = MLB_S2_ZPAIR && zpair_shape(TX, TZ);
+    const TileGeo t = tile_geo<TX, TY, TZ, ZP>(S, bm.y, S.reach);
+    const TileSite q = tile_site<TX, TY, TZ, ZP>(S, t);
     const long long N = S.N;
     const long long o3 = (long long)a * 3 * N;
     float4 *L4 = lds;
     float *Lg = reinterpret_cast<float *>(lds + t.FS);
     int *RowOff = reinterpret_cast<int *>(lds + t.FS + (t.FS + 3) / 4);
-    const int HXY = t.HX * t.HY;
+    int *RowL = RowOff + t.HY * t.HZ;
+    const int HXY = t.PXY;
     const int h = __builtin_amdgcn_readfirstlane(threadIdx.x / kBlock);   // wave-uniform
     // The collision's inputs are loaded before the gathers, so that their
     // latency hides behind the shell loops.  Every group forms the total
@@ -452,7 +495,7 @@ k_step2_tile(const SysDesc<float> *__restrict__ sys,
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
     if (S.scheme != 1) {
         const StageLane sl = stage_lane<kStep2Threads>(S, t);
-        fill_rows<kStep2Threads>(S, t, RowOff);
+        fill_rows<kStep2Threads>(S, t, RowOff, ZP ? RowL : nullptr);
         const char *c4 = reinterpret_cast<const char *>(L4 + q.c);
         const char *cg = reinterpret_cast<const char *>(Lg + q.c);
         for (int b = 0; b < S.M; ++b) {
@@ -460,7 +503,7 @@ k_step2_tile(const SysDesc<float> *__restrict__ sys,
             int kb, ke;
             split_range<kSplitS2>(S.sh_cnt[a][b], h, kb, ke);
             __syncthreads();
-            stage(S, t, sl, RowOff, L4, Lg, glb(S.n) + (long long)b * N, glb(S.vh) + (long long)b * 3 * N, gpair);
+            stage<ZP>(S, t, sl, RowOff, RowL, L4, Lg, glb(S.n) + (long long)b * N, glb(S.vh) + (long long)b * 3 * N, gpair);
             __syncthreads();
             const ConstF4 Q = shell_list(tb, S.sh_start[a][b]);
             const float g0 = Lg[q.c];
@@ -595,15 +638,19 @@ inline size_t contact_lds_bytes(int TX, int TY, int TZ, int R, int ball_total, i
     return 4 * ((size_t)maxM * FS + (size_t)ball_total + rows);
 }
 
-// float4 + float per staged site, then the row-offset table (one int per
-// halo row); at least the partial sums of the split reductions (13 floats
-// per site and group in the first gather, 3 in the second)
-inline size_t tile_lds_bytes(int TX, int TY, int TZ, int R)
+// float4 + float per staged site (z planes padded on z-paired shapes), then
+// the row-offset table and, z-paired, the row-base table (one int each per
+// halo row); at least
+// the partial sums of the split reductions (13 floats per site and group in
+// the first gather, 3 in the second)
+inline size_t tile_lds_bytes(int TX, int TY, int TZ, int R, bool zpair)
 {
-    const size_t FS = (size_t)(TX + 2 * R) * (TY + 2 * R) * (TZ + 2 * R);
+    const int plane = (TX + 2 * R) * (TY + 2 * R);
+    const bool zp = zpair && zpair_shape(TX, TZ);
+    const size_t FS = (size_t)(zp ? zpair_pitch(plane) : plane) * (TZ + 2 * R);
     const size_t rows = (size_t)(TY + 2 * R) * (TZ + 2 * R);
     const size_t reduce = std::max((size_t)kSplitG1 * 13, (size_t)kSplitS2 * 3) * kBlock * 4;
-    return std::max(16 * FS + 16 * ((FS + 3) / 4) + 4 * rows, reduce);
+    return std::max(16 * FS + 16 * ((FS + 3) / 4) + (zp ? 8 : 4) * rows, reduce);
 }
 
 }  // namespace mlb
