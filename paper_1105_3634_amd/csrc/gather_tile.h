@@ -19,8 +19,8 @@
 //
 // Tile: TX x TY x TZ = 256 sites (a template parameter; the autotuner picks
 // among the built shapes), one thread per site; per partner species the
-// block stages n_b, the three components of j_b (or V_b) and g_ab for the
-// tile plus a halo of R cells (R = largest stencil component of the
+// block stages n_b, the three components of j_b and g_ab (first gather) or
+// n_b V_b and g_ab (second gather) for the tile plus a halo of R cells (R = largest stencil component of the
 // system) into LDS; periodic wrap and walls are resolved while filling, so
 // the inner loop is address arithmetic on a uniform offset and LDS loads.
 #pragma once
@@ -31,7 +31,6 @@
 
 namespace mlb {
 
-constexpr int kTileFields = 5;   // n, v0, v1, v2, g
 
 // The gathers run several threads per tile site: thread group h (the waves
 // of threads h * 256 ... h * 256 + 255) takes the h-th part of every shell
@@ -213,6 +212,29 @@ __device__ inline void stage(const SysDesc<float> &S, const TileGeo &t, const St
         }
         lds4[i] = v;
         ldsg[i] = g;
+    }
+}
+
+// Second gather: one float4 per halo site, (n_b V_b, g_ab); the shell loop
+// then needs no separate g reads and no product with n_b.
+template <bool ZP>
+__device__ inline void stage_nv(const SysDesc<float> &S, const TileGeo &t, const StageLane &l, const int *RowOff,
+                                const int *RowL, float4 *lds4, const gfloat *__restrict__ nb,
+                                const gfloat *__restrict__ vb, const gfloat *__restrict__ gp)
+{
+    const unsigned N = (unsigned)S.N;
+    const int rows = t.HY * t.HZ;
+    if (l.rstep == 0) return;
+    for (int row = l.row0; row < rows; row += l.rstep) {
+        const int ro = RowOff[row];
+        const int i = l.hx + (ZP ? RowL[row] : row * t.HX);
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (ro >= 0) {
+            const unsigned so = (unsigned)(ro + l.gx);
+            const float n = nb[so];
+            v = make_float4(n * vb[so], n * vb[N + so], n * vb[2 * N + so], gp[so]);
+        }
+        lds4[i] = v;
     }
 }
 
@@ -452,8 +474,7 @@ k_step2_tile(const SysDesc<float> *__restrict__ sys,
     const long long N = S.N;
     const long long o3 = (long long)a * 3 * N;
     float4 *L4 = lds;
-    float *Lg = reinterpret_cast<float *>(lds + t.FS);
-    int *RowOff = reinterpret_cast<int *>(lds + t.FS + (t.FS + 3) / 4);
+    int *RowOff = reinterpret_cast<int *>(lds + t.FS);
     int *RowL = RowOff + t.HY * t.HZ;
     const int HXY = t.PXY;
     const int h = __builtin_amdgcn_readfirstlane(threadIdx.x / kBlock);   // wave-uniform
@@ -497,27 +518,27 @@ k_step2_tile(const SysDesc<float> *__restrict__ sys,
         const StageLane sl = stage_lane<kStep2Threads>(S, t);
         fill_rows<kStep2Threads>(S, t, RowOff, ZP ? RowL : nullptr);
         const char *c4 = reinterpret_cast<const char *>(L4 + q.c);
-        const char *cg = reinterpret_cast<const char *>(Lg + q.c);
         for (int b = 0; b < S.M; ++b) {
             const gfloat *__restrict__ gpair = glb(S.g) + (long long)pidx(S.M, a, b) * N;
             int kb, ke;
             split_range<kSplitS2>(S.sh_cnt[a][b], h, kb, ke);
             __syncthreads();
-            stage<ZP>(S, t, sl, RowOff, RowL, L4, Lg, glb(S.n) + (long long)b * N, glb(S.vh) + (long long)b * 3 * N, gpair);
+            stage_nv<ZP>(S, t, sl, RowOff, RowL, L4, glb(S.n) + (long long)b * N, glb(S.vh) + (long long)b * 3 * N,
+                         gpair);
             __syncthreads();
             const ConstF4 Q = shell_list(tb, S.sh_start[a][b]);
-            const float g0 = Lg[q.c];
+            const float g0 = L4[q.c].w;
             float v0 = 0.f, v1 = 0.f, v2 = 0.f;
 #pragma unroll MLB_S2_UNROLL
             for (int k = kb; k < ke; ++k) {
                 const ShellEntry ta = Q[k];
-                const int o4 = shell_off(ta.x, t.HX, HXY), o1 = o4 >> 2;
+                const int o4 = shell_off(ta.x, t.HX, HXY);
                 const float e0 = ta.y, e1 = ta.z, e2 = ta.w;
                 const float4 Ap = ld4(c4, o4), Am = ld4(c4, -o4);
-                const float tp = (g0 + ld1(cg, o1)) * Ap.x, tm = (g0 + ld1(cg, -o1)) * Am.x;
-                const float w0 = tp * Ap.y + tm * Am.y;
-                const float w1 = tp * Ap.z + tm * Am.z;
-                const float w2 = tp * Ap.w + tm * Am.w;
+                const float Gp = g0 + Ap.w, Gm = g0 + Am.w;
+                const float w0 = Gp * Ap.x + Gm * Am.x;
+                const float w1 = Gp * Ap.y + Gm * Am.y;
+                const float w2 = Gp * Ap.z + Gm * Am.z;
                 const float pr = e0 * w0 + e1 * w1 + e2 * w2;
                 v0 += e0 * pr; v1 += e1 * pr; v2 += e2 * pr;
             }
@@ -638,19 +659,19 @@ inline size_t contact_lds_bytes(int TX, int TY, int TZ, int R, int ball_total, i
     return 4 * ((size_t)maxM * FS + (size_t)ball_total + rows);
 }
 
-// float4 + float per staged site (z planes padded on z-paired shapes), then
-// the row-offset table and, z-paired, the row-base table (one int each per
-// halo row); at least
+// float4 + float per staged site in the first gather, one float4 in the
+// second (z planes padded on z-paired shapes), then the row-offset table
+// and, z-paired, the row-base table (one int each per halo row); at least
 // the partial sums of the split reductions (13 floats per site and group in
 // the first gather, 3 in the second)
-inline size_t tile_lds_bytes(int TX, int TY, int TZ, int R, bool zpair)
+inline size_t tile_lds_bytes(int TX, int TY, int TZ, int R, bool zpair, bool second)
 {
     const int plane = (TX + 2 * R) * (TY + 2 * R);
     const bool zp = zpair && zpair_shape(TX, TZ);
     const size_t FS = (size_t)(zp ? zpair_pitch(plane) : plane) * (TZ + 2 * R);
     const size_t rows = (size_t)(TY + 2 * R) * (TZ + 2 * R);
-    const size_t reduce = std::max((size_t)kSplitG1 * 13, (size_t)kSplitS2 * 3) * kBlock * 4;
-    return std::max(16 * FS + 16 * ((FS + 3) / 4) + (zp ? 8 : 4) * rows, reduce);
+    const size_t reduce = (second ? (size_t)kSplitS2 * 3 : (size_t)kSplitG1 * 13) * kBlock * 4;
+    return std::max(16 * FS + (second ? 0 : 16 * ((FS + 3) / 4)) + (zp ? 8 : 4) * rows, reduce);
 }
 
 }  // namespace mlb
