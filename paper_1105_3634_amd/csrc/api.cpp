@@ -918,7 +918,10 @@ std::string tune_key(const Batch &B)
     return k;
 }
 
-// Time every tile shape and block order over full steps; keep the fastest.
+// Time every tile shape and block order over full steps, run the way
+// mlb_step runs them (graph-replayed pairs unless graphs are off: the
+// spectral field's overlap with the first gather differs between the two);
+// keep the fastest.
 template <typename T>
 mlb_status autotune(Batch &B, const double *const *n0, const double *const *u0, hipStream_t st)
 {
@@ -944,10 +947,12 @@ mlb_status autotune(Batch &B, const double *const *n0, const double *const *u0, 
         for (int order = 0; order < 2 && status == MLB_OK; ++order) {
             status = set_tiling(B, v, order, st);
             if (status != MLB_OK) break;
-            for (int i = 0; i < warm; ++i) step_once(B, st);
+            status = run_steps(B, warm, st, false);   // captures the graph of this tiling
+            if (status != MLB_OK) break;
             float ms = 0.f;
             if (hipEventRecord(e0, st) != hipSuccess) { status = fail(MLB_EHIP, "event record"); break; }
-            for (int i = 0; i < reps; ++i) step_once(B, st);
+            status = run_steps(B, reps, st, false);
+            if (status != MLB_OK) break;
             if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
                 status = fail(MLB_EHIP, "event timing");

@@ -39,22 +39,22 @@ namespace mlb {
 // inner loop.  Split factor, shell-loop unrolling and the register budget
 // (waves per SIMD) per kernel:
 #ifndef MLB_G1_SPLIT
-#define MLB_G1_SPLIT 2
+#define MLB_G1_SPLIT 3
 #endif
 #ifndef MLB_G1_UNROLL
 #define MLB_G1_UNROLL 4
 #endif
 #ifndef MLB_G1_WAVES
-#define MLB_G1_WAVES 4
+#define MLB_G1_WAVES 6
 #endif
 #ifndef MLB_S2_SPLIT
-#define MLB_S2_SPLIT 2
+#define MLB_S2_SPLIT 3
 #endif
 #ifndef MLB_S2_UNROLL
 #define MLB_S2_UNROLL 4
 #endif
 #ifndef MLB_S2_WAVES
-#define MLB_S2_WAVES 4
+#define MLB_S2_WAVES 6
 #endif
 // z-paired LDS layout (below) in the first / second gather where the tile
 // shape allows it
