@@ -172,8 +172,11 @@ int32_t mlb_series_capacity(void);
 mlb_status mlb_series_reset(mlb_mixture h, void *stream);
 /* Least-squares fit over the recorded samples with t >= t_min, in float64 on
  * the GPU.  kind 0 (mode): D = -slope(ln A, t) / (2 pi / nx)^2, the decay
- * 1/tau = D q^2 of Sec. 5.1.  kind 1 (spread): D = slope(Var, t) / 2.
- * HOST output; synchronises the stream. */
+ * 1/tau = D q^2 of Sec. 5.1, over the samples with t >= min(t_min, first t
+ * at which A <= 0.1 A_first) and A >= 1e-6 A_first (A_first = the first
+ * recorded amplitude): a fast mode is fitted before it reaches the rounding
+ * floor of the densities.  kind 1 (spread): D = slope(Var, t) / 2.  Fewer
+ * than two samples give NaN.  HOST output; synchronises the stream. */
 mlb_status mlb_fit_series(mlb_mixture h, int32_t kind, double t_min, double *D_out, void *stream);
 /* Copy the recorded series to HOST memory: t[count], v[count]; returns the
  * count through *count.  Synchronises. */

@@ -175,15 +175,37 @@ void launch_spread(const void *n, int prec, int a, int nx, long long N, double *
 // ---------------------------------------------------------------------- fit
 // Ordinary least squares y = alpha + beta t over samples with t >= t_min.
 // kind 0: y = ln(v), D = -beta / k2;  kind 1: y = v, D = beta / 2.
+// Mode fits (kind 0) use the samples from t_lo = min(t_min, the first time
+// the amplitude is at most a tenth of the first sample's) on, as long as
+// the amplitude stays at least 1e-6 of the first sample's: a fast mode has
+// reached the float32 rounding floor of the densities long before a t_min
+// chosen for slow ones, and a slow mode never reaches either bound.
+constexpr double kFitStart = 0.1, kFitFloor = 1e-6;
+
+__device__ inline bool fit_sample(const double *series, int i, int kind, double t_lo, double a0)
+{
+    if (series[2 * i] < t_lo) return false;
+    return kind != 0 || series[2 * i + 1] >= kFitFloor * a0;
+}
+
 __global__ void k_fit(const double *__restrict__ series, const int *__restrict__ count, int cap, int kind,
                       double t_min, double k2, double *out)
 {
     if (threadIdx.x != 0) return;
     const int c = min(*count, cap);
+    double t_lo = t_min, a0 = 0.0;
+    if (kind == 0 && c > 0) {
+        a0 = series[1];
+        for (int i = 0; i < c; ++i)
+            if (series[2 * i + 1] <= kFitStart * a0) {
+                t_lo = fmin(t_min, series[2 * i]);
+                break;
+            }
+    }
     double n = 0.0, st = 0.0, sy = 0.0;
     for (int i = 0; i < c; ++i) {
+        if (!fit_sample(series, i, kind, t_lo, a0)) continue;
         const double t = series[2 * i];
-        if (t < t_min) continue;
         const double y = kind == 0 ? log(series[2 * i + 1]) : series[2 * i + 1];
         n += 1.0;
         st += t;
@@ -196,8 +218,8 @@ __global__ void k_fit(const double *__restrict__ series, const int *__restrict__
     const double tm = st / n, ym = sy / n;
     double stt = 0.0, sty = 0.0;
     for (int i = 0; i < c; ++i) {
+        if (!fit_sample(series, i, kind, t_lo, a0)) continue;
         const double t = series[2 * i];
-        if (t < t_min) continue;
         const double y = kind == 0 ? log(series[2 * i + 1]) : series[2 * i + 1];
         stt += (t - tm) * (t - tm);
         sty += (t - tm) * (y - ym);
