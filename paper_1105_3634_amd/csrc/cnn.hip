@@ -65,9 +65,10 @@ __device__ inline long long shift_site(const Grid3 &g, int x, int y, int z, int 
 //     (float32, optional), aout = act ? silu(z) : z (bf16, optional)
 //   data gradient (SGN = -1, EPI 1): W = transposed weights [t][ci][co];
 //     gin = acc * silu'(zin) (bf16)
-// Persistent blocks (one per CU) walk 16 x 8 x 4 tiles; within a tile wave w
-// owns the plane z0 + w as 8 rows of 16 consecutive x (one MFMA site block
-// per row) and all OUT channels (16 independent accumulators for OUT = 32).
+// Persistent blocks (one per CU) walk 16 x 8 x 4 tiles; within a tile each
+// wave owns kWaveRows rows of 16 consecutive x in one z plane (one MFMA site
+// block per row) and all OUT channels (2 kWaveRows independent accumulators
+// for OUT = 32).
 // The layer's weights are staged in LDS once per block; each tile with a
 // one-cell halo (18 x 10 x 6 sites) is loaded into registers while the
 // previous tile computes, then stored to LDS.  Both are chunk-major: [channel chunk][site] and
@@ -81,13 +82,30 @@ __device__ inline long long shift_site(const Grid3 &g, int x, int y, int z, int 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 constexpr int kCTX = 16, kCTY = 8, kCTZ = 4;
+// Waves per tile block: each wave owns kWaveRows rows of 16 sites in one z
+// plane (all rows with 4 waves; half of them with 8, two waves per SIMD so
+// that one wave's LDS waits overlap the other's MFMAs).
+#ifndef MLB_CONV_WAVES
+#define MLB_CONV_WAVES 8
+#endif
+constexpr int kConvWaves = MLB_CONV_WAVES, kConvThreads = 64 * kConvWaves;
+constexpr int kWaveRows = kCTY * kCTZ / kConvWaves, kRowBlocks = kCTY / kWaveRows;
+static_assert(kWaveRows * kRowBlocks == kCTY && kRowBlocks * kCTZ == kConvWaves, "waves tile the block");
 constexpr int kCHX = kCTX + 2, kCHY = kCTY + 2, kCHZ = kCTZ + 2;
 constexpr int kCHS = kCHX * kCHY * kCHZ;
 constexpr int kCRows = kCHY * kCHZ;
 
+// Byte stride between the channel-chunk planes of the staged tile.  A
+// 16-byte LDS read serves 16 lanes per clock, and consecutive 8-lane blocks
+// must fall on opposite halves of the 64 banks (measured): the site block of
+// chunk g + 1 (lanes 16 (g + 1) ..) has to start on the same bank as that of
+// chunk g, so 16-byte chunk planes are padded to a multiple of 256 bytes
+// (1080 sites x 16 bytes = 17280 would put them 128 bytes off).
+__host__ __device__ constexpr int conv_plane(int cw) { return cw == 16 ? (kCHS * cw + 255) / 256 * 256 : kCHS * cw; }
+
 __host__ __device__ constexpr int conv_lds(int kin, int out)
 {
-    return 4 * kCHS * (kin / 2) + 4 * 27 * out * (kin / 2) + 2 * 4 * kCRows;
+    return 4 * conv_plane(kin / 2) + 4 * 27 * out * (kin / 2) + 2 * 4 * kCRows;
 }
 
 __device__ inline int wrap_cell(int v, int n)
@@ -139,7 +157,7 @@ __device__ inline void conv_rows(const Grid3 &g, int ntx, int nty, int tile, int
 }
 
 template <int KIN, int OUT, int SGN, int EPI>
-__global__ void __launch_bounds__(256) k_conv_tile(Grid3 g, long long N, const unsigned short *__restrict__ in,
+__global__ void __launch_bounds__(kConvThreads) k_conv_tile(Grid3 g, long long N, const unsigned short *__restrict__ in,
                                                   const unsigned short *__restrict__ W,
                                                   const float *__restrict__ bias, const float *__restrict__ zin,
                                                   float *__restrict__ zout, unsigned short *__restrict__ aout, int act)
@@ -147,11 +165,11 @@ __global__ void __launch_bounds__(256) k_conv_tile(Grid3 g, long long N, const u
     extern __shared__ __align__(16) unsigned char Ls[];
     constexpr int CW = KIN / 2, NCH = 4, CB = OUT / 16;       // chunk bytes; 4 chunks per site or weight row
     constexpr int WROWS = 27 * OUT;
-    constexpr int RSTEP = 256 / (kCHX * NCH);                 // halo rows staged per pass
+    constexpr int RSTEP = 256 / (kCHX * NCH);                 // halo rows staged per pass (threads < 256)
     constexpr int MAXK = kCRows / RSTEP;                      // rows per staging thread
     static_assert(RSTEP * MAXK == kCRows, "staging threads cover the halo rows evenly");
     typedef typename Chunk<CW>::T CT;
-    constexpr int PI = kCHS * CW, PW = WROWS * CW;             // chunk-plane strides (bytes)
+    constexpr int PI = conv_plane(CW), PW = WROWS * CW;        // chunk-plane strides (bytes)
     unsigned char *Lin = Ls;                                  // [NCH][kCHS][CW]
     unsigned char *Lwt = Ls + NCH * PI;                       // [NCH][WROWS][CW]
     int *RowOff = reinterpret_cast<int *>(Lwt + NCH * PW);    // [2][kCRows], by tile parity
@@ -162,7 +180,7 @@ __global__ void __launch_bounds__(256) k_conv_tile(Grid3 g, long long N, const u
     {
         constexpr int WCH = WROWS * NCH;
 #pragma unroll 4
-        for (int i = tid; i < WCH; i += 256)
+        for (int i = tid; i < WCH; i += kConvThreads)
             *reinterpret_cast<CT *>(Lwt + (i % NCH) * PW + (i / NCH) * CW) =
                 *reinterpret_cast<const CT *>(W + (long long)i * (CW / 2));
     }
@@ -184,9 +202,10 @@ __global__ void __launch_bounds__(256) k_conv_tile(Grid3 g, long long N, const u
     }
 
     const int lane = tid & 63, wave = tid >> 6, li = lane & 15, gq = lane >> 4;
-    // halo index of the wave's site (x0 + li, y0 + sb, z0 + wave) is
-    // (li + 1) + (sb + 1) kCHX + (wave + 1) kCHX kCHY; Lb points at sb = 0
-    const unsigned char *Lb = Lin + gq * PI + ((li + 1) + kCHX + (wave + 1) * kCHX * kCHY) * CW;
+    const int wz = wave / kRowBlocks, wy = (wave % kRowBlocks) * kWaveRows;   // the wave's plane and first row
+    // halo index of the wave's site (x0 + li, y0 + wy + sb, z0 + wz) is
+    // (li + 1) + (wy + sb + 1) kCHX + (wz + 1) kCHX kCHY; Lb points at sb = 0
+    const unsigned char *Lb = Lin + gq * PI + ((li + 1) + (wy + 1) * kCHX + (wz + 1) * kCHX * kCHY) * CW;
     // weight row co = c 16 + li of tap t is chunk row t OUT + co
     const unsigned char *Wl = Lwt + gq * PW + li * CW;
     typedef typename std::conditional<KIN == 32, v8bf, v4s>::type OP;
@@ -210,11 +229,11 @@ __global__ void __launch_bounds__(256) k_conv_tile(Grid3 g, long long N, const u
             conv_fetch<KIN, H, H, RSTEP>(RowNext, gx, row0, chk, in, preB);
         }
 
-        v4f acc[CB][kCTY];
+        v4f acc[CB][kWaveRows];
 #pragma unroll
         for (int c = 0; c < CB; ++c)
 #pragma unroll
-            for (int sb = 0; sb < kCTY; ++sb) acc[c][sb] = v4f{0.f, 0.f, 0.f, 0.f};
+            for (int sb = 0; sb < kWaveRows; ++sb) acc[c][sb] = v4f{0.f, 0.f, 0.f, 0.f};
         OP a[CB], an[CB];
 #pragma unroll
         for (int c = 0; c < CB; ++c) a[c] = *reinterpret_cast<const OP *>(Wl + c * 16 * CW);
@@ -226,11 +245,11 @@ __global__ void __launch_bounds__(256) k_conv_tile(Grid3 g, long long N, const u
 #pragma unroll
                 for (int c = 0; c < CB; ++c)
                     an[c] = *reinterpret_cast<const OP *>(Wl + ((t + 1) * OUT + c * 16) * CW);
-            OP b[kCTY];
+            OP b[kWaveRows];
 #pragma unroll
-            for (int sb = 0; sb < kCTY; ++sb) b[sb] = *reinterpret_cast<const OP *>(Lb + (off + sb * kCHX) * CW);
+            for (int sb = 0; sb < kWaveRows; ++sb) b[sb] = *reinterpret_cast<const OP *>(Lb + (off + sb * kCHX) * CW);
 #pragma unroll
-            for (int sb = 0; sb < kCTY; ++sb)
+            for (int sb = 0; sb < kWaveRows; ++sb)
 #pragma unroll
                 for (int c = 0; c < CB; ++c) {
                     if constexpr (KIN == 32)
@@ -244,11 +263,11 @@ __global__ void __launch_bounds__(256) k_conv_tile(Grid3 g, long long N, const u
         }
 
         const int x0 = (tile % ntx) * kCTX, y0 = ((tile / ntx) % nty) * kCTY, z0 = (tile / (ntx * nty)) * kCTZ;
-        const int x = x0 + li, z = z0 + wave;
+        const int x = x0 + li, z = z0 + wz;
         if (x >= g.nx || z >= g.nz) continue;
 #pragma unroll
-        for (int sb = 0; sb < kCTY; ++sb) {
-            const int y = y0 + sb;
+        for (int sb = 0; sb < kWaveRows; ++sb) {
+            const int y = y0 + wy + sb;
             if (y >= g.ny) break;
             const long long s = ((long long)z * g.ny + y) * g.nx + x;
 #pragma unroll
@@ -600,10 +619,10 @@ void cnn_conv_fwd(int layer, const CnnShape &sh, const unsigned short *in, const
     const Grid3 g{sh.nx, sh.ny, sh.nz};
     const unsigned nb = conv_tiles(sh);
     if (net_cop(layer) == 16)
-        hipLaunchKernelGGL((k_conv_tile<32, 16, 1, 0>), dim3(nb), dim3(256), conv_lds(32, 16), st, g, sh.N, in, W, b,
+        hipLaunchKernelGGL((k_conv_tile<32, 16, 1, 0>), dim3(nb), dim3(kConvThreads), conv_lds(32, 16), st, g, sh.N, in, W, b,
                            nullptr, z, a, act);
     else
-        hipLaunchKernelGGL((k_conv_tile<32, 32, 1, 0>), dim3(nb), dim3(256), conv_lds(32, 32), st, g, sh.N, in, W, b,
+        hipLaunchKernelGGL((k_conv_tile<32, 32, 1, 0>), dim3(nb), dim3(kConvThreads), conv_lds(32, 32), st, g, sh.N, in, W, b,
                            nullptr, z, a, act);
 }
 
@@ -613,10 +632,10 @@ void cnn_conv_dgrad(int layer, const CnnShape &sh, const unsigned short *gout, c
     const Grid3 g{sh.nx, sh.ny, sh.nz};
     const unsigned nb = conv_tiles(sh);
     if (net_cop(layer) == 16)
-        hipLaunchKernelGGL((k_conv_tile<16, 32, -1, 1>), dim3(nb), dim3(256), conv_lds(16, 32), st, g, sh.N, gout, WT,
+        hipLaunchKernelGGL((k_conv_tile<16, 32, -1, 1>), dim3(nb), dim3(kConvThreads), conv_lds(16, 32), st, g, sh.N, gout, WT,
                            nullptr, zin, nullptr, gin, 0);
     else
-        hipLaunchKernelGGL((k_conv_tile<32, 32, -1, 1>), dim3(nb), dim3(256), conv_lds(32, 32), st, g, sh.N, gout, WT,
+        hipLaunchKernelGGL((k_conv_tile<32, 32, -1, 1>), dim3(nb), dim3(kConvThreads), conv_lds(32, 32), st, g, sh.N, gout, WT,
                            nullptr, zin, nullptr, gin, 0);
 }
 
