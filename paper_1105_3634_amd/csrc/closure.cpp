@@ -124,12 +124,21 @@ int net_grid(const mlb_net_s *n, int *nx, int *ny, int *nz)
     return 0;
 }
 
+// the last layer writes the force fields itself (same values as the y
+// buffer scaled by f_ref, without the [N][16] round trip)
 void net_infer_fields(mlb_net_s *n, const float *dens, const float *mom, float *force, hipStream_t st)
 {
     const CnnShape sh = shape_of(*n);
     cnn_pack_input(sh, dens, mom, n->n_ref, n->j_ref, at<unsigned short>(*n, n->x), st);
-    forward(*n, false, st);
-    cnn_unpack_output(sh, at<float>(*n, n->y), n->f_ref, force, st);
+    const unsigned short *in = at<unsigned short>(*n, n->x);
+    for (int l = 0; l < kNetLayers - 1; ++l) {
+        const auto &L = n->L[l];
+        unsigned short *a = at<unsigned short>(*n, n->a[l]);
+        cnn_conv_fwd(l, sh, in, at<unsigned short>(*n, L.wb), at<float>(*n, L.b), nullptr, a, 1, st);
+        in = a;
+    }
+    const auto &L = n->L[kNetLayers - 1];
+    cnn_conv_out_fields(sh, in, at<unsigned short>(*n, L.wb), at<float>(*n, L.b), n->f_ref, force, st);
 }
 
 float *net_check_buffer(mlb_net_s *n) { return at<float>(*n, n->nc); }

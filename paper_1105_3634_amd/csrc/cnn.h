@@ -28,6 +28,9 @@ bool cnn_prepare();
 // z (float32, may be null) = conv(in) + b; a (bf16, may be null) = act ? silu(z) : z
 void cnn_conv_fwd(int layer, const CnnShape &sh, const unsigned short *in, const unsigned short *W, const float *b,
                   float *z, unsigned short *a, int act, hipStream_t st);
+// last layer straight into lattice fields: Nf [6][N] = (conv(in) + b) * scale
+void cnn_conv_out_fields(const CnnShape &sh, const unsigned short *in, const unsigned short *W, const float *b,
+                         float scale, float *Nf, hipStream_t st);
 // gin = conv^T(gout) * silu'(zin)   (layers 1..3)
 void cnn_conv_dgrad(int layer, const CnnShape &sh, const unsigned short *gout, const unsigned short *WT,
                     const float *zin, unsigned short *gin, hipStream_t st);

@@ -65,6 +65,8 @@ __device__ inline long long shift_site(const Grid3 &g, int x, int y, int z, int 
 //     (float32, optional), aout = act ? silu(z) : z (bf16, optional)
 //   data gradient (SGN = -1, EPI 1): W = transposed weights [t][ci][co];
 //     gin = acc * silu'(zin) (bf16)
+//   output layer into lattice fields (SGN = +1, EPI 2): zout[o][s] =
+//     (acc + b) * scale for the kNetOut channels, channel-first float32
 // Persistent blocks (one per CU) walk 16 x 8 x 4 tiles; within a tile each
 // wave owns kWaveRows rows of 16 consecutive x in one z plane (one MFMA site
 // block per row) and all OUT channels (2 kWaveRows independent accumulators
@@ -160,7 +162,8 @@ template <int KIN, int OUT, int SGN, int EPI>
 __global__ void __launch_bounds__(kConvThreads) k_conv_tile(Grid3 g, long long N, const unsigned short *__restrict__ in,
                                                   const unsigned short *__restrict__ W,
                                                   const float *__restrict__ bias, const float *__restrict__ zin,
-                                                  float *__restrict__ zout, unsigned short *__restrict__ aout, int act)
+                                                  float *__restrict__ zout, unsigned short *__restrict__ aout, int act,
+                                                  float scale)
 {
     extern __shared__ __align__(16) unsigned char Ls[];
     constexpr int CW = KIN / 2, NCH = 4, CB = OUT / 16;       // chunk bytes; 4 chunks per site or weight row
@@ -287,6 +290,9 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_tile(Grid3 g, long long N
                                                     (unsigned)av[2] | ((unsigned)av[3] << 16));
                         *reinterpret_cast<uint2 *>(aout + s * OUT + o0) = pk;
                     }
+                } else if constexpr (EPI == 2) {
+                    for (int v = 0; v < 4; ++v)
+                        if (o0 + v < kNetOut) zout[(long long)(o0 + v) * N + s] = (acc[c][sb][v] + bias[o0 + v]) * scale;
                 } else {
                     const float4 zz = *reinterpret_cast<const float4 *>(zin + s * OUT + o0);
                     const float zi[4] = {zz.x, zz.y, zz.z, zz.w};
@@ -607,6 +613,8 @@ bool cnn_prepare()
                                conv_lds(32, 32)) == hipSuccess &&
            hipFuncSetAttribute((const void *)k_conv_tile<32, 16, 1, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                conv_lds(32, 16)) == hipSuccess &&
+           hipFuncSetAttribute((const void *)k_conv_tile<32, 16, 1, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               conv_lds(32, 16)) == hipSuccess &&
            hipFuncSetAttribute((const void *)k_conv_tile<32, 32, -1, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                conv_lds(32, 32)) == hipSuccess &&
            hipFuncSetAttribute((const void *)k_conv_tile<16, 32, -1, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -620,10 +628,18 @@ void cnn_conv_fwd(int layer, const CnnShape &sh, const unsigned short *in, const
     const unsigned nb = conv_tiles(sh);
     if (net_cop(layer) == 16)
         hipLaunchKernelGGL((k_conv_tile<32, 16, 1, 0>), dim3(nb), dim3(kConvThreads), conv_lds(32, 16), st, g, sh.N, in, W, b,
-                           nullptr, z, a, act);
+                           nullptr, z, a, act, 1.f);
     else
         hipLaunchKernelGGL((k_conv_tile<32, 32, 1, 0>), dim3(nb), dim3(kConvThreads), conv_lds(32, 32), st, g, sh.N, in, W, b,
-                           nullptr, z, a, act);
+                           nullptr, z, a, act, 1.f);
+}
+
+void cnn_conv_out_fields(const CnnShape &sh, const unsigned short *in, const unsigned short *W, const float *b,
+                         float scale, float *Nf, hipStream_t st)
+{
+    const Grid3 g{sh.nx, sh.ny, sh.nz};
+    hipLaunchKernelGGL((k_conv_tile<32, 16, 1, 2>), dim3(conv_tiles(sh)), dim3(kConvThreads), conv_lds(32, 16), st, g,
+                       sh.N, in, W, b, nullptr, Nf, nullptr, 0, scale);
 }
 
 void cnn_conv_dgrad(int layer, const CnnShape &sh, const unsigned short *gout, const unsigned short *WT, const float *zin,
@@ -633,10 +649,10 @@ void cnn_conv_dgrad(int layer, const CnnShape &sh, const unsigned short *gout, c
     const unsigned nb = conv_tiles(sh);
     if (net_cop(layer) == 16)
         hipLaunchKernelGGL((k_conv_tile<16, 32, -1, 1>), dim3(nb), dim3(kConvThreads), conv_lds(16, 32), st, g, sh.N, gout, WT,
-                           nullptr, zin, nullptr, gin, 0);
+                           nullptr, zin, nullptr, gin, 0, 1.f);
     else
         hipLaunchKernelGGL((k_conv_tile<32, 32, -1, 1>), dim3(nb), dim3(kConvThreads), conv_lds(32, 32), st, g, sh.N, gout, WT,
-                           nullptr, zin, nullptr, gin, 0);
+                           nullptr, zin, nullptr, gin, 0, 1.f);
 }
 
 void cnn_conv_wgrad(int layer, const CnnShape &sh, const unsigned short *gout, const unsigned short *ain, float *part,
