@@ -334,7 +334,9 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(Grid3 g, long long N, const 
     for (int c = 0; c < COP; ++c) Gs[c][tid] = ok ? gout[me * COP + c] : (unsigned short)0;
     constexpr int BM = COP / 16, BN = CIP / 16, NBLK = BM * BN;
     float *out = part + (long long)blockIdx.x * (27 * COP * CIP + COP);
-    for (int t = 0; t < 27; ++t) {
+    // blockIdx.y picks a third of the taps (one dz plane): three workgroups
+    // per chunk fill disjoint parts of the chunk's partial row
+    for (int t = 9 * (int)blockIdx.y; t < 9 * (int)blockIdx.y + 9; ++t) {
         const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
         __syncthreads();
         if (ok) {
@@ -362,21 +364,31 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(Grid3 g, long long N, const 
         }
     }
     __syncthreads();
-    if (tid < COP) {
+    if (blockIdx.y == 0 && tid < COP) {
         float sb = 0.f;
         for (int k = 0; k < 256; ++k) sb += bf2f(Gs[tid][k]);
         out[27 * COP * CIP + tid] = sb;
     }
 }
 
-// sum the per-workgroup partial rows in order: out[i] = sum_w part[w][i]
-__global__ void k_sum_rows(const float *__restrict__ part, int nrows, int len, float *__restrict__ out)
+// out[i] = sum_w part[w][i] in a fixed order: the rows are split into four
+// contiguous quarters, each summed in order by its own thread (64 columns
+// per block), and the quarter sums are added in quarter order
+__global__ void __launch_bounds__(256) k_sum_rows(const float *__restrict__ part, int nrows, int len,
+                                                  float *__restrict__ out)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= len) return;
+    __shared__ float red[4][64];
+    const int c = threadIdx.x % 64, q = threadIdx.x / 64;
+    const int i = blockIdx.x * 64 + c;
+    const int per = (nrows + 3) / 4, w0 = min(nrows, q * per), w1 = min(nrows, w0 + per);
     float s = 0.f;
-    for (int w = 0; w < nrows; ++w) s += part[(long long)w * len + i];
-    out[i] = s;
+    if (i < len) {
+#pragma unroll 8
+        for (int w = w0; w < w1; ++w) s += part[(long long)w * len + i];
+    }
+    red[q][c] = s;
+    __syncthreads();
+    if (q == 0 && i < len) out[i] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
 }
 
 // ------------------------------------------------------------- loss
@@ -662,11 +674,11 @@ void cnn_conv_wgrad(int layer, const CnnShape &sh, const unsigned short *gout, c
     const unsigned nb = nblocks(sh.N);
     int cip = 32, cop = 32;
     switch (layer) {
-    case 3: cop = 16; hipLaunchKernelGGL((k_conv_wgrad<32, 16>), dim3(nb), dim3(256), 0, st, g, sh.N, gout, ain, part); break;
-    default: hipLaunchKernelGGL((k_conv_wgrad<32, 32>), dim3(nb), dim3(256), 0, st, g, sh.N, gout, ain, part); break;
+    case 3: cop = 16; hipLaunchKernelGGL((k_conv_wgrad<32, 16>), dim3(nb, 3), dim3(256), 0, st, g, sh.N, gout, ain, part); break;
+    default: hipLaunchKernelGGL((k_conv_wgrad<32, 32>), dim3(nb, 3), dim3(256), 0, st, g, sh.N, gout, ain, part); break;
     }
     const int len = 27 * cop * cip + cop;
-    hipLaunchKernelGGL(k_sum_rows, dim3(nblocks(len)), dim3(256), 0, st, part, (int)nb, len, gw);
+    hipLaunchKernelGGL(k_sum_rows, dim3((len + 63) / 64), dim3(256), 0, st, part, (int)nb, len, gw);
 }
 
 size_t cnn_wgrad_part_floats(int layer, long long N)
