@@ -56,13 +56,13 @@ namespace mlb {
 #ifndef MLB_S2_WAVES
 #define MLB_S2_WAVES 6
 #endif
-// z-paired LDS layout (below) in the first / second gather where the tile
-// shape allows it
-#ifndef MLB_G1_ZPAIR
-#define MLB_G1_ZPAIR 0
+// Bank-aware lane layouts (below) allowed in the first / second gather, a
+// bit mask: 1 = z-paired (8-wide tiles), 2 = z-major (16-wide tiles)
+#ifndef MLB_G1_LAYOUTS
+#define MLB_G1_LAYOUTS 2
 #endif
-#ifndef MLB_S2_ZPAIR
-#define MLB_S2_ZPAIR 1
+#ifndef MLB_S2_LAYOUTS
+#define MLB_S2_LAYOUTS 3
 #endif
 constexpr int kSplitG1 = MLB_G1_SPLIT, kSplitS2 = MLB_S2_SPLIT;
 constexpr int kGather1Threads = kSplitG1 * kBlock, kStep2Threads = kSplitS2 * kBlock;
@@ -112,22 +112,33 @@ struct TileGeo {
     int FS;               // floats per staged field
 };
 
-// Bank layout of the gathers' staged tiles.  LDS has 64 banks of 4 bytes,
-// and one cycle of a 16-byte read serves 16 lanes.  With 8-wide tiles and
-// lanes laid out x, then y, those 16 lanes cover two x rows of the halo tile,
-// and at halo widths such as 16 the rows lie a multiple of 256 bytes apart:
-// the same banks, so every read of the shell loops takes two cycles.  Such
-// tiles ("z-paired") therefore pad the z planes of the staged arrays to a
-// pitch of 8 mod 16 sites and give lanes 8..15 of every 16 the next z plane
-// instead of the next y row; the two halves then lie 128 bytes apart modulo
-// 256, on disjoint banks, and the 4-byte g reads of a whole wave (4 y rows
-// x 2 planes x 8 x) fall on distinct banks as well.  Other shapes keep
-// unpadded planes and the plain lane order.
-__host__ __device__ constexpr bool zpair_shape(int TX, int TZ) { return TX == 8 && TZ % 2 == 0; }
+// Bank layouts of the gathers' staged tiles.  LDS has 64 banks of 4 bytes;
+// one clock of a 16-byte read serves 16 consecutive lanes, consecutive
+// 8-lane blocks must lie on opposite 128-byte halves (mod 256), and the
+// 16-lane runs of a read must start at the same offset mod 256 (measured).
+// The plain order (x, then y, then z) breaks this wherever a halo row is a
+// multiple of 256 bytes (8-wide tiles, rows of 16 sites) or 128 mod 256
+// (16-wide tiles, rows of 24 sites): every shell-loop read then takes two
+// clocks.  Two layouts avoid it:
+// - z-paired (8-wide tiles, TZ even): z planes padded to a pitch of 8 mod 16
+//   sites, lanes 8..15 of every 16 on the next plane instead of the next
+//   row; the two 8-lane halves lie 128 bytes apart mod 256, and the 4-byte g
+//   reads of a wave (4 rows x 2 planes x 8 x) fall on distinct banks too.
+// - z-major (16-wide tiles): z planes padded to a multiple of 16 sites
+//   (none at halo 4: 24 x 12 sites), the 16-lane runs on consecutive planes,
+//   all starting at the same offset mod 256.
+// Layout 0 keeps unpadded planes and the plain order.
+__host__ __device__ constexpr int lane_layout(int TX, int TZ, int allowed)
+{
+    return (TX == 8 && TZ % 2 == 0 && (allowed & 1)) ? 1 : (TX == 16 && (allowed & 2)) ? 2 : 0;
+}
 
-__host__ __device__ inline int zpair_pitch(int plane) { return plane + ((24 - plane % 16) % 16); }
+__host__ __device__ inline int plane_pitch(int LM, int plane)
+{
+    return LM == 1 ? plane + ((24 - plane % 16) % 16) : LM == 2 ? (plane + 15) / 16 * 16 : plane;
+}
 
-template <int TX, int TY, int TZ, bool ZP = false>
+template <int TX, int TY, int TZ, int LM = 0>
 __device__ inline TileGeo tile_geo(const SysDesc<float> &S, int local, int R)
 {
     TileGeo t;
@@ -136,7 +147,7 @@ __device__ inline TileGeo tile_geo(const SysDesc<float> &S, int local, int R)
     t.x0 = bx * TX; t.y0 = by * TY; t.z0 = bz * TZ;
     t.R = R;
     t.HX = TX + 2 * t.R; t.HY = TY + 2 * t.R; t.HZ = TZ + 2 * t.R;
-    t.PXY = ZP ? zpair_pitch(t.HX * t.HY) : t.HX * t.HY;
+    t.PXY = plane_pitch(LM, t.HX * t.HY);
     t.FS = t.PXY * t.HZ;
     return t;
 }
@@ -191,8 +202,9 @@ __device__ inline void fill_rows(const SysDesc<float> &S, const TileGeo &t, int 
     }
 }
 
-// Z-paired tiles (ZP) take each row's LDS base from RowL, others use row HX.
-template <bool ZP>
+// Padded layouts (LM != 0) take each row's LDS base from RowL, the plain one
+// uses row HX.
+template <int LM>
 __device__ inline void stage(const SysDesc<float> &S, const TileGeo &t, const StageLane &l, const int *RowOff,
                              const int *RowL, float4 *lds4, float *ldsg, const gfloat *__restrict__ nb,
                              const gfloat *__restrict__ vb, const gfloat *__restrict__ gp)
@@ -202,7 +214,7 @@ __device__ inline void stage(const SysDesc<float> &S, const TileGeo &t, const St
     if (l.rstep == 0) return;
     for (int row = l.row0; row < rows; row += l.rstep) {
         const int ro = RowOff[row];
-        const int i = l.hx + (ZP ? RowL[row] : row * t.HX);
+        const int i = l.hx + (LM ? RowL[row] : row * t.HX);
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         float g = 0.f;
         if (ro >= 0) {
@@ -217,7 +229,7 @@ __device__ inline void stage(const SysDesc<float> &S, const TileGeo &t, const St
 
 // Second gather: one float4 per halo site, (n_b V_b, g_ab); the shell loop
 // then needs no separate g reads and no product with n_b.
-template <bool ZP>
+template <int LM>
 __device__ inline void stage_nv(const SysDesc<float> &S, const TileGeo &t, const StageLane &l, const int *RowOff,
                                 const int *RowL, float4 *lds4, const gfloat *__restrict__ nb,
                                 const gfloat *__restrict__ vb, const gfloat *__restrict__ gp)
@@ -227,7 +239,7 @@ __device__ inline void stage_nv(const SysDesc<float> &S, const TileGeo &t, const
     if (l.rstep == 0) return;
     for (int row = l.row0; row < rows; row += l.rstep) {
         const int ro = RowOff[row];
-        const int i = l.hx + (ZP ? RowL[row] : row * t.HX);
+        const int i = l.hx + (LM ? RowL[row] : row * t.HX);
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         if (ro >= 0) {
             const unsigned so = (unsigned)(ro + l.gx);
@@ -299,18 +311,23 @@ struct TileSite {
     int c;   // LDS offset of the site
 };
 
-// Site of this thread: x fastest, then y, then z; z-paired tiles (ZP) take
-// x, then one bit of z, then y, then the rest of z.
-template <int TX, int TY, int TZ, bool ZP = false>
+// Site of this thread: x fastest, then y, then z; z-paired tiles (LM 1)
+// take x, then one bit of z, then y, then the rest of z; z-major tiles
+// (LM 2) x, then z, then y.
+template <int TX, int TY, int TZ, int LM = 0>
 __device__ inline TileSite tile_site(const SysDesc<float> &S, const TileGeo &t)
 {
     TileSite q;
     const int i = threadIdx.x % (TX * TY * TZ);
     q.tx = i % TX;
-    if (ZP) {
+    if (LM == 1) {
         const int j = i / (2 * TX);
         q.ty = j % TY;
         q.tz = 2 * (j / TY) + (i / TX) % 2;
+    } else if (LM == 2) {
+        const int j = i / TX;
+        q.tz = j % TZ;
+        q.ty = j / TZ;
     } else {
         q.ty = (i / TX) % TY;
         q.tz = i / (TX * TY);
@@ -335,9 +352,9 @@ k_gather1_tile(const SysDesc<float> *__restrict__ sys,
     const SysDesc<float> &S = sys[bm.x];
     const int a = blockIdx.y;
     if (a >= S.M) return;
-    constexpr bool ZP = MLB_G1_ZPAIR && zpair_shape(TX, TZ);
-    const TileGeo t = tile_geo<TX, TY, TZ, ZP>(S, bm.y, S.reach);
-    const TileSite q = tile_site<TX, TY, TZ, ZP>(S, t);
+    constexpr int LM = lane_layout(TX, TZ, MLB_G1_LAYOUTS);
+    const TileGeo t = tile_geo<TX, TY, TZ, LM>(S, bm.y, S.reach);
+    const TileSite q = tile_site<TX, TY, TZ, LM>(S, t);
     const int h = __builtin_amdgcn_readfirstlane(threadIdx.x / kBlock);   // wave-uniform
     const long long N = S.N;
     const long long o3 = (long long)a * 3 * N;
@@ -347,7 +364,7 @@ k_gather1_tile(const SysDesc<float> *__restrict__ sys,
     int *RowL = RowOff + t.HY * t.HZ;
     const int HXY = t.PXY;
     const StageLane sl = stage_lane<kGather1Threads>(S, t);
-    fill_rows<kGather1Threads>(S, t, RowOff, ZP ? RowL : nullptr);
+    fill_rows<kGather1Threads>(S, t, RowOff, LM ? RowL : nullptr);
     const char *c4 = reinterpret_cast<const char *>(L4 + q.c);
     const char *cg = reinterpret_cast<const char *>(Lg + q.c);
     const bool solid = q.active && S.walls && (q.y == 0 || q.y == S.ny - 1);
@@ -364,7 +381,7 @@ k_gather1_tile(const SysDesc<float> *__restrict__ sys,
         int kb, ke;
         split_range<kSplitG1>(S.sh_cnt[a][b], h, kb, ke);
         __syncthreads();
-        stage<ZP>(S, t, sl, RowOff, RowL, L4, Lg, glb(S.n) + (long long)b * N, glb(S.j) + (long long)b * 3 * N, gpair);
+        stage<LM>(S, t, sl, RowOff, RowL, L4, Lg, glb(S.n) + (long long)b * N, glb(S.j) + (long long)b * 3 * N, gpair);
         __syncthreads();
         const ConstF4 Q = shell_list(tb, S.sh_start[a][b]);
         const float g0 = Lg[q.c];
@@ -468,9 +485,9 @@ k_step2_tile(const SysDesc<float> *__restrict__ sys,
     const SysDesc<float> &S = sys[bm.x];
     const int a = blockIdx.y;
     if (a >= S.M) return;
-    constexpr bool ZP = MLB_S2_ZPAIR && zpair_shape(TX, TZ);
-    const TileGeo t = tile_geo<TX, TY, TZ, ZP>(S, bm.y, S.reach);
-    const TileSite q = tile_site<TX, TY, TZ, ZP>(S, t);
+    constexpr int LM = lane_layout(TX, TZ, MLB_S2_LAYOUTS);
+    const TileGeo t = tile_geo<TX, TY, TZ, LM>(S, bm.y, S.reach);
+    const TileSite q = tile_site<TX, TY, TZ, LM>(S, t);
     const long long N = S.N;
     const long long o3 = (long long)a * 3 * N;
     float4 *L4 = lds;
@@ -516,14 +533,14 @@ k_step2_tile(const SysDesc<float> *__restrict__ sys,
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
     if (S.scheme != 1) {
         const StageLane sl = stage_lane<kStep2Threads>(S, t);
-        fill_rows<kStep2Threads>(S, t, RowOff, ZP ? RowL : nullptr);
+        fill_rows<kStep2Threads>(S, t, RowOff, LM ? RowL : nullptr);
         const char *c4 = reinterpret_cast<const char *>(L4 + q.c);
         for (int b = 0; b < S.M; ++b) {
             const gfloat *__restrict__ gpair = glb(S.g) + (long long)pidx(S.M, a, b) * N;
             int kb, ke;
             split_range<kSplitS2>(S.sh_cnt[a][b], h, kb, ke);
             __syncthreads();
-            stage_nv<ZP>(S, t, sl, RowOff, RowL, L4, glb(S.n) + (long long)b * N, glb(S.vh) + (long long)b * 3 * N,
+            stage_nv<LM>(S, t, sl, RowOff, RowL, L4, glb(S.n) + (long long)b * N, glb(S.vh) + (long long)b * 3 * N,
                          gpair);
             __syncthreads();
             const ConstF4 Q = shell_list(tb, S.sh_start[a][b]);
@@ -664,11 +681,12 @@ inline size_t contact_lds_bytes(int TX, int TY, int TZ, int R, int ball_total, i
 // and, z-paired, the row-base table (one int each per halo row); at least
 // the partial sums of the split reductions (13 floats per site and group in
 // the first gather, 3 in the second)
-inline size_t tile_lds_bytes(int TX, int TY, int TZ, int R, bool zpair, bool second)
+inline size_t tile_lds_bytes(int TX, int TY, int TZ, int R, int layouts, bool second)
 {
     const int plane = (TX + 2 * R) * (TY + 2 * R);
-    const bool zp = zpair && zpair_shape(TX, TZ);
-    const size_t FS = (size_t)(zp ? zpair_pitch(plane) : plane) * (TZ + 2 * R);
+    const int LM = lane_layout(TX, TZ, layouts);
+    const bool zp = LM != 0;
+    const size_t FS = (size_t)plane_pitch(LM, plane) * (TZ + 2 * R);
     const size_t rows = (size_t)(TY + 2 * R) * (TZ + 2 * R);
     const size_t reduce = (second ? (size_t)kSplitS2 * 3 : (size_t)kSplitG1 * 13) * kBlock * 4;
     return std::max(16 * FS + (second ? 0 : 16 * ((FS + 3) / 4)) + (zp ? 8 : 4) * rows, reduce);

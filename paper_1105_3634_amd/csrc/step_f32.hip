@@ -21,18 +21,18 @@ int tile_count(int v, int nx, int ny, int nz)
 }
 
 namespace {
-size_t gather_lds_bytes_of(int v, int reach, bool zpair, bool second)
+size_t gather_lds_bytes_of(int v, int reach, int layouts, bool second)
 {
     int tx, ty, tz;
     tile_dims(v, tx, ty, tz);
     if (tx + 2 * reach > kBlock) return SIZE_MAX;   // not stageable: one halo column per thread
-    return tile_lds_bytes(tx, ty, tz, reach, zpair, second);
+    return tile_lds_bytes(tx, ty, tz, reach, layouts, second);
 }
 }  // namespace
 
 size_t tile_lds_bytes_of(int v, int reach)
 {
-    return std::max(gather_lds_bytes_of(v, reach, MLB_G1_ZPAIR, false), gather_lds_bytes_of(v, reach, MLB_S2_ZPAIR, true));
+    return std::max(gather_lds_bytes_of(v, reach, MLB_G1_LAYOUTS, false), gather_lds_bytes_of(v, reach, MLB_S2_LAYOUTS, true));
 }
 
 size_t contact_lds_bytes_of(int v, int ball_reach, int ball_total, int maxM)
@@ -47,8 +47,8 @@ namespace {
 template <int TX, int TY, int TZ>
 bool prepare_one(int reach, int ball_reach, int ball_total, int maxM)
 {
-    const size_t bytes = std::max(tile_lds_bytes(TX, TY, TZ, reach, MLB_G1_ZPAIR, false),
-                                  tile_lds_bytes(TX, TY, TZ, reach, MLB_S2_ZPAIR, true));
+    const size_t bytes = std::max(tile_lds_bytes(TX, TY, TZ, reach, MLB_G1_LAYOUTS, false),
+                                  tile_lds_bytes(TX, TY, TZ, reach, MLB_S2_LAYOUTS, true));
     const size_t cbytes = contact_lds_bytes(TX, TY, TZ, ball_reach, ball_total, maxM);
     if (bytes > 160 * 1024 || cbytes > 160 * 1024) return false;
     // staging gives each thread one halo column
@@ -83,7 +83,7 @@ void launch_contact_tile(int v, const SysDesc<float> *sys, const int2 *map, int 
 void launch_gather1_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM, Tables<float> tb,
                          int reach_max, hipStream_t st)
 {
-    const size_t lds = gather_lds_bytes_of(v, reach_max, MLB_G1_ZPAIR, false);
+    const size_t lds = gather_lds_bytes_of(v, reach_max, MLB_G1_LAYOUTS, false);
     const dim3 grid(nblk, maxM);
     if (v == 0) hipLaunchKernelGGL((k_gather1_tile<16, 4, 4>), grid, dim3(kGather1Threads), lds, st, sys, map, tb);
     else if (v == 1) hipLaunchKernelGGL((k_gather1_tile<8, 8, 4>), grid, dim3(kGather1Threads), lds, st, sys, map, tb);
@@ -93,7 +93,7 @@ void launch_gather1_tile(int v, const SysDesc<float> *sys, const int2 *map, int 
 void launch_step2_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM, Tables<float> tb,
                        int reach_max, int parity, int write_force_only, hipStream_t st)
 {
-    const size_t lds = gather_lds_bytes_of(v, reach_max, MLB_S2_ZPAIR, true);
+    const size_t lds = gather_lds_bytes_of(v, reach_max, MLB_S2_LAYOUTS, true);
     const dim3 grid(nblk, maxM);
     if (v == 0)
         hipLaunchKernelGGL((k_step2_tile<16, 4, 4>), grid, dim3(kStep2Threads), lds, st, sys, map, tb, parity, write_force_only);
