@@ -196,10 +196,21 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_tile(Grid3 g, long long N
     constexpr int H = MAXK / 2;
     static_assert(2 * H == MAXK, "two prefetch halves");
     CT preA[H], preB[H];
-    if ((int)blockIdx.x < ntiles) conv_rows(g, ntx, nty, blockIdx.x, RowOff);
+    // Tile walk.  Workgroup b runs on XCD b mod 8; with a multiple of 8
+    // blocks and at least one tile each, the blocks of one XCD take one
+    // contiguous eighth of the tiles (tile lo + w, lo + w + blocks/8, ...), so
+    // the halos that neighbouring tiles share come from that XCD's L2.
+    int t0 = blockIdx.x, tstep = gridDim.x, tend = ntiles;
+    if (gridDim.x % 8 == 0 && ntiles >= (int)gridDim.x) {
+        const int xcd = blockIdx.x % 8;
+        tstep = gridDim.x / 8;
+        t0 = (int)((long long)xcd * ntiles / 8) + (int)blockIdx.x / 8;
+        tend = (int)((long long)(xcd + 1) * ntiles / 8);
+    }
+    if (t0 < tend) conv_rows(g, ntx, nty, t0, RowOff);
     __syncthreads();
-    if (stager && (int)blockIdx.x < ntiles) {
-        const unsigned gx = column(blockIdx.x);
+    if (stager && t0 < tend) {
+        const unsigned gx = column(t0);
         conv_fetch<KIN, H, 0, RSTEP>(RowOff, gx, row0, chk, in, preA);
         conv_fetch<KIN, H, H, RSTEP>(RowOff, gx, row0, chk, in, preB);
     }
@@ -213,11 +224,11 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_tile(Grid3 g, long long N
     const unsigned char *Wl = Lwt + gq * PW + li * CW;
     typedef typename std::conditional<KIN == 32, v8bf, v4s>::type OP;
 
-    for (int tile = blockIdx.x, it = 0; tile < ntiles; tile += gridDim.x, ++it) {
+    for (int tile = t0, it = 0; tile < tend; tile += tstep, ++it) {
         __syncthreads();   // the previous tile's reads of Lin are done
-        const int next = tile + (int)gridDim.x;
+        const int next = tile + tstep;
         int *RowNext = RowOff + ((it + 1) & 1) * kCRows;
-        if (next < ntiles) conv_rows(g, ntx, nty, next, RowNext);
+        if (next < tend) conv_rows(g, ntx, nty, next, RowNext);
         if (stager) {
 #pragma unroll
             for (int k = 0; k < H; ++k) {
@@ -226,7 +237,7 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_tile(Grid3 g, long long N
             }
         }
         __syncthreads();
-        if (stager && next < ntiles) {
+        if (stager && next < tend) {
             const unsigned gx = column(next);
             conv_fetch<KIN, H, 0, RSTEP>(RowNext, gx, row0, chk, in, preA);
             conv_fetch<KIN, H, H, RSTEP>(RowNext, gx, row0, chk, in, preB);

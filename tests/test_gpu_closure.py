@@ -57,7 +57,9 @@ def random_layers(seed, scale_b=0.1):
     return layers
 
 
-@pytest.mark.parametrize("shape", [(9, 10, 12), (4, 4, 4), (3, 5, 17)])
+# (70, 30, 60): 288 tiles of 16 x 8 x 4, more than one per CU, ragged in
+# every direction: the persistent blocks walk XCD-contiguous tile ranges
+@pytest.mark.parametrize("shape", [(9, 10, 12), (4, 4, 4), (3, 5, 17), (70, 30, 60)])
 def test_forward_matches_oracle(mlb, shape):
     print(f"forward parity shape={shape}", flush=True)
     layers = random_layers(7)
