@@ -44,7 +44,10 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 __device__ inline unsigned short f2bf(float f) { return __builtin_bit_cast(unsigned short, (__bf16)f); }
 __device__ inline float bf2f(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
 
-__device__ inline float sigm(float z) { return 1.f / (1.f + __expf(-z)); }
+// logistic function with the hardware reciprocal (v_rcp_f32, about 1 ulp):
+// its results are rounded to bfloat16 or feed bfloat16 products, so the
+// correctly rounded division sequence would buy nothing
+__device__ inline float sigm(float z) { return __builtin_amdgcn_rcpf(1.f + __expf(-z)); }
 
 struct Grid3 {
     int nx, ny, nz;
