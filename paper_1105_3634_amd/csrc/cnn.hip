@@ -110,7 +110,7 @@ __host__ __device__ constexpr int conv_plane(int cw) { return cw == 16 ? (kCHS *
 
 __host__ __device__ constexpr int conv_lds(int kin, int out)
 {
-    return 4 * conv_plane(kin / 2) + 4 * 27 * out * (kin / 2) + 2 * 4 * kCRows;
+    return 4 * conv_plane(kin / 2) + 4 * 27 * out * (kin / 2) + 2 * 4 * kCRows + 4 * out;
 }
 
 __device__ inline int wrap_cell(int v, int n)
@@ -179,6 +179,7 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_tile(Grid3 g, long long N
     unsigned char *Lin = Ls;                                  // [NCH][kCHS][CW]
     unsigned char *Lwt = Ls + NCH * PI;                       // [NCH][WROWS][CW]
     int *RowOff = reinterpret_cast<int *>(Lwt + NCH * PW);    // [2][kCRows], by tile parity
+    float *Lbias = reinterpret_cast<float *>(RowOff + 2 * kCRows);   // [OUT]
     const int tid = threadIdx.x;
     const int ntx = (g.nx + kCTX - 1) / kCTX, nty = (g.ny + kCTY - 1) / kCTY, ntz = (g.nz + kCTZ - 1) / kCTZ;
     const int ntiles = ntx * nty * ntz;
@@ -211,6 +212,7 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_tile(Grid3 g, long long N
         tend = (int)((long long)(xcd + 1) * ntiles / 8);
     }
     if (t0 < tend) conv_rows(g, ntx, nty, t0, RowOff);
+    if (tid < OUT) Lbias[tid] = EPI == 1 ? 0.f : bias[tid];
     __syncthreads();
     if (stager && t0 < tend) {
         const unsigned gx = column(t0);
@@ -226,6 +228,14 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_tile(Grid3 g, long long N
     // weight row co = c 16 + li of tap t is chunk row t OUT + co
     const unsigned char *Wl = Lwt + gq * PW + li * CW;
     typedef typename std::conditional<KIN == 32, v8bf, v4s>::type OP;
+
+    // the lane's bias values, read once through LDS: a global load in the
+    // epilogue would wait (vmcnt) for the next tile's prefetch as well
+    float bl[CB][4];
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) bl[c][v] = Lbias[c * 16 + 4 * gq + v];
 
     for (int tile = t0, it = 0; tile < tend; tile += tstep, ++it) {
         __syncthreads();   // the previous tile's reads of Lin are done
@@ -294,7 +304,7 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_tile(Grid3 g, long long N
                     float zv[4];
                     unsigned short av[4];
                     for (int v = 0; v < 4; ++v) {
-                        zv[v] = acc[c][sb][v] + bias[o0 + v];
+                        zv[v] = acc[c][sb][v] + bl[c][v];
                         av[v] = f2bf(act ? zv[v] * sigm(zv[v]) : zv[v]);
                     }
                     if (zout)
@@ -306,7 +316,7 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_tile(Grid3 g, long long N
                     }
                 } else if constexpr (EPI == 2) {
                     for (int v = 0; v < 4; ++v)
-                        if (o0 + v < kNetOut) zout[(long long)(o0 + v) * N + s] = (acc[c][sb][v] + bias[o0 + v]) * scale;
+                        if (o0 + v < kNetOut) zout[(long long)(o0 + v) * N + s] = (acc[c][sb][v] + bl[c][v]) * scale;
                 } else {
                     const float4 zz = *reinterpret_cast<const float4 *>(zin + s * OUT + o0);
                     const float zi[4] = {zz.x, zz.y, zz.z, zz.w};
