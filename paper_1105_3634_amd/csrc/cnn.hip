@@ -521,16 +521,24 @@ __global__ void k_cast_weights(int n, int COP, int CIP, int cin, int split, cons
 }
 
 // ---------------------------------------------------------- packing
-// split first-layer input of one site: x[0..31] = [hi(v) | lo(v) | hi(v) | 0]
+// split first-layer input of one site: x[0..31] = [hi(v) | lo(v) | hi(v) | 0],
+// written as four 16-byte stores (a site's 64 bytes are 16-byte aligned)
 __device__ inline void store_input(unsigned short *__restrict__ x, const float v[8])
 {
-    for (int c = 0; c < 8; ++c) {
-        const unsigned short hi = f2bf(v[c]);
-        x[c] = hi;
-        x[8 + c] = f2bf(v[c] - bf2f(hi));
-        x[16 + c] = hi;
-        x[24 + c] = 0;
+    unsigned hi[4], lo[4];
+#pragma unroll
+    for (int c = 0; c < 8; c += 2) {
+        const unsigned short h0 = f2bf(v[c]), h1 = f2bf(v[c + 1]);
+        const unsigned short l0 = f2bf(v[c] - bf2f(h0)), l1 = f2bf(v[c + 1] - bf2f(h1));
+        hi[c / 2] = (unsigned)h0 | ((unsigned)h1 << 16);
+        lo[c / 2] = (unsigned)l0 | ((unsigned)l1 << 16);
     }
+    uint4 *o = reinterpret_cast<uint4 *>(x);
+    const uint4 H = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+    o[0] = H;
+    o[1] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+    o[2] = H;
+    o[3] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 // network input of site s: (n_0, n_1) / n_ref - 1, (j_0, j_1) / j_ref
