@@ -144,11 +144,11 @@ def d12_check(mlb, mix, n0, u0):
 def closure_leg(mlb, W, steps=5000, train_box=(192, 12, 12)):
     """Learned force closure on the 192x64x64 binary workload at the
     step-binary physics: train the network on snapshots of the plain solver
-    (a 192x12x12 box, composition modes and a composition step), then run
-    the plain step, the closure with exact-force checks every 50 steps
-    (fallback above 1e-2 relative error), and the closure without fallback;
-    D_12 from the mode decay of each, and the throughput of plain and
-    closure steps."""
+    (a 192x12x12 box, composition modes of the workload's wavelength), then
+    run the plain step, the closure with exact-force checks every 50 steps
+    (the exact force until the next check whenever a check's relative error
+    is above 1e-2), and the closure with every check passing; D_12 from the
+    mode decay of each, and the throughput of plain and closure steps."""
     import torch
 
     from paper_1105_3634_amd.closure_train import init_params, train_closure
@@ -163,14 +163,14 @@ def closure_leg(mlb, W, steps=5000, train_box=(192, 12, 12)):
             return m, n0, u0
         return make
 
-    def step_state():
-        m = W.Mixture(nx, ny, nz, sigma=(2.0, 3.0), tau=1.0, name="closure_train")
-        n0, u0 = W.step_state(m, n_tot)
-        return m, n0, u0
-
-    specs = [(0.05, 192, 0.0), (0.02, 96, 0.0), (0.1, 192, 0.0), (0.03, 64, 0.0), (0.07, 128, 0.0),
-             (0.04, 192, 0.0), (0.01, 192, 0.0), (0.05, 96, 0.005), (0.05, 192, 0.01)]
-    states = [state(a, wl, nz_, 300 + i) for i, (a, wl, nz_) in enumerate(specs)] + [step_state]
+    # composition modes at the workload's wavelength (the box length along
+    # x), amplitudes 0.01 .. 0.1.  A composition-step state in the pool
+    # would set the force scale f_ref two orders of magnitude above these
+    # modes' forces, which bfloat16 activations then do not resolve (first
+    # check error about 1 instead of 0.01 - 0.1).
+    specs = [(0.05, 192, 0.0), (0.1, 192, 0.0), (0.04, 192, 0.0), (0.01, 192, 0.0), (0.07, 192, 0.0),
+             (0.03, 192, 0.0), (0.06, 192, 0.0), (0.02, 192, 0.0), (0.08, 192, 0.0)]
+    states = [state(a, wl, nz_, 300 + i) for i, (a, wl, nz_) in enumerate(specs)]
     tnet = mlb.GpuNet((nz, ny, nx), training=True)
     tnet.set_params(init_params(0))
     rep = train_closure(tnet, states, per_state=200, sample_every=5, epochs=10, lr=2e-3)
@@ -197,8 +197,10 @@ def closure_leg(mlb, W, steps=5000, train_box=(192, 12, 12)):
         out = {"d12": D}
         if closure:
             st = g.closure_stats()
-            out.update({"checks": st["checks"], "fallback_step": st["fallback_step"], "active_at_end": st["active"],
-                        "first_check_err": errs[0] if errs else None, "last_check_err": st["last_err"]})
+            out.update({"checks": st["checks"], "failed_checks": st["failed_checks"],
+                        "network_steps": st["net_steps"], "first_fallback_step": st["fallback_step"],
+                        "active_at_end": st["active"], "first_check_err": errs[0] if errs else None,
+                        "last_check_err": st["last_err"]})
         return out
 
     def rate(closure, k=200):
@@ -229,6 +231,7 @@ def closure_leg(mlb, W, steps=5000, train_box=(192, 12, 12)):
         "train": {"box": list(train_box), "snapshots": rep.samples, "adam_steps": rep.steps,
                   "collect_s": rep.collect_seconds, "train_s": rep.train_seconds},
         "plain": plain, "closure_checked": checked, "closure_no_fallback": forced,
+        "d12_rel_diff_checked": checked["d12"] / plain["d12"] - 1.0,
         "d12_rel_diff_no_fallback": forced["d12"] / plain["d12"] - 1.0,
         "ssu_per_s": {"plain": r_plain, "closure": r_net, "speedup": r_net / r_plain},
         "passes_ms_per_step": {"plain": p_plain, "closure": p_net},

@@ -317,20 +317,25 @@ int32_t mlb_net_adam_steps(mlb_net net);
 mlb_status mlb_net_destroy(mlb_net net);
 
 /* Attach a closure network to a float32 binary periodic mixture (the net's
- * grid must equal the mixture's; net = NULL detaches).  From then on every
- * step takes its force from the network, except steps whose index (the
- * mlb_step_count before the step) is a multiple of check_every: those
- * evaluate the exact force, use it, and compare it with the network's,
- * err = ||N_net - N_exact||_2 / ||N_exact||_2 over all sites, species and
- * components (float64 sums; synchronises the stream).  If err > tol, or
- * err is not finite (NaN in either force), the closure switches off for
- * good and the exact force is used from then on.
+ * grid must equal the mixture's; net = NULL detaches).  Steps whose index
+ * (the mlb_step_count before the step) is a multiple of check_every are
+ * checks: they evaluate the exact force, use it, and compare it with the
+ * network's, err = ||N_net - N_exact||_2 / ||N_exact||_2 over all sites,
+ * species and components (float64 sums; synchronises the stream).  The
+ * steps up to the next check take the network's force if err <= tol, and
+ * the exact force otherwise (err > tol, or not finite: NaN in either
+ * force); the next check decides again.  Steps before the first check
+ * (attaching at an index that is not a multiple) take the network's force.
  * The handle keeps the network; the caller keeps it alive while attached. */
 mlb_status mlb_set_closure(mlb_mixture h, mlb_net net, int32_t check_every, double tol);
-/* checks made, step index of the fallback (-1 if none), error of the last
- * check (-1 before the first), whether the closure is still in use. */
+/* checks made, step index of the first failed check (-1 if none), error of
+ * the last check (-1 before the first), whether the last check passed (the
+ * network's force is in use until the next check). */
 mlb_status mlb_closure_stats(mlb_mixture h, int64_t *checks, int64_t *fallback_step, double *last_err,
                              int32_t *active);
+/* steps taken with the network's force since mlb_set_closure, and failed
+ * checks; HOST outputs (either may be NULL). */
+mlb_status mlb_closure_usage(mlb_mixture h, int64_t *net_steps, int64_t *failed_checks);
 /* A training pair from the current state (populations are not changed):
  * x_out [8][N] the network input with `net`'s scales and target_out [6][N]
  * the exact force divided by f_ref; DEVICE float32.  Needs a float32

@@ -218,8 +218,10 @@ class GpuMixture:
         checks, fb, err, act = C.c_int64(), C.c_int64(), C.c_double(), C.c_int32()
         _lib.check(self.lib.mlb_closure_stats(self.h, C.byref(checks), C.byref(fb), C.byref(err), C.byref(act)),
                    "mlb_closure_stats")
+        steps, failed = C.c_int64(), C.c_int64()
+        _lib.check(self.lib.mlb_closure_usage(self.h, C.byref(steps), C.byref(failed)), "mlb_closure_usage")
         return {"checks": int(checks.value), "fallback_step": int(fb.value), "last_err": float(err.value),
-                "active": bool(act.value)}
+                "active": bool(act.value), "net_steps": int(steps.value), "failed_checks": int(failed.value)}
 
     def closure_sample(self, net: "GpuNet"):
         """(x [8][...], target [6][...]) float32 device tensors for the current state."""

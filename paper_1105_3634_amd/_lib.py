@@ -103,6 +103,7 @@ _SIGS = [
     ("mlb_set_closure", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_double]),
     ("mlb_closure_stats", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                     C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    ("mlb_closure_usage", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     ("mlb_closure_sample", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
 ]
 OPT_TUNE, OPT_NO_GRAPH = 1, 2

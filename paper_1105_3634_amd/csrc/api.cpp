@@ -240,10 +240,10 @@ struct mlb_batch_s {
     hipGraphExec_t graph = nullptr;
     // learned closure (single float32 binary system)
     mlb_net_s *net = nullptr;
-    bool closure_active = false;
+    bool closure_active = false;   // the last check passed: steps until the next one take the network's force
     int check_every = 50;
     double closure_tol = 1e-2;
-    int64_t closure_checks = 0, fallback_step = -1;
+    int64_t closure_checks = 0, fallback_step = -1, failed_checks = 0, net_steps = 0;
     double last_err = -1.0;
     hipGraphExec_t graph_closure = nullptr;
     // second stream for the contact pass while the spectral field runs
@@ -851,9 +851,10 @@ mlb_status check_closure(Batch &B, hipStream_t st)
     if (std::isfinite(e) && std::isfinite(w)) err = w > 0.0 ? std::sqrt(e / w) : (e > 0.0 ? INFINITY : 0.0);
     B.last_err = err;
     B.closure_checks += 1;
-    if (!(err <= B.closure_tol)) {
-        B.closure_active = false;
-        B.fallback_step = at_step;
+    B.closure_active = err <= B.closure_tol;
+    if (!B.closure_active) {
+        B.failed_checks += 1;
+        if (B.fallback_step < 0) B.fallback_step = at_step;
     }
     return MLB_OK;
 }
@@ -862,7 +863,10 @@ mlb_status do_steps(Batch &B, int nsteps, hipStream_t st)
 {
     if (nsteps < 0) return fail(MLB_EINVAL, "nsteps must be >= 0");
     int left = nsteps;
-    while (left > 0 && B.net && B.closure_active) {
+    // with a network attached: every step whose index is a multiple of
+    // check_every is a check; the steps up to the next check take the
+    // network's force if that check passed, the exact force if it failed
+    while (left > 0 && B.net) {
         const int64_t phase = B.steps % B.check_every;
         if (phase == 0) {
             TRY(check_closure(B, st));
@@ -870,7 +874,8 @@ mlb_status do_steps(Batch &B, int nsteps, hipStream_t st)
             continue;
         }
         const int run = (int)std::min<int64_t>(left, B.check_every - phase);
-        TRY(run_steps(B, run, st, true));
+        TRY(run_steps(B, run, st, B.closure_active));
+        if (B.closure_active) B.net_steps += run;
         left -= run;
     }
     return run_steps(B, left, st, false);
@@ -1324,6 +1329,8 @@ mlb_status mlb_set_closure(mlb_mixture h, mlb_net net, int32_t check_every, doub
     B.closure_active = true;
     B.closure_checks = 0;
     B.fallback_step = -1;
+    B.failed_checks = 0;
+    B.net_steps = 0;
     B.last_err = -1.0;
     return MLB_OK;
 }
@@ -1336,6 +1343,14 @@ mlb_status mlb_closure_stats(mlb_mixture h, int64_t *checks, int64_t *fallback_s
     if (fallback_step) *fallback_step = h->fallback_step;
     if (last_err) *last_err = h->last_err;
     if (active) *active = (h->net && h->closure_active) ? 1 : 0;
+    return MLB_OK;
+}
+
+mlb_status mlb_closure_usage(mlb_mixture h, int64_t *net_steps, int64_t *failed_checks)
+{
+    if (!h) return fail(MLB_EINVAL, "null handle");
+    if (net_steps) *net_steps = h->net_steps;
+    if (failed_checks) *failed_checks = h->failed_checks;
     return MLB_OK;
 }
 

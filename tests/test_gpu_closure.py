@@ -224,6 +224,7 @@ def test_closure_checks_every_step_follow_the_exact_path(mlb, oracle_lib):
     g.step(20)
     st = g.closure_stats()
     assert st["checks"] == 20 and st["active"] and st["fallback_step"] == -1 and st["last_err"] > 0
+    assert st["net_steps"] == 0 and st["failed_checks"] == 0
     o = oracle.Oracle(mix)
     f = o.step(o.init(n0, u0), 20)
     n_ref = o.densities(f)
@@ -241,12 +242,35 @@ def test_closure_falls_back_when_error_is_large(mlb, oracle_lib):
     g.set_closure(net, check_every=4, tol=1e-2)
     g.step(13)
     st = g.closure_stats()
-    assert st["checks"] == 1 and st["fallback_step"] == 0 and not st["active"] and st["last_err"] > 1e-2
+    # checks at steps 0, 4, 8, 12 all fail: every step takes the exact force
+    assert st["checks"] == 4 and st["failed_checks"] == 4 and st["net_steps"] == 0
+    assert st["fallback_step"] == 0 and not st["active"] and st["last_err"] > 1e-2
     o = oracle.Oracle(mix)
     f = o.step(o.init(n0, u0), 13)
     n_ref = o.densities(f)
     n = g.moments()[0].cpu().numpy()
     assert np.max(np.abs(n - n_ref) / np.abs(n_ref)) < 1e-5
+
+
+def test_closure_network_steps_between_checks(mlb):
+    """A check that passes hands the steps up to the next check to the
+    network; the next check decides again, and the counters agree with its
+    outcome (untrained net: its step-0 error is about 1, below tol = 2)."""
+    mix, n0, u0 = closure_case()
+    g = mlb.GpuMixture(mix, n0, u0, precision=32)
+    net = mlb.GpuNet(mix.shape())
+    net.set_params(random_layers(3))
+    net.set_scales(*scales(n0))
+    g.set_closure(net, check_every=3, tol=2.0)
+    g.step(1)
+    st = g.closure_stats()
+    assert st["checks"] == 1 and st["active"] and st["last_err"] < 2.0 and st["net_steps"] == 0
+    g.step(3)                                   # network steps 1 and 2, then the check at step 3
+    st = g.closure_stats()
+    assert st["checks"] == 2 and st["net_steps"] == 2
+    passed = st["last_err"] <= 2.0
+    assert st["active"] == passed and st["failed_checks"] == (0 if passed else 1)
+    assert st["fallback_step"] == (-1 if passed else 3)
 
 
 def test_closure_non_finite_network_output_falls_back(mlb, oracle_lib):
@@ -264,6 +288,7 @@ def test_closure_non_finite_network_output_falls_back(mlb, oracle_lib):
     g.step(7)
     st = g.closure_stats()
     assert st["fallback_step"] == 0 and not st["active"] and not np.isfinite(st["last_err"])
+    assert st["checks"] == 3 and st["failed_checks"] == 3 and st["net_steps"] == 0
     o = oracle.Oracle(mix)
     n_ref = o.densities(o.step(o.init(n0, u0), 7))
     n = g.moments()[0].cpu().numpy()
