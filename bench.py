@@ -173,7 +173,8 @@ def closure_leg(mlb, W, steps=5000, train_box=(192, 12, 12)):
     states = [state(a, wl, nz_, 300 + i) for i, (a, wl, nz_) in enumerate(specs)]
     tnet = mlb.GpuNet((nz, ny, nx), training=True)
     tnet.set_params(init_params(0))
-    rep = train_closure(tnet, states, per_state=200, sample_every=5, epochs=10, lr=2e-3)
+    # snapshots every 25 steps span the 5000-step run; 20 epochs at lr 1e-3
+    rep = train_closure(tnet, states, per_state=200, sample_every=25, epochs=20, lr=1e-3)
     params = tnet.get_params(flat=True)
     del tnet
 
