@@ -264,6 +264,26 @@ def ensemble_leg(mlb, W, steps=1000, timed=200):
     torch.cuda.synchronize()
     run_s = time.perf_counter() - t0
     D = b.fit(t_min=200)
+    # a fit is well conditioned when, over the fit's window (the library's
+    # rule), ln A is a straight line (R^2 >= 0.98) through at least five
+    # samples that stay above 1e-4 of the first amplitude (clear of the
+    # rounding floor; oscillating decay fails the R^2 test)
+    good = []
+    for k in range(len(mixes)):
+        t, a = b.series(k)
+        if len(a) == 0 or not a[0] > 0:
+            continue
+        low = np.flatnonzero(a <= 0.1 * a[0])
+        t_lo = min(200.0, t[low[0]]) if low.size else 200.0
+        sel = (t >= t_lo) & (a >= 1e-6 * a[0])
+        tw, lw = t[sel], np.log(a[sel])
+        if len(tw) < 5 or np.exp(lw.min()) < 1e-4 * a[0]:
+            continue
+        fit = np.polyval(np.polyfit(tw, lw, 1), tw)
+        ss = np.sum((lw - lw.mean()) ** 2)
+        if ss > 0 and 1.0 - np.sum((lw - fit) ** 2) / ss >= 0.98:
+            good.append(k)
+    Dg = D[good] if good else np.array([np.nan])
     b.step(4)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -280,7 +300,9 @@ def ensemble_leg(mlb, W, steps=1000, timed=200):
         "ssu_per_s": ssu_step * timed / dt, "ms_per_step": dt * 1e3 / timed,
         "run_with_mode_records": {"steps": steps, "seconds": run_s},
         "d12": {"min": float(np.min(D)), "median": float(np.median(D)), "max": float(np.max(D)),
-                "finite": bool(np.all(np.isfinite(D)))},
+                "finite": bool(np.all(np.isfinite(D))), "well_conditioned": len(good),
+                "well_conditioned_min": float(np.min(Dg)), "well_conditioned_median": float(np.median(Dg)),
+                "well_conditioned_max": float(np.max(Dg))},
         "tuning": {"shape": mlb.GpuBatch.SHAPES[tune["shape"]], "order": ["linear", "xcd-chunked"][tune["order"]],
                    "trial_ms": tune["trial_ms"]},
         "passes_ms_per_step": {k: v[0] / 10 for k, v in passes.items() if v[1]},

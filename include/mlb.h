@@ -246,6 +246,10 @@ mlb_status mlb_batch_record_modes(mlb_batch h, void *stream);
 /* Mode-decay fit of every system (kind 0 of mlb_fit_series): D_out is a
  * HOST array of `count` values.  Synchronises. */
 mlb_status mlb_batch_fit(mlb_batch h, double t_min, double *D_out, void *stream);
+/* Recorded series of one system, as mlb_get_series (HOST outputs;
+ * synchronises; an out-of-range system is MLB_EINVAL). */
+mlb_status mlb_batch_get_series(mlb_batch h, int32_t system, double *t, double *v, int32_t capacity,
+                                int32_t *count, void *stream);
 /* The tile shape (0: 16x4x4, 1: 8x8x4, 2: 32x4x2) and block order (0:
  * linear, 1: XCD-chunked) in use; trial_ms (HOST, 6 values, may be NULL)
  * receives the measured milliseconds per step of each candidate

@@ -312,6 +312,17 @@ class GpuBatch:
         _lib.check(self.lib.mlb_batch_fit(self.h, float(t_min), out, _stream_handle(self.stream)), "mlb_batch_fit")
         return np.array(out[:])
 
+    def series(self, system: int):
+        """(t, amplitude) of one system's recorded mode series (host arrays)."""
+        cap = int(self.lib.mlb_series_capacity())
+        t = (C.c_double * cap)()
+        v = (C.c_double * cap)()
+        cnt = C.c_int32()
+        _lib.check(self.lib.mlb_batch_get_series(self.h, int(system), t, v, cap, C.byref(cnt),
+                                                 _stream_handle(self.stream)), "mlb_batch_get_series")
+        n = cnt.value
+        return np.array(t[:n]), np.array(v[:n])
+
     def tuning(self):
         shape, order = C.c_int32(), C.c_int32()
         ms = (C.c_double * 6)()

@@ -83,6 +83,8 @@ _SIGS = [
     ("mlb_batch_get_populations", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     ("mlb_batch_record_modes", C.c_int, [C.c_void_p, C.c_void_p]),
     ("mlb_batch_fit", C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_double), C.c_void_p]),
+    ("mlb_batch_get_series", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       C.c_int32, C.POINTER(C.c_int32), C.c_void_p]),
     ("mlb_batch_tuning", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     ("mlb_batch_profile_begin", C.c_int, [C.c_void_p]),
     ("mlb_batch_profile_end", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_void_p]),

@@ -1252,11 +1252,12 @@ mlb_status mlb_fit_series(mlb_mixture h, int32_t kind, double t_min, double *D_o
     return MLB_OK;
 }
 
-mlb_status mlb_get_series(mlb_mixture h, double *t, double *v, int32_t capacity, int32_t *count, void *stream)
+namespace {
+mlb_status copy_series(Batch &B, int k, double *t, double *v, int32_t capacity, int32_t *count, void *stream)
 {
-    if (!h || !count) return fail(MLB_EINVAL, "handle and count are required");
+    Batch *h = &B;
     hipStream_t st = S_(stream);
-    const SysHost &S = h->sys[0];
+    const SysHost &S = h->sys[(size_t)k];
     int c = 0;
     HIP_TRY(hipMemcpyAsync(&c, h->ws + S.series_cnt, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1273,6 +1274,21 @@ mlb_status mlb_get_series(mlb_mixture h, double *t, double *v, int32_t capacity,
         }
     }
     return MLB_OK;
+}
+}  // namespace
+
+mlb_status mlb_get_series(mlb_mixture h, double *t, double *v, int32_t capacity, int32_t *count, void *stream)
+{
+    if (!h || !count) return fail(MLB_EINVAL, "handle and count are required");
+    return copy_series(*h, 0, t, v, capacity, count, stream);
+}
+
+mlb_status mlb_batch_get_series(mlb_batch h, int32_t system, double *t, double *v, int32_t capacity,
+                                int32_t *count, void *stream)
+{
+    if (!h || !count) return fail(MLB_EINVAL, "handle and count are required");
+    if (system < 0 || system >= h->count) return fail(MLB_EINVAL, "system index out of range");
+    return copy_series(*h, system, t, v, capacity, count, stream);
 }
 
 int64_t mlb_step_count(mlb_mixture h) { return h ? h->steps : -1; }
