@@ -116,9 +116,13 @@ def test_batch_mode_fit_matches_single_system_fit():
         Ds = g.fit(0, t_min=20)
         assert Db[k] == Ds, (k, Db[k], Ds)
         t, v = g.series()
+        tb, vb = b.series(k)
+        assert np.array_equal(tb, t) and np.array_equal(vb, v)
         low = np.flatnonzero(v <= 0.1 * v[0])
         t_lo = min(20.0, t[low[0]]) if low.size else 20.0
         sel = (t >= t_lo) & (v >= 1e-6 * v[0])
         slope = np.polyfit(t[sel], np.log(v[sel]), 1)[0]
         kk = 2 * np.pi / sy[k][0].nx
         np.testing.assert_allclose(Ds, -slope / kk ** 2, rtol=1e-9)
+    with pytest.raises(mlb.MlbError):
+        b.series(len(sy))
