@@ -373,7 +373,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=200, help="untimed steps before the timed region (the GPU reaches its steady clocks)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tail", choices=["auto", "direct", "spectral"], default="auto")
     ap.add_argument("--tiling", default=None, metavar="SHAPE,ORDER",
