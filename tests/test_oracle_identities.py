@@ -11,6 +11,11 @@
   friction coefficient gamma_ab = (8/3) sqrt(2 pi mu kT) g n_b sigma^2 of
   Sec. 3 (end of the linear estimates) and eq. (gammasymmetrized1).
 - Plane Couette flow between moving walls in the dilute limit.
+- A species with no particles anywhere drops out: every sum over partner
+  species (the BMCSL contact values through the packing fractions, the
+  shell integrals of eqs. (potmeanforce) and (viscousforce), the attractive
+  field below eq. (potmeanforce)) gets exact zeros from it, so the other
+  species evolve as the mixture without it, bit for bit.
 """
 import math
 
@@ -164,3 +169,29 @@ def test_dilute_couette_profile(oracle_lib):
     y = np.arange(1, 9)
     expect = -U + 2 * U * (y - 0.5) / 8.0
     np.testing.assert_allclose(ux, expect, atol=2e-6)
+
+
+@pytest.mark.parametrize("scheme", [W.SCHEME_CN_J1, W.SCHEME_FE])
+def test_absent_species_drops_out(oracle_lib, scheme):
+    """A binary whose second species is empty everywhere against the one-species
+    system of the first: populations and every field of species 0 agree bit for
+    bit after 5 steps (a wrong pair or diameter index in a cross-species term
+    would make them differ, since sigma_11 and eps_01 differ from sigma_00 and
+    eps_00)."""
+    eps2 = np.array([[0.1, 0.07], [0.07, 0.05]])
+    m2 = W.Mixture(10, 11, 9, sigma=(2.5, 3.5), eps=eps2, rc_factor=2.0, scheme=scheme)
+    m1 = W.Mixture(10, 11, 9, sigma=(2.5,), eps=np.array([[0.1]]), rc_factor=2.0, scheme=scheme)
+    n0, u0 = W.random_state(m2, [0.02, 0.01], rel=0.4, u_amp=0.03, seed=33)
+    n0[1] = 0.0
+    u0[1] = 0.0
+    o2, o1 = oracle_lib.Oracle(m2), oracle_lib.Oracle(m1)
+    f2 = o2.step(o2.init(n0, u0), 5)
+    f1 = o1.step(o1.init(n0[:1], u0[:1]), 5)
+    assert np.array_equal(np.asarray(f2)[:1], np.asarray(f1))
+    assert not np.asarray(f2)[1].any()
+    d2, d1 = o2.fields(f2), o1.fields(f1)
+    assert np.array_equal(d2["u"], d1["u"])
+    assert np.array_equal(d2["g"][:1], d1["g"])          # pair (0, 0) comes first
+    for k in ("n", "j", "vhat", "H", "N", "gam", "Nmf", "Ntail", "Dold", "Dnew"):
+        assert np.array_equal(d2[k][:1], d1[k]), k
+    assert np.abs(d1["Ntail"]).max() > 0 and np.abs(d1["H"]).max() > 0
