@@ -74,3 +74,85 @@ def test_params_layout_matches_header():
             names.append(nm[0][0])
     assert names == [f[0] for f in _lib.Params._fields_]
     assert ctypes.sizeof(_lib.Params) == 4 * 8 + 8 * (2 + 4 + 4 + 16 + 1 + 12 + 2)
+
+
+def _bad_params(edit):
+    import paper_1105_3634_amd as mlb
+    p = mlb.make_params(W.Mixture(8, 8, 8, sigma=(2.0, 3.0), eps=np.array([[0.1, 0.05], [0.05, 0.1]])))
+    edit(p)
+    return p
+
+
+@pytest.mark.parametrize("edit,why", [
+    (lambda p: setattr(p, "nspecies", 0), "nspecies"),
+    (lambda p: setattr(p, "nspecies", 5), "nspecies"),
+    (lambda p: setattr(p, "nx", 0), "lattice sizes"),
+    (lambda p: (setattr(p, "nx", 1024), setattr(p, "ny", 1024), setattr(p, "nz", 1024)), "too large"),
+    (lambda p: setattr(p, "precision", 16), "precision"),
+    (lambda p: setattr(p, "scheme", 7), "scheme"),
+    (lambda p: setattr(p, "tail_mode", 9), "tail mode"),
+    (lambda p: (setattr(p, "walls_y", 1), setattr(p, "ny", 2)), "ny >= 3"),
+    (lambda p: p.mass.__setitem__(1, 2.0), "unit masses"),
+    (lambda p: p.sigma.__setitem__(0, 41.0), "sigma"),
+    (lambda p: p.sigma.__setitem__(0, float("nan")), "sigma"),
+    (lambda p: setattr(p, "rc_factor", 1.0), "rc_factor"),
+    (lambda p: p.eps.__setitem__(1, -0.1), "eps"),
+])
+def test_invalid_parameters_are_rejected_on_the_host(edit, why):
+    """Every rejection of the parameter check comes back as MLB_EINVAL with a
+    message naming the offending field, before any device work."""
+    import paper_1105_3634_amd as mlb
+    with pytest.raises(mlb.MlbError) as e:
+        mlb.workspace_bytes(_bad_params(edit))
+    assert e.value.status == -1
+    assert why in str(e.value), str(e.value)
+
+
+def test_null_arguments_are_rejected_without_device_work():
+    """Calls on a NULL handle, or without their required outputs, return
+    MLB_EINVAL (-1) and set the last-error message; destroying NULL is a
+    no-op.  None of these paths reaches the GPU."""
+    import paper_1105_3634_amd as mlb
+    lib = mlb._lib.load()
+    calls = [
+        lambda: lib.mlb_step(None, 1, None),
+        lambda: lib.mlb_batch_step(None, 1, None),
+        lambda: lib.mlb_fields(None, *([None] * 7), None),
+        lambda: lib.mlb_get_populations(None, None, None),
+        lambda: lib.mlb_conserved(None, None, None, None),
+        lambda: lib.mlb_set_closure(None, None, 50, 1e-2),
+        lambda: lib.mlb_init_mixture_ex(None, None, 0, None, None, 0, None, None),
+    ]
+    for call in calls:
+        lib.mlb_last_error()
+        assert call() == -1
+        assert lib.mlb_last_error().decode()
+    out = ctypes.c_void_p(1)
+    assert lib.mlb_init_mixture_ex(None, None, 0, None, None, 0, None, ctypes.byref(out)) == -1
+    assert out.value is None and "params" in lib.mlb_last_error().decode()
+    assert lib.mlb_destroy(None) == 0 and lib.mlb_batch_destroy(None) == 0
+    assert lib.mlb_batch_workspace_bytes(None, 0) == 0
+    assert lib.mlb_pass_name(-1) == b"" and lib.mlb_pass_name(10 ** 6) == b""
+
+
+def test_batch_sizing_names_the_bad_system():
+    import paper_1105_3634_amd as mlb
+    lib = mlb._lib.load()
+    good = mlb.make_params(W.Mixture(8, 8, 8, sigma=(2.0, 3.0)))
+    bad = _bad_params(lambda p: setattr(p, "tau", 0.5))
+    arr = (mlb._lib.Params * 3)(good, good, bad)
+    assert lib.mlb_batch_workspace_bytes(arr, 2) > 0
+    assert lib.mlb_batch_workspace_bytes(arr, 3) == 0
+    msg = lib.mlb_last_error().decode()
+    assert "system 2" in msg and "tau" in msg, msg
+
+
+def test_network_sizes():
+    """The closure network (8 -> 32 -> 32 -> 32 -> 6 channels, 3x3x3 kernels):
+    27 * (8*32 + 32*32 + 32*32 + 32*6) = 67 392 weights, one per MAC at a site,
+    plus 102 biases; an empty box has no workspace."""
+    import paper_1105_3634_amd as mlb
+    lib = mlb._lib.load()
+    assert lib.mlb_net_param_count() == 67392 + 102
+    assert lib.mlb_net_workspace_bytes(0, 8, 8, 0) == 0
+    assert lib.mlb_net_workspace_bytes(8, 8, 8, 1) > lib.mlb_net_workspace_bytes(8, 8, 8, 0) > 0
