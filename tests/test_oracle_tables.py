@@ -34,7 +34,7 @@ def test_shell_counts_match_sums_of_three_squares(oracle_lib, sab):
     assert np.all((r2 >= lo) & (r2 < hi))
 
 
-def test_survey_shell_sizes(oracle_lib):
+def test_shell_sizes_at_the_workload_diameters(oracle_lib):
     # shells at sigma_ab of the workloads: 62, 98, 194, 234 points
     for s, n in [(2.0, 62), (3.0, 98), (3.75, 194), (4.5, 234), (2.5, 66), (4.0, 210)]:
         o = oracle_lib.Oracle(_mix([s]))
