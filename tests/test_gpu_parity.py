@@ -194,6 +194,54 @@ def test_absent_species_reduces_to_single_species():
             assert err < 1e-6
 
 
+def _spread(n_tracer, nx):
+    """Second moment along x, about the box centre, of the y,z-summed density."""
+    prof = n_tracer.sum(axis=(0, 1))
+    x = np.arange(nx) - 0.5 * nx
+    mass = prof.sum()
+    mean = (prof * x).sum() / mass
+    return (prof * x * x).sum() / mass - mean * mean
+
+
+def test_spread_record_and_fit_against_oracle(oracle_lib):
+    """The tracer-band second moment of Sec. 5.2, recorded on the GPU in float64
+    every 10 steps of the walled ternary (moving walls, tail), against the same
+    moment of the oracle's densities computed here with numpy; the spread fit
+    D = slope(Var, t) / 2 against numpy's least-squares line over the same
+    samples (all, then t >= 30)."""
+    m, n0, u0 = _case("couette_small")
+    tracer, every, samples = m.M - 1, 10, 7
+    o = oracle_lib.Oracle(m)
+    f = o.init(n0, u0)
+    ref = []
+    for k in range(samples):
+        ref.append(_spread(o.fields(f)["n"][tracer], m.nx))
+        if k + 1 < samples:
+            f = o.step(f, every)
+    ref = np.array(ref)
+    t_ref = every * np.arange(samples, dtype=np.float64)
+    assert np.ptp(ref) > 1e-3 * ref[0]          # the band does spread
+    for prec, tol in ((64, 1e-12), (32, 1e-5)):
+        print(f"[spread] case=couette_small precision={prec}", flush=True)
+        g = _gpu(m, n0, u0, prec)
+        g.reset_series()
+        for k in range(samples):
+            g.record_spread(tracer)
+            if k + 1 < samples:
+                g.step(every)
+        t, v = g.series()
+        assert np.array_equal(t, t_ref)
+        err = np.abs(v - ref).max() / np.abs(ref).max()
+        print(f"  variance rel err {err:.2e}", flush=True)
+        assert err < tol
+        for t_min in (0.0, 30.0):
+            sel = t >= t_min
+            want = 0.5 * np.polyfit(t[sel], (ref if prec == 64 else v)[sel], 1)[0]
+            got = g.fit(1, t_min)
+            print(f"  t_min={t_min}: D {got:.10f} numpy {want:.10f}", flush=True)
+            assert abs(got - want) <= 1e-9 * abs(want)
+
+
 def test_fp32_forces_parts(oracle_lib):
     import paper_1105_3634_amd as mlb
     m, n0, u0 = _case("ternary_tail_ext")
