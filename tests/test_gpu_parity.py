@@ -242,6 +242,51 @@ def test_spread_record_and_fit_against_oracle(oracle_lib):
             assert abs(got - want) <= 1e-9 * abs(want)
 
 
+def test_mode_record_against_oracle(oracle_lib):
+    """The composition-mode amplitude of Sec. 5.1, |sum_r (n_0 - n_1)
+    exp(-i 2 pi x / nx)|, recorded on the GPU every 10 steps of the bulk
+    binary, against numpy's projection of the oracle's densities; the mode
+    fit D = -slope(ln A, t) / k^2 against numpy's line over the same
+    amplitude window (t from the first sample at or below 0.1 A_first, or
+    t_min if earlier, and A >= 1e-6 A_first)."""
+    m, n0, u0 = _case("bulk_small")
+    every, samples = 10, 7
+    k = 2 * np.pi / m.nx
+    x = np.arange(m.nx)
+    o = oracle_lib.Oracle(m)
+    f = o.init(n0, u0)
+    ref = []
+    for j in range(samples):
+        n = o.fields(f)["n"]
+        dn = (n[0] - n[1]).sum(axis=(0, 1))
+        ref.append(np.hypot((dn * np.cos(k * x)).sum(), (dn * np.sin(k * x)).sum()))
+        if j + 1 < samples:
+            f = o.step(f, every)
+    ref = np.array(ref)
+    assert ref[-1] < 0.9 * ref[0]               # the mode decays
+    for prec, tol in ((64, 1e-12), (32, 1e-5)):
+        print(f"[mode] case=bulk_small precision={prec}", flush=True)
+        g = _gpu(m, n0, u0, prec)
+        g.reset_series()
+        for j in range(samples):
+            g.record_mode(0, 1)
+            if j + 1 < samples:
+                g.step(every)
+        t, v = g.series()
+        assert np.array_equal(t, every * np.arange(samples, dtype=np.float64))
+        err = np.abs(v - ref).max() / ref[0]
+        print(f"  amplitude rel err {err:.2e}", flush=True)
+        assert err < tol
+        for t_min in (0.0, 30.0):
+            low = np.flatnonzero(v <= 0.1 * v[0])
+            t_lo = min(t_min, t[low[0]]) if low.size else t_min
+            sel = (t >= t_lo) & (v >= 1e-6 * v[0])
+            want = -np.polyfit(t[sel], np.log((ref if prec == 64 else v)[sel]), 1)[0] / k ** 2
+            got = g.fit(0, t_min)
+            print(f"  t_min={t_min}: D {got:.10f} numpy {want:.10f}", flush=True)
+            assert abs(got - want) <= 1e-9 * abs(want)
+
+
 def test_fp32_forces_parts(oracle_lib):
     import paper_1105_3634_amd as mlb
     m, n0, u0 = _case("ternary_tail_ext")
