@@ -126,6 +126,12 @@ def load() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "(or python paper_1105_3634_amd/build.py); there is no fallback path")
+    # torch first: its HIP runtime owns the device memory and streams handed to
+    # the library, and the library must bind to that same runtime (same
+    # soname).  Loaded the other way round, the system runtime comes first
+    # and library calls on torch's allocations have failed with "no
+    # ROCm-capable device".
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     for name, res, args in _SIGS:
         fn = getattr(lib, name)
