@@ -124,6 +124,29 @@ mlb_status mlb_init_mixture_ex(const mlb_params *p, void *workspace, size_t work
                                const double *n0, const double *u0, uint32_t options, void *stream,
                                mlb_mixture *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * mlb_init_mixture, but the workspace is a static device array of the
+ * library, MLB_STATIC_WORKSPACE_BYTES bytes per GPU, held by every GPU the
+ * library runs on until the process ends.  The caller still owns n0 and u0
+ * (DEVICE float64, as mlb_init_mixture) and every output buffer of later
+ * calls.  The array of the calling thread's current device is used.
+ *   - MLB_ENOMEM if mlb_workspace_bytes(p) exceeds the maximum (no device
+ *     work is done then); MLB_EINVAL for invalid parameters.
+ *   - One such mixture per GPU at a time: while one is alive (until its
+ *     mlb_destroy) a second call on the same GPU returns MLB_ESTATE.  The
+ *     array keeps the contents of the last mixture that used it; the
+ *     library initialises everything a mixture reads before reading it.
+ *     Calls on one GPU that overlap (e.g. from two threads) race.
+ *   - Neither this call nor mlb_step on the handle allocates device memory:
+ *     the handle replays no graph (graph capture and instantiation
+ *     allocate; mlb_set_graph(h, 1) turns them back on) and runs every pass
+ *     on the caller's stream (no second stream).  Options of
+ *     mlb_init_mixture_ex are not available (no autotuning). */
+#define MLB_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+mlb_status mlb_init_mixture_static(const mlb_params *p, const double *n0, const double *u0, void *stream,
+                                   mlb_mixture *out);
+
 /* Tile shape and block order in use (see mlb_batch_tuning). */
 mlb_status mlb_tuning(mlb_mixture h, int32_t *shape, int32_t *order, double *trial_ms);
 

@@ -72,7 +72,10 @@ class GpuMixture:
     """One mixture on the GPU.  Fields come back as torch tensors on the device."""
 
     def __init__(self, mix, n0: np.ndarray, u0: np.ndarray, precision: int = 32, tail_mode: int = TAIL_AUTO,
-                 device: str = "cuda:0", stream=None, options: int = 0):
+                 device: str = "cuda:0", stream=None, options: int = 0, static_workspace: bool = False):
+        """static_workspace: use the library's static device workspace
+        (mlb_init_mixture_static) instead of a torch-allocated one; `options`
+        must then be 0."""
         torch = _torch()
         self.lib = _lib.load()
         self.mix = mix
@@ -84,15 +87,24 @@ class GpuMixture:
         self.device = torch.device(device)
         self.dtype = torch.float64 if precision == 64 else torch.float32
         self.stream = stream
+        n0_d = torch.as_tensor(np.ascontiguousarray(n0, dtype=np.float64)).to(self.device)
+        u0_d = torch.as_tensor(np.ascontiguousarray(u0, dtype=np.float64)).to(self.device)
+        assert n0_d.numel() == self.M * self.N and u0_d.numel() == 3 * self.M * self.N
+        h = C.c_void_p()
+        if static_workspace:
+            assert options == 0, "options are not available with the static workspace"
+            with torch.cuda.device(self.device):
+                st = self.lib.mlb_init_mixture_static(C.byref(self.params), C.c_void_p(n0_d.data_ptr()),
+                                                      C.c_void_p(u0_d.data_ptr()), _stream_handle(stream),
+                                                      C.byref(h))
+            _lib.check(st, "mlb_init_mixture_static")
+            self.h = h
+            return
         nbytes = workspace_bytes(self.params)
         raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         off = (-raw.data_ptr()) % 256
         self._ws_raw = raw
         self.ws = raw[off:off + nbytes]
-        n0_d = torch.as_tensor(np.ascontiguousarray(n0, dtype=np.float64)).to(self.device)
-        u0_d = torch.as_tensor(np.ascontiguousarray(u0, dtype=np.float64)).to(self.device)
-        assert n0_d.numel() == self.M * self.N and u0_d.numel() == 3 * self.M * self.N
-        h = C.c_void_p()
         st = self.lib.mlb_init_mixture_ex(C.byref(self.params), C.c_void_p(self.ws.data_ptr()), nbytes,
                                           C.c_void_p(n0_d.data_ptr()), C.c_void_p(u0_d.data_ptr()), int(options),
                                           _stream_handle(stream), C.byref(h))

@@ -53,6 +53,8 @@ _SIGS = [
                                    C.c_void_p, C.POINTER(C.c_void_p)]),
     ("mlb_init_mixture_ex", C.c_int, [C.POINTER(Params), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
                                       C.c_uint32, C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("mlb_init_mixture_static", C.c_int, [C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.POINTER(C.c_void_p)]),
     ("mlb_tuning", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     ("mlb_step", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     ("mlb_moments", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -109,6 +111,7 @@ _SIGS = [
     ("mlb_closure_sample", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
 ]
 OPT_TUNE, OPT_NO_GRAPH = 1, 2
+STATIC_WORKSPACE_BYTES = 64 << 20   # MLB_STATIC_WORKSPACE_BYTES
 
 
 def opt_tiling(shape: int, order: int) -> int:

@@ -25,6 +25,9 @@
 #include "net_internal.h"
 #include "spectral.h"
 
+// Workspace of mlb_init_mixture_static (one copy per GPU).
+static __device__ __align__(256) char scratch[MLB_STATIC_WORKSPACE_BYTES];
+
 namespace {
 
 thread_local std::string g_err;
@@ -198,6 +201,22 @@ struct Tuning {
     double trial_ms[2 * mlb::kTileVariants] = {0, 0, 0, 0, 0, 0};
 };
 
+// Static device workspace of mlb_init_mixture_static.  In host code the
+// name stands for a host-side shadow, not a device address: the device
+// address comes from hipGetSymbolAddress, once per device (each GPU holds
+// its own copy), and is kept in g_static_ptr.  At most one live mixture per
+// device uses it.
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices] = {};
+bool g_static_busy[kMaxDevices] = {};
+
+void release_static(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (dev >= 0 && dev < kMaxDevices) g_static_busy[dev] = false;
+}
+
 // Autotuner results keyed by a signature of the batch (process-wide).
 std::mutex g_tune_mu;
 std::map<std::string, Tuning> g_tune_cache;
@@ -249,9 +268,12 @@ struct mlb_batch_s {
     // second stream for the contact pass while the spectral field runs
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // device whose static workspace this handle holds (-1: caller's workspace)
+    int static_dev = -1;
 
     virtual ~mlb_batch_s()
     {
+        if (static_dev >= 0) release_static(static_dev);
         if (graph) (void)hipGraphExecDestroy(graph);
         if (graph_closure) (void)hipGraphExecDestroy(graph_closure);
         if (ev_fork) (void)hipEventDestroy(ev_fork);
@@ -983,9 +1005,11 @@ mlb_status autotune(Batch &B, const double *const *n0, const double *const *u0, 
     return init_populations<T>(B, n0, u0, st);   // the trial steps changed the state
 }
 
+// no_alloc: no graph replay and no second stream (both allocate), no autotuning.
 template <typename T>
 mlb_status create(Batch &B, const mlb_params *params, int count, void *workspace, size_t bytes,
-                  const double *const *n0, const double *const *u0, uint32_t options, hipStream_t st)
+                  const double *const *n0, const double *const *u0, uint32_t options, hipStream_t st,
+                  bool no_alloc = false)
 {
     std::string why;
     if (!plan_batch(B, params, count, why)) return fail(MLB_EINVAL, why);
@@ -996,7 +1020,7 @@ mlb_status create(Batch &B, const mlb_params *params, int count, void *workspace
     for (int k = 0; k < count; ++k)
         if (!n0[k] || !u0[k]) return fail(MLB_EINVAL, "n0 and u0 are required for every system");
     B.ws = static_cast<char *>(workspace);
-    B.use_graph = (options & MLB_OPT_NO_GRAPH) == 0;
+    B.use_graph = !no_alloc && (options & MLB_OPT_NO_GRAPH) == 0;
     if (B.tiled && !mlb::tile_prepare(B.reach_max, B.ball_reach_max, B.ball_total_max, B.maxM))
         B.tiled = false;
     TRY(upload_static<T>(B, st));
@@ -1005,7 +1029,7 @@ mlb_status create(Batch &B, const mlb_params *params, int count, void *workspace
         if (S.spectral) TRY(setup_spectral(B, S, st));
     bool any_spectral = false;
     for (auto &S : B.sys) any_spectral = any_spectral || S.spectral;
-    if (any_spectral) {
+    if (any_spectral && !no_alloc) {
         // default priority, like every stream of the library
         HIP_TRY(hipStreamCreateWithFlags(&B.side, hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&B.ev_fork, hipEventDisableTiming));
@@ -1123,6 +1147,45 @@ mlb_status mlb_init_mixture(const mlb_params *p, void *workspace, size_t workspa
                             const double *u0, void *stream, mlb_mixture *out)
 {
     return mlb_init_mixture_ex(p, workspace, workspace_bytes, n0, u0, 0, stream, out);
+}
+
+mlb_status mlb_init_mixture_static(const mlb_params *p, const double *n0, const double *u0, void *stream,
+                                   mlb_mixture *out)
+{
+    if (!out) return fail(MLB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!p) return fail(MLB_EINVAL, "params is NULL");
+    const size_t need = workspace_for(p, 1);
+    if (need == 0) return MLB_EINVAL;   // workspace_for left the reason
+    if (need > MLB_STATIC_WORKSPACE_BYTES)
+        return fail(MLB_ENOMEM, "the mixture needs " + std::to_string(need) + " bytes of workspace; the static " +
+                                    "workspace holds " + std::to_string((size_t)MLB_STATIC_WORKSPACE_BYTES));
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(MLB_EUNSUPPORTED, "device index beyond the static workspace table");
+    void *ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (g_static_busy[dev])
+            return fail(MLB_ESTATE, "the static workspace of this device is held by another mixture; destroy it first");
+        if (!g_static_ptr[dev]) {
+            void *ptr = nullptr;
+            HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+            if (!ptr) return fail(MLB_EHIP, "hipGetSymbolAddress returned no address for the static workspace");
+            g_static_ptr[dev] = ptr;
+        }
+        ws = g_static_ptr[dev];
+        g_static_busy[dev] = true;
+    }
+    std::unique_ptr<mlb_mixture_s> h(new mlb_mixture_s());
+    h->static_dev = dev;   // the destructor releases the array, also on failure below
+    const double *n0v[1] = {n0}, *u0v[1] = {u0};
+    mlb_status s = p->precision == 64
+                       ? create<double>(*h, p, 1, ws, MLB_STATIC_WORKSPACE_BYTES, n0v, u0v, 0, S_(stream), true)
+                       : create<float>(*h, p, 1, ws, MLB_STATIC_WORKSPACE_BYTES, n0v, u0v, 0, S_(stream), true);
+    if (s != MLB_OK) return s;
+    *out = h.release();
+    return MLB_OK;
 }
 
 mlb_status mlb_step(mlb_mixture h, int32_t nsteps, void *stream)
