@@ -62,6 +62,7 @@ def _load():
     lib.or_pair_constants.argtypes = [C.c_void_p, C.c_int, C.c_int, dp]
     lib.or_moments.argtypes = [C.c_void_p, dp, dp]
     lib.or_step_ext.argtypes = [C.c_void_p, dp, dp, dp]
+    lib.or_set_force_profile.argtypes = [C.c_void_p, dp]
     lib.or_threads.restype = C.c_int
     lib.or_set_threads.argtypes = [C.c_int]
     _lib = lib
@@ -117,6 +118,15 @@ class Oracle:
         if h and _lib is not None:
             _lib.or_destroy(h)
             self._h = None
+
+    def set_force_profile(self, profile: Optional[np.ndarray]) -> None:
+        """Body force per lattice row [M][3][ny] added to the uniform one (None removes it)."""
+        if profile is None:
+            _lib.or_set_force_profile(self._h, None)
+            return
+        prof = np.ascontiguousarray(profile, dtype=np.float64)
+        assert prof.shape == (self.M, 3, self.m.ny)
+        _lib.or_set_force_profile(self._h, _ptr(prof))
 
     # ---------------------------------------------------------------- state
     def init(self, n0: np.ndarray, u0: np.ndarray) -> np.ndarray:

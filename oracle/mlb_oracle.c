@@ -187,6 +187,9 @@ typedef struct {
     double *n, *j, *u, *g, *vh, *H, *N2, *Nmf, *Ntl, *Nex, *Dold, *Dnew, *Gam;
     /* optional externally supplied attractive field sum_b (K_ab * n_b) [M][3][N] */
     const double *tail_ext;
+    /* optional body force per lattice row, F^a(y) = fext[a] + profile[a][y],
+     * [M][3][ny] (NULL: the uniform fext) */
+    double *fy;
 } or_ctx;
 
 static int pair_index(int M, int a, int b)
@@ -275,7 +278,7 @@ void or_destroy(or_ctx *c)
     }
     free(c->n); free(c->j); free(c->u); free(c->g); free(c->vh); free(c->H);
     free(c->N2); free(c->Nmf); free(c->Ntl); free(c->Nex); free(c->Dold);
-    free(c->Dnew); free(c->Gam);
+    free(c->Dnew); free(c->Gam); free(c->fy);
     free(c);
 }
 
@@ -489,7 +492,8 @@ static void gather_one(or_ctx *c)
             for (int d = 0; d < 3; ++d) {
                 double Nmf = na * mf[d];
                 double Ntl = na * tl[d];
-                double Nex = na * c->p.fext[a * 3 + d];
+                double Fa = c->fy ? c->fy[((size_t)a * 3 + d) * ny + y] : c->p.fext[a * 3 + d];
+                double Nex = na * Fa;
                 double Nc = (Nmf + Ntl) + Nex;
                 double Dd = dv[d];
                 c->Nmf[o3 + d * N + s] = Nmf;
@@ -692,6 +696,24 @@ void or_step(or_ctx *c, const double *fin, double *fout, int nsteps)
     }
     if (nsteps <= 0) memcpy(fout, a, sizeof(double) * nf);
     free(a);
+}
+
+/* External force varying with the lattice row y (the F^a of eq. evolution
+ * as a function of y; Sec. 5.2 drives its modulated flow this way):
+ * profile [M][3][ny] is added to the uniform fext; NULL removes it. */
+void or_set_force_profile(or_ctx *c, const double *profile)
+{
+    const int M = c->M, ny = c->p.ny;
+    free(c->fy);
+    c->fy = NULL;
+    if (!profile) return;
+    c->fy = (double *)malloc(sizeof(double) * 3 * (size_t)M * (size_t)ny);
+    for (int a = 0; a < M; ++a)
+        for (int d = 0; d < 3; ++d)
+            for (int y = 0; y < ny; ++y) {
+                size_t i = ((size_t)a * 3 + d) * ny + y;
+                c->fy[i] = c->p.fext[a * 3 + d] + profile[i];
+            }
 }
 
 /* Species densities of f (S1 only), n [M][N]. */

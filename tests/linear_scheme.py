@@ -198,11 +198,12 @@ class LinearScheme:
                                  for b in range(self.M)) for a in range(self.M)])
 
     # ------------------------------------------------------------ one step
-    def _forces(self, k, dn, dj, comp):
+    def _forces(self, k, dn, dj, comp, fext=0.0):
         """Force density N_a (component comp) of the scheme for the moment
-        amplitudes dn, dj (complex, exp(i k x) convention)."""
+        amplitudes dn, dj (complex, exp(i k x) convention) and a body force
+        of amplitude fext per particle on every species."""
         M = self.M
-        Nc = np.zeros(M, complex)
+        Nc = self.n0 * fext + 0j
         if comp == 0:
             for a in range(M):
                 for p in range(M):
@@ -259,10 +260,131 @@ class LinearScheme:
             T[:, col] = 3 * B2 * P
         return T
 
+    def transverse_forced(self, k: float) -> np.ndarray:
+        """Steady transverse momentum amplitudes dj_a,y under a body force
+        cos(k x) e_y of unit amplitude per particle on every species (the
+        Kolmogorov flow that drives the modulated shear of Sec. 5.2): the
+        fixed point of j' = T j + f."""
+        M = self.M
+        ph = np.exp(-1j * k * CV[:, 0])
+        B2 = (WV * CV[:, 1] ** 2 * ph).sum()
+        zero = np.zeros(M, complex)
+        f = 3 * B2 * self._forces(k, zero, zero, 1, fext=1.0)
+        return np.linalg.solve(np.eye(M) - self.transverse(k), f).real
+
+    def shear_viscosity(self, L: int) -> float:
+        """Kinematic viscosity nu of the shear mode (the slowest transverse
+        eigenvalue, decay exp(-nu k^2 t) of eq. dd3) at k = 2 pi / L."""
+        k = 2 * math.pi / L
+        lam = np.linalg.eigvals(self.transverse(k))
+        return float(-math.log(np.abs(lam).max()) / k ** 2)
+
+    def paper_viscosity(self, tau: float = 1.0, lattice: bool = True) -> float:
+        """nu = (eta^K + eta^C) / rho (Sec. 4.1): eta^C = (4/15) sum_ab
+        sqrt(2 pi mu kT) s^4 g n_a n_b, the sphere's s^2 (4 pi / 15) replaced
+        by the lattice shell's fourth moment when `lattice`; eta^K / rho is
+        the lattice BGK value (tau - 1/2) kT (the paper's continuum kT tau
+        carries the -1/2 of the discrete streaming)."""
+        eta = 0.0
+        for a in range(self.M):
+            for b in range(self.M):
+                s = self.sab[a, b]
+                if lattice:
+                    e = self.shells[a][b]
+                    r2 = (e ** 2).sum(1)
+                    m4 = self.what[a, b] * (r2 * e[:, 0] ** 2 * e[:, 1] ** 2 / r2 ** 2).sum()
+                else:
+                    m4 = s * s * 4 * math.pi / 15
+                # (4/15) sqrt(2 pi mu kT) s^4 = 2 s^2 sqrt(2 mu kT / pi) (1/2) s^2 (4 pi / 15)
+                eta += 2 * s * s * math.sqrt(2 * MU * KT / math.pi) * 0.5 * m4 * self.g[a, b] * self.n0[a] * self.n0[b]
+        return (tau - 0.5) * KT + eta / self.n0.sum()
+
     # ------------------------------------------------------------- modes
+    def longitudinal_modes(self, L: int) -> np.ndarray:
+        """Eigenvalues of one longitudinal step at k = 2 pi / L."""
+        return np.linalg.eigvals(self.longitudinal(2 * math.pi / L))
+
     def diffusion(self, L: int) -> float:
         """D of the slowest real (non-oscillating) longitudinal mode at k = 2 pi / L."""
         k = 2 * math.pi / L
         lam = np.linalg.eigvals(self.longitudinal(k))
         real = lam[np.abs(lam.imag) < 1e-12].real
         return float(-math.log(real.max()) / k ** 2)
+
+
+def taylor_passive_scalar(D: float, U: float, Ly: float, Lx: float, nmodes: int = 64) -> float:
+    """Effective axial diffusion of a passive scalar mode exp(i q x), q = 2 pi /
+    Lx, in the flow u_x(y) = U cos(2 pi y / Ly) with molecular diffusion D:
+    -lambda / q^2 for the slowest eigenvalue lambda of the advection-diffusion
+    operator on the y Fourier modes exp(i m k y), k = 2 pi / Ly (the flow
+    couples m to m +- 1 with i q U / 2).  As q -> 0 it tends to Sec. 5.2,
+    eq. (taylordiff): D (1 + Pe^2 / (2 pi^2)), Pe = U Ly / (2 D)."""
+    q, k = 2 * math.pi / Lx, 2 * math.pi / Ly
+    m = np.arange(-nmodes, nmodes + 1)
+    A = np.diag(-D * (q * q + (m * k) ** 2)).astype(complex)
+    off = -0.5j * q * U
+    for i in range(len(m) - 1):
+        A[i, i + 1] = off
+        A[i + 1, i] = off
+    lam = np.linalg.eigvals(A)
+    return float(-lam.real.max() / (q * q))
+
+
+def hydrodynamics(lin: LinearScheme, tau: float = 1.0) -> dict:
+    """The hydrodynamic coefficients of Sec. 4.2 for a binary at rest, from
+    the long-wavelength forces of Sec. 3 (eq. diciotto with the lattice
+    shell's radius; the attractive part from the lattice moment of the
+    force kernel) and the viscosities of Sec. 4.1 (lattice fourth moments):
+
+      chemical potentials  d mu_a / d n_b = kT delta_ab / n_a + K_ab
+      pressure             d P / d n_b    = kT + sum_a n_a K_ab
+      sound speed          c_s^2 = (dP/drho)_c                        (eq. cc2)
+      friction             gamma = gamma^AB + gamma^BA (unit masses,
+                           eq. gammasymmetrized1)
+      diffusion            D_P = c (1 - c) [(dmu_D/dc)_rho - (dmu_D/drho)_c
+                           (dP/dc)_rho / (dP/drho)_c] / gamma, the diffusive
+                           root of the determinant of Sec. 4.2 to order q^2
+                           (D_0 of the paper when (dP/dc)_rho = 0)
+      sound damping        Gamma = [nu_l + c (1 - c) (dmu_D/drho)_c
+                           (dP/dc)_rho / (gamma (dP/drho)_c)] / 2, the acoustic
+                           root to order q^2 (eq. damping, with the factor
+                           c (1 - c) / gamma its dimensions require), nu_l =
+                           (4/3 eta + eta_b) / rho: kinetic part 2 (tau - 1/2) kT
+                           (lattice BGK: eta_b^K = 2/3 eta^K), collisional part
+                           from the parallel lattice moment (eta_b^C = 5/3 eta^C
+                           for the sphere)."""
+    assert lin.M == 2
+    n0 = lin.n0
+    K = lin.paper_mean_field_limit(lattice_radius=True)
+    for a in range(2):
+        for b in range(2):
+            e = lin.tails[a][b]
+            if e is None:
+                continue
+            r = np.sqrt((e ** 2).sum(1))
+            K[a, b] -= (6 * lin.eps[a, b] * lin.sab[a, b] ** 6 / r ** 6 * (e[:, 0] / r) ** 2).sum()
+    dmu = np.array([[KT * (a == b) / n0[a] + K[a, b] for b in range(2)] for a in range(2)])
+    dP = np.array([KT + sum(n0[a] * K[a, b] for a in range(2)) for b in range(2)])
+    rho = n0.sum()
+    c = n0[0] / rho
+
+    def d_rho(v):
+        return c * v[0] + (1 - c) * v[1]
+
+    def d_c(v):
+        return rho * (v[0] - v[1])
+
+    muD = dmu[0] - dmu[1]
+    gam = sum(8 / 3 * math.sqrt(2 * math.pi * MU * KT) * lin.g[0, 1] * lin.sab[0, 1] ** 2 * n0[b] for b in range(2))
+    coupling = d_rho(muD) * d_c(dP) / d_rho(dP)
+    nul_c = 0.0
+    for a in range(2):
+        for b in range(2):
+            e = lin.shells[a][b]
+            r2 = (e ** 2).sum(1)
+            m4 = lin.what[a, b] * (r2 * (e[:, 0] ** 2 / r2) ** 2).sum()
+            nul_c += n0[a] * 2 * lin.sab[a, b] ** 2 * math.sqrt(2 * MU * KT / math.pi) * lin.g[a, b] * n0[b] * 0.5 * m4
+    nul = 2 * (tau - 0.5) * KT + nul_c / rho
+    return {"cs": math.sqrt(d_rho(dP)), "gamma": gam, "D_P": c * (1 - c) * (d_c(muD) - coupling) / gam,
+            "D_0": c * (1 - c) * d_c(muD) / gam, "Gamma": 0.5 * (nul + c * (1 - c) * coupling / gam),
+            "nu": lin.paper_viscosity(tau), "Delta": c * (1 - c) * d_c(muD)}
