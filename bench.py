@@ -26,7 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "species-site updates/s: plain vs batched/CNN-closure at fixed D12 error; HBM GB/s"
-FP32_PEAK_TFLOPS = 157.3       # MI355X vector FP32 (256 CU x 128 lanes x 2 flop x 2.4 GHz)
+FP32_PEAK_TFLOPS = 157.3       # MI355X vector FP32, published (packed: 256 CU x 4 SIMD x 16 lanes x 2 x 2 flop x 2.4 GHz)
+FP32_NONPACKED_TFLOPS = 78.6   # the same without packed FP32, which this build disables
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0     # MI355X dense bf16 matrix
 
@@ -53,10 +54,13 @@ def ball_size(s):
 def algorithmic_work(mix, tail_direct: bool):
     """Flops (fma = 2) and HBM bytes per pass for one step, from the stencil sizes.
 
-    Per species-site:
-      gather1: 25 flop per shell point (pair form, mean field, friction),
-               3.5 flop per tail point when the tail is summed directly, + 40;
-      step2:   14.5 flop per shell point + 30 per velocity (collision, forcing);
+    Per species-site, counted as the method's work on a full shell point
+    (not the regrouped kernel's own operation count, which is lower):
+      gather1: 34 flop per shell point (pair value, mean field, dissipative
+               pair form at the old velocities, friction rate),
+               8 flop per tail point when the tail is summed directly, + 40;
+      step2:   18 flop per shell point (pair form at the predicted velocities)
+               + 30 per velocity (collision, forcing);
       contact: 1 per ball point per species + 12 per pair;
       moments: 19 + 3 x 18 per species + 10.
     Bytes: the minimal HBM traffic of each pass (fields read once, written once)."""
@@ -72,8 +76,8 @@ def algorithmic_work(mix, tail_direct: bool):
     flops = {
         "moments": N * M * (19 + 54 + 10),
         "contact": N * (sum(ball_size(s) for s in sig) + 12 * P),
-        "gather1": N * sum(25 * sum(S[a]) + (3.5 * sum(T[a]) if tail_direct else 0) + 40 for a in range(M)),
-        "step2": N * sum(14.5 * sum(S[a]) + 30 * 19 for a in range(M)),
+        "gather1": N * sum(34 * sum(S[a]) + (8 * sum(T[a]) if tail_direct else 0) + 40 for a in range(M)),
+        "step2": N * sum(18 * sum(S[a]) + 30 * 19 for a in range(M)),
     }
     bytes_ = {
         # f in; n, j, u out
@@ -204,10 +208,10 @@ def closure_leg(mlb, W, steps=5000, train_box=(192, 12, 12)):
                         "last_check_err": st["last_err"]})
         return out
 
-    def rate(closure, k=200):
+    def rate(closure, k=200, check_every=1 << 30, tol=float("inf")):
         g = mlb.GpuMixture(mix, n0, u0, precision=32, device="cuda:0")
         if closure:
-            g.set_closure(net, check_every=1 << 30, tol=float("inf"))
+            g.set_closure(net, check_every=check_every, tol=tol)
         g.step(2)                                  # the step-0 check, graph capture
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -223,7 +227,12 @@ def closure_leg(mlb, W, steps=5000, train_box=(192, 12, 12)):
     checked = run(True, 1e-2)
     forced = run(True, float("inf"))
     r_plain, p_plain = rate(False)
+    # network-only steps (no check after the first): the speed of a step on
+    # the network's force, not of a run at any stated accuracy
     r_net, p_net = rate(True)
+    # the checked run as it is used: checks every 50 steps at tolerance 1e-2,
+    # the exact force up to the next check after a failed one
+    r_chk, _ = rate(True, k=500, check_every=50, tol=1e-2)
     macs = 27 * (8 * 32 + 32 * 32 + 32 * 32 + 32 * 6)
     net_ms = p_net.get("closure", 0.0)
     tflops = 2.0 * macs * mix.N / (net_ms * 1e-3) / 1e12 if net_ms else None
@@ -234,7 +243,9 @@ def closure_leg(mlb, W, steps=5000, train_box=(192, 12, 12)):
         "plain": plain, "closure_checked": checked, "closure_no_fallback": forced,
         "d12_rel_diff_checked": checked["d12"] / plain["d12"] - 1.0,
         "d12_rel_diff_no_fallback": forced["d12"] / plain["d12"] - 1.0,
-        "ssu_per_s": {"plain": r_plain, "closure": r_net, "speedup": r_net / r_plain},
+        "ssu_per_s": {"plain": r_plain, "closure_network_steps_only": r_net,
+                      "speedup_network_steps_only": r_net / r_plain,
+                      "closure_checked_tol_1e-2": r_chk, "speedup_checked_tol_1e-2": r_chk / r_plain},
         "passes_ms_per_step": {"plain": p_plain, "closure": p_net},
         "network_roofline": {"bound": "mfma", "achieved": tflops, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                              "frac": tflops / BF16_PEAK_TFLOPS if tflops else None,
@@ -263,26 +274,11 @@ def ensemble_leg(mlb, W, steps=1000, timed=200):
             b.step(10)
     torch.cuda.synchronize()
     run_s = time.perf_counter() - t0
-    D = b.fit(t_min=200)
-    # a fit is well conditioned when, over the fit's window (the library's
-    # rule), ln A is a straight line (R^2 >= 0.98) through at least five
-    # samples that stay above 1e-4 of the first amplitude (clear of the
-    # rounding floor; oscillating decay fails the R^2 test)
-    good = []
-    for k in range(len(mixes)):
-        t, a = b.series(k)
-        if len(a) == 0 or not a[0] > 0:
-            continue
-        low = np.flatnonzero(a <= 0.1 * a[0])
-        t_lo = min(200.0, t[low[0]]) if low.size else 200.0
-        sel = (t >= t_lo) & (a >= 1e-6 * a[0])
-        tw, lw = t[sel], np.log(a[sel])
-        if len(tw) < 5 or np.exp(lw.min()) < 1e-4 * a[0]:
-            continue
-        fit = np.polyval(np.polyfit(tw, lw, 1), tw)
-        ss = np.sum((lw - lw.mean()) ** 2)
-        if ss > 0 and 1.0 - np.sum((lw - fit) ** 2) / ss >= 0.98:
-            good.append(k)
+    fits = b.fit_ex(t_min=200)
+    D = fits[:, 0]
+    # the library's quality flag: ln A on a straight line (R^2 >= 0.98)
+    # through at least five samples above 1e-4 of the first amplitude
+    good = [k for k in range(len(mixes)) if fits[k, 4] == 1.0]
     Dg = D[good] if good else np.array([np.nan])
     b.step(4)
     torch.cuda.synchronize()
@@ -310,13 +306,13 @@ def ensemble_leg(mlb, W, steps=1000, timed=200):
 
 
 def taylor_leg(mlb, W, steps=5000, timed=200, packing=0.2):
-    """Taylor dispersion: the ternary mixture in Couette flow between walls
-    moving at -+U (256x64x16, tail 0.3 kT, spectral tail zero-padded past the
-    walls), a Gaussian tracer band of species 3; the axial spread of the
-    tracer is recorded every 10 steps and D_eff is half the slope of its
-    variance; throughput of `timed` graph-replayed steps.  Packing 0.2: at
-    0.25 the fluid piles up against the zero-density wall layers (no wall
-    potential) and the state diverges within 500 steps, in float64 too."""
+    """Taylor dispersion between walls: the ternary mixture in Couette flow
+    between walls moving at -+U (256x64x16, tail 0.3 kT, spectral tail
+    zero-padded past the walls), a Gaussian tracer band of species 3.  D_eff
+    from the decay of the tracer's section-averaged mode at k = 2 pi / nx
+    (recorded every 10 steps; eq. c99 makes that mode decay at D_eff k^2),
+    which, unlike the band's variance, does not depend on where the band sits
+    in the periodic box; throughput of `timed` graph-replayed steps."""
     import torch
 
     mix, n0, u0 = W.config_taylor_couette(packing=packing)
@@ -325,12 +321,12 @@ def taylor_leg(mlb, W, steps=5000, timed=200, packing=0.2):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for t in range(0, steps + 1, 10):
-        g.record_spread(2)
+        g.record_mode(2, -1)
         if t < steps:
             g.step(10)
     torch.cuda.synchronize()
     run_s = time.perf_counter() - t0
-    d_eff = g.fit(1, t_min=steps / 5)
+    fit = g.fit_ex(0, t_min=steps / 5)
     mass, _ = g.conserved()
     g.step(4)
     torch.cuda.synchronize()
@@ -346,14 +342,105 @@ def taylor_leg(mlb, W, steps=5000, timed=200, packing=0.2):
         "workload": f"taylor_couette_{mix.nx}x{mix.ny}x{mix.nz}", "species": mix.M, "sites": mix.N,
         "packing": packing,
         "ssu_per_s": ssu_step * timed / dt, "ms_per_step": dt * 1e3 / timed,
-        "run_with_spread_records": {"steps": steps, "seconds": run_s},
-        "d_eff": d_eff, "mass_finite": bool(np.all(np.isfinite(mass))),
+        "run_with_mode_records": {"steps": steps, "seconds": run_s},
+        "d_eff": fit["D"], "d_eff_fit": {"r2": fit["r2"], "samples": fit["samples"],
+                                         "well_conditioned": fit["well_conditioned"]},
+        "mass_finite": bool(np.all(np.isfinite(mass))),
         "tuning": {"shape": ["16x4x4", "8x8x4", "32x4x2"][tune["shape"]], "order": ["linear", "xcd-chunked"][tune["order"]]},
         "passes_ms_per_step": {k: v[0] / 10 for k, v in passes.items() if v[1]},
     }
 
 
+def kolmogorov_leg(mlb, W, packing=0.332, box=(80, 40, 40), pes=(0.0, 1.0, 2.0, 3.0), steps=600):
+    """The paper's Taylor-dispersion experiment (Sec. 5.2): a binary of
+    diameters 8 and 4 cells at mole fraction 1/2 and packing 0.332 in an
+    80x40x40 periodic box, a composition mode along x, and the modulated
+    flow u_x(y) = U cos(2 pi y / Ly) of eq. (ushape) driven by the body force
+    profile that sustains it (its amplitude from a flow-only calibration
+    run).  For each Peclet number Pe = U Ly / (2 D) (D from the Pe = 0 run)
+    D_eff comes from the library's mode record and fit, next to eq.
+    (taylordiff) D (1 + Pe^2 / (2 pi^2)) and the passive-scalar eigenvalue
+    at the box's own axial wavenumber (finite Lx / Ly)."""
+    import torch
+
+    nx, ny, nz = box
+    sigma = (8.0, 4.0)
+    n_tot = W.number_density(packing, (0.5, 0.5), sigma)
+    k = 2 * math.pi / ny
+    cosy = np.cos(k * np.arange(ny))
+
+    def mixture():
+        return W.Mixture(nx, ny, nz, sigma=sigma, name=f"kolmogorov_{nx}x{ny}x{nz}")
+
+    # flow-only calibration: steady amplitude per unit force
+    m = mixture()
+    n0, u0 = W.uniform_state(m, [0.5 * n_tot, 0.5 * n_tot])
+    g = mlb.GpuMixture(m, n0, u0, precision=32, device="cuda:0")
+    F1 = 1e-5
+    prof = np.zeros((2, 3, ny))
+    prof[:, 0, :] = F1 * cosy[None, :]
+    g.set_force_profile(prof)
+    g.step(400)
+
+    def flow_amp(gm):
+        n, j = (t.cpu().numpy().astype(np.float64) for t in gm.moments())
+        ux = j[:, 0].sum(0) / n.sum(0)
+        return 2.0 / ny * float((ux.mean(axis=(0, 2)) * cosy).sum())
+
+    per_force = flow_amp(g) / F1
+    del g
+    out = {"workload": f"kolmogorov_{nx}x{ny}x{nz}", "sigma": list(sigma), "packing": packing, "x1": 0.5,
+           "runs": []}
+    D = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for pe in pes:
+        U = 0.0 if pe == 0.0 else pe * 2.0 * D / ny
+        m = mixture()
+        n0, u0 = W.mode_state(m, n_tot, 0.5, 0.02)
+        u0[:, 0] = U * cosy[None, None, :, None]
+        g = mlb.GpuMixture(m, n0, u0, precision=32, device="cuda:0")
+        prof = np.zeros((2, 3, ny))
+        prof[:, 0, :] = (U / per_force) * cosy[None, :]
+        g.set_force_profile(prof)
+        g.reset_series()
+        for t in range(0, steps + 1, 5):
+            g.record_mode(0, 1)
+            if t < steps:
+                g.step(5)
+        fit = g.fit_ex(0, t_min=60.0)
+        U_meas = flow_amp(g)
+        if pe == 0.0:
+            D = fit["D"]
+        pe_meas = U_meas * ny / (2.0 * D)
+        out["runs"].append({"pe_target": pe, "U": U_meas, "pe": pe_meas, "d_eff": fit["D"],
+                            "paper_taylordiff": D * (1.0 + pe_meas ** 2 / (2.0 * math.pi ** 2)),
+                            "r2": fit["r2"], "well_conditioned": fit["well_conditioned"]})
+    torch.cuda.synchronize()
+    out["seconds"] = time.perf_counter() - t0
+    out["D"] = D
+    # quadratic growth of Sec. 5.2: (D_eff / D - 1) against Pe^2
+    pe2 = np.array([r["pe"] ** 2 for r in out["runs"]])
+    rel = np.array([r["d_eff"] / D - 1.0 for r in out["runs"]])
+    out["slope_vs_pe2"] = float(np.polyfit(pe2, rel, 1)[0]) if len(pe2) > 1 else None
+    out["slope_paper"] = 1.0 / (2.0 * math.pi ** 2)
+    return out
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(mix, n0, u0, target_s=12.0):
+    """The float64 oracle on the host: all its OpenMP threads over a sample of
+    about target_s seconds, then one thread over one step (the same per-site
+    arithmetic, so the same result)."""
     import oracle
     o = oracle.Oracle(mix)
     f = o.init(n0, u0)
@@ -364,9 +451,24 @@ def cpu_baseline(mix, n0, u0, target_s=12.0):
     t0 = time.perf_counter()
     o.step(f, steps)
     dt = time.perf_counter() - t0
-    return {"value": mix.M * mix.N * steps / dt, "unit": "SSU/s", "cores": oracle.threads(), "kind": "oracle",
+    threads = oracle.threads()
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        o.step(f, 1)
+        dt_one = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    return {"value": mix.M * mix.N * steps / dt, "unit": "SSU/s", "cores": threads, "kind": "oracle",
             "sample": f"{steps} full steps of the same {mix.nx}x{mix.ny}x{mix.nz} workload in float64 "
-                      f"(direct tail sum), after 1 untimed step"}
+                      f"(direct tail sum), after 1 untimed step",
+            "single_core": {"value": mix.M * mix.N / dt_one, "unit": "SSU/s", "cores": 1,
+                            "sample": "1 full step of the same workload on one thread"},
+            "cpu_model": _cpu_model(), "host_cpus_visible": affinity}
 
 
 def main():
@@ -383,6 +485,8 @@ def main():
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--no-taylor", action="store_true", help="skip the Taylor-dispersion (walls) leg")
+    ap.add_argument("--no-kolmogorov", action="store_true",
+                    help="skip the Taylor-dispersion leg in the modulated (Kolmogorov) flow")
     ap.add_argument("--closure-steps", type=int, default=5000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB elementwise copy (counter calibration for profiles)")
@@ -464,7 +568,8 @@ def main():
                    "sigma": list(mix.sigma), "packing": 0.3, "eps_over_kT": 0.5, "rc_over_sigma": mix.rc_factor,
                    "tail": "direct" if tail_direct else "spectral", "scheme": "CN-J1", "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                     "frac_of_nonpacked_peak": achieved / FP32_NONPACKED_TFLOPS, "traffic": traffic,
                      "traffic_algorithmic": bytes_[dom], "flop_per_launch": flops[dom],
                      "avg_launch_ms": avg_ms[dom]},
         "timing": "value and ms_per_step: the timed steps replayed from the captured hipGraph (the default "
@@ -490,6 +595,11 @@ def main():
             line["taylor"] = taylor_leg(mlb, W)
         except Exception as exc:      # reported in the line; the headline stands on its own
             line["taylor"] = {"error": f"{type(exc).__name__}: {exc}"}
+    if not args.no_kolmogorov:
+        try:
+            line["taylor_kolmogorov"] = kolmogorov_leg(mlb, W)
+        except Exception as exc:      # reported in the line; the headline stands on its own
+            line["taylor_kolmogorov"] = {"error": f"{type(exc).__name__}: {exc}"}
     if not args.no_closure:
         try:
             line["closure"] = closure_leg(mlb, W, steps=args.closure_steps)

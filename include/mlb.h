@@ -177,6 +177,16 @@ mlb_status mlb_fields(mlb_mixture h, void *n, void *j, void *u, void *g, void *v
 mlb_status mlb_get_populations(mlb_mixture h, void *f_out, void *stream);
 mlb_status mlb_set_populations(mlb_mixture h, const void *f_in, void *stream);
 
+/* Body force varying across the lattice rows (the external force F^a of
+ * Sec. 2, eq. evolution, as a function of y; a y-periodic profile drives the
+ * periodically modulated shear flow of Sec. 5.2, eq. ushape).  profile: HOST
+ * float64 [M][3][ny]; from the next step on, species a at a site of row y
+ * feels F^a(y) = ext_force[a] + profile[a][.][y] (the sum formed in float64,
+ * then rounded to the mixture's precision).  NULL removes the profile
+ * (back to the uniform ext_force).  Solid wall layers feel no force.
+ * Synchronises `stream`.  MLB_EINVAL for non-finite values. */
+mlb_status mlb_set_force_profile(mlb_mixture h, const double *profile, void *stream);
+
 /* Global FP64 sums of the current state, accumulated on the GPU in float64:
  * mass[a] = sum_r n_a, mom[3a+d] = sum_r j_a,d (the conserved quantities of
  * eqs. continuity and momentcomponent).  HOST outputs; synchronises the
@@ -185,7 +195,11 @@ mlb_status mlb_conserved(mlb_mixture h, double *mass, double *mom, void *stream)
 
 /* Composition-mode projection (Sec. 5.1): appends one float64 sample
  * (t, |sum_r (n_a - n_b) exp(-i 2 pi x / nx)|) for species pair (a, b) to the
- * handle's on-device time series (capacity mlb_series_capacity()). */
+ * handle's on-device time series (capacity mlb_series_capacity()).  With
+ * b = -1 the sample is the mode of species a alone, |sum_r n_a exp(-i 2 pi x
+ * / nx)|: the section-averaged mode of a tracer band, which decays at
+ * D_eff q^2 (Sec. 5.2, eqs. c99 and taylordiff) and, unlike its variance,
+ * does not depend on where the band sits in the periodic box. */
 mlb_status mlb_record_mode(mlb_mixture h, int32_t a, int32_t b, void *stream);
 /* Second-moment record for a tracer band (Sec. 5.2): appends (t, Var_x) of
  * the y,z-summed density of species a along x, in float64. */
@@ -201,6 +215,14 @@ mlb_status mlb_series_reset(mlb_mixture h, void *stream);
  * floor of the densities.  kind 1 (spread): D = slope(Var, t) / 2.  Fewer
  * than two samples give NaN.  HOST output; synchronises the stream. */
 mlb_status mlb_fit_series(mlb_mixture h, int32_t kind, double t_min, double *D_out, void *stream);
+/* As mlb_fit_series, with the fit's quality: out5 (HOST, 5 doubles) =
+ * D, the slope, the number of samples fitted, the coefficient of
+ * determination R^2 of the line, and a well-conditioned flag (1.0 when the
+ * samples lie on a straight line, R^2 >= 0.98, at least five of them, and a
+ * mode fit's window stays above 1e-4 of the first amplitude; 0.0
+ * otherwise: oscillating decay, or a mode lost in the rounding floor of the
+ * densities).  Synchronises. */
+mlb_status mlb_fit_series_ex(mlb_mixture h, int32_t kind, double t_min, double *out5, void *stream);
 /* Copy the recorded series to HOST memory: t[count], v[count]; returns the
  * count through *count.  Synchronises. */
 mlb_status mlb_get_series(mlb_mixture h, double *t, double *v, int32_t capacity, int32_t *count,
@@ -269,6 +291,9 @@ mlb_status mlb_batch_record_modes(mlb_batch h, void *stream);
 /* Mode-decay fit of every system (kind 0 of mlb_fit_series): D_out is a
  * HOST array of `count` values.  Synchronises. */
 mlb_status mlb_batch_fit(mlb_batch h, double t_min, double *D_out, void *stream);
+/* As mlb_batch_fit with the quality of every fit: out5 is a HOST array of
+ * count x 5 doubles laid out as mlb_fit_series_ex's. */
+mlb_status mlb_batch_fit_ex(mlb_batch h, double t_min, double *out5, void *stream);
 /* Recorded series of one system, as mlb_get_series (HOST outputs;
  * synchronises; an out-of-range system is MLB_EINVAL). */
 mlb_status mlb_batch_get_series(mlb_batch h, int32_t system, double *t, double *v, int32_t capacity,

@@ -177,6 +177,17 @@ class GpuMixture:
                    "mlb_set_populations")
         self._keep = f
 
+    def set_force_profile(self, profile: Optional[np.ndarray]) -> None:
+        """Body force per lattice row, [M][3][ny] float64 (added to the uniform
+        ext_force), or None to remove it."""
+        if profile is None:
+            ptr = None
+        else:
+            prof = np.ascontiguousarray(profile, dtype=np.float64)
+            assert prof.shape == (self.M, 3, self.shape[1])
+            ptr = prof.ctypes.data_as(C.POINTER(C.c_double))
+        _lib.check(self.lib.mlb_set_force_profile(self.h, ptr, _stream_handle(self.stream)), "mlb_set_force_profile")
+
     # ---------------------------------------------------------------- timing
     def profile_begin(self) -> None:
         _lib.check(self.lib.mlb_profile_begin(self.h), "mlb_profile_begin")
@@ -209,6 +220,13 @@ class GpuMixture:
         _lib.check(self.lib.mlb_fit_series(self.h, kind, float(t_min), C.byref(out), _stream_handle(self.stream)),
                    "mlb_fit_series")
         return float(out.value)
+
+    def fit_ex(self, kind: int = 0, t_min: float = 0.0) -> Dict[str, float]:
+        """The fit with its quality (mlb_fit_series_ex)."""
+        out = (C.c_double * 5)()
+        _lib.check(self.lib.mlb_fit_series_ex(self.h, kind, float(t_min), out, _stream_handle(self.stream)),
+                   "mlb_fit_series_ex")
+        return {"D": out[0], "slope": out[1], "samples": int(out[2]), "r2": out[3], "well_conditioned": out[4] == 1.0}
 
     def series(self):
         cap = int(self.lib.mlb_series_capacity())
@@ -323,6 +341,13 @@ class GpuBatch:
         out = (C.c_double * self.count)()
         _lib.check(self.lib.mlb_batch_fit(self.h, float(t_min), out, _stream_handle(self.stream)), "mlb_batch_fit")
         return np.array(out[:])
+
+    def fit_ex(self, t_min: float = 0.0) -> np.ndarray:
+        """[count][5] = (D, slope, samples, R^2, well-conditioned flag) (mlb_batch_fit_ex)."""
+        out = (C.c_double * (5 * self.count))()
+        _lib.check(self.lib.mlb_batch_fit_ex(self.h, float(t_min), out, _stream_handle(self.stream)),
+                   "mlb_batch_fit_ex")
+        return np.array(out[:]).reshape(self.count, 5)
 
     def series(self, system: int):
         """(t, amplitude) of one system's recorded mode series (host arrays)."""

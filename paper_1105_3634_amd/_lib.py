@@ -62,12 +62,14 @@ _SIGS = [
     ("mlb_fields", C.c_int, [C.c_void_p] + [C.c_void_p] * 7 + [C.c_void_p]),
     ("mlb_get_populations", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("mlb_set_populations", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("mlb_set_force_profile", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
     ("mlb_conserved", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]),
     ("mlb_record_mode", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
     ("mlb_record_spread", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     ("mlb_series_capacity", C.c_int32, []),
     ("mlb_series_reset", C.c_int, [C.c_void_p, C.c_void_p]),
     ("mlb_fit_series", C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_double), C.c_void_p]),
+    ("mlb_fit_series_ex", C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_double), C.c_void_p]),
     ("mlb_get_series", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32,
                                  C.POINTER(C.c_int32), C.c_void_p]),
     ("mlb_step_count", C.c_int64, [C.c_void_p]),
@@ -85,6 +87,7 @@ _SIGS = [
     ("mlb_batch_get_populations", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     ("mlb_batch_record_modes", C.c_int, [C.c_void_p, C.c_void_p]),
     ("mlb_batch_fit", C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_double), C.c_void_p]),
+    ("mlb_batch_fit_ex", C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_double), C.c_void_p]),
     ("mlb_batch_get_series", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                        C.c_int32, C.POINTER(C.c_int32), C.c_void_p]),
     ("mlb_batch_tuning", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)]),

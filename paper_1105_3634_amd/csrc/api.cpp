@@ -54,6 +54,7 @@ mlb_status fail(mlb_status st, const std::string &msg)
 constexpr size_t kAlign = 256;
 constexpr int kSeriesCap = 8192;
 constexpr int kRedParts = 512;
+constexpr int kFitOut = 8;   // doubles per fit result: D, slope, samples, R^2, well-conditioned flag
 constexpr int kXcds = 8;   // MI355X: workgroups are dealt round-robin over 8 XCDs
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -194,6 +195,8 @@ struct SysHost {
     size_t f0 = 0, f1 = 0, n = 0, j = 0, u = 0, g = 0, vh = 0, H = 0, Nf = 0, Tloc = 0, gfac = 0;
     size_t wxf = 0, wxi = 0, wyf = 0, wyi = 0, wzf = 0, wzi = 0, S = 0, s1 = 0, s2 = 0, tail = 0;
     size_t series = 0, series_cnt = 0;
+    size_t fprof = 0;            // body force per lattice row [M][3][ny]
+    bool has_profile = false;
 };
 
 struct Tuning {
@@ -265,6 +268,7 @@ struct mlb_batch_s {
     int64_t closure_checks = 0, fallback_step = -1, failed_checks = 0, net_steps = 0;
     double last_err = -1.0;
     hipGraphExec_t graph_closure = nullptr;
+    unsigned long long graph_closure_version = 0;   // net version the closure graph was captured with
     // second stream for the contact pass while the spectral field runs
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -384,7 +388,7 @@ bool plan_batch(Batch &B, const mlb_params *params, int count, std::string &why)
     B.t_sh_q = take(16 * (nsh + mlb::kShellPad));
     B.red = take(sizeof(double) * kRedParts * 16);
     B.red_out = take(sizeof(double) * 16);
-    B.fit_out = take(sizeof(double) * 4 * (size_t)count);
+    B.fit_out = take(sizeof(double) * kFitOut * (size_t)count);
     for (auto &S : B.sys) {
         const size_t M = (size_t)S.M, N = (size_t)S.N, P = (size_t)S.P;
         S.f0 = take(ts * M * mlb::kQ * N);
@@ -415,6 +419,7 @@ bool plan_batch(Batch &B, const mlb_params *params, int count, std::string &why)
         }
         S.series = take(sizeof(double) * 2 * kSeriesCap);
         S.series_cnt = take(sizeof(int));
+        S.fprof = take(ts * 3 * M * (size_t)S.p.ny);
     }
     B.total = off;
     return true;
@@ -449,6 +454,7 @@ void fill_desc(Batch &B, int k, mlb::SysDesc<T> &D)
     D.gfac = D.tail_deferred ? reinterpret_cast<T *>(ws + S.gfac) : nullptr;
     D.parts = nullptr;
     D.parts_mask = 0;
+    D.fprof = S.has_profile ? reinterpret_cast<const T *>(ws + S.fprof) : nullptr;
     D.tail_direct = S.spectral ? 0 : 1;
     D.scheme = p->scheme;
     D.omega_is_one = (1.0 / p->tau == 1.0) ? 1 : 0;
@@ -832,6 +838,12 @@ mlb_status run_steps(Batch &B, int nsteps, hipStream_t st, bool with_net)
 {
     hipGraphExec_t &graph = with_net ? B.graph_closure : B.graph;
     void (*one)(Batch &, hipStream_t) = with_net ? net_step : plain_step;
+    // the network's scales are kernel arguments of the captured inference:
+    // a graph captured before they changed would replay the old ones
+    if (with_net && graph && B.graph_closure_version != mlb::net_version(B.net)) {
+        (void)hipGraphExecDestroy(graph);
+        graph = nullptr;
+    }
     int left = nsteps;
     if (B.use_graph && !B.profiling && left >= 2) {
         if (B.parity == 1) {
@@ -839,7 +851,10 @@ mlb_status run_steps(Batch &B, int nsteps, hipStream_t st, bool with_net)
             --left;
         }
         if (left >= 2) {
-            if (!graph) TRY(capture_pair(B, &graph, one));
+            if (!graph) {
+                TRY(capture_pair(B, &graph, one));
+                if (with_net) B.graph_closure_version = mlb::net_version(B.net);
+            }
             while (left >= 2) {
                 HIP_TRY(hipGraphLaunch(graph, st));
                 B.steps += 2;
@@ -1122,6 +1137,33 @@ mlb_status profile_end(Batch &B, double *ms, int32_t *launches, hipStream_t st)
 
 }  // namespace
 
+namespace {
+template <typename T>
+mlb_status set_profile(Batch &B, const double *prof, hipStream_t st)
+{
+    SysHost &S = B.sys[0];
+    const int M = S.M, ny = S.p.ny;
+    if (prof) {
+        // F^a(y) = ext_force[a] + profile[a][y], added in float64 on the host
+        std::vector<T> tab((size_t)3 * M * ny);
+        for (int a = 0; a < M; ++a)
+            for (int d = 0; d < 3; ++d)
+                for (int y = 0; y < ny; ++y) {
+                    const size_t i = ((size_t)a * 3 + d) * ny + y;
+                    if (!std::isfinite(prof[i])) return fail(MLB_EINVAL, "force profile values must be finite");
+                    tab[i] = (T)(S.p.ext_force[a * 3 + d] + prof[i]);
+                }
+        HIP_TRY(hipMemcpyAsync(B.ws + S.fprof, tab.data(), sizeof(T) * tab.size(), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));   // the host table dies here
+    }
+    S.has_profile = prof != nullptr;
+    fill_desc<T>(B, 0, *B.hdesc<T>(0));
+    HIP_TRY(hipMemcpyAsync(B.ws + B.desc, B.hdesc<T>(0), B.desc_size, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return MLB_OK;
+}
+}  // namespace
+
 // ===================================================================== ABI
 extern "C" {
 
@@ -1246,6 +1288,14 @@ mlb_status mlb_set_populations(mlb_mixture h, const void *f_in, void *stream)
     return MLB_OK;
 }
 
+
+mlb_status mlb_set_force_profile(mlb_mixture h, const double *profile, void *stream)
+{
+    if (!h) return fail(MLB_EINVAL, "handle is NULL");
+    if (h->count != 1) return fail(MLB_EUNSUPPORTED, "force profiles are per mixture");
+    return h->prec == 64 ? set_profile<double>(*h, profile, S_(stream)) : set_profile<float>(*h, profile, S_(stream));
+}
+
 mlb_status mlb_conserved(mlb_mixture h, double *mass, double *mom, void *stream)
 {
     if (!h) return fail(MLB_EINVAL, "handle is NULL");
@@ -1270,7 +1320,7 @@ mlb_status mlb_record_mode(mlb_mixture h, int32_t a, int32_t b, void *stream)
 {
     if (!h) return fail(MLB_EINVAL, "handle is NULL");
     const SysHost &S = h->sys[0];
-    if (a < 0 || b < 0 || a >= S.M || b >= S.M || a == b) return fail(MLB_EINVAL, "bad species pair");
+    if (a < 0 || b < -1 || a >= S.M || b >= S.M || a == b) return fail(MLB_EINVAL, "bad species pair");
     TRY(moments_of(*h, 0, nullptr, nullptr, S_(stream)));
     return record_mode_of(*h, 0, a, b, S_(stream));
 }
@@ -1299,9 +1349,9 @@ mlb_status mlb_series_reset(mlb_mixture h, void *stream)
     return MLB_OK;
 }
 
-mlb_status mlb_fit_series(mlb_mixture h, int32_t kind, double t_min, double *D_out, void *stream)
+mlb_status mlb_fit_series_ex(mlb_mixture h, int32_t kind, double t_min, double *out5, void *stream)
 {
-    if (!h || !D_out) return fail(MLB_EINVAL, "handle and output are required");
+    if (!h || !out5) return fail(MLB_EINVAL, "handle and output are required");
     if (kind != 0 && kind != 1) return fail(MLB_EINVAL, "kind must be 0 (mode) or 1 (spread)");
     hipStream_t st = S_(stream);
     const SysHost &S = h->sys[0];
@@ -1310,8 +1360,17 @@ mlb_status mlb_fit_series(mlb_mixture h, int32_t kind, double t_min, double *D_o
     mlb::launch_fit(reinterpret_cast<const double *>(h->ws + S.series),
                     reinterpret_cast<const int *>(h->ws + S.series_cnt), kSeriesCap, kind, t_min, k * k, out, st);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(D_out, out, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(out5, out, sizeof(double) * 5, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    return MLB_OK;
+}
+
+mlb_status mlb_fit_series(mlb_mixture h, int32_t kind, double t_min, double *D_out, void *stream)
+{
+    if (!h || !D_out) return fail(MLB_EINVAL, "handle and output are required");
+    double out[5];
+    TRY(mlb_fit_series_ex(h, kind, t_min, out, stream));
+    *D_out = out[0];
     return MLB_OK;
 }
 
@@ -1505,9 +1564,9 @@ mlb_status mlb_batch_record_modes(mlb_batch h, void *stream)
     return MLB_OK;
 }
 
-mlb_status mlb_batch_fit(mlb_batch h, double t_min, double *D_out, void *stream)
+mlb_status mlb_batch_fit_ex(mlb_batch h, double t_min, double *out5, void *stream)
 {
-    if (!h || !D_out) return fail(MLB_EINVAL, "handle and output are required");
+    if (!h || !out5) return fail(MLB_EINVAL, "handle and output are required");
     hipStream_t st = S_(stream);
     double *out = reinterpret_cast<double *>(h->ws + h->fit_out);
     for (int k = 0; k < h->count; ++k) {
@@ -1515,13 +1574,23 @@ mlb_status mlb_batch_fit(mlb_batch h, double t_min, double *D_out, void *stream)
         const double kk = 2.0 * M_PI / (double)S.p.nx;
         mlb::launch_fit(reinterpret_cast<const double *>(h->ws + S.series),
                         reinterpret_cast<const int *>(h->ws + S.series_cnt), kSeriesCap, 0, t_min, kk * kk,
-                        out + 4 * k, st);
+                        out + kFitOut * k, st);
     }
     HIP_TRY(hipGetLastError());
-    std::vector<double> host(4 * (size_t)h->count);
+    std::vector<double> host(kFitOut * (size_t)h->count);
     HIP_TRY(hipMemcpyAsync(host.data(), out, sizeof(double) * host.size(), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    for (int k = 0; k < h->count; ++k) D_out[k] = host[4 * (size_t)k];
+    for (int k = 0; k < h->count; ++k)
+        for (int i = 0; i < 5; ++i) out5[5 * (size_t)k + i] = host[kFitOut * (size_t)k + i];
+    return MLB_OK;
+}
+
+mlb_status mlb_batch_fit(mlb_batch h, double t_min, double *D_out, void *stream)
+{
+    if (!h || !D_out) return fail(MLB_EINVAL, "handle and output are required");
+    std::vector<double> all(5 * (size_t)h->count);
+    TRY(mlb_batch_fit_ex(h, t_min, all.data(), stream));
+    for (int k = 0; k < h->count; ++k) D_out[k] = all[5 * (size_t)k];
     return MLB_OK;
 }
 

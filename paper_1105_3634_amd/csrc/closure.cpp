@@ -31,6 +31,9 @@ struct mlb_net_s {
     size_t part = 0, loss = 0, err = 0, nc = 0;
     int nblk = 0;
     float n_ref = 1.f, j_ref = 1.f, f_ref = 1.f;
+    // bumped whenever something a captured inference graph bakes in (the
+    // scales, passed as kernel arguments) changes
+    unsigned long long version = 0;
     int adam_t = 0;
 };
 
@@ -123,6 +126,8 @@ int net_grid(const mlb_net_s *n, int *nx, int *ny, int *nz)
     *nx = n->nx; *ny = n->ny; *nz = n->nz;
     return 0;
 }
+
+unsigned long long net_version(const mlb_net_s *n) { return n->version; }
 
 // the last layer writes the force fields itself (same values as the y
 // buffer scaled by f_ref, without the [N][16] round trip)
@@ -259,6 +264,7 @@ mlb_status mlb_net_set_scales(mlb_net n, double n_ref, double j_ref, double f_re
     n->n_ref = (float)n_ref;
     n->j_ref = (float)j_ref;
     n->f_ref = (float)f_ref;
+    n->version += 1;
     return MLB_OK;
 }
 

@@ -450,7 +450,9 @@ k_gather1_tile(const SysDesc<float> *__restrict__ sys,
                          T02 * ja0 + T12 * ja1 + T22 * ja2};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const float Nmf = na * mfv[d], Ntl = na * tlv[d], Nex = na * S.fext[a][d];
+        const float fe = S.fprof ? glb(const_cast<float *>(S.fprof))[((long long)a * 3 + d) * S.ny + q.y]
+                                 : S.fext[a][d];
+        const float Nmf = na * mfv[d], Ntl = na * tlv[d], Nex = na * fe;
         const float Nc = Nmf + Ntl + Nex;
         const float Dd = na * djv[d] - Tj[d];
         if (S.scheme == 1) {

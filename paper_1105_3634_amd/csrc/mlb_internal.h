@@ -60,6 +60,7 @@ struct SysDesc {
     T dd[kMaxS][kMaxS];              // sigma_a sigma_b / (sigma_a + sigma_b)
     T s2[kMaxS], s3[kMaxS];          // (pi/6) sigma^2, (pi/6) sigma^3
     T fext[kMaxS][3];
+    const T *fprof;                  // body force per lattice row [M][3][ny] (replaces fext when set)
     T omega, om1;
     T wall_ux[2];
 };

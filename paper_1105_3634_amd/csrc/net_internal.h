@@ -13,6 +13,8 @@ namespace mlb {
 mlb_status set_error(mlb_status st, const std::string &msg);
 
 int net_grid(const mlb_net_s *n, int *nx, int *ny, int *nz);
+// changes whenever a captured inference graph of the net must be re-captured
+unsigned long long net_version(const mlb_net_s *n);
 // force [2][3][N] = f_ref * CNN((n_a / n_ref - 1, j_a / j_ref)) for a binary float32 state
 void net_infer_fields(mlb_net_s *n, const float *dens, const float *mom, float *force, hipStream_t st);
 // [6][N] float32 scratch for the closure force at check steps

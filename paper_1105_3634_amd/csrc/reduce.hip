@@ -3,7 +3,9 @@
 //  - conserved quantities: sum_r n_a and sum_r j_a (the species continuity
 //    and momentum balances of Sec. 2, eqs. continuity and momentcomponent);
 //  - the composition-mode amplitude |sum_r (n_a - n_b) exp(-i k x)| whose
-//    decay 1/tau = D q^2 gives the mutual diffusion coefficient (Sec. 5.1);
+//    decay 1/tau = D q^2 gives the mutual diffusion coefficient (Sec. 5.1),
+//    or the amplitude |sum_r n_a exp(-i k x)| of one species (a tracer band,
+//    whose section-averaged modes decay at D_eff q^2, Sec. 5.2);
 //  - the x-variance of a tracer band (Taylor dispersion, Sec. 5.2);
 //  - a least-squares fit of a recorded time series.
 // Two passes: each block reduces a grid-strided slice (wave shuffles, then
@@ -91,7 +93,8 @@ __global__ void __launch_bounds__(kRedThreads) k_mode_partial(const T *__restric
     for (long long s = (long long)blockIdx.x * kRedThreads + threadIdx.x; s < N;
          s += (long long)gridDim.x * kRedThreads) {
         const int x = (int)(s % nx);
-        const double dn = (double)n[(long long)a * N + s] - (double)n[(long long)b * N + s];
+        const double dn = b >= 0 ? (double)n[(long long)a * N + s] - (double)n[(long long)b * N + s]
+                                 : (double)n[(long long)a * N + s];
         double sn, cs;
         sincos(k * (double)x, &sn, &cs);
         acc[0] += dn * cs;
@@ -125,14 +128,18 @@ __global__ void __launch_bounds__(kRedThreads) k_spread_partial(const T *__restr
 }
 
 // kind 0: amplitude sqrt(c^2 + s^2) from 2 columns; kind 1: variance from 3 columns.
-__global__ void k_append_series(const double *__restrict__ partials, int nparts, int kind, double *series,
-                                int *count, int cap, double t)
+// Thread t sums the partial rows t, t + 256, ... in order; the block sum then
+// adds the threads in a fixed tree, so the result does not depend on timing.
+__global__ void __launch_bounds__(kRedThreads) k_append_series(const double *__restrict__ partials, int nparts,
+                                                               int kind, double *series, int *count, int cap, double t)
 {
-    if (threadIdx.x != 0) return;
+    __shared__ double lds[3 * 4];
     const int nv = kind == 0 ? 2 : 3;
     double acc[3] = {0.0, 0.0, 0.0};
-    for (int p = 0; p < nparts; ++p)
+    for (int p = threadIdx.x; p < nparts; p += kRedThreads)
         for (int k = 0; k < nv; ++k) acc[k] += partials[(long long)p * nv + k];
+    block_sum(acc, nv, lds);
+    if (threadIdx.x != 0) return;
     double v;
     if (kind == 0) {
         v = sqrt(acc[0] * acc[0] + acc[1] * acc[1]);
@@ -157,7 +164,8 @@ void launch_mode(const void *n, int prec, int a, int b, int nx, long long N, dou
     else
         hipLaunchKernelGGL(k_mode_partial<float>, dim3(nparts), dim3(kRedThreads), 0, st, (const float *)n, a, b,
                            nx, N, partials);
-    hipLaunchKernelGGL(k_append_series, dim3(1), dim3(64), 0, st, partials, nparts, 0, series, count, cap, t);
+    hipLaunchKernelGGL(k_append_series, dim3(1), dim3(kRedThreads), 0, st, partials, nparts, 0, series, count, cap,
+                       t);
 }
 
 void launch_spread(const void *n, int prec, int a, int nx, long long N, double *partials, int nparts,
@@ -169,7 +177,8 @@ void launch_spread(const void *n, int prec, int a, int nx, long long N, double *
     else
         hipLaunchKernelGGL(k_spread_partial<float>, dim3(nparts), dim3(kRedThreads), 0, st, (const float *)n, a,
                            nx, N, partials);
-    hipLaunchKernelGGL(k_append_series, dim3(1), dim3(64), 0, st, partials, nparts, 1, series, count, cap, t);
+    hipLaunchKernelGGL(k_append_series, dim3(1), dim3(kRedThreads), 0, st, partials, nparts, 1, series, count, cap,
+                       t);
 }
 
 // ---------------------------------------------------------------------- fit
@@ -181,6 +190,7 @@ void launch_spread(const void *n, int prec, int a, int nx, long long N, double *
 // reached the float32 rounding floor of the densities long before a t_min
 // chosen for slow ones, and a slow mode never reaches either bound.
 constexpr double kFitStart = 0.1, kFitFloor = 1e-6;
+constexpr double kFitGoodR2 = 0.98, kFitGoodFloor = 1e-4;
 
 __device__ inline bool fit_sample(const double *series, int i, int kind, double t_lo, double a0)
 {
@@ -213,6 +223,10 @@ __global__ void k_fit(const double *__restrict__ series, const int *__restrict__
     }
     if (n < 2.0) {
         out[0] = nan("");
+        out[1] = nan("");
+        out[2] = n;
+        out[3] = 0.0;
+        out[4] = 0.0;
         return;
     }
     const double tm = st / n, ym = sy / n;
@@ -225,9 +239,26 @@ __global__ void k_fit(const double *__restrict__ series, const int *__restrict__
         sty += (t - tm) * (y - ym);
     }
     const double beta = sty / stt;
+    // coefficient of determination and the smallest amplitude of the window
+    double syy = 0.0, sres = 0.0, vmin = INFINITY;
+    for (int i = 0; i < c; ++i) {
+        if (!fit_sample(series, i, kind, t_lo, a0)) continue;
+        const double t = series[2 * i];
+        const double y = kind == 0 ? log(series[2 * i + 1]) : series[2 * i + 1];
+        const double r = y - (ym + beta * (t - tm));
+        syy += (y - ym) * (y - ym);
+        sres += r * r;
+        vmin = fmin(vmin, series[2 * i + 1]);
+    }
+    const double r2 = syy > 0.0 ? 1.0 - sres / syy : 0.0;
     out[0] = kind == 0 ? -beta / k2 : 0.5 * beta;
     out[1] = beta;
     out[2] = n;
+    out[3] = r2;
+    // well conditioned: a straight line (R^2 >= 0.98) through at least five
+    // samples; a mode fit also keeps its window above 1e-4 of the first
+    // amplitude, clear of the rounding floor of float32 densities
+    out[4] = (n >= 5.0 && r2 >= kFitGoodR2 && (kind != 0 || vmin >= kFitGoodFloor * a0)) ? 1.0 : 0.0;
 }
 
 void launch_fit(const double *series, const int *count, int cap, int kind, double t_min, double k2, double *out,

@@ -275,7 +275,8 @@ __global__ void __launch_bounds__(kBlock) k_gather1(const SysDesc<T> *__restrict
     for (int d = 0; d < 3; ++d) {
         const T Nmf = na * mf[d];
         const T Ntl = na * tl[d];
-        const T Nex = na * S.fext[a][d];
+        const T fe = S.fprof ? S.fprof[((long long)a * 3 + d) * S.ny + r.y] : S.fext[a][d];
+        const T Nex = na * fe;
         const T Nc = (Nmf + Ntl) + Nex;
         const T Dd = dv[d];
         if (S.scheme == 1) {

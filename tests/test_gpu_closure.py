@@ -361,3 +361,24 @@ def test_closure_graph_replays_match_eager(mlb):
     for a, b in zip(runs[0][0], runs[1][0]):
         np.testing.assert_array_equal(a, b)
     assert runs[0][1] == runs[1][1] and runs[0][1]["checks"] == 3
+
+
+def test_closure_graph_follows_rescaled_network(mlb):
+    """The network's scales are baked into a captured inference graph as
+    kernel arguments: after mlb_net_set_scales the replayed network steps must
+    use the new scales, as eager steps do (attach, step, rescale, step)."""
+    mix, n0, u0 = closure_case(16, 10, 10)
+    n_ref, j_ref, f_ref = scales(n0)
+    runs = []
+    for graph in (False, True):
+        g = mlb.GpuMixture(mix, n0, u0, precision=32)
+        g.set_graph(graph)
+        net = mlb.GpuNet(mix.shape())
+        net.set_params(random_layers(8, scale_b=0.02))
+        net.set_scales(n_ref, j_ref, f_ref)
+        g.set_closure(net, check_every=100, tol=float("inf"))
+        g.step(5)                                  # check at 0, then network steps (graph pairs)
+        net.set_scales(n_ref, 2.0 * j_ref, 3.0 * f_ref)
+        g.step(4)                                  # network steps only
+        runs.append(g.populations().cpu().numpy())
+    np.testing.assert_array_equal(runs[0], runs[1])
