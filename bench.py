@@ -437,6 +437,49 @@ def _cpu_model():
     return "unknown"
 
 
+def tail_study_leg(mlb, W, steps=2000):
+    """Tail dependence of D (Sec. 4.1, eq. berthelot): equal-diameter binaries
+    at packing 0.3 with diameters 2 and 4, c = 0.1 .. 0.9, without tails and
+    with Lorentz-Berthelot tails of strengths w_AA = -5 kT, w_BB = w_AA / 2
+    (w = int U), advanced as one float32 batch; D of each from its mode
+    record; the ratio D_tail / D_hs next to the linear estimate's factor
+    1 + c (1 - c) n (w_AA + w_BB - 2 w_AB) / kT."""
+    import torch
+
+    x1s = (0.1, 0.3, 0.5, 0.7, 0.9)
+    sys_ = []
+    for sigma in (2.0, 4.0):
+        for tails in (False, True):
+            for x1 in x1s:
+                sys_.append((sigma, tails, x1) + W.config_tail_study(sigma, 0.3, x1, tails=tails))
+    b = mlb.GpuBatch([s[3] for s in sys_], [s[4] for s in sys_], [s[5] for s in sys_], precision=32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(0, steps + 1, 10):
+        b.record_modes()
+        if t < steps:
+            b.step(10)
+    fits = b.fit_ex(t_min=200)
+    torch.cuda.synchronize()
+    out = {"workload": "tail_study_20_systems", "packing": 0.3, "w_AA_over_kT": -5.0, "steps": steps,
+           "seconds": time.perf_counter() - t0, "by_sigma": {}}
+    D = {(s[0], s[1], s[2]): float(q[0]) for s, q in zip(sys_, fits)}
+    for sigma in (2.0, 4.0):
+        rows = []
+        for (sg, tails, x1, m, n0, _) in sys_:
+            if sg != sigma or not tails:
+                continue
+            eps = m.eps_matrix()
+            w = -(4.0 * math.pi / 3.0) * eps * sigma ** 3 * (1.0 - m.rc_factor ** -3)
+            n = float(n0[0].mean() + n0[1].mean())
+            rows.append({"c": x1, "D_hs": D[(sigma, False, x1)], "D_tail": D[(sigma, True, x1)],
+                         "ratio": D[(sigma, True, x1)] / D[(sigma, False, x1)],
+                         "paper_factor_w": 1.0 + x1 * (1.0 - x1) * n * (w[0, 0] + w[1, 1] - 2.0 * w[0, 1]) / (1.0 / 3.0)})
+        out["by_sigma"][str(sigma)] = rows
+    out["all_well_conditioned"] = bool(np.all(fits[:, 4] == 1.0))
+    return out
+
+
 def cpu_baseline(mix, n0, u0, target_s=12.0):
     """The float64 oracle on the host: all its OpenMP threads over a sample of
     about target_s seconds, then one thread over one step (the same per-site
@@ -485,6 +528,7 @@ def main():
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--no-taylor", action="store_true", help="skip the Taylor-dispersion (walls) leg")
+    ap.add_argument("--no-tails", action="store_true", help="skip the tail-dependence (D(c)) leg")
     ap.add_argument("--no-kolmogorov", action="store_true",
                     help="skip the Taylor-dispersion leg in the modulated (Kolmogorov) flow")
     ap.add_argument("--closure-steps", type=int, default=5000)
@@ -600,6 +644,11 @@ def main():
             line["taylor_kolmogorov"] = kolmogorov_leg(mlb, W)
         except Exception as exc:      # reported in the line; the headline stands on its own
             line["taylor_kolmogorov"] = {"error": f"{type(exc).__name__}: {exc}"}
+    if not args.no_tails:
+        try:
+            line["tail_study"] = tail_study_leg(mlb, W)
+        except Exception as exc:      # reported in the line; the headline stands on its own
+            line["tail_study"] = {"error": f"{type(exc).__name__}: {exc}"}
     if not args.no_closure:
         try:
             line["closure"] = closure_leg(mlb, W, steps=args.closure_steps)

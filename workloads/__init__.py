@@ -217,3 +217,39 @@ def config_ensemble(count=64, seed=4242, edges=(32, 48, 64, 96), amplitude=0.05,
         n0, u0 = mode_state(m, n, x1, amplitude)
         out.append(EnsembleMember(m, n0, u0, x1, xi))
     return out
+
+
+# ----------------------------------------------- attractive tails (Sec. 4.1)
+def berthelot_eps(w: Sequence[float], sigma: Sequence[float], rc_factor: float = 2.5) -> np.ndarray:
+    """Depths eps_ab of the tails U_ab = -eps_ab (sigma_ab / r)^6, sigma_ab < r
+    <= rc sigma_ab, whose strengths w_ab = int d^3r U_ab(r) (the w_0 of the
+    paper's linear estimate) follow the geometric-mean (Lorentz-Berthelot)
+    rule w_ab = sqrt(w_aa w_bb) from the like strengths w[a] (negative:
+    attraction).  int U = -(4 pi / 3) eps sigma^3 (1 - rc^-3)."""
+    M = len(sigma)
+    eps = np.zeros((M, M))
+    for a in range(M):
+        for b in range(M):
+            wab = -math.sqrt(w[a] * w[b])
+            sab = 0.5 * (sigma[a] + sigma[b])
+            eps[a, b] = -wab / (4.0 * math.pi / 3.0 * sab ** 3 * (1.0 - rc_factor ** -3))
+    return eps
+
+
+def config_tail_study(sigma: float, packing: float, x1: float, w_aa: float = -5.0 * KT,
+                      tails: bool = True, nx: Optional[int] = None, amplitude: float = 0.05):
+    """Equal-diameter binary at the stated packing and mole fraction x1 with
+    Lorentz-Berthelot tails of strengths w_AA and w_BB = w_AA / 2 (the
+    attraction of the paper's D(c) study, Sec. 4.1), or none; a composition
+    mode along x of wavelength nx.  The cross-section is just wider than the
+    tail's reach."""
+    rc = 2.5
+    reach = int(math.floor(rc * sigma))
+    ny = reach + 3
+    L = nx if nx is not None else 32 * int(sigma)
+    eps = berthelot_eps([w_aa, 0.5 * w_aa], (sigma, sigma), rc) if tails else None
+    m = Mixture(L, ny, ny, sigma=(sigma, sigma), eps=eps, rc_factor=rc,
+                name=f"tail_study_s{sigma:g}_x{x1:g}_{'lb' if tails else 'hs'}")
+    n = number_density(packing, (x1, 1.0 - x1), m.sigma)
+    n0, u0 = mode_state(m, n, x1, amplitude)
+    return m, n0, u0
