@@ -19,8 +19,9 @@
  * The paper leaves the lattice discretisation to another paper; the
  * readings taken here (lattice shells, BMCSL contact values of ball-smoothed
  * packing fractions, Crank-Nicolson friction with one Jacobi predictor
- * sweep, halfway bounce-back walls) are the ones listed in the design notes
- * of the repository, and every arithmetic step below is written in the
+ * sweep, halfway bounce-back walls beyond which the hard-core stencils see
+ * the mirrored fluid moving with the wall) are the ones listed in the design
+ * notes of the repository, and every arithmetic step below is written in the
  * fixed order that a bit-exact FP64 comparison relies on:
  *   velocities in canonical order, stencil half-lists sorted by
  *   (|e|^2, ex, ey, ez) with each (+e,-e) pair combined first, species
@@ -294,8 +295,9 @@ static inline int wrap(int v, int n)
     return r < 0 ? r + n : r;
 }
 
-/* Linear index of r + e; -1 when the neighbour lies outside a walled box
- * (such sites carry zero density, momentum, contact value and velocity). */
+/* Linear index of r + e as the attractive field sees it; -1 when the
+ * neighbour lies outside a walled box (no fluid there: the field sums zero
+ * density beyond a wall). */
 static inline long neighbour(const or_ctx *c, int x, int y, int z, int ex, int ey, int ez)
 {
     int xx = wrap(x + ex, c->p.nx);
@@ -310,6 +312,43 @@ static inline long neighbour(const or_ctx *c, int x, int y, int z, int ex, int e
 }
 
 static inline double fld(const double *F, long s) { return s < 0 ? 0.0 : F[s]; }
+
+/* Neighbour of r + e as the hard-core stencils (smoothing balls and the
+ * shells of the mean field and of the friction) see it.  In a periodic box
+ * and inside the fluid rows it is the site itself.  Beyond a wall
+ * (y + e_y <= 0 or >= ny - 1 in a walled box) it is the mirror image of the
+ * fluid across the nearer wall plane, y = 1/2 or y = ny - 3/2, where halfway
+ * bounce-back puts the walls: the image carries the density and contact
+ * value of the mirrored fluid site and moves with the wall.  *img is 0 for
+ * a fluid site, 1 for an image beyond the y = 0 wall, 2 beyond the
+ * y = ny - 1 wall. */
+static inline long hc_neighbour(const or_ctx *c, int x, int y, int z, int ex, int ey, int ez, int *img)
+{
+    int xx = wrap(x + ex, c->p.nx);
+    int zz = wrap(z + ez, c->p.nz);
+    int yy = y + ey;
+    *img = 0;
+    if (c->p.walls_y) {
+        if (yy <= 0) {
+            yy = 1 - yy;
+            *img = 1;
+        } else if (yy >= c->p.ny - 1) {
+            yy = 2 * c->p.ny - 3 - yy;
+            *img = 2;
+        }
+    } else {
+        yy = wrap(yy, c->p.ny);
+    }
+    return ((long)zz * c->p.ny + yy) * c->p.nx + xx;
+}
+
+/* Component d of a velocity field V at a hard-core neighbour: the wall's
+ * velocity (u_wall, 0, 0) for an image, else V there. */
+static inline double hc_vel(const or_ctx *c, const double *V, long s, int img, int d, long N)
+{
+    if (img) return d == 0 ? c->p.wall_ux[img - 1] : 0.0;
+    return V[(size_t)d * N + s];
+}
 
 /* --------------------------------------------------- S1: moments, eq. (colonna) */
 static void moments(or_ctx *c, const double *f)
@@ -374,9 +413,10 @@ static void contact_values(or_ctx *c)
             const or_list *B = &c->ball[cc];
             double acc = nc[s];
             for (int k = 0; k < B->n; ++k) {
-                long sp = neighbour(c, x, y, z, B->e[3 * k], B->e[3 * k + 1], B->e[3 * k + 2]);
-                long sm = neighbour(c, x, y, z, -B->e[3 * k], -B->e[3 * k + 1], -B->e[3 * k + 2]);
-                acc = acc + (fld(nc, sp) + fld(nc, sm));
+                int ip, im;
+                long sp = hc_neighbour(c, x, y, z, B->e[3 * k], B->e[3 * k + 1], B->e[3 * k + 2], &ip);
+                long sm = hc_neighbour(c, x, y, z, -B->e[3 * k], -B->e[3 * k + 1], -B->e[3 * k + 2], &im);
+                acc = acc + (nc[sp] + nc[sm]);
             }
             nb[cc] = acc / (double)B->full;
         }
@@ -444,10 +484,11 @@ static void gather_one(or_ctx *c)
                 for (int k = 0; k < S->n; ++k) {
                     int ex = S->e[3 * k], ey = S->e[3 * k + 1], ez = S->e[3 * k + 2];
                     const double *eh = S->unit + 3 * k;
-                    long sp = neighbour(c, x, y, z, ex, ey, ez);
-                    long sm = neighbour(c, x, y, z, -ex, -ey, -ez);
-                    double Gp = g0 + fld(gp, sp), Gm = g0 + fld(gp, sm);
-                    double np_ = fld(nb, sp), nm_ = fld(nb, sm);
+                    int ip, im;
+                    long sp = hc_neighbour(c, x, y, z, ex, ey, ez, &ip);
+                    long sm = hc_neighbour(c, x, y, z, -ex, -ey, -ez, &im);
+                    double Gp = g0 + gp[sp], Gm = g0 + gp[sm];
+                    double np_ = nb[sp], nm_ = nb[sm];
                     double tp = Gp * np_, tm = Gm * nm_;
                     double dt = tp - tm;
                     smf[0] = smf[0] + eh[0] * dt;
@@ -456,8 +497,11 @@ static void gather_one(or_ctx *c)
                     sg = sg + (tp + tm);
                     double Xp[3], Xm[3];
                     for (int d = 0; d < 3; ++d) {
-                        Xp[d] = na * fld(jb + (size_t)d * N, sp) - np_ * ja[d];
-                        Xm[d] = na * fld(jb + (size_t)d * N, sm) - nm_ * ja[d];
+                        /* an image's momentum density: its density times the wall's velocity */
+                        double jp = ip ? np_ * hc_vel(c, NULL, 0, ip, d, N) : jb[(size_t)d * N + sp];
+                        double jm = im ? nm_ * hc_vel(c, NULL, 0, im, d, N) : jb[(size_t)d * N + sm];
+                        Xp[d] = na * jp - np_ * ja[d];
+                        Xm[d] = na * jm - nm_ * ja[d];
                     }
                     double pp = Gp * ((eh[0] * Xp[0] + eh[1] * Xp[1]) + eh[2] * Xp[2]);
                     double pm = Gm * ((eh[0] * Xm[0] + eh[1] * Xm[1]) + eh[2] * Xm[2]);
@@ -548,14 +592,15 @@ static void gather_two(or_ctx *c)
                 for (int k = 0; k < S->n; ++k) {
                     int ex = S->e[3 * k], ey = S->e[3 * k + 1], ez = S->e[3 * k + 2];
                     const double *eh = S->unit + 3 * k;
-                    long sp = neighbour(c, x, y, z, ex, ey, ez);
-                    long sm = neighbour(c, x, y, z, -ex, -ey, -ez);
-                    double tp = (g0 + fld(gp, sp)) * fld(nb, sp);
-                    double tm = (g0 + fld(gp, sm)) * fld(nb, sm);
+                    int ip, im;
+                    long sp = hc_neighbour(c, x, y, z, ex, ey, ez, &ip);
+                    long sm = hc_neighbour(c, x, y, z, -ex, -ey, -ez, &im);
+                    double tp = (g0 + gp[sp]) * nb[sp];
+                    double tm = (g0 + gp[sm]) * nb[sm];
                     double Yp[3], Ym[3];
                     for (int d = 0; d < 3; ++d) {
-                        Yp[d] = fld(vb + (size_t)d * N, sp) - va[d];
-                        Ym[d] = fld(vb + (size_t)d * N, sm) - va[d];
+                        Yp[d] = hc_vel(c, vb, sp, ip, d, N) - va[d];
+                        Ym[d] = hc_vel(c, vb, sm, im, d, N) - va[d];
                     }
                     double pp = tp * ((eh[0] * Yp[0] + eh[1] * Yp[1]) + eh[2] * Yp[2]);
                     double pm = tm * ((eh[0] * Ym[0] + eh[1] * Ym[1]) + eh[2] * Ym[2]);

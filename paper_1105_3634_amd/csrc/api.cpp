@@ -152,6 +152,13 @@ bool build_tables(const mlb_params *p, HostTables &t, std::string &why)
               std::to_string(t.reach[1]) + "," + std::to_string(t.reach[2]) + "); enlarge the box";
         return false;
     }
+    // with walls the hard-core stencils read mirror images of the fluid
+    // beyond a wall: one reflection must land inside the ny - 2 fluid rows
+    if (p->walls_y && std::max(t.shell_reach, t.ball_reach) > p->ny - 2) {
+        why = "walls need at least " + std::to_string(std::max(t.shell_reach, t.ball_reach)) +
+              " fluid rows (the shell reach) between them; enlarge ny";
+        return false;
+    }
     if (t.reach[0] > 127 || t.reach[1] > 127 || t.reach[2] > 127) { why = "stencil too wide"; return false; }
     return true;
 }
@@ -1020,6 +1027,53 @@ mlb_status autotune(Batch &B, const double *const *n0, const double *const *u0, 
     return init_populations<T>(B, n0, u0, st);   // the trial steps changed the state
 }
 
+mlb_status moments_of(Batch &B, int k, void *n_out, void *j_out, hipStream_t st);
+
+// Spectral radii already evaluated, keyed by the parameter block and the
+// densities (tests and ensembles create the same states many times).
+std::mutex g_stab_mu;
+std::map<std::string, double> g_stab_cache;
+
+double cached_radius(const mlb_params *p, const double *n)
+{
+    std::string key(reinterpret_cast<const char *>(p), sizeof(mlb_params));
+    key.append(reinterpret_cast<const char *>(n), sizeof(double) * (size_t)p->nspecies);
+    {
+        std::lock_guard<std::mutex> lk(g_stab_mu);
+        auto it = g_stab_cache.find(key);
+        if (it != g_stab_cache.end()) return it->second;
+    }
+    const double rho = mlb::stability_radius(p, n, 8);
+    std::lock_guard<std::mutex> lk(g_stab_mu);
+    g_stab_cache[key] = rho;
+    return rho;
+}
+
+// The linear-stability guard at every system's box-mean densities (species
+// masses from the float64 sums over the fluid sites).
+mlb_status check_mean_states(Batch &B, hipStream_t st)
+{
+    for (int k = 0; k < B.count; ++k) {
+        SysHost &S = B.sys[k];
+        TRY(moments_of(B, k, nullptr, nullptr, st));
+        double *out = reinterpret_cast<double *>(B.ws + B.red_out);
+        mlb::launch_conserved(B.ws + S.n, B.ws + S.j, B.prec, S.M, S.N, reinterpret_cast<double *>(B.ws + B.red),
+                              kRedParts, out, st);
+        double host[16];
+        HIP_TRY(hipMemcpyAsync(host, out, sizeof(double) * 4 * S.M, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        const double fluid = (double)S.p.nx * S.p.nz * (S.p.walls_y ? S.p.ny - 2 : S.p.ny);
+        double nb[MLB_MAX_SPECIES];
+        for (int a = 0; a < S.M; ++a) nb[a] = host[a] / fluid;
+        const double rho = cached_radius(&S.p, nb);
+        if (!(rho <= 1.0 + 1e-6))
+            return fail(MLB_EUNSTABLE, "system " + std::to_string(k) + ": the scheme is linearly unstable at the box-mean " +
+                                           "densities (spectral radius " + std::to_string(rho) + "); use the " +
+                                           "Crank-Nicolson scheme, or MLB_OPT_NO_STABILITY_CHECK to run anyway");
+    }
+    return MLB_OK;
+}
+
 // no_alloc: no graph replay and no second stream (both allocate), no autotuning.
 template <typename T>
 mlb_status create(Batch &B, const mlb_params *params, int count, void *workspace, size_t bytes,
@@ -1053,6 +1107,7 @@ mlb_status create(Batch &B, const mlb_params *params, int count, void *workspace
     TRY(init_populations<T>(B, n0, u0, st));
     for (auto &S : B.sys) mlb::launch_zero_i32(reinterpret_cast<int *>(B.ws + S.series_cnt), 1, st);
     HIP_TRY(hipStreamSynchronize(st));
+    if (!(options & MLB_OPT_NO_STABILITY_CHECK)) TRY(check_mean_states(B, st));
     const int fixed_shape = (int)((options >> 4) & 15u) - 1, fixed_order = (int)((options >> 8) & 1u);
     if (fixed_shape >= mlb::kTileVariants) return fail(MLB_EINVAL, "MLB_OPT_TILING: no such tile shape");
     if (B.tiled && fixed_shape >= 0) {
@@ -1168,6 +1223,19 @@ mlb_status set_profile(Batch &B, const double *prof, hipStream_t st)
 extern "C" {
 
 size_t mlb_workspace_bytes(const mlb_params *p) { return workspace_for(p, 1); }
+
+mlb_status mlb_check_stability(const mlb_params *p, const double *n_bulk, double *radius)
+{
+    std::string why;
+    if (!validate(p, why)) return fail(MLB_EINVAL, why);
+    if (!n_bulk) return fail(MLB_EINVAL, "n_bulk is NULL");
+    for (int a = 0; a < p->nspecies; ++a)
+        if (!(n_bulk[a] >= 0.0) || !std::isfinite(n_bulk[a])) return fail(MLB_EINVAL, "densities must be >= 0");
+    const double rho = cached_radius(p, n_bulk);
+    if (radius) *radius = rho;
+    if (!(rho <= 1.0 + 1e-6)) return fail(MLB_EUNSTABLE, "spectral radius " + std::to_string(rho) + " > 1");
+    return MLB_OK;
+}
 
 mlb_status mlb_init_mixture_ex(const mlb_params *p, void *workspace, size_t workspace_bytes, const double *n0,
                                const double *u0, uint32_t options, void *stream, mlb_mixture *out)

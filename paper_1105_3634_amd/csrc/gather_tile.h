@@ -154,12 +154,19 @@ __device__ inline TileGeo tile_geo(const SysDesc<float> &S, int local, int R)
 
 // Staging of the halo tile.  Rows (hy, hz) of the tile are numbered
 // row = hy + HY hz; RowOff[row] holds the global site offset of the row's
-// x = 0 site ((gz ny + gy) nx after periodic wrap), or -1 for a row outside
-// the walls.  Thread t owns the halo column hx = t % HX (its wrapped global
+// x = 0 site ((gz ny + gy) nx after periodic wrap) in its low 29 bits and,
+// in bits 29-30, 0 for a fluid row or 1 / 2 for a row beyond the y = 0 /
+// y = ny - 1 wall: the hard-core stencils see there the mirror image of the
+// fluid across the wall plane (y = 1/2 or ny - 3/2), so the offset is that
+// of the mirrored fluid row, and the image moves with the wall (the staging
+// replaces its momentum or velocity by the wall's).  Sites number below
+// 2^29 (checked on the host).  Thread t owns the halo column hx = t % HX (its wrapped global
 // x computed once) and the rows t / HX, t / HX + NT / HX, ... (NT threads per
 // block); consecutive
 // threads read consecutive x, so global loads coalesce, and the per-element
 // work is a table read, an add and the loads.
+constexpr int kRowImgShift = 29, kRowOffMask = (1 << kRowImgShift) - 1;
+
 __device__ inline int wrap_mod(int v, int n)
 {
     v %= n;
@@ -193,12 +200,19 @@ __device__ inline void fill_rows(const SysDesc<float> &S, const TileGeo &t, int 
         if (RowL) RowL[r] = hy * t.HX + hz * t.PXY;
         int gy = t.y0 - t.R + hy;
         const int gz = wrap_mod(t.z0 - t.R + hz, S.nz);
+        int img = 0;
         if (S.walls) {
-            RowOff[r] = (gy >= 0 && gy < S.ny) ? (gz * S.ny + gy) * S.nx : -1;
+            if (gy <= 0) {
+                gy = 1 - gy;
+                img = 1;
+            } else if (gy >= S.ny - 1) {
+                gy = 2 * S.ny - 3 - gy;
+                img = 2;
+            }
         } else {
             gy = wrap_mod(gy, S.ny);
-            RowOff[r] = (gz * S.ny + gy) * S.nx;
         }
+        RowOff[r] = (gz * S.ny + gy) * S.nx | img << kRowImgShift;
     }
 }
 
@@ -214,16 +228,15 @@ __device__ inline void stage(const SysDesc<float> &S, const TileGeo &t, const St
     if (l.rstep == 0) return;
     for (int row = l.row0; row < rows; row += l.rstep) {
         const int ro = RowOff[row];
+        const int img = ro >> kRowImgShift;
         const int i = l.hx + (LM ? RowL[row] : row * t.HX);
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        float g = 0.f;
-        if (ro >= 0) {
-            const unsigned so = (unsigned)(ro + l.gx);
-            v = make_float4(nb[so], vb[so], vb[N + so], vb[2 * N + so]);
-            g = gp[so];
-        }
+        const unsigned so = (unsigned)((ro & kRowOffMask) + l.gx);
+        const float n = nb[so];
+        // an image's momentum density: its density times the wall's velocity
+        const float4 v = img ? make_float4(n, n * S.wall_ux[img - 1], 0.f, 0.f)
+                             : make_float4(n, vb[so], vb[N + so], vb[2 * N + so]);
         lds4[i] = v;
-        ldsg[i] = g;
+        ldsg[i] = gp[so];
     }
 }
 
@@ -239,22 +252,20 @@ __device__ inline void stage_nv(const SysDesc<float> &S, const TileGeo &t, const
     if (l.rstep == 0) return;
     for (int row = l.row0; row < rows; row += l.rstep) {
         const int ro = RowOff[row];
+        const int img = ro >> kRowImgShift;
         const int i = l.hx + (LM ? RowL[row] : row * t.HX);
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (ro >= 0) {
-            const unsigned so = (unsigned)(ro + l.gx);
-            const float n = nb[so];
-            v = make_float4(n * vb[so], n * vb[N + so], n * vb[2 * N + so], gp[so]);
-        }
-        lds4[i] = v;
+        const unsigned so = (unsigned)((ro & kRowOffMask) + l.gx);
+        const float n = nb[so];
+        // an image moves with the wall: n (u_wall, 0, 0)
+        lds4[i] = img ? make_float4(n * S.wall_ux[img - 1], 0.f, 0.f, gp[so])
+                      : make_float4(n * vb[so], n * vb[N + so], n * vb[2 * N + so], gp[so]);
     }
 }
 
-// One scalar field of the halo tile (zero outside the walls; unpadded
-// planes).  The thread's
-// rows go in batches of 8 whose loads are all issued before the first store
-// to LDS (one wait for memory per batch); rows outside the walls read site 0
-// and store zero.
+// One scalar field of the halo tile (rows beyond a wall take the mirrored
+// fluid row; unpadded planes).  The thread's rows go in batches of 8 whose
+// loads are all issued before the first store to LDS (one wait for memory
+// per batch).
 __device__ inline void stage1(const TileGeo &t, const StageLane &l, const int *RowOff, float *dst,
                               const gfloat *__restrict__ src)
 {
@@ -266,9 +277,7 @@ __device__ inline void stage1(const TileGeo &t, const StageLane &l, const int *R
 #pragma unroll
         for (int k = 0; k < B; ++k) {
             const int row = row0 + k * l.rstep;
-            const int ro = row < rows ? RowOff[row] : -1;
-            const float x = src[ro >= 0 ? (unsigned)(ro + l.gx) : 0u];
-            v[k] = ro >= 0 ? x : 0.f;
+            v[k] = src[row < rows ? (unsigned)((RowOff[row] & kRowOffMask) + l.gx) : 0u];
         }
 #pragma unroll
         for (int k = 0; k < B; ++k) {

@@ -83,6 +83,37 @@ __device__ inline T ld(const T *__restrict__ F, long long s)
     return s < 0 ? T(0) : F[s];
 }
 
+// r + e as the hard-core stencils (smoothing balls, mean-field and friction
+// shells) see it: the site itself in a periodic box and inside the fluid
+// rows; beyond a wall (y + e_y <= 0 or >= ny - 1) the mirror image of the
+// fluid across the nearer wall plane (y = 1/2 or y = ny - 3/2, where halfway
+// bounce-back puts the walls), which carries that fluid site's density and
+// contact value and moves with the wall.  img: 0 fluid, 1 image beyond the
+// y = 0 wall, 2 beyond the y = ny - 1 wall.  The host checks that the shell
+// reach stays inside the fluid rows, so one reflection suffices.
+template <typename T>
+__device__ inline long long hc_nbr(const SysDesc<T> &S, const Site &r, int ex, int ey, int ez, int &img)
+{
+    int xx = r.x + ex;
+    xx = xx < 0 ? xx + S.nx : (xx >= S.nx ? xx - S.nx : xx);
+    int zz = r.z + ez;
+    zz = zz < 0 ? zz + S.nz : (zz >= S.nz ? zz - S.nz : zz);
+    int yy = r.y + ey;
+    img = 0;
+    if (S.walls) {
+        if (yy <= 0) {
+            yy = 1 - yy;
+            img = 1;
+        } else if (yy >= S.ny - 1) {
+            yy = 2 * S.ny - 3 - yy;
+            img = 2;
+        }
+    } else {
+        yy = yy < 0 ? yy + S.ny : (yy >= S.ny ? yy - S.ny : yy);
+    }
+    return ((long long)zz * S.ny + yy) * S.nx + xx;
+}
+
 __device__ inline int pidx(int M, int a, int b)
 {
     const int lo = a < b ? a : b, hi = a < b ? b : a;
@@ -161,8 +192,9 @@ __global__ void __launch_bounds__(kBlock) k_contact(const SysDesc<T> *__restrict
         for (int k = 0; k < bn; ++k) {
             int ex, ey, ez;
             unpack_offset(tb.bl_e[b0 + k], ex, ey, ez);
-            const long long sp = nbr(S, r, ex, ey, ez), sm = nbr(S, r, -ex, -ey, -ez);
-            acc = acc + (ld(nc, sp) + ld(nc, sm));
+            int ip, im;
+            const long long sp = hc_nbr(S, r, ex, ey, ez, ip), sm = hc_nbr(S, r, -ex, -ey, -ez, im);
+            acc = acc + (nc[sp] + nc[sm]);
         }
         nb[c] = acc / (T)S.bl_full[c];
     }
@@ -225,21 +257,29 @@ __global__ void __launch_bounds__(kBlock) k_gather1(const SysDesc<T> *__restrict
             unpack_offset(tb.sh_e[k0 + k], ex, ey, ez);
             const T e0 = tb.sh_u[3 * (k0 + k) + 0], e1 = tb.sh_u[3 * (k0 + k) + 1],
                     e2 = tb.sh_u[3 * (k0 + k) + 2];
-            const long long sp = nbr(S, r, ex, ey, ez), sm = nbr(S, r, -ex, -ey, -ez);
-            const T Gp = g0 + ld(gp, sp), Gm = g0 + ld(gp, sm);
-            const T np_ = ld(nb, sp), nm_ = ld(nb, sm);
+            int ip, im;
+            const long long sp = hc_nbr(S, r, ex, ey, ez, ip), sm = hc_nbr(S, r, -ex, -ey, -ez, im);
+            const T Gp = g0 + gp[sp], Gm = g0 + gp[sm];
+            const T np_ = nb[sp], nm_ = nb[sm];
             const T tp = Gp * np_, tm = Gm * nm_;
             const T dt = tp - tm;
             smf[0] = smf[0] + e0 * dt;
             smf[1] = smf[1] + e1 * dt;
             smf[2] = smf[2] + e2 * dt;
             sg = sg + (tp + tm);
-            const T Xp0 = na * ld(jb, sp) - np_ * ja[0];
-            const T Xp1 = na * ld(jb + N, sp) - np_ * ja[1];
-            const T Xp2 = na * ld(jb + 2 * N, sp) - np_ * ja[2];
-            const T Xm0 = na * ld(jb, sm) - nm_ * ja[0];
-            const T Xm1 = na * ld(jb + N, sm) - nm_ * ja[1];
-            const T Xm2 = na * ld(jb + 2 * N, sm) - nm_ * ja[2];
+            // an image's momentum density: its density times the wall's velocity
+            const T jp0 = ip ? np_ * S.wall_ux[ip - 1] : jb[sp];
+            const T jp1 = ip ? np_ * T(0) : jb[N + sp];
+            const T jp2 = ip ? np_ * T(0) : jb[2 * N + sp];
+            const T jm0 = im ? nm_ * S.wall_ux[im - 1] : jb[sm];
+            const T jm1 = im ? nm_ * T(0) : jb[N + sm];
+            const T jm2 = im ? nm_ * T(0) : jb[2 * N + sm];
+            const T Xp0 = na * jp0 - np_ * ja[0];
+            const T Xp1 = na * jp1 - np_ * ja[1];
+            const T Xp2 = na * jp2 - np_ * ja[2];
+            const T Xm0 = na * jm0 - nm_ * ja[0];
+            const T Xm1 = na * jm1 - nm_ * ja[1];
+            const T Xm2 = na * jm2 - nm_ * ja[2];
             const T pp = Gp * ((e0 * Xp0 + e1 * Xp1) + e2 * Xp2);
             const T pm = Gm * ((e0 * Xm0 + e1 * Xm1) + e2 * Xm2);
             const T pq = pp + pm;
@@ -365,11 +405,17 @@ __global__ void __launch_bounds__(kBlock) k_step2(const SysDesc<T> *__restrict__
                 unpack_offset(tb.sh_e[k0 + k], ex, ey, ez);
                 const T e0 = tb.sh_u[3 * (k0 + k) + 0], e1 = tb.sh_u[3 * (k0 + k) + 1],
                         e2 = tb.sh_u[3 * (k0 + k) + 2];
-                const long long sp = nbr(S, r, ex, ey, ez), sm = nbr(S, r, -ex, -ey, -ez);
-                const T tp = (g0 + ld(gp, sp)) * ld(nb, sp);
-                const T tm = (g0 + ld(gp, sm)) * ld(nb, sm);
-                const T Yp0 = ld(vb, sp) - va[0], Yp1 = ld(vb + N, sp) - va[1], Yp2 = ld(vb + 2 * N, sp) - va[2];
-                const T Ym0 = ld(vb, sm) - va[0], Ym1 = ld(vb + N, sm) - va[1], Ym2 = ld(vb + 2 * N, sm) - va[2];
+                int ip, im;
+                const long long sp = hc_nbr(S, r, ex, ey, ez, ip), sm = hc_nbr(S, r, -ex, -ey, -ez, im);
+                const T tp = (g0 + gp[sp]) * nb[sp];
+                const T tm = (g0 + gp[sm]) * nb[sm];
+                // an image moves with the wall: (u_wall, 0, 0)
+                const T Yp0 = (ip ? S.wall_ux[ip - 1] : vb[sp]) - va[0];
+                const T Yp1 = (ip ? T(0) : vb[N + sp]) - va[1];
+                const T Yp2 = (ip ? T(0) : vb[2 * N + sp]) - va[2];
+                const T Ym0 = (im ? S.wall_ux[im - 1] : vb[sm]) - va[0];
+                const T Ym1 = (im ? T(0) : vb[N + sm]) - va[1];
+                const T Ym2 = (im ? T(0) : vb[2 * N + sm]) - va[2];
                 const T pp = tp * ((e0 * Yp0 + e1 * Yp1) + e2 * Yp2);
                 const T pm = tm * ((e0 * Ym0 + e1 * Ym1) + e2 * Ym2);
                 const T pq = pp + pm;

@@ -4,9 +4,10 @@ ensemble workloads (calls only the oracle and the seeded workloads).
 taylor_couette_256x64x16_5.json: the ternary mixture between moving walls
   (256x64x16, sigma 2, 3, 4, packing 0.25, eps/kT = 0.3 with cutoff 2.5
   sigma, walls at y = 0 and 63 moving at -+0.05, tracer band of species 3)
-  advanced 5 steps by the ordered oracle step (direct attractive sum, walls
-  as solid layers); species densities at 4096 seeded sites, the field max
-  norms and the species masses.
+  advanced by the ordered oracle step (direct attractive sum; beyond a wall
+  the hard-core stencils see the mirrored fluid moving with the wall, the
+  attractive field sees nothing); species densities at 4096 seeded sites,
+  the field max norms and the species masses.
 closure_physics_192x64x64_5.json: the learned-closure workload's plain
   path (binary, sigma 2 and 3, packing 0.2, composition mode along x,
   192x64x64), 5 oracle steps; densities at 4096 seeded sites.

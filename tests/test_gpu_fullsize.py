@@ -68,7 +68,7 @@ def test_d12_from_mode_decay(golden):
 # Taylor/Couette (256x64x16 ternary, moving walls, tail) and the 64-system
 # ensemble at full size against float64 oracle references written by
 # tests/golden/make_fullsize_goldens.py (oracle only).
-TAYLOR = os.path.join(os.path.dirname(__file__), "golden", "taylor_couette_256x64x16_5.json")
+TAYLOR = os.path.join(os.path.dirname(__file__), "golden", "taylor_couette_256x64x16_20.json")
 ENSEMBLE = os.path.join(os.path.dirname(__file__), "golden", "ensemble_64_members_20.json")
 
 
@@ -77,9 +77,10 @@ def _load(path):
         return json.load(fh)
 
 
-def test_taylor_couette_float64_bit_exact_5_steps():
+def test_taylor_couette_float64_bit_exact_20_steps():
     """Float64 follows the oracle's operation order: the sampled densities
-    after 5 steps are equal bit for bit (walls, moving walls, direct tail)."""
+    after 20 steps are equal bit for bit (moving walls with the mirrored
+    hard-core images, direct tail) at the workload's packing 0.25."""
     import paper_1105_3634_amd as mlb
     ref = _load(TAYLOR)
     m, n0, u0 = W.config_taylor_couette()
@@ -94,7 +95,7 @@ def test_taylor_couette_float64_bit_exact_5_steps():
         assert n[a].sum() == pytest.approx(ref["mass"][a], rel=1e-13)
 
 
-def test_taylor_couette_float32_5_steps():
+def test_taylor_couette_float32_20_steps():
     """Float32 with the spectral field on the y-padded transform (tiled
     gathers): sampled densities within 1e-5 of the field's max norm."""
     import paper_1105_3634_amd as mlb
@@ -155,3 +156,34 @@ def test_closure_workload_plain_path_float32_5_steps():
         print(f"  species {a}: fp32 rel err {err:.2e}", flush=True)
         assert err < 1e-5
         np.testing.assert_allclose(n[a].sum(), ref["mass"][a], rtol=1e-5)
+
+
+COUETTE = os.path.join(os.path.dirname(__file__), "golden", "taylor_couette_64x24x12_600.json")
+
+
+def test_couette_tracer_dispersion_against_oracle():
+    """The Taylor/Couette physics at packing 0.25 on 64x24x12, float32 with the
+    spectral field on the y-padded transform: the tracer's section-averaged
+    mode recorded every 10 steps for 600 steps against the oracle's series
+    (1e-4 of the first amplitude), and the library's D_eff fit against the
+    oracle's within 2 %."""
+    import paper_1105_3634_amd as mlb
+    ref = _load(COUETTE)
+    m, n0, u0 = W.config_taylor_couette(64, 24, 12)
+    print(f"[couette D_eff] shape={m.shape()} steps={ref['steps']}", flush=True)
+    g = mlb.GpuMixture(m, n0, u0, precision=32, device="cuda:0")
+    g.reset_series()
+    for t in range(0, ref["steps"] + 1, ref["every"]):
+        g.record_mode(2, -1)
+        if t < ref["steps"]:
+            g.step(ref["every"])
+    t, v = g.series()
+    amp = np.array(ref["amplitude"])
+    assert np.array_equal(t, np.array(ref["t"]))
+    err = np.abs(v - amp).max() / amp[0]
+    fit = g.fit_ex(0, ref["fit_t_min"])
+    print(f"  series rel err {err:.2e}; D_eff {fit['D']:.6f} oracle {ref['D_eff']:.6f}", flush=True)
+    assert err < 1e-4
+    assert abs(fit["D"] / ref["D_eff"] - 1) < 0.02
+    mass = g.conserved()[0]
+    np.testing.assert_allclose(mass, ref["mass"], rtol=1e-5)

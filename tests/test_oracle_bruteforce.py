@@ -8,6 +8,9 @@ rules alone, on grids small enough for O(N^2):
   drag + viscous pair form     eqs. (gammaab), (tensorgamma), (viscousforce)
   friction rate, predictor, corrector, the BMCSL contact values of
   ball-smoothed packing fractions.
+In a walled box the hard-core sums (balls, shells) also run over the mirror
+images of the fluid across the wall planes, which move with the walls; the
+attractive field runs over the fluid only.
 """
 import math
 
@@ -23,15 +26,33 @@ CV = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1
 
 
 def _pairs(m):
+    """Displacements from every target site to every source point.  In a
+    periodic box the sources are the sites (minimum image).  In a walled box
+    they are the fluid sites plus their mirror images across the wall planes
+    y = 1/2 and y = ny - 3/2 (the hard-core stencils' view beyond a wall);
+    `img` is 0 for a fluid source, 1 / 2 for an image beyond the y = 0 /
+    y = ny - 1 wall, `src` the fluid site a source takes its fields from."""
     z, y, x = np.meshgrid(np.arange(m.nz), np.arange(m.ny), np.arange(m.nx), indexing="ij")
     P = np.stack([x.ravel(), y.ravel(), z.ravel()], 1)
-    E = P[None, :, :] - P[:, None, :]          # E[s, s'] = r' - r
+    N = len(P)
+    if m.walls_y:
+        fluid = np.flatnonzero((P[:, 1] > 0) & (P[:, 1] < m.ny - 1))
+        lo = P[fluid].copy()
+        lo[:, 1] = 1 - lo[:, 1]
+        hi = P[fluid].copy()
+        hi[:, 1] = 2 * m.ny - 3 - hi[:, 1]
+        Q = np.concatenate([P[fluid], lo, hi])
+        src = np.concatenate([fluid, fluid, fluid])
+        img = np.concatenate([np.zeros(len(fluid), int), np.ones(len(fluid), int), 2 * np.ones(len(fluid), int)])
+    else:
+        Q, src, img = P, np.arange(N), np.zeros(N, int)
+    E = Q[None, :, :] - P[:, None, :]          # E[s, q] = r_q - r_s
     for d, L in ((0, m.nx), (2, m.nz)):
         E[..., d] = (E[..., d] + L // 2) % L - L // 2
     if not m.walls_y:
         E[..., 1] = (E[..., 1] + m.ny // 2) % m.ny - m.ny // 2
     R2 = (E ** 2).sum(-1)
-    return E.astype(float), R2, P
+    return E.astype(float), R2, P, src, img
 
 
 def _ball_count(R):
@@ -46,16 +67,25 @@ def brute_force(m, f):
     fl = f.reshape(M, 19, N)
     n = fl.sum(1)
     j = np.einsum("aiN,id->adN", fl, CV)
-    E, R2, P = _pairs(m)
+    E, R2, P, src, img = _pairs(m)
     solid = np.zeros(N, bool)
     if m.walls_y:
         solid = (P[:, 1] == 0) | (P[:, 1] == m.ny - 1)
     sig = m.sigma
+    # fields at the sources: an image has its fluid site's density and contact
+    # value and the wall's velocity
+    ns = n[:, src]
+    js = j[:, :, src].copy()
+    wall_u = np.zeros((len(src), 3))
+    for k, uw in ((1, m.wall_ux[0]), (2, m.wall_ux[1])):
+        wall_u[img == k, 0] = uw
+    js[:, :, img > 0] = ns[:, None, img > 0] * wall_u.T[None, :, img > 0]
+    fluid_src = (img == 0).astype(float)
     # smoothed densities and contact values
     nbar = np.zeros((M, N))
     for c in range(M):
         R = sig[c] / 2
-        nbar[c] = ((R2 <= R * R) * n[c][None, :]).sum(1) / _ball_count(R)
+        nbar[c] = ((R2 <= R * R) * ns[c][None, :]).sum(1) / _ball_count(R)
     x2 = sum(math.pi / 6 * sig[c] ** 2 * nbar[c] for c in range(M))
     x3 = sum(math.pi / 6 * sig[c] ** 3 * nbar[c] for c in range(M))
     g = {}
@@ -83,18 +113,19 @@ def brute_force(m, f):
             count = int(((rr >= (sab - 0.5) ** 2) & (rr < (sab + 0.5) ** 2)).sum())
             what = 4 * math.pi / count
             kap = 2 * sab ** 2 * math.sqrt(2 * 0.5 * KT / math.pi) * what
-            G = 0.5 * (g[a, b][:, None] + g[a, b][None, :]) * S
+            G = 0.5 * (g[a, b][:, None] + g[a, b][src][None, :]) * S
             shells[a, b] = (G, kap)
-            out["Nmf"][a] += -KT * sab ** 2 * what * n[a][None, :] * np.einsum("sr,srd->ds", G * n[b][None, :], Eh)
-            gam[a] += kap / 3 * (G * n[b][None, :]).sum(1)
-            X_ = n[a][:, None, None] * j[b].T[None, :, :] - n[b][None, :, None] * j[a].T[:, None, :]
+            out["Nmf"][a] += -KT * sab ** 2 * what * n[a][None, :] * np.einsum("sr,srd->ds", G * ns[b][None, :], Eh)
+            gam[a] += kap / 3 * (G * ns[b][None, :]).sum(1)
+            X_ = n[a][:, None, None] * js[b].T[None, :, :] - ns[b][None, :, None] * j[a].T[:, None, :]
             proj = (Eh * X_).sum(-1)
             out["Dold"][a] += kap * np.einsum("sr,srd->ds", G * proj, Eh)
             if eps[a, b] != 0:
-                T = (R2 > sab ** 2) & (R2 <= (m.rc_factor * sab) ** 2)
+                # the attractive field sees the fluid only (no images)
+                T = (R2 > sab ** 2) & (R2 <= (m.rc_factor * sab) ** 2) & (fluid_src[None, :] > 0)
                 with np.errstate(divide="ignore"):
                     Up = np.where(T, 6 * eps[a, b] * sab ** 6 / np.where(R2 > 0, R2, 1) ** 3.5, 0.0)
-                out["Ntail"][a] += n[a][None, :] * np.einsum("sr,srd->ds", Up * n[b][None, :], Eh)
+                out["Ntail"][a] += n[a][None, :] * np.einsum("sr,srd->ds", Up * ns[b][None, :], Eh)
     fx = m.fext_matrix()
     Next = n[:, None, :] * fx[:, :, None]
     Nc = out["Nmf"] + out["Ntail"] + Next
@@ -104,12 +135,14 @@ def brute_force(m, f):
                      / (n[:, None, :] * (1 + hg[:, None, :])), 0.0)
     H = Nc + 0.5 * out["Dold"]
     Dnew = np.zeros((M, 3, N))
+    Vs = V[:, :, src].copy()
+    Vs[:, :, img > 0] = wall_u.T[None, :, img > 0]
     for a in range(M):
         for b in range(M):
             G, kap = shells[a, b]
-            Y_ = V[b].T[None, :, :] - V[a].T[:, None, :]
+            Y_ = Vs[b].T[None, :, :] - V[a].T[:, None, :]
             proj = (Eh * Y_).sum(-1)
-            Dnew[a] += kap * n[a][None, :] * np.einsum("sr,srd->ds", G * n[b][None, :] * proj, Eh)
+            Dnew[a] += kap * n[a][None, :] * np.einsum("sr,srd->ds", G * ns[b][None, :] * proj, Eh)
     Nf = H + 0.5 * Dnew
     for k in ("Nmf", "Ntail", "Dold"):
         out[k][:, :, solid] = 0
@@ -156,6 +189,13 @@ def test_bruteforce_ternary_tail_external(oracle_lib):
 def test_bruteforce_walls(oracle_lib):
     m = W.Mixture(8, 9, 8, sigma=(2.0, 3.0), walls_y=True, wall_ux=(-0.03, 0.04))
     n0, u0 = W.random_state(m, [0.012, 0.009], rel=0.4, u_amp=0.03, seed=13)
+    _compare(oracle_lib, m, n0, u0)
+
+
+def test_bruteforce_walls_with_tail(oracle_lib):
+    eps = np.array([[0.1, 0.07], [0.07, 0.05]])
+    m = W.Mixture(10, 10, 10, sigma=(2.0, 2.5), eps=eps, rc_factor=1.6, walls_y=True, wall_ux=(0.02, -0.05))
+    n0, u0 = W.random_state(m, [0.014, 0.009], rel=0.4, u_amp=0.03, seed=15)
     _compare(oracle_lib, m, n0, u0)
 
 
