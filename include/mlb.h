@@ -61,6 +61,7 @@ typedef enum {
     MLB_EINVAL = -1,       /* invalid argument or parameter set                   */
     MLB_ENOMEM = -2,       /* workspace smaller than mlb_workspace_bytes()         */
     MLB_EHIP = -3,         /* a HIP runtime call failed                            */
+    MLB_EUNSTABLE = -4,    /* the scheme is linearly unstable at the given state    */
     MLB_ENONFINITE = -5,   /* a conserved sum is not finite                        */
     MLB_ESTATE = -6,       /* call not valid in the handle's current state        */
     MLB_EUNSUPPORTED = -7  /* option not available for this precision or geometry */
@@ -69,7 +70,9 @@ typedef enum {
 enum { MLB_SCHEME_CN_J1 = 0, MLB_SCHEME_FE = 1 };
 enum { MLB_TAIL_AUTO = 0, MLB_TAIL_DIRECT = 1, MLB_TAIL_SPECTRAL = 2 };
 enum { MLB_OPT_TUNE = 1u,       /* time every tile shape and block order at init, keep the fastest */
-       MLB_OPT_NO_GRAPH = 2u }; /* launch the passes eagerly instead of replaying a graph */
+       MLB_OPT_NO_GRAPH = 2u,   /* launch the passes eagerly instead of replaying a graph */
+       MLB_OPT_NO_STABILITY_CHECK = 512u }; /* skip the linear-stability guard at init (studies of
+                                           unstable schemes) */
 /* Fixed float32 tiling instead of the default or tuned one (overrides
  * MLB_OPT_TUNE): tile shape 0 = 16x4x4, 1 = 8x8x4, 2 = 32x4x2 sites; block
  * order 0 = linear, 1 = XCD-chunked.  Reproducible profiles use it. */
@@ -146,6 +149,22 @@ mlb_status mlb_init_mixture_ex(const mlb_params *p, void *workspace, size_t work
 #define MLB_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
 mlb_status mlb_init_mixture_static(const mlb_params *p, const double *n0, const double *u0, void *stream,
                                    mlb_mixture *out);
+
+/* Linear stability of the step at uniform species densities n_bulk (HOST
+ * float64 [M]) with velocities zero: the spectral radius of the step
+ * linearised around that state (contact values, mean field, attractive
+ * field, the dissipative pair form of eqs. gammaab, tensorgamma and
+ * viscousforce under the chosen time scheme, collision and streaming) over
+ * the wavevectors k = pi (i, j, l) / 4, i, j, l = 0..4, k = 0 excluded
+ * (power iteration on the 19 M populations).  radius (HOST, may be NULL)
+ * receives it.  MLB_EUNSTABLE if it exceeds 1 + 1e-6: the forward-Euler
+ * friction grows once the friction rate per step is of order one.  Host
+ * only; lattice size and walls do not enter.  mlb_init_mixture, _ex,
+ * _static and mlb_init_batch run this guard on every system at its
+ * box-mean densities (fluid sites) unless MLB_OPT_NO_STABILITY_CHECK is
+ * given; states denser than the mean (e.g. a composition step) can still
+ * be unstable where the mean is not. */
+mlb_status mlb_check_stability(const mlb_params *p, const double *n_bulk, double *radius);
 
 /* Tile shape and block order in use (see mlb_batch_tuning). */
 mlb_status mlb_tuning(mlb_mixture h, int32_t *shape, int32_t *order, double *trial_ms);

@@ -17,7 +17,7 @@ Q = 19
 NPASS = 6
 
 MLB_OK = 0
-STATUS = {0: "MLB_OK", -1: "MLB_EINVAL", -2: "MLB_ENOMEM", -3: "MLB_EHIP", -5: "MLB_ENONFINITE",
+STATUS = {0: "MLB_OK", -1: "MLB_EINVAL", -2: "MLB_ENOMEM", -3: "MLB_EHIP", -4: "MLB_EUNSTABLE", -5: "MLB_ENONFINITE",
           -6: "MLB_ESTATE", -7: "MLB_EUNSUPPORTED"}
 
 SCHEME_CN_J1, SCHEME_FE = 0, 1
@@ -55,6 +55,7 @@ _SIGS = [
                                       C.c_uint32, C.c_void_p, C.POINTER(C.c_void_p)]),
     ("mlb_init_mixture_static", C.c_int, [C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_void_p,
                                           C.POINTER(C.c_void_p)]),
+    ("mlb_check_stability", C.c_int, [C.POINTER(Params), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("mlb_tuning", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     ("mlb_step", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     ("mlb_moments", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -113,7 +114,7 @@ _SIGS = [
     ("mlb_closure_usage", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     ("mlb_closure_sample", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
 ]
-OPT_TUNE, OPT_NO_GRAPH = 1, 2
+OPT_TUNE, OPT_NO_GRAPH, OPT_NO_STABILITY_CHECK = 1, 2, 512
 STATIC_WORKSPACE_BYTES = 64 << 20   # MLB_STATIC_WORKSPACE_BYTES
 
 

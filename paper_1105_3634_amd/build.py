@@ -35,6 +35,7 @@ UNITS = [
     ("closure.cpp", ["-ffp-contract=off", "-x", "hip"]),
     ("tables.cpp", ["-ffp-contract=off", "-x", "hip"]),
     ("api.cpp", ["-ffp-contract=off", "-x", "hip"]),
+    ("stability.cpp", ["-ffp-contract=off"]),
 ]
 
 

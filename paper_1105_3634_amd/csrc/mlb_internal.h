@@ -10,6 +10,8 @@
 #include <string>
 #include <vector>
 
+#include "../../include/mlb.h"
+
 namespace mlb {
 
 constexpr int kMaxS = 4;
@@ -87,6 +89,10 @@ struct HostStencil {
 
 enum { kShell = 0, kBall = 1, kTail = 2 };
 HostStencil build_stencil(int kind, double s, double rc);
+
+// Spectral radius of the linearised step at uniform densities n0 (host
+// float64) over the wavevectors pi (i, j, l) / kgrid, k = 0 excluded.
+double stability_radius(const mlb_params *p, const double *n0, int kgrid);
 
 struct PairConst {
     double cm, cg, ck, dd;

@@ -156,3 +156,39 @@ def test_network_sizes():
     assert lib.mlb_net_param_count() == 67392 + 102
     assert lib.mlb_net_workspace_bytes(0, 8, 8, 0) == 0
     assert lib.mlb_net_workspace_bytes(8, 8, 8, 1) > lib.mlb_net_workspace_bytes(8, 8, 8, 0) > 0
+
+
+def _stability(sigma, n, scheme, tau=1.0, eps=None):
+    import ctypes as C
+    import paper_1105_3634_amd as mlb
+    from paper_1105_3634_amd import _lib
+    lib = _lib.load()
+    m = W.Mixture(16, 16, 16, sigma=sigma, tau=tau, scheme=scheme, eps=eps)
+    p = mlb.make_params(m, 64)
+    r = C.c_double()
+    st = lib.mlb_check_stability(C.byref(p), (C.c_double * len(sigma))(*n), C.byref(r))
+    return st, r.value
+
+
+def test_stability_guard_flags_forward_euler_friction():
+    """Host-side linear stability at uniform states: the forward-Euler
+    friction grows where the friction rate per step is of order one (the
+    dense corner of the ensemble's draws, the pure sigma = 3 half of the
+    step binary, the bulk-diffusion state), Crank-Nicolson with one Jacobi
+    predictor does not; a dilute forward-Euler state with tau = 0.8 is
+    stable."""
+    n = W.number_density(0.35, (0.9, 0.1), (2.0, 4.0))
+    st, r = _stability((2.0, 4.0), [0.9 * n, 0.1 * n], W.SCHEME_FE)
+    assert st == -4 and r > 3.0
+    st, r = _stability((2.0, 4.0), [0.9 * n, 0.1 * n], W.SCHEME_CN_J1)
+    assert st == 0 and r < 1.0
+    n = W.number_density(0.2, (0.5, 0.5), (2.0, 3.0))
+    st, r = _stability((2.0, 3.0), [0.0, n], W.SCHEME_FE)
+    assert st == -4 and 1.2 < r < 1.4
+    assert _stability((2.0, 3.0), [0.0, n], W.SCHEME_CN_J1)[0] == 0
+    n = W.number_density(0.3, (0.5, 0.5), (3.0, 4.5))
+    eps = np.full((2, 2), 0.5 / 3.0)
+    st, r = _stability((3.0, 4.5), [n / 2, n / 2], W.SCHEME_FE, eps=eps)
+    assert st == -4 and 1.0 < r < 1.05
+    assert _stability((3.0, 4.5), [n / 2, n / 2], W.SCHEME_CN_J1, eps=eps)[0] == 0
+    assert _stability((2.0, 2.5), [0.006, 0.004], W.SCHEME_FE, tau=0.8)[0] == 0
