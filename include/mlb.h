@@ -383,6 +383,19 @@ mlb_status mlb_net_forward(mlb_net net, const float *x, float *y, void *stream);
  * otherwise). */
 mlb_status mlb_net_train_step(mlb_net net, const float *x, const float *target, float lr, float loss_weight,
                               int32_t update, double *loss, float *grads, void *stream);
+/* Statistics of a training pool of `count` samples, x [count][8][N] and
+ * targets t [count][6][N] (DEVICE float32, channel-first): out (HOST,
+ * count + 1 doubles) receives out[0] = the mean square of the momentum
+ * channels 2..7 of x over the pool and out[1 + s] = the mean square of
+ * target s (float64 sums).  Synchronises. */
+mlb_status mlb_net_pool_stats(mlb_net net, const float *x, const float *t, int32_t count, double *out, void *stream);
+/* In place on the same pool: x's momentum channels divided by j_div, the
+ * targets by f_div (both > 0). */
+mlb_status mlb_net_pool_rescale(mlb_net net, float *x, float *t, int32_t count, double j_div, double f_div,
+                                void *stream);
+/* err (HOST) = ||y - t||_2 / ||t||_2 over [6][N] DEVICE float32 arrays of the
+ * net's grid, float64 sums (the closure check's measure).  Synchronises. */
+mlb_status mlb_net_rel_error(mlb_net net, const float *y, const float *t, double *err, void *stream);
 /* Adam steps taken since the last mlb_net_set_params. */
 int32_t mlb_net_adam_steps(mlb_net net);
 mlb_status mlb_net_destroy(mlb_net net);

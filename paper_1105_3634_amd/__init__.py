@@ -467,6 +467,33 @@ class GpuNet:
                                             _stream_handle(self.stream)), "mlb_net_forward")
         return y
 
+    def pool_stats(self, x, t):
+        """(mean square of the momentum channels of x over the pool, [mean square
+        of each target]) for a pool x [S][8][...], t [S][6][...] (mlb_net_pool_stats)."""
+        S = int(x.shape[0])
+        assert x.is_contiguous() and t.is_contiguous() and x.numel() == S * 8 * self.N and t.numel() == S * 6 * self.N
+        out = (C.c_double * (S + 1))()
+        _lib.check(self.lib.mlb_net_pool_stats(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()), S, out,
+                                               _stream_handle(self.stream)), "mlb_net_pool_stats")
+        return float(out[0]), [float(v) for v in out[1:]]
+
+    def pool_rescale(self, x, t, j_div: float, f_div: float) -> None:
+        """In place: x's momentum channels / j_div, t / f_div (mlb_net_pool_rescale)."""
+        S = int(x.shape[0])
+        assert x.is_contiguous() and t.is_contiguous() and x.numel() == S * 8 * self.N and t.numel() == S * 6 * self.N
+        _lib.check(self.lib.mlb_net_pool_rescale(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()), S,
+                                                 float(j_div), float(f_div), _stream_handle(self.stream)),
+                   "mlb_net_pool_rescale")
+
+    def rel_error(self, y, t) -> float:
+        """||y - t|| / ||t|| over [6][...] float32 device tensors (mlb_net_rel_error)."""
+        y = self._dev(y, 6)
+        t = self._dev(t, 6)
+        err = C.c_double()
+        _lib.check(self.lib.mlb_net_rel_error(self.h, C.c_void_p(y.data_ptr()), C.c_void_p(t.data_ptr()),
+                                              C.byref(err), _stream_handle(self.stream)), "mlb_net_rel_error")
+        return float(err.value)
+
     def train_step(self, x, target, lr: float = 1e-3, update: bool = True, want_loss: bool = True,
                    want_grads: bool = False, loss_weight: float = 1.0):
         """One Adam step on loss_weight x MSE; returns (loss before the update or None, gradients or None)."""

@@ -106,6 +106,11 @@ _SIGS = [
     ("mlb_net_forward", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("mlb_net_train_step", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_float, C.c_float, C.c_int32,
                                      C.POINTER(C.c_double), C.POINTER(C.c_float), C.c_void_p]),
+    ("mlb_net_pool_stats", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_double),
+                                     C.c_void_p]),
+    ("mlb_net_pool_rescale", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_double,
+                                       C.c_void_p]),
+    ("mlb_net_rel_error", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
     ("mlb_net_adam_steps", C.c_int32, [C.c_void_p]),
     ("mlb_net_destroy", C.c_int, [C.c_void_p]),
     ("mlb_set_closure", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_double]),

@@ -11,7 +11,10 @@ checks use).
 
 The scales fix the network's units: n_ref is the mean species density of
 the first state, j_ref and f_ref are the RMS momentum density and force
-over the pool, so inputs and targets are O(1).
+over the pool, so inputs and targets are O(1).  The pool's sums, its
+rescaling and the error measure run in the library (mlb_net_pool_stats,
+mlb_net_pool_rescale, mlb_net_rel_error); this module only sequences calls
+and keeps the pool's device tensors.
 """
 from __future__ import annotations
 
@@ -76,7 +79,9 @@ def fit(net: GpuNet, x, t, epochs: int, lr: float = 1e-3, lr_final: float = 1e-5
     S = x.shape[0]
     total = epochs * S
     decay = (lr_final / lr) ** (1.0 / max(1, total - 1))
-    wts = (1.0 / t.double().pow(2).flatten(1).mean(dim=1).clamp_min(1e-300)).tolist()
+    # each pair's loss is divided by its target's mean square (library sums)
+    _, target_ms = net.pool_stats(x, t)
+    wts = [1.0 / max(v, 1e-300) for v in target_ms]
     rng = np.random.Generator(np.random.PCG64(seed))
     losses = []
     k = 0
@@ -103,10 +108,10 @@ def train_closure(net: GpuNet, states: Sequence[Callable[[], tuple]], per_state:
     n_ref = float(np.mean(n0))
     x, t = collect(net, states, per_state, sample_every, n_ref, device)
     t1 = time.perf_counter()
-    j_ref = max(float(x[:, 2:].double().pow(2).mean().sqrt().item()), 1e-30)
-    f_ref = max(float(t.double().pow(2).mean().sqrt().item()), 1e-30)
-    x[:, 2:] /= j_ref
-    t /= f_ref
+    j_ms, t_ms = net.pool_stats(x, t)
+    j_ref = max(math.sqrt(j_ms), 1e-30)
+    f_ref = max(math.sqrt(sum(t_ms) / len(t_ms)), 1e-30)
+    net.pool_rescale(x, t, j_ref, f_ref)
     scales = (n_ref, j_ref, f_ref)
     net.set_scales(*scales)
     losses = fit(net, x, t, epochs, lr, lr_final, seed, log_every, log)
@@ -118,5 +123,4 @@ def closure_error(net: GpuNet, g: GpuMixture) -> float:
     """Relative L2 error of the network's force against the exact force in the
     current state of mixture `g` (same grid as `net`)."""
     x, t = g.closure_sample(net)
-    y = net.forward(x)
-    return float((y.double() - t.double()).norm().item() / t.double().norm().item())
+    return net.rel_error(net.forward(x), t)

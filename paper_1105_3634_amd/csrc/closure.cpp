@@ -28,7 +28,7 @@ struct mlb_net_s {
         int nw, cop, cip, cout, cin;
     } L[mlb::kNetLayers];
     size_t x = 0, a[3] = {0, 0, 0}, z[3] = {0, 0, 0}, y = 0, tg = 0, g3 = 0, g[2] = {0, 0};
-    size_t part = 0, loss = 0, err = 0, nc = 0;
+    size_t part = 0, loss = 0, err = 0, nc = 0, pool = 0;
     int nblk = 0;
     float n_ref = 1.f, j_ref = 1.f, f_ref = 1.f;
     // bumped whenever something a captured inference graph bakes in (the
@@ -41,6 +41,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kErrParts = 1024;
+constexpr int kPoolParts = 32, kPoolChunk = 256;   // partial sums per sample, samples per pass
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -76,6 +77,7 @@ bool plan(mlb_net_s &n, int nx, int ny, int nz, int training)
     n.y = take(4 * 16 * N);
     n.nc = take(4 * 6 * N);
     n.err = take(8 * 2 * (size_t)kErrParts);
+    n.pool = take(8 * (size_t)kPoolParts * kPoolChunk);
     if (training) {
         for (int l = 0; l < 3; ++l) n.z[l] = take(4 * 32 * N);
         n.tg = take(4 * 6 * N);
@@ -265,6 +267,84 @@ mlb_status mlb_net_set_scales(mlb_net n, double n_ref, double j_ref, double f_re
     n->j_ref = (float)j_ref;
     n->f_ref = (float)f_ref;
     n->version += 1;
+    return MLB_OK;
+}
+
+namespace {
+// float64 sums of squares over `len` floats at base + s stride for samples
+// s = 0..count-1 (partials on the GPU, added on the host in fixed order)
+mlb_status pool_sumsq(mlb_net_s &n, const float *base, long long stride, long long len, int count, double *out,
+                      hipStream_t st)
+{
+    std::vector<double> h((size_t)kPoolParts * kPoolChunk);
+    double *part = at<double>(n, n.pool);
+    for (int s0 = 0; s0 < count; s0 += kPoolChunk) {
+        const int c = std::min(kPoolChunk, count - s0);
+        mlb::cnn_pool_sumsq(base + (long long)s0 * stride, stride, len, c, part, kPoolParts, st);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(h.data(), part, sizeof(double) * kPoolParts * c, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int s = 0; s < c; ++s) {
+            double acc = 0.0;
+            for (int p = 0; p < kPoolParts; ++p) acc += h[(size_t)s * kPoolParts + p];
+            out[s0 + s] = acc;
+        }
+    }
+    return MLB_OK;
+}
+}  // namespace
+
+mlb_status mlb_net_pool_stats(mlb_net n, const float *x, const float *t, int32_t count, double *out, void *stream)
+{
+    if (mlb_status s = check_net(n)) return s;
+    if (!x || !t || !out || count < 1) return mlb::set_error(MLB_EINVAL, "x, t, out and count >= 1 are required");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const long long N = n->N;
+    std::vector<double> sx((size_t)count), stt((size_t)count);
+    // the momentum channels 2..7 of every input sample
+    if (mlb_status s = pool_sumsq(*n, x + 2 * N, 8 * N, 6 * N, count, sx.data(), st)) return s;
+    if (mlb_status s = pool_sumsq(*n, t, 6 * N, 6 * N, count, stt.data(), st)) return s;
+    double jx = 0.0;
+    for (int s = 0; s < count; ++s) jx += sx[(size_t)s];
+    out[0] = jx / (6.0 * (double)N * count);
+    for (int s = 0; s < count; ++s) out[1 + s] = stt[(size_t)s] / (6.0 * (double)N);
+    return MLB_OK;
+}
+
+mlb_status mlb_net_pool_rescale(mlb_net n, float *x, float *t, int32_t count, double j_div, double f_div, void *stream)
+{
+    if (mlb_status s = check_net(n)) return s;
+    if (!x || !t || count < 1) return mlb::set_error(MLB_EINVAL, "x, t and count >= 1 are required");
+    if (!(j_div > 0) || !(f_div > 0) || !std::isfinite(j_div) || !std::isfinite(f_div))
+        return mlb::set_error(MLB_EINVAL, "divisors must be positive and finite");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const long long N = n->N;
+    for (int s0 = 0; s0 < count; s0 += kPoolChunk) {       // grid.y stays within its limit
+        const int c = std::min(kPoolChunk, count - s0);
+        mlb::cnn_pool_scale(x + 2 * N + (long long)s0 * 8 * N, 8 * N, 6 * N, c, (float)(1.0 / j_div), st);
+        mlb::cnn_pool_scale(t + (long long)s0 * 6 * N, 6 * N, 6 * N, c, (float)(1.0 / f_div), st);
+        HIP_TRY(hipGetLastError());
+    }
+    return MLB_OK;
+}
+
+mlb_status mlb_net_rel_error(mlb_net n, const float *y, const float *t, double *err, void *stream)
+{
+    if (mlb_status s = check_net(n)) return s;
+    if (!y || !t || !err) return mlb::set_error(MLB_EINVAL, "y, t and err are required");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *part = at<double>(*n, n->err);
+    mlb::cnn_err_partial(6 * n->N, y, t, part, kErrParts, st);
+    HIP_TRY(hipGetLastError());
+    std::vector<double> h(2 * (size_t)kErrParts);
+    HIP_TRY(hipMemcpyAsync(h.data(), part, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    double e = 0.0, w = 0.0;
+    for (int p = 0; p < kErrParts; ++p) {
+        e += h[2 * (size_t)p];
+        w += h[2 * (size_t)p + 1];
+    }
+    *err = w > 0.0 ? std::sqrt(e / w) : (e > 0.0 ? INFINITY : 0.0);
     return MLB_OK;
 }
 

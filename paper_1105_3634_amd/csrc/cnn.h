@@ -63,5 +63,11 @@ void cnn_pack_target(const CnnShape &sh, const float *Nf, float f_ref, float *tg
 void cnn_unpack_output(const CnnShape &sh, const float *y, float f_ref, float *Nf, hipStream_t st);
 // squared-error partials: part[2w] = sum (a - b)^2, part[2w + 1] = sum b^2
 void cnn_err_partial(long long n, const float *a, const float *b, double *part, int nparts, hipStream_t st);
+// training pool of `count` samples: part[s * nparts + p] = partial sums of
+// squares of the `len` floats at base + s stride (float64)
+void cnn_pool_sumsq(const float *base, long long stride, long long len, int count, double *part, int nparts,
+                    hipStream_t st);
+// base + s stride, len floats, times mul, for every sample s
+void cnn_pool_scale(float *base, long long stride, long long len, int count, float mul, hipStream_t st);
 
 }  // namespace mlb

@@ -774,4 +774,43 @@ void cnn_err_partial(long long n, const float *a, const float *b, double *part, 
     hipLaunchKernelGGL(k_err_partial, dim3(nparts), dim3(256), 0, st, n, a, b, part);
 }
 
+// Sums of squares of `len` floats at base + s stride for every sample s of a
+// training pool (float64): block (p, s) writes part[s * nparts + p].
+__global__ void __launch_bounds__(256) k_pool_sumsq(const float *__restrict__ base, long long stride, long long len,
+                                                    double *__restrict__ part)
+{
+    __shared__ double r[256];
+    const float *x = base + (long long)blockIdx.y * stride;
+    double acc = 0.0;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < len; i += (long long)gridDim.x * 256) {
+        const double v = (double)x[i];
+        acc += v * v;
+    }
+    r[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) r[threadIdx.x] += r[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(long long)blockIdx.y * gridDim.x + blockIdx.x] = r[0];
+}
+
+__global__ void k_pool_scale(float *__restrict__ base, long long stride, long long len, float mul)
+{
+    float *x = base + (long long)blockIdx.y * stride;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < len; i += (long long)gridDim.x * 256)
+        x[i] *= mul;
+}
+
+void cnn_pool_sumsq(const float *base, long long stride, long long len, int count, double *part, int nparts,
+                    hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pool_sumsq, dim3(nparts, count), dim3(256), 0, st, base, stride, len, part);
+}
+
+void cnn_pool_scale(float *base, long long stride, long long len, int count, float mul, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pool_scale, dim3(64, count), dim3(256), 0, st, base, stride, len, mul);
+}
+
 }  // namespace mlb

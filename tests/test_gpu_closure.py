@@ -382,3 +382,72 @@ def test_closure_graph_follows_rescaled_network(mlb):
         g.step(4)                                  # network steps only
         runs.append(g.populations().cpu().numpy())
     np.testing.assert_array_equal(runs[0], runs[1])
+
+
+def test_pool_statistics_rescale_and_error(mlb):
+    """The training-pool sums, the in-place rescaling and the relative error
+    run in the library: against numpy on the same random pool."""
+    import torch
+    shape = (6, 7, 9)
+    net = mlb.GpuNet(shape, training=True)
+    N = int(np.prod(shape))
+    rng = np.random.default_rng(5)
+    S = 300                                           # more than one pass of the library's sample chunks
+    x = rng.normal(size=(S, 8) + shape).astype(np.float32)
+    t = (rng.normal(size=(S, 6) + shape) * rng.uniform(0.1, 3.0, size=(S, 1, 1, 1, 1))).astype(np.float32)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    j_ms, t_ms = net.pool_stats(xd, td)
+    x64, t64 = x.astype(np.float64), t.astype(np.float64)
+    assert abs(j_ms / np.mean(x64[:, 2:] ** 2) - 1) < 1e-12
+    np.testing.assert_allclose(t_ms, (t64 ** 2).reshape(S, -1).mean(1), rtol=1e-12)
+    net.pool_rescale(xd, td, 2.0, 4.0)
+    xr, tr = xd.cpu().numpy(), td.cpu().numpy()
+    np.testing.assert_array_equal(xr[:, :2], x[:, :2])
+    np.testing.assert_allclose(xr[:, 2:], x[:, 2:] * np.float32(0.5), rtol=1e-7)
+    np.testing.assert_allclose(tr, t * np.float32(0.25), rtol=1e-7)
+    y = t[0] + rng.normal(scale=0.1, size=t[0].shape).astype(np.float32)
+    err = net.rel_error(torch.from_numpy(y).cuda(), torch.from_numpy(t[0]).cuda())
+    ref = np.linalg.norm(y.astype(np.float64) - t64[0]) / np.linalg.norm(t64[0])
+    assert abs(err / ref - 1) < 1e-12
+    assert N > 0
+
+
+def test_trained_network_passes_a_check_the_zero_network_fails(mlb):
+    """What the trained network gains: trained as the closure benchmark trains
+    it (snapshots of the plain solver every 25 steps over 5000 steps of
+    composition modes with amplitudes 0.01 - 0.1 on a 192x12x12 box at the
+    step-binary physics, 20 epochs), it passes the exact-force check on a
+    held-out state (amplitude 0.045, after 300 steps) at tolerance 0.2, where
+    the network with all parameters zero (a force of zero) fails with error 1."""
+    from paper_1105_3634_amd.closure_train import closure_error, init_params, train_closure
+    nx, ny, nz = 192, 12, 12
+    n_tot = W.number_density(0.2, (0.5, 0.5), (2.0, 3.0))
+
+    def state(amp):
+        def make():
+            m = W.Mixture(nx, ny, nz, sigma=(2.0, 3.0), tau=1.0, name="closure_train")
+            n0, u0 = W.mode_state(m, n_tot, 0.5, amp)
+            return m, n0, u0
+        return make
+
+    net = mlb.GpuNet((nz, ny, nx), training=True)
+    net.set_params(init_params(0))
+    amps = (0.05, 0.1, 0.04, 0.01, 0.07, 0.03, 0.06, 0.02, 0.08)
+    rep = train_closure(net, [state(a) for a in amps], per_state=200, sample_every=25, epochs=20, lr=1e-3)
+    m, n0, u0 = state(0.045)()
+    g = mlb.GpuMixture(m, n0, u0, precision=32)
+    g.step(300)
+    err_trained = closure_error(net, g)
+    zero = mlb.GpuNet((nz, ny, nx))
+    zero.set_scales(*rep.scales)
+    err_zero = closure_error(zero, g)
+    print(f"  held-out check error: trained {err_trained:.4f}, zero network {err_zero:.4f}", flush=True)
+    assert err_zero == pytest.approx(1.0, abs=1e-12)
+    assert err_trained < 0.2
+    for nt, passes in ((net, True), (zero, False)):
+        g2 = mlb.GpuMixture(m, n0, u0, precision=32)
+        g2.step(300)
+        g2.set_closure(nt, check_every=300, tol=0.2)
+        g2.step(1)                                   # checks fall on multiples of check_every: step 300
+        st = g2.closure_stats()
+        assert st["checks"] == 1 and st["active"] == passes, (st, err_trained)
