@@ -192,9 +192,17 @@ mlb_status mlb_forces(mlb_mixture h, void *nphi_out, uint32_t parts, void *strea
 mlb_status mlb_fields(mlb_mixture h, void *n, void *j, void *u, void *g, void *vhat, void *H,
                       void *nphi, void *stream);
 
-/* Copy the populations [M][19][N] out of / into the mixture (device). */
+/* Copy the populations [M][19][N] out of / into the mixture (device).
+ * Checkpoint and resume: the populations and the step count are the whole
+ * state of a run (every other field is derived from the populations at the
+ * start of each step), so a mixture created with the same parameters, given
+ * a saved f by mlb_set_populations and the saved count by
+ * mlb_set_step_count, continues bit for bit as the run it was saved from. */
 mlb_status mlb_get_populations(mlb_mixture h, void *f_out, void *stream);
 mlb_status mlb_set_populations(mlb_mixture h, const void *f_in, void *stream);
+/* Set the step count (the time stamp of recorded samples and the phase of
+ * closure checks) for a resumed run; MLB_EINVAL if negative. */
+mlb_status mlb_set_step_count(mlb_mixture h, int64_t steps);
 
 /* Body force varying across the lattice rows (the external force F^a of
  * Sec. 2, eq. evolution, as a function of y; a y-periodic profile drives the
@@ -304,6 +312,10 @@ mlb_status mlb_batch_step(mlb_batch h, int32_t nsteps, void *stream);
 /* Per-system views: densities / momenta, populations of system k (device). */
 mlb_status mlb_batch_moments(mlb_batch h, int32_t system, void *n_out, void *j_out, void *stream);
 mlb_status mlb_batch_get_populations(mlb_batch h, int32_t system, void *f_out, void *stream);
+/* Checkpoint and resume of an ensemble, as for one mixture: the populations
+ * of system k (device, [M_k][19][N_k]) and the batch's step count. */
+mlb_status mlb_batch_set_populations(mlb_batch h, int32_t system, const void *f_in, void *stream);
+mlb_status mlb_batch_set_step_count(mlb_batch h, int64_t steps);
 /* Append the (species 0 - species 1) mode amplitude of every system to its
  * own float64 time series (systems with one species are skipped). */
 mlb_status mlb_batch_record_modes(mlb_batch h, void *stream);

@@ -139,6 +139,10 @@ class GpuMixture:
     def steps(self) -> int:
         return int(self.lib.mlb_step_count(self.h))
 
+    def set_step_count(self, steps: int) -> None:
+        """Resume a checkpoint: the step count saved with the populations."""
+        _lib.check(self.lib.mlb_set_step_count(self.h, int(steps)), "mlb_set_step_count")
+
     def _empty(self, *shape):
         return _torch().empty(shape, dtype=self.dtype, device=self.device)
 
@@ -312,6 +316,17 @@ class GpuBatch:
     @property
     def steps(self) -> int:
         return int(self.lib.mlb_batch_step_count(self.h))
+
+    def set_step_count(self, steps: int) -> None:
+        _lib.check(self.lib.mlb_batch_set_step_count(self.h, int(steps)), "mlb_batch_set_step_count")
+
+    def set_populations(self, k: int, f) -> None:
+        M, sh = self._shape(k)
+        f = f.to(device=self.device, dtype=self.dtype).contiguous()
+        assert tuple(f.shape) == (M, Q) + sh
+        _lib.check(self.lib.mlb_batch_set_populations(self.h, int(k), C.c_void_p(f.data_ptr()),
+                                                      _stream_handle(self.stream)), "mlb_batch_set_populations")
+        self._keep = f
 
     def _shape(self, k):
         m = self.mixes[k]

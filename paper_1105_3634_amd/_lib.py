@@ -63,6 +63,7 @@ _SIGS = [
     ("mlb_fields", C.c_int, [C.c_void_p] + [C.c_void_p] * 7 + [C.c_void_p]),
     ("mlb_get_populations", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("mlb_set_populations", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("mlb_set_step_count", C.c_int, [C.c_void_p, C.c_int64]),
     ("mlb_set_force_profile", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
     ("mlb_conserved", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]),
     ("mlb_record_mode", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
@@ -86,6 +87,8 @@ _SIGS = [
     ("mlb_batch_step", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     ("mlb_batch_moments", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("mlb_batch_get_populations", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    ("mlb_batch_set_populations", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    ("mlb_batch_set_step_count", C.c_int, [C.c_void_p, C.c_int64]),
     ("mlb_batch_record_modes", C.c_int, [C.c_void_p, C.c_void_p]),
     ("mlb_batch_fit", C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_double), C.c_void_p]),
     ("mlb_batch_fit_ex", C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_double), C.c_void_p]),

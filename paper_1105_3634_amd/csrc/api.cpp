@@ -1158,6 +1158,15 @@ mlb_status populations_of(Batch &B, int k, void *f_out, hipStream_t st)
     return MLB_OK;
 }
 
+mlb_status set_populations_of(Batch &B, int k, const void *f_in, hipStream_t st)
+{
+    if (k < 0 || k >= B.count) return fail(MLB_EINVAL, "bad system index");
+    const SysHost &S = B.sys[k];
+    HIP_TRY(hipMemcpyAsync(B.ws + (B.parity ? S.f1 : S.f0), f_in, tsize_of(B.prec) * S.M * mlb::kQ * S.N,
+                           hipMemcpyDeviceToDevice, st));
+    return MLB_OK;
+}
+
 mlb_status record_mode_of(Batch &B, int k, int a, int b, hipStream_t st)
 {
     SysHost &S = B.sys[k];
@@ -1350,9 +1359,14 @@ mlb_status mlb_get_populations(mlb_mixture h, void *f_out, void *stream)
 mlb_status mlb_set_populations(mlb_mixture h, const void *f_in, void *stream)
 {
     if (!h || !f_in) return fail(MLB_EINVAL, "handle and input are required");
-    const SysHost &S = h->sys[0];
-    HIP_TRY(hipMemcpyAsync(h->ws + (h->parity ? S.f1 : S.f0), f_in, tsize_of(h->prec) * S.M * mlb::kQ * S.N,
-                           hipMemcpyDeviceToDevice, S_(stream)));
+    return set_populations_of(*h, 0, f_in, S_(stream));
+}
+
+mlb_status mlb_set_step_count(mlb_mixture h, int64_t steps)
+{
+    if (!h) return fail(MLB_EINVAL, "handle is NULL");
+    if (steps < 0) return fail(MLB_EINVAL, "step count must be >= 0");
+    h->steps = steps;
     return MLB_OK;
 }
 
@@ -1693,6 +1707,20 @@ mlb_status mlb_batch_profile_end(mlb_batch h, double *ms, int32_t *launches, voi
 }
 
 int64_t mlb_batch_step_count(mlb_batch h) { return h ? h->steps : -1; }
+
+mlb_status mlb_batch_set_populations(mlb_batch h, int32_t system, const void *f_in, void *stream)
+{
+    if (!h || !f_in) return fail(MLB_EINVAL, "handle and input are required");
+    return set_populations_of(*h, system, f_in, S_(stream));
+}
+
+mlb_status mlb_batch_set_step_count(mlb_batch h, int64_t steps)
+{
+    if (!h) return fail(MLB_EINVAL, "handle is NULL");
+    if (steps < 0) return fail(MLB_EINVAL, "step count must be >= 0");
+    h->steps = steps;
+    return MLB_OK;
+}
 
 mlb_status mlb_batch_destroy(mlb_batch h)
 {
