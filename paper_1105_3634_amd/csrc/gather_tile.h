@@ -482,6 +482,17 @@ k_gather1_tile(const SysDesc<float> *__restrict__ sys,
     }
 }
 
+// c.v for a lattice velocity c (components -1, 0, 1): signed sums of the
+// components, no products; -0 is the exact identity of the first addition
+__device__ inline float cdot(int cx, int cy, int cz, const float v[3])
+{
+    float acc = -0.f;
+    if (cx) acc += cx > 0 ? v[0] : -v[0];
+    if (cy) acc += cy > 0 ? v[1] : -v[1];
+    if (cz) acc += cz > 0 ? v[2] : -v[2];
+    return acc;
+}
+
 // ------------------------------- second gather + collision + push streaming
 template <int TX, int TY, int TZ>
 __global__ void __launch_bounds__(kStep2Threads) __attribute__((amdgpu_waves_per_eu(MLB_S2_WAVES)))
@@ -602,18 +613,45 @@ k_step2_tile(const SysDesc<float> *__restrict__ sys,
         return;
     }
     gfloat *__restrict__ fout = glb(S.f[parity ^ 1]) + (long long)a * kQ * N;
+    // The collision of eq. (evolution) with the force term, regrouped so that
+    // only the parts that depend on c_i stay inside the population loop:
+    //   omega psi_i + src_i = w_i E_i (A + 3 c_i.P),
+    //   E_i = (1 - 3/2 u.u) + c_i.u (3 + 9/2 c_i.u),
+    //   P = omega (j - n u) + N,  A = omega n - 3 u.P
+    // (psi_i = w_i E_i (n + 3 (j - n u).(c_i - u)), src_i = 3 w_i E_i (c_i - u).N).
     const bool w1 = S.omega_is_one != 0;
-    const Site r{q.x, q.y, q.z};
+    const float om = w1 ? 1.f : S.omega;
+    const float uu = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
+    const float B = 1.f - 1.5f * uu;
+    float P[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) P[d] = om * (ja[d] - na * u[d]) + Na[d];
+    const float A = om * na - 3.f * ((u[0] * P[0] + u[1] * P[1]) + u[2] * P[2]);
+    // neighbour offsets with periodic wrap (32-bit: sites number below 2^29);
+    // beyond a wall the population bounces back instead
+    const int nx = S.nx, nxy = S.nx * S.ny, s32 = (int)s;
+    const int ox[2] = {q.x == 0 ? nx - 1 : -1, q.x == nx - 1 ? 1 - nx : 1};
+    const int oy[2] = {q.y == 0 ? nxy - nx : -nx, q.y == S.ny - 1 ? nx - nxy : nx};
+    const int nall = (int)S.N;
+    const int oz[2] = {q.z == 0 ? nall - nxy : -nxy, q.z == S.nz - 1 ? nxy - nall : nxy};
+    const bool wlo = S.walls && q.y == 1, whi = S.walls && q.y == S.ny - 2;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
         if (i < ib || i >= ie) continue;
-        const float fs = post_collision<float>(i, fi[i], w1, S.omega, S.om1, na, ja, u, Na);
-        const int yy = q.y + kC[i][1];
-        if (S.walls && (yy == 0 || yy == S.ny - 1)) {
-            const float uw = (yy == 0) ? S.wall_ux[0] : S.wall_ux[1];
-            fout[(long long)opposite(i) * N + s] = fs - ((6.f * lattice_weight<float>(i)) * na) * ((float)kC[i][0] * uw);
+        const int cx = kC[i][0], cy = kC[i][1], cz = kC[i][2];
+        const float cu = cdot(cx, cy, cz, u), cP = cdot(cx, cy, cz, P);
+        const float E = B + cu * (3.f + 4.5f * cu);
+        float fs = (lattice_weight<float>(i) * E) * (A + 3.f * cP);
+        if (!w1) fs += S.om1 * fi[i];
+        if ((cy < 0 && wlo) || (cy > 0 && whi)) {
+            const float uw = cy < 0 ? S.wall_ux[0] : S.wall_ux[1];
+            fout[(long long)opposite(i) * N + s] = fs - ((6.f * lattice_weight<float>(i)) * na) * ((float)cx * uw);
         } else {
-            fout[(long long)i * N + nbr(S, r, kC[i][0], kC[i][1], kC[i][2])] = fs;
+            int o = s32;
+            if (cx) o += ox[cx > 0];
+            if (cy) o += oy[cy > 0];
+            if (cz) o += oz[cz > 0];
+            fout[(long long)i * N + o] = fs;
         }
     }
 }
