@@ -300,7 +300,7 @@ def ensemble_leg(mlb, W, steps=1000, timed=200):
                 "well_conditioned_min": float(np.min(Dg)), "well_conditioned_median": float(np.median(Dg)),
                 "well_conditioned_max": float(np.max(Dg))},
         "tuning": {"shape": mlb.GpuBatch.SHAPES[tune["shape"]], "order": ["linear", "xcd-chunked"][tune["order"]],
-                   "trial_ms": tune["trial_ms"]},
+                   "gather1_groups_per_site": tune["gather1_split"], "trial_ms": tune["trial_ms"]},
         "passes_ms_per_step": {k: v[0] / 10 for k, v in passes.items() if v[1]},
     }
 
@@ -350,7 +350,8 @@ def taylor_leg(mlb, W, steps=5000, timed=200, packing=0.25):
         "d_eff": fit["D"], "d_eff_fit": {"r2": fit["r2"], "samples": fit["samples"],
                                          "well_conditioned": fit["well_conditioned"]},
         "mass_finite": bool(np.all(np.isfinite(mass))),
-        "tuning": {"shape": ["16x4x4", "8x8x4", "32x4x2"][tune["shape"]], "order": ["linear", "xcd-chunked"][tune["order"]]},
+        "tuning": {"shape": ["16x4x4", "8x8x4", "32x4x2"][tune["shape"]], "order": ["linear", "xcd-chunked"][tune["order"]],
+                   "gather1_groups_per_site": tune["gather1_split"]},
         "passes_ms_per_step": {k: v[0] / 10 for k, v in passes.items() if v[1]},
     }
 
@@ -538,9 +539,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=200, help="untimed steps before the timed region (the GPU reaches its steady clocks)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tail", choices=["auto", "direct", "spectral"], default="auto")
-    ap.add_argument("--tiling", default=None, metavar="SHAPE,ORDER",
-                    help="fixed tile shape (0: 16x4x4, 1: 8x8x4, 2: 32x4x2) and block order (0 linear, "
-                         "1 XCD-chunked) instead of the start-up autotuning (reproducible profiles)")
+    ap.add_argument("--tiling", default=None, metavar="SHAPE,ORDER[,SPLIT]",
+                    help="fixed tile shape (0: 16x4x4, 1: 8x8x4, 2: 32x4x2), block order (0 linear, "
+                         "1 XCD-chunked) and the first gather's thread groups per site (2 or 3, default 3) "
+                         "instead of the start-up autotuning (reproducible profiles)")
     ap.add_argument("--no-d12", action="store_true", help="skip the 2000-step D_12 accuracy check")
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
@@ -574,8 +576,8 @@ def main():
     mix, n0, u0 = W.config_bulk_diffusion()
     tail_mode = {"auto": mlb.TAIL_AUTO, "direct": mlb.TAIL_DIRECT, "spectral": mlb.TAIL_SPECTRAL}[args.tail]
     if args.tiling:
-        shape, order = (int(v) for v in args.tiling.split(","))
-        opts = mlb.opt_tiling(shape, order)
+        vals = [int(v) for v in args.tiling.split(",")]
+        opts = mlb.opt_tiling(*vals)
     else:
         opts = mlb.OPT_TUNE
     g = mlb.GpuMixture(mix, n0, u0, precision=32, tail_mode=tail_mode, device="cuda:0", options=opts)
@@ -610,7 +612,8 @@ def main():
     shapes = ("16,4,4", "8,8,4", "32,4,2")
     tune = g.tuning()
     kname = {"gather1": "k_gather1_tile", "step2": "k_step2_tile"}.get(dom)
-    traffic = counter_traffic(f"{kname}<{shapes[tune['shape']]}>") if kname else None
+    kargs = shapes[tune["shape"]] + (f",{tune['gather1_split']}" if dom == "gather1" else "")
+    traffic = counter_traffic(f"{kname}<{kargs}>") if kname else None
     total_bytes = sum(bytes_.values()) * args.steps
     line = {
         "metric": METRIC,

@@ -69,14 +69,18 @@ typedef enum {
 
 enum { MLB_SCHEME_CN_J1 = 0, MLB_SCHEME_FE = 1 };
 enum { MLB_TAIL_AUTO = 0, MLB_TAIL_DIRECT = 1, MLB_TAIL_SPECTRAL = 2 };
-enum { MLB_OPT_TUNE = 1u,       /* time every tile shape and block order at init, keep the fastest */
+enum { MLB_OPT_TUNE = 1u,       /* time every float32 tiling (tile shape, block order, thread groups
+                                   of the first gather) at init, keep the fastest */
        MLB_OPT_NO_GRAPH = 2u,   /* launch the passes eagerly instead of replaying a graph */
        MLB_OPT_NO_STABILITY_CHECK = 512u }; /* skip the linear-stability guard at init (studies of
                                            unstable schemes) */
 /* Fixed float32 tiling instead of the default or tuned one (overrides
  * MLB_OPT_TUNE): tile shape 0 = 16x4x4, 1 = 8x8x4, 2 = 32x4x2 sites; block
- * order 0 = linear, 1 = XCD-chunked.  Reproducible profiles use it. */
+ * order 0 = linear, 1 = XCD-chunked.  Reproducible profiles use it.  With
+ * MLB_OPT_TILING, MLB_OPT_GATHER1_SPLIT(s) also fixes the thread groups per
+ * site of the first gather (2 or 3; 3 when not given). */
 #define MLB_OPT_TILING(shape, order) ((((uint32_t)(shape) + 1u) & 15u) << 4 | ((uint32_t)(order) & 1u) << 8)
+#define MLB_OPT_GATHER1_SPLIT(s) (((uint32_t)(s) & 3u) << 10)
 enum { MLB_PART_MF = 1u, MLB_PART_TAIL = 2u, MLB_PART_DISS = 4u, MLB_PART_EXT = 8u,
        MLB_PART_ALL = 15u };
 
@@ -168,6 +172,9 @@ mlb_status mlb_check_stability(const mlb_params *p, const double *n_bulk, double
 
 /* Tile shape and block order in use (see mlb_batch_tuning). */
 mlb_status mlb_tuning(mlb_mixture h, int32_t *shape, int32_t *order, double *trial_ms);
+/* As mlb_tuning, with the first gather's thread groups per site and the
+ * time of every candidate (see mlb_batch_tuning_ex). */
+mlb_status mlb_tuning_ex(mlb_mixture h, int32_t *shape, int32_t *order, int32_t *gather1_split, double *trial_ms);
 
 /* Advance the populations by nsteps >= 0 time steps of the kinetic equation
  * (Sec. 2, eq. evolution, with the field of Sec. 3). */
@@ -331,9 +338,15 @@ mlb_status mlb_batch_get_series(mlb_batch h, int32_t system, double *t, double *
                                 int32_t *count, void *stream);
 /* The tile shape (0: 16x4x4, 1: 8x8x4, 2: 32x4x2) and block order (0:
  * linear, 1: XCD-chunked) in use; trial_ms (HOST, 6 values, may be NULL)
- * receives the measured milliseconds per step of each candidate
- * (index 2 * shape + order; 0 when not measured). */
+ * receives the measured milliseconds per step of each tile shape and order
+ * (index 2 * shape + order; the faster of the first gather's two splits;
+ * 0 when not measured).  -1 outputs for untiled handles. */
 mlb_status mlb_batch_tuning(mlb_batch h, int32_t *shape, int32_t *order, double *trial_ms);
+/* As mlb_batch_tuning, with the first gather's thread groups per tile site
+ * (2 or 3) in use and trial_ms (HOST, 12 values, may be NULL) for every
+ * candidate: index (split - 2) 6 + 2 shape + order. */
+mlb_status mlb_batch_tuning_ex(mlb_batch h, int32_t *shape, int32_t *order, int32_t *gather1_split,
+                               double *trial_ms);
 mlb_status mlb_batch_profile_begin(mlb_batch h);
 mlb_status mlb_batch_profile_end(mlb_batch h, double *ms, int32_t *launches, void *stream);
 int64_t mlb_batch_step_count(mlb_batch h);

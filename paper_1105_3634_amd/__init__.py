@@ -127,10 +127,14 @@ class GpuMixture:
         _lib.check(self.lib.mlb_step(self.h, int(nsteps), _stream_handle(self.stream)), "mlb_step")
 
     def tuning(self):
-        shape, order = C.c_int32(), C.c_int32()
-        ms = (C.c_double * 6)()
-        _lib.check(self.lib.mlb_tuning(self.h, C.byref(shape), C.byref(order), ms), "mlb_tuning")
-        return {"shape": int(shape.value), "order": int(order.value), "trial_ms": list(ms[:])}
+        """Float32 tiling in use: shape, order, the first gather's thread groups
+        per site and the time of every tuned candidate (mlb_tuning_ex)."""
+        shape, order, split = C.c_int32(), C.c_int32(), C.c_int32()
+        ms = (C.c_double * 12)()
+        _lib.check(self.lib.mlb_tuning_ex(self.h, C.byref(shape), C.byref(order), C.byref(split), ms),
+                   "mlb_tuning_ex")
+        return {"shape": int(shape.value), "order": int(order.value), "gather1_split": int(split.value),
+                "trial_ms": list(ms[:])}
 
     def set_graph(self, enable: bool) -> None:
         _lib.check(self.lib.mlb_set_graph(self.h, 1 if enable else 0), "mlb_set_graph")
@@ -376,10 +380,12 @@ class GpuBatch:
         return np.array(t[:n]), np.array(v[:n])
 
     def tuning(self):
-        shape, order = C.c_int32(), C.c_int32()
-        ms = (C.c_double * 6)()
-        _lib.check(self.lib.mlb_batch_tuning(self.h, C.byref(shape), C.byref(order), ms), "mlb_batch_tuning")
-        return {"shape": int(shape.value), "order": int(order.value), "trial_ms": list(ms[:])}
+        shape, order, split = C.c_int32(), C.c_int32(), C.c_int32()
+        ms = (C.c_double * 12)()
+        _lib.check(self.lib.mlb_batch_tuning_ex(self.h, C.byref(shape), C.byref(order), C.byref(split), ms),
+                   "mlb_batch_tuning_ex")
+        return {"shape": int(shape.value), "order": int(order.value), "gather1_split": int(split.value),
+                "trial_ms": list(ms[:])}
 
     def profile_begin(self) -> None:
         _lib.check(self.lib.mlb_batch_profile_begin(self.h), "mlb_batch_profile_begin")

@@ -206,9 +206,12 @@ struct SysHost {
     bool has_profile = false;
 };
 
+// Float32 tiling: tile shape, block order and the first gather's thread
+// groups per site (2 or 3); trial_ms[(split - 2) 2 V + 2 shape + order].
+constexpr int kSplitChoices = 2, kTrials = 2 * mlb::kTileVariants * kSplitChoices;
 struct Tuning {
-    int shape = 0, order = 1;
-    double trial_ms[2 * mlb::kTileVariants] = {0, 0, 0, 0, 0, 0};
+    int shape = 0, order = 1, g1split = 3;
+    double trial_ms[kTrials] = {};
 };
 
 // Static device workspace of mlb_init_mixture_static.  In host code the
@@ -558,7 +561,7 @@ mlb_status upload_static(Batch &B, hipStream_t st)
     return MLB_OK;
 }
 
-mlb_status set_tiling(Batch &B, int shape, int order, hipStream_t st)
+mlb_status set_tiling(Batch &B, int shape, int order, int g1split, hipStream_t st)
 {
     int nblk = 0;
     std::vector<int2> m = tile_map(B, shape, order, nblk);
@@ -568,6 +571,7 @@ mlb_status set_tiling(Batch &B, int shape, int order, hipStream_t st)
     B.nblk_tile = nblk;
     B.tune.shape = shape;
     B.tune.order = order;
+    B.tune.g1split = g1split;
     if (B.graph) {
         (void)hipGraphExecDestroy(B.graph);
         B.graph = nullptr;
@@ -711,7 +715,7 @@ void run_passes(Batch &B, hipStream_t st, bool query, int qk, int force_only)
         if constexpr (std::is_same<T, float>::value) {
             if (tiled) {
                 pass(B, kPassGather1, st,
-                     [&] { mlb::launch_gather1_tile(shape, sys, tmap, ntl, M, tb, B.reach_max, st); });
+                     [&] { mlb::launch_gather1_tile(shape, B.tune.g1split, sys, tmap, ntl, M, tb, B.reach_max, st); });
                 return;
             }
         }
@@ -980,7 +984,7 @@ mlb_status autotune(Batch &B, const double *const *n0, const double *const *u0, 
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
             const Tuning cached = it->second;
-            TRY(set_tiling(B, cached.shape, cached.order, st));
+            TRY(set_tiling(B, cached.shape, cached.order, cached.g1split, st));
             B.tune = cached;
             return MLB_OK;
         }
@@ -992,9 +996,10 @@ mlb_status autotune(Batch &B, const double *const *n0, const double *const *u0, 
     HIP_TRY(hipEventCreate(&e1));
     const int warm = 2, reps = 6;
     mlb_status status = MLB_OK;
+    for (int split = 2; split < 2 + kSplitChoices && status == MLB_OK; ++split)
     for (int v = 0; v < mlb::kTileVariants && status == MLB_OK; ++v)
         for (int order = 0; order < 2 && status == MLB_OK; ++order) {
-            status = set_tiling(B, v, order, st);
+            status = set_tiling(B, v, order, split, st);
             if (status != MLB_OK) break;
             status = run_steps(B, warm, st, false);   // captures the graph of this tiling
             if (status != MLB_OK) break;
@@ -1008,17 +1013,18 @@ mlb_status autotune(Batch &B, const double *const *n0, const double *const *u0, 
                 break;
             }
             const double per = ms / reps;
-            best.trial_ms[2 * v + order] = per;
+            best.trial_ms[(split - 2) * 2 * mlb::kTileVariants + 2 * v + order] = per;
             if (per < best_ms) {
                 best_ms = per;
                 best.shape = v;
                 best.order = order;
+                best.g1split = split;
             }
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (status != MLB_OK) return status;
-    TRY(set_tiling(B, best.shape, best.order, st));
+    TRY(set_tiling(B, best.shape, best.order, best.g1split, st));
     B.tune = best;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1093,7 +1099,7 @@ mlb_status create(Batch &B, const mlb_params *params, int count, void *workspace
     if (B.tiled && !mlb::tile_prepare(B.reach_max, B.ball_reach_max, B.ball_total_max, B.maxM))
         B.tiled = false;
     TRY(upload_static<T>(B, st));
-    if (B.tiled) TRY(set_tiling(B, 0, 1, st));
+    if (B.tiled) TRY(set_tiling(B, 0, 1, 3, st));
     for (auto &S : B.sys)
         if (S.spectral) TRY(setup_spectral(B, S, st));
     bool any_spectral = false;
@@ -1109,11 +1115,11 @@ mlb_status create(Batch &B, const mlb_params *params, int count, void *workspace
     HIP_TRY(hipStreamSynchronize(st));
     if (!(options & MLB_OPT_NO_STABILITY_CHECK)) TRY(check_mean_states(B, st));
     const int fixed_shape = (int)((options >> 4) & 15u) - 1, fixed_order = (int)((options >> 8) & 1u);
+    const int fixed_split = (int)((options >> 10) & 3u);
     if (fixed_shape >= mlb::kTileVariants) return fail(MLB_EINVAL, "MLB_OPT_TILING: no such tile shape");
+    if (fixed_split == 1) return fail(MLB_EINVAL, "MLB_OPT_GATHER1_SPLIT: 2 or 3 thread groups per site");
     if (B.tiled && fixed_shape >= 0) {
-        TRY(set_tiling(B, fixed_shape, fixed_order, st));
-        B.tune.shape = fixed_shape;
-        B.tune.order = fixed_order;
+        TRY(set_tiling(B, fixed_shape, fixed_order, fixed_split ? fixed_split : 3, st));
     } else if (B.tiled && (options & MLB_OPT_TUNE)) {
         TRY(autotune<T>(B, n0, u0, st));
     }
@@ -1687,8 +1693,33 @@ mlb_status mlb_batch_tuning(mlb_batch h, int32_t *shape, int32_t *order, double 
     if (shape) *shape = h->tiled ? h->tune.shape : -1;
     if (order) *order = h->tiled ? h->tune.order : -1;
     if (trial_ms)
-        for (int i = 0; i < 2 * mlb::kTileVariants; ++i) trial_ms[i] = h->tune.trial_ms[i];
+        // per tile shape and order, the faster of the first gather's splits
+        for (int i = 0; i < 2 * mlb::kTileVariants; ++i) {
+            double best = 0.0;
+            for (int c = 0; c < kSplitChoices; ++c) {
+                const double v = h->tune.trial_ms[c * 2 * mlb::kTileVariants + i];
+                if (v > 0.0 && (best == 0.0 || v < best)) best = v;
+            }
+            trial_ms[i] = best;
+        }
     return MLB_OK;
+}
+
+mlb_status mlb_batch_tuning_ex(mlb_batch h, int32_t *shape, int32_t *order, int32_t *gather1_split,
+                               double *trial_ms)
+{
+    if (!h) return fail(MLB_EINVAL, "handle is NULL");
+    if (shape) *shape = h->tiled ? h->tune.shape : -1;
+    if (order) *order = h->tiled ? h->tune.order : -1;
+    if (gather1_split) *gather1_split = h->tiled ? h->tune.g1split : -1;
+    if (trial_ms)
+        for (int i = 0; i < kTrials; ++i) trial_ms[i] = h->tune.trial_ms[i];
+    return MLB_OK;
+}
+
+mlb_status mlb_tuning_ex(mlb_mixture h, int32_t *shape, int32_t *order, int32_t *gather1_split, double *trial_ms)
+{
+    return mlb_batch_tuning_ex(h, shape, order, gather1_split, trial_ms);
 }
 
 mlb_status mlb_batch_profile_begin(mlb_batch h)

@@ -38,9 +38,6 @@ namespace mlb {
 // CU at the same LDS footprint hide the LDS and scalar-load latencies of the
 // inner loop.  Split factor, shell-loop unrolling and the register budget
 // (waves per SIMD) per kernel:
-#ifndef MLB_G1_SPLIT
-#define MLB_G1_SPLIT 3
-#endif
 #ifndef MLB_G1_UNROLL
 #define MLB_G1_UNROLL 4
 #endif
@@ -64,8 +61,11 @@ namespace mlb {
 #ifndef MLB_S2_LAYOUTS
 #define MLB_S2_LAYOUTS 3
 #endif
-constexpr int kSplitG1 = MLB_G1_SPLIT, kSplitS2 = MLB_S2_SPLIT;
-constexpr int kGather1Threads = kSplitG1 * kBlock, kStep2Threads = kSplitS2 * kBlock;
+// The first gather runs with 2 or 3 thread groups per tile site (a launch
+// parameter the autotuner picks: fewer groups leave LDS and wave slots to
+// the spectral field that runs beside it); the second with kSplitS2.
+constexpr int kSplitG1Max = 3, kSplitS2 = MLB_S2_SPLIT;
+constexpr int kStep2Threads = kSplitS2 * kBlock;
 
 // shell entries [kb, ke) of group h of SPLIT
 template <int SPLIT>
@@ -349,13 +349,13 @@ __device__ inline TileSite tile_site(const SysDesc<float> &S, const TileGeo &t)
 }
 
 // ------------------------------------------------------------ first gather
-template <int TX, int TY, int TZ>
-__global__ void __launch_bounds__(kGather1Threads) __attribute__((amdgpu_waves_per_eu(MLB_G1_WAVES)))
+template <int TX, int TY, int TZ, int SPLIT>
+__global__ void __launch_bounds__(SPLIT * kBlock) __attribute__((amdgpu_waves_per_eu(MLB_G1_WAVES)))
 k_gather1_tile(const SysDesc<float> *__restrict__ sys,
                                                          const int2 *__restrict__ bmap, Tables<float> tb)
 {
     extern __shared__ float4 lds[];
-    static_assert(TX * TY * TZ == kBlock, "kSplitG1 threads per tile site");
+    static_assert(TX * TY * TZ == kBlock && SPLIT >= 2 && SPLIT <= kSplitG1Max, "SPLIT threads per tile site");
     const int2 bm = bmap[blockIdx.x];
     if (bm.x < 0) return;
     const SysDesc<float> &S = sys[bm.x];
@@ -372,14 +372,14 @@ k_gather1_tile(const SysDesc<float> *__restrict__ sys,
     int *RowOff = reinterpret_cast<int *>(lds + t.FS + (t.FS + 3) / 4);
     int *RowL = RowOff + t.HY * t.HZ;
     const int HXY = t.PXY;
-    const StageLane sl = stage_lane<kGather1Threads>(S, t);
-    fill_rows<kGather1Threads>(S, t, RowOff, LM ? RowL : nullptr);
+    const StageLane sl = stage_lane<SPLIT * kBlock>(S, t);
+    fill_rows<SPLIT * kBlock>(S, t, RowOff, LM ? RowL : nullptr);
     const char *c4 = reinterpret_cast<const char *>(L4 + q.c);
     const char *cg = reinterpret_cast<const char *>(Lg + q.c);
     const bool solid = q.active && S.walls && (q.y == 0 || q.y == S.ny - 1);
-    // group 0 stores H and V-hat, group 1 (or 0 when alone) the friction
-    // tensor and 1 / (1 + Gamma / 2)
-    const bool do_hv = h == 0, do_t = kSplitG1 == 1 || h == 1;
+    // group 0 stores H and V-hat, group 1 the friction tensor and
+    // 1 / (1 + Gamma / 2)
+    const bool do_hv = h == 0, do_t = h == 1;
     const long long sc = q.active && (do_hv || do_t) ? q.s : 0;
     const float na = glb(S.n)[(long long)a * N + sc];
     const float ja0 = glb(S.j)[o3 + sc], ja1 = glb(S.j)[o3 + N + sc], ja2 = glb(S.j)[o3 + 2 * N + sc];
@@ -388,7 +388,7 @@ k_gather1_tile(const SysDesc<float> *__restrict__ sys,
     for (int b = 0; b < S.M; ++b) {
         const gfloat *__restrict__ gpair = glb(S.g) + (long long)pidx(S.M, a, b) * N;
         int kb, ke;
-        split_range<kSplitG1>(S.sh_cnt[a][b], h, kb, ke);
+        split_range<SPLIT>(S.sh_cnt[a][b], h, kb, ke);
         __syncthreads();
         stage<LM>(S, t, sl, RowOff, RowL, L4, Lg, glb(S.n) + (long long)b * N, glb(S.j) + (long long)b * 3 * N, gpair);
         __syncthreads();
@@ -423,7 +423,7 @@ k_gather1_tile(const SysDesc<float> *__restrict__ sys,
         gam += S.cg[a][b] * (t00 + t11 + t22);
     }
     float part[13] = {mf0, mf1, mf2, dj0, dj1, dj2, gam, T00, T01, T02, T11, T12, T22};
-    split_allreduce<kSplitG1>(lds, part);
+    split_allreduce<SPLIT>(lds, part);
     mf0 = part[0]; mf1 = part[1]; mf2 = part[2]; dj0 = part[3]; dj1 = part[4]; dj2 = part[5]; gam = part[6];
     T00 = part[7]; T01 = part[8]; T02 = part[9]; T11 = part[10]; T12 = part[11]; T22 = part[12];
     if (!q.active || !(do_hv || do_t)) return;
@@ -737,7 +737,7 @@ inline size_t tile_lds_bytes(int TX, int TY, int TZ, int R, int layouts, bool se
     const bool zp = LM != 0;
     const size_t FS = (size_t)plane_pitch(LM, plane) * (TZ + 2 * R);
     const size_t rows = (size_t)(TY + 2 * R) * (TZ + 2 * R);
-    const size_t reduce = (second ? (size_t)kSplitS2 * 3 : (size_t)kSplitG1 * 13) * kBlock * 4;
+    const size_t reduce = (second ? (size_t)kSplitS2 * 3 : (size_t)kSplitG1Max * 13) * kBlock * 4;
     return std::max(16 * FS + (second ? 0 : 16 * ((FS + 3) / 4)) + (zp ? 8 : 4) * rows, reduce);
 }
 

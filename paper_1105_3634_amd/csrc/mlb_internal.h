@@ -123,8 +123,8 @@ struct Launch {
 // variant v: 0 = 16x4x4, 1 = 8x8x4, 2 = 32x4x2 sites.
 constexpr int kTileVariants = 3;
 void tile_dims(int v, int &tx, int &ty, int &tz);
-void launch_gather1_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM, Tables<float> tb,
-                         int reach_max, hipStream_t st);
+void launch_gather1_tile(int v, int split, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM,
+                         Tables<float> tb, int reach_max, hipStream_t st);
 void launch_step2_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM, Tables<float> tb,
                        int reach_max, int parity, int write_force_only, hipStream_t st);
 // contact values on the same tiles (halo = ball reach), one thread per site

@@ -53,7 +53,9 @@ bool prepare_one(int reach, int ball_reach, int ball_total, int maxM)
     if (bytes > 160 * 1024 || cbytes > 160 * 1024) return false;
     // staging gives each thread one halo column
     if (TX + 2 * reach > kBlock || TX + 2 * ball_reach > kBlock) return false;
-    if (hipFuncSetAttribute((const void *)k_gather1_tile<TX, TY, TZ>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    if (hipFuncSetAttribute((const void *)k_gather1_tile<TX, TY, TZ, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)bytes) != hipSuccess ||
+        hipFuncSetAttribute((const void *)k_gather1_tile<TX, TY, TZ, 3>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)bytes) != hipSuccess)
         return false;
     if (hipFuncSetAttribute((const void *)k_contact_tile<TX, TY, TZ>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -80,14 +82,25 @@ void launch_contact_tile(int v, const SysDesc<float> *sys, const int2 *map, int 
     else hipLaunchKernelGGL((k_contact_tile<32, 4, 2>), dim3(nblk), dim3(kBlock), lds, st, sys, map, tb);
 }
 
-void launch_gather1_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM, Tables<float> tb,
-                         int reach_max, hipStream_t st)
+namespace {
+template <int SPLIT>
+void gather1_split(int v, const SysDesc<float> *sys, const int2 *map, dim3 grid, size_t lds, Tables<float> tb,
+                   hipStream_t st)
+{
+    const dim3 block(SPLIT * kBlock);
+    if (v == 0) hipLaunchKernelGGL((k_gather1_tile<16, 4, 4, SPLIT>), grid, block, lds, st, sys, map, tb);
+    else if (v == 1) hipLaunchKernelGGL((k_gather1_tile<8, 8, 4, SPLIT>), grid, block, lds, st, sys, map, tb);
+    else hipLaunchKernelGGL((k_gather1_tile<32, 4, 2, SPLIT>), grid, block, lds, st, sys, map, tb);
+}
+}  // namespace
+
+void launch_gather1_tile(int v, int split, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM,
+                         Tables<float> tb, int reach_max, hipStream_t st)
 {
     const size_t lds = gather_lds_bytes_of(v, reach_max, MLB_G1_LAYOUTS, false);
     const dim3 grid(nblk, maxM);
-    if (v == 0) hipLaunchKernelGGL((k_gather1_tile<16, 4, 4>), grid, dim3(kGather1Threads), lds, st, sys, map, tb);
-    else if (v == 1) hipLaunchKernelGGL((k_gather1_tile<8, 8, 4>), grid, dim3(kGather1Threads), lds, st, sys, map, tb);
-    else hipLaunchKernelGGL((k_gather1_tile<32, 4, 2>), grid, dim3(kGather1Threads), lds, st, sys, map, tb);
+    if (split == 2) gather1_split<2>(v, sys, map, grid, lds, tb, st);
+    else gather1_split<3>(v, sys, map, grid, lds, tb, st);
 }
 
 void launch_step2_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM, Tables<float> tb,

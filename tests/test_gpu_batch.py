@@ -75,10 +75,11 @@ def test_autotuner_restores_initial_state():
     bt = mlb.GpuBatch(mixes, n0s, u0s, precision=32, options=mlb.OPT_TUNE)
     tune = bt.tuning()
     print(f"  tuning: {tune}", flush=True)
-    assert tune["shape"] in (0, 1, 2) and tune["order"] in (0, 1)
-    assert all(v > 0 for v in tune["trial_ms"])
+    assert tune["shape"] in (0, 1, 2) and tune["order"] in (0, 1) and tune["gather1_split"] in (2, 3)
+    assert len(tune["trial_ms"]) == 12 and all(v > 0 for v in tune["trial_ms"])
     assert bt.steps == 0
-    b0 = mlb.GpuBatch(mixes, n0s, u0s, precision=32)
+    b0 = mlb.GpuBatch(mixes, n0s, u0s, precision=32,
+                      options=mlb.opt_tiling(tune["shape"], tune["order"], tune["gather1_split"]))
     bt.step(4)
     b0.step(4)
     for k in range(len(sy)):

@@ -379,21 +379,29 @@ def test_fp32_spectral_100_steps(oracle_lib, name):
 @pytest.mark.parametrize("name", ["walls", "bulk_small"])
 def test_fp32_tilings_agree_bit_for_bit(name):
     """Every tile shape and block order (MLB_OPT_TILING) sums each site's
-    shell lists in the same order, so the float32 states agree bit for bit."""
+    shell lists in the same order, so for one split of the first gather's
+    shell lists over thread groups the float32 states agree bit for bit;
+    the two splits (2 and 3 groups, MLB_OPT_GATHER1_SPLIT) add the partial
+    sums in different groupings and agree to float32 rounding."""
     import paper_1105_3634_amd as mlb
     m, n0, u0 = _case(name)
-    ref = None
-    for shape in range(3):
-        for order in range(2):
-            print(f"[tilings] case={name} shape={shape} order={order}", flush=True)
-            g = _gpu(m, n0, u0, 32, options=mlb.opt_tiling(shape, order))
-            t = g.tuning()
-            assert (t["shape"], t["order"]) == (shape, order)
-            g.step(6)
-            n, j = g.moments()
-            got = (_np(n), _np(j))
-            del g
-            if ref is None:
-                ref = got
-                continue
-            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (shape, order)
+    refs = {}
+    for split in (3, 2):
+        for shape in range(3):
+            for order in range(2):
+                print(f"[tilings] case={name} split={split} shape={shape} order={order}", flush=True)
+                g = _gpu(m, n0, u0, 32, options=mlb.opt_tiling(shape, order, split))
+                t = g.tuning()
+                assert (t["shape"], t["order"], t["gather1_split"]) == (shape, order, split)
+                g.step(6)
+                n, j = g.moments()
+                got = (_np(n), _np(j))
+                del g
+                if split not in refs:
+                    refs[split] = got
+                    continue
+                ref = refs[split]
+                assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (split, shape, order)
+    e = _rel_maxnorm(refs[2][0], refs[3][0])
+    print(f"  split 2 vs 3: density rel diff {e:.2e}", flush=True)
+    assert e < 1e-6
