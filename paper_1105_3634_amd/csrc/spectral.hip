@@ -326,7 +326,12 @@ __global__ void __launch_bounds__(256) k_yz_inverse(YZArgs a)
     }
 }
 
-// LDS bytes of the y/z kernels: two padded complex planes.
+// LDS bytes of the y/z kernels: two padded complex planes.  They run beside
+// the first gather's tiles and must fit in what those leave of a CU's LDS,
+// so the DFT matrices stay in global memory (L2-resident): copied into LDS
+// they tripled the footprint and the overlapped step took 16 % longer.
+constexpr size_t kYZLdsMax = 150 * 1024;
+
 size_t yz_lds_bytes(int ny, int nz)
 {
     const size_t PX = (size_t)nz * (ny + 1), PT = (size_t)ny * (nz + 1);
@@ -337,7 +342,7 @@ size_t yz_lds_bytes(int ny, int nz)
 bool SpectralPlan::fused_fits(int ny, int nz, int M)
 {
     (void)M;
-    return yz_lds_bytes(ny, nz) <= 150 * 1024 && (long long)ny * nz < (1LL << 30);
+    return yz_lds_bytes(ny, nz) <= kYZLdsMax && (long long)ny * nz < (1LL << 30);
 }
 
 // ------------------------------------------------------------------ plan
@@ -419,12 +424,15 @@ void SpectralPlan::launch_yz(int mode, int nfields, const float *in, float *out,
 
 bool SpectralPlan::prepare(int ny, int nz, int M)
 {
+    (void)ny;
+    (void)nz;
     (void)M;
-    const size_t bytes = yz_lds_bytes(ny, nz);
-    return hipFuncSetAttribute((const void *)k_yz_forward, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
-               hipSuccess &&
-           hipFuncSetAttribute((const void *)k_yz_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
-               hipSuccess;
+    // the largest dynamic LDS any plan may ask for: plans of other sizes in
+    // the same process then never find a smaller limit set by this one
+    const int bytes = (int)kYZLdsMax;
+    for (const void *fn : {(const void *)k_yz_forward, (const void *)k_yz_inverse})
+        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess) return false;
+    return true;
 }
 
 void SpectralPlan::build_spectrum(const float *placed, float *s1, float *s2, hipStream_t st) const

@@ -44,25 +44,25 @@ size_t contact_lds_bytes_of(int v, int ball_reach, int ball_total, int maxM)
 }
 
 namespace {
+constexpr size_t kLdsMax = 160 * 1024;   // LDS of one CU
+
 template <int TX, int TY, int TZ>
 bool prepare_one(int reach, int ball_reach, int ball_total, int maxM)
 {
     const size_t bytes = std::max(tile_lds_bytes(TX, TY, TZ, reach, MLB_G1_LAYOUTS, false),
                                   tile_lds_bytes(TX, TY, TZ, reach, MLB_S2_LAYOUTS, true));
     const size_t cbytes = contact_lds_bytes(TX, TY, TZ, ball_reach, ball_total, maxM);
-    if (bytes > 160 * 1024 || cbytes > 160 * 1024) return false;
+    if (bytes > kLdsMax || cbytes > kLdsMax) return false;
     // staging gives each thread one halo column
     if (TX + 2 * reach > kBlock || TX + 2 * ball_reach > kBlock) return false;
-    if (hipFuncSetAttribute((const void *)k_gather1_tile<TX, TY, TZ, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)bytes) != hipSuccess ||
-        hipFuncSetAttribute((const void *)k_gather1_tile<TX, TY, TZ, 3>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)bytes) != hipSuccess)
-        return false;
-    if (hipFuncSetAttribute((const void *)k_contact_tile<TX, TY, TZ>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)cbytes) != hipSuccess)
-        return false;
-    return hipFuncSetAttribute((const void *)k_step2_tile<TX, TY, TZ>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)bytes) == hipSuccess;
+    // the limit is set to the whole LDS of a CU, not to this handle's need:
+    // handles with a smaller reach created later must not lower it under
+    // the launches of a live handle with a larger one
+    for (const void *fn : {(const void *)k_gather1_tile<TX, TY, TZ, 2>, (const void *)k_gather1_tile<TX, TY, TZ, 3>,
+                           (const void *)k_contact_tile<TX, TY, TZ>, (const void *)k_step2_tile<TX, TY, TZ>})
+        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax) != hipSuccess)
+            return false;
+    return true;
 }
 }  // namespace
 

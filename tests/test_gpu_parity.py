@@ -405,3 +405,27 @@ def test_fp32_tilings_agree_bit_for_bit(name):
     e = _rel_maxnorm(refs[2][0], refs[3][0])
     print(f"  split 2 vs 3: density rel diff {e:.2e}", flush=True)
     assert e < 1e-6
+
+
+def test_handles_of_different_reach_coexist():
+    """A live float32 handle with large stencils (bulk diffusion physics,
+    sigma 3 and 4.5, spectral tail) keeps stepping exactly as when alone
+    after handles with smaller stencils and planes have been created: the
+    kernels' LDS limits are never lowered below a live handle's launches."""
+    import torch
+    m, n0, u0 = _case("bulk_small")
+    alone = _gpu(m, n0, u0, 32)
+    alone.step(4)
+    f_alone = alone.populations().clone()
+    del alone
+    big = _gpu(m, n0, u0, 32)
+    big.step(2)
+    ms, ns, us = _case("random_binary")
+    small = _gpu(ms, ns, us, 32)
+    mc, nc, uc = _case("couette_small")
+    other_plane = _gpu(mc, nc, uc, 32)
+    small.step(2)
+    other_plane.step(2)
+    big.step(2)
+    torch.cuda.synchronize()
+    assert torch.equal(big.populations(), f_alone)
