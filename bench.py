@@ -445,6 +445,43 @@ def kolmogorov_leg(mlb, W, packing=0.332, box=(80, 40, 40), pes=(0.0, 1.0, 2.0, 
     return out
 
 
+def sweep_leg(mlb, W, edge, steps, warmup, opts):
+    """Off-cache size sweep: the step-binary physics (sigma 2 and 3, packing
+    0.2, no tail, tau = 1) on an edge^3 periodic box, float32, graph-replayed
+    steps as mlb_step runs them; per-pass times from a second, serialised run
+    with HIP events; algorithmic bytes and flops per pass as for the
+    headline.  At 128^3 the populations alone (2 x 19 x 2 x 4 B per site,
+    both buffers) are 640 MB, beyond the chip's 256 MB last-level cache."""
+    import torch
+
+    mix, n0, u0 = W.config_step_binary(edge, edge, edge)
+    g = mlb.GpuMixture(mix, n0, u0, precision=32, device="cuda:0", options=opts)
+    del n0, u0
+    g.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    g.profile_begin()
+    g.step(steps)
+    passes = g.profile_end()
+    mass, _ = g.conserved()
+    flops, bytes_, _, _ = algorithmic_work(mix, True)
+    ms = {k: v[0] / v[1] for k, v in passes.items() if v[1]}
+    step_bytes = sum(bytes_.values())
+    out = {"workload": f"step_binary_{edge}x{edge}x{edge}", "sites": mix.N, "steps": steps,
+           "ssu_per_s": mix.M * mix.N * steps / elapsed, "ms_per_step": elapsed * 1e3 / steps,
+           "finite": bool(np.all(np.isfinite(mass))),
+           "bytes_per_step_algorithmic": step_bytes,
+           "hbm_gbs_algorithmic": step_bytes * steps / elapsed / 1e9,
+           "hbm_frac_algorithmic": step_bytes * steps / elapsed / 8e12,
+           "passes": {k: {"ms": ms[k], "gbs_algorithmic": bytes_[k] / (ms[k] * 1e-3) / 1e9,
+                          "tflops_method": flops[k] / (ms[k] * 1e-3) / 1e12} for k in ms if k in bytes_},
+           "tuning": g.tuning()}
+    return out
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -551,6 +588,12 @@ def main():
     ap.add_argument("--no-kolmogorov", action="store_true",
                     help="skip the Taylor-dispersion leg in the modulated (Kolmogorov) flow")
     ap.add_argument("--closure-steps", type=int, default=5000)
+    ap.add_argument("--sweep", type=int, default=None, metavar="EDGE",
+                    help="only the off-cache size sweep: step-binary physics on an EDGE^3 box, one JSON line")
+    ap.add_argument("--ensemble-only", action="store_true",
+                    help="only the batched-ensemble leg (profiling runs), one JSON line")
+    ap.add_argument("--ensemble-steps", type=int, default=1000)
+    ap.add_argument("--ensemble-timed", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB elementwise copy (counter calibration for profiles)")
     args = ap.parse_args()
@@ -573,13 +616,19 @@ def main():
         print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4}))
         return
 
-    mix, n0, u0 = W.config_bulk_diffusion()
-    tail_mode = {"auto": mlb.TAIL_AUTO, "direct": mlb.TAIL_DIRECT, "spectral": mlb.TAIL_SPECTRAL}[args.tail]
     if args.tiling:
         vals = [int(v) for v in args.tiling.split(",")]
         opts = mlb.opt_tiling(*vals)
     else:
         opts = mlb.OPT_TUNE
+    if args.sweep:
+        print(json.dumps(sweep_leg(mlb, W, args.sweep, args.steps, args.warmup, opts)), flush=True)
+        return
+    if args.ensemble_only:
+        print(json.dumps(ensemble_leg(mlb, W, steps=args.ensemble_steps, timed=args.ensemble_timed)), flush=True)
+        return
+    mix, n0, u0 = W.config_bulk_diffusion()
+    tail_mode = {"auto": mlb.TAIL_AUTO, "direct": mlb.TAIL_DIRECT, "spectral": mlb.TAIL_SPECTRAL}[args.tail]
     g = mlb.GpuMixture(mix, n0, u0, precision=32, tail_mode=tail_mode, device="cuda:0", options=opts)
     g.step(args.warmup)
     torch.cuda.synchronize()
@@ -651,7 +700,7 @@ def main():
         line["d12"] = acc
     if not args.no_ensemble:
         try:
-            line["ensemble"] = ensemble_leg(mlb, W)
+            line["ensemble"] = ensemble_leg(mlb, W, steps=args.ensemble_steps, timed=args.ensemble_timed)
         except Exception as exc:      # reported in the line; the headline stands on its own
             line["ensemble"] = {"error": f"{type(exc).__name__}: {exc}"}
     if not args.no_taylor:
