@@ -384,7 +384,8 @@ mlb_status mlb_batch_destroy(mlb_batch h);
 typedef struct mlb_net_s *mlb_net;
 
 size_t mlb_net_param_count(void);
-/* Workspace bytes for a network on an nx x ny x nz grid; 0 if invalid. */
+/* Workspace bytes for a network on an nx x ny x nz grid (fewer than 2^29
+ * sites, as for a mixture); 0 if invalid. */
 size_t mlb_net_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t training);
 /* Create with all parameters zero (asynchronous on `stream`). */
 mlb_status mlb_net_create(int32_t nx, int32_t ny, int32_t nz, int32_t training, void *workspace,

@@ -57,6 +57,9 @@ bool plan(mlb_net_s &n, int nx, int ny, int nz, int training)
     if (nx < 1 || ny < 1 || nz < 1 || training < 0 || training > 1) return false;
     n.nx = nx; n.ny = ny; n.nz = nz; n.training = training;
     n.N = (long long)nx * ny * nz;
+    // the convolution's halo-row offsets are 32-bit site indices, as the
+    // lattice's are: the same cap of 2^29 sites
+    if (n.N >= (1LL << 29)) return false;
     n.nblk = (int)((n.N + 255) / 256);
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + std::max<size_t>(bytes, 1)); return o; };

@@ -146,7 +146,8 @@ __device__ __forceinline__ void conv_fetch(const int *RowOff, unsigned gx, int r
 #pragma unroll
     for (int k = 0; k < H; ++k) {
         const unsigned site = (unsigned)RowOff[row0 + (K0 + k) * RSTEP] + gx;
-        pre[k] = *reinterpret_cast<const CT *>(in + site * KIN + chk * (KIN / 4));   // KIN / 4 channels per chunk
+        // KIN / 4 channels per chunk; the element offset in 64 bits (site KIN exceeds 2^32 from 2^27 sites)
+        pre[k] = *reinterpret_cast<const CT *>(in + (size_t)site * KIN + chk * (KIN / 4));
     }
 }
 

@@ -156,6 +156,9 @@ def test_network_sizes():
     assert lib.mlb_net_param_count() == 67392 + 102
     assert lib.mlb_net_workspace_bytes(0, 8, 8, 0) == 0
     assert lib.mlb_net_workspace_bytes(8, 8, 8, 1) > lib.mlb_net_workspace_bytes(8, 8, 8, 0) > 0
+    # the lattice's cap of 2^29 sites holds for the network's grid as well
+    assert lib.mlb_net_workspace_bytes(1024, 1024, 511, 0) > 0
+    assert lib.mlb_net_workspace_bytes(1024, 1024, 512, 0) == 0
 
 
 def _stability(sigma, n, scheme, tau=1.0, eps=None):
