@@ -253,7 +253,7 @@ def closure_leg(mlb, W, steps=5000, train_box=(192, 12, 12)):
     }
 
 
-def ensemble_leg(mlb, W, steps=1000, timed=200):
+def ensemble_leg(mlb, W, steps=1000, timed=200, opts=None):
     """Batched ensemble: 64 independent periodic binary systems (edges from
     {32, 48, 64, 96}, x1, packing and sigma_22 drawn from a seed) advanced
     by shared launches with the autotuned tile shape and the graph-captured
@@ -264,7 +264,7 @@ def ensemble_leg(mlb, W, steps=1000, timed=200):
     members = W.config_ensemble()
     mixes = [m.mixture for m in members]
     b = mlb.GpuBatch(mixes, [m.n0 for m in members], [m.u0 for m in members], precision=32,
-                     options=mlb.OPT_TUNE, device="cuda:0")
+                     options=mlb.OPT_TUNE if opts is None else opts, device="cuda:0")
     ssu_step = sum(len(m.sigma) * m.N for m in mixes)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -445,6 +445,40 @@ def kolmogorov_leg(mlb, W, packing=0.332, box=(80, 40, 40), pes=(0.0, 1.0, 2.0, 
     return out
 
 
+def network_leg(mlb, W, reps=20):
+    """The closure network's kernels alone on the 192x64x64 grid (profiling
+    runs): `reps` forward passes and `reps` training steps (forward, both
+    backward products, Adam) on seeded random inputs and targets, with
+    He-initialised parameters; throughput against the bfloat16 MFMA peak."""
+    import torch
+
+    from paper_1105_3634_amd.closure_train import init_params
+
+    mix, _, _ = W.config_closure_physics()
+    shape = mix.shape()
+    net = mlb.GpuNet(shape, training=True)
+    net.set_params(init_params(0))
+    gen = torch.Generator(device="cuda:0").manual_seed(7)
+    x = torch.randn((8,) + shape, generator=gen, device="cuda:0")
+    t = torch.randn((6,) + shape, generator=gen, device="cuda:0")
+    net.forward(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.forward(x)
+    torch.cuda.synchronize()
+    fwd = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.train_step(x, t, lr=1e-4, want_loss=False)
+    torch.cuda.synchronize()
+    trn = (time.perf_counter() - t0) / reps
+    macs = 27 * (8 * 32 + 32 * 32 + 32 * 32 + 32 * 6) * mix.N
+    return {"workload": f"network_{mix.nx}x{mix.ny}x{mix.nz}", "forward_ms": fwd * 1e3, "train_step_ms": trn * 1e3,
+            "forward_tflops": 2.0 * macs / fwd / 1e12, "train_tflops": 6.0 * macs / trn / 1e12,
+            "peak_bf16_tflops": BF16_PEAK_TFLOPS}
+
+
 def sweep_leg(mlb, W, edge, steps, warmup, opts):
     """Off-cache size sweep: the step-binary physics (sigma 2 and 3, packing
     0.2, no tail, tau = 1) on an edge^3 periodic box, float32, graph-replayed
@@ -592,6 +626,8 @@ def main():
                     help="only the off-cache size sweep: step-binary physics on an EDGE^3 box, one JSON line")
     ap.add_argument("--ensemble-only", action="store_true",
                     help="only the batched-ensemble leg (profiling runs), one JSON line")
+    ap.add_argument("--network-only", action="store_true",
+                    help="only the closure network's kernels (forward and training steps, --steps of each)")
     ap.add_argument("--ensemble-steps", type=int, default=1000)
     ap.add_argument("--ensemble-timed", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -625,7 +661,11 @@ def main():
         print(json.dumps(sweep_leg(mlb, W, args.sweep, args.steps, args.warmup, opts)), flush=True)
         return
     if args.ensemble_only:
-        print(json.dumps(ensemble_leg(mlb, W, steps=args.ensemble_steps, timed=args.ensemble_timed)), flush=True)
+        print(json.dumps(ensemble_leg(mlb, W, steps=args.ensemble_steps, timed=args.ensemble_timed, opts=opts)),
+              flush=True)
+        return
+    if args.network_only:
+        print(json.dumps(network_leg(mlb, W, reps=args.steps)), flush=True)
         return
     mix, n0, u0 = W.config_bulk_diffusion()
     tail_mode = {"auto": mlb.TAIL_AUTO, "direct": mlb.TAIL_DIRECT, "spectral": mlb.TAIL_SPECTRAL}[args.tail]
