@@ -38,6 +38,7 @@ class _Params(C.Structure):
         ("walls_y", C.c_int32),
         ("wall_ux", C.c_double * 2),
         ("scheme", C.c_int32),
+        ("mass", C.c_double * MAX_SPECIES),
     ]
 
 
@@ -56,7 +57,7 @@ def _load():
     lib.or_init.argtypes = [C.c_void_p, dp, dp, dp]
     lib.or_step.argtypes = [C.c_void_p, dp, dp, C.c_int]
     lib.or_fields.argtypes = [C.c_void_p, dp] + [dp] * 9
-    lib.or_collide_site.argtypes = [C.c_void_p, dp, C.c_double, dp, dp, dp, dp]
+    lib.or_collide_site.argtypes = [C.c_void_p, C.c_int, dp, C.c_double, dp, dp, dp, dp]
     lib.or_stencil.restype = C.c_int
     lib.or_stencil.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), dp]
     lib.or_pair_constants.argtypes = [C.c_void_p, C.c_int, C.c_int, dp]
@@ -106,6 +107,8 @@ class Oracle:
         p.walls_y = 1 if m.walls_y else 0
         p.wall_ux[0], p.wall_ux[1] = m.wall_ux
         p.scheme = m.scheme
+        for a, ma in enumerate(m.mass_vector()):
+            p.mass[a] = float(ma)
         self._h = lib.or_create(C.byref(p))
         if not self._h:
             raise ValueError("oracle rejected the mixture parameters")
@@ -222,13 +225,14 @@ class Oracle:
         return d["n"], d["j"]
 
     # ---------------------------------------------------------------- hooks
-    def collide_site(self, fi, na, ja, u, Na) -> np.ndarray:
+    def collide_site(self, fi, na, ja, u, Na, species: int = 0) -> np.ndarray:
+        """f*_i of one site of `species` (its mass sets the equilibrium's theta)."""
         fi = np.ascontiguousarray(fi, dtype=np.float64)
         ja = np.ascontiguousarray(ja, dtype=np.float64)
         u = np.ascontiguousarray(u, dtype=np.float64)
         Na = np.ascontiguousarray(Na, dtype=np.float64)
         out = np.empty(Q)
-        _lib.or_collide_site(self._h, _ptr(fi), float(na), _ptr(ja), _ptr(u), _ptr(Na), _ptr(out))
+        _lib.or_collide_site(self._h, int(species), _ptr(fi), float(na), _ptr(ja), _ptr(u), _ptr(Na), _ptr(out))
         return out
 
     def stencil(self, which: str, a: int, b: int = 0):

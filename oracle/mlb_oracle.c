@@ -52,6 +52,7 @@ typedef struct {
     int32_t walls_y;                 /* 1: solid layers at y=0 and y=ny-1  */
     double wall_ux[2];               /* x velocity of the y=0 / y=ny-1 wall */
     int32_t scheme;                  /* 0: CN-J1, 1: forward Euler         */
+    double mass[OR_MAXS];            /* species masses m_a (> 0)           */
 } or_params;
 
 /* D3Q19 in canonical order: rest, +-x, +-y, +-z, then the xy, xz, yz edges.
@@ -184,6 +185,11 @@ typedef struct {
     double ck[OR_MAXS][OR_MAXS]; /* dissipative pair form: kappa / 2        */
     double dd[OR_MAXS][OR_MAXS]; /* BMCSL d_ab = s_a s_b / (s_a + s_b)      */
     double s2[OR_MAXS], s3[OR_MAXS]; /* (pi/6) sigma^2, (pi/6) sigma^3      */
+    /* per species: 1/m_a; m_a/kT = 1/theta_a (theta_a = kT/m_a, the thermal
+     * speed^2 of eq. psia); (9/2)(theta_a - 1/3), the weight of the Hermite
+     * temperature term of the lattice equilibrium (0 when theta_a is the
+     * lattice's c_s^2 = 1/3, i.e. m_a = 1 at kT = 1/3) */
+    double im[OR_MAXS], ith[OR_MAXS], dth[OR_MAXS];
     /* work fields */
     double *n, *j, *u, *g, *vh, *H, *N2, *Nmf, *Ntl, *Nex, *Dold, *Dnew, *Gam;
     /* optional externally supplied attractive field sum_b (K_ab * n_b) [M][3][N] */
@@ -203,6 +209,8 @@ static int pair_index(int M, int a, int b)
 or_ctx *or_create(const or_params *p)
 {
     if (p->M < 1 || p->M > OR_MAXS || p->nx < 1 || p->ny < 1 || p->nz < 1) return NULL;
+    for (int a = 0; a < p->M; ++a)
+        if (!(p->mass[a] > 0.0)) return NULL;
     or_ctx *c = (or_ctx *)calloc(1, sizeof(or_ctx));
     c->p = *p;
     c->M = p->M;
@@ -212,6 +220,10 @@ or_ctx *or_create(const or_params *p)
     c->om1 = 1.0 - c->omega;
     const double kT = p->kT;
     for (int a = 0; a < c->M; ++a) {
+        double ma = p->mass[a];
+        c->im[a] = 1.0 / ma;
+        c->ith[a] = ma / kT;
+        c->dth[a] = 4.5 * (kT / ma - 1.0 / 3.0);
         double sg = p->sigma[a];
         c->s2[a] = (M_PI / 6.0) * (sg * sg);
         c->s3[a] = (M_PI / 6.0) * ((sg * sg) * sg);
@@ -221,8 +233,8 @@ or_ctx *or_create(const or_params *p)
         for (int b = 0; b < c->M; ++b) {
             double sa = p->sigma[a], sb = p->sigma[b];
             double sab = 0.5 * (sa + sb);
-            /* unit masses: reduced mass m_a m_b / (m_a + m_b) = 1/2 */
-            double mu = 0.5;
+            /* reduced mass of the colliding pair (below eq. viscousforce) */
+            double mu = (p->mass[a] * p->mass[b]) / (p->mass[a] + p->mass[b]);
             build_list(&c->shell[a][b], 0, sab, 0.0);
             double what = (4.0 * M_PI) / (double)c->shell[a][b].full;
             double kap = ((2.0 * (sab * sab)) * sqrt((2.0 * mu * kT) / M_PI)) * what;
@@ -373,14 +385,15 @@ static void moments(or_ctx *c, const double *f)
             }
             c->n[(size_t)a * N + s] = na;
             for (int d = 0; d < 3; ++d) c->j[((size_t)a * 3 + d) * N + s] = ja[d];
-            /* unit masses: rho_a = n_a and the barycentric velocity is
-             * sum_a j_a / sum_a n_a (Sec. 2, eq. massdensity and below) */
+            /* mass densities rho_a = m_a n_a; the barycentric velocity is
+             * sum_a m_a j_a / sum_a m_a n_a (Sec. 2, eq. massdensity and below) */
+            const double ma = c->p.mass[a];
             if (a == 0) {
-                nt = na;
-                jt[0] = ja[0]; jt[1] = ja[1]; jt[2] = ja[2];
+                nt = ma * na;
+                jt[0] = ma * ja[0]; jt[1] = ma * ja[1]; jt[2] = ma * ja[2];
             } else {
-                nt = nt + na;
-                jt[0] = jt[0] + ja[0]; jt[1] = jt[1] + ja[1]; jt[2] = jt[2] + ja[2];
+                nt = nt + ma * na;
+                jt[0] = jt[0] + ma * ja[0]; jt[1] = jt[1] + ma * ja[1]; jt[2] = jt[2] + ma * ja[2];
             }
         }
         for (int d = 0; d < 3; ++d) c->u[(size_t)d * N + s] = (nt != 0.0) ? jt[d] / nt : 0.0;
@@ -449,8 +462,9 @@ static void contact_values(or_ctx *c)
  *     Gam_a = (1/3) sum_b kappa_ab sum_e G n_b(r+e)
  * with G = (g_ab(r) + g_ab(r+e)) / 2 and w_hat = 4 pi / |S_ab|.
  * The predictor takes the local diagonal of the velocity-dependent force
- * implicitly (one Jacobi sweep of a Crank-Nicolson step):
- *   V_a = [j_a + Nc_a + D_a[u] + Gam_a j_a / 2] / [n_a (1 + Gam_a / 2)]
+ * implicitly (one Jacobi sweep of a Crank-Nicolson step); a force density
+ * changes the number flux j_a at the rate 1/m_a (eq. momentcomponent):
+ *   V_a = [j_a + (Nc_a + D_a[u]) / m_a + Gam_a j_a / (2 m_a)] / [n_a (1 + Gam_a / (2 m_a))]
  *   H_a = Nc_a + D_a[u] / 2,   Nc_a = Nmf_a + Ntl_a + n_a F^a. */
 static void gather_one(or_ctx *c)
 {
@@ -532,7 +546,8 @@ static void gather_one(or_ctx *c)
             }
             if (c->tail_ext)
                 for (int d = 0; d < 3; ++d) tl[d] = c->tail_ext[o3 + (size_t)d * N + s];
-            double hg = 0.5 * gam;
+            const double im = c->im[a];
+            double hg = (0.5 * gam) * im;
             for (int d = 0; d < 3; ++d) {
                 double Nmf = na * mf[d];
                 double Ntl = na * tl[d];
@@ -551,7 +566,7 @@ static void gather_one(or_ctx *c)
                 } else {
                     c->H[o3 + d * N + s] = Nc + 0.5 * Dd;
                     c->vh[o3 + d * N + s] =
-                        (na != 0.0) ? (((ja[d] + Nc) + Dd) + hg * ja[d]) / (na * (1.0 + hg)) : 0.0;
+                        (na != 0.0) ? (((ja[d] + im * Nc) + im * Dd) + hg * ja[d]) / (na * (1.0 + hg)) : 0.0;
                 }
             }
             c->Gam[(size_t)a * N + s] = gam;
@@ -621,25 +636,40 @@ static void gather_two(or_ctx *c)
 }
 
 /* ----------------- S5: orthogonalised BGK collision plus the field term.
- * With E_i(u) = 1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u (second-order Hermite
- * form of eq. psia at the barycentric u, kT/m = 1/3):
- *   psi_perp_i = w_i E_i [n_a + 3 (j_a - n_a u).(c_i - u)]     eq. (prefactor)
- *   S_i        = w_i E_i 3 (c_i - u).N_a                         eq. (evolution)
- *   f*_i = (1 - omega) f_i + omega psi_perp_i + S_i. */
-static inline double post_collision(const or_ctx *c, int i, double fi, double na, const double ja[3],
-                                    const double u[3], const double Na[3])
+ * The Maxwellian of eq. (psia) at the barycentric u with thermal speed^2
+ * theta_a = kT/m_a, in second-order Hermite form on the lattice
+ * (c_s^2 = 1/3):
+ *   E_i(u) = 1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u + (9/2)(theta_a - 1/3)(c.c - 1)
+ * (the last term gives sum_i w_i E_i c c = theta_a I + u u; it vanishes for
+ * theta_a = 1/3), and
+ *   psi_perp_i = w_i E_i [n_a + (m_a/kT) (j_a - n_a u).(c_i - u)]  eq. (prefactor)
+ *   S_i        = w_i E_i (c_i - u).N_a / kT                      eq. (evolution)
+ *   f*_i = (1 - omega) f_i + omega psi_perp_i + S_i.
+ * psi_perp carries n_a and j_a; S_i adds no mass and N_a / m_a to j_a. */
+static inline double hermite_E(const or_ctx *c, int a, int i, const double u[3])
 {
     double uu = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
     double cx = (double)C[i][0], cy = (double)C[i][1], cz = (double)C[i][2];
     double cu = (cx * u[0] + cy * u[1]) + cz * u[2];
     double E = ((1.0 + 3.0 * cu) + (4.5 * cu) * cu) - 1.5 * uu;
-    double wE = weight_of(i) * E;
+    if (c->dth[a] != 0.0) {
+        int c2 = C[i][0] * C[i][0] + C[i][1] * C[i][1] + C[i][2] * C[i][2];
+        E = E + c->dth[a] * (double)(c2 - 1);
+    }
+    return E;
+}
+
+static inline double post_collision(const or_ctx *c, int a, int i, double fi, double na, const double ja[3],
+                                    const double u[3], const double Na[3])
+{
+    double cx = (double)C[i][0], cy = (double)C[i][1], cz = (double)C[i][2];
+    double wE = weight_of(i) * hermite_E(c, a, i, u);
     double m0 = cx - u[0], m1 = cy - u[1], m2 = cz - u[2];
     double v0 = ja[0] - na * u[0], v1 = ja[1] - na * u[1], v2 = ja[2] - na * u[2];
     double dotv = (v0 * m0 + v1 * m1) + v2 * m2;
     double dotN = (m0 * Na[0] + m1 * Na[1]) + m2 * Na[2];
-    double psi = wE * (na + 3.0 * dotv);
-    double src = wE * (3.0 * dotN);
+    double psi = wE * (na + c->ith[a] * dotv);
+    double src = wE * (3.0 * dotN);   /* 3 = 1/kT */
     return (c->om1 * fi + c->omega * psi) + src;
 }
 
@@ -664,7 +694,7 @@ static void collide_stream(or_ctx *c, const double *f, double *fo)
             double ja[3] = {c->j[o3 + s], c->j[o3 + N + s], c->j[o3 + 2 * N + s]};
             double Na[3] = {c->N2[o3 + s], c->N2[o3 + N + s], c->N2[o3 + 2 * N + s]};
             for (int i = 0; i < OR_Q; ++i) {
-                double fs = post_collision(c, i, fa[(size_t)i * N + s], na, ja, u, Na);
+                double fs = post_collision(c, a, i, fa[(size_t)i * N + s], na, ja, u, Na);
                 int yy = y + C[i][1];
                 if (c->p.walls_y && (yy == 0 || yy == ny - 1)) {
                     double uw = (yy == 0) ? c->p.wall_ux[0] : c->p.wall_ux[1];
@@ -697,12 +727,13 @@ void or_init(or_ctx *c, const double *n0, const double *u0, double *f)
         double jj[OR_MAXS][3];
         for (int a = 0; a < M; ++a) {
             double na = n0[(size_t)a * N + s];
+            const double ma = c->p.mass[a];
             for (int d = 0; d < 3; ++d) jj[a][d] = na * u0[((size_t)a * 3 + d) * N + s];
             if (a == 0) {
-                nt = na; jt[0] = jj[a][0]; jt[1] = jj[a][1]; jt[2] = jj[a][2];
+                nt = ma * na; jt[0] = ma * jj[a][0]; jt[1] = ma * jj[a][1]; jt[2] = ma * jj[a][2];
             } else {
-                nt = nt + na;
-                jt[0] = jt[0] + jj[a][0]; jt[1] = jt[1] + jj[a][1]; jt[2] = jt[2] + jj[a][2];
+                nt = nt + ma * na;
+                jt[0] = jt[0] + ma * jj[a][0]; jt[1] = jt[1] + ma * jj[a][1]; jt[2] = jt[2] + ma * jj[a][2];
             }
         }
         double u[3];
@@ -711,15 +742,12 @@ void or_init(or_ctx *c, const double *n0, const double *u0, double *f)
             double na = n0[(size_t)a * N + s];
             for (int i = 0; i < OR_Q; ++i) {
                 /* omega = 1 form of the collision with no field: psi_perp */
-                double uu = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
                 double cx = (double)C[i][0], cy = (double)C[i][1], cz = (double)C[i][2];
-                double cu = (cx * u[0] + cy * u[1]) + cz * u[2];
-                double E = ((1.0 + 3.0 * cu) + (4.5 * cu) * cu) - 1.5 * uu;
-                double wE = weight_of(i) * E;
+                double wE = weight_of(i) * hermite_E(c, a, i, u);
                 double m0 = cx - u[0], m1 = cy - u[1], m2 = cz - u[2];
                 double v0 = jj[a][0] - na * u[0], v1 = jj[a][1] - na * u[1], v2 = jj[a][2] - na * u[2];
                 double dotv = (v0 * m0 + v1 * m1) + v2 * m2;
-                f[((size_t)a * OR_Q + i) * N + s] = wE * (na + 3.0 * dotv);
+                f[((size_t)a * OR_Q + i) * N + s] = wE * (na + c->ith[a] * dotv);
             }
         }
     }
@@ -811,12 +839,12 @@ void or_fields(or_ctx *c, const double *f, double *n, double *j, double *u, doub
     if (gam) memcpy(gam, c->Gam, sizeof(double) * M * N);
 }
 
-/* Collision of a single site (test hook for the moment identities):
- * returns f*_i, i = 0..18, for given f_i, n_a, j_a, u and N_a. */
-void or_collide_site(or_ctx *c, const double *fi, double na, const double *ja, const double *u,
+/* Collision of a single site of species a (test hook for the moment
+ * identities): returns f*_i, i = 0..18, for given f_i, n_a, j_a, u and N_a. */
+void or_collide_site(or_ctx *c, int a, const double *fi, double na, const double *ja, const double *u,
                      const double *Na, double *out)
 {
-    for (int i = 0; i < OR_Q; ++i) out[i] = post_collision(c, i, fi[i], na, ja, u, Na);
+    for (int i = 0; i < OR_Q; ++i) out[i] = post_collision(c, a, i, fi[i], na, ja, u, Na);
 }
 
 /* Stencil export (test hook).  which: 0 shell(a,b), 1 tail(a,b), 2 ball(a).

@@ -21,7 +21,12 @@ exactly a small complex matrix:
                    predictor V, then the Crank-Nicolson average (or forward
                    Euler)
   collision        f* = w_i [dn + 3 c_i . (dj + N)]   (omega = 1, linearised
-                   orthogonalised equilibrium plus field term)
+                   orthogonalised equilibrium plus field term, unit masses);
+                   with masses m_a (thermal speed^2 theta_a = kT / m_a):
+                   f* = w_i h_i [dn + (m_a/kT) c_i.(dj - n du) + 3 c_i.N]
+                        + 3 w_i n c_i.du,  h_i = 1 + (9/2)(theta_a - 1/3)(c_i^2 - 1),
+                   du = sum_b m_b dj_b / sum_b m_b n_b the barycentric
+                   velocity, and the predictor's force over m_a
   streaming        f'(x) = f*(x - c_x)  ->  exp(-i k c_x)
 
 Eigenvalues of that matrix give the decay per step of every mode: composition
@@ -35,7 +40,6 @@ from typing import Optional, Sequence
 import numpy as np
 
 KT = 1.0 / 3.0
-MU = 0.5            # reduced mass of two unit masses
 
 # D3Q19 velocities and weights (any order: only sums over them enter)
 _C = [(0, 0, 0)] + [(s * (d == 0), s * (d == 1), s * (d == 2)) for d in range(3) for s in (1, -1)]
@@ -87,10 +91,15 @@ class LinearScheme:
     eps_ab (cutoff rc sigma_ab), scheme "cnj1" or "fe"."""
 
     def __init__(self, sigma: Sequence[float], n0: Sequence[float], eps: Optional[np.ndarray] = None,
-                 rc: float = 2.5, scheme: str = "cnj1"):
+                 rc: float = 2.5, scheme: str = "cnj1", mass: Optional[Sequence[float]] = None):
         self.sig = np.asarray(sigma, float)
         self.n0 = np.asarray(n0, float)
         self.M = len(self.sig)
+        self.mass = np.ones(self.M) if mass is None else np.asarray(mass, float)
+        self.mu = np.outer(self.mass, self.mass) / np.add.outer(self.mass, self.mass)
+        self.rho = float((self.mass * self.n0).sum())
+        self.ith = self.mass / KT                       # 1 / theta_a
+        self.dth = 4.5 * (KT / self.mass - 1.0 / 3.0)   # weight of the temperature term
         self.eps = np.zeros((self.M, self.M)) if eps is None else np.asarray(eps, float)
         self.rc = rc
         self.scheme = scheme
@@ -110,7 +119,7 @@ class LinearScheme:
             self.dg[:, :, c] = (bmcsl(up, self.sig) - bmcsl(dn, self.sig)) / (2 * h)
         # shell weight 4 pi / |S| and kappa = 2 s^2 sqrt(2 mu kT / pi) w_hat
         self.what = np.array([[4 * math.pi / len(self.shells[a][b]) for b in range(M)] for a in range(M)])
-        self.kappa = 2 * self.sab ** 2 * math.sqrt(2 * MU * KT / math.pi) * self.what
+        self.kappa = 2 * self.sab ** 2 * np.sqrt(2 * self.mu * KT / math.pi) * self.what
 
     # ------------------------------------------------------------ stencil sums
     def _unit(self, e):
@@ -194,7 +203,7 @@ class LinearScheme:
         sqrt(2 mu kT / pi), c = 4 pi / 15 (perpendicular) or 4 pi / 5 (parallel);
         returns the coefficient of -q^2 u."""
         c = 4 * math.pi / 5 if comp == 0 else 4 * math.pi / 15
-        return np.array([c * sum(self.sab[a, b] ** 4 * self.n0[b] * self.g[a, b] * math.sqrt(2 * MU * KT / math.pi)
+        return np.array([c * sum(self.sab[a, b] ** 4 * self.n0[b] * self.g[a, b] * math.sqrt(2 * self.mu[a, b] * KT / math.pi)
                                  for b in range(self.M)) for a in range(self.M)])
 
     # ------------------------------------------------------------ one step
@@ -227,37 +236,51 @@ class LinearScheme:
         if self.scheme == "fe":
             return Nc + Dold
         Gam = np.array([sum(kg[a, b] * self.n0[b] * Sn[a, b] for b in range(M)) for a in range(M)])
-        V = (dj + Nc + Dold + 0.5 * Gam * dj) / (self.n0 * (1 + 0.5 * Gam))
+        hg = 0.5 * Gam / self.mass
+        V = (dj + (Nc + Dold) / self.mass + hg * dj) / (self.n0 * (1 + hg))
         return Nc + 0.5 * Dold + 0.5 * pair_form_v(V)
+
+    def _lattice_sums(self, k, comp):
+        """sum_i w_i ph_i c^p (and with the temperature factor c^2 - 1) for
+        the streaming phase ph_i = exp(-i k c_x) and c = c_comp."""
+        ph = np.exp(-1j * k * CV[:, 0])
+        cc = CV[:, comp]
+        t = (CV ** 2).sum(1) - 1.0
+        S = [(WV * cc ** p * ph).sum() for p in range(3)]
+        T = [(WV * t * cc ** p * ph).sum() for p in range(3)]
+        return S, T
+
+    def _collide_stream(self, k, comp, dn, dj, N):
+        """Moments (dn', dj'_comp) after the linearised collision and streaming
+        of the wave exp(i k x), given the force densities N (component comp)."""
+        (S0, S1, S2), (T0, T1, T2) = self._lattice_sums(k, comp)
+        du = (self.mass * dj).sum() / self.rho
+        X = self.ith * (dj - self.n0 * du) + 3 * N           # per species
+        h = self.dth
+        dn_new = (S0 + h * T0) * dn + (S1 + h * T1) * X + 3 * S1 * self.n0 * du
+        dj_new = (S1 + h * T1) * dn + (S2 + h * T2) * X + 3 * S2 * self.n0 * du
+        return dn_new, dj_new
 
     def longitudinal(self, k: float) -> np.ndarray:
         """One step on (dn_0..dn_{M-1}, dj_0,x..dj_{M-1},x)."""
         M = self.M
-        ph = np.exp(-1j * k * CV[:, 0])
-        A0 = (WV * ph).sum()
-        A1 = (WV * CV[:, 0] * ph).sum()
-        A2 = (WV * CV[:, 0] ** 2 * ph).sum()
         T = np.zeros((2 * M, 2 * M), complex)
         for col in range(2 * M):
             v = np.zeros(2 * M, complex)
             v[col] = 1.0
             dn, dj = v[:M], v[M:]
-            P = dj + self._forces(k, dn, dj, 0)
-            T[:M, col] = A0 * dn + 3 * A1 * P
-            T[M:, col] = A1 * dn + 3 * A2 * P
+            T[:M, col], T[M:, col] = self._collide_stream(k, 0, dn, dj, self._forces(k, dn, dj, 0))
         return T
 
     def transverse(self, k: float) -> np.ndarray:
         """One step on (dj_0,y .. dj_{M-1},y) for a wave along x."""
         M = self.M
-        ph = np.exp(-1j * k * CV[:, 0])
-        B2 = (WV * CV[:, 1] ** 2 * ph).sum()
+        zero = np.zeros(M, complex)
         T = np.zeros((M, M), complex)
         for col in range(M):
             dj = np.zeros(M, complex)
             dj[col] = 1.0
-            P = dj + self._forces(k, np.zeros(M, complex), dj, 1)
-            T[:, col] = 3 * B2 * P
+            T[:, col] = self._collide_stream(k, 1, zero, dj, self._forces(k, zero, dj, 1))[1]
         return T
 
     def transverse_forced(self, k: float) -> np.ndarray:
@@ -266,10 +289,8 @@ class LinearScheme:
         Kolmogorov flow that drives the modulated shear of Sec. 5.2): the
         fixed point of j' = T j + f."""
         M = self.M
-        ph = np.exp(-1j * k * CV[:, 0])
-        B2 = (WV * CV[:, 1] ** 2 * ph).sum()
         zero = np.zeros(M, complex)
-        f = 3 * B2 * self._forces(k, zero, zero, 1, fext=1.0)
+        f = self._collide_stream(k, 1, zero, zero, self._forces(k, zero, zero, 1, fext=1.0))[1]
         return np.linalg.solve(np.eye(M) - self.transverse(k), f).real
 
     def shear_viscosity(self, L: int) -> float:
@@ -296,7 +317,7 @@ class LinearScheme:
                 else:
                     m4 = s * s * 4 * math.pi / 15
                 # (4/15) sqrt(2 pi mu kT) s^4 = 2 s^2 sqrt(2 mu kT / pi) (1/2) s^2 (4 pi / 15)
-                eta += 2 * s * s * math.sqrt(2 * MU * KT / math.pi) * 0.5 * m4 * self.g[a, b] * self.n0[a] * self.n0[b]
+                eta += 2 * s * s * math.sqrt(2 * self.mu[a, b] * KT / math.pi) * 0.5 * m4 * self.g[a, b] * self.n0[a] * self.n0[b]
         return (tau - 0.5) * KT + eta / self.n0.sum()
 
     # ------------------------------------------------------------- modes
@@ -375,7 +396,7 @@ def hydrodynamics(lin: LinearScheme, tau: float = 1.0) -> dict:
         return rho * (v[0] - v[1])
 
     muD = dmu[0] - dmu[1]
-    gam = sum(8 / 3 * math.sqrt(2 * math.pi * MU * KT) * lin.g[0, 1] * lin.sab[0, 1] ** 2 * n0[b] for b in range(2))
+    gam = sum(8 / 3 * math.sqrt(2 * math.pi * lin.mu[0, 1] * KT) * lin.g[0, 1] * lin.sab[0, 1] ** 2 * n0[b] for b in range(2))
     coupling = d_rho(muD) * d_c(dP) / d_rho(dP)
     nul_c = 0.0
     for a in range(2):
@@ -383,7 +404,7 @@ def hydrodynamics(lin: LinearScheme, tau: float = 1.0) -> dict:
             e = lin.shells[a][b]
             r2 = (e ** 2).sum(1)
             m4 = lin.what[a, b] * (r2 * (e[:, 0] ** 2 / r2) ** 2).sum()
-            nul_c += n0[a] * 2 * lin.sab[a, b] ** 2 * math.sqrt(2 * MU * KT / math.pi) * lin.g[a, b] * n0[b] * 0.5 * m4
+            nul_c += n0[a] * 2 * lin.sab[a, b] ** 2 * math.sqrt(2 * lin.mu[a, b] * KT / math.pi) * lin.g[a, b] * n0[b] * 0.5 * m4
     nul = 2 * (tau - 0.5) * KT + nul_c / rho
     return {"cs": math.sqrt(d_rho(dP)), "gamma": gam, "D_P": c * (1 - c) * (d_c(muD) - coupling) / gam,
             "D_0": c * (1 - c) * d_c(muD) / gam, "Gamma": 0.5 * (nul + c * (1 - c) * coupling / gam),

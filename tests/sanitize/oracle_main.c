@@ -55,7 +55,10 @@ static or_params base(int nx, int ny, int nz, int M)
     p.tau = 1.0;
     p.kT = 1.0 / 3.0;
     p.rc_factor = 2.5;
-    for (int a = 0; a < M; ++a) p.sigma[a] = 2.0 + a;
+    for (int a = 0; a < M; ++a) {
+        p.sigma[a] = 2.0 + a;
+        p.mass[a] = 1.0;
+    }
     return p;
 }
 
@@ -69,7 +72,8 @@ int main(void)
     for (int i = 0; i < 9; ++i) p.eps[i] = 0.1;
     p.walls_y = 1;
     p.wall_ux[0] = -0.02, p.wall_ux[1] = 0.02;
-    bad |= run("ternary between moving walls, tails, force profile", p, 1, 4);
+    p.mass[0] = 0.7, p.mass[1] = 1.0, p.mass[2] = 2.5;
+    bad |= run("ternary between moving walls, tails, force profile, unequal masses", p, 1, 4);
     p = base(10, 10, 10, 2);
     p.scheme = 1, p.tau = 0.8;
     bad |= run("forward Euler", p, 0, 4);

@@ -39,10 +39,16 @@ class Mixture:
     wall_ux: Tuple[float, float] = (0.0, 0.0)  # x velocity of the y=0 / y=ny-1 wall
     scheme: int = SCHEME_CN_J1
     name: str = ""
+    mass: Optional[Tuple[float, ...]] = None  # m_a (None: all 1); kT / m_a is the species' thermal speed^2
 
     @property
     def M(self) -> int:
         return len(self.sigma)
+
+    def mass_vector(self) -> np.ndarray:
+        if self.mass is None:
+            return np.ones(self.M)
+        return np.asarray(self.mass, dtype=np.float64).reshape(self.M)
 
     @property
     def N(self) -> int:
