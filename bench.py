@@ -569,6 +569,46 @@ def tail_study_leg(mlb, W, steps=2000):
     return out
 
 
+def mass_study_leg(mlb, W, steps=3000):
+    """Unequal species masses (Sec. 2, eqs. psia, prefactor; Sec. 4.1,
+    eqs. gammasymmetrized1 and mutualdiffusion): equal-diameter binaries
+    (sigma 3, packing 0.2, c = 1/2, composition mode of amplitude 0.02 on
+    192x8x8) with six mass pairs in one float32 batch; D of each from its
+    mode record, against D^AB = kT / ((8/3) n sqrt(2 pi mu_AB kT) g sigma^2),
+    g the Carnahan-Starling contact value, which depends on the masses only
+    through the reduced mass mu_AB."""
+    import torch
+
+    masses = [(1.0, 1.0), (2.0, 2.0), (0.7, 0.7), (0.7, 2.0), (2.5, 0.7), (1.0, 2.5)]
+    sigma, xi = 3.0, 0.2
+    n = W.number_density(xi, (0.5, 0.5), (sigma, sigma))
+    mixes, n0s, u0s = [], [], []
+    for mass in masses:
+        m = W.Mixture(192, 8, 8, sigma=(sigma, sigma), mass=mass, name=f"mass_{mass[0]:g}_{mass[1]:g}")
+        n0, u0 = W.mode_state(m, n, 0.5, 0.02)
+        mixes.append(m)
+        n0s.append(n0)
+        u0s.append(u0)
+    b = mlb.GpuBatch(mixes, n0s, u0s, precision=32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(0, steps + 1, 10):
+        b.record_modes()
+        if t < steps:
+            b.step(10)
+    fits = b.fit_ex(t_min=300)
+    torch.cuda.synchronize()
+    g = (1 - xi / 2) / (1 - xi) ** 3
+    rows = []
+    for mass, q in zip(masses, fits):
+        mu = mass[0] * mass[1] / (mass[0] + mass[1])
+        d_paper = 3.0 / (8.0 * n) * math.sqrt(1.0 / 3.0) / (math.sqrt(2 * math.pi * mu) * sigma ** 2 * g)
+        rows.append({"masses": list(mass), "mu_AB": mu, "D": float(q[0]), "D_paper": d_paper,
+                     "ratio": float(q[0]) / d_paper, "well_conditioned": bool(q[4] == 1.0)})
+    return {"workload": "mass_study_6_systems_192x8x8", "sigma": sigma, "packing": xi, "steps": steps,
+            "seconds": time.perf_counter() - t0, "systems": rows}
+
+
 def cpu_baseline(mix, n0, u0, target_s=12.0):
     """The float64 oracle on the host: all its OpenMP threads over a sample of
     about target_s seconds, then one thread over one step (the same per-site
@@ -621,6 +661,7 @@ def main():
     ap.add_argument("--no-tails", action="store_true", help="skip the tail-dependence (D(c)) leg")
     ap.add_argument("--no-kolmogorov", action="store_true",
                     help="skip the Taylor-dispersion leg in the modulated (Kolmogorov) flow")
+    ap.add_argument("--no-masses", action="store_true", help="skip the unequal-mass D study")
     ap.add_argument("--closure-steps", type=int, default=5000)
     ap.add_argument("--sweep", type=int, default=None, metavar="EDGE",
                     help="only the off-cache size sweep: step-binary physics on an EDGE^3 box, one JSON line")
@@ -758,6 +799,11 @@ def main():
             line["tail_study"] = tail_study_leg(mlb, W)
         except Exception as exc:      # reported in the line; the headline stands on its own
             line["tail_study"] = {"error": f"{type(exc).__name__}: {exc}"}
+    if not args.no_masses:
+        try:
+            line["mass_study"] = mass_study_leg(mlb, W)
+        except Exception as exc:      # reported in the line; the headline stands on its own
+            line["mass_study"] = {"error": f"{type(exc).__name__}: {exc}"}
     if not args.no_closure:
         try:
             line["closure"] = closure_leg(mlb, W, steps=args.closure_steps)

@@ -5,7 +5,7 @@
  *
  * The method (Marini Bettolo Marconi & Melchionna, "Multicomponent diffusion
  * in nanosystems"): M species of hard spheres with diameters sigma_aa,
- * unit masses, uniform temperature T and optional attractive tails evolve
+ * masses m_alpha, uniform temperature T and optional attractive tails evolve
  * by the kinetic equation of Sec. 2, eq. (evolution): relaxation at rate
  * omega towards the orthogonalised local equilibrium psi_perp of
  * eqs. (psia)-(prefactor), plus the molecular-field term
@@ -20,7 +20,13 @@
  *     velocity dependence (one local Jacobi predictor sweep);
  *   - an external body force F^a (eq. evolution).
  * Space and velocity are discretised on a D3Q19 lattice (spacing and time
- * step 1, kT = 1/3, m = 1).
+ * step 1, kT = 1/3 = c_s^2).  Populations count particles (sum_i f_ai = n_a,
+ * sum_i c_i f_ai = j_a, the number flux); species a's equilibrium is the
+ * second-order Hermite form of eq. (psia) with thermal speed^2
+ * theta_a = kT/m_a, i.e. the c_s^2 form plus (9/2)(theta_a - 1/3)(c.c - 1);
+ * the orthogonalising factor of eq. (prefactor) is m_a/kT, and a force
+ * density N_a changes j_a at the rate N_a/m_a.  Unit masses give the plain
+ * D3Q19 equilibrium.
  *
  * Conventions for every entry point:
  *   - Device pointers are HIP device addresses; "host" pointers are CPU
@@ -93,8 +99,10 @@ typedef struct {
     int32_t tail_mode;             /* MLB_TAIL_*: AUTO = spectral in 32, direct in 64 */
     int32_t walls_y;               /* 0: y periodic; 1: solid layers y=0 and y=ny-1   */
     double tau;                    /* relaxation time, omega = 1/tau (one for all)    */
-    double kT;                     /* must be 1/3 (= c_s^2 with unit masses)          */
-    double mass[MLB_MAX_SPECIES];  /* must all be 1                                   */
+    double kT;                     /* must be 1/3 (the D3Q19 lattice's c_s^2)         */
+    double mass[MLB_MAX_SPECIES];  /* m_a in [0.625, 2.5]: species a's equilibrium has
+                                      thermal speed^2 kT/m_a in [2/15, 8/15] (see
+                                      below); the barycentric velocity is mass-weighted */
     double sigma[MLB_MAX_SPECIES]; /* hard-core diameters sigma_aa; sigma_ab = mean   */
     double eps[MLB_MAX_SPECIES * MLB_MAX_SPECIES]; /* U_ab = -eps_ab (sigma_ab/r)^6 for
                                       sigma_ab < r <= rc_factor sigma_ab; 0 = off; row
@@ -108,7 +116,7 @@ typedef struct mlb_mixture_s *mlb_mixture;
 
 /* Bytes of device workspace a mixture with these parameters needs (256-byte
  * aligned pointer required).  Returns 0 if the parameters are invalid (the
- * reason is in mlb_last_error()).  Conditions: 1 <= M <= 4, masses 1,
+ * reason is in mlb_last_error()).  Conditions: 1 <= M <= 4, masses in [0.625, 2.5],
  * kT = 1/3, sigma > 0, every stencil offset smaller than the box edge in
  * each periodic direction. */
 size_t mlb_workspace_bytes(const mlb_params *p);
@@ -222,8 +230,9 @@ mlb_status mlb_set_step_count(mlb_mixture h, int64_t steps);
 mlb_status mlb_set_force_profile(mlb_mixture h, const double *profile, void *stream);
 
 /* Global FP64 sums of the current state, accumulated on the GPU in float64:
- * mass[a] = sum_r n_a, mom[3a+d] = sum_r j_a,d (the conserved quantities of
- * eqs. continuity and momentcomponent).  HOST outputs; synchronises the
+ * mass[a] = sum_r n_a (particles of species a), mom[3a+d] = sum_r j_a,d
+ * (number flux; the conserved momentum of eqs. continuity and
+ * momentcomponent is sum_a m_a mom[3a+d]).  HOST outputs; synchronises the
  * stream.  Returns MLB_ENONFINITE if any sum is not finite. */
 mlb_status mlb_conserved(mlb_mixture h, double *mass, double *mom, void *stream);
 

@@ -28,7 +28,8 @@ def _torch():
 def make_params(mix, precision: int = 32, tail_mode: int = TAIL_AUTO) -> _lib.Params:
     """Fill the C parameter block from a mixture description (any object with
     nx, ny, nz, sigma, tau, kT, rc_factor, walls_y, wall_ux, scheme and the
-    eps_matrix() / fext_matrix() accessors)."""
+    eps_matrix() / fext_matrix() accessors; masses from mass_vector() when
+    it has one, else 1)."""
     p = _lib.Params()
     p.nx, p.ny, p.nz = int(mix.nx), int(mix.ny), int(mix.nz)
     M = len(mix.sigma)
@@ -41,8 +42,9 @@ def make_params(mix, precision: int = 32, tail_mode: int = TAIL_AUTO) -> _lib.Pa
     p.kT = float(mix.kT)
     eps = np.asarray(mix.eps_matrix(), dtype=np.float64).reshape(M, M)
     fx = np.asarray(mix.fext_matrix(), dtype=np.float64).reshape(M, 3)
+    mass = np.asarray(mix.mass_vector(), dtype=np.float64).reshape(M) if hasattr(mix, "mass_vector") else np.ones(M)
     for a in range(M):
-        p.mass[a] = 1.0
+        p.mass[a] = float(mass[a])
         p.sigma[a] = float(mix.sigma[a])
         for b in range(M):
             p.eps[a * _lib.MAX_SPECIES + b] = float(eps[a, b])

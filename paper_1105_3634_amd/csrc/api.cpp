@@ -56,6 +56,7 @@ constexpr int kSeriesCap = 8192;
 constexpr int kRedParts = 512;
 constexpr int kFitOut = 8;   // doubles per fit result: D, slope, samples, R^2, well-conditioned flag
 constexpr int kXcds = 8;   // MI355X: workgroups are dealt round-robin over 8 XCDs
+constexpr double kMassMin = 0.625, kMassMax = 2.5;   // species masses the lattice equilibrium represents
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -83,10 +84,15 @@ bool validate(const mlb_params *p, std::string &why)
     if (p->scheme != MLB_SCHEME_CN_J1 && p->scheme != MLB_SCHEME_FE) { why = "unknown scheme"; return false; }
     if (p->tail_mode < MLB_TAIL_AUTO || p->tail_mode > MLB_TAIL_SPECTRAL) { why = "unknown tail mode"; return false; }
     if (!(p->tau > 0.5)) { why = "tau must exceed 1/2"; return false; }
-    if (std::fabs(p->kT - 1.0 / 3.0) > 1e-12) { why = "kT must be 1/3 (unit masses on D3Q19)"; return false; }
+    if (std::fabs(p->kT - 1.0 / 3.0) > 1e-12) { why = "kT must be 1/3 (the D3Q19 lattice's c_s^2)"; return false; }
     if (p->walls_y && p->ny < 3) { why = "walls need ny >= 3"; return false; }
     for (int a = 0; a < M; ++a) {
-        if (p->mass[a] != 1.0) { why = "only unit masses are supported"; return false; }
+        // theta_a = kT/m_a in [2/15, 8/15]: the lattice equilibrium at rest
+        // keeps at least a tenth of its weight on every velocity
+        if (!(p->mass[a] >= kMassMin && p->mass[a] <= kMassMax)) {
+            why = "masses must lie in [0.625, 2.5]";
+            return false;
+        }
         if (!(p->sigma[a] > 0.0) || p->sigma[a] > 40.0) { why = "sigma must be in (0, 40]"; return false; }
         for (int b = 0; b < M; ++b) {
             const double e = p->eps[a * MLB_MAX_SPECIES + b];
@@ -469,6 +475,15 @@ void fill_desc(Batch &B, int k, mlb::SysDesc<T> &D)
     D.scheme = p->scheme;
     D.omega_is_one = (1.0 / p->tau == 1.0) ? 1 : 0;
     const HostTables &t = S.tabs;
+    D.unit_mass = 1;
+    for (int a = 0; a < S.M; ++a) {
+        const double ma = p->mass[a];
+        D.unit_mass = D.unit_mass && ma == 1.0;
+        D.mass[a] = (T)ma;
+        D.im[a] = (T)(1.0 / ma);
+        D.ith[a] = (T)(ma / p->kT);
+        D.dth[a] = (T)(4.5 * (p->kT / ma - 1.0 / 3.0));
+    }
     for (int a = 0; a < S.M; ++a) {
         D.bl_start[a] = S.bl_base + t.bl_start[a]; D.bl_cnt[a] = t.bl_cnt[a]; D.bl_full[a] = t.bl_full[a];
         const double sg = p->sigma[a];
@@ -478,7 +493,8 @@ void fill_desc(Batch &B, int k, mlb::SysDesc<T> &D)
         for (int b = 0; b < S.M; ++b) {
             D.sh_start[a][b] = S.sh_base + t.sh_start[a][b]; D.sh_cnt[a][b] = t.sh_cnt[a][b];
             D.tl_start[a][b] = S.tl_base + t.tl_start[a][b]; D.tl_cnt[a][b] = t.tl_cnt[a][b];
-            const mlb::PairConst c = mlb::pair_constants(p->sigma[a], p->sigma[b], p->kT, t.sh_full[a][b]);
+            const mlb::PairConst c =
+                mlb::pair_constants(p->sigma[a], p->sigma[b], p->kT, t.sh_full[a][b], p->mass[a], p->mass[b]);
             D.cm[a][b] = (T)c.cm; D.cg[a][b] = (T)c.cg; D.ck[a][b] = (T)c.ck; D.dd[a][b] = (T)c.dd;
         }
     }

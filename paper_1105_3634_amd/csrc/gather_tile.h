@@ -378,7 +378,7 @@ k_gather1_tile(const SysDesc<float> *__restrict__ sys,
     const char *cg = reinterpret_cast<const char *>(Lg + q.c);
     const bool solid = q.active && S.walls && (q.y == 0 || q.y == S.ny - 1);
     // group 0 stores H and V-hat, group 1 the friction tensor and
-    // 1 / (1 + Gamma / 2)
+    // (1/m_a) / (1 + Gamma / (2 m_a))
     const bool do_hv = h == 0, do_t = h == 1;
     const long long sc = q.active && (do_hv || do_t) ? q.s : 0;
     const float na = glb(S.n)[(long long)a * N + sc];
@@ -442,9 +442,12 @@ k_gather1_tile(const SysDesc<float> *__restrict__ sys,
         }
         return;
     }
-    const float hg = 0.5f * gam;
+    // a force density changes the number flux at the rate 1/m_a
+    const float im = S.im[a];
+    const float hg = (0.5f * gam) * im;
     if (do_t) {
-        if (S.tail_deferred) glb(S.gfac)[(long long)a * N + s] = (na != 0.f) ? 1.f / (1.f + hg) : 0.f;
+        // the deferred spectral field enters V-hat as (1/m_a) C_a / (1 + hg)
+        if (S.tail_deferred) glb(S.gfac)[(long long)a * N + s] = (na != 0.f) ? im / (1.f + hg) : 0.f;
         Tout[0 * N + s] = T00; Tout[1 * N + s] = T01; Tout[2 * N + s] = T02;
         Tout[3 * N + s] = T11; Tout[4 * N + s] = T12; Tout[5 * N + s] = T22;
     }
@@ -469,7 +472,8 @@ k_gather1_tile(const SysDesc<float> *__restrict__ sys,
             glb(S.vh)[o3 + d * N + s] = 0.f;
         } else {
             glb(S.H)[o3 + d * N + s] = Nc + 0.5f * Dd;
-            glb(S.vh)[o3 + d * N + s] = (na != 0.f) ? (jav[d] + Nc + Dd + hg * jav[d]) / (na * (1.f + hg)) : 0.f;
+            glb(S.vh)[o3 + d * N + s] =
+                (na != 0.f) ? ((jav[d] + im * Nc) + im * Dd + hg * jav[d]) / (na * (1.f + hg)) : 0.f;
         }
         if (S.parts) {
             float acc = 0.f;
@@ -616,16 +620,18 @@ k_step2_tile(const SysDesc<float> *__restrict__ sys,
     // The collision of eq. (evolution) with the force term, regrouped so that
     // only the parts that depend on c_i stay inside the population loop:
     //   omega psi_i + src_i = w_i E_i (A + 3 c_i.P),
-    //   E_i = (1 - 3/2 u.u) + c_i.u (3 + 9/2 c_i.u),
-    //   P = omega (j - n u) + N,  A = omega n - 3 u.P
-    // (psi_i = w_i E_i (n + 3 (j - n u).(c_i - u)), src_i = 3 w_i E_i (c_i - u).N).
+    //   E_i = (1 - 3/2 u.u) + c_i.u (3 + 9/2 c_i.u) [+ dth (c_i.c_i - 1)],
+    //   P = omega m_a (j - n u) + N,  A = omega n - 3 u.P
+    // (psi_i = w_i E_i (n + (m_a/kT) (j - n u).(c_i - u)), src_i = 3 w_i E_i
+    // (c_i - u).N, with m_a/kT = 3 m_a; dth = (9/2)(kT/m_a - 1/3)).
     const bool w1 = S.omega_is_one != 0;
     const float om = w1 ? 1.f : S.omega;
     const float uu = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
     const float B = 1.f - 1.5f * uu;
+    const float omm = om * S.mass[a], dth = S.dth[a];
     float P[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) P[d] = om * (ja[d] - na * u[d]) + Na[d];
+    for (int d = 0; d < 3; ++d) P[d] = omm * (ja[d] - na * u[d]) + Na[d];
     const float A = om * na - 3.f * ((u[0] * P[0] + u[1] * P[1]) + u[2] * P[2]);
     // neighbour offsets with periodic wrap (32-bit: sites number below 2^29);
     // beyond a wall the population bounces back instead
@@ -640,7 +646,8 @@ k_step2_tile(const SysDesc<float> *__restrict__ sys,
         if (i < ib || i >= ie) continue;
         const int cx = kC[i][0], cy = kC[i][1], cz = kC[i][2];
         const float cu = cdot(cx, cy, cz, u), cP = cdot(cx, cy, cz, P);
-        const float E = B + cu * (3.f + 4.5f * cu);
+        float E = B + cu * (3.f + 4.5f * cu);
+        if (!S.unit_mass) E += dth * (float)(cx * cx + cy * cy + cz * cz - 1);
         float fs = (lattice_weight<float>(i) * E) * (A + 3.f * cP);
         if (!w1) fs += S.om1 * fi[i];
         if ((cy < 0 && wlo) || (cy > 0 && whi)) {

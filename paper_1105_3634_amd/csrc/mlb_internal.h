@@ -45,7 +45,7 @@ struct SysDesc {
     T *tail;                         // attractive field sum_b K_ab * n_b [M][3][N] (spectral mode)
     T *parts;                        // optional force-part accumulator [M][3][N] (forces query)
     T *Tloc;                         // local friction tensor sum_b ck Ts_b [M][6][N] (tiled path)
-    T *gfac;                         // 1 / (1 + Gamma_a / 2) per species-site when the tail is deferred [M][N]
+    T *gfac;                         // (1/m_a) / (1 + Gamma_a / (2 m_a)) per species-site when the tail is deferred [M][N]
     unsigned parts_mask;
     int tail_direct;                 // 1: direct tail sum in the first gather
     int tail_deferred;               // 1: the first gather leaves the spectral tail out; k_add_tail adds it
@@ -62,6 +62,11 @@ struct SysDesc {
     T dd[kMaxS][kMaxS];              // sigma_a sigma_b / (sigma_a + sigma_b)
     T s2[kMaxS], s3[kMaxS];          // (pi/6) sigma^2, (pi/6) sigma^3
     T fext[kMaxS][3];
+    // species masses (Sec. 2): m_a, 1/m_a, m_a/kT = 1/theta_a and the weight
+    // (9/2)(theta_a - 1/3) of the lattice equilibrium's temperature term;
+    // unit_mass = 1 when every m_a is 1 (the term then vanishes everywhere)
+    T mass[kMaxS], im[kMaxS], ith[kMaxS], dth[kMaxS];
+    int unit_mass;
     const T *fprof;                  // body force per lattice row [M][3][ny] (replaces fext when set)
     T omega, om1;
     T wall_ux[2];
@@ -97,7 +102,7 @@ double stability_radius(const mlb_params *p, const double *n0, int kgrid);
 struct PairConst {
     double cm, cg, ck, dd;
 };
-PairConst pair_constants(double sa, double sb, double kT, int shell_full);
+PairConst pair_constants(double sa, double sb, double kT, int shell_full, double ma, double mb);
 
 // A launch covers the blocks of many systems: block b works on system
 // map[b].x (a negative value idles the block), local block map[b].y.
@@ -113,7 +118,7 @@ struct Launch {
                       int parity, int write_force_only, hipStream_t st);
     // collision + streaming with the given force S.Nf
     static void collide(const SysDesc<T> *sys, const int2 *map, int nblk, int maxM, int parity, hipStream_t st);
-    // the deferred spectral tail: H += n_a C_a, V-hat += C_a / (1 + Gamma_a / 2)
+    // the deferred spectral tail: H += n_a C_a, V-hat += (C_a / m_a) / (1 + Gamma_a / (2 m_a))
     static void add_tail(const SysDesc<T> *sys, const int2 *map, int nblk, int maxM, hipStream_t st);
     static void init_pop(const SysDesc<T> *sys, const int2 *map, int nblk, const double *n0,
                          const double *u0, hipStream_t st);

@@ -13,8 +13,11 @@
 //   pair form       D_a[V] = sum_b kappa_ab g_ab (n_a ST_ab V_b n_b - n_b ST0_ab n_a V_a)
 //                   (eqs. gammaab, tensorgamma, viscousforce), ST = sum e e^T cos(k.e)
 //   time scheme     forward Euler, or Crank-Nicolson with one Jacobi
-//                   predictor as the step applies it
-//   collision       f* = (1 - omega) f + omega w (dn + 3 c.dj) + 3 w c.N
+//                   predictor as the step applies it (forces over m_a)
+//   collision       f* = (1 - omega) f + omega psi + 3 w h c.N, with
+//                   psi = w h (dn + (m_a/kT) c.(dj - n du)) + 3 w n c.du,
+//                   h = 1 + (9/2)(kT/m_a - 1/3)(c.c - 1), du the mass-weighted
+//                   barycentric velocity (unit masses: psi = w (dn + 3 c.dj))
 //   streaming       f' = exp(-i k.c) f*
 // The spectral radius over a grid of k (k = 0 excluded: its conserved
 // modes sit at 1) comes from power iteration.  The forward-Euler treatment
@@ -88,7 +91,8 @@ double stability_radius(const mlb_params *p, const double *n0, int kgrid)
             const double sab = 0.5 * (p->sigma[a] + p->sigma[b]);
             shell[a][b] = build_stencil(kShell, sab, 0.0);
             what[a][b] = 4.0 * M_PI / (double)shell[a][b].full;
-            kap[a][b] = 2.0 * sab * sab * std::sqrt(2.0 * 0.5 * kT / M_PI) * what[a][b];
+            const double mu = (p->mass[a] * p->mass[b]) / (p->mass[a] + p->mass[b]);
+            kap[a][b] = 2.0 * sab * sab * std::sqrt(2.0 * mu * kT / M_PI) * what[a][b];
             if (p->eps[a * MLB_MAX_SPECIES + b] > 0.0) tail[a][b] = build_stencil(kTail, sab, p->rc_factor);
         }
     std::mt19937_64 rng(12345);
@@ -178,12 +182,14 @@ double stability_radius(const mlb_params *p, const double *n0, int kgrid)
                             Gam[a] += kg * n0[b] * P[a][b].ST0;
                         }
                     }
-                    for (int a = 0; a < M; ++a)
+                    for (int a = 0; a < M; ++a) {
+                        const double im = 1.0 / p->mass[a], hg = 0.5 * Gam[a] * im;
                         for (int d = 0; d < 3; ++d) {
-                            V[a][d] = n0[a] > 0.0 ? (dj[a][d] + Nc[a][d] + Dold[a][d] + 0.5 * Gam[a] * dj[a][d]) /
-                                                        (n0[a] * (1.0 + 0.5 * Gam[a]))
+                            V[a][d] = n0[a] > 0.0 ? (dj[a][d] + im * (Nc[a][d] + Dold[a][d]) + hg * dj[a][d]) /
+                                                        (n0[a] * (1.0 + hg))
                                                   : cd(0.0);
                         }
+                    }
                     for (int a = 0; a < M; ++a)
                         for (int d = 0; d < 3; ++d) {
                             if (p->scheme == MLB_SCHEME_FE) {
@@ -198,17 +204,33 @@ double stability_radius(const mlb_params *p, const double *n0, int kgrid)
                             }
                             Nf[a][d] = Nc[a][d] + 0.5 * Dold[a][d] + 0.5 * n0[a] * dnew;
                         }
-                    for (int a = 0; a < M; ++a)
+                    // barycentric velocity (mass-weighted) of the perturbation
+                    cd du[3] = {0.0, 0.0, 0.0};
+                    double rho0 = 0.0;
+                    for (int a = 0; a < M; ++a) {
+                        rho0 += p->mass[a] * n0[a];
+                        for (int d = 0; d < 3; ++d) du[d] += p->mass[a] * dj[a][d];
+                    }
+                    for (int d = 0; d < 3; ++d) du[d] = rho0 > 0.0 ? du[d] / rho0 : cd(0.0);
+                    // linearised collision at rest with theta_a = kT/m_a:
+                    //   psi_perp_i = w_i h_i [dn + (m_a/kT) c.(dj - n du)] + 3 w_i n c.du
+                    //   S_i = 3 w_i h_i c.N,  h_i = 1 + (9/2)(theta_a - 1/3)(c.c - 1)
+                    for (int a = 0; a < M; ++a) {
+                        const double ith = p->mass[a] / kT, dth = 4.5 * (kT / p->mass[a] - 1.0 / 3.0);
                         for (int i = 0; i < kQ; ++i) {
-                            cd cj = 0.0, cN = 0.0;
+                            cd cv = 0.0, cN = 0.0, cu = 0.0;
                             for (int d = 0; d < 3; ++d) {
-                                cj += (double)kCx[i][d] * dj[a][d];
+                                cv += (double)kCx[i][d] * (dj[a][d] - n0[a] * du[d]);
                                 cN += (double)kCx[i][d] * Nf[a][d];
+                                cu += (double)kCx[i][d] * du[d];
                             }
-                            const cd fs = (1.0 - omega) * f[(size_t)a * kQ + i] + omega * wq(i) * (dn[a] + 3.0 * cj) +
-                                          3.0 * wq(i) * cN;
+                            const int c2 = kCx[i][0] * kCx[i][0] + kCx[i][1] * kCx[i][1] + kCx[i][2] * kCx[i][2];
+                            const double h = 1.0 + dth * (double)(c2 - 1);
+                            const cd psi = wq(i) * (h * (dn[a] + ith * cv) + 3.0 * n0[a] * cu);
+                            const cd fs = (1.0 - omega) * f[(size_t)a * kQ + i] + omega * psi + 3.0 * wq(i) * h * cN;
                             out[(size_t)a * kQ + i] = shift[i] * fs;
                         }
+                    }
                 };
                 std::vector<cd> x((size_t)dim), y((size_t)dim);
                 for (auto &v : x) v = cd(nd(rng), nd(rng));

@@ -154,12 +154,14 @@ __global__ void __launch_bounds__(kBlock) k_moments(const SysDesc<T> *__restrict
         S.n[(long long)a * N + s] = na;
 #pragma unroll
         for (int d = 0; d < 3; ++d) S.j[((long long)a * 3 + d) * N + s] = ja[d];
+        // barycentric velocity: mass-weighted (Sec. 2, eq. massdensity and below)
+        const T ma = S.mass[a];
         if (a == 0) {
-            nt = na;
-            jt[0] = ja[0]; jt[1] = ja[1]; jt[2] = ja[2];
+            nt = ma * na;
+            jt[0] = ma * ja[0]; jt[1] = ma * ja[1]; jt[2] = ma * ja[2];
         } else {
-            nt = nt + na;
-            jt[0] = jt[0] + ja[0]; jt[1] = jt[1] + ja[1]; jt[2] = jt[2] + ja[2];
+            nt = nt + ma * na;
+            jt[0] = jt[0] + ma * ja[0]; jt[1] = jt[1] + ma * ja[1]; jt[2] = jt[2] + ma * ja[2];
         }
     }
 #pragma unroll
@@ -310,7 +312,9 @@ __global__ void __launch_bounds__(kBlock) k_gather1(const SysDesc<T> *__restrict
         // spectral mode: sum_b (K_ab * n_b) precomputed for this species
         tl[0] = S.tail[o3 + s]; tl[1] = S.tail[o3 + N + s]; tl[2] = S.tail[o3 + 2 * N + s];
     }
-    const T hg = T(0.5) * gam;
+    // a force density changes the number flux at the rate 1/m_a
+    const T im = S.im[a];
+    const T hg = (T(0.5) * gam) * im;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const T Nmf = na * mf[d];
@@ -325,7 +329,7 @@ __global__ void __launch_bounds__(kBlock) k_gather1(const SysDesc<T> *__restrict
         } else {
             S.H[o3 + d * N + s] = Nc + T(0.5) * Dd;
             S.vh[o3 + d * N + s] =
-                (na != T(0)) ? (((ja[d] + Nc) + Dd) + hg * ja[d]) / (na * (T(1) + hg)) : T(0);
+                (na != T(0)) ? (((ja[d] + im * Nc) + im * Dd) + hg * ja[d]) / (na * (T(1) + hg)) : T(0);
         }
         if (S.parts) {
             T acc = T(0);
@@ -339,26 +343,33 @@ __global__ void __launch_bounds__(kBlock) k_gather1(const SysDesc<T> *__restrict
 }
 
 // ------------------------------------------------------------------ step 2
-// Orthogonalised BGK collision with the field term (eq. evolution):
-//   E_i = 1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u
-//   psi_perp_i = w_i E_i [n_a + 3 (j_a - n_a u).(c_i - u)]     eq. (prefactor)
-//   S_i = w_i E_i 3 (c_i - u).N_a
+// Orthogonalised BGK collision with the field term (eq. evolution), the
+// Maxwellian of eq. (psia) with thermal speed^2 theta_a = kT/m_a in
+// second-order Hermite form on the lattice (c_s^2 = 1/3):
+//   E_i = 1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u + (9/2)(theta_a - 1/3)(c.c - 1)
+//   psi_perp_i = w_i E_i [n_a + (m_a/kT) (j_a - n_a u).(c_i - u)]     eq. (prefactor)
+//   S_i = w_i E_i (c_i - u).N_a / kT
 //   f*_i = (1 - omega) f_i + omega psi_perp_i + S_i
+// ith = m_a/kT, dth = (9/2)(theta_a - 1/3) (0 for unit masses: no term).
 template <typename T>
 __device__ inline T post_collision(int i, T fi, bool omega_one, T omega, T om1, T na, const T ja[3],
-                                   const T u[3], const T Na[3])
+                                   const T u[3], const T Na[3], T ith, T dth)
 {
     const T uu = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
     const T cx = (T)kC[i][0], cy = (T)kC[i][1], cz = (T)kC[i][2];
     const T cu = (cx * u[0] + cy * u[1]) + cz * u[2];
-    const T E = ((T(1) + T(3) * cu) + (T(4.5) * cu) * cu) - T(1.5) * uu;
+    T E = ((T(1) + T(3) * cu) + (T(4.5) * cu) * cu) - T(1.5) * uu;
+    if (dth != T(0)) {
+        const int c2 = kC[i][0] * kC[i][0] + kC[i][1] * kC[i][1] + kC[i][2] * kC[i][2];
+        E = E + dth * (T)(c2 - 1);
+    }
     const T wE = lattice_weight<T>(i) * E;
     const T m0 = cx - u[0], m1 = cy - u[1], m2 = cz - u[2];
     const T v0 = ja[0] - na * u[0], v1 = ja[1] - na * u[1], v2 = ja[2] - na * u[2];
     const T dotv = (v0 * m0 + v1 * m1) + v2 * m2;
     const T dotN = (m0 * Na[0] + m1 * Na[1]) + m2 * Na[2];
-    const T psi = wE * (na + T(3) * dotv);
-    const T src = wE * (T(3) * dotN);
+    const T psi = wE * (na + ith * dotv);
+    const T src = wE * (T(3) * dotN);   // 3 = 1/kT
     if (omega_one) return psi + src;
     return (om1 * fi + omega * psi) + src;
 }
@@ -445,7 +456,7 @@ __global__ void __launch_bounds__(kBlock) k_step2(const SysDesc<T> *__restrict__
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
         const T fi = w1 ? T(0) : fin[(long long)i * N + s];
-        const T fs = post_collision<T>(i, fi, w1, S.omega, S.om1, na, ja, u, Na);
+        const T fs = post_collision<T>(i, fi, w1, S.omega, S.om1, na, ja, u, Na, S.ith[a], S.dth[a]);
         const int yy = r.y + kC[i][1];
         if (S.walls && (yy == 0 || yy == S.ny - 1)) {
             const T uw = (yy == 0) ? S.wall_ux[0] : S.wall_ux[1];
@@ -484,7 +495,7 @@ __global__ void __launch_bounds__(kBlock) k_collide(const SysDesc<T> *__restrict
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
         const T fi = w1 ? T(0) : fin[(long long)i * N + s];
-        const T fs = post_collision<T>(i, fi, w1, S.omega, S.om1, na, ja, u, Na);
+        const T fs = post_collision<T>(i, fi, w1, S.omega, S.om1, na, ja, u, Na, S.ith[a], S.dth[a]);
         const int yy = r.y + kC[i][1];
         if (S.walls && (yy == 0 || yy == S.ny - 1)) {
             const T uw = (yy == 0) ? S.wall_ux[0] : S.wall_ux[1];
@@ -498,7 +509,7 @@ __global__ void __launch_bounds__(kBlock) k_collide(const SysDesc<T> *__restrict
 
 // The attractive field computed beside the first gather (tiled float32
 // path): its contribution N_tail = n_a C_a enters the predictor-time force
-// H and, through N^c, the predictor V-hat = (... + N^c ...) / (n_a (1 + Gamma_a / 2)).
+// H and, through N^c, the predictor V-hat = (... + N^c / m_a ...) / (n_a (1 + Gamma_a / (2 m_a))).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_add_tail(const SysDesc<T> *__restrict__ sys,
                                                      const int2 *__restrict__ bmap)
@@ -563,12 +574,13 @@ __global__ void __launch_bounds__(kBlock) k_init_pop(const SysDesc<T> *__restric
     T jj[kMaxS][3];
     for (int a = 0; a < S.M; ++a) {
         const T na = (T)n0[(long long)a * N + s];
+        const T ma = S.mass[a];
         for (int d = 0; d < 3; ++d) jj[a][d] = na * (T)u0[((long long)a * 3 + d) * N + s];
         if (a == 0) {
-            nt = na; jt[0] = jj[a][0]; jt[1] = jj[a][1]; jt[2] = jj[a][2];
+            nt = ma * na; jt[0] = ma * jj[a][0]; jt[1] = ma * jj[a][1]; jt[2] = ma * jj[a][2];
         } else {
-            nt = nt + na;
-            jt[0] = jt[0] + jj[a][0]; jt[1] = jt[1] + jj[a][1]; jt[2] = jt[2] + jj[a][2];
+            nt = nt + ma * na;
+            jt[0] = jt[0] + ma * jj[a][0]; jt[1] = jt[1] + ma * jj[a][1]; jt[2] = jt[2] + ma * jj[a][2];
         }
     }
     T u[3];
@@ -579,7 +591,7 @@ __global__ void __launch_bounds__(kBlock) k_init_pop(const SysDesc<T> *__restric
 #pragma unroll
         for (int i = 0; i < kQ; ++i)
             f[((long long)a * kQ + i) * N + s] =
-                post_collision<T>(i, T(0), true, T(1), T(0), na, jj[a], u, zero3);
+                post_collision<T>(i, T(0), true, T(1), T(0), na, jj[a], u, zero3, S.ith[a], S.dth[a]);
     }
 }
 

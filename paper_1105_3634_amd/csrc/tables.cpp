@@ -71,10 +71,10 @@ HostStencil build_stencil(int kind, double s, double rc)
 //   cg    = kappa / 6                    (trace/3 of the friction tensor, x 1/2)
 //   ck    = kappa / 2                    (pair form, x 1/2 of G)
 //   dd    = s_a s_b / (s_a + s_b)        (BMCSL contact-value coefficient)
-PairConst pair_constants(double sa, double sb, double kT, int shell_full)
+PairConst pair_constants(double sa, double sb, double kT, int shell_full, double ma, double mb)
 {
     const double sab = 0.5 * (sa + sb);
-    const double mu = 0.5;
+    const double mu = (ma * mb) / (ma + mb);   // reduced mass of the pair (below eq. viscousforce)
     const double what = (4.0 * M_PI) / (double)shell_full;
     const double kap = ((2.0 * (sab * sab)) * std::sqrt((2.0 * mu * kT) / M_PI)) * what;
     PairConst c;

@@ -38,7 +38,7 @@ int main()
             for (double v : h.v)
                 if (!std::isfinite(v)) return 2;
         }
-        mlb::PairConst c = mlb::pair_constants(s, 0.5 * s + 1.0, 1.0 / 3.0, 100);
+        mlb::PairConst c = mlb::pair_constants(s, 0.5 * s + 1.0, 1.0 / 3.0, 100, 0.7, 2.0);
         if (!std::isfinite(c.cm)) return 3;
     }
     const double s2[2] = {2.0, 3.0}, s3[3] = {2.0, 3.0, 4.0};
@@ -46,6 +46,7 @@ int main()
     for (int scheme = 0; scheme <= 1; ++scheme)
         for (double eps : {0.0, 0.1}) {
             mlb_params p = make(2, s2, scheme, scheme ? 0.8 : 1.0, eps);
+            p.mass[0] = 0.7, p.mass[1] = 2.0;
             const double r2 = mlb::stability_radius(&p, n2, 4);
             p = make(3, s3, scheme, 1.0, eps);
             const double r3 = mlb::stability_radius(&p, n3, 4);

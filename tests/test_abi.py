@@ -92,7 +92,8 @@ def _bad_params(edit):
     (lambda p: setattr(p, "scheme", 7), "scheme"),
     (lambda p: setattr(p, "tail_mode", 9), "tail mode"),
     (lambda p: (setattr(p, "walls_y", 1), setattr(p, "ny", 2)), "ny >= 3"),
-    (lambda p: p.mass.__setitem__(1, 2.0), "unit masses"),
+    (lambda p: p.mass.__setitem__(1, 2.6), "masses must lie in"),
+    (lambda p: p.mass.__setitem__(0, 0.6), "masses must lie in"),
     (lambda p: p.sigma.__setitem__(0, 41.0), "sigma"),
     (lambda p: p.sigma.__setitem__(0, float("nan")), "sigma"),
     (lambda p: setattr(p, "rc_factor", 1.0), "rc_factor"),
@@ -161,12 +162,12 @@ def test_network_sizes():
     assert lib.mlb_net_workspace_bytes(1024, 1024, 512, 0) == 0
 
 
-def _stability(sigma, n, scheme, tau=1.0, eps=None):
+def _stability(sigma, n, scheme, tau=1.0, eps=None, mass=None):
     import ctypes as C
     import paper_1105_3634_amd as mlb
     from paper_1105_3634_amd import _lib
     lib = _lib.load()
-    m = W.Mixture(16, 16, 16, sigma=sigma, tau=tau, scheme=scheme, eps=eps)
+    m = W.Mixture(16, 16, 16, sigma=sigma, tau=tau, scheme=scheme, eps=eps, mass=mass)
     p = mlb.make_params(m, 64)
     r = C.c_double()
     st = lib.mlb_check_stability(C.byref(p), (C.c_double * len(sigma))(*n), C.byref(r))
@@ -195,3 +196,21 @@ def test_stability_guard_flags_forward_euler_friction():
     assert st == -4 and 1.0 < r < 1.05
     assert _stability((3.0, 4.5), [n / 2, n / 2], W.SCHEME_CN_J1, eps=eps)[0] == 0
     assert _stability((2.0, 2.5), [0.006, 0.004], W.SCHEME_FE, tau=0.8)[0] == 0
+
+
+def test_stability_guard_with_masses():
+    """The friction rate per step of species a is Gamma_a / m_a: at the
+    bulk-diffusion state forward Euler is unstable with light species
+    (m = 0.625: radius 1.31) and stable with heavy ones (m = 2.5: 0.974);
+    Crank-Nicolson with one Jacobi predictor stays stable at the dense
+    ensemble corner for every mass pair tried."""
+    eps = np.full((2, 2), 0.5 / 3.0)
+    n = W.number_density(0.3, (0.5, 0.5), (3.0, 4.5))
+    st, r = _stability((3.0, 4.5), [n / 2, n / 2], W.SCHEME_FE, eps=eps, mass=(0.625, 0.625))
+    assert st == -4 and 1.25 < r < 1.4
+    st, r = _stability((3.0, 4.5), [n / 2, n / 2], W.SCHEME_FE, eps=eps, mass=(2.5, 2.5))
+    assert st == 0 and r < 1.0
+    n = W.number_density(0.35, (0.9, 0.1), (2.0, 4.0))
+    for mass in ((0.7, 2.0), (2.5, 0.7), (0.625, 0.625), (2.5, 2.5)):
+        st, r = _stability((2.0, 4.0), [0.9 * n, 0.1 * n], W.SCHEME_CN_J1, mass=mass)
+        assert st == 0 and r < 1.0, (mass, r)
