@@ -300,7 +300,9 @@ def ensemble_leg(mlb, W, steps=1000, timed=200, opts=None):
                 "well_conditioned_min": float(np.min(Dg)), "well_conditioned_median": float(np.median(Dg)),
                 "well_conditioned_max": float(np.max(Dg))},
         "tuning": {"shape": mlb.GpuBatch.SHAPES[tune["shape"]], "order": ["linear", "xcd-chunked"][tune["order"]],
-                   "gather1_groups_per_site": tune["gather1_split"], "trial_ms": tune["trial_ms"]},
+                   "gather1_groups_per_site": tune["gather1_split"],
+                   "gather1_sign_groups": tune["gather1_sign_groups"], "trial_ms": tune["trial_ms"],
+                   "sign_groups_ms": tune["sign_groups_ms"]},
         "passes_ms_per_step": {k: v[0] / 10 for k, v in passes.items() if v[1]},
     }
 
@@ -351,7 +353,8 @@ def taylor_leg(mlb, W, steps=5000, timed=200, packing=0.25):
                                          "well_conditioned": fit["well_conditioned"]},
         "mass_finite": bool(np.all(np.isfinite(mass))),
         "tuning": {"shape": ["16x4x4", "8x8x4", "32x4x2"][tune["shape"]], "order": ["linear", "xcd-chunked"][tune["order"]],
-                   "gather1_groups_per_site": tune["gather1_split"]},
+                   "gather1_groups_per_site": tune["gather1_split"],
+                   "gather1_sign_groups": tune["gather1_sign_groups"]},
         "passes_ms_per_step": {k: v[0] / 10 for k, v in passes.items() if v[1]},
     }
 
@@ -650,10 +653,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=200, help="untimed steps before the timed region (the GPU reaches its steady clocks)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tail", choices=["auto", "direct", "spectral"], default="auto")
-    ap.add_argument("--tiling", default=None, metavar="SHAPE,ORDER[,SPLIT]",
+    ap.add_argument("--tiling", default=None, metavar="SHAPE,ORDER[,SPLIT[,GROUPS]]",
                     help="fixed tile shape (0: 16x4x4, 1: 8x8x4, 2: 32x4x2), block order (0 linear, "
-                         "1 XCD-chunked) and the first gather's thread groups per site (2 or 3, default 3) "
-                         "instead of the start-up autotuning (reproducible profiles)")
+                         "1 XCD-chunked), the first gather's thread groups per site (2 or 3, default 3) and its "
+                         "shell loop (0 plain, the default; 1 sign-grouped) instead of the start-up autotuning "
+                         "(reproducible profiles)")
     ap.add_argument("--no-d12", action="store_true", help="skip the 2000-step D_12 accuracy check")
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
@@ -742,7 +746,8 @@ def main():
     shapes = ("16,4,4", "8,8,4", "32,4,2")
     tune = g.tuning()
     kname = {"gather1": "k_gather1_tile", "step2": "k_step2_tile"}.get(dom)
-    kargs = shapes[tune["shape"]] + (f",{tune['gather1_split']}" if dom == "gather1" else "")
+    kargs = shapes[tune["shape"]] + (f",{tune['gather1_split']},{'true' if tune['gather1_sign_groups'] == 1 else 'false'}"
+                                     if dom == "gather1" else "")
     traffic = counter_traffic(f"{kname}<{kargs}>") if kname else None
     total_bytes = sum(bytes_.values()) * args.steps
     line = {

@@ -76,7 +76,8 @@ typedef enum {
 enum { MLB_SCHEME_CN_J1 = 0, MLB_SCHEME_FE = 1 };
 enum { MLB_TAIL_AUTO = 0, MLB_TAIL_DIRECT = 1, MLB_TAIL_SPECTRAL = 2 };
 enum { MLB_OPT_TUNE = 1u,       /* time every float32 tiling (tile shape, block order, thread groups
-                                   of the first gather) at init, keep the fastest */
+                                   of the first gather, then the sign-grouped shell loop on the
+                                   fastest) at init, keep the fastest */
        MLB_OPT_NO_GRAPH = 2u,   /* launch the passes eagerly instead of replaying a graph */
        MLB_OPT_NO_STABILITY_CHECK = 512u }; /* skip the linear-stability guard at init (studies of
                                            unstable schemes) */
@@ -84,9 +85,15 @@ enum { MLB_OPT_TUNE = 1u,       /* time every float32 tiling (tile shape, block 
  * MLB_OPT_TUNE): tile shape 0 = 16x4x4, 1 = 8x8x4, 2 = 32x4x2 sites; block
  * order 0 = linear, 1 = XCD-chunked.  Reproducible profiles use it.  With
  * MLB_OPT_TILING, MLB_OPT_GATHER1_SPLIT(s) also fixes the thread groups per
- * site of the first gather (2 or 3; 3 when not given). */
+ * site of the first gather (2 or 3; 3 when not given), and
+ * MLB_OPT_GATHER1_SIGN_GROUPS(g) its shell loop: 0 = plain (also when not
+ * given), 1 = sign-grouped (the points of a half-shell that differ only in
+ * the signs of their y and z components summed together: the same sums of
+ * eqs. potmeanforce, tensorgamma and viscousforce in another association,
+ * equal to the plain loop to float32 rounding). */
 #define MLB_OPT_TILING(shape, order) ((((uint32_t)(shape) + 1u) & 15u) << 4 | ((uint32_t)(order) & 1u) << 8)
 #define MLB_OPT_GATHER1_SPLIT(s) (((uint32_t)(s) & 3u) << 10)
+#define MLB_OPT_GATHER1_SIGN_GROUPS(g) (((uint32_t)(g) ? 2u : 1u) << 12)
 enum { MLB_PART_MF = 1u, MLB_PART_TAIL = 2u, MLB_PART_DISS = 4u, MLB_PART_EXT = 8u,
        MLB_PART_ALL = 15u };
 
@@ -183,6 +190,8 @@ mlb_status mlb_tuning(mlb_mixture h, int32_t *shape, int32_t *order, double *tri
 /* As mlb_tuning, with the first gather's thread groups per site and the
  * time of every candidate (see mlb_batch_tuning_ex). */
 mlb_status mlb_tuning_ex(mlb_mixture h, int32_t *shape, int32_t *order, int32_t *gather1_split, double *trial_ms);
+/* The first gather's shell loop in use (see mlb_batch_tuning_groups). */
+mlb_status mlb_tuning_groups(mlb_mixture h, int32_t *sign_groups, double *groups_ms);
 
 /* Advance the populations by nsteps >= 0 time steps of the kinetic equation
  * (Sec. 2, eq. evolution, with the field of Sec. 3). */
@@ -356,6 +365,12 @@ mlb_status mlb_batch_tuning(mlb_batch h, int32_t *shape, int32_t *order, double 
  * candidate: index (split - 2) 6 + 2 shape + order. */
 mlb_status mlb_batch_tuning_ex(mlb_batch h, int32_t *shape, int32_t *order, int32_t *gather1_split,
                                double *trial_ms);
+/* The first gather's shell loop in use: *sign_groups = 1 for the
+ * sign-grouped loop, 0 for the plain one, -1 for untiled handles; groups_ms
+ * (HOST, may be NULL) receives the autotuner's milliseconds per step of the
+ * chosen tiling with the sign-grouped loop (0 when not measured; the plain
+ * loop's time is that tiling's trial_ms entry). */
+mlb_status mlb_batch_tuning_groups(mlb_batch h, int32_t *sign_groups, double *groups_ms);
 mlb_status mlb_batch_profile_begin(mlb_batch h);
 mlb_status mlb_batch_profile_end(mlb_batch h, double *ms, int32_t *launches, void *stream);
 int64_t mlb_batch_step_count(mlb_batch h);

@@ -130,13 +130,16 @@ class GpuMixture:
 
     def tuning(self):
         """Float32 tiling in use: shape, order, the first gather's thread groups
-        per site and the time of every tuned candidate (mlb_tuning_ex)."""
-        shape, order, split = C.c_int32(), C.c_int32(), C.c_int32()
-        ms = (C.c_double * 12)()
+        per site and shell loop, and the time of every tuned candidate
+        (mlb_tuning_ex, mlb_tuning_groups)."""
+        shape, order, split, groups = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        ms, gms = (C.c_double * 12)(), C.c_double()
         _lib.check(self.lib.mlb_tuning_ex(self.h, C.byref(shape), C.byref(order), C.byref(split), ms),
                    "mlb_tuning_ex")
+        _lib.check(self.lib.mlb_tuning_groups(self.h, C.byref(groups), C.byref(gms)), "mlb_tuning_groups")
         return {"shape": int(shape.value), "order": int(order.value), "gather1_split": int(split.value),
-                "trial_ms": list(ms[:])}
+                "gather1_sign_groups": int(groups.value), "trial_ms": list(ms[:]),
+                "sign_groups_ms": float(gms.value)}
 
     def set_graph(self, enable: bool) -> None:
         _lib.check(self.lib.mlb_set_graph(self.h, 1 if enable else 0), "mlb_set_graph")
@@ -382,12 +385,15 @@ class GpuBatch:
         return np.array(t[:n]), np.array(v[:n])
 
     def tuning(self):
-        shape, order, split = C.c_int32(), C.c_int32(), C.c_int32()
-        ms = (C.c_double * 12)()
+        shape, order, split, groups = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        ms, gms = (C.c_double * 12)(), C.c_double()
         _lib.check(self.lib.mlb_batch_tuning_ex(self.h, C.byref(shape), C.byref(order), C.byref(split), ms),
                    "mlb_batch_tuning_ex")
+        _lib.check(self.lib.mlb_batch_tuning_groups(self.h, C.byref(groups), C.byref(gms)),
+                   "mlb_batch_tuning_groups")
         return {"shape": int(shape.value), "order": int(order.value), "gather1_split": int(split.value),
-                "trial_ms": list(ms[:])}
+                "gather1_sign_groups": int(groups.value), "trial_ms": list(ms[:]),
+                "sign_groups_ms": float(gms.value)}
 
     def profile_begin(self) -> None:
         _lib.check(self.lib.mlb_batch_profile_begin(self.h), "mlb_batch_profile_begin")

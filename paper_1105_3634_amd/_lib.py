@@ -59,6 +59,7 @@ _SIGS = [
     ("mlb_tuning", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     ("mlb_tuning_ex", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                 C.POINTER(C.c_double)]),
+    ("mlb_tuning_groups", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     ("mlb_step", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     ("mlb_moments", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("mlb_forces", C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p]),
@@ -99,6 +100,7 @@ _SIGS = [
     ("mlb_batch_tuning", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     ("mlb_batch_tuning_ex", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_double)]),
+    ("mlb_batch_tuning_groups", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     ("mlb_batch_profile_begin", C.c_int, [C.c_void_p]),
     ("mlb_batch_profile_end", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_void_p]),
     ("mlb_batch_step_count", C.c_int64, [C.c_void_p]),
@@ -130,10 +132,12 @@ OPT_TUNE, OPT_NO_GRAPH, OPT_NO_STABILITY_CHECK = 1, 2, 512
 STATIC_WORKSPACE_BYTES = 64 << 20   # MLB_STATIC_WORKSPACE_BYTES
 
 
-def opt_tiling(shape: int, order: int, gather1_split: int = 0) -> int:
-    """Option bits of a fixed float32 tiling (MLB_OPT_TILING and
-    MLB_OPT_GATHER1_SPLIT in mlb.h; split 0 = the default, 3)."""
-    return ((shape + 1) & 15) << 4 | (order & 1) << 8 | (gather1_split & 3) << 10
+def opt_tiling(shape: int, order: int, gather1_split: int = 0, sign_groups: int = 0) -> int:
+    """Option bits of a fixed float32 tiling (MLB_OPT_TILING,
+    MLB_OPT_GATHER1_SPLIT and MLB_OPT_GATHER1_SIGN_GROUPS in mlb.h; split 0 =
+    the default, 3; sign_groups 1 = the sign-grouped shell loop)."""
+    return (((shape + 1) & 15) << 4 | (order & 1) << 8 | (gather1_split & 3) << 10
+            | (2 if sign_groups else 1) << 12)
 
 _lib = None
 

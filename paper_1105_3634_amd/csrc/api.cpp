@@ -64,6 +64,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct HostTables {
     std::vector<int32_t> sh_e, tl_e, bl_e;
     std::vector<double> sh_u, tl_w;
+    std::vector<float> sg;   // sign groups, 4 floats per float4
+    int sg_start[mlb::kMaxS][mlb::kMaxS][mlb::kGroupKinds] = {}, sg_cnt[mlb::kMaxS][mlb::kMaxS][mlb::kGroupKinds] = {};
     int sh_start[mlb::kMaxS][mlb::kMaxS] = {}, sh_cnt[mlb::kMaxS][mlb::kMaxS] = {};
     int sh_full[mlb::kMaxS][mlb::kMaxS] = {};
     int tl_start[mlb::kMaxS][mlb::kMaxS] = {}, tl_cnt[mlb::kMaxS][mlb::kMaxS] = {};
@@ -103,6 +105,59 @@ bool validate(const mlb_params *p, std::string &why)
     return true;
 }
 
+// Sign groups of the (a, b) shell half-list for the float32 first gather:
+// points that differ only in the signs of their y and z components share
+// |e_hat| and are summed together.  The representative of a group has
+// e_y, e_z >= 0; members follow in the order (+y, +z), (-y, +z), (+y, -z),
+// (-y, -z).  Returns false if the half-list is not closed under these sign
+// changes (it always is: they keep |e|^2 and the first component).
+bool build_groups(const mlb::HostStencil &sh, HostTables &t, int a, int b)
+{
+    std::map<int32_t, size_t> at;
+    for (size_t k = 0; k < sh.e.size(); ++k) at[sh.e[k]] = k;
+    auto bits = [](int32_t v) { float f; std::memcpy(&f, &v, 4); return f; };
+    std::vector<float> kind[mlb::kGroupKinds];
+    int cnt[mlb::kGroupKinds] = {}, covered = 0;
+    for (size_t k = 0; k < sh.e.size(); ++k) {
+        int ex, ey, ez;
+        mlb::unpack_offset(sh.e[k], ex, ey, ez);
+        const double ux = sh.v[3 * k], uy = sh.v[3 * k + 1], uz = sh.v[3 * k + 2];
+        auto member = [&](int x, int y, int z) { return at.count(mlb::pack_offset(x, y, z)) == 1; };
+        const int nz = (ex != 0) + (ey != 0) + (ez != 0);
+        if (nz == 3 && ey > 0 && ez > 0) {
+            if (!member(ex, -ey, ez) || !member(ex, ey, -ez) || !member(ex, -ey, -ez)) return false;
+            const float f[16] = {bits(mlb::pack_offset(ex, ey, ez)), bits(mlb::pack_offset(ex, -ey, ez)),
+                                 bits(mlb::pack_offset(ex, ey, -ez)), bits(mlb::pack_offset(ex, -ey, -ez)),
+                                 (float)ux, (float)uy, (float)uz, 0.f,
+                                 (float)(ux * ux), (float)(uy * uy), (float)(uz * uz), 0.f,
+                                 (float)(ux * uy), (float)(ux * uz), (float)(uy * uz), 0.f};
+            kind[0].insert(kind[0].end(), f, f + 16);
+            ++cnt[0]; covered += 4;
+        } else if (nz == 2 && ((ez == 0 && ey > 0) || (ey == 0 && ez > 0) || (ex == 0 && ez > 0))) {
+            // shared axis A (e_x, or e_y when e_x = 0), flipped axis B
+            const int kd = ez == 0 ? 1 : ey == 0 ? 2 : 3;
+            const double A = kd == 3 ? uy : ux, B = kd == 1 ? uy : uz;
+            const int32_t o2 = kd == 1 ? mlb::pack_offset(ex, -ey, ez) : mlb::pack_offset(ex, ey, -ez);
+            if (at.count(o2) != 1) return false;
+            const float f[8] = {bits(sh.e[k]), bits(o2), (float)A, (float)B,
+                                (float)(A * A), (float)(B * B), (float)(A * B), 0.f};
+            kind[kd].insert(kind[kd].end(), f, f + 8);
+            ++cnt[kd]; covered += 2;
+        } else if (nz == 1) {
+            const float f[4] = {bits(sh.e[k]), (float)ux, (float)uy, (float)uz};
+            kind[4].insert(kind[4].end(), f, f + 4);
+            ++cnt[4]; covered += 1;
+        }
+    }
+    if (covered != (int)sh.e.size()) return false;
+    for (int kd = 0; kd < mlb::kGroupKinds; ++kd) {
+        t.sg_start[a][b][kd] = (int)(t.sg.size() / 4);
+        t.sg_cnt[a][b][kd] = cnt[kd];
+        t.sg.insert(t.sg.end(), kind[kd].begin(), kind[kd].end());
+    }
+    return true;
+}
+
 bool build_tables(const mlb_params *p, HostTables &t, std::string &why)
 {
     const int M = p->nspecies;
@@ -128,6 +183,7 @@ bool build_tables(const mlb_params *p, HostTables &t, std::string &why)
             t.sh_full[a][b] = sh.full;
             t.sh_e.insert(t.sh_e.end(), sh.e.begin(), sh.e.end());
             t.sh_u.insert(t.sh_u.end(), sh.v.begin(), sh.v.end());
+            if (!build_groups(sh, t, a, b)) { why = "shell half-list not closed under sign changes"; return false; }
             for (int d = 0; d < 3; ++d) t.shell_reach = std::max(t.shell_reach, sh.max_abs[d]);
             reach(sh);
             const double eps = p->eps[a * MLB_MAX_SPECIES + b];
@@ -202,6 +258,7 @@ struct SysHost {
     long long N = 0;
     HostTables tabs;
     int sh_base = 0, tl_base = 0, bl_base = 0;   // offsets into the batch tables
+    int sg_base = 0;                             // float4 offset of the sign groups
     bool spectral = false;
     mlb::SpectralPlan plan;
     int nblocks = 0;
@@ -212,12 +269,16 @@ struct SysHost {
     bool has_profile = false;
 };
 
-// Float32 tiling: tile shape, block order and the first gather's thread
-// groups per site (2 or 3); trial_ms[(split - 2) 2 V + 2 shape + order].
+// Float32 tiling: tile shape, block order, the first gather's thread
+// groups per site (2 or 3) and its shell loop (plain or sign-grouped);
+// trial_ms[(split - 2) 2 V + 2 shape + order] with the plain loop,
+// groups_ms the chosen tiling with the sign-grouped loop.
 constexpr int kSplitChoices = 2, kTrials = 2 * mlb::kTileVariants * kSplitChoices;
 struct Tuning {
     int shape = 0, order = 1, g1split = 3;
+    bool groups = false;
     double trial_ms[kTrials] = {};
+    double groups_ms = 0.0;
 };
 
 // Static device workspace of mlb_init_mixture_static.  In host code the
@@ -258,7 +319,7 @@ struct mlb_batch_s {
     size_t total = 0;
     // shared regions
     size_t desc = 0, map_site = 0, map_tile = 0, map_ident = 0;
-    size_t t_sh_e = 0, t_sh_u = 0, t_tl_e = 0, t_tl_w = 0, t_bl_e = 0, t_sh_q = 0;
+    size_t t_sh_e = 0, t_sh_u = 0, t_tl_e = 0, t_tl_w = 0, t_bl_e = 0, t_sh_q = 0, t_sg_q = 0;
     size_t red = 0, red_out = 0, fit_out = 0;
     size_t desc_size = 0;
     int nblk_site = 0, nblk_tile = 0, ident_len = 0;
@@ -314,6 +375,7 @@ struct mlb_batch_s {
         tb.tl_w = reinterpret_cast<const T *>(ws + t_tl_w);
         tb.bl_e = reinterpret_cast<const int32_t *>(ws + t_bl_e);
         tb.sh_q = reinterpret_cast<const float4 *>(ws + t_sh_q);
+        tb.sg_q = reinterpret_cast<const float4 *>(ws + t_sg_q);
         return tb;
     }
 };
@@ -391,10 +453,10 @@ bool plan_batch(Batch &B, const mlb_params *params, int count, std::string &why)
     B.map_tile = take(sizeof(int2) * (size_t)B.map_tile_cap);
     B.map_ident = take(sizeof(int2) * (size_t)B.ident_len);
     // tables (concatenated)
-    size_t nsh = 0, ntl = 0, nbl = 0;
+    size_t nsh = 0, ntl = 0, nbl = 0, nsg = 0;
     for (auto &S : B.sys) {
-        S.sh_base = (int)nsh; S.tl_base = (int)ntl; S.bl_base = (int)nbl;
-        nsh += S.tabs.sh_e.size(); ntl += S.tabs.tl_e.size(); nbl += S.tabs.bl_e.size();
+        S.sh_base = (int)nsh; S.tl_base = (int)ntl; S.bl_base = (int)nbl; S.sg_base = (int)nsg;
+        nsh += S.tabs.sh_e.size(); ntl += S.tabs.tl_e.size(); nbl += S.tabs.bl_e.size(); nsg += S.tabs.sg.size() / 4;
     }
     B.t_sh_e = take(4 * nsh);
     B.t_sh_u = take(ts * 3 * nsh);
@@ -402,6 +464,7 @@ bool plan_batch(Batch &B, const mlb_params *params, int count, std::string &why)
     B.t_tl_w = take(ts * 3 * ntl);
     B.t_bl_e = take(4 * nbl);
     B.t_sh_q = take(16 * (nsh + mlb::kShellPad));
+    B.t_sg_q = take(16 * (nsg + mlb::kShellPad));
     B.red = take(sizeof(double) * kRedParts * 16);
     B.red_out = take(sizeof(double) * 16);
     B.fit_out = take(sizeof(double) * kFitOut * (size_t)count);
@@ -492,6 +555,10 @@ void fill_desc(Batch &B, int k, mlb::SysDesc<T> &D)
         for (int d = 0; d < 3; ++d) D.fext[a][d] = (T)p->ext_force[a * 3 + d];
         for (int b = 0; b < S.M; ++b) {
             D.sh_start[a][b] = S.sh_base + t.sh_start[a][b]; D.sh_cnt[a][b] = t.sh_cnt[a][b];
+            for (int kd = 0; kd < mlb::kGroupKinds; ++kd) {
+                D.sg_start[a][b][kd] = S.sg_base + t.sg_start[a][b][kd];
+                D.sg_cnt[a][b][kd] = t.sg_cnt[a][b][kd];
+            }
             D.tl_start[a][b] = S.tl_base + t.tl_start[a][b]; D.tl_cnt[a][b] = t.tl_cnt[a][b];
             const mlb::PairConst c =
                 mlb::pair_constants(p->sigma[a], p->sigma[b], p->kT, t.sh_full[a][b], p->mass[a], p->mass[b]);
@@ -562,6 +629,10 @@ mlb_status upload_static(Batch &B, hipStream_t st)
         sh_q[k] = make_float4(bits, (float)sh_u[3 * k], (float)sh_u[3 * k + 1], (float)sh_u[3 * k + 2]);
     }
     TRY(up(B.t_sh_q, sh_q.data(), sizeof(float4) * sh_q.size()));
+    std::vector<float> sg;
+    for (auto &S : B.sys) sg.insert(sg.end(), S.tabs.sg.begin(), S.tabs.sg.end());
+    sg.resize(sg.size() + 4 * mlb::kShellPad, 0.f);
+    TRY(up(B.t_sg_q, sg.data(), sizeof(float) * sg.size()));
     // per-site block map and the identity map used by single-system launches
     std::vector<int2> site, ident((size_t)B.ident_len);
     for (int k = 0; k < B.count; ++k)
@@ -577,7 +648,7 @@ mlb_status upload_static(Batch &B, hipStream_t st)
     return MLB_OK;
 }
 
-mlb_status set_tiling(Batch &B, int shape, int order, int g1split, hipStream_t st)
+mlb_status set_tiling(Batch &B, int shape, int order, int g1split, bool groups, hipStream_t st)
 {
     int nblk = 0;
     std::vector<int2> m = tile_map(B, shape, order, nblk);
@@ -588,6 +659,7 @@ mlb_status set_tiling(Batch &B, int shape, int order, int g1split, hipStream_t s
     B.tune.shape = shape;
     B.tune.order = order;
     B.tune.g1split = g1split;
+    B.tune.groups = groups;
     if (B.graph) {
         (void)hipGraphExecDestroy(B.graph);
         B.graph = nullptr;
@@ -731,7 +803,10 @@ void run_passes(Batch &B, hipStream_t st, bool query, int qk, int force_only)
         if constexpr (std::is_same<T, float>::value) {
             if (tiled) {
                 pass(B, kPassGather1, st,
-                     [&] { mlb::launch_gather1_tile(shape, B.tune.g1split, sys, tmap, ntl, M, tb, B.reach_max, st); });
+                     [&] {
+                         mlb::launch_gather1_tile(shape, B.tune.g1split, B.tune.groups, sys, tmap, ntl, M, tb,
+                                                  B.reach_max, st);
+                     });
                 return;
             }
         }
@@ -1000,7 +1075,7 @@ mlb_status autotune(Batch &B, const double *const *n0, const double *const *u0, 
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
             const Tuning cached = it->second;
-            TRY(set_tiling(B, cached.shape, cached.order, cached.g1split, st));
+            TRY(set_tiling(B, cached.shape, cached.order, cached.g1split, cached.groups, st));
             B.tune = cached;
             return MLB_OK;
         }
@@ -1012,23 +1087,28 @@ mlb_status autotune(Batch &B, const double *const *n0, const double *const *u0, 
     HIP_TRY(hipEventCreate(&e1));
     const int warm = 2, reps = 6;
     mlb_status status = MLB_OK;
+    // graph-replayed steps of one tiling, ms per step (< 0 on failure)
+    auto trial = [&](int v, int order, int split, bool groups) -> double {
+        status = set_tiling(B, v, order, split, groups, st);
+        if (status != MLB_OK) return -1.0;
+        status = run_steps(B, warm, st, false);   // captures the graph of this tiling
+        if (status != MLB_OK) return -1.0;
+        float ms = 0.f;
+        if (hipEventRecord(e0, st) != hipSuccess) { status = fail(MLB_EHIP, "event record"); return -1.0; }
+        status = run_steps(B, reps, st, false);
+        if (status != MLB_OK) return -1.0;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            status = fail(MLB_EHIP, "event timing");
+            return -1.0;
+        }
+        return ms / reps;
+    };
     for (int split = 2; split < 2 + kSplitChoices && status == MLB_OK; ++split)
     for (int v = 0; v < mlb::kTileVariants && status == MLB_OK; ++v)
         for (int order = 0; order < 2 && status == MLB_OK; ++order) {
-            status = set_tiling(B, v, order, split, st);
+            const double per = trial(v, order, split, false);
             if (status != MLB_OK) break;
-            status = run_steps(B, warm, st, false);   // captures the graph of this tiling
-            if (status != MLB_OK) break;
-            float ms = 0.f;
-            if (hipEventRecord(e0, st) != hipSuccess) { status = fail(MLB_EHIP, "event record"); break; }
-            status = run_steps(B, reps, st, false);
-            if (status != MLB_OK) break;
-            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                status = fail(MLB_EHIP, "event timing");
-                break;
-            }
-            const double per = ms / reps;
             best.trial_ms[(split - 2) * 2 * mlb::kTileVariants + 2 * v + order] = per;
             if (per < best_ms) {
                 best_ms = per;
@@ -1037,10 +1117,15 @@ mlb_status autotune(Batch &B, const double *const *n0, const double *const *u0, 
                 best.g1split = split;
             }
         }
+    // the sign-grouped shell loop on the chosen tiling
+    if (status == MLB_OK) {
+        best.groups_ms = trial(best.shape, best.order, best.g1split, true);
+        if (status == MLB_OK && best.groups_ms < best_ms) best.groups = true;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (status != MLB_OK) return status;
-    TRY(set_tiling(B, best.shape, best.order, best.g1split, st));
+    TRY(set_tiling(B, best.shape, best.order, best.g1split, best.groups, st));
     B.tune = best;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1115,7 +1200,7 @@ mlb_status create(Batch &B, const mlb_params *params, int count, void *workspace
     if (B.tiled && !mlb::tile_prepare(B.reach_max, B.ball_reach_max, B.ball_total_max, B.maxM))
         B.tiled = false;
     TRY(upload_static<T>(B, st));
-    if (B.tiled) TRY(set_tiling(B, 0, 1, 3, st));
+    if (B.tiled) TRY(set_tiling(B, 0, 1, 3, false, st));
     for (auto &S : B.sys)
         if (S.spectral) TRY(setup_spectral(B, S, st));
     bool any_spectral = false;
@@ -1132,10 +1217,12 @@ mlb_status create(Batch &B, const mlb_params *params, int count, void *workspace
     if (!(options & MLB_OPT_NO_STABILITY_CHECK)) TRY(check_mean_states(B, st));
     const int fixed_shape = (int)((options >> 4) & 15u) - 1, fixed_order = (int)((options >> 8) & 1u);
     const int fixed_split = (int)((options >> 10) & 3u);
+    const int fixed_groups = (int)((options >> 12) & 3u);
     if (fixed_shape >= mlb::kTileVariants) return fail(MLB_EINVAL, "MLB_OPT_TILING: no such tile shape");
     if (fixed_split == 1) return fail(MLB_EINVAL, "MLB_OPT_GATHER1_SPLIT: 2 or 3 thread groups per site");
+    if (fixed_groups == 3) return fail(MLB_EINVAL, "MLB_OPT_GATHER1_SIGN_GROUPS: 0 or 1");
     if (B.tiled && fixed_shape >= 0) {
-        TRY(set_tiling(B, fixed_shape, fixed_order, fixed_split ? fixed_split : 3, st));
+        TRY(set_tiling(B, fixed_shape, fixed_order, fixed_split ? fixed_split : 3, fixed_groups == 2, st));
     } else if (B.tiled && (options & MLB_OPT_TUNE)) {
         TRY(autotune<T>(B, n0, u0, st));
     }
@@ -1736,6 +1823,19 @@ mlb_status mlb_batch_tuning_ex(mlb_batch h, int32_t *shape, int32_t *order, int3
 mlb_status mlb_tuning_ex(mlb_mixture h, int32_t *shape, int32_t *order, int32_t *gather1_split, double *trial_ms)
 {
     return mlb_batch_tuning_ex(h, shape, order, gather1_split, trial_ms);
+}
+
+mlb_status mlb_batch_tuning_groups(mlb_batch h, int32_t *sign_groups, double *groups_ms)
+{
+    if (!h) return fail(MLB_EINVAL, "handle is NULL");
+    if (sign_groups) *sign_groups = h->tiled ? (h->tune.groups ? 1 : 0) : -1;
+    if (groups_ms) *groups_ms = h->tune.groups_ms;
+    return MLB_OK;
+}
+
+mlb_status mlb_tuning_groups(mlb_mixture h, int32_t *sign_groups, double *groups_ms)
+{
+    return mlb_batch_tuning_groups(h, sign_groups, groups_ms);
 }
 
 mlb_status mlb_batch_profile_begin(mlb_batch h)

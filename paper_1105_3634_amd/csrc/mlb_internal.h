@@ -16,6 +16,10 @@ namespace mlb {
 
 constexpr int kMaxS = 4;
 constexpr int kQ = 19;
+// Sign groups of a shell half-list (float32 first gather): 0 = four points
+// (+-e_y, +-e_z), 1 = two points (+-e_y, e_z = 0), 2 = two points (e_y = 0,
+// +-e_z), 3 = two points (e_x = 0, +-e_z), 4 = single points on an axis.
+constexpr int kGroupKinds = 5;
 constexpr int kBlock = 256;          // threads per block of the per-site passes
 
 // Stencil offsets travel packed: three signed bytes (ex, ey, ez).
@@ -53,6 +57,7 @@ struct SysDesc {
     int omega_is_one;
     // stencils: indices into the batch-wide tables
     int sh_start[kMaxS][kMaxS], sh_cnt[kMaxS][kMaxS];
+    int sg_start[kMaxS][kMaxS][kGroupKinds], sg_cnt[kMaxS][kMaxS][kGroupKinds];   // sign groups (float4 index, groups)
     int tl_start[kMaxS][kMaxS], tl_cnt[kMaxS][kMaxS];
     int bl_start[kMaxS], bl_cnt[kMaxS], bl_full[kMaxS];
     // constants (computed in float64 on the host, rounded to T)
@@ -81,6 +86,12 @@ struct Tables {
     // float32 tiled gathers: the shell half-lists as float4 (packed offset
     // bits, unit vector), followed by kShellPad zero entries
     const float4 *sh_q;
+    // the same half-lists in sign groups (see kGroupKinds): a four-point
+    // group is four float4 (the members' packed offsets; |e_hat|; the
+    // squares; the products xy, xz, yz), a two-point group two float4 ((the
+    // members' offsets, |e_hat| on the shared and the flipped axis); the
+    // squares and their product), a single point the sh_q entry
+    const float4 *sg_q;
 };
 constexpr int kShellPad = 8;
 
@@ -128,8 +139,9 @@ struct Launch {
 // variant v: 0 = 16x4x4, 1 = 8x8x4, 2 = 32x4x2 sites.
 constexpr int kTileVariants = 3;
 void tile_dims(int v, int &tx, int &ty, int &tz);
-void launch_gather1_tile(int v, int split, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM,
-                         Tables<float> tb, int reach_max, hipStream_t st);
+// (groups: the sign-grouped shell loop, see gather_tile.h)
+void launch_gather1_tile(int v, int split, bool groups, const SysDesc<float> *sys, const int2 *map, int nblk,
+                         int maxM, Tables<float> tb, int reach_max, hipStream_t st);
 void launch_step2_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM, Tables<float> tb,
                        int reach_max, int parity, int write_force_only, hipStream_t st);
 // contact values on the same tiles (halo = ball reach), one thread per site

@@ -58,7 +58,8 @@ bool prepare_one(int reach, int ball_reach, int ball_total, int maxM)
     // the limit is set to the whole LDS of a CU, not to this handle's need:
     // handles with a smaller reach created later must not lower it under
     // the launches of a live handle with a larger one
-    for (const void *fn : {(const void *)k_gather1_tile<TX, TY, TZ, 2>, (const void *)k_gather1_tile<TX, TY, TZ, 3>,
+    for (const void *fn : {(const void *)k_gather1_tile<TX, TY, TZ, 2, false>, (const void *)k_gather1_tile<TX, TY, TZ, 3, false>,
+                           (const void *)k_gather1_tile<TX, TY, TZ, 2, true>, (const void *)k_gather1_tile<TX, TY, TZ, 3, true>,
                            (const void *)k_contact_tile<TX, TY, TZ>, (const void *)k_step2_tile<TX, TY, TZ>})
         if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax) != hipSuccess)
             return false;
@@ -83,24 +84,29 @@ void launch_contact_tile(int v, const SysDesc<float> *sys, const int2 *map, int 
 }
 
 namespace {
-template <int SPLIT>
+template <int SPLIT, bool GROUPED>
 void gather1_split(int v, const SysDesc<float> *sys, const int2 *map, dim3 grid, size_t lds, Tables<float> tb,
                    hipStream_t st)
 {
     const dim3 block(SPLIT * kBlock);
-    if (v == 0) hipLaunchKernelGGL((k_gather1_tile<16, 4, 4, SPLIT>), grid, block, lds, st, sys, map, tb);
-    else if (v == 1) hipLaunchKernelGGL((k_gather1_tile<8, 8, 4, SPLIT>), grid, block, lds, st, sys, map, tb);
-    else hipLaunchKernelGGL((k_gather1_tile<32, 4, 2, SPLIT>), grid, block, lds, st, sys, map, tb);
+    if (v == 0) hipLaunchKernelGGL((k_gather1_tile<16, 4, 4, SPLIT, GROUPED>), grid, block, lds, st, sys, map, tb);
+    else if (v == 1) hipLaunchKernelGGL((k_gather1_tile<8, 8, 4, SPLIT, GROUPED>), grid, block, lds, st, sys, map, tb);
+    else hipLaunchKernelGGL((k_gather1_tile<32, 4, 2, SPLIT, GROUPED>), grid, block, lds, st, sys, map, tb);
 }
 }  // namespace
 
-void launch_gather1_tile(int v, int split, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM,
-                         Tables<float> tb, int reach_max, hipStream_t st)
+void launch_gather1_tile(int v, int split, bool groups, const SysDesc<float> *sys, const int2 *map, int nblk,
+                         int maxM, Tables<float> tb, int reach_max, hipStream_t st)
 {
     const size_t lds = gather_lds_bytes_of(v, reach_max, MLB_G1_LAYOUTS, false);
     const dim3 grid(nblk, maxM);
-    if (split == 2) gather1_split<2>(v, sys, map, grid, lds, tb, st);
-    else gather1_split<3>(v, sys, map, grid, lds, tb, st);
+    if (split == 2) {
+        if (groups) gather1_split<2, true>(v, sys, map, grid, lds, tb, st);
+        else gather1_split<2, false>(v, sys, map, grid, lds, tb, st);
+    } else {
+        if (groups) gather1_split<3, true>(v, sys, map, grid, lds, tb, st);
+        else gather1_split<3, false>(v, sys, map, grid, lds, tb, st);
+    }
 }
 
 void launch_step2_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM, Tables<float> tb,

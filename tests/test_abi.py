@@ -123,6 +123,8 @@ def test_null_arguments_are_rejected_without_device_work():
         lambda: lib.mlb_conserved(None, None, None, None),
         lambda: lib.mlb_set_closure(None, None, 50, 1e-2),
         lambda: lib.mlb_init_mixture_ex(None, None, 0, None, None, 0, None, None),
+        lambda: lib.mlb_tuning_groups(None, None, None),
+        lambda: lib.mlb_batch_tuning_groups(None, None, None),
     ]
     for call in calls:
         lib.mlb_last_error()

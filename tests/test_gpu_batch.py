@@ -78,8 +78,10 @@ def test_autotuner_restores_initial_state():
     assert tune["shape"] in (0, 1, 2) and tune["order"] in (0, 1) and tune["gather1_split"] in (2, 3)
     assert len(tune["trial_ms"]) == 12 and all(v > 0 for v in tune["trial_ms"])
     assert bt.steps == 0
+    assert tune["gather1_sign_groups"] in (0, 1) and tune["sign_groups_ms"] > 0
     b0 = mlb.GpuBatch(mixes, n0s, u0s, precision=32,
-                      options=mlb.opt_tiling(tune["shape"], tune["order"], tune["gather1_split"]))
+                      options=mlb.opt_tiling(tune["shape"], tune["order"], tune["gather1_split"],
+                                             tune["gather1_sign_groups"]))
     bt.step(4)
     b0.step(4)
     for k in range(len(sy)):

@@ -136,6 +136,34 @@ def test_fp32_densities_within_1e5(oracle_lib, name, steps):
     assert e32 < 1e-5
 
 
+@pytest.mark.parametrize("name,steps", [("step_binary", 100), ("walls", 100), ("fe_tau", 60),
+                                        ("ternary_tail_ext", 50), ("quaternary_wide", 30),
+                                        ("single_species", 100), ("absent_species", 60)])
+def test_fp32_sign_grouped_gather_within_1e5(oracle_lib, name, steps):
+    """The first gather's sign-grouped shell loop (MLB_OPT_GATHER1_SIGN_GROUPS):
+    float32 densities against the oracle within 1e-5, and the force parts of
+    one step within 2e-6, on the 16x4x4 and 8x8x4 tilings."""
+    import paper_1105_3634_amd as mlb
+    m, n0, u0 = _case(name)
+    o = oracle_lib.Oracle(m)
+    f0 = o.init(n0, u0)
+    no = o.fields(o.step(f0, steps))["n"]
+    for shape in (0, 1):
+        print(f"[fp32 sign groups] case={name} shape={shape} steps={steps}", flush=True)
+        g = _gpu(m, n0, u0, 32, options=mlb.opt_tiling(shape, 1, 3, 1))
+        assert g.tuning()["gather1_sign_groups"] == 1
+        if name == "ternary_tail_ext":
+            ref = o.fields(f0)
+            got = _np(g.forces(mlb.PART_ALL))
+            e = np.abs(got - ref["N"]).max() / np.abs(ref["N"]).max()
+            print(f"  force rel err {e:.3e}", flush=True)
+            assert e < 2e-6
+        g.step(steps)
+        e32 = _rel_maxnorm(_np(g.moments()[0]), no)
+        print(f"  fp32 rel err {e32:.3e}", flush=True)
+        assert e32 < 1e-5
+
+
 def test_zero_density_sites(oracle_lib):
     """Sites with no fluid at all (total density zero): the mean velocity there
     is zero, the contact values are those of the empty fluid (1) while the
@@ -380,31 +408,38 @@ def test_fp32_spectral_100_steps(oracle_lib, name):
 def test_fp32_tilings_agree_bit_for_bit(name):
     """Every tile shape and block order (MLB_OPT_TILING) sums each site's
     shell lists in the same order, so for one split of the first gather's
-    shell lists over thread groups the float32 states agree bit for bit;
-    the two splits (2 and 3 groups, MLB_OPT_GATHER1_SPLIT) add the partial
-    sums in different groupings and agree to float32 rounding."""
+    shell lists over thread groups and one form of its shell loop the
+    float32 states agree bit for bit; the two splits (2 and 3 groups,
+    MLB_OPT_GATHER1_SPLIT) and the plain and sign-grouped loops
+    (MLB_OPT_GATHER1_SIGN_GROUPS) add the same terms in different groupings
+    and agree to float32 rounding."""
     import paper_1105_3634_amd as mlb
     m, n0, u0 = _case(name)
     refs = {}
-    for split in (3, 2):
-        for shape in range(3):
-            for order in range(2):
-                print(f"[tilings] case={name} split={split} shape={shape} order={order}", flush=True)
-                g = _gpu(m, n0, u0, 32, options=mlb.opt_tiling(shape, order, split))
-                t = g.tuning()
-                assert (t["shape"], t["order"], t["gather1_split"]) == (shape, order, split)
-                g.step(6)
-                n, j = g.moments()
-                got = (_np(n), _np(j))
-                del g
-                if split not in refs:
-                    refs[split] = got
-                    continue
-                ref = refs[split]
-                assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (split, shape, order)
-    e = _rel_maxnorm(refs[2][0], refs[3][0])
-    print(f"  split 2 vs 3: density rel diff {e:.2e}", flush=True)
-    assert e < 1e-6
+    for groups in (0, 1):
+        for split in (3, 2):
+            for shape in range(3):
+                for order in range(2):
+                    print(f"[tilings] case={name} groups={groups} split={split} shape={shape} order={order}",
+                          flush=True)
+                    g = _gpu(m, n0, u0, 32, options=mlb.opt_tiling(shape, order, split, groups))
+                    t = g.tuning()
+                    assert (t["shape"], t["order"], t["gather1_split"], t["gather1_sign_groups"]) == \
+                        (shape, order, split, groups)
+                    g.step(6)
+                    n, j = g.moments()
+                    got = (_np(n), _np(j))
+                    del g
+                    key = (groups, split)
+                    if key not in refs:
+                        refs[key] = got
+                        continue
+                    ref = refs[key]
+                    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), key + (shape, order)
+    for a, b in (((0, 2), (0, 3)), ((1, 3), (0, 3)), ((1, 2), (0, 3))):
+        e = _rel_maxnorm(refs[a][0], refs[b][0])
+        print(f"  {a} vs {b}: density rel diff {e:.2e}", flush=True)
+        assert e < 1e-6
 
 
 def test_handles_of_different_reach_coexist():
