@@ -76,8 +76,9 @@ typedef enum {
 enum { MLB_SCHEME_CN_J1 = 0, MLB_SCHEME_FE = 1 };
 enum { MLB_TAIL_AUTO = 0, MLB_TAIL_DIRECT = 1, MLB_TAIL_SPECTRAL = 2 };
 enum { MLB_OPT_TUNE = 1u,       /* time every float32 tiling (tile shape, block order, thread groups
-                                   of the first gather, then the sign-grouped shell loop on the
-                                   fastest) at init, keep the fastest */
+                                   of the first gather), then the two fastest again, longer, with
+                                   the plain and the sign-grouped shell loop, at init; keep the
+                                   fastest */
        MLB_OPT_NO_GRAPH = 2u,   /* launch the passes eagerly instead of replaying a graph */
        MLB_OPT_NO_STABILITY_CHECK = 512u }; /* skip the linear-stability guard at init (studies of
                                            unstable schemes) */
