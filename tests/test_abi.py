@@ -216,3 +216,18 @@ def test_stability_guard_with_masses():
     for mass in ((0.7, 2.0), (2.5, 0.7), (0.625, 0.625), (2.5, 2.5)):
         st, r = _stability((2.0, 4.0), [0.9 * n, 0.1 * n], W.SCHEME_CN_J1, mass=mass)
         assert st == 0 and r < 1.0, (mass, r)
+
+
+def test_sign_group_tables_cover_every_shell():
+    """The float32 first gather's sign groups (points of a half-shell that
+    differ only in the signs of their y and z components) are built on the
+    host for every pair; init refuses a half-list that is not closed under
+    those sign changes or leaves a point out.  Sizing a batch builds them:
+    every diameter pair from 1 to 9 in steps of 0.25 (shell radii up to
+    9.5 lattice units) must pass."""
+    import paper_1105_3634_amd as mlb
+    sig = [1.0 + 0.25 * k for k in range(33)]
+    for s1 in sig[::4]:
+        for s2 in sig:
+            m = W.Mixture(24, 24, 24, sigma=(s1, s2))
+            assert mlb.workspace_bytes(mlb.make_params(m, precision=32)) > 0, (s1, s2)
