@@ -226,6 +226,15 @@ def closure_leg(mlb, W, steps=5000, train_box=(192, 12, 12)):
     plain = run(False, 0.0)
     checked = run(True, 1e-2)
     forced = run(True, float("inf"))
+    # looser check tolerances: how many of the steps the network carries,
+    # and D_12 and the throughput of the run at each
+    sweep = {}
+    for tol in (0.03, 0.05, 0.1, 0.2):
+        r = run(True, tol)
+        rr, _ = rate(True, k=500, check_every=50, tol=tol)
+        sweep[f"{tol:g}"] = {"network_steps": r["network_steps"], "failed_checks": r["failed_checks"],
+                             "checks": r["checks"], "d12": r["d12"], "d12_rel_diff": r["d12"] / plain["d12"] - 1.0,
+                             "ssu_per_s": rr, "speedup": None}
     r_plain, p_plain = rate(False)
     # network-only steps (no check after the first): the speed of a step on
     # the network's force, not of a run at any stated accuracy
@@ -233,6 +242,8 @@ def closure_leg(mlb, W, steps=5000, train_box=(192, 12, 12)):
     # the checked run as it is used: checks every 50 steps at tolerance 1e-2,
     # the exact force up to the next check after a failed one
     r_chk, _ = rate(True, k=500, check_every=50, tol=1e-2)
+    for v in sweep.values():
+        v["speedup"] = v["ssu_per_s"] / r_plain
     macs = 27 * (8 * 32 + 32 * 32 + 32 * 32 + 32 * 6)
     net_ms = p_net.get("closure", 0.0)
     tflops = 2.0 * macs * mix.N / (net_ms * 1e-3) / 1e12 if net_ms else None
@@ -241,6 +252,7 @@ def closure_leg(mlb, W, steps=5000, train_box=(192, 12, 12)):
         "train": {"box": list(train_box), "snapshots": rep.samples, "adam_steps": rep.steps,
                   "collect_s": rep.collect_seconds, "train_s": rep.train_seconds},
         "plain": plain, "closure_checked": checked, "closure_no_fallback": forced,
+        "tolerance_sweep": sweep,
         "d12_rel_diff_checked": checked["d12"] / plain["d12"] - 1.0,
         "d12_rel_diff_no_fallback": forced["d12"] / plain["d12"] - 1.0,
         "ssu_per_s": {"plain": r_plain, "closure_network_steps_only": r_net,
@@ -673,6 +685,7 @@ def main():
                     help="only the batched-ensemble leg (profiling runs), one JSON line")
     ap.add_argument("--network-only", action="store_true",
                     help="only the closure network's kernels (forward and training steps, --steps of each)")
+    ap.add_argument("--closure-only", action="store_true", help="only the learned-closure leg")
     ap.add_argument("--ensemble-steps", type=int, default=1000)
     ap.add_argument("--ensemble-timed", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -711,6 +724,9 @@ def main():
         return
     if args.network_only:
         print(json.dumps(network_leg(mlb, W, reps=args.steps)), flush=True)
+        return
+    if args.closure_only:
+        print(json.dumps(closure_leg(mlb, W, steps=args.closure_steps)), flush=True)
         return
     mix, n0, u0 = W.config_bulk_diffusion()
     tail_mode = {"auto": mlb.TAIL_AUTO, "direct": mlb.TAIL_DIRECT, "spectral": mlb.TAIL_SPECTRAL}[args.tail]
