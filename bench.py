@@ -148,58 +148,97 @@ def d12_check(mlb, mix, n0, u0):
 def closure_leg(mlb, W, steps=5000, train_box=(192, 12, 12)):
     """Learned force closure on the 192x64x64 binary workload at the
     step-binary physics: train the network on snapshots of the plain solver
-    (a 192x12x12 box, composition modes of the workload's wavelength), then
-    run the plain step, the closure with exact-force checks every 50 steps
-    (the exact force until the next check whenever a check's relative error
-    is above 1e-2), and the closure with every check passing; D_12 from the
-    mode decay of each, and the throughput of plain and closure steps."""
+    (a 192x12x12 box, composition modes of the workload's wavelength), four
+    candidates from different seeds, and keep the one whose checked run on a
+    held-out state of the training box (tolerance 0.1) puts the most steps
+    on the network with D_12 within 1 % of the plain run's; then run the
+    plain step, the closure with exact-force checks every 50 steps (the
+    exact force until the next check whenever a check's relative error is
+    above the tolerance) at several tolerances, and the closure with every
+    check passing; D_12 from the mode decay of each, and the throughput of
+    each run."""
     import torch
 
-    from paper_1105_3634_amd.closure_train import init_params, train_closure
+    from paper_1105_3634_amd.closure_train import fit, init_params, prepare_pool
 
     nx, ny, nz = train_box
     n_tot = W.number_density(0.2, (0.5, 0.5), (2.0, 3.0))
 
-    def state(amp, wl, noise, seed):
+    def state(amp):
         def make():
             m = W.Mixture(nx, ny, nz, sigma=(2.0, 3.0), tau=1.0, name="closure_train")
-            n0, u0 = W.mode_state(m, n_tot, 0.5, amp, noise=noise, seed=seed, wavelength=wl)
+            n0, u0 = W.mode_state(m, n_tot, 0.5, amp)
             return m, n0, u0
         return make
 
     # composition modes at the workload's wavelength (the box length along
     # x), amplitudes 0.01 .. 0.1.  A composition-step state in the pool
     # would set the force scale f_ref two orders of magnitude above these
-    # modes' forces, which bfloat16 activations then do not resolve (first
-    # check error about 1 instead of 0.01 - 0.1).
-    specs = [(0.05, 192, 0.0), (0.1, 192, 0.0), (0.04, 192, 0.0), (0.01, 192, 0.0), (0.07, 192, 0.0),
-             (0.03, 192, 0.0), (0.06, 192, 0.0), (0.02, 192, 0.0), (0.08, 192, 0.0)]
-    states = [state(a, wl, nz_, 300 + i) for i, (a, wl, nz_) in enumerate(specs)]
+    # modes' forces.
+    amps = (0.05, 0.1, 0.04, 0.01, 0.07, 0.03, 0.06, 0.02, 0.08)
     tnet = mlb.GpuNet((nz, ny, nx), training=True)
-    tnet.set_params(init_params(0))
-    # snapshots every 25 steps span the 5000-step run; 20 epochs at lr 1e-3
-    rep = train_closure(tnet, states, per_state=200, sample_every=25, epochs=20, lr=1e-3)
-    params = tnet.get_params(flat=True)
-    del tnet
+    # snapshots every 25 steps span the 5000-step run
+    x, t, scales, collect_s = prepare_pool(tnet, [state(a) for a in amps], per_state=200, sample_every=25)
+    print(f"closure: {int(x.shape[0])} training pairs in {collect_s:.1f} s", file=sys.stderr, flush=True)
+
+    # held-out validation on the training box: amplitude 0.045, the
+    # workload's 5000 steps and checks every 50
+    def d12_run(net, tol):
+        m, n0, u0 = state(0.045)()
+        g = mlb.GpuMixture(m, n0, u0, precision=32, device="cuda:0")
+        if net is not None:
+            g.set_closure(net, check_every=50, tol=tol)
+        for k in range(0, steps + 1, 10):
+            g.record_mode(0, 1)
+            if k < steps:
+                g.step(10)
+        D = g.fit(0, t_min=200)
+        return D, (g.closure_stats()["net_steps"] if net is not None else 0)
+
+    d_val_plain, _ = d12_run(None, 0.0)
+    cands = []
+    t_fit = time.perf_counter()
+    for seed in (0, 1, 2, 3):
+        tnet.set_params(init_params(seed))
+        fit(tnet, x, t, epochs=20, lr=1e-3, lr_final=1e-5, seed=seed)
+        d, ns = d12_run(tnet, 0.1)
+        cands.append({"seed": seed, "params": tnet.get_params(flat=True), "val_d12_rel_diff": d / d_val_plain - 1.0,
+                      "val_network_steps": ns})
+        print(f"closure: candidate {seed}: validation D_12 {d / d_val_plain - 1.0:+.4f}, network steps {ns}/{steps}",
+              file=sys.stderr, flush=True)
+    train_s = time.perf_counter() - t_fit
+    ok = [c for c in cands if abs(c["val_d12_rel_diff"]) <= 0.01 and c["val_network_steps"] > 0]
+    used = [c for c in cands if c["val_network_steps"] > 0] or cands
+    best = (max(ok, key=lambda c: c["val_network_steps"]) if ok
+            else min(used, key=lambda c: abs(c["val_d12_rel_diff"])))
+    params = best["params"]
+    samples = int(x.shape[0])
+    del tnet, x, t
+    torch.cuda.empty_cache()
 
     mix, n0, u0 = W.config_closure_physics()
     net = mlb.GpuNet(mix.shape())
     net.set_params(params)
-    net.set_scales(*rep.scales)
+    net.set_scales(*scales)
 
     def run(closure, tol):
         g = mlb.GpuMixture(mix, n0, u0, precision=32, device="cuda:0")
         if closure:
             g.set_closure(net, check_every=50, tol=tol)
         errs = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         for t in range(0, steps + 1, 10):
             g.record_mode(0, 1)
             if t < steps:
                 g.step(10)
             if closure and t % 50 == 0:
                 errs.append(g.closure_stats()["last_err"])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
         D = g.fit(0, t_min=200)
-        out = {"d12": D}
+        # the whole run's throughput: checks, fallbacks and mode records included
+        out = {"d12": D, "ssu_per_s": mix.M * mix.N * steps / dt}
         if closure:
             st = g.closure_stats()
             out.update({"checks": st["checks"], "failed_checks": st["failed_checks"],
@@ -229,35 +268,42 @@ def closure_leg(mlb, W, steps=5000, train_box=(192, 12, 12)):
     # looser check tolerances: how many of the steps the network carries,
     # and D_12 and the throughput of the run at each
     sweep = {}
-    for tol in (0.03, 0.05, 0.1, 0.2):
+    for tol in (0.02, 0.05, 0.1, 0.2, 0.3, 0.5):
         r = run(True, tol)
-        rr, _ = rate(True, k=500, check_every=50, tol=tol)
+        print(f"closure: tolerance {tol:g}: network steps {r['network_steps']}/{steps}, "
+              f"D_12 {r['d12'] / plain['d12'] - 1.0:+.4f}", file=sys.stderr, flush=True)
         sweep[f"{tol:g}"] = {"network_steps": r["network_steps"], "failed_checks": r["failed_checks"],
                              "checks": r["checks"], "d12": r["d12"], "d12_rel_diff": r["d12"] / plain["d12"] - 1.0,
-                             "ssu_per_s": rr, "speedup": None}
+                             "ssu_per_s": r["ssu_per_s"], "speedup": r["ssu_per_s"] / plain["ssu_per_s"]}
     r_plain, p_plain = rate(False)
     # network-only steps (no check after the first): the speed of a step on
     # the network's force, not of a run at any stated accuracy
     r_net, p_net = rate(True)
-    # the checked run as it is used: checks every 50 steps at tolerance 1e-2,
-    # the exact force up to the next check after a failed one
-    r_chk, _ = rate(True, k=500, check_every=50, tol=1e-2)
-    for v in sweep.values():
-        v["speedup"] = v["ssu_per_s"] / r_plain
-    macs = 27 * (8 * 32 + 32 * 32 + 32 * 32 + 32 * 6)
+    # the stated accuracy: D_12 within 2 % of the plain run; of the swept
+    # tolerances that meet it, the one where the network carries most steps
+    meets = [(k, v) for k, v in sweep.items() if math.isfinite(v["d12"]) and abs(v["d12_rel_diff"]) <= 0.02]
+    at_accuracy = None
+    if meets:
+        k, v = max(meets, key=lambda kv: kv[1]["network_steps"])
+        at_accuracy = {"tol": float(k), "network_steps": v["network_steps"], "d12_rel_diff": v["d12_rel_diff"],
+                       "ssu_per_s": v["ssu_per_s"], "speedup": v["speedup"]}
+    macs = 27 * (14 * 32 + 32 * 32 + 32 * 32 + 32 * 6)
     net_ms = p_net.get("closure", 0.0)
     tflops = 2.0 * macs * mix.N / (net_ms * 1e-3) / 1e12 if net_ms else None
     return {
         "workload": f"closure_{mix.nx}x{mix.ny}x{mix.nz}", "steps": steps,
-        "train": {"box": list(train_box), "snapshots": rep.samples, "adam_steps": rep.steps,
-                  "collect_s": rep.collect_seconds, "train_s": rep.train_seconds},
+        "train": {"box": list(train_box), "snapshots": samples, "adam_steps_per_candidate": 20 * samples,
+                  "collect_s": collect_s, "train_and_validate_s": train_s,
+                  "candidates": [{k: v for k, v in c.items() if k != "params"} for c in cands],
+                  "kept_seed": best["seed"], "validation_d12_plain": d_val_plain},
         "plain": plain, "closure_checked": checked, "closure_no_fallback": forced,
-        "tolerance_sweep": sweep,
+        "tolerance_sweep": sweep, "at_d12_within_2pct": at_accuracy,
         "d12_rel_diff_checked": checked["d12"] / plain["d12"] - 1.0,
         "d12_rel_diff_no_fallback": forced["d12"] / plain["d12"] - 1.0,
         "ssu_per_s": {"plain": r_plain, "closure_network_steps_only": r_net,
                       "speedup_network_steps_only": r_net / r_plain,
-                      "closure_checked_tol_1e-2": r_chk, "speedup_checked_tol_1e-2": r_chk / r_plain},
+                      "plain_run": plain["ssu_per_s"], "closure_checked_tol_1e-2_run": checked["ssu_per_s"],
+                      "speedup_checked_tol_1e-2": checked["ssu_per_s"] / plain["ssu_per_s"]},
         "passes_ms_per_step": {"plain": p_plain, "closure": p_net},
         "network_roofline": {"bound": "mfma", "achieved": tflops, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                              "frac": tflops / BF16_PEAK_TFLOPS if tflops else None,
@@ -474,7 +520,7 @@ def network_leg(mlb, W, reps=20):
     net = mlb.GpuNet(shape, training=True)
     net.set_params(init_params(0))
     gen = torch.Generator(device="cuda:0").manual_seed(7)
-    x = torch.randn((8,) + shape, generator=gen, device="cuda:0")
+    x = torch.randn((mlb.NET_CHANNELS[0],) + shape, generator=gen, device="cuda:0")
     t = torch.randn((6,) + shape, generator=gen, device="cuda:0")
     net.forward(x)
     torch.cuda.synchronize()
@@ -488,7 +534,7 @@ def network_leg(mlb, W, reps=20):
         net.train_step(x, t, lr=1e-4, want_loss=False)
     torch.cuda.synchronize()
     trn = (time.perf_counter() - t0) / reps
-    macs = 27 * (8 * 32 + 32 * 32 + 32 * 32 + 32 * 6) * mix.N
+    macs = 27 * (14 * 32 + 32 * 32 + 32 * 32 + 32 * 6) * mix.N
     return {"workload": f"network_{mix.nx}x{mix.ny}x{mix.nz}", "forward_ms": fwd * 1e3, "train_step_ms": trn * 1e3,
             "forward_tflops": 2.0 * macs / fwd / 1e12, "train_tflops": 6.0 * macs / trn / 1e12,
             "peak_bf16_tflops": BF16_PEAK_TFLOPS}

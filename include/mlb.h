@@ -388,14 +388,13 @@ mlb_status mlb_batch_destroy(mlb_batch h);
  * the collision with streaming.
  *
  * Network: four 3x3x3 convolutions on the periodic lattice, channels
- * 8 -> 32 -> 32 -> 32 -> 6, SiLU s(z) = z / (1 + exp(-z)) after the first
- * three.  Input channels (n_0 / n_ref - 1, n_1 / n_ref - 1, j_0 / j_ref,
- * j_1 / j_ref) (j_a: x, y, z), output channels N_a,d / f_ref at index
- * 3a + d.  Weights and activations are bfloat16 with float32 accumulation
- * on the matrix cores; the first layer carries inputs and weights as
- * bfloat16 hi/lo pairs (about 16 significant bits), because the force is a
- * small spatial derivative of its inputs.  Adam keeps float32 master
- * weights.
+ * 14 -> 32 -> 32 -> 32 -> 6, SiLU s(z) = z / (1 + exp(-z)) after the first
+ * three.  Input channels: 0..1 n_a / n_ref - 1; 2..7 j_a,d / j_ref at
+ * 2 + 3a + d; 8..13 the lattice pressure gradients c_s^2 (n_a(r + e_d) -
+ * n_a(r - e_d)) / 2 / f_ref at 8 + 3a + d (c_s^2 = 1/3, periodic wrap).
+ * Output channels N_a,d / f_ref at index 3a + d.  Weights and activations
+ * are bfloat16 with float32 accumulation on the matrix cores; Adam keeps
+ * float32 master weights.
  *
  * Parameters (mlb_net_param_count() floats) travel as HOST float32 arrays,
  * layer by layer: W[co][ci][kz][ky][kx] (kz, ky, kx = offset + 1; the
@@ -421,11 +420,11 @@ mlb_status mlb_net_set_params(mlb_net net, const float *params, void *stream);
 mlb_status mlb_net_get_params(mlb_net net, float *params, void *stream);
 /* Input and output scales n_ref, j_ref, f_ref (all > 0; default 1). */
 mlb_status mlb_net_set_scales(mlb_net net, double n_ref, double j_ref, double f_ref);
-/* y [6][N] = network(x [8][N]); DEVICE float32, channel-first, x fastest. */
+/* y [6][N] = network(x [14][N]); DEVICE float32, channel-first, x fastest. */
 mlb_status mlb_net_forward(mlb_net net, const float *x, float *y, void *stream);
 /* One training step on loss_weight times the mean squared error over all
  * N x 6 outputs: forward, backward, and (update != 0) one Adam step with
- * rate lr, b1 = 0.9, b2 = 0.999, eps = 1e-8.  x [8][N] and target [6][N]
+ * rate lr, b1 = 0.9, b2 = 0.999, eps = 1e-8.  x [14][N] and target [6][N]
  * are DEVICE float32; loss_weight > 0 (e.g. the reciprocal mean square of
  * the target, for a relative error).  loss (HOST, may be NULL) receives the
  * weighted loss before the update; grads (HOST, may be NULL,
@@ -434,14 +433,14 @@ mlb_status mlb_net_forward(mlb_net net, const float *x, float *y, void *stream);
  * otherwise). */
 mlb_status mlb_net_train_step(mlb_net net, const float *x, const float *target, float lr, float loss_weight,
                               int32_t update, double *loss, float *grads, void *stream);
-/* Statistics of a training pool of `count` samples, x [count][8][N] and
+/* Statistics of a training pool of `count` samples, x [count][14][N] and
  * targets t [count][6][N] (DEVICE float32, channel-first): out (HOST,
  * count + 1 doubles) receives out[0] = the mean square of the momentum
  * channels 2..7 of x over the pool and out[1 + s] = the mean square of
  * target s (float64 sums).  Synchronises. */
 mlb_status mlb_net_pool_stats(mlb_net net, const float *x, const float *t, int32_t count, double *out, void *stream);
-/* In place on the same pool: x's momentum channels divided by j_div, the
- * targets by f_div (both > 0). */
+/* In place on the same pool: x's momentum channels 2..7 divided by j_div,
+ * its gradient channels 8..13 and the targets by f_div (both > 0). */
 mlb_status mlb_net_pool_rescale(mlb_net net, float *x, float *t, int32_t count, double j_div, double f_div,
                                 void *stream);
 /* err (HOST) = ||y - t||_2 / ||t||_2 over [6][N] DEVICE float32 arrays of the
@@ -472,7 +471,7 @@ mlb_status mlb_closure_stats(mlb_mixture h, int64_t *checks, int64_t *fallback_s
  * checks; HOST outputs (either may be NULL). */
 mlb_status mlb_closure_usage(mlb_mixture h, int64_t *net_steps, int64_t *failed_checks);
 /* A training pair from the current state (populations are not changed):
- * x_out [8][N] the network input with `net`'s scales and target_out [6][N]
+ * x_out [14][N] the network input with `net`'s scales and target_out [6][N]
  * the exact force divided by f_ref; DEVICE float32.  Needs a float32
  * binary mixture on `net`'s grid. */
 mlb_status mlb_closure_sample(mlb_mixture h, mlb_net net, float *x_out, float *target_out, void *stream);

@@ -4,9 +4,10 @@ The closure is a small 3D convolutional network that maps the local
 state of a binary mixture to the force densities N_a = n_a Phi_a of the
 kinetic equation (Sec. 2, eq. evolution; Sec. 3, eq. splitforce):
 
-  input  x  [8][Z][Y][X]:  (n_0, n_1) and (j_0, j_1) after affine scaling
+  input  x  [14][Z][Y][X]: (n_0, n_1), (j_0, j_1) and the pressure gradients
+                           of n_0 and n_1, each after affine scaling
   layers    4 convolutions with 3x3x3 kernels on the periodic lattice,
-            channels 8 -> 32 -> 32 -> 32 -> 6, SiLU after the first three
+            channels 14 -> 32 -> 32 -> 32 -> 6, SiLU after the first three
   output y  [6][Z][Y][X]:  N_0 and N_1 (three components each) after scaling
 
 Convolution (cross-correlation, periodic):
@@ -24,7 +25,7 @@ from typing import Dict, List, Tuple
 import numpy as np
 
 TAPS = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
-CHANNELS = (8, 32, 32, 32, 6)
+CHANNELS = (14, 32, 32, 32, 6)
 
 
 def shift(x: np.ndarray, d) -> np.ndarray:

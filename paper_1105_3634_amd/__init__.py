@@ -267,9 +267,9 @@ class GpuMixture:
                 "active": bool(act.value), "net_steps": int(steps.value), "failed_checks": int(failed.value)}
 
     def closure_sample(self, net: "GpuNet"):
-        """(x [8][...], target [6][...]) float32 device tensors for the current state."""
+        """(x [14][...], target [6][...]) float32 device tensors for the current state."""
         torch = _torch()
-        x = torch.empty((8,) + self.shape, dtype=torch.float32, device=self.device)
+        x = torch.empty((NET_CHANNELS[0],) + self.shape, dtype=torch.float32, device=self.device)
         t = torch.empty((6,) + self.shape, dtype=torch.float32, device=self.device)
         _lib.check(self.lib.mlb_closure_sample(self.h, net.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
                                                _stream_handle(self.stream)), "mlb_closure_sample")
@@ -406,7 +406,7 @@ class GpuBatch:
         return {self.lib.mlb_pass_name(k).decode(): (ms[k], cnt[k]) for k in range(_lib.NPASS)}
 
 
-NET_CHANNELS = (8, 32, 32, 32, 6)
+NET_CHANNELS = (14, 32, 32, 32, 6)
 
 
 def net_flatten(layers) -> np.ndarray:
@@ -488,9 +488,9 @@ class GpuNet:
         return x
 
     def forward(self, x):
-        """x [8][nz][ny][nx] -> y [6][nz][ny][nx] (float32 device tensors)."""
+        """x [14][nz][ny][nx] -> y [6][nz][ny][nx] (float32 device tensors)."""
         torch = _torch()
-        x = self._dev(x, 8)
+        x = self._dev(x, NET_CHANNELS[0])
         y = torch.empty((6,) + self.shape, dtype=torch.float32, device=self.device)
         _lib.check(self.lib.mlb_net_forward(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
                                             _stream_handle(self.stream)), "mlb_net_forward")
@@ -498,18 +498,20 @@ class GpuNet:
 
     def pool_stats(self, x, t):
         """(mean square of the momentum channels of x over the pool, [mean square
-        of each target]) for a pool x [S][8][...], t [S][6][...] (mlb_net_pool_stats)."""
+        of each target]) for a pool x [S][14][...], t [S][6][...] (mlb_net_pool_stats)."""
         S = int(x.shape[0])
-        assert x.is_contiguous() and t.is_contiguous() and x.numel() == S * 8 * self.N and t.numel() == S * 6 * self.N
+        assert x.is_contiguous() and t.is_contiguous()
+        assert x.numel() == S * NET_CHANNELS[0] * self.N and t.numel() == S * 6 * self.N
         out = (C.c_double * (S + 1))()
         _lib.check(self.lib.mlb_net_pool_stats(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()), S, out,
                                                _stream_handle(self.stream)), "mlb_net_pool_stats")
         return float(out[0]), [float(v) for v in out[1:]]
 
     def pool_rescale(self, x, t, j_div: float, f_div: float) -> None:
-        """In place: x's momentum channels / j_div, t / f_div (mlb_net_pool_rescale)."""
+        """In place: x's momentum channels / j_div, its gradient channels and t / f_div (mlb_net_pool_rescale)."""
         S = int(x.shape[0])
-        assert x.is_contiguous() and t.is_contiguous() and x.numel() == S * 8 * self.N and t.numel() == S * 6 * self.N
+        assert x.is_contiguous() and t.is_contiguous()
+        assert x.numel() == S * NET_CHANNELS[0] * self.N and t.numel() == S * 6 * self.N
         _lib.check(self.lib.mlb_net_pool_rescale(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()), S,
                                                  float(j_div), float(f_div), _stream_handle(self.stream)),
                    "mlb_net_pool_rescale")
@@ -526,7 +528,7 @@ class GpuNet:
     def train_step(self, x, target, lr: float = 1e-3, update: bool = True, want_loss: bool = True,
                    want_grads: bool = False, loss_weight: float = 1.0):
         """One Adam step on loss_weight x MSE; returns (loss before the update or None, gradients or None)."""
-        x = self._dev(x, 8)
+        x = self._dev(x, NET_CHANNELS[0])
         t = self._dev(target, 6)
         loss = C.c_double()
         grads = np.empty(self.nparams, dtype=np.float32) if want_grads else None

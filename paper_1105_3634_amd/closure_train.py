@@ -38,7 +38,7 @@ class TrainReport:
     train_seconds: float
 
 
-def init_params(seed: int = 0, channels=(8, 32, 32, 32, 6)):
+def init_params(seed: int = 0, channels=(14, 32, 32, 32, 6)):
     """Uniform He initialisation (fan-in 27 Ci), zero biases; PCG64-seeded."""
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
@@ -52,7 +52,7 @@ def collect(net: GpuNet, states: Sequence[Callable[[], tuple]], per_state: int, 
             n_ref: float, device: str = "cuda:0"):
     """Training pairs with input scales (n_ref, 1) and unit force scale: for
     every initial state, `per_state` snapshots taken every `sample_every`
-    steps from step 0 on.  Returns device tensors x [S][8][...], t [S][6][...]."""
+    steps from step 0 on.  Returns device tensors x [S][14][...], t [S][6][...]."""
     import torch
 
     net.set_scales(n_ref, 1.0, 1.0)
@@ -72,7 +72,7 @@ def collect(net: GpuNet, states: Sequence[Callable[[], tuple]], per_state: int, 
 
 def fit(net: GpuNet, x, t, epochs: int, lr: float = 1e-3, lr_final: float = 1e-5, seed: int = 0,
         log_every: int = 0, log: Optional[Callable[[str], None]] = None) -> List[float]:
-    """Shuffled epochs over scaled pairs x [S][8][...], t [S][6][...]; the
+    """Shuffled epochs over scaled pairs x [S][14][...], t [S][6][...]; the
     learning rate decays geometrically from lr to lr_final over all steps."""
     import torch
 
@@ -97,26 +97,35 @@ def fit(net: GpuNet, x, t, epochs: int, lr: float = 1e-3, lr_final: float = 1e-5
     return losses
 
 
-def train_closure(net: GpuNet, states: Sequence[Callable[[], tuple]], per_state: int = 100, sample_every: int = 10,
-                  epochs: int = 10, lr: float = 1e-3, lr_final: float = 1e-5, seed: int = 0,
-                  log_every: int = 0, log: Optional[Callable[[str], None]] = None,
-                  device: str = "cuda:0") -> TrainReport:
+def prepare_pool(net: GpuNet, states: Sequence[Callable[[], tuple]], per_state: int = 100, sample_every: int = 10,
+                 device: str = "cuda:0"):
     """Collect pairs from `states` (callables returning (mixture, n0, u0) on
-    the net's grid), fix the scales from them, and fit the network."""
+    the net's grid) and fix the scales from them: returns the rescaled pool
+    (x, t), the scales (n_ref, j_ref, f_ref), already set on `net`, and the
+    collection time."""
     t0 = time.perf_counter()
     _, n0, _ = states[0]()
     n_ref = float(np.mean(n0))
     x, t = collect(net, states, per_state, sample_every, n_ref, device)
-    t1 = time.perf_counter()
     j_ms, t_ms = net.pool_stats(x, t)
     j_ref = max(math.sqrt(j_ms), 1e-30)
     f_ref = max(math.sqrt(sum(t_ms) / len(t_ms)), 1e-30)
     net.pool_rescale(x, t, j_ref, f_ref)
     scales = (n_ref, j_ref, f_ref)
     net.set_scales(*scales)
+    return x, t, scales, time.perf_counter() - t0
+
+
+def train_closure(net: GpuNet, states: Sequence[Callable[[], tuple]], per_state: int = 100, sample_every: int = 10,
+                  epochs: int = 10, lr: float = 1e-3, lr_final: float = 1e-5, seed: int = 0,
+                  log_every: int = 0, log: Optional[Callable[[str], None]] = None,
+                  device: str = "cuda:0") -> TrainReport:
+    """Collect pairs from `states`, fix the scales from them, and fit the network."""
+    x, t, scales, collect_s = prepare_pool(net, states, per_state, sample_every, device)
+    t1 = time.perf_counter()
     losses = fit(net, x, t, epochs, lr, lr_final, seed, log_every, log)
     return TrainReport(samples=int(x.shape[0]), steps=epochs * int(x.shape[0]), losses=losses, scales=scales,
-                       collect_seconds=t1 - t0, train_seconds=time.perf_counter() - t1)
+                       collect_seconds=collect_s, train_seconds=time.perf_counter() - t1)
 
 
 def closure_error(net: GpuNet, g: GpuMixture) -> float:

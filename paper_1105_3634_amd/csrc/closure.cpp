@@ -42,6 +42,7 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr int kErrParts = 1024;
 constexpr int kPoolParts = 32, kPoolChunk = 256;   // partial sums per sample, samples per pass
+constexpr long long kIn = mlb::kNetIn;             // input channels of a pool sample
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -139,7 +140,7 @@ unsigned long long net_version(const mlb_net_s *n) { return n->version; }
 void net_infer_fields(mlb_net_s *n, const float *dens, const float *mom, float *force, hipStream_t st)
 {
     const CnnShape sh = shape_of(*n);
-    cnn_pack_input(sh, dens, mom, n->n_ref, n->j_ref, at<unsigned short>(*n, n->x), st);
+    cnn_pack_input(sh, dens, mom, n->n_ref, n->j_ref, n->f_ref, at<unsigned short>(*n, n->x), st);
     const unsigned short *in = at<unsigned short>(*n, n->x);
     for (int l = 0; l < kNetLayers - 1; ++l) {
         const auto &L = n->L[l];
@@ -230,7 +231,7 @@ mlb_status mlb_net_set_params(mlb_net n, const float *params, void *stream)
         HIP_TRY(hipMemsetAsync(n->ws + L.v, 0, 4 * (size_t)L.nw, st));
         HIP_TRY(hipMemsetAsync(n->ws + L.mb, 0, 4 * (size_t)L.cop, st));
         HIP_TRY(hipMemsetAsync(n->ws + L.vb, 0, 4 * (size_t)L.cop, st));
-        mlb::cnn_cast(L.nw, L.cop, L.cip, L.cin, mlb::net_split(l) ? 1 : 0, at<float>(*n, L.w), at<unsigned short>(*n, L.wb),
+        mlb::cnn_cast(L.nw, L.cop, L.cip, at<float>(*n, L.w), at<unsigned short>(*n, L.wb),
                       at<unsigned short>(*n, L.wt), st);
     }
     n->adam_t = 0;
@@ -305,7 +306,7 @@ mlb_status mlb_net_pool_stats(mlb_net n, const float *x, const float *t, int32_t
     const long long N = n->N;
     std::vector<double> sx((size_t)count), stt((size_t)count);
     // the momentum channels 2..7 of every input sample
-    if (mlb_status s = pool_sumsq(*n, x + 2 * N, 8 * N, 6 * N, count, sx.data(), st)) return s;
+    if (mlb_status s = pool_sumsq(*n, x + 2 * N, kIn * N, 6 * N, count, sx.data(), st)) return s;
     if (mlb_status s = pool_sumsq(*n, t, 6 * N, 6 * N, count, stt.data(), st)) return s;
     double jx = 0.0;
     for (int s = 0; s < count; ++s) jx += sx[(size_t)s];
@@ -324,7 +325,8 @@ mlb_status mlb_net_pool_rescale(mlb_net n, float *x, float *t, int32_t count, do
     const long long N = n->N;
     for (int s0 = 0; s0 < count; s0 += kPoolChunk) {       // grid.y stays within its limit
         const int c = std::min(kPoolChunk, count - s0);
-        mlb::cnn_pool_scale(x + 2 * N + (long long)s0 * 8 * N, 8 * N, 6 * N, c, (float)(1.0 / j_div), st);
+        mlb::cnn_pool_scale(x + 2 * N + (long long)s0 * kIn * N, kIn * N, 6 * N, c, (float)(1.0 / j_div), st);
+        mlb::cnn_pool_scale(x + 8 * N + (long long)s0 * kIn * N, kIn * N, 6 * N, c, (float)(1.0 / f_div), st);
         mlb::cnn_pool_scale(t + (long long)s0 * 6 * N, 6 * N, 6 * N, c, (float)(1.0 / f_div), st);
         HIP_TRY(hipGetLastError());
     }
@@ -396,7 +398,7 @@ mlb_status mlb_net_train_step(mlb_net n, const float *x, const float *target, fl
         n->adam_t += 1;
         for (int l = 0; l < mlb::kNetLayers; ++l) {
             const auto &L = n->L[l];
-            mlb::cnn_adam(L.nw, L.cop, L.cip, L.cout, L.cin, mlb::net_split(l) ? 1 : 0, at<float>(*n, L.w), at<float>(*n, L.gw),
+            mlb::cnn_adam(L.nw, L.cop, L.cip, L.cout, L.cin, at<float>(*n, L.w), at<float>(*n, L.gw),
                           at<float>(*n, L.m), at<float>(*n, L.v), lr, 0.9, 0.999, 1e-8, n->adam_t,
                           at<unsigned short>(*n, L.wb), at<unsigned short>(*n, L.wt), at<float>(*n, L.b),
                           at<float>(*n, L.gb), at<float>(*n, L.mb), at<float>(*n, L.vb), st);
@@ -421,11 +423,7 @@ mlb_status mlb_net_train_step(mlb_net n, const float *x, const float *target, fl
             HIP_TRY(hipStreamSynchronize(st));
             for (int co = 0; co < L.cout; ++co)
                 for (int ci = 0; ci < L.cin; ++ci)
-                    for (int t = 0; t < 27; ++t) {
-                        const size_t k = ((size_t)t * L.cop + co) * L.cip + ci;
-                        // split layer: the weight's gradient is that of its x_hi and x_lo slots
-                        *p++ = mlb::net_split(l) ? w[k] + w[k + L.cin] : w[k];
-                    }
+                    for (int t = 0; t < 27; ++t) *p++ = w[((size_t)t * L.cop + co) * L.cip + ci];
             for (int co = 0; co < L.cout; ++co) *p++ = b[co];
         }
     }

@@ -1,7 +1,5 @@
 // Internal launch interface of the closure network kernels (cnn.hip).
 // Activations are channel-last bfloat16 [site][C]; C padded to 16 or 32.
-// The first layer is split bfloat16 (hi/lo parts of inputs and weights in
-// its 32 packed input channels).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,11 +12,10 @@ struct CnnShape {
 };
 
 // Layer l (0..3) has packed (in, out) channels (32, 32), (32, 32), (32, 32), (32, 16);
-// layer 0's 32 input slots hold [x_hi | x_lo | x_hi | 0] of its 8 inputs.
+// layer 0's 32 input slots hold its 14 inputs, then zeros.
 constexpr int kNetLayers = 4;
-constexpr int kNetIn = 8, kNetHidden = 32, kNetOut = 6;
+constexpr int kNetIn = 14, kNetHidden = 32, kNetOut = 6;
 inline int net_cip(int) { return 32; }
-inline bool net_split(int l) { return l == 0; }
 inline int net_cop(int l) { return l == 3 ? 16 : 32; }
 inline int net_cin(int l) { return l == 0 ? kNetIn : kNetHidden; }
 inline int net_cout(int l) { return l == 3 ? kNetOut : kNetHidden; }
@@ -44,17 +41,17 @@ void cnn_mse(const CnnShape &sh, float wgt, const float *y, const float *tg, uns
              hipStream_t st);
 // one Adam step (1-based `step`); the decay constants enter in float64 so
 // that 1 - b and 1 - b^t carry no float32 rounding of b
-void cnn_adam(int n, int cop, int cip, int cout, int cin, int split, float *w, const float *gw, float *m, float *v, float lr,
+void cnn_adam(int n, int cop, int cip, int cout, int cin, float *w, const float *gw, float *m, float *v, float lr,
               double b1, double b2, double eps, int step, unsigned short *wb, unsigned short *wt, float *b,
               const float *gb, float *mb, float *vb, hipStream_t st);
-void cnn_cast(int n, int cop, int cip, int cin, int split, const float *w, unsigned short *wb, unsigned short *wt,
-              hipStream_t st);
-// lattice fields -> network input: (n_a / n_ref - 1, j_a / j_ref)
-void cnn_pack_input(const CnnShape &sh, const float *n, const float *j, float n_ref, float j_ref, unsigned short *x,
-                    hipStream_t st);
-// channel-first float32 [8][N] -> packed split input [N][32]
+void cnn_cast(int n, int cop, int cip, const float *w, unsigned short *wb, unsigned short *wt, hipStream_t st);
+// lattice fields -> network input: (n_a / n_ref - 1, j_a / j_ref, c_s^2 grad n_a / f_ref)
+// (central differences on the periodic grid, c_s^2 = 1/3)
+void cnn_pack_input(const CnnShape &sh, const float *n, const float *j, float n_ref, float j_ref, float f_ref,
+                    unsigned short *x, hipStream_t st);
+// channel-first float32 [14][N] -> packed input [N][32]
 void cnn_pack_x(const CnnShape &sh, const float *xf, unsigned short *x, hipStream_t st);
-// channel-first float32 input [8][N] and target [6][N] = Nf / f_ref from lattice fields
+// channel-first float32 input [14][N] and target [6][N] = Nf / f_ref from lattice fields
 void cnn_fields_x(const CnnShape &sh, const float *n, const float *j, float n_ref, float j_ref, const float *Nf,
                   float f_ref, float *xf, float *tf, hipStream_t st);
 // channel-first [6][N] / f_ref -> [N][6]

@@ -1,10 +1,16 @@
 // Learned force closure: a 3D convolutional network on the lattice.
 //
-// It maps the local state of a binary mixture (densities n_a and momentum
-// densities j_a, scaled) to the force densities N_a = n_a Phi_a of the
-// kinetic equation (Sec. 2, eq. evolution; the field of Sec. 3,
-// eq. splitforce).  Four 3x3x3 convolutions on the periodic lattice,
-// channels 8 -> 32 -> 32 -> 32 -> 6, SiLU after the first three.
+// It maps the local state of a binary mixture to the force densities
+// N_a = n_a Phi_a of the kinetic equation (Sec. 2, eq. evolution; the field
+// of Sec. 3, eq. splitforce).  Four 3x3x3 convolutions on the periodic
+// lattice, channels 14 -> 32 -> 32 -> 32 -> 6, SiLU after the first three.
+// The 14 inputs of a site are its scaled densities n_a / n_ref - 1, its
+// momentum densities j_a / j_ref and the lattice pressure gradients
+// c_s^2 grad n_a / f_ref (central differences, c_s^2 = 1/3).  The force is
+// dominated by derivatives of the densities; given as inputs at the scale
+// of the force they need no more than bfloat16's 8 bits, where a network
+// that had to difference the densities itself would lose them to the
+// rounding of the undifferentiated values.
 //
 // Layout: activations channel-last [site][C] (C padded to a multiple of
 // 16), weights [tap][C_out][C_in] in bfloat16, accumulation in float32 on
@@ -12,15 +18,6 @@
 // tiles with v_mfma_f32_16x16x32_bf16 (k_conv_tile); the weight gradient
 // contracts over sites with v_mfma_f32_16x16x16bf16_1k (k_conv_wgrad).
 // 16 x 16 output blocks: D[4g + v][j] in lane j + 16g, element v.
-//
-// The first layer runs in split bfloat16: every input value x is carried as
-// hi = bf16(x) and lo = bf16(x - hi), every weight w as hi and lo the same
-// way, and the 32 packed input channels [x_hi | x_lo | x_hi | 0] meet the
-// weight row [w_hi | w_hi | w_lo | 0], so one contraction gives
-// w_hi x_hi + w_hi x_lo + w_lo x_hi, about 16 significant bits.  The
-// force is a spatial derivative of fields whose local values it barely
-// changes; with 8-bit inputs or first-layer weights the rounding of the
-// undifferentiated part would swamp it.
 //
 // Kernels: convolution forward (bias, optional SiLU, stores the
 // pre-activation for the backward pass), data gradient (transposed
@@ -450,46 +447,29 @@ __global__ void k_mse(long long N, int COP, int NOUT, float wgt, const float *__
 // ------------------------------------------------------------- Adam
 // master [t][co][ci] float32 (padded layout), grads same layout; refreshes
 // the bf16 copies W [t][co][ci] and WT [t][ci][co].  Padded entries stay 0.
-// split (first layer, CIP = 4 cin): master entries ci < cin; the gradient of
-// w is that of its x_hi and x_lo slots, and the bf16 row gets w_hi, w_hi,
-// w_lo, 0 in slots ci, ci + cin, ci + 2 cin, ci + 3 cin.
 struct AdamConst {
     float lr, b1, b2, omb1, omb2, c1, c2, eps;   // omb = 1 - b, c = 1 - b^t (formed in float64)
 };
 
-__device__ inline void store_split(unsigned short *wb, int i, int cin, float w)
-{
-    const unsigned short hi = f2bf(w);
-    wb[i] = hi;
-    wb[i + cin] = hi;
-    wb[i + 2 * cin] = f2bf(w - bf2f(hi));
-    wb[i + 3 * cin] = 0;
-}
-
-__global__ void k_adam(int n, int COP, int CIP, int cout, int cin, int split, float *__restrict__ w,
-                       const float *__restrict__ gw, float *__restrict__ m, float *__restrict__ v, AdamConst k,
-                       unsigned short *__restrict__ wb, unsigned short *__restrict__ wt)
+__global__ void k_adam(int n, int COP, int CIP, int cout, int cin, float *__restrict__ w, const float *__restrict__ gw,
+                       float *__restrict__ m, float *__restrict__ v, AdamConst k, unsigned short *__restrict__ wb,
+                       unsigned short *__restrict__ wt)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int t = i / (COP * CIP), r = i - t * COP * CIP, co = r / CIP, ci = r - co * CIP;
-    if (split && ci >= cin) return;                // written by the owner of slot ci % cin
     if (co >= cout || ci >= cin) {
         wb[i] = 0;
         wt[((long long)t * CIP + ci) * COP + co] = 0;
         return;
     }
-    const float gi = split ? gw[i] + gw[i + cin] : gw[i];
+    const float gi = gw[i];
     const float mi = k.b1 * m[i] + k.omb1 * gi;
     const float vi = k.b2 * v[i] + k.omb2 * gi * gi;
     m[i] = mi;
     v[i] = vi;
     const float wi = w[i] - k.lr * (mi / k.c1) / (sqrtf(vi / k.c2) + k.eps);
     w[i] = wi;
-    if (split) {
-        store_split(wb, i, cin, wi);
-        return;
-    }
     wb[i] = f2bf(wi);
     wt[((long long)t * CIP + ci) * COP + co] = f2bf(wi);
 }
@@ -507,81 +487,93 @@ __global__ void k_adam_bias(int n, float *__restrict__ b, const float *__restric
 }
 
 // refresh bf16 copies from float32 masters (after loading weights)
-__global__ void k_cast_weights(int n, int COP, int CIP, int cin, int split, const float *__restrict__ w,
-                               unsigned short *__restrict__ wb, unsigned short *__restrict__ wt)
+__global__ void k_cast_weights(int n, int COP, int CIP, const float *__restrict__ w, unsigned short *__restrict__ wb,
+                               unsigned short *__restrict__ wt)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int t = i / (COP * CIP), r = i - t * COP * CIP, co = r / CIP, ci = r - co * CIP;
-    if (split) {
-        if (ci < cin) store_split(wb, i, cin, w[i]);
-        return;
-    }
     wb[i] = f2bf(w[i]);
     wt[((long long)t * CIP + ci) * COP + co] = f2bf(w[i]);
 }
 
 // ---------------------------------------------------------- packing
-// split first-layer input of one site: x[0..31] = [hi(v) | lo(v) | hi(v) | 0],
-// written as four 16-byte stores (a site's 64 bytes are 16-byte aligned)
-__device__ inline void store_input(unsigned short *__restrict__ x, const float v[8])
+// first-layer input of one site: x[0..31] = [bf16(v[0..13]) | 0], written as
+// four 16-byte stores (a site's 64 bytes are 16-byte aligned)
+__device__ inline void store_input(unsigned short *__restrict__ x, const float v[kNetIn])
 {
-    unsigned hi[4], lo[4];
+    unsigned p[16];
 #pragma unroll
-    for (int c = 0; c < 8; c += 2) {
-        const unsigned short h0 = f2bf(v[c]), h1 = f2bf(v[c + 1]);
-        const unsigned short l0 = f2bf(v[c] - bf2f(h0)), l1 = f2bf(v[c + 1] - bf2f(h1));
-        hi[c / 2] = (unsigned)h0 | ((unsigned)h1 << 16);
-        lo[c / 2] = (unsigned)l0 | ((unsigned)l1 << 16);
+    for (int c = 0; c < 16; ++c) {
+        const unsigned short a = 2 * c < kNetIn ? f2bf(v[2 * c]) : 0, b = 2 * c + 1 < kNetIn ? f2bf(v[2 * c + 1]) : 0;
+        p[c] = (unsigned)a | ((unsigned)b << 16);
     }
     uint4 *o = reinterpret_cast<uint4 *>(x);
-    const uint4 H = make_uint4(hi[0], hi[1], hi[2], hi[3]);
-    o[0] = H;
-    o[1] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
-    o[2] = H;
-    o[3] = make_uint4(0u, 0u, 0u, 0u);
+    o[0] = make_uint4(p[0], p[1], p[2], p[3]);
+    o[1] = make_uint4(p[4], p[5], p[6], p[7]);
+    o[2] = make_uint4(p[8], p[9], p[10], p[11]);
+    o[3] = make_uint4(p[12], p[13], p[14], p[15]);
 }
 
-// network input of site s: (n_0, n_1) / n_ref - 1, (j_0, j_1) / j_ref
-__global__ void k_pack_input(long long N, const float *__restrict__ n, const float *__restrict__ j, float n_ref,
-                             float j_ref, unsigned short *__restrict__ x)
+// The 14 inputs of site s: v[0..1] = n_a / n_ref - 1, v[2..7] = j_a,d / j_ref
+// (index 2 + 3a + d), v[8..13] = c_s^2 (n_a(s + e_d) - n_a(s - e_d)) / 2 / f_ref
+// (index 8 + 3a + d), neighbours with periodic wrap.
+__device__ inline void site_inputs(const CnnShape &sh, long long s, const float *__restrict__ n,
+                                   const float *__restrict__ j, float n_ref, float j_ref, float f_ref, float v[kNetIn])
+{
+    const long long N = sh.N;
+    const int nx = sh.nx, ny = sh.ny, nz = sh.nz;
+    const long long nxy = (long long)nx * ny;
+    const int x = (int)(s % nx), y = (int)((s / nx) % ny), z = (int)(s / nxy);
+    const long long dxp = x == nx - 1 ? 1 - nx : 1, dxm = x == 0 ? nx - 1 : -1;
+    const long long dyp = y == ny - 1 ? nx - nxy : nx, dym = y == 0 ? nxy - nx : -nx;
+    const long long dzp = z == nz - 1 ? nxy - N : nxy, dzm = z == 0 ? N - nxy : -nxy;
+    const long long dp[3] = {dxp, dyp, dzp}, dm[3] = {dxm, dym, dzm};
+    const float gsc = (1.f / 6.f) / f_ref;   // c_s^2 / 2 / f_ref
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const float *na = n + a * N;
+        v[a] = na[s] / n_ref - 1.f;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            v[2 + 3 * a + d] = j[(3 * a + d) * N + s] / j_ref;
+            v[8 + 3 * a + d] = (na[s + dp[d]] - na[s + dm[d]]) * gsc;
+        }
+    }
+}
+
+__global__ void k_pack_input(CnnShape sh, const float *__restrict__ n, const float *__restrict__ j, float n_ref,
+                             float j_ref, float f_ref, unsigned short *__restrict__ x)
 {
     const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= N) return;
-    float v[8];
-    v[0] = n[s] / n_ref - 1.f;
-    v[1] = n[N + s] / n_ref - 1.f;
-    for (int d = 0; d < 3; ++d) {
-        v[2 + d] = j[d * N + s] / j_ref;
-        v[5 + d] = j[(3 + d) * N + s] / j_ref;
-    }
+    if (s >= sh.N) return;
+    float v[kNetIn];
+    site_inputs(sh, s, n, j, n_ref, j_ref, f_ref, v);
     store_input(x + s * 32, v);
 }
 
-// input from channel-first float32 xf [8][N]
+// input from channel-first float32 xf [14][N]
 __global__ void k_pack_x(long long N, const float *__restrict__ xf, unsigned short *__restrict__ x)
 {
     const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= N) return;
-    float v[8];
-    for (int c = 0; c < 8; ++c) v[c] = xf[c * N + s];
+    float v[kNetIn];
+    for (int c = 0; c < kNetIn; ++c) v[c] = xf[c * N + s];
     store_input(x + s * 32, v);
 }
 
 // channel-first float32 network input and target from lattice fields:
-// xf[c][s] as in k_pack_input, tf[c][s] = N_c(s) / f_ref
-__global__ void k_fields_x(long long N, const float *__restrict__ n, const float *__restrict__ j, float n_ref,
+// xf[c][s] = the inputs of site_inputs, tf[c][s] = N_c(s) / f_ref
+__global__ void k_fields_x(CnnShape sh, const float *__restrict__ n, const float *__restrict__ j, float n_ref,
                            float j_ref, const float *__restrict__ Nf, float f_ref, float *__restrict__ xf,
                            float *__restrict__ tf)
 {
     const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long N = sh.N;
     if (s >= N) return;
-    xf[s] = n[s] / n_ref - 1.f;
-    xf[N + s] = n[N + s] / n_ref - 1.f;
-    for (int d = 0; d < 3; ++d) {
-        xf[(2 + d) * N + s] = j[d * N + s] / j_ref;
-        xf[(5 + d) * N + s] = j[(3 + d) * N + s] / j_ref;
-    }
+    float v[kNetIn];
+    site_inputs(sh, s, n, j, n_ref, j_ref, f_ref, v);
+    for (int c = 0; c < kNetIn; ++c) xf[c * N + s] = v[c];
     for (int c = 0; c < 6; ++c) tf[c * N + s] = Nf[c * N + s] / f_ref;
 }
 
@@ -725,27 +717,25 @@ void cnn_mse(const CnnShape &sh, float wgt, const float *y, const float *tg, uns
     hipLaunchKernelGGL(k_mse, dim3(nblocks(sh.N)), dim3(256), 0, st, sh.N, 16, 6, wgt, y, tg, gout, loss_part);
 }
 
-void cnn_adam(int n, int cop, int cip, int cout, int cin, int split, float *w, const float *gw, float *m, float *v, float lr,
+void cnn_adam(int n, int cop, int cip, int cout, int cin, float *w, const float *gw, float *m, float *v, float lr,
               double b1, double b2, double eps, int step, unsigned short *wb, unsigned short *wt, float *b,
               const float *gb, float *mb, float *vb, hipStream_t st)
 {
     const AdamConst k{lr, (float)b1, (float)b2, (float)(1.0 - b1), (float)(1.0 - b2),
                       (float)(1.0 - std::pow(b1, step)), (float)(1.0 - std::pow(b2, step)), (float)eps};
-    hipLaunchKernelGGL(k_adam, dim3(nblocks(n)), dim3(256), 0, st, n, cop, cip, cout, cin, split, w, gw, m, v, k, wb,
-                       wt);
+    hipLaunchKernelGGL(k_adam, dim3(nblocks(n)), dim3(256), 0, st, n, cop, cip, cout, cin, w, gw, m, v, k, wb, wt);
     hipLaunchKernelGGL(k_adam_bias, dim3(1), dim3(64), 0, st, cop, b, gb, mb, vb, k);
 }
 
-void cnn_cast(int n, int cop, int cip, int cin, int split, const float *w, unsigned short *wb, unsigned short *wt,
-              hipStream_t st)
+void cnn_cast(int n, int cop, int cip, const float *w, unsigned short *wb, unsigned short *wt, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cast_weights, dim3(nblocks(n)), dim3(256), 0, st, n, cop, cip, cin, split, w, wb, wt);
+    hipLaunchKernelGGL(k_cast_weights, dim3(nblocks(n)), dim3(256), 0, st, n, cop, cip, w, wb, wt);
 }
 
-void cnn_pack_input(const CnnShape &sh, const float *n, const float *j, float n_ref, float j_ref, unsigned short *x,
-                    hipStream_t st)
+void cnn_pack_input(const CnnShape &sh, const float *n, const float *j, float n_ref, float j_ref, float f_ref,
+                    unsigned short *x, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_pack_input, dim3(nblocks(sh.N)), dim3(256), 0, st, sh.N, n, j, n_ref, j_ref, x);
+    hipLaunchKernelGGL(k_pack_input, dim3(nblocks(sh.N)), dim3(256), 0, st, sh, n, j, n_ref, j_ref, f_ref, x);
 }
 
 void cnn_pack_x(const CnnShape &sh, const float *xf, unsigned short *x, hipStream_t st)
@@ -756,8 +746,7 @@ void cnn_pack_x(const CnnShape &sh, const float *xf, unsigned short *x, hipStrea
 void cnn_fields_x(const CnnShape &sh, const float *n, const float *j, float n_ref, float j_ref, const float *Nf,
                   float f_ref, float *xf, float *tf, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_fields_x, dim3(nblocks(sh.N)), dim3(256), 0, st, sh.N, n, j, n_ref, j_ref, Nf, f_ref, xf,
-                       tf);
+    hipLaunchKernelGGL(k_fields_x, dim3(nblocks(sh.N)), dim3(256), 0, st, sh, n, j, n_ref, j_ref, Nf, f_ref, xf, tf);
 }
 
 void cnn_pack_target(const CnnShape &sh, const float *Nf, float f_ref, float *tg, hipStream_t st)

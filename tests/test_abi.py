@@ -151,12 +151,12 @@ def test_batch_sizing_names_the_bad_system():
 
 
 def test_network_sizes():
-    """The closure network (8 -> 32 -> 32 -> 32 -> 6 channels, 3x3x3 kernels):
-    27 * (8*32 + 32*32 + 32*32 + 32*6) = 67 392 weights, one per MAC at a site,
+    """The closure network (14 -> 32 -> 32 -> 32 -> 6 channels, 3x3x3 kernels):
+    27 * (14*32 + 32*32 + 32*32 + 32*6) = 72 576 weights, one per MAC at a site,
     plus 102 biases; an empty box has no workspace."""
     import paper_1105_3634_amd as mlb
     lib = mlb._lib.load()
-    assert lib.mlb_net_param_count() == 67392 + 102
+    assert lib.mlb_net_param_count() == 27 * (14 * 32 + 32 * 32 + 32 * 32 + 32 * 6) + 102
     assert lib.mlb_net_workspace_bytes(0, 8, 8, 0) == 0
     assert lib.mlb_net_workspace_bytes(8, 8, 8, 1) > lib.mlb_net_workspace_bytes(8, 8, 8, 0) > 0
     # the lattice's cap of 2^29 sites holds for the network's grid as well

@@ -6,16 +6,15 @@ step (moments -> network -> collision + streaming, with exact-force checks
 and fallback) against the lattice oracle.
 
 Tolerances follow from the arithmetic.  bfloat16 keeps 8 significant bits,
-so one rounding moves a value by at most u = 2^-9 (relative).  The first
-layer is split bfloat16 (about 16 bits, negligible here); the forward pass
-rounds the weights of layers 1-3 and the three hidden activations once
-each, so the relative L2 error of the output is bounded by about
-3 sqrt(2) u = 8.3e-3 (4 sqrt(2) u is asserted).  With the weights of layers
-1-3 pre-rounded on the oracle side only the three activation roundings
-remain: 3 u = 5.9e-3.  The backward pass adds one rounding of the gradient
-per layer (four more), hence 2.5e-2 per gradient tensor.  Adam runs in
-float32 on float32 master weights: agreement to a few float32 ulps of the
-weight plus a few ulps of the step.
+so one rounding moves a value by at most u = 2^-9 (relative).  The forward
+pass rounds the inputs, the weights of the four layers and the three
+hidden activations once each (eight roundings, k / sqrt(2) u each way of
+counting: 4 sqrt(2) u = 1.1e-2; 5 sqrt(2) u is asserted).  With the inputs
+and all weights pre-rounded on the oracle side only the three activation
+roundings remain: 3 u = 5.9e-3.  The backward pass adds one rounding of
+the gradient per layer (four more, 6 sqrt(2) u = 1.7e-2), hence 2.5e-2 per
+gradient tensor.  Adam runs in float32 on float32 master weights:
+agreement to a few float32 ulps of the weight plus a few ulps of the step.
 """
 import numpy as np
 import pytest
@@ -26,6 +25,7 @@ from oracle import cnn
 pytestmark = pytest.mark.gpu
 
 U_BF16 = 2.0 ** -9
+CIN = cnn.CHANNELS[0]
 
 
 def bf16(a):
@@ -64,16 +64,15 @@ def test_forward_matches_oracle(mlb, shape):
     print(f"forward parity shape={shape}", flush=True)
     layers = random_layers(7)
     rng = np.random.default_rng(3)
-    x = rng.normal(scale=0.7, size=(8,) + shape)
+    x = rng.normal(scale=0.7, size=(CIN,) + shape)
     net = mlb.GpuNet(shape)
     net.set_params(layers)
     y = net.forward(x).cpu().numpy().astype(np.float64)
     y_ref, _ = cnn.forward(layers, x)
-    assert rel_l2(y, y_ref) < 4 * np.sqrt(2) * U_BF16
-    # with the weights of layers 1-3 rounded as the device rounds them
-    rounded = [{"W": L["W"] if l == 0 else bf16(L["W"]), "b": np.float32(L["b"]).astype(np.float64)}
-               for l, L in enumerate(layers)]
-    y_r, _ = cnn.forward(rounded, np.float32(x).astype(np.float64))
+    assert rel_l2(y, y_ref) < 5 * np.sqrt(2) * U_BF16
+    # with the inputs and all weights rounded as the device rounds them
+    rounded = [{"W": bf16(L["W"]), "b": np.float32(L["b"]).astype(np.float64)} for L in layers]
+    y_r, _ = cnn.forward(rounded, bf16(x))
     assert rel_l2(y, y_r) < 3 * U_BF16
     assert np.max(np.abs(y - y_r)) < 8 * U_BF16 * np.max(np.abs(y_r))
 
@@ -88,7 +87,7 @@ def test_parameter_roundtrip_and_zero_network(mlb):
     np.testing.assert_array_equal(back, flat)
     zero = np.zeros_like(flat)
     net.set_params(zero)
-    y = net.forward(np.random.default_rng(0).normal(size=(8,) + shape)).cpu().numpy()
+    y = net.forward(np.random.default_rng(0).normal(size=(CIN,) + shape)).cpu().numpy()
     assert np.all(y == 0.0)
 
 
@@ -97,7 +96,7 @@ def test_gradients_match_oracle(mlb):
     print("gradient parity", flush=True)
     layers = random_layers(5)
     rng = np.random.default_rng(9)
-    x = rng.normal(scale=0.7, size=(8,) + shape)
+    x = rng.normal(scale=0.7, size=(CIN,) + shape)
     t = rng.normal(scale=0.5, size=(6,) + shape)
     net = mlb.GpuNet(shape, training=True)
     net.set_params(layers)
@@ -118,7 +117,7 @@ def test_adam_two_steps_match_oracle(mlb):
     shape = (6, 6, 7)
     layers = random_layers(2)
     rng = np.random.default_rng(4)
-    x = rng.normal(scale=0.7, size=(8,) + shape)
+    x = rng.normal(scale=0.7, size=(CIN,) + shape)
     t = rng.normal(scale=0.5, size=(6,) + shape)
     net = mlb.GpuNet(shape, training=True)
     net.set_params(layers)
@@ -135,40 +134,13 @@ def test_adam_two_steps_match_oracle(mlb):
     assert net.adam_steps == 2
 
 
-def test_split_first_layer_resolves_small_gradients(mlb):
-    """A smooth input riding on an offset: the first layer must resolve its
-    differences far below bfloat16's resolution of the offset."""
-    shape = (4, 4, 32)
-    layers = [{"W": np.zeros((co, ci, 3, 3, 3)), "b": np.zeros(co)} for ci, co in
-              zip((8, 32, 32, 32), (32, 32, 32, 6))]
-    # layer 0, channel 0: central x-difference of input 0; layers 1-3 carry
-    # channel 0 through (with the SiLUs in between)
-    rng = np.random.default_rng(5)
-    layers[0]["W"][0, 0, 1, 1, 2] = 1.0
-    layers[0]["W"][0, 0, 1, 1, 0] = -1.0
-    for l in (1, 2):
-        layers[l]["W"][0, 0, 1, 1, 1] = 1.0
-    layers[3]["W"][0, 0, 1, 1, 1] = 1.0
-    x = np.zeros((8,) + shape)
-    xx = np.arange(shape[2])
-    x[0] = (0.3 + 1e-3 * np.sin(2 * np.pi * xx / shape[2]))[None, None, :]
-    x[1:] = rng.normal(scale=0.1, size=(7,) + shape)
-    net = mlb.GpuNet(shape)
-    net.set_params(layers)
-    y = net.forward(x).cpu().numpy().astype(np.float64)
-    y_ref, _ = cnn.forward(layers, np.float32(x).astype(np.float64))
-    # the difference of neighbours is 2e-4 on a 0.3 offset: bfloat16 inputs
-    # would resolve it only to 0.3 * 2^-9 = 6e-4
-    assert rel_l2(y[0], y_ref[0]) < 4 * U_BF16
-
-
 def test_training_reduces_loss(mlb):
     """A few hundred Adam steps fit a fixed smooth target (the network can
     represent a linear 3x3x3 stencil exactly)."""
     shape = (8, 8, 8)
     rng = np.random.default_rng(1)
-    x = rng.normal(scale=0.5, size=(8,) + shape)
-    Wt = rng.normal(scale=0.1, size=(6, 8, 3, 3, 3))
+    x = rng.normal(scale=0.5, size=(CIN,) + shape)
+    Wt = rng.normal(scale=0.1, size=(6, CIN, 3, 3, 3))
     t = cnn.conv3d(x, Wt, np.zeros(6))
     net = mlb.GpuNet(shape, training=True)
     net.set_params(cnn.init_params(seed=0))
@@ -202,7 +174,11 @@ def test_closure_sample_matches_oracle(mlb, oracle_lib):
     x, t = g.closure_sample(net)
     x, t = x.cpu().numpy(), t.cpu().numpy()
     d = o.fields(f)
-    x_ref = np.concatenate([d["n"] / n_ref - 1.0, d["j"][0] / j_ref, d["j"][1] / j_ref])
+    # inputs: densities, momenta, lattice pressure gradients c_s^2 (n(r + e_d) - n(r - e_d)) / 2
+    # (central differences with periodic wrap, c_s^2 = 1/3) in force units
+    grads = [(np.roll(d["n"][a], -1, axis=ax) - np.roll(d["n"][a], 1, axis=ax)) / 6.0 / f_ref
+             for a in range(2) for ax in (2, 1, 0)]
+    x_ref = np.concatenate([d["n"] / n_ref - 1.0, d["j"][0] / j_ref, d["j"][1] / j_ref, np.stack(grads)])
     t_ref = d["N"].reshape(6, *mix.shape()) / f_ref
     assert np.max(np.abs(x - x_ref)) < 1e-5 * max(1.0, np.max(np.abs(x_ref)))
     assert np.max(np.abs(t - t_ref)) < 1e-4 * np.max(np.abs(t_ref))
@@ -393,17 +369,18 @@ def test_pool_statistics_rescale_and_error(mlb):
     N = int(np.prod(shape))
     rng = np.random.default_rng(5)
     S = 300                                           # more than one pass of the library's sample chunks
-    x = rng.normal(size=(S, 8) + shape).astype(np.float32)
+    x = rng.normal(size=(S, CIN) + shape).astype(np.float32)
     t = (rng.normal(size=(S, 6) + shape) * rng.uniform(0.1, 3.0, size=(S, 1, 1, 1, 1))).astype(np.float32)
     xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
     j_ms, t_ms = net.pool_stats(xd, td)
     x64, t64 = x.astype(np.float64), t.astype(np.float64)
-    assert abs(j_ms / np.mean(x64[:, 2:] ** 2) - 1) < 1e-12
+    assert abs(j_ms / np.mean(x64[:, 2:8] ** 2) - 1) < 1e-12
     np.testing.assert_allclose(t_ms, (t64 ** 2).reshape(S, -1).mean(1), rtol=1e-12)
     net.pool_rescale(xd, td, 2.0, 4.0)
     xr, tr = xd.cpu().numpy(), td.cpu().numpy()
     np.testing.assert_array_equal(xr[:, :2], x[:, :2])
-    np.testing.assert_allclose(xr[:, 2:], x[:, 2:] * np.float32(0.5), rtol=1e-7)
+    np.testing.assert_allclose(xr[:, 2:8], x[:, 2:8] * np.float32(0.5), rtol=1e-7)
+    np.testing.assert_allclose(xr[:, 8:], x[:, 8:] * np.float32(0.25), rtol=1e-7)
     np.testing.assert_allclose(tr, t * np.float32(0.25), rtol=1e-7)
     y = t[0] + rng.normal(scale=0.1, size=t[0].shape).astype(np.float32)
     err = net.rel_error(torch.from_numpy(y).cuda(), torch.from_numpy(t[0]).cuda())
