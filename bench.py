@@ -359,7 +359,8 @@ def ensemble_leg(mlb, W, steps=1000, timed=200, opts=None):
                 "well_conditioned_max": float(np.max(Dg))},
         "tuning": {"shape": mlb.GpuBatch.SHAPES[tune["shape"]], "order": ["linear", "xcd-chunked"][tune["order"]],
                    "gather1_groups_per_site": tune["gather1_split"],
-                   "gather1_sign_groups": tune["gather1_sign_groups"], "trial_ms": tune["trial_ms"],
+                   "gather1_sign_groups": tune["gather1_sign_groups"],
+                   "gather1_shape": mlb.GpuBatch.G1_SHAPES[tune["gather1_shape"]], "trial_ms": tune["trial_ms"],
                    "sign_groups_ms": tune["sign_groups_ms"]},
         "passes_ms_per_step": {k: v[0] / 10 for k, v in passes.items() if v[1]},
     }
@@ -711,11 +712,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=200, help="untimed steps before the timed region (the GPU reaches its steady clocks)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tail", choices=["auto", "direct", "spectral"], default="auto")
-    ap.add_argument("--tiling", default=None, metavar="SHAPE,ORDER[,SPLIT[,GROUPS]]",
+    ap.add_argument("--tiling", default=None, metavar="SHAPE,ORDER[,SPLIT[,GROUPS[,OWN]]]",
                     help="fixed tile shape (0: 16x4x4, 1: 8x8x4, 2: 32x4x2), block order (0 linear, "
-                         "1 XCD-chunked), the first gather's thread groups per site (2 or 3, default 3) and its "
-                         "shell loop (0 plain, the default; 1 sign-grouped) instead of the start-up autotuning "
-                         "(reproducible profiles)")
+                         "1 XCD-chunked), the first gather's thread groups per site (2 or 3, default 3), its "
+                         "shell loop (0 plain, the default; 1 sign-grouped) and its tiles (0 the tiling's shape, "
+                         "the default; 1 4x8x8) instead of the start-up autotuning (reproducible profiles)")
     ap.add_argument("--no-d12", action="store_true", help="skip the 2000-step D_12 accuracy check")
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
@@ -805,11 +806,12 @@ def main():
     avg_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in passes.items()}
     dom = max((k for k in avg_ms if k in flops), key=lambda k: avg_ms[k])
     achieved = flops[dom] / (avg_ms[dom] * 1e-3) / 1e12
-    shapes = ("16,4,4", "8,8,4", "32,4,2")
+    shapes = ("16,4,4", "8,8,4", "32,4,2", "4,8,8")
     tune = g.tuning()
     kname = {"gather1": "k_gather1_tile", "step2": "k_step2_tile"}.get(dom)
-    kargs = shapes[tune["shape"]] + (f",{tune['gather1_split']},{'true' if tune['gather1_sign_groups'] == 1 else 'false'}"
-                                     if dom == "gather1" else "")
+    kargs = (shapes[tune["gather1_shape"]] + f",{tune['gather1_split']},"
+             f"{'true' if tune['gather1_sign_groups'] == 1 else 'false'}" if dom == "gather1"
+             else shapes[tune["shape"]])
     traffic = counter_traffic(f"{kname}<{kargs}>") if kname else None
     total_bytes = sum(bytes_.values()) * args.steps
     line = {

@@ -77,8 +77,9 @@ enum { MLB_SCHEME_CN_J1 = 0, MLB_SCHEME_FE = 1 };
 enum { MLB_TAIL_AUTO = 0, MLB_TAIL_DIRECT = 1, MLB_TAIL_SPECTRAL = 2 };
 enum { MLB_OPT_TUNE = 1u,       /* time every float32 tiling (tile shape, block order, thread groups
                                    of the first gather), then the two fastest again, longer, with
-                                   the plain and the sign-grouped shell loop, at init; keep the
-                                   fastest */
+                                   the plain and the sign-grouped shell loop and with the first
+                                   gather on the tiling's shape and on its own 4x8x8 tiles, at
+                                   init; keep the fastest */
        MLB_OPT_NO_GRAPH = 2u,   /* launch the passes eagerly instead of replaying a graph */
        MLB_OPT_NO_STABILITY_CHECK = 512u }; /* skip the linear-stability guard at init (studies of
                                            unstable schemes) */
@@ -91,10 +92,14 @@ enum { MLB_OPT_TUNE = 1u,       /* time every float32 tiling (tile shape, block 
  * given), 1 = sign-grouped (the points of a half-shell that differ only in
  * the signs of their y and z components summed together: the same sums of
  * eqs. potmeanforce, tensorgamma and viscousforce in another association,
- * equal to the plain loop to float32 rounding). */
+ * equal to the plain loop to float32 rounding), and MLB_OPT_GATHER1_OWN_TILES(t)
+ * the first gather's tiles: 0 = the tiling's shape (also when not given),
+ * 1 = 4x8x8 sites (its 16-byte LDS reads free of bank conflicts at the
+ * LDS size of 8x8x4; the sums are those of every other shape, bit for bit). */
 #define MLB_OPT_TILING(shape, order) ((((uint32_t)(shape) + 1u) & 15u) << 4 | ((uint32_t)(order) & 1u) << 8)
 #define MLB_OPT_GATHER1_SPLIT(s) (((uint32_t)(s) & 3u) << 10)
 #define MLB_OPT_GATHER1_SIGN_GROUPS(g) (((uint32_t)(g) ? 2u : 1u) << 12)
+#define MLB_OPT_GATHER1_OWN_TILES(t) (((uint32_t)(t) ? 2u : 1u) << 14)
 enum { MLB_PART_MF = 1u, MLB_PART_TAIL = 2u, MLB_PART_DISS = 4u, MLB_PART_EXT = 8u,
        MLB_PART_ALL = 15u };
 
@@ -193,6 +198,8 @@ mlb_status mlb_tuning(mlb_mixture h, int32_t *shape, int32_t *order, double *tri
 mlb_status mlb_tuning_ex(mlb_mixture h, int32_t *shape, int32_t *order, int32_t *gather1_split, double *trial_ms);
 /* The first gather's shell loop in use (see mlb_batch_tuning_groups). */
 mlb_status mlb_tuning_groups(mlb_mixture h, int32_t *sign_groups, double *groups_ms);
+/* The first gather's tile shape in use (see mlb_batch_tuning_gather1_shape). */
+mlb_status mlb_tuning_gather1_shape(mlb_mixture h, int32_t *shape);
 
 /* Advance the populations by nsteps >= 0 time steps of the kinetic equation
  * (Sec. 2, eq. evolution, with the field of Sec. 3). */
@@ -372,6 +379,10 @@ mlb_status mlb_batch_tuning_ex(mlb_batch h, int32_t *shape, int32_t *order, int3
  * chosen tiling with the sign-grouped loop (0 when not measured; the plain
  * loop's time is that tiling's trial_ms entry). */
 mlb_status mlb_batch_tuning_groups(mlb_batch h, int32_t *sign_groups, double *groups_ms);
+/* shape (HOST, may be NULL): the first gather's tile shape, 0..2 as in
+ * MLB_OPT_TILING or 3 = its own 4x8x8 tiles; -1 when the float32 tiles are
+ * not in use. */
+mlb_status mlb_batch_tuning_gather1_shape(mlb_batch h, int32_t *shape);
 mlb_status mlb_batch_profile_begin(mlb_batch h);
 mlb_status mlb_batch_profile_end(mlb_batch h, double *ms, int32_t *launches, void *stream);
 int64_t mlb_batch_step_count(mlb_batch h);

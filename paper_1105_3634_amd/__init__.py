@@ -130,15 +130,16 @@ class GpuMixture:
 
     def tuning(self):
         """Float32 tiling in use: shape, order, the first gather's thread groups
-        per site and shell loop, and the time of every tuned candidate
-        (mlb_tuning_ex, mlb_tuning_groups)."""
-        shape, order, split, groups = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        per site, shell loop and tile shape, and the time of every tuned
+        candidate (mlb_tuning_ex, mlb_tuning_groups, mlb_tuning_gather1_shape)."""
+        shape, order, split, groups, g1 = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         ms, gms = (C.c_double * 12)(), C.c_double()
         _lib.check(self.lib.mlb_tuning_ex(self.h, C.byref(shape), C.byref(order), C.byref(split), ms),
                    "mlb_tuning_ex")
         _lib.check(self.lib.mlb_tuning_groups(self.h, C.byref(groups), C.byref(gms)), "mlb_tuning_groups")
+        _lib.check(self.lib.mlb_tuning_gather1_shape(self.h, C.byref(g1)), "mlb_tuning_gather1_shape")
         return {"shape": int(shape.value), "order": int(order.value), "gather1_split": int(split.value),
-                "gather1_sign_groups": int(groups.value), "trial_ms": list(ms[:]),
+                "gather1_sign_groups": int(groups.value), "gather1_shape": int(g1.value), "trial_ms": list(ms[:]),
                 "sign_groups_ms": float(gms.value)}
 
     def set_graph(self, enable: bool) -> None:
@@ -280,6 +281,7 @@ class GpuBatch:
     """An ensemble of independent mixtures advanced by shared launches."""
 
     SHAPES = ("16x4x4", "8x8x4", "32x4x2")
+    G1_SHAPES = SHAPES + ("4x8x8",)
 
     def __init__(self, mixes: Sequence, n0s: Sequence[np.ndarray], u0s: Sequence[np.ndarray], precision: int = 32,
                  options: int = 0, device: str = "cuda:0", stream=None):
@@ -385,14 +387,15 @@ class GpuBatch:
         return np.array(t[:n]), np.array(v[:n])
 
     def tuning(self):
-        shape, order, split, groups = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        shape, order, split, groups, g1 = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         ms, gms = (C.c_double * 12)(), C.c_double()
         _lib.check(self.lib.mlb_batch_tuning_ex(self.h, C.byref(shape), C.byref(order), C.byref(split), ms),
                    "mlb_batch_tuning_ex")
         _lib.check(self.lib.mlb_batch_tuning_groups(self.h, C.byref(groups), C.byref(gms)),
                    "mlb_batch_tuning_groups")
+        _lib.check(self.lib.mlb_batch_tuning_gather1_shape(self.h, C.byref(g1)), "mlb_batch_tuning_gather1_shape")
         return {"shape": int(shape.value), "order": int(order.value), "gather1_split": int(split.value),
-                "gather1_sign_groups": int(groups.value), "trial_ms": list(ms[:]),
+                "gather1_sign_groups": int(groups.value), "gather1_shape": int(g1.value), "trial_ms": list(ms[:]),
                 "sign_groups_ms": float(gms.value)}
 
     def profile_begin(self) -> None:

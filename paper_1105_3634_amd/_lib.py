@@ -60,6 +60,7 @@ _SIGS = [
     ("mlb_tuning_ex", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                 C.POINTER(C.c_double)]),
     ("mlb_tuning_groups", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    ("mlb_tuning_gather1_shape", C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     ("mlb_step", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     ("mlb_moments", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("mlb_forces", C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p]),
@@ -101,6 +102,7 @@ _SIGS = [
     ("mlb_batch_tuning_ex", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_double)]),
     ("mlb_batch_tuning_groups", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    ("mlb_batch_tuning_gather1_shape", C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     ("mlb_batch_profile_begin", C.c_int, [C.c_void_p]),
     ("mlb_batch_profile_end", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_void_p]),
     ("mlb_batch_step_count", C.c_int64, [C.c_void_p]),
@@ -132,12 +134,14 @@ OPT_TUNE, OPT_NO_GRAPH, OPT_NO_STABILITY_CHECK = 1, 2, 512
 STATIC_WORKSPACE_BYTES = 64 << 20   # MLB_STATIC_WORKSPACE_BYTES
 
 
-def opt_tiling(shape: int, order: int, gather1_split: int = 0, sign_groups: int = 0) -> int:
+def opt_tiling(shape: int, order: int, gather1_split: int = 0, sign_groups: int = 0, own_tiles: int = 0) -> int:
     """Option bits of a fixed float32 tiling (MLB_OPT_TILING,
-    MLB_OPT_GATHER1_SPLIT and MLB_OPT_GATHER1_SIGN_GROUPS in mlb.h; split 0 =
-    the default, 3; sign_groups 1 = the sign-grouped shell loop)."""
+    MLB_OPT_GATHER1_SPLIT, MLB_OPT_GATHER1_SIGN_GROUPS and
+    MLB_OPT_GATHER1_OWN_TILES in mlb.h; split 0 = the default, 3; sign_groups
+    1 = the sign-grouped shell loop; own_tiles 1 = the first gather on 4x8x8
+    tiles)."""
     return (((shape + 1) & 15) << 4 | (order & 1) << 8 | (gather1_split & 3) << 10
-            | (2 if sign_groups else 1) << 12)
+            | (2 if sign_groups else 1) << 12 | (2 if own_tiles else 1) << 14)
 
 _lib = None
 

@@ -270,12 +270,14 @@ struct SysHost {
 };
 
 // Float32 tiling: tile shape, block order, the first gather's thread
-// groups per site (2 or 3) and its shell loop (plain or sign-grouped);
-// trial_ms[(split - 2) 2 V + 2 shape + order] with the plain loop,
-// groups_ms the chosen tiling with the sign-grouped loop.
+// groups per site (2 or 3), its shell loop (plain or sign-grouped) and its
+// own tile shape (the common one, or 4x8x8); trial_ms[(split - 2) 2 V +
+// 2 shape + order] with the plain loop, groups_ms the chosen tiling with the
+// sign-grouped loop.
 constexpr int kSplitChoices = 2, kTrials = 2 * mlb::kTileVariants * kSplitChoices;
+constexpr int kG1Own = 3;   // the first gather's own shape variant (4x8x8)
 struct Tuning {
-    int shape = 0, order = 1, g1split = 3;
+    int shape = 0, order = 1, g1split = 3, g1shape = 0;
     bool groups = false;
     double trial_ms[kTrials] = {};
     double groups_ms = 0.0;
@@ -318,12 +320,12 @@ struct mlb_batch_s {
     char *ws = nullptr;
     size_t total = 0;
     // shared regions
-    size_t desc = 0, map_site = 0, map_tile = 0, map_ident = 0;
+    size_t desc = 0, map_site = 0, map_tile = 0, map_g1 = 0, map_ident = 0;
     size_t t_sh_e = 0, t_sh_u = 0, t_tl_e = 0, t_tl_w = 0, t_bl_e = 0, t_sh_q = 0, t_sg_q = 0;
     size_t red = 0, red_out = 0, fit_out = 0;
     size_t desc_size = 0;
-    int nblk_site = 0, nblk_tile = 0, ident_len = 0;
-    int map_tile_cap = 0;
+    int nblk_site = 0, nblk_tile = 0, nblk_g1 = 0, ident_len = 0;
+    int map_tile_cap = 0, map_g1_cap = 0;
     Tuning tune;
     std::vector<unsigned char> desc_host;   // count stepping descriptors + 1 query descriptor
     int parity = 0;
@@ -438,19 +440,23 @@ bool plan_batch(Batch &B, const mlb_params *params, int count, std::string &why)
         B.nblk_site += S.nblocks;
         ident = std::max(ident, S.nblocks);
     }
-    for (int v = 0; v < mlb::kTileVariants; ++v) {
+    int g1_tiles_total = 0;
+    for (int v = 0; v < mlb::kG1Variants; ++v) {
         int tot = 0;
         for (auto &S : B.sys) {
             const int nt = mlb::tile_count(v, S.p.nx, S.p.ny, S.p.nz);
             tot += nt;
             max_tiles_any = std::max(max_tiles_any, nt);
         }
-        tiles_total_max = std::max(tiles_total_max, tot);
+        if (v < mlb::kTileVariants) tiles_total_max = std::max(tiles_total_max, tot);
+        else g1_tiles_total = tot;
     }
     B.ident_len = std::max(ident, max_tiles_any);
     B.map_tile_cap = (tiles_total_max + kXcds - 1) / kXcds * kXcds;
+    B.map_g1_cap = (g1_tiles_total + kXcds - 1) / kXcds * kXcds;
     B.map_site = take(sizeof(int2) * (size_t)B.nblk_site);
     B.map_tile = take(sizeof(int2) * (size_t)B.map_tile_cap);
+    B.map_g1 = take(sizeof(int2) * (size_t)B.map_g1_cap);
     B.map_ident = take(sizeof(int2) * (size_t)B.ident_len);
     // tables (concatenated)
     size_t nsh = 0, ntl = 0, nbl = 0, nsg = 0;
@@ -648,18 +654,28 @@ mlb_status upload_static(Batch &B, hipStream_t st)
     return MLB_OK;
 }
 
-mlb_status set_tiling(Batch &B, int shape, int order, int g1split, bool groups, hipStream_t st)
+// g1shape: the first gather's tile shape (`shape`, or kG1Own with its own
+// block map in the same order)
+mlb_status set_tiling(Batch &B, int shape, int order, int g1split, bool groups, int g1shape, hipStream_t st)
 {
-    int nblk = 0;
+    int nblk = 0, ng1 = 0;
     std::vector<int2> m = tile_map(B, shape, order, nblk);
     if (nblk > B.map_tile_cap) return fail(MLB_EINVAL, "tile map overflow");
     HIP_TRY(hipMemcpyAsync(B.ws + B.map_tile, m.data(), sizeof(int2) * m.size(), hipMemcpyHostToDevice, st));
+    std::vector<int2> m1;
+    if (g1shape != shape) {
+        m1 = tile_map(B, g1shape, order, ng1);
+        if (ng1 > B.map_g1_cap) return fail(MLB_EINVAL, "tile map overflow");
+        HIP_TRY(hipMemcpyAsync(B.ws + B.map_g1, m1.data(), sizeof(int2) * m1.size(), hipMemcpyHostToDevice, st));
+    }
     HIP_TRY(hipStreamSynchronize(st));
     B.nblk_tile = nblk;
+    B.nblk_g1 = g1shape != shape ? ng1 : nblk;
     B.tune.shape = shape;
     B.tune.order = order;
     B.tune.g1split = g1split;
     B.tune.groups = groups;
+    B.tune.g1shape = g1shape;
     if (B.graph) {
         (void)hipGraphExecDestroy(B.graph);
         B.graph = nullptr;
@@ -778,14 +794,17 @@ void run_passes(Batch &B, hipStream_t st, bool query, int qk, int force_only)
     const int M = query ? B.sys[qk].M : B.maxM;
     // float32 LDS tiles: contact values and both gathers share the tile map
     bool tiled = false;
-    int shape = 0, ntl = 0;
-    const int2 *tmap = nullptr;
+    int shape = 0, ntl = 0, g1shape = 0, ng1 = 0;
+    const int2 *tmap = nullptr, *g1map = nullptr;
     if constexpr (std::is_same<T, float>::value) {
         if (B.tiled) {
             tiled = true;
             shape = B.tune.shape;
+            g1shape = B.tune.g1shape;
             tmap = query ? B.map_of(B.map_ident) : B.map_of(B.map_tile);
             ntl = query ? mlb::tile_count(shape, B.sys[qk].p.nx, B.sys[qk].p.ny, B.sys[qk].p.nz) : B.nblk_tile;
+            g1map = query ? tmap : B.map_of(g1shape != shape ? B.map_g1 : B.map_tile);
+            ng1 = query ? mlb::tile_count(g1shape, B.sys[qk].p.nx, B.sys[qk].p.ny, B.sys[qk].p.nz) : B.nblk_g1;
         }
     }
     auto contact = [&](hipStream_t s) {
@@ -804,7 +823,7 @@ void run_passes(Batch &B, hipStream_t st, bool query, int qk, int force_only)
             if (tiled) {
                 pass(B, kPassGather1, st,
                      [&] {
-                         mlb::launch_gather1_tile(shape, B.tune.g1split, B.tune.groups, sys, tmap, ntl, M, tb,
+                         mlb::launch_gather1_tile(g1shape, B.tune.g1split, B.tune.groups, sys, g1map, ng1, M, tb,
                                                   B.reach_max, st);
                      });
                 return;
@@ -1075,7 +1094,7 @@ mlb_status autotune(Batch &B, const double *const *n0, const double *const *u0, 
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
             const Tuning cached = it->second;
-            TRY(set_tiling(B, cached.shape, cached.order, cached.g1split, cached.groups, st));
+            TRY(set_tiling(B, cached.shape, cached.order, cached.g1split, cached.groups, cached.g1shape, st));
             B.tune = cached;
             return MLB_OK;
         }
@@ -1101,8 +1120,8 @@ mlb_status autotune(Batch &B, const double *const *n0, const double *const *u0, 
     };
     // one tiling: two warm-up steps (they capture its graph), then at least
     // six timed steps and at least min_ms of GPU time in one timed run
-    auto trial = [&](int v, int order, int split, bool groups, double min_ms) -> double {
-        status = set_tiling(B, v, order, split, groups, st);
+    auto trial = [&](int v, int order, int split, bool groups, int g1v, double min_ms) -> double {
+        status = set_tiling(B, v, order, split, groups, g1v, st);
         if (status != MLB_OK) return -1.0;
         status = run_steps(B, 2, st, false);
         if (status != MLB_OK) return -1.0;
@@ -1112,16 +1131,18 @@ mlb_status autotune(Batch &B, const double *const *n0, const double *const *u0, 
         return timed(reps);
     };
     // the clocks settle on the first tiling before anything is timed
-    (void)trial(0, 0, 2, false, 10.0);
+    (void)trial(0, 0, 2, false, 0, 10.0);
     for (int split = 2; split < 2 + kSplitChoices && status == MLB_OK; ++split)
     for (int v = 0; v < mlb::kTileVariants && status == MLB_OK; ++v)
         for (int order = 0; order < 2 && status == MLB_OK; ++order) {
-            const double per = trial(v, order, split, false, 5.0);
+            const double per = trial(v, order, split, false, v, 5.0);
             if (status != MLB_OK) break;
             best.trial_ms[(split - 2) * 2 * mlb::kTileVariants + 2 * v + order] = per;
         }
     // final round, timed longer: the two fastest tilings with the plain and
-    // the sign-grouped shell loop
+    // the sign-grouped shell loop, each with the first gather on the
+    // tiling's shape and on its own 4x8x8 tiles
+    const bool own_fits = mlb::gather1_lds_bytes_of(kG1Own, B.reach_max) <= 160 * 1024;
     if (status == MLB_OK) {
         int idx[kTrials];
         for (int k = 0; k < kTrials; ++k) idx[k] = k;
@@ -1131,19 +1152,22 @@ mlb_status autotune(Batch &B, const double *const *n0, const double *const *u0, 
             const int split = 2 + k / (2 * mlb::kTileVariants), v = (k / 2) % mlb::kTileVariants, order = k % 2;
             double grouped_ms = 0.0;
             bool chosen = false;
-            for (int groups = 0; groups < 2 && status == MLB_OK; ++groups) {
-                const double per = trial(v, order, split, groups != 0, 15.0);
-                if (status != MLB_OK) break;
-                if (groups) grouped_ms = per;
-                if (per < best_ms) {
-                    best_ms = per;
-                    best.shape = v;
-                    best.order = order;
-                    best.g1split = split;
-                    best.groups = groups != 0;
-                    chosen = true;
+            for (int g1 = 0; g1 < (own_fits ? 2 : 1) && status == MLB_OK; ++g1)
+                for (int groups = 0; groups < 2 && status == MLB_OK; ++groups) {
+                    const int g1v = g1 ? kG1Own : v;
+                    const double per = trial(v, order, split, groups != 0, g1v, 15.0);
+                    if (status != MLB_OK) break;
+                    if (groups && g1 == 0) grouped_ms = per;
+                    if (per < best_ms) {
+                        best_ms = per;
+                        best.shape = v;
+                        best.order = order;
+                        best.g1split = split;
+                        best.groups = groups != 0;
+                        best.g1shape = g1v;
+                        chosen = true;
+                    }
                 }
-            }
             // the sign-grouped time reported is that of the chosen tiling
             if (chosen) best.groups_ms = grouped_ms;
         }
@@ -1151,7 +1175,7 @@ mlb_status autotune(Batch &B, const double *const *n0, const double *const *u0, 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (status != MLB_OK) return status;
-    TRY(set_tiling(B, best.shape, best.order, best.g1split, best.groups, st));
+    TRY(set_tiling(B, best.shape, best.order, best.g1split, best.groups, best.g1shape, st));
     B.tune = best;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1226,7 +1250,7 @@ mlb_status create(Batch &B, const mlb_params *params, int count, void *workspace
     if (B.tiled && !mlb::tile_prepare(B.reach_max, B.ball_reach_max, B.ball_total_max, B.maxM))
         B.tiled = false;
     TRY(upload_static<T>(B, st));
-    if (B.tiled) TRY(set_tiling(B, 0, 1, 3, false, st));
+    if (B.tiled) TRY(set_tiling(B, 0, 1, 3, false, 0, st));
     for (auto &S : B.sys)
         if (S.spectral) TRY(setup_spectral(B, S, st));
     bool any_spectral = false;
@@ -1244,11 +1268,14 @@ mlb_status create(Batch &B, const mlb_params *params, int count, void *workspace
     const int fixed_shape = (int)((options >> 4) & 15u) - 1, fixed_order = (int)((options >> 8) & 1u);
     const int fixed_split = (int)((options >> 10) & 3u);
     const int fixed_groups = (int)((options >> 12) & 3u);
+    const int fixed_g1 = (int)((options >> 14) & 3u);
     if (fixed_shape >= mlb::kTileVariants) return fail(MLB_EINVAL, "MLB_OPT_TILING: no such tile shape");
     if (fixed_split == 1) return fail(MLB_EINVAL, "MLB_OPT_GATHER1_SPLIT: 2 or 3 thread groups per site");
     if (fixed_groups == 3) return fail(MLB_EINVAL, "MLB_OPT_GATHER1_SIGN_GROUPS: 0 or 1");
+    if (fixed_g1 == 3) return fail(MLB_EINVAL, "MLB_OPT_GATHER1_OWN_TILES: 0 or 1");
     if (B.tiled && fixed_shape >= 0) {
-        TRY(set_tiling(B, fixed_shape, fixed_order, fixed_split ? fixed_split : 3, fixed_groups == 2, st));
+        TRY(set_tiling(B, fixed_shape, fixed_order, fixed_split ? fixed_split : 3, fixed_groups == 2,
+                       fixed_g1 == 2 ? kG1Own : fixed_shape, st));
     } else if (B.tiled && (options & MLB_OPT_TUNE)) {
         TRY(autotune<T>(B, n0, u0, st));
     }
@@ -1862,6 +1889,18 @@ mlb_status mlb_batch_tuning_groups(mlb_batch h, int32_t *sign_groups, double *gr
 mlb_status mlb_tuning_groups(mlb_mixture h, int32_t *sign_groups, double *groups_ms)
 {
     return mlb_batch_tuning_groups(h, sign_groups, groups_ms);
+}
+
+mlb_status mlb_batch_tuning_gather1_shape(mlb_batch h, int32_t *shape)
+{
+    if (!h) return fail(MLB_EINVAL, "handle is NULL");
+    if (shape) *shape = h->tiled ? h->tune.g1shape : -1;
+    return MLB_OK;
+}
+
+mlb_status mlb_tuning_gather1_shape(mlb_mixture h, int32_t *shape)
+{
+    return mlb_batch_tuning_gather1_shape(h, shape);
 }
 
 mlb_status mlb_batch_profile_begin(mlb_batch h)

@@ -136,12 +136,18 @@ struct Launch {
 };
 
 // Float32 tiled gathers (gather_tile.h, built in step_f32.hip); tile shape
-// variant v: 0 = 16x4x4, 1 = 8x8x4, 2 = 32x4x2 sites.
+// variant v: 0 = 16x4x4, 1 = 8x8x4, 2 = 32x4x2 sites for all tiled passes;
+// the first gather also runs on 3 = 4x8x8 (rows of 4 + 2R halo sites: at
+// reach 4 its 16-byte LDS reads fall on distinct banks, at the LDS
+// footprint of 8x8x4).
 constexpr int kTileVariants = 3;
+constexpr int kG1Variants = 4;
 void tile_dims(int v, int &tx, int &ty, int &tz);
 // (groups: the sign-grouped shell loop, see gather_tile.h)
 void launch_gather1_tile(int v, int split, bool groups, const SysDesc<float> *sys, const int2 *map, int nblk,
                          int maxM, Tables<float> tb, int reach_max, hipStream_t st);
+// dynamic LDS of the first gather on shape v (SIZE_MAX if it cannot stage)
+size_t gather1_lds_bytes_of(int v, int reach);
 void launch_step2_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, int maxM, Tables<float> tb,
                        int reach_max, int parity, int write_force_only, hipStream_t st);
 // contact values on the same tiles (halo = ball reach), one thread per site

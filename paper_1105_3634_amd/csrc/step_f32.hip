@@ -1,6 +1,7 @@
 // Float32 instantiation of the per-site passes (contraction allowed) and
-// the tiled float32 gathers in three tile shapes.
+// the tiled float32 gathers in three tile shapes (four for the first gather).
 #include <cstdint>
+#include <initializer_list>
 
 #include "gather_tile.h"
 
@@ -9,7 +10,7 @@ template struct Launch<float>;
 
 void tile_dims(int v, int &tx, int &ty, int &tz)
 {
-    static const int D[kTileVariants][3] = {{16, 4, 4}, {8, 8, 4}, {32, 4, 2}};
+    static const int D[kG1Variants][3] = {{16, 4, 4}, {8, 8, 4}, {32, 4, 2}, {4, 8, 8}};
     tx = D[v][0]; ty = D[v][1]; tz = D[v][2];
 }
 
@@ -30,6 +31,8 @@ size_t gather_lds_bytes_of(int v, int reach, int layouts, bool second)
 }
 }  // namespace
 
+size_t gather1_lds_bytes_of(int v, int reach) { return gather_lds_bytes_of(v, reach, MLB_G1_LAYOUTS, false); }
+
 size_t tile_lds_bytes_of(int v, int reach)
 {
     return std::max(gather_lds_bytes_of(v, reach, MLB_G1_LAYOUTS, false), gather_lds_bytes_of(v, reach, MLB_S2_LAYOUTS, true));
@@ -46,24 +49,35 @@ size_t contact_lds_bytes_of(int v, int ball_reach, int ball_total, int maxM)
 namespace {
 constexpr size_t kLdsMax = 160 * 1024;   // LDS of one CU
 
-template <int TX, int TY, int TZ>
-bool prepare_one(int reach, int ball_reach, int ball_total, int maxM)
+// The limits are set to the whole LDS of a CU, not to this handle's need:
+// handles with a smaller reach created later must not lower them under the
+// launches of a live handle with a larger one.
+bool raise_lds_limit(std::initializer_list<const void *> fns)
 {
-    const size_t bytes = std::max(tile_lds_bytes(TX, TY, TZ, reach, MLB_G1_LAYOUTS, false),
-                                  tile_lds_bytes(TX, TY, TZ, reach, MLB_S2_LAYOUTS, true));
-    const size_t cbytes = contact_lds_bytes(TX, TY, TZ, ball_reach, ball_total, maxM);
-    if (bytes > kLdsMax || cbytes > kLdsMax) return false;
-    // staging gives each thread one halo column
-    if (TX + 2 * reach > kBlock || TX + 2 * ball_reach > kBlock) return false;
-    // the limit is set to the whole LDS of a CU, not to this handle's need:
-    // handles with a smaller reach created later must not lower it under
-    // the launches of a live handle with a larger one
-    for (const void *fn : {(const void *)k_gather1_tile<TX, TY, TZ, 2, false>, (const void *)k_gather1_tile<TX, TY, TZ, 3, false>,
-                           (const void *)k_gather1_tile<TX, TY, TZ, 2, true>, (const void *)k_gather1_tile<TX, TY, TZ, 3, true>,
-                           (const void *)k_contact_tile<TX, TY, TZ>, (const void *)k_step2_tile<TX, TY, TZ>})
+    for (const void *fn : fns)
         if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax) != hipSuccess)
             return false;
     return true;
+}
+
+template <int TX, int TY, int TZ>
+bool prepare_gather1(int reach)
+{
+    if (tile_lds_bytes(TX, TY, TZ, reach, MLB_G1_LAYOUTS, false) > kLdsMax) return false;
+    if (TX + 2 * reach > kBlock) return false;   // staging gives each thread one halo column
+    return raise_lds_limit({(const void *)k_gather1_tile<TX, TY, TZ, 2, false>, (const void *)k_gather1_tile<TX, TY, TZ, 3, false>,
+                            (const void *)k_gather1_tile<TX, TY, TZ, 2, true>, (const void *)k_gather1_tile<TX, TY, TZ, 3, true>});
+}
+
+template <int TX, int TY, int TZ>
+bool prepare_one(int reach, int ball_reach, int ball_total, int maxM)
+{
+    const size_t bytes = tile_lds_bytes(TX, TY, TZ, reach, MLB_S2_LAYOUTS, true);
+    const size_t cbytes = contact_lds_bytes(TX, TY, TZ, ball_reach, ball_total, maxM);
+    if (bytes > kLdsMax || cbytes > kLdsMax) return false;
+    if (TX + 2 * reach > kBlock || TX + 2 * ball_reach > kBlock) return false;
+    return prepare_gather1<TX, TY, TZ>(reach) &&
+           raise_lds_limit({(const void *)k_contact_tile<TX, TY, TZ>, (const void *)k_step2_tile<TX, TY, TZ>});
 }
 }  // namespace
 
@@ -71,7 +85,7 @@ bool tile_prepare(int reach_max, int ball_reach_max, int ball_total_max, int max
 {
     return prepare_one<16, 4, 4>(reach_max, ball_reach_max, ball_total_max, maxM) &&
            prepare_one<8, 8, 4>(reach_max, ball_reach_max, ball_total_max, maxM) &&
-           prepare_one<32, 4, 2>(reach_max, ball_reach_max, ball_total_max, maxM);
+           prepare_one<32, 4, 2>(reach_max, ball_reach_max, ball_total_max, maxM) && prepare_gather1<4, 8, 8>(reach_max);
 }
 
 void launch_contact_tile(int v, const SysDesc<float> *sys, const int2 *map, int nblk, Tables<float> tb,
@@ -91,7 +105,8 @@ void gather1_split(int v, const SysDesc<float> *sys, const int2 *map, dim3 grid,
     const dim3 block(SPLIT * kBlock);
     if (v == 0) hipLaunchKernelGGL((k_gather1_tile<16, 4, 4, SPLIT, GROUPED>), grid, block, lds, st, sys, map, tb);
     else if (v == 1) hipLaunchKernelGGL((k_gather1_tile<8, 8, 4, SPLIT, GROUPED>), grid, block, lds, st, sys, map, tb);
-    else hipLaunchKernelGGL((k_gather1_tile<32, 4, 2, SPLIT, GROUPED>), grid, block, lds, st, sys, map, tb);
+    else if (v == 2) hipLaunchKernelGGL((k_gather1_tile<32, 4, 2, SPLIT, GROUPED>), grid, block, lds, st, sys, map, tb);
+    else hipLaunchKernelGGL((k_gather1_tile<4, 8, 8, SPLIT, GROUPED>), grid, block, lds, st, sys, map, tb);
 }
 }  // namespace
 

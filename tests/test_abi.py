@@ -125,6 +125,8 @@ def test_null_arguments_are_rejected_without_device_work():
         lambda: lib.mlb_init_mixture_ex(None, None, 0, None, None, 0, None, None),
         lambda: lib.mlb_tuning_groups(None, None, None),
         lambda: lib.mlb_batch_tuning_groups(None, None, None),
+        lambda: lib.mlb_tuning_gather1_shape(None, None),
+        lambda: lib.mlb_batch_tuning_gather1_shape(None, None),
     ]
     for call in calls:
         lib.mlb_last_error()

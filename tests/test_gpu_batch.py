@@ -79,9 +79,10 @@ def test_autotuner_restores_initial_state():
     assert len(tune["trial_ms"]) == 12 and all(v > 0 for v in tune["trial_ms"])
     assert bt.steps == 0
     assert tune["gather1_sign_groups"] in (0, 1) and tune["sign_groups_ms"] > 0
+    assert tune["gather1_shape"] in (tune["shape"], 3)
     b0 = mlb.GpuBatch(mixes, n0s, u0s, precision=32,
                       options=mlb.opt_tiling(tune["shape"], tune["order"], tune["gather1_split"],
-                                             tune["gather1_sign_groups"]))
+                                             tune["gather1_sign_groups"], tune["gather1_shape"] == 3))
     bt.step(4)
     b0.step(4)
     for k in range(len(sy)):

@@ -142,15 +142,16 @@ def test_fp32_densities_within_1e5(oracle_lib, name, steps):
 def test_fp32_sign_grouped_gather_within_1e5(oracle_lib, name, steps):
     """The first gather's sign-grouped shell loop (MLB_OPT_GATHER1_SIGN_GROUPS):
     float32 densities against the oracle within 1e-5, and the force parts of
-    one step within 2e-6, on the 16x4x4 and 8x8x4 tilings."""
+    one step within 2e-6, on the 16x4x4 and 8x8x4 tilings, the latter also
+    with the first gather on its own 4x8x8 tiles."""
     import paper_1105_3634_amd as mlb
     m, n0, u0 = _case(name)
     o = oracle_lib.Oracle(m)
     f0 = o.init(n0, u0)
     no = o.fields(o.step(f0, steps))["n"]
-    for shape in (0, 1):
-        print(f"[fp32 sign groups] case={name} shape={shape} steps={steps}", flush=True)
-        g = _gpu(m, n0, u0, 32, options=mlb.opt_tiling(shape, 1, 3, 1))
+    for shape, own in ((0, 0), (1, 0), (1, 1)):
+        print(f"[fp32 sign groups] case={name} shape={shape} own={own} steps={steps}", flush=True)
+        g = _gpu(m, n0, u0, 32, options=mlb.opt_tiling(shape, 1, 3, 1, own))
         assert g.tuning()["gather1_sign_groups"] == 1
         if name == "ternary_tail_ext":
             ref = o.fields(f0)
@@ -406,10 +407,11 @@ def test_fp32_spectral_100_steps(oracle_lib, name):
 
 @pytest.mark.parametrize("name", ["walls", "bulk_small"])
 def test_fp32_tilings_agree_bit_for_bit(name):
-    """Every tile shape and block order (MLB_OPT_TILING) sums each site's
-    shell lists in the same order, so for one split of the first gather's
-    shell lists over thread groups and one form of its shell loop the
-    float32 states agree bit for bit; the two splits (2 and 3 groups,
+    """Every tile shape and block order (MLB_OPT_TILING), and the first
+    gather on its own 4x8x8 tiles (MLB_OPT_GATHER1_OWN_TILES), sum each
+    site's shell lists in the same order, so for one split of the first
+    gather's shell lists over thread groups and one form of its shell loop
+    the float32 states agree bit for bit; the two splits (2 and 3 groups,
     MLB_OPT_GATHER1_SPLIT) and the plain and sign-grouped loops
     (MLB_OPT_GATHER1_SIGN_GROUPS) add the same terms in different groupings
     and agree to float32 rounding."""
@@ -420,22 +422,24 @@ def test_fp32_tilings_agree_bit_for_bit(name):
         for split in (3, 2):
             for shape in range(3):
                 for order in range(2):
-                    print(f"[tilings] case={name} groups={groups} split={split} shape={shape} order={order}",
-                          flush=True)
-                    g = _gpu(m, n0, u0, 32, options=mlb.opt_tiling(shape, order, split, groups))
-                    t = g.tuning()
-                    assert (t["shape"], t["order"], t["gather1_split"], t["gather1_sign_groups"]) == \
-                        (shape, order, split, groups)
-                    g.step(6)
-                    n, j = g.moments()
-                    got = (_np(n), _np(j))
-                    del g
-                    key = (groups, split)
-                    if key not in refs:
-                        refs[key] = got
-                        continue
-                    ref = refs[key]
-                    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), key + (shape, order)
+                    for own in ((0, 1) if order == 1 else (0,)):
+                        print(f"[tilings] case={name} groups={groups} split={split} shape={shape} order={order} "
+                              f"own={own}", flush=True)
+                        g = _gpu(m, n0, u0, 32, options=mlb.opt_tiling(shape, order, split, groups, own))
+                        t = g.tuning()
+                        assert (t["shape"], t["order"], t["gather1_split"], t["gather1_sign_groups"],
+                                t["gather1_shape"]) == (shape, order, split, groups, 3 if own else shape)
+                        g.step(6)
+                        n, j = g.moments()
+                        got = (_np(n), _np(j))
+                        del g
+                        key = (groups, split)
+                        if key not in refs:
+                            refs[key] = got
+                            continue
+                        ref = refs[key]
+                        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), \
+                            key + (shape, order, own)
     for a, b in (((0, 2), (0, 3)), ((1, 3), (0, 3)), ((1, 2), (0, 3))):
         e = _rel_maxnorm(refs[a][0], refs[b][0])
         print(f"  {a} vs {b}: density rel diff {e:.2e}", flush=True)
