@@ -389,29 +389,44 @@ def test_pool_statistics_rescale_and_error(mlb):
     assert N > 0
 
 
-def test_trained_network_passes_a_check_the_zero_network_fails(mlb):
-    """What the trained network gains: trained as the closure benchmark trains
-    it (snapshots of the plain solver every 25 steps over 5000 steps of
-    composition modes with amplitudes 0.01 - 0.1 on a 192x12x12 box at the
-    step-binary physics, 20 epochs), it passes the exact-force check on a
-    held-out state (amplitude 0.045, after 300 steps) at tolerance 0.2, where
-    the network with all parameters zero (a force of zero) fails with error 1."""
-    from paper_1105_3634_amd.closure_train import closure_error, init_params, train_closure
-    nx, ny, nz = 192, 12, 12
+TRAIN_BOX = (192, 12, 12)
+
+
+def _train_state(amp):
+    nx, ny, nz = TRAIN_BOX
     n_tot = W.number_density(0.2, (0.5, 0.5), (2.0, 3.0))
 
-    def state(amp):
-        def make():
-            m = W.Mixture(nx, ny, nz, sigma=(2.0, 3.0), tau=1.0, name="closure_train")
-            n0, u0 = W.mode_state(m, n_tot, 0.5, amp)
-            return m, n0, u0
-        return make
+    def make():
+        m = W.Mixture(nx, ny, nz, sigma=(2.0, 3.0), tau=1.0, name="closure_train")
+        n0, u0 = W.mode_state(m, n_tot, 0.5, amp)
+        return m, n0, u0
+    return make
 
+
+@pytest.fixture(scope="module")
+def trained(mlb):
+    """A network trained as the closure benchmark trains its candidates
+    (snapshots of the plain solver every 25 steps over 5000 steps of
+    composition modes with amplitudes 0.01 - 0.1 on a 192x12x12 box at the
+    step-binary physics, 20 epochs), with network seed 3."""
+    from paper_1105_3634_amd.closure_train import init_params, train_closure
+    nx, ny, nz = TRAIN_BOX
     net = mlb.GpuNet((nz, ny, nx), training=True)
-    net.set_params(init_params(0))
+    net.set_params(init_params(3))
     amps = (0.05, 0.1, 0.04, 0.01, 0.07, 0.03, 0.06, 0.02, 0.08)
-    rep = train_closure(net, [state(a) for a in amps], per_state=200, sample_every=25, epochs=20, lr=1e-3)
-    m, n0, u0 = state(0.045)()
+    rep = train_closure(net, [_train_state(a) for a in amps], per_state=200, sample_every=25, epochs=20, lr=1e-3,
+                        seed=3)
+    return net, rep
+
+
+def test_trained_network_passes_a_check_the_zero_network_fails(mlb, trained):
+    """What the trained network gains: it passes the exact-force check on a
+    held-out state (amplitude 0.045, after 300 steps) at tolerance 0.2, where
+    the network with all parameters zero (a force of zero) fails with error 1."""
+    from paper_1105_3634_amd.closure_train import closure_error
+    net, rep = trained
+    nx, ny, nz = TRAIN_BOX
+    m, n0, u0 = _train_state(0.045)()
     g = mlb.GpuMixture(m, n0, u0, precision=32)
     g.step(300)
     err_trained = closure_error(net, g)
@@ -428,3 +443,34 @@ def test_trained_network_passes_a_check_the_zero_network_fails(mlb):
         g2.step(1)                                   # checks fall on multiples of check_every: step 300
         st = g2.closure_stats()
         assert st["checks"] == 1 and st["active"] == passes, (st, err_trained)
+
+
+def test_trained_network_carries_steps_within_the_d12_bar(mlb, trained):
+    """The stated accuracy: a checked run (checks every 50 steps, tolerance
+    0.1) of 5000 steps on the held-out state puts at least 15 % of the steps
+    on the trained network with the fitted D_12 within 2 % of the plain
+    run's; the zero network carries none (its runs take the exact force
+    throughout)."""
+    net, rep = trained
+
+    def run(nt):
+        m, n0, u0 = _train_state(0.045)()
+        g = mlb.GpuMixture(m, n0, u0, precision=32)
+        if nt is not None:
+            g.set_closure(nt, check_every=50, tol=0.1)
+        for k in range(0, 5001, 10):
+            g.record_mode(0, 1)
+            if k < 5000:
+                g.step(10)
+        return g.fit(0, t_min=200), (g.closure_stats()["net_steps"] if nt is not None else 0)
+
+    d_plain, _ = run(None)
+    d_net, steps = run(net)
+    nx, ny, nz = TRAIN_BOX
+    zero = mlb.GpuNet((nz, ny, nx))
+    zero.set_scales(*rep.scales)
+    d_zero, steps_zero = run(zero)
+    print(f"  D_12 plain {d_plain:.5f}, closure {d_net:.5f} ({steps} network steps), zero network "
+          f"{d_zero:.5f} ({steps_zero})", flush=True)
+    assert steps >= 750 and abs(d_net / d_plain - 1.0) <= 0.02
+    assert steps_zero == 0 and d_zero == pytest.approx(d_plain, rel=1e-4)
