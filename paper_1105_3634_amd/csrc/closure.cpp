@@ -76,7 +76,7 @@ bool plan(mlb_net_s &n, int nx, int ny, int nz, int training)
         L.b = take(4 * (size_t)L.cop); L.mb = take(4 * (size_t)L.cop); L.vb = take(4 * (size_t)L.cop);
     }
     const size_t N = (size_t)n.N;
-    n.x = take(2 * 32 * N);
+    n.x = take(2 * (size_t)mlb::kNetInSlots * N);
     for (int l = 0; l < 3; ++l) n.a[l] = take(2 * 32 * N);
     n.y = take(4 * 16 * N);
     n.nc = take(4 * 6 * N);

@@ -11,11 +11,12 @@ struct CnnShape {
     long long N;
 };
 
-// Layer l (0..3) has packed (in, out) channels (32, 32), (32, 32), (32, 32), (32, 16);
-// layer 0's 32 input slots hold its 14 inputs, then zeros.
+// Layer l (0..3) has packed (in, out) channels (16, 32), (32, 32), (32, 32), (32, 16);
+// layer 0's 16 input slots hold its 14 inputs, then zeros.
 constexpr int kNetLayers = 4;
 constexpr int kNetIn = 14, kNetHidden = 32, kNetOut = 6;
-inline int net_cip(int) { return 32; }
+constexpr int kNetInSlots = 16;
+inline int net_cip(int l) { return l == 0 ? kNetInSlots : 32; }
 inline int net_cop(int l) { return l == 3 ? 16 : 32; }
 inline int net_cin(int l) { return l == 0 ? kNetIn : kNetHidden; }
 inline int net_cout(int l) { return l == 3 ? kNetOut : kNetHidden; }
@@ -49,7 +50,7 @@ void cnn_cast(int n, int cop, int cip, const float *w, unsigned short *wb, unsig
 // (central differences on the periodic grid, c_s^2 = 1/3)
 void cnn_pack_input(const CnnShape &sh, const float *n, const float *j, float n_ref, float j_ref, float f_ref,
                     unsigned short *x, hipStream_t st);
-// channel-first float32 [14][N] -> packed input [N][32]
+// channel-first float32 [14][N] -> packed input [N][16]
 void cnn_pack_x(const CnnShape &sh, const float *xf, unsigned short *x, hipStream_t st);
 // channel-first float32 input [14][N] and target [6][N] = Nf / f_ref from lattice fields
 void cnn_fields_x(const CnnShape &sh, const float *n, const float *j, float n_ref, float j_ref, const float *Nf,

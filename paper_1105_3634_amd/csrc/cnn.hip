@@ -498,21 +498,20 @@ __global__ void k_cast_weights(int n, int COP, int CIP, const float *__restrict_
 }
 
 // ---------------------------------------------------------- packing
-// first-layer input of one site: x[0..31] = [bf16(v[0..13]) | 0], written as
-// four 16-byte stores (a site's 64 bytes are 16-byte aligned)
+// first-layer input of one site: x[0..15] = [bf16(v[0..13]) | 0], written as
+// two 16-byte stores (a site's 32 bytes are 16-byte aligned)
 __device__ inline void store_input(unsigned short *__restrict__ x, const float v[kNetIn])
 {
-    unsigned p[16];
+    static_assert(kNetIn <= kNetInSlots && kNetInSlots == 16, "two 16-byte stores per site");
+    unsigned p[8];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
+    for (int c = 0; c < 8; ++c) {
         const unsigned short a = 2 * c < kNetIn ? f2bf(v[2 * c]) : 0, b = 2 * c + 1 < kNetIn ? f2bf(v[2 * c + 1]) : 0;
         p[c] = (unsigned)a | ((unsigned)b << 16);
     }
     uint4 *o = reinterpret_cast<uint4 *>(x);
     o[0] = make_uint4(p[0], p[1], p[2], p[3]);
     o[1] = make_uint4(p[4], p[5], p[6], p[7]);
-    o[2] = make_uint4(p[8], p[9], p[10], p[11]);
-    o[3] = make_uint4(p[12], p[13], p[14], p[15]);
 }
 
 // The 14 inputs of site s: v[0..1] = n_a / n_ref - 1, v[2..7] = j_a,d / j_ref
@@ -549,7 +548,7 @@ __global__ void k_pack_input(CnnShape sh, const float *__restrict__ n, const flo
     if (s >= sh.N) return;
     float v[kNetIn];
     site_inputs(sh, s, n, j, n_ref, j_ref, f_ref, v);
-    store_input(x + s * 32, v);
+    store_input(x + s * kNetInSlots, v);
 }
 
 // input from channel-first float32 xf [14][N]
@@ -559,7 +558,7 @@ __global__ void k_pack_x(long long N, const float *__restrict__ xf, unsigned sho
     if (s >= N) return;
     float v[kNetIn];
     for (int c = 0; c < kNetIn; ++c) v[c] = xf[c * N + s];
-    store_input(x + s * 32, v);
+    store_input(x + s * kNetInSlots, v);
 }
 
 // channel-first float32 network input and target from lattice fields:
@@ -655,6 +654,8 @@ bool cnn_prepare()
            hipFuncSetAttribute((const void *)k_conv_tile<32, 32, -1, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                conv_lds(32, 32)) == hipSuccess &&
            hipFuncSetAttribute((const void *)k_conv_tile<16, 32, -1, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               conv_lds(16, 32)) == hipSuccess &&
+           hipFuncSetAttribute((const void *)k_conv_tile<16, 32, 1, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                conv_lds(16, 32)) == hipSuccess;
 }
 
@@ -665,6 +666,9 @@ void cnn_conv_fwd(int layer, const CnnShape &sh, const unsigned short *in, const
     const unsigned nb = conv_tiles(sh);
     if (net_cop(layer) == 16)
         hipLaunchKernelGGL((k_conv_tile<32, 16, 1, 0>), dim3(nb), dim3(kConvThreads), conv_lds(32, 16), st, g, sh.N, in, W, b,
+                           nullptr, z, a, act, 1.f);
+    else if (net_cip(layer) == 16)
+        hipLaunchKernelGGL((k_conv_tile<16, 32, 1, 0>), dim3(nb), dim3(kConvThreads), conv_lds(16, 32), st, g, sh.N, in, W, b,
                            nullptr, z, a, act, 1.f);
     else
         hipLaunchKernelGGL((k_conv_tile<32, 32, 1, 0>), dim3(nb), dim3(kConvThreads), conv_lds(32, 32), st, g, sh.N, in, W, b,
@@ -699,6 +703,7 @@ void cnn_conv_wgrad(int layer, const CnnShape &sh, const unsigned short *gout, c
     const unsigned nb = nblocks(sh.N);
     int cip = 32, cop = 32;
     switch (layer) {
+    case 0: cip = 16; hipLaunchKernelGGL((k_conv_wgrad<16, 32>), dim3(nb, 3), dim3(256), 0, st, g, sh.N, gout, ain, part); break;
     case 3: cop = 16; hipLaunchKernelGGL((k_conv_wgrad<32, 16>), dim3(nb, 3), dim3(256), 0, st, g, sh.N, gout, ain, part); break;
     default: hipLaunchKernelGGL((k_conv_wgrad<32, 32>), dim3(nb, 3), dim3(256), 0, st, g, sh.N, gout, ain, part); break;
     }
