@@ -1238,6 +1238,15 @@ mlb_status create(Batch &B, const mlb_params *params, int count, void *workspace
                   bool no_alloc = false)
 {
     std::string why;
+    // the fixed-tiling option fields, checked before any device work
+    const int fixed_shape = (int)((options >> 4) & 15u) - 1, fixed_order = (int)((options >> 8) & 1u);
+    const int fixed_split = (int)((options >> 10) & 3u);
+    const int fixed_groups = (int)((options >> 12) & 3u);
+    const int fixed_g1 = (int)((options >> 14) & 3u);
+    if (fixed_shape >= mlb::kTileVariants) return fail(MLB_EINVAL, "MLB_OPT_TILING: no such tile shape");
+    if (fixed_split == 1) return fail(MLB_EINVAL, "MLB_OPT_GATHER1_SPLIT: 2 or 3 thread groups per site");
+    if (fixed_groups == 3) return fail(MLB_EINVAL, "MLB_OPT_GATHER1_SIGN_GROUPS: 0 or 1");
+    if (fixed_g1 == 3) return fail(MLB_EINVAL, "MLB_OPT_GATHER1_OWN_TILES: 0 or 1");
     if (!plan_batch(B, params, count, why)) return fail(MLB_EINVAL, why);
     if (!workspace || ((uintptr_t)workspace % kAlign) != 0)
         return fail(MLB_EINVAL, "workspace must be a 256-byte aligned device pointer");
@@ -1265,14 +1274,6 @@ mlb_status create(Batch &B, const mlb_params *params, int count, void *workspace
     for (auto &S : B.sys) mlb::launch_zero_i32(reinterpret_cast<int *>(B.ws + S.series_cnt), 1, st);
     HIP_TRY(hipStreamSynchronize(st));
     if (!(options & MLB_OPT_NO_STABILITY_CHECK)) TRY(check_mean_states(B, st));
-    const int fixed_shape = (int)((options >> 4) & 15u) - 1, fixed_order = (int)((options >> 8) & 1u);
-    const int fixed_split = (int)((options >> 10) & 3u);
-    const int fixed_groups = (int)((options >> 12) & 3u);
-    const int fixed_g1 = (int)((options >> 14) & 3u);
-    if (fixed_shape >= mlb::kTileVariants) return fail(MLB_EINVAL, "MLB_OPT_TILING: no such tile shape");
-    if (fixed_split == 1) return fail(MLB_EINVAL, "MLB_OPT_GATHER1_SPLIT: 2 or 3 thread groups per site");
-    if (fixed_groups == 3) return fail(MLB_EINVAL, "MLB_OPT_GATHER1_SIGN_GROUPS: 0 or 1");
-    if (fixed_g1 == 3) return fail(MLB_EINVAL, "MLB_OPT_GATHER1_OWN_TILES: 0 or 1");
     if (B.tiled && fixed_shape >= 0) {
         TRY(set_tiling(B, fixed_shape, fixed_order, fixed_split ? fixed_split : 3, fixed_groups == 2,
                        fixed_g1 == 2 ? kG1Own : fixed_shape, st));

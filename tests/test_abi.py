@@ -140,6 +140,27 @@ def test_null_arguments_are_rejected_without_device_work():
     assert lib.mlb_pass_name(-1) == b"" and lib.mlb_pass_name(10 ** 6) == b""
 
 
+@pytest.mark.parametrize("bits, field", [
+    (15 << 4, "MLB_OPT_TILING"),                  # shape 14
+    ((2 << 4) | (1 << 10), "MLB_OPT_GATHER1_SPLIT"),
+    ((2 << 4) | (3 << 12), "MLB_OPT_GATHER1_SIGN_GROUPS"),
+    ((2 << 4) | (3 << 14), "MLB_OPT_GATHER1_OWN_TILES"),
+])
+def test_undefined_tiling_options_are_rejected_before_device_work(bits, field):
+    """The fixed-tiling option fields are checked before the workspace, the
+    initial fields or the GPU are touched: undefined values return MLB_EINVAL
+    naming the field, with NULL workspace and fields."""
+    import paper_1105_3634_amd as mlb
+    lib = mlb._lib.load()
+    p = mlb.make_params(W.Mixture(8, 8, 8, sigma=(2.0, 3.0)))
+    arr = (mlb._lib.Params * 1)(p)
+    out = ctypes.c_void_p(1)
+    assert lib.mlb_init_batch(arr, 1, None, 0, None, None, bits, None, ctypes.byref(out)) == -1
+    assert out.value is None
+    assert field in lib.mlb_last_error().decode()
+    assert mlb.opt_tiling(1, 1, 2, 1, 1) >> 14 & 3 == 2 and mlb.opt_tiling(1, 1, 2, 1) >> 14 & 3 == 1
+
+
 def test_batch_sizing_names_the_bad_system():
     import paper_1105_3634_amd as mlb
     lib = mlb._lib.load()

@@ -89,6 +89,30 @@ def test_autotuner_restores_initial_state():
         assert np.array_equal(_np(bt.populations(k)), _np(b0.populations(k)))
 
 
+@pytest.mark.parametrize("order", [0, 1])
+def test_batch_first_gather_own_tiles_bit_identical(order):
+    """The first gather on its own 4x8x8 tiles (MLB_OPT_GATHER1_OWN_TILES: its
+    own block map, whose per-system tile counts differ from the 8x8x4 map of
+    the other passes on these uneven boxes) gives the same float32 states
+    as on the 8x8x4 tiles, bit for bit; an undefined value of the option is
+    refused."""
+    import paper_1105_3634_amd as mlb
+    sy = _systems()
+    args = ([s[0] for s in sy], [s[1] for s in sy], [s[2] for s in sy])
+    runs = []
+    for own in (0, 1):
+        print(f"[batch own tiles] order={order} own={own}", flush=True)
+        b = mlb.GpuBatch(*args, precision=32, options=mlb.opt_tiling(1, order, 2, 1, own))
+        assert b.tuning()["gather1_shape"] == (3 if own else 1)
+        b.step(5)
+        runs.append([_np(b.populations(k)) for k in range(len(sy))])
+        del b
+    for k in range(len(sy)):
+        assert np.array_equal(runs[0][k], runs[1][k]), k
+    with pytest.raises(mlb.MlbError):
+        mlb.GpuBatch(*args, precision=32, options=mlb.opt_tiling(1, order, 2, 1) | (3 << 14))
+
+
 def test_batch_fp32_against_oracle(oracle_lib):
     import paper_1105_3634_amd as mlb
     sy = _systems()[:2]
