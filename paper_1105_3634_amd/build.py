@@ -29,6 +29,7 @@ COMMON += os.environ.get("MLB_HIPFLAGS", "").split()
 UNITS = [
     ("step_f64.hip", ["-ffp-contract=off"]),
     ("step_f32.hip", ["-ffp-contract=fast"]),
+    ("collide_f32.hip", ["-ffp-contract=fast"]),
     ("reduce.hip", ["-ffp-contract=off"]),
     ("spectral.hip", ["-ffp-contract=fast"]),
     ("cnn.hip", ["-ffp-contract=fast"]),

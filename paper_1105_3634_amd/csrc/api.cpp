@@ -21,6 +21,7 @@
 
 #include "../../include/mlb.h"
 #include "cnn.h"
+#include "collide_f32.h"
 #include "mlb_internal.h"
 #include "net_internal.h"
 #include "spectral.h"
@@ -922,7 +923,7 @@ void closure_step(Batch &B, hipStream_t st, bool check)
         double *part = mlb::net_err_buffer(B.net, &nparts);
         mlb::cnn_err_partial(3 * S.M * S.N, Nc, Nf, part, nparts, st);
     }
-    pass(B, kPassStep2, st, [&] { mlb::Launch<T>::collide(sys, smap, B.nblk_site, B.maxM, par, st); });
+    pass(B, kPassStep2, st, [&] { mlb::launch_collide_f32(sys, smap, B.nblk_site, B.maxM, par, st); });
     B.parity ^= 1;
     B.steps += 1;
 }

@@ -127,8 +127,6 @@ struct Launch {
                         hipStream_t st);
     static void step2(const SysDesc<T> *sys, const int2 *map, int nblk, int maxM, Tables<T> tb,
                       int parity, int write_force_only, hipStream_t st);
-    // collision + streaming with the given force S.Nf
-    static void collide(const SysDesc<T> *sys, const int2 *map, int nblk, int maxM, int parity, hipStream_t st);
     // the deferred spectral tail: H += n_a C_a, V-hat += (C_a / m_a) / (1 + Gamma_a / (2 m_a))
     static void add_tail(const SysDesc<T> *sys, const int2 *map, int nblk, int maxM, hipStream_t st);
     static void init_pop(const SysDesc<T> *sys, const int2 *map, int nblk, const double *n0,

@@ -468,45 +468,6 @@ __global__ void __launch_bounds__(kBlock) k_step2(const SysDesc<T> *__restrict__
     }
 }
 
-// Collision and push streaming with a given force Nf [M][3][N] (a force
-// computed elsewhere, e.g. by the learned closure).
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_collide(const SysDesc<T> *__restrict__ sys,
-                                                    const int2 *__restrict__ bmap, int parity)
-{
-    const int2 bm = bmap[blockIdx.x];
-    if (bm.x < 0) return;
-    const SysDesc<T> &S = sys[bm.x];
-    const int a = blockIdx.y;
-    if (a >= S.M) return;
-    const long long s = (long long)bm.y * kBlock + threadIdx.x;
-    if (s >= S.N) return;
-    const long long N = S.N;
-    const Site r = site_of(S, s);
-    if (is_solid(S, r.y)) return;
-    const long long o3 = (long long)a * 3 * N;
-    const T na = S.n[(long long)a * N + s];
-    const T Na[3] = {S.Nf[o3 + s], S.Nf[o3 + N + s], S.Nf[o3 + 2 * N + s]};
-    const T ja[3] = {S.j[o3 + s], S.j[o3 + N + s], S.j[o3 + 2 * N + s]};
-    const T u[3] = {S.u[s], S.u[N + s], S.u[2 * N + s]};
-    const T *__restrict__ fin = S.f[parity] + (long long)a * kQ * N;
-    T *__restrict__ fout = S.f[parity ^ 1] + (long long)a * kQ * N;
-    const bool w1 = S.omega_is_one != 0;
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-        const T fi = w1 ? T(0) : fin[(long long)i * N + s];
-        const T fs = post_collision<T>(i, fi, w1, S.omega, S.om1, na, ja, u, Na, S.ith[a], S.dth[a]);
-        const int yy = r.y + kC[i][1];
-        if (S.walls && (yy == 0 || yy == S.ny - 1)) {
-            const T uw = (yy == 0) ? S.wall_ux[0] : S.wall_ux[1];
-            const T cux = (T)kC[i][0] * uw;
-            fout[(long long)opposite(i) * N + s] = fs - ((T(6) * lattice_weight<T>(i)) * na) * cux;
-        } else {
-            fout[(long long)i * N + nbr(S, r, kC[i][0], kC[i][1], kC[i][2])] = fs;
-        }
-    }
-}
-
 // The attractive field computed beside the first gather (tiled float32
 // path): its contribution N_tail = n_a C_a enters the predictor-time force
 // H and, through N^c, the predictor V-hat = (... + N^c / m_a ...) / (n_a (1 + Gamma_a / (2 m_a))).
@@ -618,11 +579,6 @@ void Launch<T>::step2(const SysDesc<T> *sys, const int2 *map, int nblk, int maxM
 {
     hipLaunchKernelGGL(k_step2<T>, dim3(nblk, maxM), dim3(kBlock), 0, st, sys, map, tb, parity,
                        write_force_only);
-}
-template <typename T>
-void Launch<T>::collide(const SysDesc<T> *sys, const int2 *map, int nblk, int maxM, int parity, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_collide<T>, dim3(nblk, maxM), dim3(kBlock), 0, st, sys, map, parity);
 }
 template <typename T>
 void Launch<T>::add_tail(const SysDesc<T> *sys, const int2 *map, int nblk, int maxM, hipStream_t st)
