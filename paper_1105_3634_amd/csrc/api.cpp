@@ -1156,7 +1156,7 @@ mlb_status autotune(Batch &B, const double *const *n0, const double *const *u0, 
             for (int g1 = 0; g1 < (own_fits ? 2 : 1) && status == MLB_OK; ++g1)
                 for (int groups = 0; groups < 2 && status == MLB_OK; ++groups) {
                     const int g1v = g1 ? kG1Own : v;
-                    const double per = trial(v, order, split, groups != 0, g1v, 15.0);
+                    const double per = trial(v, order, split, groups != 0, g1v, 30.0);
                     if (status != MLB_OK) break;
                     if (groups && g1 == 0) grouped_ms = per;
                     if (per < best_ms) {
